@@ -1,0 +1,260 @@
+"""ctypes binding of the FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg use
+this module.  It never imports the HIP package and the HIP package never
+imports it.  All arrays are float64 numpy arrays in caller order (gas first).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+D = C.POINTER(C.c_double)
+I64 = C.POINTER(C.c_int64)
+I32 = C.POINTER(C.c_int32)
+U64 = C.POINTER(C.c_uint64)
+
+SOFT_ADAPTIVE, SOFT_CONSTANT, SOFT_ADAPTIVE_NOCORR = 0, 1, 2
+WALK_PARTICLE, WALK_GROUP, WALK_DIRECT = 0, 1, 2
+NBR_TREE, NBR_BRUTE = 0, 1
+
+
+class Params(C.Structure):
+    _fields_ = [("G", C.c_double), ("theta", C.c_double), ("quadrupole", C.c_int32),
+                ("soft_mode", C.c_int32), ("eta_h", C.c_double), ("eta_eps", C.c_double),
+                ("gamma", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
+                ("av_eps2", C.c_double), ("tc92", C.c_int32), ("h_maxit", C.c_int32),
+                ("h_tol", C.c_double), ("kappa", C.c_double), ("leaf_size", C.c_int32),
+                ("group_size", C.c_int32), ("walk_mode", C.c_int32), ("nbr_mode", C.c_int32),
+                ("gravity", C.c_int32), ("hydro", C.c_int32)]
+
+
+class Run(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_gas", C.c_int64),
+                ("x", D), ("y", D), ("z", D), ("vx", D), ("vy", D), ("vz", D), ("m", D), ("u", D),
+                ("h_in", D), ("eps_in", D),
+                ("h", D), ("nh", D), ("rho", D), ("omega", D), ("zeta", D), ("divv", D),
+                ("eps", D), ("neps", D), ("ups", D), ("xi", D),
+                ("ax", D), ("ay", D), ("az", D), ("pot", D), ("dudt", D), ("maxmu", D),
+                ("cnt_node", I64), ("cnt_pair", I64), ("cnt_sph", I64), ("iters", I32),
+                ("n_noconv", C.c_int64)]
+
+
+def eta_from_nnei(nnei: float) -> float:
+    """eta such that N_nei = (4 pi / 3) (2 eta)^3 (Sect. 2.1, eps-n relation)."""
+    return 0.5 * (3.0 * nnei / (4.0 * np.pi)) ** (1.0 / 3.0)
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b  # noqa: F401  (package-relative when imported as oracle.oracle)
+            _b.build()
+        L = C.CDLL(path)
+        L.orc_compute_forces.argtypes = [C.POINTER(Params), C.POINTER(Run)]
+        L.orc_compute_forces.restype = C.c_int
+        L.orc_tree_build.argtypes = [C.c_int64, D, D, D, D, C.c_int32]
+        L.orc_tree_build.restype = C.c_void_p
+        L.orc_tree_free.argtypes = [C.c_void_p]
+        L.orc_tree_nnodes.argtypes = [C.c_void_p]
+        L.orc_tree_nnodes.restype = C.c_int64
+        L.orc_tree_root.argtypes = [C.c_void_p, D, I32]
+        L.orc_tree_keys.argtypes = [C.c_void_p, U64, I64]
+        L.orc_tree_nodes.argtypes = [C.c_void_p, I32, U64, I64, I64, I64, I32, I64]
+        L.orc_tree_moments.argtypes = [C.c_void_p, D, D, D, D, D, D, D, D]
+        L.orc_tree_groups.argtypes = [C.c_void_p, C.c_int32, I64]
+        L.orc_tree_groups.restype = C.c_int64
+        L.orc_neighbours.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_int64, D, D, D, D, C.c_int32,
+                                     I64, I64, C.c_int64]
+        L.orc_neighbours.restype = C.c_int64
+        L.orc_potential_energy.argtypes = [C.c_int64, D, D, D, D, D, C.c_double]
+        L.orc_potential_energy.restype = C.c_double
+        L.orc_kick_drift.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_int32] + [D] * 15
+        L.orc_timestep.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64] + [D] * 12 + [C.c_double]
+        L.orc_timestep.restype = C.c_double
+        L.orc_diagnostics.argtypes = [C.c_int64, C.c_int64] + [D] * 10
+        L.orc_eval_kernel.argtypes = [C.c_int, C.c_int64, D, D, D]
+        L.orc_num_threads.restype = C.c_int
+        L.orc_multipole_field.argtypes = [C.c_int64, D, D, D, D, C.c_double, C.c_double, C.c_double,
+                                          C.c_int32, D, D]
+        _LIB = L
+    return _LIB
+
+
+def _p(a, t=D):
+    if a is None:
+        return t()
+    return a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def params(**kw) -> Params:
+    """Defaults: G = 1, theta = 0.5 with quadrupoles, adaptive softening with
+    correction terms, 50 neighbours, gamma = 5/3, alpha = 1, beta = 2,
+    eta_AV^2 = 0.01 hbar^2, TC92 gradient on, Newton tolerance 1e-6."""
+    d = dict(G=1.0, theta=0.5, quadrupole=1, soft_mode=SOFT_ADAPTIVE,
+             eta_h=eta_from_nnei(50.0), eta_eps=eta_from_nnei(50.0), gamma=5.0 / 3.0, alpha=1.0,
+             beta=2.0, av_eps2=0.01, tc92=1, h_maxit=60, h_tol=1e-6, kappa=0.1, leaf_size=8,
+             group_size=32, walk_mode=WALK_GROUP, nbr_mode=NBR_TREE, gravity=1, hydro=1)
+    if "nnei" in kw:
+        e = eta_from_nnei(kw.pop("nnei"))
+        d["eta_h"] = d["eta_eps"] = e
+    d.update(kw)
+    return Params(**d)
+
+
+KERNELS = {"W": 0, "dWdr": 1, "dWdh": 2, "tc92": 3, "phi": 4, "dphidr": 5, "dphideps": 6}
+
+
+def kernel(name: str, r, h):
+    r = _f64(np.atleast_1d(r))
+    h = _f64(np.broadcast_to(np.atleast_1d(h), r.shape))
+    out = np.empty_like(r)
+    lib().orc_eval_kernel(KERNELS[name], r.size, _p(r), _p(h), _p(out))
+    return out
+
+
+def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=None) -> dict:
+    """Full oracle force evaluation on an initial-condition dict.
+
+    ``vel``/``u`` override the velocities and internal energies used in the
+    forces (the predicted values of the leapfrog)."""
+    n, n_gas = int(ic["n"]), int(ic["n_gas"])
+    x, y, z, m = (_f64(ic[k]) for k in ("x", "y", "z", "m"))
+    if vel is None:
+        vx, vy, vz = (_f64(ic[k]) for k in ("vx", "vy", "vz"))
+    else:
+        vx, vy, vz = (_f64(v) for v in vel)
+    uu = _f64(ic["u"] if u is None else u)
+    hin = None if h_in is None else _f64(h_in)
+    ein = None if eps_in is None else _f64(eps_in)
+    out = {k: np.zeros(n) for k in ("h", "nh", "rho", "omega", "zeta", "divv", "eps", "neps", "ups",
+                                     "xi", "ax", "ay", "az", "pot", "dudt", "maxmu")}
+    cnt = {k: np.zeros(n, np.int64) for k in ("cnt_node", "cnt_pair", "cnt_sph")}
+    iters = np.zeros(n, np.int32)
+    r = Run(n=n, n_gas=n_gas, x=_p(x), y=_p(y), z=_p(z), vx=_p(vx), vy=_p(vy), vz=_p(vz), m=_p(m),
+            u=_p(uu), h_in=_p(hin), eps_in=_p(ein), iters=_p(iters, I32),
+            **{k: _p(v) for k, v in out.items()}, **{k: _p(v, I64) for k, v in cnt.items()})
+    rc = lib().orc_compute_forces(C.byref(prm), C.byref(r))
+    if rc != 0:
+        raise RuntimeError(f"orc_compute_forces failed ({rc})")
+    out.update(cnt)
+    out["iters"] = iters
+    out["n_noconv"] = int(r.n_noconv)
+    return out
+
+
+def tree(ic_or_xyz, leaf_size: int, m=None, group_size: int | None = None) -> dict:
+    if isinstance(ic_or_xyz, dict):
+        x, y, z = (_f64(ic_or_xyz[k]) for k in ("x", "y", "z"))
+        m = ic_or_xyz.get("m") if m is None else m
+    else:
+        x, y, z = (_f64(a) for a in ic_or_xyz)
+    n = x.size
+    mm = None if m is None else _f64(m)
+    L = lib()
+    t = L.orc_tree_build(n, _p(x), _p(y), _p(z), _p(mm), leaf_size)
+    if not t:
+        raise RuntimeError("orc_tree_build failed")
+    try:
+        nn = L.orc_tree_nnodes(t)
+        x0 = np.zeros(3)
+        e = np.zeros(1, np.int32)
+        L.orc_tree_root(t, _p(x0), _p(e, I32))
+        keys = np.zeros(n, np.uint64)
+        perm = np.zeros(n, np.int64)
+        L.orc_tree_keys(t, _p(keys, U64), _p(perm, I64))
+        level = np.zeros(nn, np.int32)
+        prefix = np.zeros(nn, np.uint64)
+        first, count, child, parent = (np.zeros(nn, np.int64) for _ in range(4))
+        nchild = np.zeros(nn, np.int32)
+        L.orc_tree_nodes(t, _p(level, I32), _p(prefix, U64), _p(first, I64), _p(count, I64),
+                         _p(child, I64), _p(nchild, I32), _p(parent, I64))
+        mass, delta, side = np.zeros(nn), np.zeros(nn), np.zeros(nn)
+        com, centre, bmin, bmax = (np.zeros((nn, 3)) for _ in range(4))
+        quad = np.zeros((nn, 6))
+        L.orc_tree_moments(t, _p(mass), _p(com), _p(quad), _p(centre), _p(side), _p(delta),
+                           _p(bmin), _p(bmax))
+        out = dict(x0=x0, e=int(e[0]), keys=keys, perm=perm, level=level, prefix=prefix,
+                   first=first, count=count, child=child, nchild=nchild, parent=parent, mass=mass,
+                   com=com, quad=quad, centre=centre, side=side, delta=delta, bmin=bmin, bmax=bmax)
+        if group_size is not None:
+            ng = L.orc_tree_groups(t, group_size, I64())
+            gn = np.zeros(max(ng, 1), np.int64)
+            L.orc_tree_groups(t, group_size, _p(gn, I64))
+            out["groups"] = gn[:ng]
+        return out
+    finally:
+        L.orc_tree_free(t)
+
+
+def neighbours(kind: int, x, y, z, length, n_gas: int, mode: int = NBR_TREE, leaf_size: int = 8,
+               cap: int | None = None):
+    """CSR neighbour sets (offsets[n+1], idx) -- see orc_neighbours."""
+    x, y, z, length = (_f64(a) for a in (x, y, z, length))
+    n = x.size
+    off = np.zeros(n + 1, np.int64)
+    if cap is None:
+        cap = 256 * n + 1024
+    idx = np.zeros(cap, np.int64)
+    tot = lib().orc_neighbours(kind, mode, n, n_gas, _p(x), _p(y), _p(z), _p(length), leaf_size,
+                               _p(off, I64), _p(idx, I64), cap)
+    if tot < 0:
+        return neighbours(kind, x, y, z, length, n_gas, mode, leaf_size, cap=int(off[-1]) + 1)
+    return off, idx[:tot].copy()
+
+
+def potential_energy(x, y, z, m, eps, G: float = 1.0) -> float:
+    x, y, z, m, eps = (_f64(a) for a in (x, y, z, m, eps))
+    return lib().orc_potential_energy(x.size, _p(x), _p(y), _p(z), _p(m), _p(eps), G)
+
+
+def kick_drift(st: dict, dt: float, phase: int, acc, dudt, pred: dict | None = None):
+    """In-place KDK half step on a state dict (x, y, z, vx, vy, vz, u)."""
+    ax, ay, az = (_f64(a) for a in acc)
+    du = _f64(dudt)
+    n, n_gas = int(st["n"]), int(st["n_gas"])
+    vp = [None] * 4 if pred is None else [pred["vx"], pred["vy"], pred["vz"], pred["u"]]
+    lib().orc_kick_drift(n, n_gas, dt, phase, *(_p(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "u")),
+                         _p(ax), _p(ay), _p(az), _p(du), *(_p(v) for v in vp))
+
+
+def timestep(prm: Params, st: dict, out: dict, eta_dt: float = 0.1) -> float:
+    n, n_gas = int(st["n"]), int(st["n_gas"])
+    arrs = [st["vx"], st["vy"], st["vz"], st["u"], out["h"], out["eps"], out["ax"], out["ay"],
+            out["az"], out["dudt"], out["divv"], out["maxmu"]]
+    arrs = [_f64(a) for a in arrs]
+    return lib().orc_timestep(C.byref(prm), n, n_gas, *(_p(a) for a in arrs), eta_dt)
+
+
+def diagnostics(st: dict, pot) -> np.ndarray:
+    out = np.zeros(9)
+    a = [_f64(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u")]
+    p = _f64(pot)
+    lib().orc_diagnostics(int(st["n"]), int(st["n_gas"]), *(_p(v) for v in a), _p(p), _p(out))
+    return out
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def multipole_field(x, y, z, m, point, quadrupole: bool = True):
+    """Acceleration and potential at ``point`` from the set's root-node
+    expansion (monopole + optional quadrupole)."""
+    x, y, z, m = (_f64(a) for a in (x, y, z, m))
+    acc = np.zeros(3)
+    pot = np.zeros(1)
+    lib().orc_multipole_field(x.size, _p(x), _p(y), _p(z), _p(m), float(point[0]), float(point[1]),
+                              float(point[2]), int(quadrupole), _p(acc), _p(pot))
+    return acc, float(pot[0])

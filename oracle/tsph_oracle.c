@@ -1,0 +1,1356 @@
+/*
+ * tsph_oracle.c -- FP64 CPU oracle (TEST INFRASTRUCTURE ONLY; see the header).
+ *
+ * Source of every formula: Merlin et al., "EvoL: the new Padova T-SPH parallel
+ * code for cosmological simulations - I" (arXiv:0912.1786).  Section and
+ * equation labels below are the paper's.  Where the printed text is garbled or
+ * silent the adopted reading is named at the point of use; the full list of
+ * readings is kept with the design notes of the repository.
+ *
+ * Parity status (what pins each part, in tests/test_oracle_*.py):
+ *   kernels          closed-form values, continuity, integral of W, finite
+ *                    differences of each derivative                  pinned
+ *   keys/tree        independent prefix enumeration, partition invariants
+ *                                                                     pinned
+ *   h / eps solve    lattice self-consistency, brute-force neighbours,
+ *                    monotonicity, eps-N_nei relation                 pinned
+ *   gravity          theta = 0 equals the O(N^2) sum, quadrupole error order,
+ *                    Plummer potential and field, finite differences of the
+ *                    softened Lagrangian (correction terms), momentum pinned
+ *   SPH forces       finite differences of the thermal energy at fixed
+ *                    entropy, exact dE/dt = 0 identity, momentum      pinned
+ *   integrator       energy drift scaling with dt^2                   pinned
+ *   timestep rule    criteria of Sect. 4.2 with the adopted etas    parity unpinned
+ *
+ * Plain loops, no blocking or fusion; OpenMP only distributes independent
+ * sinks over threads.
+ */
+#include "tsph_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXLEVEL 21
+
+/* ===================================================================== */
+/* Kernel functions                                                       */
+/* ===================================================================== */
+
+/* Cubic spline density kernel, Sect. 2.1 Eq. (spline): W = w(u)/(pi h^3),
+ * support 2h.  The printed normalisation writes h for the softening kernel;
+ * it is read as 1/(pi eps^3) there (the same shape with the kernel's own
+ * length). */
+double orc_w(double u)
+{
+  if (u < 1.0) return 1.0 - 1.5 * u * u + 0.75 * u * u * u;
+  if (u < 2.0) { double t = 2.0 - u; return 0.25 * t * t * t; }
+  return 0.0;
+}
+
+double orc_dw(double u)
+{
+  if (u < 1.0) return -3.0 * u + 2.25 * u * u;
+  if (u < 2.0) { double t = 2.0 - u; return -0.75 * t * t; }
+  return 0.0;
+}
+
+double orc_W(double r, double h) { return orc_w(r / h) / (M_PI * h * h * h); }
+
+double orc_dWdr(double r, double h) { return orc_dw(r / h) / (M_PI * h * h * h * h); }
+
+/* dW/dh at fixed r = -(3 w + u w')/(pi h^4): chain rule on w(r/h)/(pi h^3). */
+double orc_dWdh(double r, double h)
+{
+  double u = r / h;
+  return -(3.0 * orc_w(u) + u * orc_dw(u)) / (M_PI * h * h * h * h);
+}
+
+/* Thomas & Couchman (1992) kernel gradient, Sect. 3 footnote to the
+ * equations of motion: constant slope inside u < 2/3.  The printed form lacks
+ * the 1/h^4 of a 3-D gradient; it is restored here. */
+double orc_dWdr_tc92(double r, double h)
+{
+  double u = r / h, s;
+  if (u < 2.0 / 3.0) s = 1.0;
+  else if (u < 1.0) s = 0.75 * u * (4.0 - 3.0 * u);
+  else if (u < 2.0) { double t = 2.0 - u; s = 0.75 * t * t; }
+  else s = 0.0;
+  return -s / (M_PI * h * h * h * h);
+}
+
+/* Softened potential kernel, Sect. 2.1 Eq. (softphi); phi -> -1/r for u >= 2. */
+double orc_phi(double r, double eps)
+{
+  double u = r / eps;
+  if (u < 1.0) {
+    double u2 = u * u;
+    return ((2.0 / 3.0) * u2 - 0.3 * u2 * u2 + 0.1 * u2 * u2 * u - 1.4) / eps;
+  }
+  if (u < 2.0) {
+    double u2 = u * u;
+    return ((4.0 / 3.0) * u2 - u2 * u + 0.3 * u2 * u2 - u2 * u2 * u / 30.0 - 1.6 + 1.0 / (15.0 * u)) / eps;
+  }
+  return -1.0 / r;
+}
+
+/* Softened force kernel d phi/d r, Sect. 2.1 Eq. (softforce); 1/r^2 for u >= 2. */
+double orc_dphidr(double r, double eps)
+{
+  double u = r / eps;
+  if (u < 1.0) {
+    double u2 = u * u;
+    return ((4.0 / 3.0) * u - 1.2 * u2 * u + 0.5 * u2 * u2) / (eps * eps);
+  }
+  if (u < 2.0) {
+    double u2 = u * u;
+    return ((8.0 / 3.0) * u - 3.0 * u2 + 1.2 * u2 * u - u2 * u2 / 6.0 - 1.0 / (15.0 * u2)) / (eps * eps);
+  }
+  return 1.0 / (r * r);
+}
+
+/* d phi / d eps at fixed r, Sect. 2.1 Eq. (dphidh).  Derived as
+ * -(f + u f')/eps^2 from phi = f(u)/eps; in the outer branch this gives
+ * -3/2 u^4 where the paper prints +3/2 u^4 (the printed sign makes the
+ * function discontinuous at u = 1 and non-zero at u = 2). */
+double orc_dphideps(double r, double eps)
+{
+  double u = r / eps;
+  if (u < 1.0) {
+    double u2 = u * u;
+    return (-2.0 * u2 + 1.5 * u2 * u2 - 0.6 * u2 * u2 * u + 1.4) / (eps * eps);
+  }
+  if (u < 2.0) {
+    double u2 = u * u;
+    return (-4.0 * u2 + 4.0 * u2 * u - 1.5 * u2 * u2 + 0.2 * u2 * u2 * u + 1.6) / (eps * eps);
+  }
+  return 0.0;
+}
+
+/* ===================================================================== */
+/* Tree: root cube, Morton keys, canonical oct-tree (Sect. 2.2)            */
+/* ===================================================================== */
+
+struct orc_tree {
+  int64_t n;
+  int32_t leaf_size;
+  double x0[3];
+  int32_t e;                  /* root cube side = 2^e                        */
+  uint64_t *keys;             /* sorted keys                                 */
+  int64_t *perm;              /* sorted position -> caller index             */
+  double *xs, *ys, *zs, *ms;  /* sorted positions, masses                    */
+  int64_t nnodes, cap;
+  int32_t *level;
+  uint64_t *prefix;
+  int64_t *first, *count, *child, *parent;
+  int32_t *nchild;
+  double *mass, *com, *quad, *centre, *side, *delta, *bmin, *bmax;
+  int64_t *leaf_of;           /* sorted position -> leaf node                */
+};
+
+/* Power-of-two root cube: x0 = component-wise minimum, side = the maximum
+ * extent rounded up to a power of two.  The cube subdivision is the
+ * hierarchical partition of Sect. 2.2. */
+static void root_cube(int64_t n, const double *x, const double *y, const double *z,
+                      double *x0, int32_t *e)
+{
+  double lo[3] = {x[0], y[0], z[0]}, hi[3] = {x[0], y[0], z[0]};
+  for (int64_t i = 1; i < n; i++) {
+    if (x[i] < lo[0]) lo[0] = x[i];
+    if (x[i] > hi[0]) hi[0] = x[i];
+    if (y[i] < lo[1]) lo[1] = y[i];
+    if (y[i] > hi[1]) hi[1] = y[i];
+    if (z[i] < lo[2]) lo[2] = z[i];
+    if (z[i] > hi[2]) hi[2] = z[i];
+  }
+  double L = 0.0;
+  for (int d = 0; d < 3; d++) {
+    double ext = hi[d] - lo[d];
+    if (ext > L) L = ext;
+    x0[d] = lo[d];
+  }
+  if (L > 0.0) {
+    int ex;
+    double f = frexp(L, &ex); /* L = f 2^ex, f in [0.5, 1) */
+    *e = (f == 0.5) ? ex - 1 : ex;
+  } else {
+    *e = 0;
+  }
+}
+
+static uint64_t spread3(uint64_t v)
+{
+  /* put bit b of v at bit 3b, by a plain loop */
+  uint64_t r = 0;
+  for (int b = 0; b < ORC_MAXLEVEL; b++) r |= ((v >> b) & 1ull) << (3 * b);
+  return r;
+}
+
+static uint64_t cell_coord(double xv, double x0, double scale)
+{
+  double c = floor((xv - x0) * scale);
+  if (c < 0.0) c = 0.0;
+  if (c > 2097151.0) c = 2097151.0;
+  return (uint64_t)c;
+}
+
+typedef struct { uint64_t key; int64_t idx; } key_idx;
+
+static int keyidx_cmp(const void *a, const void *b)
+{
+  const key_idx *p = (const key_idx *)a, *q = (const key_idx *)b;
+  if (p->key < q->key) return -1;
+  if (p->key > q->key) return 1;
+  return (p->idx < q->idx) ? -1 : (p->idx > q->idx);
+}
+
+static int tree_push(orc_tree *t, int32_t level, uint64_t prefix, int64_t first, int64_t count,
+                     int64_t parent)
+{
+  if (t->nnodes == t->cap) {
+    int64_t nc = t->cap ? 2 * t->cap : 1024;
+    t->level = realloc(t->level, nc * sizeof(int32_t));
+    t->prefix = realloc(t->prefix, nc * sizeof(uint64_t));
+    t->first = realloc(t->first, nc * sizeof(int64_t));
+    t->count = realloc(t->count, nc * sizeof(int64_t));
+    t->child = realloc(t->child, nc * sizeof(int64_t));
+    t->parent = realloc(t->parent, nc * sizeof(int64_t));
+    t->nchild = realloc(t->nchild, nc * sizeof(int32_t));
+    if (!t->level || !t->prefix || !t->first || !t->count || !t->child || !t->parent || !t->nchild)
+      return -1;
+    t->cap = nc;
+  }
+  int64_t k = t->nnodes++;
+  t->level[k] = level;
+  t->prefix[k] = prefix;
+  t->first[k] = first;
+  t->count[k] = count;
+  t->child[k] = -1;
+  t->nchild[k] = 0;
+  t->parent[k] = parent;
+  return 0;
+}
+
+void orc_tree_free(orc_tree *t)
+{
+  if (!t) return;
+  free(t->keys); free(t->perm); free(t->xs); free(t->ys); free(t->zs); free(t->ms);
+  free(t->level); free(t->prefix); free(t->first); free(t->count); free(t->child);
+  free(t->parent); free(t->nchild);
+  free(t->mass); free(t->com); free(t->quad); free(t->centre); free(t->side); free(t->delta);
+  free(t->bmin); free(t->bmax); free(t->leaf_of);
+  free(t);
+}
+
+static void tree_moments(orc_tree *t)
+{
+  int64_t nn = t->nnodes;
+  t->mass = calloc(nn, sizeof(double));
+  t->com = calloc(3 * nn, sizeof(double));
+  t->quad = calloc(6 * nn, sizeof(double));
+  t->centre = calloc(3 * nn, sizeof(double));
+  t->side = calloc(nn, sizeof(double));
+  t->delta = calloc(nn, sizeof(double));
+  t->bmin = calloc(3 * nn, sizeof(double));
+  t->bmax = calloc(3 * nn, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t k = 0; k < nn; k++) {
+    int64_t f = t->first[k], c = t->count[k];
+    /* cube geometry from level and prefix: side 2^(e-L); centre
+     * x0 + (2 i + 1) side/2 (one rounding, in the addition) */
+    int L = t->level[k];
+    double s = ldexp(1.0, t->e - L);
+    uint64_t ix = 0, iy = 0, iz = 0;
+    for (int b = 0; b < L; b++) {
+      uint64_t dgt = (t->prefix[k] >> (3 * b)) & 7ull;
+      ix |= ((dgt >> 2) & 1ull) << b;
+      iy |= ((dgt >> 1) & 1ull) << b;
+      iz |= (dgt & 1ull) << b;
+    }
+    t->side[k] = s;
+    t->centre[3 * k + 0] = t->x0[0] + (double)(2 * ix + 1) * (0.5 * s);
+    t->centre[3 * k + 1] = t->x0[1] + (double)(2 * iy + 1) * (0.5 * s);
+    t->centre[3 * k + 2] = t->x0[2] + (double)(2 * iz + 1) * (0.5 * s);
+    /* monopole, centre of mass (Sect. 2.2), tight bounding box */
+    double M = 0, sx = 0, sy = 0, sz = 0;
+    double lo[3] = {t->xs[f], t->ys[f], t->zs[f]}, hi[3] = {t->xs[f], t->ys[f], t->zs[f]};
+    for (int64_t q = f; q < f + c; q++) {
+      M += t->ms[q];
+      sx += t->ms[q] * t->xs[q];
+      sy += t->ms[q] * t->ys[q];
+      sz += t->ms[q] * t->zs[q];
+      double p[3] = {t->xs[q], t->ys[q], t->zs[q]};
+      for (int d = 0; d < 3; d++) {
+        if (p[d] < lo[d]) lo[d] = p[d];
+        if (p[d] > hi[d]) hi[d] = p[d];
+      }
+    }
+    double cx = sx / M, cy = sy / M, cz = sz / M;
+    t->mass[k] = M;
+    t->com[3 * k + 0] = cx;
+    t->com[3 * k + 1] = cy;
+    t->com[3 * k + 2] = cz;
+    for (int d = 0; d < 3; d++) { t->bmin[3 * k + d] = lo[d]; t->bmax[3 * k + d] = hi[d]; }
+    /* traceless quadrupole about the centre of mass:
+     * Q_ab = sum m (3 d_a d_b - |d|^2 delta_ab), order xx, yy, zz, xy, xz, yz */
+    double Q[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t q = f; q < f + c; q++) {
+      double dx = t->xs[q] - cx, dy = t->ys[q] - cy, dz = t->zs[q] - cz;
+      double d2 = dx * dx + dy * dy + dz * dz, mq = t->ms[q];
+      Q[0] += mq * (3 * dx * dx - d2);
+      Q[1] += mq * (3 * dy * dy - d2);
+      Q[2] += mq * (3 * dz * dz - d2);
+      Q[3] += mq * 3 * dx * dy;
+      Q[4] += mq * 3 * dx * dz;
+      Q[5] += mq * 3 * dy * dz;
+    }
+    for (int a = 0; a < 6; a++) t->quad[6 * k + a] = Q[a];
+    /* Dubinski offset delta = |centre of mass - geometric centre| (Eq. opcrit) */
+    double ox = cx - t->centre[3 * k], oy = cy - t->centre[3 * k + 1], oz = cz - t->centre[3 * k + 2];
+    t->delta[k] = sqrt(ox * ox + oy * oy + oz * oz);
+  }
+}
+
+orc_tree *orc_tree_build(int64_t n, const double *x, const double *y, const double *z,
+                         const double *m, int32_t leaf_size)
+{
+  if (n <= 0 || leaf_size < 1) return NULL;
+  orc_tree *t = calloc(1, sizeof(orc_tree));
+  t->n = n;
+  t->leaf_size = leaf_size;
+  root_cube(n, x, y, z, t->x0, &t->e);
+  double scale = ldexp(1.0, ORC_MAXLEVEL - t->e);
+  key_idx *ki = malloc(n * sizeof(key_idx));
+  for (int64_t i = 0; i < n; i++) {
+    uint64_t cx = cell_coord(x[i], t->x0[0], scale);
+    uint64_t cy = cell_coord(y[i], t->x0[1], scale);
+    uint64_t cz = cell_coord(z[i], t->x0[2], scale);
+    ki[i].key = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+    ki[i].idx = i;
+  }
+  /* stable order by (key, original index) */
+  qsort(ki, n, sizeof(key_idx), keyidx_cmp);
+  t->keys = malloc(n * sizeof(uint64_t));
+  t->perm = malloc(n * sizeof(int64_t));
+  t->xs = malloc(n * sizeof(double));
+  t->ys = malloc(n * sizeof(double));
+  t->zs = malloc(n * sizeof(double));
+  t->ms = malloc(n * sizeof(double));
+  for (int64_t p = 0; p < n; p++) {
+    int64_t i = ki[p].idx;
+    t->keys[p] = ki[p].key;
+    t->perm[p] = i;
+    t->xs[p] = x[i];
+    t->ys[p] = y[i];
+    t->zs[p] = z[i];
+    t->ms[p] = m ? m[i] : 1.0;
+  }
+  free(ki);
+  /* canonical oct-tree in level order: a node is (level, key prefix) with a
+   * non-zero count; it is split into its non-empty octants (in octant order)
+   * when it holds more than leaf_size particles and is above the finest
+   * level.  Processing the queue front to back yields nodes ordered by
+   * (level, first particle), children of a node contiguous. */
+  tree_push(t, 0, 0, 0, n, -1);
+  for (int64_t k = 0; k < t->nnodes; k++) {
+    int32_t L = t->level[k];
+    if (t->count[k] <= leaf_size || L >= ORC_MAXLEVEL) continue;
+    int shift = 3 * (ORC_MAXLEVEL - (L + 1));
+    int64_t p = t->first[k], end = t->first[k] + t->count[k];
+    int64_t c0 = t->nnodes;
+    int32_t nc = 0;
+    uint64_t pre = t->prefix[k];
+    for (uint64_t oct = 0; oct < 8; oct++) {
+      int64_t q = p;
+      while (q < end && ((t->keys[q] >> shift) & 7ull) == oct) q++;
+      if (q > p) {
+        if (tree_push(t, L + 1, (pre << 3) | oct, p, q - p, k) != 0) { orc_tree_free(t); return NULL; }
+        nc++;
+      }
+      p = q;
+    }
+    t->child[k] = c0;
+    t->nchild[k] = nc;
+  }
+  t->leaf_of = malloc(n * sizeof(int64_t));
+  for (int64_t k = 0; k < t->nnodes; k++)
+    if (t->nchild[k] == 0)
+      for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++) t->leaf_of[q] = k;
+  tree_moments(t);
+  return t;
+}
+
+int64_t orc_tree_nnodes(const orc_tree *t) { return t->nnodes; }
+
+void orc_tree_root(const orc_tree *t, double *x0, int32_t *e)
+{
+  for (int d = 0; d < 3; d++) x0[d] = t->x0[d];
+  *e = t->e;
+}
+
+void orc_tree_keys(const orc_tree *t, uint64_t *keys, int64_t *perm)
+{
+  if (keys) memcpy(keys, t->keys, t->n * sizeof(uint64_t));
+  if (perm) memcpy(perm, t->perm, t->n * sizeof(int64_t));
+}
+
+void orc_tree_nodes(const orc_tree *t, int32_t *level, uint64_t *prefix, int64_t *first,
+                    int64_t *count, int64_t *child, int32_t *nchild, int64_t *parent)
+{
+  int64_t nn = t->nnodes;
+  if (level) memcpy(level, t->level, nn * sizeof(int32_t));
+  if (prefix) memcpy(prefix, t->prefix, nn * sizeof(uint64_t));
+  if (first) memcpy(first, t->first, nn * sizeof(int64_t));
+  if (count) memcpy(count, t->count, nn * sizeof(int64_t));
+  if (child) memcpy(child, t->child, nn * sizeof(int64_t));
+  if (nchild) memcpy(nchild, t->nchild, nn * sizeof(int32_t));
+  if (parent) memcpy(parent, t->parent, nn * sizeof(int64_t));
+}
+
+void orc_tree_moments(const orc_tree *t, double *mass, double *com, double *quad, double *centre,
+                      double *side, double *delta, double *bmin, double *bmax)
+{
+  int64_t nn = t->nnodes;
+  if (mass) memcpy(mass, t->mass, nn * sizeof(double));
+  if (com) memcpy(com, t->com, 3 * nn * sizeof(double));
+  if (quad) memcpy(quad, t->quad, 6 * nn * sizeof(double));
+  if (centre) memcpy(centre, t->centre, 3 * nn * sizeof(double));
+  if (side) memcpy(side, t->side, nn * sizeof(double));
+  if (delta) memcpy(delta, t->delta, nn * sizeof(double));
+  if (bmin) memcpy(bmin, t->bmin, 3 * nn * sizeof(double));
+  if (bmax) memcpy(bmax, t->bmax, 3 * nn * sizeof(double));
+}
+
+static int is_group(const orc_tree *t, int64_t k, int32_t G)
+{
+  int fits = (t->count[k] <= G) || (t->nchild[k] == 0);
+  int top = (t->parent[k] < 0) || (t->count[t->parent[k]] > G);
+  return fits && top;
+}
+
+int64_t orc_tree_groups(const orc_tree *t, int32_t G, int64_t *group_node)
+{
+  /* walk particle positions: the group containing position p starts there */
+  int64_t ng = 0;
+  int64_t *start = malloc(t->n * sizeof(int64_t));
+  for (int64_t p = 0; p < t->n; p++) start[p] = -1;
+  for (int64_t k = 0; k < t->nnodes; k++)
+    if (is_group(t, k, G)) start[t->first[k]] = k;
+  for (int64_t p = 0; p < t->n; p++)
+    if (start[p] >= 0) {
+      if (group_node) group_node[ng] = start[p];
+      ng++;
+    }
+  free(start);
+  return ng;
+}
+
+/* ===================================================================== */
+/* Geometry predicates (one rounding per operation, fixed order)           */
+/* ===================================================================== */
+
+static double sq_axis(double lo, double hi, double p)
+{
+  double d = 0.0;
+  if (p < lo) d = lo - p;
+  else if (p > hi) d = p - hi;
+  return d * d;
+}
+
+static double box_point_d2(const double *lo, const double *hi, double px, double py, double pz)
+{
+  double s = sq_axis(lo[0], hi[0], px);
+  s = s + sq_axis(lo[1], hi[1], py);
+  s = s + sq_axis(lo[2], hi[2], pz);
+  return s;
+}
+
+static double gap_axis(double lo1, double hi1, double lo2, double hi2)
+{
+  double d = 0.0;
+  if (hi1 < lo2) d = lo2 - hi1;
+  else if (hi2 < lo1) d = lo1 - hi2;
+  return d * d;
+}
+
+static double box_box_d2(const double *lo1, const double *hi1, const double *lo2, const double *hi2)
+{
+  double s = gap_axis(lo1[0], hi1[0], lo2[0], hi2[0]);
+  s = s + gap_axis(lo1[1], hi1[1], lo2[1], hi2[1]);
+  s = s + gap_axis(lo1[2], hi1[2], lo2[2], hi2[2]);
+  return s;
+}
+
+static double pair_r2(double xi, double yi, double zi, double xj, double yj, double zj)
+{
+  double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+  return dx * dx + dy * dy + dz * dz;
+}
+
+/* ===================================================================== */
+/* Force evaluation                                                        */
+/* ===================================================================== */
+
+typedef struct {
+  const orc_params *p;
+  const orc_tree *t;
+  int64_t n, n_gas;
+  /* sorted-order per-particle data */
+  double *vx, *vy, *vz, *u;
+  char *gas;
+  double *h, *nh, *rho, *omega, *zeta, *divv;
+  double *eps, *neps, *ups, *xi;
+  double *ax, *ay, *az, *pot, *dudt, *maxmu;
+  double *P, *cs;
+  int64_t *cnt_node, *cnt_pair, *cnt_sph;
+  int32_t *iters;
+  /* per-node maxima after the solves */
+  double *epsmax, *hmax;
+  int64_t *ngas;
+} ctx_t;
+
+typedef struct {
+  int64_t *idx;
+  int64_t n, cap;
+  int64_t *stack;
+} cand_t;
+
+static void cand_add(cand_t *c, int64_t q)
+{
+  if (c->n == c->cap) {
+    c->cap = c->cap ? 2 * c->cap : 256;
+    c->idx = realloc(c->idx, c->cap * sizeof(int64_t));
+  }
+  c->idx[c->n++] = q;
+}
+
+/* candidates for sink position p: particles (of the solve's set) within R,
+ * found through leaves whose bounding box lies closer than R */
+static void collect(const ctx_t *C, int64_t p, double R, int gas_only, cand_t *c)
+{
+  const orc_tree *t = C->t;
+  double R2 = R * R, px = t->xs[p], py = t->ys[p], pz = t->zs[p];
+  int64_t sp = 0;
+  c->n = 0;
+  c->stack[sp++] = 0;
+  while (sp > 0) {
+    int64_t k = c->stack[--sp];
+    if (gas_only && C->ngas[k] == 0) continue;
+    if (!(box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz) < R2)) continue;
+    if (t->nchild[k] == 0) {
+      for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++) {
+        if (gas_only && !C->gas[q]) continue;
+        if (pair_r2(px, py, pz, t->xs[q], t->ys[q], t->zs[q]) < R2) cand_add(c, q);
+      }
+    } else {
+      for (int32_t a = t->nchild[k] - 1; a >= 0; a--) c->stack[sp++] = t->child[k] + a;
+    }
+  }
+}
+
+typedef struct { double n, sdh, rho, msdh, mdphi, divv; } sums_t;
+
+/* number-density sum and its h-derivative over the candidates, Eqs. (rho0),
+ * (nsum); self term included (j = i) */
+static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, int full, int mode)
+{
+  const orc_tree *t = C->t;
+  sums_t s = {0, 0, 0, 0, 0, 0};
+  double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
+  for (int64_t a = 0; a < c->n; a++) {
+    int64_t q = c->idx[a];
+    double r2 = pair_r2(px, py, pz, t->xs[q], t->ys[q], t->zs[q]);
+    double r = sqrt(r2);
+    if (!(r < 2.0 * h)) continue;
+    double W = orc_W(r, h), dWdh = orc_dWdh(r, h);
+    s.n += W;
+    s.sdh += dWdh;
+    if (full) {
+      double mq = t->ms[q];
+      if (mode == 0) {
+        /* gas: mass density, zeta, velocity divergence */
+        s.rho += mq * W;
+        s.msdh += mq * dWdh;
+        if (r > 0.0) {
+          double g = orc_dWdr(r, h) / r; /* grad_i W = g (x_i - x_j) */
+          double dvx = C->vx[p] - C->vx[q], dvy = C->vy[p] - C->vy[q], dvz = C->vz[p] - C->vz[q];
+          s.divv += g * (dvx * (px - t->xs[q]) + dvy * (py - t->ys[q]) + dvz * (pz - t->zs[q]));
+        }
+      } else {
+        /* softening: mass-weighted d phi / d eps (Eq. zeta) */
+        s.mdphi += mq * orc_dphideps(r, h);
+      }
+    }
+  }
+  return s;
+}
+
+/* Self-consistent length for one sink (Sect. 2.1 "iterative method",
+ * Eq. (iter); Sect. 3 Eq. (hn)).  The relation eta = h n^(1/3) is solved as
+ * g(h) = h^3 n(h) - eta^3 = 0; g is non-decreasing in h (each h^3 W term is),
+ * so the root is unique and a bracket is kept.  g'(h) = 3 h^2 n Omega*, the
+ * printed f' = -(3 n/h) Upsilon rescaled by -h^3.  Newton steps that
+ * leave the bracket fall back to bisection; iteration stops when the step is
+ * below tol times the starting value.  Candidates are gathered once within
+ * 2 h_guess (1 + kappa) and the search radius is doubled when the root lies
+ * beyond it (Sect. 3.1, enlarged search radius). */
+static int solve_length(const ctx_t *C, int64_t p, int gas_only, double eta, double guess,
+                        cand_t *c, double *h_out, int32_t *iters)
+{
+  const orc_params *P = C->p;
+  int64_t set_size = gas_only ? C->n_gas : C->n;
+  double eta3 = eta * eta * eta;
+  if (!((double)set_size / M_PI > eta3) || !(guess > 0.0)) {
+    *h_out = guess > 0.0 ? guess : 0.0;
+    return 0;
+  }
+  double hi = guess * (1.0 + P->kappa);
+  int grow = 0;
+  for (;;) {
+    collect(C, p, 2.0 * hi, gas_only, c);
+    sums_t s = kernel_sums(C, p, hi, c, 0, 0);
+    (*iters)++;
+    if (hi * hi * hi * s.n - eta3 >= 0.0) break;
+    hi *= 2.0;
+    if (++grow > 200) { *h_out = hi; return 0; }
+  }
+  double lo = 0.0, h = guess, hinit = guess;
+  int ok = 0;
+  for (int it = 0; it < P->h_maxit; it++) {
+    sums_t s = kernel_sums(C, p, h, c, 0, 0);
+    (*iters)++;
+    double g = h * h * h * s.n - eta3;
+    double gp = 3.0 * h * h * s.n + h * h * h * s.sdh;
+    if (g < 0.0) lo = h;
+    else hi = h;
+    double hn = h - g / gp;
+    if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+    if (fabs(hn - h) < P->h_tol * hinit) { h = hn; ok = 1; break; }
+    h = hn;
+  }
+  *h_out = h;
+  return ok;
+}
+
+static double cold_guess(const ctx_t *C, int64_t p, int gas_only, double eta)
+{
+  const orc_tree *t = C->t;
+  int64_t k = t->leaf_of[p];
+  double cnt = (double)t->count[k];
+  if (gas_only && C->ngas[k] > 0) cnt = (double)C->ngas[k];
+  double s = t->side[k];
+  return eta * cbrt(s * s * s / cnt);
+}
+
+static int64_t total_noconv = 0;
+
+static void density_phase(ctx_t *C, const double *h_in, const double *eps_in)
+{
+  const orc_params *P = C->p;
+  const orc_tree *t = C->t;
+  int64_t n = C->n;
+  int64_t noconv = 0;
+#pragma omp parallel reduction(+ : noconv)
+  {
+    cand_t c = {0};
+    c.stack = malloc((8 * 22 * 8 + t->nnodes + 16) * sizeof(int64_t));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t p = 0; p < n; p++) {
+      int64_t i = t->perm[p];
+      /* gas: smoothing length over gas neighbours (Sect. 3, Eqs. hn, nsum) */
+      if (P->hydro && C->gas[p]) {
+        double guess = (h_in && h_in[i] > 0.0) ? h_in[i] : cold_guess(C, p, 1, P->eta_h);
+        double h;
+        if (!solve_length(C, p, 1, P->eta_h, guess, &c, &h, &C->iters[p])) noconv++;
+        double hr = h * (1.0 + P->kappa);
+        collect(C, p, 2.0 * hr, 1, &c);
+        sums_t s = kernel_sums(C, p, h, &c, 1, 0);
+        C->h[p] = h;
+        C->nh[p] = s.n;
+        C->rho[p] = s.rho;
+        /* grad-h terms, Sect. 3 Eq. (drhodr) and the definitions after it:
+         * Omega* = 1 - (dh/dn) sum dW/dh, zeta = (dh/dn) sum m dW/dh,
+         * dh/dn = -h/(3 n) */
+        C->omega[p] = 1.0 + (h / (3.0 * s.n)) * s.sdh;
+        C->zeta[p] = -(h / (3.0 * s.n)) * s.msdh;
+        /* velocity divergence (Sect. 2.1), with the gas kernel */
+        C->divv[p] = -s.divv / (s.n * C->omega[p]);
+      }
+      /* all species: adaptive softening length over all neighbours
+       * (Sect. 2.1, Eq. etan; Sect. 3.2, independent eps and h) */
+      if (P->gravity) {
+        if (P->soft_mode == ORC_SOFT_CONSTANT) {
+          C->eps[p] = eps_in[i];
+          C->ups[p] = 1.0;
+          C->xi[p] = 0.0;
+          C->neps[p] = 0.0;
+        } else {
+          double guess = (eps_in && eps_in[i] > 0.0) ? eps_in[i] : cold_guess(C, p, 0, P->eta_eps);
+          double e;
+          if (!solve_length(C, p, 0, P->eta_eps, guess, &c, &e, &C->iters[p])) noconv++;
+          double er = e * (1.0 + P->kappa);
+          collect(C, p, 2.0 * er, 0, &c);
+          sums_t s = kernel_sums(C, p, e, &c, 1, 1);
+          C->eps[p] = e;
+          C->neps[p] = s.n;
+          /* Upsilon = 1 - (d eps/dn) sum dW/d eps; xi~ = (d eps/dn) sum m dphi/deps
+           * (Eq. zeta with the neighbour mass inside the sum, so that the
+           * force is the gradient of the softened Lagrangian for unequal
+           * masses) */
+          C->ups[p] = 1.0 + (e / (3.0 * s.n)) * s.sdh;
+          C->xi[p] = (P->soft_mode == ORC_SOFT_ADAPTIVE) ? -(e / (3.0 * s.n)) * s.mdphi : 0.0;
+        }
+      }
+    }
+    free(c.idx);
+    free(c.stack);
+  }
+  total_noconv = noconv;
+}
+
+/* per-node maxima of eps (all) and h (gas), gas counts */
+static void node_maxima(ctx_t *C)
+{
+  const orc_tree *t = C->t;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t k = 0; k < t->nnodes; k++) {
+    double em = 0.0, hm = 0.0;
+    for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++) {
+      if (C->eps[q] > em) em = C->eps[q];
+      if (C->gas[q] && C->h[q] > hm) hm = C->h[q];
+    }
+    C->epsmax[k] = em;
+    C->hmax[k] = hm;
+  }
+}
+
+/* ---- gravity ----------------------------------------------------------- */
+
+/* Far-field node: monopole plus traceless quadrupole about the centre of
+ * mass (Sect. 2.2), unsoftened. r = x_i - com.
+ *   a = -G M r/r^3 + G [Q r / r^5 - 5/2 (r.Q.r) r / r^7]
+ *   phi = -G M / r - G/2 (r.Q.r) / r^5 */
+static void far_node(const ctx_t *C, int64_t k, double px, double py, double pz, double *a,
+                     double *pot)
+{
+  const orc_tree *t = C->t;
+  double G = C->p->G;
+  double dx = px - t->com[3 * k], dy = py - t->com[3 * k + 1], dz = pz - t->com[3 * k + 2];
+  double r2 = dx * dx + dy * dy + dz * dz;
+  double r = sqrt(r2), M = t->mass[k];
+  double ir3 = 1.0 / (r2 * r);
+  a[0] -= G * M * dx * ir3;
+  a[1] -= G * M * dy * ir3;
+  a[2] -= G * M * dz * ir3;
+  *pot -= G * M / r;
+  if (C->p->quadrupole) {
+    const double *Q = &t->quad[6 * k];
+    double qx = Q[0] * dx + Q[3] * dy + Q[4] * dz;
+    double qy = Q[3] * dx + Q[1] * dy + Q[5] * dz;
+    double qz = Q[4] * dx + Q[5] * dy + Q[2] * dz;
+    double rqr = dx * qx + dy * qy + dz * qz;
+    double ir5 = ir3 / r2, ir7 = ir5 / r2;
+    a[0] += G * (qx * ir5 - 2.5 * rqr * dx * ir7);
+    a[1] += G * (qy * ir5 - 2.5 * rqr * dy * ir7);
+    a[2] += G * (qz * ir5 - 2.5 * rqr * dz * ir7);
+    *pot -= 0.5 * G * rqr * ir5;
+  }
+}
+
+/* Softened pair j -> i (Sect. 2.1 Eq. dLgravdr, App. B):
+ *   a_i -= G m_j 1/2 [phi'(r, eps_i) + phi'(r, eps_j)] r_hat
+ *   a_i -= G/2 [xi_i/Ups_i dW/dr(r, eps_i) + (m_j/m_i) xi_j/Ups_j dW/dr(r, eps_j)] r_hat
+ * with r_hat = (x_i - x_j)/r.  The correction's mass weighting is the one
+ * that makes the force the gradient of the softened Lagrangian for unequal
+ * masses (xi~ carries the neighbour masses); for equal masses it coincides
+ * with the printed form. */
+static void near_pair(const ctx_t *C, int64_t p, int64_t q, double *a, double *pot)
+{
+  const orc_tree *t = C->t;
+  double G = C->p->G;
+  double dx = t->xs[p] - t->xs[q], dy = t->ys[p] - t->ys[q], dz = t->zs[p] - t->zs[q];
+  double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
+  double ei = C->eps[p], ej = C->eps[q], mj = t->ms[q];
+  *pot += G * mj * 0.5 * (orc_phi(r, ei) + orc_phi(r, ej));
+  if (!(r > 0.0)) return;
+  double f = G * mj * 0.5 * (orc_dphidr(r, ei) + orc_dphidr(r, ej));
+  if (C->p->soft_mode == ORC_SOFT_ADAPTIVE) {
+    f += 0.5 * G * ((C->xi[p] / C->ups[p]) * orc_dWdr(r, ei) +
+                    (mj / t->ms[p]) * (C->xi[q] / C->ups[q]) * orc_dWdr(r, ej));
+  }
+  a[0] -= f * dx / r;
+  a[1] -= f * dy / r;
+  a[2] -= f * dz / r;
+}
+
+/* opening test (Sect. 2.2 Eq. opcrit, Dubinski): accept a node when the sink
+ * is farther from its centre of mass than l/theta + delta (strictly), and no
+ * particle of the node can lie within the softening reach 2 max(eps_i,
+ * eps_node) of the sink ("softening-clear"); accepted nodes are unsoftened. */
+static int accept_point(const ctx_t *C, int64_t k, double px, double py, double pz, double ei)
+{
+  const orc_params *P = C->p;
+  const orc_tree *t = C->t;
+  if (!(P->theta > 0.0)) return 0;
+  double rm = t->side[k] / P->theta + t->delta[k];
+  double d2 = pair_r2(px, py, pz, t->com[3 * k], t->com[3 * k + 1], t->com[3 * k + 2]);
+  if (!(d2 > rm * rm)) return 0;
+  double s = 2.0 * (ei > C->epsmax[k] ? ei : C->epsmax[k]);
+  return box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz) >= s * s;
+}
+
+static int accept_box(const ctx_t *C, int64_t k, const double *lo, const double *hi, double emax)
+{
+  const orc_params *P = C->p;
+  const orc_tree *t = C->t;
+  if (!(P->theta > 0.0)) return 0;
+  double rm = t->side[k] / P->theta + t->delta[k];
+  double d2 = box_point_d2(lo, hi, t->com[3 * k], t->com[3 * k + 1], t->com[3 * k + 2]);
+  if (!(d2 > rm * rm)) return 0;
+  double s = 2.0 * (emax > C->epsmax[k] ? emax : C->epsmax[k]);
+  return box_box_d2(lo, hi, &t->bmin[3 * k], &t->bmax[3 * k]) >= s * s;
+}
+
+static void self_term(const ctx_t *C, int64_t p, double *pot)
+{
+  *pot += C->p->G * C->t->ms[p] * orc_phi(0.0, C->eps[p]);
+}
+
+static void gravity_particle_walk(ctx_t *C)
+{
+  const orc_tree *t = C->t;
+#pragma omp parallel
+  {
+    int64_t *stack = malloc((8 * 22 * 8 + t->nnodes + 16) * sizeof(int64_t));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t p = 0; p < C->n; p++) {
+      double a[3] = {0, 0, 0}, pot = 0.0;
+      int64_t nnode = 0, npair = 0, sp = 0;
+      double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
+      stack[sp++] = 0;
+      while (sp > 0) {
+        int64_t k = stack[--sp];
+        if (accept_point(C, k, px, py, pz, C->eps[p])) {
+          far_node(C, k, px, py, pz, a, &pot);
+          nnode++;
+        } else if (t->nchild[k] == 0) {
+          for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++)
+            if (q != p) { near_pair(C, p, q, a, &pot); npair++; }
+        } else {
+          for (int32_t b = t->nchild[k] - 1; b >= 0; b--) stack[sp++] = t->child[k] + b;
+        }
+      }
+      self_term(C, p, &pot);
+      C->ax[p] = a[0]; C->ay[p] = a[1]; C->az[p] = a[2];
+      C->pot[p] = pot;
+      C->cnt_node[p] = nnode;
+      C->cnt_pair[p] = npair;
+    }
+    free(stack);
+  }
+}
+
+/* Group mode: every sink of a group (a maximal node of at most group_size
+ * particles) receives the interaction set found with the group's bounding box
+ * and its largest eps in the opening test.  The set is a superset of each
+ * member's per-particle set, so accuracy is at least that of the
+ * per-particle walk. */
+static void gravity_group_walk(ctx_t *C)
+{
+  const orc_tree *t = C->t;
+  int32_t G = C->p->group_size;
+  int64_t ng = orc_tree_groups(t, G, NULL);
+  int64_t *gn = malloc((ng + 1) * sizeof(int64_t));
+  orc_tree_groups(t, G, gn);
+#pragma omp parallel
+  {
+    int64_t *stack = malloc((8 * 22 * 8 + t->nnodes + 16) * sizeof(int64_t));
+    int64_t *acc = malloc((t->nnodes + 1) * sizeof(int64_t));
+    int64_t *lvs = malloc((t->nnodes + 1) * sizeof(int64_t));
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t g = 0; g < ng; g++) {
+      int64_t kg = gn[g];
+      const double *lo = &t->bmin[3 * kg], *hi = &t->bmax[3 * kg];
+      double emax = C->epsmax[kg];
+      int64_t na = 0, nl = 0, sp = 0;
+      stack[sp++] = 0;
+      while (sp > 0) {
+        int64_t k = stack[--sp];
+        if (accept_box(C, k, lo, hi, emax)) acc[na++] = k;
+        else if (t->nchild[k] == 0) lvs[nl++] = k;
+        else for (int32_t b = t->nchild[k] - 1; b >= 0; b--) stack[sp++] = t->child[k] + b;
+      }
+      for (int64_t p = t->first[kg]; p < t->first[kg] + t->count[kg]; p++) {
+        double a[3] = {0, 0, 0}, pot = 0.0;
+        int64_t npair = 0;
+        double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
+        for (int64_t b = 0; b < na; b++) far_node(C, acc[b], px, py, pz, a, &pot);
+        for (int64_t b = 0; b < nl; b++) {
+          int64_t k = lvs[b];
+          for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++)
+            if (q != p) { near_pair(C, p, q, a, &pot); npair++; }
+        }
+        self_term(C, p, &pot);
+        C->ax[p] = a[0]; C->ay[p] = a[1]; C->az[p] = a[2];
+        C->pot[p] = pot;
+        C->cnt_node[p] = na;
+        C->cnt_pair[p] = npair;
+      }
+    }
+    free(stack); free(acc); free(lvs);
+  }
+  free(gn);
+}
+
+/* O(N^2): every pair softened and corrected, the definition the tree
+ * approximates (theta -> 0). */
+static void gravity_direct(ctx_t *C)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t p = 0; p < C->n; p++) {
+    double a[3] = {0, 0, 0}, pot = 0.0;
+    for (int64_t q = 0; q < C->n; q++)
+      if (q != p) near_pair(C, p, q, a, &pot);
+    self_term(C, p, &pot);
+    C->ax[p] = a[0]; C->ay[p] = a[1]; C->az[p] = a[2];
+    C->pot[p] = pot;
+    C->cnt_node[p] = 0;
+    C->cnt_pair[p] = C->n - 1;
+  }
+}
+
+/* ---- SPH ---------------------------------------------------------------- */
+
+/* Pair i <- j of the variable-mass Lagrangian SPH equations (Sect. 3 Eqs.
+ * motionvarmass, thermalvarmass, Sect. 3.3 Eq. mu_visc; App. B).  Convention:
+ * grad_i W_ij(h) = dW/dr(r, h) (x_i - x_j)/r.  With it the equations read
+ *   a_i  = -sum_j m_j [A_ij gW(h_i) + A_ji gW(h_j) + Pi_ij Gbar_ij]
+ *   du_i =  sum_j m_j [A_ij v_ij . gW(h_i) + 1/2 Pi_ij v_ij . Gbar_ij]
+ * A_ij = P_i f_ij / rho_i^2, f_ij = 1 + zeta_i/(m_j Omega*_i),
+ * Gbar_ij = 1/2 [f_ij gW(h_i) + f_ji gW(h_j)], v_ij = v_i - v_j; this is the
+ * printed set once the 1/m_i of dv/dt and the orientation of the gradient are
+ * made consistent (pressure repulsive, compression heating).  Pi_ij is the
+ * Monaghan-Gingold term with hbar, cbar, rhobar the arithmetic pair means and
+ * eta^2 = av_eps2 hbar^2; it acts only on approaching pairs. */
+static void sph_pair(const ctx_t *C, int64_t p, int64_t q, double *a, double *du, double *mumax)
+{
+  const orc_params *P = C->p;
+  const orc_tree *t = C->t;
+  double dx = t->xs[p] - t->xs[q], dy = t->ys[p] - t->ys[q], dz = t->zs[p] - t->zs[q];
+  double r2 = dx * dx + dy * dy + dz * dz;
+  if (!(r2 > 0.0)) return;
+  double r = sqrt(r2);
+  double hi = C->h[p], hj = C->h[q], mi = t->ms[p], mj = t->ms[q];
+  double gi = (P->tc92 ? orc_dWdr_tc92(r, hi) : orc_dWdr(r, hi)) / r;
+  double gj = (P->tc92 ? orc_dWdr_tc92(r, hj) : orc_dWdr(r, hj)) / r;
+  double fij = 1.0 + C->zeta[p] / (mj * C->omega[p]);
+  double fji = 1.0 + C->zeta[q] / (mi * C->omega[q]);
+  double Ai = C->P[p] * fij / (C->rho[p] * C->rho[p]);
+  double Aj = C->P[q] * fji / (C->rho[q] * C->rho[q]);
+  double vx = C->vx[p] - C->vx[q], vy = C->vy[p] - C->vy[q], vz = C->vz[p] - C->vz[q];
+  double vd = vx * dx + vy * dy + vz * dz;
+  double s = mj * (Ai * gi + Aj * gj);
+  double e = mj * Ai * gi * vd;
+  if (vd < 0.0) {
+    double hb = 0.5 * (hi + hj);
+    double mu = hb * vd / (r2 + P->av_eps2 * hb * hb);
+    double cb = 0.5 * (C->cs[p] + C->cs[q]);
+    double rb = 0.5 * (C->rho[p] + C->rho[q]);
+    double Pi = (-P->alpha * cb * mu + P->beta * mu * mu) / rb;
+    double Gb = 0.5 * (fij * gi + fji * gj);
+    s += mj * Pi * Gb;
+    e += 0.5 * mj * Pi * Gb * vd;
+    if (fabs(mu) > *mumax) *mumax = fabs(mu);
+  }
+  a[0] -= s * dx;
+  a[1] -= s * dy;
+  a[2] -= s * dz;
+  *du += e;
+}
+
+/* symmetric neighbour condition r < 2 max(h_i, h_j) (Sect. 3.1) */
+static int sph_nbr(const ctx_t *C, int64_t p, int64_t q)
+{
+  const orc_tree *t = C->t;
+  double r2 = pair_r2(t->xs[p], t->ys[p], t->zs[p], t->xs[q], t->ys[q], t->zs[q]);
+  double R = 2.0 * (C->h[p] > C->h[q] ? C->h[p] : C->h[q]);
+  return r2 < R * R;
+}
+
+static void sph_phase(ctx_t *C)
+{
+  const orc_params *P = C->p;
+  const orc_tree *t = C->t;
+  for (int64_t p = 0; p < C->n; p++) {
+    if (!C->gas[p]) continue;
+    C->P[p] = (P->gamma - 1.0) * C->rho[p] * C->u[p];
+    C->cs[p] = sqrt(P->gamma * (P->gamma - 1.0) * C->u[p]);
+  }
+#pragma omp parallel
+  {
+    int64_t *stack = malloc((8 * 22 * 8 + t->nnodes + 16) * sizeof(int64_t));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t p = 0; p < C->n; p++) {
+      if (!C->gas[p]) continue;
+      double a[3] = {0, 0, 0}, du = 0.0, mumax = 0.0;
+      int64_t npair = 0;
+      if (P->nbr_mode == ORC_NBR_BRUTE) {
+        for (int64_t q = 0; q < C->n; q++)
+          if (q != p && C->gas[q] && sph_nbr(C, p, q)) { sph_pair(C, p, q, a, &du, &mumax); npair++; }
+      } else {
+        int64_t sp = 0;
+        double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
+        stack[sp++] = 0;
+        while (sp > 0) {
+          int64_t k = stack[--sp];
+          if (C->ngas[k] == 0) continue;
+          double R = 2.0 * (C->h[p] > C->hmax[k] ? C->h[p] : C->hmax[k]);
+          if (!(box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz) < R * R)) continue;
+          if (t->nchild[k] == 0) {
+            for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++)
+              if (q != p && C->gas[q] && sph_nbr(C, p, q)) { sph_pair(C, p, q, a, &du, &mumax); npair++; }
+          } else {
+            for (int32_t b = t->nchild[k] - 1; b >= 0; b--) stack[sp++] = t->child[k] + b;
+          }
+        }
+      }
+      C->ax[p] += a[0];
+      C->ay[p] += a[1];
+      C->az[p] += a[2];
+      C->dudt[p] = du;
+      C->maxmu[p] = mumax;
+      C->cnt_sph[p] = npair;
+    }
+    free(stack);
+  }
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+int orc_compute_forces(const orc_params *p, orc_run *r)
+{
+  if (!p || !r || r->n <= 0 || r->n_gas < 0 || r->n_gas > r->n) return -1;
+  if (!r->x || !r->y || !r->z || !r->m) return -1;
+  if (p->gravity && p->soft_mode == ORC_SOFT_CONSTANT && !r->eps_in) return -1;
+  int64_t n = r->n;
+  orc_tree *t = orc_tree_build(n, r->x, r->y, r->z, r->m, p->leaf_size);
+  if (!t) return -2;
+  ctx_t C;
+  memset(&C, 0, sizeof(C));
+  C.p = p;
+  C.t = t;
+  C.n = n;
+  C.n_gas = r->n_gas;
+  C.vx = calloc(n, sizeof(double)); C.vy = calloc(n, sizeof(double)); C.vz = calloc(n, sizeof(double));
+  C.u = calloc(n, sizeof(double));
+  C.gas = calloc(n, 1);
+  for (int64_t q = 0; q < n; q++) {
+    int64_t i = t->perm[q];
+    C.vx[q] = r->vx ? r->vx[i] : 0.0;
+    C.vy[q] = r->vy ? r->vy[i] : 0.0;
+    C.vz[q] = r->vz ? r->vz[i] : 0.0;
+    C.gas[q] = i < r->n_gas;
+    C.u[q] = (C.gas[q] && r->u) ? r->u[i] : 0.0;
+  }
+  C.h = calloc(n, sizeof(double)); C.nh = calloc(n, sizeof(double)); C.rho = calloc(n, sizeof(double));
+  C.omega = calloc(n, sizeof(double)); C.zeta = calloc(n, sizeof(double)); C.divv = calloc(n, sizeof(double));
+  C.eps = calloc(n, sizeof(double)); C.neps = calloc(n, sizeof(double)); C.ups = calloc(n, sizeof(double));
+  C.xi = calloc(n, sizeof(double));
+  C.ax = calloc(n, sizeof(double)); C.ay = calloc(n, sizeof(double)); C.az = calloc(n, sizeof(double));
+  C.pot = calloc(n, sizeof(double)); C.dudt = calloc(n, sizeof(double)); C.maxmu = calloc(n, sizeof(double));
+  C.P = calloc(n, sizeof(double)); C.cs = calloc(n, sizeof(double));
+  C.cnt_node = calloc(n, sizeof(int64_t)); C.cnt_pair = calloc(n, sizeof(int64_t));
+  C.cnt_sph = calloc(n, sizeof(int64_t));
+  C.iters = calloc(n, sizeof(int32_t));
+  C.epsmax = calloc(t->nnodes, sizeof(double));
+  C.hmax = calloc(t->nnodes, sizeof(double));
+  C.ngas = calloc(t->nnodes, sizeof(int64_t));
+  for (int64_t k = 0; k < t->nnodes; k++) {
+    int64_t g = 0;
+    for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++) g += C.gas[q];
+    C.ngas[k] = g;
+  }
+  /* 1. densities and lengths (Sect. 3.1: first, gather, walk) */
+  density_phase(&C, r->h_in, r->eps_in);
+  node_maxima(&C);
+  /* 2. gravity with the softened near field and its corrections */
+  if (p->gravity) {
+    if (p->walk_mode == ORC_WALK_DIRECT) gravity_direct(&C);
+    else if (p->walk_mode == ORC_WALK_GROUP) gravity_group_walk(&C);
+    else gravity_particle_walk(&C);
+  }
+  /* 3. SPH pressure, viscosity and heating (Sect. 3.1: second walk) */
+  if (p->hydro) sph_phase(&C);
+  r->n_noconv = total_noconv;
+  /* scatter to caller order */
+  for (int64_t q = 0; q < n; q++) {
+    int64_t i = t->perm[q];
+#define OUT(arr, src) if (r->arr) r->arr[i] = C.src[q]
+    OUT(h, h); OUT(nh, nh); OUT(rho, rho); OUT(omega, omega); OUT(zeta, zeta); OUT(divv, divv);
+    OUT(eps, eps); OUT(neps, neps); OUT(ups, ups); OUT(xi, xi);
+    OUT(ax, ax); OUT(ay, ay); OUT(az, az); OUT(pot, pot); OUT(dudt, dudt); OUT(maxmu, maxmu);
+    OUT(cnt_node, cnt_node); OUT(cnt_pair, cnt_pair); OUT(cnt_sph, cnt_sph); OUT(iters, iters);
+#undef OUT
+  }
+  free(C.vx); free(C.vy); free(C.vz); free(C.u); free(C.gas);
+  free(C.h); free(C.nh); free(C.rho); free(C.omega); free(C.zeta); free(C.divv);
+  free(C.eps); free(C.neps); free(C.ups); free(C.xi);
+  free(C.ax); free(C.ay); free(C.az); free(C.pot); free(C.dudt); free(C.maxmu);
+  free(C.P); free(C.cs); free(C.cnt_node); free(C.cnt_pair); free(C.cnt_sph); free(C.iters);
+  free(C.epsmax); free(C.hmax); free(C.ngas);
+  orc_tree_free(t);
+  return 0;
+}
+
+/* ===================================================================== */
+/* Neighbour sets                                                          */
+/* ===================================================================== */
+
+static int cmp_i64_int(const void *a, const void *b)
+{
+  int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+  return (x > y) - (x < y);
+}
+
+int64_t orc_neighbours(int kind, int mode, int64_t n, int64_t n_gas, const double *x,
+                       const double *y, const double *z, const double *len, int32_t leaf_size,
+                       int64_t *offsets, int64_t *idx, int64_t cap)
+{
+  /* The predicates are the symmetric ones of Sect. 3.1 and the correction
+   * criterion of Sect. 2.1, evaluated on caller-order coordinates with
+   * dx = x_j - x_i, r^2 = dx dx + dy dy + dz dz (left to right). */
+  int64_t *cnt = calloc(n, sizeof(int64_t));
+  orc_tree *t = (mode == ORC_NBR_TREE) ? orc_tree_build(n, x, y, z, NULL, leaf_size) : NULL;
+  double *lmax = NULL;
+  if (t) {
+    lmax = calloc(t->nnodes, sizeof(double));
+    for (int64_t k = 0; k < t->nnodes; k++) {
+      double mx = 0.0;
+      for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++) {
+        int64_t j = t->perm[q];
+        if (kind != 2 && j >= n_gas) continue;
+        if (len[j] > mx) mx = len[j];
+      }
+      lmax[k] = mx;
+    }
+  }
+  for (int pass = 0; pass < 2; pass++) {
+    int64_t total = 0;
+    if (pass == 1) {
+      offsets[0] = 0;
+      for (int64_t i = 0; i < n; i++) offsets[i + 1] = offsets[i] + cnt[i];
+      total = offsets[n];
+      if (total > cap) { free(cnt); free(lmax); orc_tree_free(t); return -1; }
+    }
+#pragma omp parallel
+    {
+      int64_t *stack = t ? malloc((8 * 22 * 8 + t->nnodes + 16) * sizeof(int64_t)) : NULL;
+#pragma omp for schedule(dynamic, 16)
+      for (int64_t i = 0; i < n; i++) {
+        int sink = (kind == 2) || (i < n_gas);
+        if (!sink) continue;
+        int64_t c = 0, base = pass ? offsets[i] : 0;
+        if (!t) {
+          for (int64_t j = 0; j < n; j++) {
+            if (kind != 2 && j >= n_gas) continue;
+            if (kind != 0 && j == i) continue;
+            double r2 = pair_r2(x[i], y[i], z[i], x[j], y[j], z[j]);
+            double L = (kind == 0) ? len[i] : (len[i] > len[j] ? len[i] : len[j]);
+            double R = 2.0 * L;
+            if (r2 < R * R) { if (pass) idx[base + c] = j; c++; }
+          }
+        } else {
+          int64_t sp = 0;
+          stack[sp++] = 0;
+          while (sp > 0) {
+            int64_t k = stack[--sp];
+            double L = (kind == 0) ? len[i] : (len[i] > lmax[k] ? len[i] : lmax[k]);
+            double R = 2.0 * L;
+            if (!(box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], x[i], y[i], z[i]) < R * R)) continue;
+            if (t->nchild[k] == 0) {
+              for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++) {
+                int64_t j = t->perm[q];
+                if (kind != 2 && j >= n_gas) continue;
+                if (kind != 0 && j == i) continue;
+                double r2 = pair_r2(x[i], y[i], z[i], x[j], y[j], z[j]);
+                double Lp = (kind == 0) ? len[i] : (len[i] > len[j] ? len[i] : len[j]);
+                double Rp = 2.0 * Lp;
+                if (r2 < Rp * Rp) { if (pass) idx[base + c] = j; c++; }
+              }
+            } else {
+              for (int32_t b = t->nchild[k] - 1; b >= 0; b--) stack[sp++] = t->child[k] + b;
+            }
+          }
+        }
+        if (pass) qsort(idx + base, c, sizeof(int64_t), cmp_i64_int);
+        else cnt[i] = c;
+      }
+      free(stack);
+    }
+    if (pass == 1) {
+      free(cnt); free(lmax); orc_tree_free(t);
+      return total;
+    }
+  }
+  return -1;
+}
+
+/* ===================================================================== */
+/* Direct potential, integrator, time-step, diagnostics                    */
+/* ===================================================================== */
+
+/* Softened potential energy (Sect. 2.1, Eqs. Lagrangian, potential, Lgrav):
+ * V = (G/2) sum_i sum_j m_i m_j phi(r_ij, eps_i), the j = i terms included.
+ * phi is the negative kernel of Eq. (softphi), so V < 0 and L = T - V. */
+double orc_potential_energy(int64_t n, const double *x, const double *y, const double *z,
+                            const double *m, const double *eps, double G)
+{
+  double V = 0.0;
+#pragma omp parallel for reduction(+ : V) schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    double s = 0.0;
+    for (int64_t j = 0; j < n; j++) {
+      double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+      s += m[j] * orc_phi(sqrt(dx * dx + dy * dy + dz * dz), eps[i]);
+    }
+    V += m[i] * s;
+  }
+  return 0.5 * G * V;
+}
+
+/* Kick-drift-kick leapfrog (Sect. 4.1).  phase 0: first half kick and drift,
+ * plus the predicted end-of-step velocity v_n + a_n dt (and u_n + du_n dt)
+ * used by the next force evaluation; phase 1: closing half kick. */
+void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
+                    double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                    double *u, const double *ax, const double *ay, const double *az,
+                    const double *dudt, double *vpx, double *vpy, double *vpz, double *up)
+{
+  for (int64_t i = 0; i < n; i++) {
+    if (phase == 0) {
+      if (vpx) { vpx[i] = vx[i] + dt * ax[i]; vpy[i] = vy[i] + dt * ay[i]; vpz[i] = vz[i] + dt * az[i]; }
+      vx[i] += 0.5 * dt * ax[i];
+      vy[i] += 0.5 * dt * ay[i];
+      vz[i] += 0.5 * dt * az[i];
+      x[i] += dt * vx[i];
+      y[i] += dt * vy[i];
+      z[i] += dt * vz[i];
+      if (i < n_gas) {
+        if (up) up[i] = u[i] + dt * dudt[i];
+        u[i] += 0.5 * dt * dudt[i];
+      }
+    } else {
+      vx[i] += 0.5 * dt * ax[i];
+      vy[i] += 0.5 * dt * ay[i];
+      vz[i] += 0.5 * dt * az[i];
+      if (i < n_gas) u[i] += 0.5 * dt * dudt[i];
+    }
+  }
+}
+
+/* Global time-step (Sect. 4.2): min over particles of the acceleration,
+ * Courant and thermal-energy criteria, all with the same eta. */
+double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double *vx,
+                    const double *vy, const double *vz, const double *u, const double *h,
+                    const double *eps, const double *ax, const double *ay, const double *az,
+                    const double *dudt, const double *divv, const double *maxmu, double eta_dt)
+{
+  (void)vx; (void)vy; (void)vz;
+  double dt = INFINITY;
+  for (int64_t i = 0; i < n; i++) {
+    double amag = sqrt(ax[i] * ax[i] + ay[i] * ay[i] + az[i] * az[i]);
+    double len = eps ? eps[i] : INFINITY;
+    if (i < n_gas && h && h[i] < len) len = h[i];
+    if (amag > 0.0 && len < INFINITY) {
+      double t = eta_dt * sqrt(len / amag);
+      if (t < dt) dt = t;
+    }
+    if (i < n_gas && p->hydro) {
+      double c = sqrt(p->gamma * (p->gamma - 1.0) * u[i]);
+      double den = h[i] * fabs(divv[i]) + c + 1.2 * (p->alpha * c + p->beta * maxmu[i]);
+      if (den > 0.0) {
+        double t = eta_dt * h[i] / den;
+        if (t < dt) dt = t;
+      }
+      if (dudt[i] != 0.0) {
+        double t = eta_dt * fabs(u[i] / dudt[i]);
+        if (t < dt) dt = t;
+      }
+    }
+  }
+  return dt;
+}
+
+void orc_diagnostics(int64_t n, int64_t n_gas, const double *x, const double *y, const double *z,
+                     const double *vx, const double *vy, const double *vz, const double *m,
+                     const double *u, const double *pot, double *out)
+{
+  double ek = 0, eth = 0, V = 0, P[3] = {0, 0, 0}, L[3] = {0, 0, 0};
+  for (int64_t i = 0; i < n; i++) {
+    ek += 0.5 * m[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+    if (i < n_gas && u) eth += m[i] * u[i];
+    if (pot) V += 0.5 * m[i] * pot[i];
+    P[0] += m[i] * vx[i];
+    P[1] += m[i] * vy[i];
+    P[2] += m[i] * vz[i];
+    L[0] += m[i] * (y[i] * vz[i] - z[i] * vy[i]);
+    L[1] += m[i] * (z[i] * vx[i] - x[i] * vz[i]);
+    L[2] += m[i] * (x[i] * vy[i] - y[i] * vx[i]);
+  }
+  out[0] = ek; out[1] = eth; out[2] = V;
+  out[3] = P[0]; out[4] = P[1]; out[5] = P[2];
+  out[6] = L[0]; out[7] = L[1]; out[8] = L[2];
+}
+
+/* batch evaluation of the kernel functions for the tests:
+ * which 0 W, 1 dW/dr, 2 dW/dh, 3 TC92 dW/dr, 4 phi, 5 dphi/dr, 6 dphi/deps */
+void orc_eval_kernel(int which, int64_t n, const double *r, const double *h, double *out)
+{
+  for (int64_t i = 0; i < n; i++) {
+    double v = 0.0;
+    switch (which) {
+      case 0: v = orc_W(r[i], h[i]); break;
+      case 1: v = orc_dWdr(r[i], h[i]); break;
+      case 2: v = orc_dWdh(r[i], h[i]); break;
+      case 3: v = orc_dWdr_tc92(r[i], h[i]); break;
+      case 4: v = orc_phi(r[i], h[i]); break;
+      case 5: v = orc_dphidr(r[i], h[i]); break;
+      case 6: v = orc_dphideps(r[i], h[i]); break;
+      default: v = NAN;
+    }
+    out[i] = v;
+  }
+}
+
+/* Field of a particle set at a point through its node expansion (monopole,
+ * plus the quadrupole when asked) -- the far-field arm of the walk, exposed so
+ * that its error order can be checked against the direct sum. */
+void orc_multipole_field(int64_t n, const double *x, const double *y, const double *z,
+                         const double *m, double px, double py, double pz, int32_t quadrupole,
+                         double *acc, double *pot)
+{
+  orc_tree *t = orc_tree_build(n, x, y, z, m, 1 << 30);
+  orc_params P;
+  memset(&P, 0, sizeof(P));
+  P.G = 1.0;
+  P.quadrupole = quadrupole;
+  ctx_t Cx;
+  memset(&Cx, 0, sizeof(Cx));
+  Cx.p = &P;
+  Cx.t = t;
+  double a[3] = {0, 0, 0}, ph = 0.0;
+  far_node(&Cx, 0, px, py, pz, a, &ph);
+  acc[0] = a[0]; acc[1] = a[1]; acc[2] = a[2];
+  *pot = ph;
+  orc_tree_free(t);
+}

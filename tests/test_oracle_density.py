@@ -1,0 +1,126 @@
+"""Pins of the oracle's h / eps solve and density sums (Sect. 2.1 Eqs. rho0,
+etan, iter; Sect. 3 Eqs. densitySPH, hn, nsum, drhodr; Sect. 3.1 gather and
+symmetric neighbour definitions)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_0912_1786_amd import inputs
+
+LAT = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lattice.json")))
+
+
+def _centre(ic, c):
+    pos = np.stack([ic["x"], ic["y"], ic["z"]], 1)
+    return int(np.argmin(np.sum((pos - c) ** 2, 1)))
+
+
+@pytest.mark.parametrize("eta", ["1.2", "1.2143", "1.1428"])
+def test_lattice_self_consistent_length(orc, eta):
+    ic = inputs.cubic_lattice(14)
+    p = orc.params(eta_h=float(eta), eta_eps=float(eta), gravity=0, hydro=1, h_tol=1e-12)
+    out = orc.compute_forces(ic, p)
+    c = _centre(ic, 7.0)
+    assert out["h"][c] == pytest.approx(LAT["h_over_delta"][eta], abs=2e-6)
+    assert out["rho"][c] - 1.0 == pytest.approx(LAT["rho_excess"][eta], rel=0.1)
+    # every interior particle equal to round-off
+    pos = np.stack([ic["x"], ic["y"], ic["z"]], 1)
+    inner = np.all((pos > 4) & (pos < 10), axis=1)
+    assert np.ptp(out["h"][inner]) < 1e-11
+    # the relation itself: h^3 n = eta^3 at the solution
+    assert out["h"][c] ** 3 * out["nh"][c] == pytest.approx(float(eta) ** 3, rel=1e-12)
+
+
+def test_bcc_mixed_mass_number_density(orc):
+    """Two interpenetrating lattices shifted by half a spacing (the mixed-mass
+    density test of Sect. 3): with number-density summation both species see
+    the same n, independent of their masses."""
+    a = inputs.cubic_lattice(10, spacing=1.0, mass=0.9)
+    b = inputs.cubic_lattice(10, spacing=1.0, mass=0.1)
+    ic = {k: np.concatenate([a[k], b[k] + (0.5 if k in "xyz" else 0.0)]) for k in
+          ("x", "y", "z", "vx", "vy", "vz", "m", "u")}
+    ic["n"] = ic["n_gas"] = a["n"] + b["n"]
+    deff = 0.5 ** (1.0 / 3.0)  # two particles per unit cell
+    p = orc.params(eta_h=1.2, eta_eps=1.2, gravity=0, h_tol=1e-12)
+    out = orc.compute_forces(ic, p)
+    ia, ib = _centre(ic, 5.0), a["n"] + _centre(b, 5.0)
+    assert out["h"][ia] / deff == pytest.approx(out["h"][ib] / deff, rel=1e-10)
+    n0 = 2.0
+    # n / n0 at the self-consistent length (which sits at h/Delta_eff ~ 1.2)
+    assert out["nh"][ia] / n0 == pytest.approx((1.2 / (out["h"][ia] / deff)) ** 3, rel=1e-10)
+    assert abs(out["nh"][ia] / n0 - 1.0) < 0.01
+    # the mass densities differ only through the neighbours' masses
+    assert out["rho"][ia] == pytest.approx(out["rho"][ib], rel=1e-10)
+
+
+def _numpy_brute(kind, x, y, z, L, n_gas):
+    n = x.size
+    res = []
+    for i in range(n):
+        sink = kind == 2 or i < n_gas
+        if not sink:
+            res.append(np.zeros(0, np.int64))
+            continue
+        dx, dy, dz = x - x[i], y - y[i], z - z[i]
+        r2 = dx * dx + dy * dy
+        r2 = r2 + dz * dz
+        Lm = L[i] if kind == 0 else np.maximum(L[i], L)
+        R = 2.0 * Lm
+        ok = r2 < R * R
+        if kind != 2:
+            ok &= np.arange(n) < n_gas
+        if kind != 0:
+            ok[i] = False
+        res.append(np.nonzero(ok)[0])
+    return res
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_neighbour_sets_bit_exact(orc, kind):
+    ic = inputs.two_species_field(n_dm=600, n_gas=600, n_halo=4, seed=2)
+    p = orc.params(nnei=50)
+    out = orc.compute_forces(ic, p)
+    L = out["eps"] if kind == 2 else out["h"]
+    x, y, z = ic["x"], ic["y"], ic["z"]
+    ref = _numpy_brute(kind, x, y, z, L, ic["n_gas"])
+    for mode in (orc.NBR_TREE, orc.NBR_BRUTE):
+        off, idx = orc.neighbours(kind, x, y, z, L, ic["n_gas"], mode=mode, leaf_size=8)
+        for i in range(ic["n"]):
+            assert np.array_equal(idx[off[i]:off[i + 1]], ref[i]), (mode, i)
+
+
+def test_weighted_count_is_nnei(orc):
+    """The solved length holds the kernel-weighted count (4 pi/3)(2h)^3 n at
+    N_nei (Sect. 2.1, eps-n relation) for every particle of a random field."""
+    ic = inputs.random_cloud(8000, seed=3, masses=(1.0, 1.0))
+    p = orc.params(nnei=60, gravity=0, h_tol=1e-10)
+    out = orc.compute_forces(ic, p)
+    h, n = out["h"], out["nh"]
+    assert out["n_noconv"] == 0
+    assert np.allclose(4 * np.pi / 3 * (2 * h) ** 3 * n, 60.0, rtol=1e-9)
+
+
+def test_solution_independent_of_guess(orc):
+    ic = inputs.evrard(2000, seed=6)
+    p = orc.params(gravity=1, hydro=1, h_tol=1e-10)
+    cold = orc.compute_forces(ic, p)
+    warm = orc.compute_forces(ic, p, h_in=cold["h"] * 0.7, eps_in=cold["eps"] * 1.6)
+    assert np.allclose(cold["h"], warm["h"], rtol=1e-11)
+    assert np.allclose(cold["eps"], warm["eps"], rtol=1e-11)
+    assert np.allclose(cold["rho"], warm["rho"], rtol=1e-10)
+    # pure gas with equal etas: eps == h and Upsilon == Omega*
+    assert np.allclose(cold["eps"], cold["h"], rtol=1e-11)
+    assert np.allclose(cold["ups"], cold["omega"], rtol=1e-9)
+    # xi is negative (Sect. 2.1: the correction acts as a negative pressure)
+    assert np.all(cold["xi"] < 0)
+
+
+def test_equal_mass_grad_h_reduction(orc):
+    """Equal masses: zeta = m (1 - Omega*), so f_ij = 1/Omega*_i and the
+    equations reduce to the standard grad-h form (Sect. 3)."""
+    ic = inputs.evrard(1500, seed=7)
+    out = orc.compute_forces(ic, orc.params(gravity=0))
+    m = ic["m"][0]
+    assert np.allclose(out["zeta"], m * (1.0 - out["omega"]), rtol=1e-9, atol=1e-15)
