@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Throughput of the Tree+SPH step on one MI355X.
+
+Workload: the two-species clustered field -- 1,048,576 gas + 1,048,576 dark
+matter particles (DM:gas particle mass 5:1) in 64 Plummer halos inside a unit
+cube, theta = 0.5 with quadrupoles, 60 neighbours for both h and eps,
+adaptive softening with correction terms, FP64.  Inputs are seeded and
+synthetic (paper_0912_1786_amd.inputs) and resident in HBM before timing.
+
+A step is one leapfrog step through the C ABI: kick-drift (half kick, drift,
+predicted v and u), tsph_compute_forces (root cube, keys, radix sort, tree,
+moments, h/eps solves and densities, gravity walk, SPH forces, output
+scatter and time-step criteria) and the closing half kick.
+
+Prints ONE JSON line: particle-steps/s = N * steps / wall time of the timed
+steps, with a roofline entry for the dominant kernel (its duration measured
+with HIP events recorded on its own stream inside the timed region) and the
+FP64 oracle timed on the host's cores on a bounded sample of the same recipe.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (tree gravity+SPH) at N=2M, 1 GPU; served p50/p99 step latency"
+
+# FP64 vector peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# Floating-point operations per interaction in the gravity walk kernel,
+# counted from its source with FMA = 2, add/mul/div/sqrt = 1:
+#   far node, monopole + quadrupole ........................... 60
+#   near pair beyond 2 max(eps) (Newtonian branch) ............ 27
+#   near pair inside 2 max(eps) (softened + correction terms) . 110
+F_NODE, F_PAIR, F_SOFT = 60.0, 27.0, 110.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(nps: int, seed: int):
+    """The FP64 oracle, as it stands, on the same recipe at a reduced size:
+    one full force evaluation plus the two half kicks."""
+    from oracle import build as obuild, oracle as O
+    from paper_0912_1786_amd import inputs
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
+        obuild.build()
+    ic = inputs.two_species_field(n_dm=nps, n_gas=nps, n_halo=64, seed=seed)
+    prm = O.params(nnei=60, theta=0.5, leaf_size=16, group_size=64, walk_mode=O.WALK_GROUP)
+    t0 = time.perf_counter()
+    out = O.compute_forces(ic, prm)
+    st = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in ic.items()}
+    O.kick_drift(st, 1e-4, 0, (out["ax"], out["ay"], out["az"]), out["dudt"])
+    O.kick_drift(st, 1e-4, 1, (out["ax"], out["ay"], out["az"]), out["dudt"])
+    dt = time.perf_counter() - t0
+    n = ic["n"]
+    return {"value": n / dt, "unit": "particle-steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"same recipe at N={n} (2x{nps}, seed {seed}): one force evaluation "
+                      f"(tree, h/eps solves, group walk, SPH) + KDK kicks, {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--nps", type=int, default=1 << 20, help="particles per species")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--leaf", type=int, default=16)
+    ap.add_argument("--group", type=int, default=64)
+    ap.add_argument("--cpu-nps", type=int, default=1 << 18, help="per-species size of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this engine has no multi-GPU path (each GPU would run its own "
+              "simulations); run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0912_1786_amd import inputs, tsph
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    ic = inputs.two_species_field(n_dm=args.nps, n_gas=args.nps, n_halo=64, seed=args.seed)
+    n = ic["n"]
+    prm = tsph.tsph_default_params(nnei=60, theta=0.5, leaf_size=args.leaf, group_size=args.group)
+    sim = tsph.Simulation(ic, prm, want_pot=False)
+    log(f"[bench] N={n} inputs ready in {time.time() - t0:.1f}s; arena "
+        f"{tsph.tsph_bytes_required(n, prm) / 2**30:.2f} GiB")
+    # first evaluation (cold start of h and eps) and the global time-step
+    sim.compute_forces()
+    dt = sim.timestep()
+    flags, noconv = sim.flags()
+    log(f"[bench] first force pass done: dt={dt:.3e} flags={flags:#x} noconv={noconv}")
+    for w in range(args.warmup):
+        sim.step(dt)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {w + 1}/{args.warmup} done")
+    tsph.tsph_timing(sim.ctx, True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k].record()
+        sim.step(dt)
+    evs[args.steps].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    phases, calls = tsph.tsph_phase_times(sim.ctx)
+    flags, noconv = sim.flags()
+    total_ms = sum(step_ms)
+    log(f"[bench] timed {args.steps} steps: {total_ms:.1f} ms (wall {wall * 1e3:.1f} ms); per step "
+        + ", ".join(f"{m:.1f}" for m in step_ms))
+    log("[bench] phase ms/step: " + ", ".join(f"{k}={v / calls:.2f}" for k, v in phases.items()))
+    value = n * args.steps / (total_ms / 1e3)
+
+    # roofline of the dominant kernel (the gravity walk)
+    dom = max(phases, key=lambda k: phases[k])
+    grav_ms = phases["gravity"] / calls
+    roof = None
+    cpath = os.path.join(ROOT, "oracle", "algorithmic_counts.json")
+    if os.path.exists(cpath):
+        c = json.load(open(cpath))
+        if c["n"] == n and c["leaf_size"] == args.leaf:
+            soft = c["softened_pairs_per_particle"]
+            per_particle = (c["far_nodes_per_particle"] * F_NODE
+                            + (c["near_pairs_per_particle"] - soft) * F_PAIR + soft * F_SOFT)
+            flops = n * per_particle
+            achieved = flops / (grav_ms / 1e3) / 1e12
+            roof = {"kernel": "k_gravity", "bound": "alu", "achieved": round(achieved, 3),
+                    "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                    "traffic": None, "algorithmic_flop_per_launch": flops, "avg_launch_ms": round(grav_ms, 3),
+                    "dominant_phase": dom}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_ms / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "two_species_field_2M", "n": n, "n_gas": ic["n_gas"], "n_dm": n - ic["n_gas"],
+                   "halos": 64, "mass_ratio_dm_gas": 5, "theta": 0.5, "quadrupole": True, "nnei": 60,
+                   "softening": "adaptive+corrections", "leaf_size": args.leaf, "group_size": args.group,
+                   "precision": "fp64", "seed": args.seed},
+        "phase_ms_per_step": {k: round(v / calls, 3) for k, v in phases.items()},
+        "median_step_ms": round(sorted(step_ms)[len(step_ms) // 2], 3),
+        "device_flags": flags,
+        "roofline": roof,
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_nps, args.seed)
+        log(f"[bench] oracle: {out['cpu_baseline']['value']:.3e} particle-steps/s on "
+            f"{out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

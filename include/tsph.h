@@ -1,0 +1,198 @@
+/*
+ * tsph.h -- C ABI of the MI355X (gfx950) Tree+SPH per-step force engine.
+ *
+ * The library evaluates, for one time-step of a self-gravitating gas + dark
+ * matter particle system, the quantities of EvoL's force pass (Merlin et al.,
+ * "EvoL: the new Padova T-SPH parallel code for cosmological simulations -
+ * I", arXiv:0912.1786):
+ *
+ *   - the Barnes-Hut oct-tree over Morton-sorted particles with monopole and
+ *     quadrupole node moments (Sect. 2.2) and the Dubinski opening test
+ *     (Eq. opcrit);
+ *   - the self-consistent smoothing length h of gas particles and softening
+ *     length eps of all particles from eta = h n^(1/3) (Sect. 2.1 Eqs. rho0,
+ *     etan, iter; Sect. 3 Eqs. hn, nsum; Sect. 3.2), with the mass density,
+ *     the grad-h terms Omega*, zeta (Eq. drhodr) and the softening terms
+ *     Upsilon, xi (Eq. zeta);
+ *   - the gravitational acceleration with the symmetrised spline-softened
+ *     near field and its adaptive-softening correction terms (Eq. dLgravdr,
+ *     App. B);
+ *   - the variable-mass SPH acceleration and heating with Monaghan-Gingold
+ *     viscosity (Eqs. motionvarmass, thermalvarmass, mu_visc; App. B);
+ *   - the kick-drift-kick leapfrog with predicted velocities (Sect. 4.1), the
+ *     global time-step criteria (Sect. 4.2) and energy/momentum diagnostics.
+ *
+ * Conventions
+ *   - Units with G = params.G (1 by default).
+ *   - Particles are in *caller order*; gas particles are indices [0, n_gas),
+ *     every per-particle array has n entries (entries of the non-gas
+ *     particles in gas-only arrays are ignored on input and written as 0).
+ *   - Every pointer inside tsph_state is a DEVICE pointer to FP64 data owned
+ *     by the caller.  The library never frees or reallocates them.
+ *   - A context owns all scratch memory (keys, permutation, nodes, lists,
+ *     flags), sized once by tsph_create for capacity_n particles.  No
+ *     compute call allocates memory.
+ *   - A context is used from one host thread and one stream at a time.
+ *     Separate contexts may run concurrently on separate streams.
+ *   - Stream arguments are hipStream_t values passed as void* (NULL = the
+ *     default stream).  Calls enqueue work and return; they do not wait for
+ *     the device except where stated.
+ *   - No C++ exception crosses the ABI.  Errors are returned as tsph_status;
+ *     tsph_last_error gives the text of the last failure on a context.
+ *   - Device-side conditions (list overflow, non-convergence, non-finite
+ *     values) set bits in a device flag word that tsph_read_flags returns.
+ */
+#ifndef TSPH_H
+#define TSPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TSPH_OK = 0,
+  TSPH_EINVAL = -1,     /* invalid argument (null pointer, size, parameter)   */
+  TSPH_ENOMEM = -2,     /* device allocation failed in tsph_create            */
+  TSPH_EHIP = -3,       /* a HIP runtime call failed                          */
+  TSPH_ECAPACITY = -4,  /* n exceeds the context capacity                     */
+  TSPH_ENOCONV = -5,    /* a length solve did not converge (tsph_read_flags)  */
+  TSPH_EOVERFLOW = -6   /* a device list or the node array overflowed        */
+} tsph_status;
+
+enum { TSPH_SOFT_ADAPTIVE = 0,        /* eps solved, correction terms on (Sect. 2.1) */
+       TSPH_SOFT_CONSTANT = 1,        /* eps given by the caller, no corrections     */
+       TSPH_SOFT_ADAPTIVE_NOCORR = 2  /* eps solved, correction terms off            */ };
+enum { TSPH_FP64 = 0 };
+enum { TSPH_KD_FIRST = 0, TSPH_KD_SECOND = 1 };
+
+/* device flag bits */
+#define TSPH_FLAG_NODE_CAPACITY 0x1u  /* tree needed more nodes than reserved        */
+#define TSPH_FLAG_STACK_OVERFLOW 0x2u /* a walk stack overflowed (result invalid)    */
+#define TSPH_FLAG_LIST_OVERFLOW 0x4u  /* a candidate list overflowed (result invalid) */
+#define TSPH_FLAG_NOCONV 0x8u         /* an h/eps solve did not converge             */
+#define TSPH_FLAG_NONFINITE 0x10u     /* a non-finite input position or mass         */
+#define TSPH_FLAG_INTERNAL 0x20u      /* an internal index check failed (bug)        */
+
+typedef struct {
+  double G;            /* gravitational constant                               */
+  double theta;        /* opening parameter; 0 opens every node (direct sum)   */
+  int32_t quadrupole;  /* 1: far nodes carry quadrupoles (Sect. 2.2)           */
+  int32_t soft_mode;   /* TSPH_SOFT_*                                          */
+  double eta_h;        /* h = eta_h n_gas^(-1/3)  (N_nei = 4 pi/3 (2 eta)^3)   */
+  double eta_eps;      /* eps = eta_eps n_all^(-1/3)                           */
+  double gamma;        /* adiabatic index, P = (gamma - 1) rho u               */
+  double alpha, beta;  /* viscosity coefficients (Sect. 3.3)                   */
+  double av_eps2;      /* eta^2 = av_eps2 * hbar^2 in mu_ij (0.01)             */
+  int32_t tc92;        /* 1: Thomas & Couchman gradient in the SPH pairs       */
+  int32_t h_maxit;     /* Newton iterations per solve                          */
+  double h_tol;        /* stop when |dh| < h_tol * h_start                      */
+  double kappa;        /* candidate search radius 2 h_guess (1 + kappa)        */
+  int32_t leaf_size;   /* particles per tree leaf (1..64)                      */
+  int32_t group_size;  /* sinks per walk group (leaf_size..64)                 */
+  int32_t precision;   /* TSPH_FP64                                             */
+  int32_t gravity;     /* 1: self-gravity on                                   */
+  int32_t hydro;       /* 1: SPH on                                            */
+  int32_t reserved;
+  double eta_dt;       /* time-step coefficient of the Sect. 4.2 criteria      */
+} tsph_params;
+
+typedef struct {
+  int64_t n, n_gas;
+  /* integrator state (FP64, written only by tsph_kick_drift) */
+  double *x, *y, *z;
+  double *vx, *vy, *vz;
+  double *m;
+  double *u;                 /* specific internal energy (gas entries)         */
+  /* predicted end-of-step velocity and energy used by the forces (Sect. 4.1);
+   * written by tsph_kick_drift(TSPH_KD_FIRST); for the first evaluation the
+   * caller copies v and u here */
+  double *vpx, *vpy, *vpz, *up;
+  /* lengths: in = guess (<= 0: cold start; constant eps in TSPH_SOFT_CONSTANT),
+   * out = solved value */
+  double *h, *eps;
+  /* outputs */
+  double *ax, *ay, *az;      /* total acceleration                              */
+  double *dudt;              /* du/dt (gas)                                     */
+  double *rho;               /* SPH mass density (gas)                          */
+  double *pot;               /* potential per unit mass; may be NULL            */
+} tsph_state;
+
+/* Create a context on the current HIP device for up to capacity_n particles.
+ * Allocates every scratch buffer once.  *out receives the context. */
+tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p);
+tsph_status tsph_destroy(void *ctx);
+/* Replace the parameters (same capacity). */
+tsph_status tsph_set_params(void *ctx, const tsph_params *p);
+/* Fill p with the defaults: G=1, theta=0.5, quadrupoles, adaptive softening,
+ * 50 neighbours, gamma=5/3, alpha=1, beta=2, av_eps2=0.01, TC92 on,
+ * h_tol=1e-6, kappa=0.1, leaf 16, group 64, eta_dt=0.1. */
+void tsph_default_params(tsph_params *p);
+/* Device bytes a context of this capacity reserves (host-only, no GPU). */
+tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t *bytes);
+
+/* Root cube, Morton keys, radix sort, gather into key order, canonical
+ * oct-tree in level order and node moments (Sect. 2.2). */
+tsph_status tsph_build_tree(void *ctx, const tsph_state *s, void *stream);
+/* Full force pass: tree, h/eps solves and densities, gravity walk, SPH
+ * forces.  Reads x, v^p, u^p, m, h, eps; writes h, eps, a, dudt, rho, pot. */
+tsph_status tsph_compute_forces(void *ctx, tsph_state *s, void *stream);
+/* Leapfrog half steps (Sect. 4.1).  TSPH_KD_FIRST: v^p = v + dt a,
+ * u^p = u + dt du/dt, then v += dt/2 a, x += dt v, u += dt/2 du/dt.
+ * TSPH_KD_SECOND: v += dt/2 a, u += dt/2 du/dt. */
+tsph_status tsph_kick_drift(void *ctx, tsph_state *s, double dt, int32_t phase, void *stream);
+/* Global time-step (Sect. 4.2) from the last tsph_compute_forces: min over
+ * particles of eta_dt sqrt(min(eps,h)/|a|), the Courant criterion and
+ * eta_dt |u / du/dt|.  Writes one double to dt_device. */
+tsph_status tsph_timestep(void *ctx, const tsph_state *s, double *dt_device, void *stream);
+/* FP64 totals: out_device[0..8] = E_kin, E_th, V (= 1/2 sum m pot), Px, Py,
+ * Pz, Lx, Ly, Lz.  Needs s->pot from the last force pass. */
+tsph_status tsph_diagnostics(void *ctx, const tsph_state *s, double *out_device, void *stream);
+/* Synchronise the context's last stream and return the OR of the device flag
+ * bits since the previous call (then clear them); n_noconv receives the
+ * number of unconverged length solves. */
+tsph_status tsph_read_flags(void *ctx, uint32_t *flags, int64_t *n_noconv);
+
+/* Per-phase timing with HIP events recorded on the stream of each
+ * tsph_compute_forces call: phase 0 tree build, 1 length solves and
+ * densities, 2 gravity walk, 3 SPH forces, 4 output scatter and time-step.
+ * tsph_timing(ctx, 1) creates the events and resets the totals (allocates;
+ * not for captured streams); tsph_phase_times waits for the recorded calls
+ * and returns the summed milliseconds per phase and the number of calls. */
+tsph_status tsph_timing(void *ctx, int32_t enable);
+tsph_status tsph_phase_times(void *ctx, double *ms_out /* [5] */, int64_t *calls);
+
+/* Debug exports (synchronous copies to host memory, for the tests). */
+enum { TSPH_DBG_KEYS = 0,      /* uint64[n] sorted Morton keys                         */
+       TSPH_DBG_PERM = 1,      /* int32[n] sorted position -> caller index             */
+       TSPH_DBG_NODES = 2,     /* int32[7][nnodes] level, first, count, child, nchild,  *
+                                * parent, ngas                                          */
+       TSPH_DBG_NNODES = 3,    /* int64[1] node count                                  */
+       TSPH_DBG_MOMENTS = 4,   /* double[16][nnodes] mass, com(3), quad(6), bmin(3),    *
+                                * bmax(3)                                               */
+       TSPH_DBG_GROUPS = 5,    /* int32[ngroups] group nodes                           */
+       TSPH_DBG_NGROUPS = 6,   /* int64[1]                                             */
+       TSPH_DBG_COUNTS = 7,    /* int32[3][n] (caller order) far nodes, near pairs,    *
+                                * SPH pairs per particle in the last force pass        */
+       TSPH_DBG_NBR = 8,       /* int32[3][n][max] neighbour lists, see below          */
+       TSPH_DBG_ROOT = 9,      /* double[4] x0, y0, z0, side                            */
+       TSPH_DBG_SOLVE = 10     /* double[8][n] (caller order) nh, omega, zeta, divv,   *
+                                * neps, ups, xi, maxmu                                  */ };
+/* Enable per-particle neighbour-list recording (up to max_per_particle
+ * entries per particle and kind: density gather r < 2h_i, SPH pairs
+ * r < 2max(h_i,h_j), gravity-correction pairs r < 2max(eps_i,eps_j)); lists
+ * hold caller indices in the order found, padded with -1; a longer list sets
+ * TSPH_FLAG_LIST_OVERFLOW.  max_per_particle = 0 disables.  Allocates. */
+tsph_status tsph_debug_lists(void *ctx, int32_t max_per_particle);
+tsph_status tsph_debug_export(void *ctx, int32_t what, void *host, size_t cap_bytes,
+                              size_t *written);
+
+const char *tsph_last_error(const void *ctx);
+const char *tsph_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -42,7 +42,7 @@ class Run(C.Structure):
                 ("eps", D), ("neps", D), ("ups", D), ("xi", D),
                 ("ax", D), ("ay", D), ("az", D), ("pot", D), ("dudt", D), ("maxmu", D),
                 ("cnt_node", I64), ("cnt_pair", I64), ("cnt_sph", I64), ("iters", I32),
-                ("n_noconv", C.c_int64)]
+                ("n_noconv", C.c_int64), ("sinks", I64), ("n_sinks", C.c_int64), ("cnt_soft", I64)]
 
 
 def eta_from_nnei(nnei: float) -> float:
@@ -124,7 +124,7 @@ def kernel(name: str, r, h):
     return out
 
 
-def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=None) -> dict:
+def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=None, sinks=None) -> dict:
     """Full oracle force evaluation on an initial-condition dict.
 
     ``vel``/``u`` override the velocities and internal energies used in the
@@ -140,10 +140,12 @@ def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=No
     ein = None if eps_in is None else _f64(eps_in)
     out = {k: np.zeros(n) for k in ("h", "nh", "rho", "omega", "zeta", "divv", "eps", "neps", "ups",
                                      "xi", "ax", "ay", "az", "pot", "dudt", "maxmu")}
-    cnt = {k: np.zeros(n, np.int64) for k in ("cnt_node", "cnt_pair", "cnt_sph")}
+    cnt = {k: np.zeros(n, np.int64) for k in ("cnt_node", "cnt_pair", "cnt_sph", "cnt_soft")}
+    snk = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
     iters = np.zeros(n, np.int32)
     r = Run(n=n, n_gas=n_gas, x=_p(x), y=_p(y), z=_p(z), vx=_p(vx), vy=_p(vy), vz=_p(vz), m=_p(m),
-            u=_p(uu), h_in=_p(hin), eps_in=_p(ein), iters=_p(iters, I32),
+            u=_p(uu), h_in=_p(hin), eps_in=_p(ein), iters=_p(iters, I32), sinks=_p(snk, I64),
+            n_sinks=0 if snk is None else snk.size,
             **{k: _p(v) for k, v in out.items()}, **{k: _p(v, I64) for k, v in cnt.items()})
     rc = lib().orc_compute_forces(C.byref(prm), C.byref(r))
     if rc != 0:

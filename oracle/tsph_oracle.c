@@ -505,8 +505,9 @@ typedef struct {
   double *eps, *neps, *ups, *xi;
   double *ax, *ay, *az, *pot, *dudt, *maxmu;
   double *P, *cs;
-  int64_t *cnt_node, *cnt_pair, *cnt_sph;
+  int64_t *cnt_node, *cnt_pair, *cnt_sph, *cnt_soft;
   int32_t *iters;
+  char *active;               /* sinks of the gravity/SPH passes            */
   /* per-node maxima after the solves */
   double *epsmax, *hmax;
   int64_t *ngas;
@@ -827,8 +828,9 @@ static void gravity_particle_walk(ctx_t *C)
     int64_t *stack = malloc((8 * 22 * 8 + t->nnodes + 16) * sizeof(int64_t));
 #pragma omp for schedule(dynamic, 16)
     for (int64_t p = 0; p < C->n; p++) {
+      if (!C->active[p]) continue;
       double a[3] = {0, 0, 0}, pot = 0.0;
-      int64_t nnode = 0, npair = 0, sp = 0;
+      int64_t nnode = 0, npair = 0, nsoft = 0, sp = 0;
       double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
       stack[sp++] = 0;
       while (sp > 0) {
@@ -838,7 +840,12 @@ static void gravity_particle_walk(ctx_t *C)
           nnode++;
         } else if (t->nchild[k] == 0) {
           for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++)
-            if (q != p) { near_pair(C, p, q, a, &pot); npair++; }
+            if (q != p) {
+              near_pair(C, p, q, a, &pot);
+              npair++;
+              double R = 2.0 * (C->eps[p] > C->eps[q] ? C->eps[p] : C->eps[q]);
+              if (pair_r2(px, py, pz, t->xs[q], t->ys[q], t->zs[q]) < R * R) nsoft++;
+            }
         } else {
           for (int32_t b = t->nchild[k] - 1; b >= 0; b--) stack[sp++] = t->child[k] + b;
         }
@@ -848,6 +855,7 @@ static void gravity_particle_walk(ctx_t *C)
       C->pot[p] = pot;
       C->cnt_node[p] = nnode;
       C->cnt_pair[p] = npair;
+      C->cnt_soft[p] = nsoft;
     }
     free(stack);
   }
@@ -911,6 +919,7 @@ static void gravity_direct(ctx_t *C)
 {
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t p = 0; p < C->n; p++) {
+    if (!C->active[p]) continue;
     double a[3] = {0, 0, 0}, pot = 0.0;
     for (int64_t q = 0; q < C->n; q++)
       if (q != p) near_pair(C, p, q, a, &pot);
@@ -994,7 +1003,7 @@ static void sph_phase(ctx_t *C)
     int64_t *stack = malloc((8 * 22 * 8 + t->nnodes + 16) * sizeof(int64_t));
 #pragma omp for schedule(dynamic, 16)
     for (int64_t p = 0; p < C->n; p++) {
-      if (!C->gas[p]) continue;
+      if (!C->gas[p] || !C->active[p]) continue;
       double a[3] = {0, 0, 0}, du = 0.0, mumax = 0.0;
       int64_t npair = 0;
       if (P->nbr_mode == ORC_NBR_BRUTE) {
@@ -1071,7 +1080,20 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   C.P = calloc(n, sizeof(double)); C.cs = calloc(n, sizeof(double));
   C.cnt_node = calloc(n, sizeof(int64_t)); C.cnt_pair = calloc(n, sizeof(int64_t));
   C.cnt_sph = calloc(n, sizeof(int64_t));
+  C.cnt_soft = calloc(n, sizeof(int64_t));
   C.iters = calloc(n, sizeof(int32_t));
+  C.active = malloc(n);
+  if (r->n_sinks > 0) {
+    if (p->walk_mode == ORC_WALK_GROUP) { orc_tree_free(t); return -1; }
+    int64_t *inv = malloc(n * sizeof(int64_t));
+    for (int64_t q = 0; q < n; q++) inv[t->perm[q]] = q;
+    memset(C.active, 0, n);
+    for (int64_t s = 0; s < r->n_sinks; s++)
+      if (r->sinks[s] >= 0 && r->sinks[s] < n) C.active[inv[r->sinks[s]]] = 1;
+    free(inv);
+  } else {
+    memset(C.active, 1, n);
+  }
   C.epsmax = calloc(t->nnodes, sizeof(double));
   C.hmax = calloc(t->nnodes, sizeof(double));
   C.ngas = calloc(t->nnodes, sizeof(int64_t));
@@ -1100,6 +1122,7 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
     OUT(eps, eps); OUT(neps, neps); OUT(ups, ups); OUT(xi, xi);
     OUT(ax, ax); OUT(ay, ay); OUT(az, az); OUT(pot, pot); OUT(dudt, dudt); OUT(maxmu, maxmu);
     OUT(cnt_node, cnt_node); OUT(cnt_pair, cnt_pair); OUT(cnt_sph, cnt_sph); OUT(iters, iters);
+    OUT(cnt_soft, cnt_soft);
 #undef OUT
   }
   free(C.vx); free(C.vy); free(C.vz); free(C.u); free(C.gas);
@@ -1107,6 +1130,7 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   free(C.eps); free(C.neps); free(C.ups); free(C.xi);
   free(C.ax); free(C.ay); free(C.az); free(C.pot); free(C.dudt); free(C.maxmu);
   free(C.P); free(C.cs); free(C.cnt_node); free(C.cnt_pair); free(C.cnt_sph); free(C.iters);
+  free(C.cnt_soft); free(C.active);
   free(C.epsmax); free(C.hmax); free(C.ngas);
   orc_tree_free(t);
   return 0;

@@ -72,6 +72,12 @@ typedef struct {
   int64_t *cnt_node, *cnt_pair, *cnt_sph;          /* interaction counts         */
   int32_t *iters;                                  /* Newton passes per particle */
   int64_t n_noconv;                                /* out: unsolved lengths      */
+  /* optional sink sample (caller indices): when n_sinks > 0 the gravity and
+   * SPH passes run for these sinks only (per-particle or direct walk); the
+   * length solves still cover every particle */
+  const int64_t *sinks;
+  int64_t n_sinks;
+  int64_t *cnt_soft;                               /* near pairs inside 2 max(eps) */
 } orc_run;
 
 /* Full force evaluation: tree, h/eps solves, gravity walk, SPH forces.

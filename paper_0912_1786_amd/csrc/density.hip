@@ -1,0 +1,432 @@
+// density.hip -- self-consistent smoothing length h (gas) and softening
+// length eps (all species), densities and correction factors.
+//
+// Merlin et al., arXiv:0912.1786: Sect. 2.1 (Eqs. rho0, etan, iter, zeta and
+// the derivative terms between them), Sect. 3 (Eqs. densitySPH, hn, nsum,
+// drhodr), Sect. 3.1 (gather view, enlarged search radius), Sect. 3.2
+// (independent eps and h).
+//
+// One wavefront per walk group (a maximal tree node of at most 64 particles);
+// lane i owns sink i.  The wave walks the tree once per search radius and
+// keeps the candidate leaves in LDS; every Newton pass then streams those
+// leaves with wave-uniform (scalar) loads while each lane evaluates its own
+// sink.  The relation eta = h n^(1/3) is solved as g(h) = h^3 n(h) - eta^3 = 0,
+// monotone in h, with a bracket, Newton steps and a bisection fallback; the
+// candidate radius 2 h_guess (1 + kappa) is doubled when the root lies beyond
+// it.
+#include <stdio.h>
+
+#include "tsph_internal.h"
+
+namespace tsph {
+
+constexpr int kDensLeafCap = 1024;  // cached candidate leaves (>= 2 x 64)
+constexpr int kDensStackCap = 1536;
+constexpr double kPi = 3.14159265358979323846;
+
+struct DensArgs {
+  int64_t n, n_gas, cap_n;
+  const int32_t *groups;
+  const int32_t *ngroups;
+  const NodeTopo *topo;
+  const NodeBox *nbox;
+  const int32_t *nngas;
+  const int32_t *nlevel;
+  const DevRoot *root;
+  const double4 *pm;
+  const double4 *vu;
+  const uint8_t *gas;
+  const int32_t *leaf_of;
+  const int32_t *perm;
+  const int32_t *nnodes;
+  double *hs, *es;
+  double4 *sph;
+  double *zo;
+  double2 *soft;
+  double *solve;
+  int32_t *work;
+  uint32_t *flags;
+  int32_t *noconv;
+  int32_t *dbg;
+  int32_t dbg_max;
+  double eta_h, eta_eps, kappa, h_tol, gamma;
+  int32_t maxit, soft_mode, hydro, gravity, shared;
+};
+
+struct Sums {
+  double n, sdh, rho, msdh, mdphi, divv;
+};
+
+// One walk over the leaves that some staged sink ball reaches (s_snk[s] =
+// sink position and ball radius); the group box grown by the largest radius R
+// is a cheap first filter.  Leaves are handed to visit(count, last) in
+// batches of at least `batch` held in s_leaf (capacity batch + 64); visit
+// returns false to stop the walk.  Returns false if the walk was stopped or a
+// structural check failed.
+template <class V>
+__device__ bool walk_leaves(const DensArgs &A, const NodeBox &gb, double R, bool gas_only, int *s_stack,
+                            int *s_leaf, const double4 *s_snk, int batch, V &&visit) {
+  const int ln = lane();
+  int nleaf = 0, sp = 1, rounds = 0;
+  const int guard = *A.nnodes + 2;
+  if (ln == 0) s_stack[0] = 0;
+  __syncthreads();
+  const double R2 = R * R;
+  while (sp > 0) {
+    if (++rounds > guard) {
+      atomicOr(A.flags, TSPH_FLAG_INTERNAL);
+      return false;
+    }
+    const int take = walk_take(sp, kDensStackCap);
+    const int k = ln < take ? s_stack[sp - take + ln] : -1;
+    sp -= take;
+    __syncthreads();
+    bool hit = false, leaf = false;
+    NodeTopo nd{0, 0, -1, 0};
+    const NodeBox b = A.nbox[k >= 0 ? k : 0];
+    if (k >= 0 && (!gas_only || A.nngas[k] > 0)) {
+      double d2 = axis_gap_box(gb.lox, gb.hix, b.lox, b.hix);
+      d2 = d2 + axis_gap_box(gb.loy, gb.hiy, b.loy, b.hiy);
+      d2 = d2 + axis_gap_box(gb.loz, gb.hiz, b.loz, b.hiz);
+      hit = d2 < R2;
+    }
+    hit = balls_reach_box(s_snk, b.lox, b.loy, b.loz, b.hix, b.hiy, b.hiz, 0.0, hit) && hit;
+    if (hit) {
+      nd = A.topo[k];
+      leaf = nd.nchild == 0;
+    }
+    const uint64_t lm = ballot(leaf);
+    if (leaf) s_leaf[nleaf + mbcnt(lm)] = k;
+    nleaf += __popcll(lm);
+    const int nch = (hit && !leaf) ? nd.nchild : 0;
+    const int incl = wave_incl_scan(nch);
+    const int tot = __shfl(incl, kWave - 1, kWave);
+    if (sp + tot > kDensStackCap) {  // excluded by walk_take; kept as a guard
+      atomicOr(A.flags, TSPH_FLAG_STACK_OVERFLOW);
+      return false;
+    }
+    for (int a = 0; a < nch; a++) s_stack[sp + incl - nch + a] = nd.child + a;
+    sp += tot;
+    __syncthreads();
+    if (nleaf >= batch) {
+      if (!visit(nleaf, false)) return false;
+      nleaf = 0;
+      __syncthreads();
+    }
+  }
+  bool ok = visit(nleaf, true);
+  __syncthreads();
+  return ok;
+}
+
+// kernel sums over a batch of candidate leaves at length h (per lane).  kFull
+// adds the mass density, the mass-weighted h-derivative, the velocity
+// divergence (gas solve) and the mass-weighted d phi / d eps (softening).
+template <bool kFull>
+__device__ void leaf_sums(const DensArgs &A, int nleaf, const int *s_leaf, bool gas_only, double px,
+                          double py, double pz, const double4 &vp, double h, bool want_div, bool want_phi,
+                          int32_t *dbg_row, int &ndbg, Sums &s) {
+  const double ih = 1.0 / h;
+  const double ih3 = ih * ih * ih / kPi;
+  const double ih4 = ih3 * ih;
+  const double two_h = 2.0 * h;
+  const double R2 = two_h * two_h;
+  for (int j = 0; j < nleaf; j++) {
+    const int k = uniform(s_leaf[j]);
+    const NodeTopo nd = A.topo[k];
+    for (int q = nd.first; q < nd.first + nd.count; q++) {
+      if (gas_only && !A.gas[q]) continue;
+      const double4 a = A.pm[q];
+      const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+      if (kFull && dbg_row && r2 < R2) {
+        if (ndbg < A.dbg_max) dbg_row[ndbg] = A.perm[q];
+        ndbg++;
+      }
+      if (!(r2 < R2)) continue;
+      const double r = sqrt(r2);
+      const double qq = r * ih;
+      double w, dw;
+      m4(qq, w, dw);
+      const double W = w * ih3;
+      const double dWdh = -(3.0 * w + qq * dw) * ih4;
+      s.n += W;
+      s.sdh += dWdh;
+      if (kFull) {
+        s.rho += a.w * W;
+        s.msdh += a.w * dWdh;
+        if (want_phi) s.mdphi += a.w * soft_pe(r, h);
+        if (want_div && r > 0.0) {
+          const double4 v = A.vu[q];
+          const double g = dw * ih4 / r;  // dW/dr / r
+          s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
+        }
+      }
+    }
+  }
+}
+
+// The candidate set of the current sink balls: cached in s_leaf when it fits,
+// otherwise streamed by re-walking the tree on every pass.
+struct Cands {
+  int nleaf;
+  bool cached;
+  double R;
+  bool gas_only;
+};
+
+__device__ Cands gather(const DensArgs &A, const NodeBox &gb, double R, bool gas_only, int *s_stack, int *s_leaf,
+                        const double4 *s_snk, bool &fail) {
+  Cands c{0, true, R, gas_only};
+  bool full = false;
+  bool ok = walk_leaves(A, gb, R, gas_only, s_stack, s_leaf, s_snk, kDensLeafCap - kWave,
+                        [&](int nl, bool last) {
+                          if (!last) {
+                            full = true;
+                            return false;
+                          }
+                          c.nleaf = nl;
+                          return true;
+                        });
+  if (full) {
+    c.cached = false;
+    c.nleaf = 0;
+  } else if (!ok) {
+    fail = true;
+  }
+  return c;
+}
+
+template <bool kFull>
+__device__ Sums pass(const DensArgs &A, const NodeBox &gb, const Cands &c, int *s_stack, int *s_leaf,
+                     const double4 *s_snk, double px, double py, double pz, const double4 &vp, double h,
+                     bool want_div, bool want_phi, int32_t *dbg_row, bool &fail) {
+  Sums s{0, 0, 0, 0, 0, 0};
+  int ndbg = 0;
+  if (c.cached) {
+    leaf_sums<kFull>(A, c.nleaf, s_leaf, c.gas_only, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
+  } else {
+    bool ok = walk_leaves(A, gb, c.R, c.gas_only, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
+      leaf_sums<kFull>(A, nl, s_leaf, c.gas_only, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
+      return true;
+    });
+    if (!ok) fail = true;
+  }
+  if (kFull && dbg_row && ndbg > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
+  return s;
+}
+
+struct SolveOut {
+  double h;
+  Sums s;
+  bool ok;
+};
+
+// One self-consistent length per lane (inactive lanes follow along).  The
+// bracket [0, hi] starts at hi = h_guess (1 + kappa) (a quarter of it on a
+// cold start) and hi doubles until g(hi) >= 0 for every lane; Newton steps
+// that leave the bracket are replaced by bisection; iteration stops when
+// |dh| < h_tol h_start.  Quantities are then evaluated at the final h.
+__device__ SolveOut solve_length(const DensArgs &A, const NodeBox &gb, bool sink, bool gas_only, double eta,
+                                 double guess, double px, double py, double pz, double4 vp, bool want_div,
+                                 bool want_phi, int *s_stack, int *s_leaf, double4 *s_snk, bool cold,
+                                 int32_t *dbg_row) {
+  SolveOut o;
+  const double eta3 = eta * eta * eta;
+  const int64_t set_size = gas_only ? A.n_gas : A.n;
+  const bool solvable = sink && ((double)set_size / kPi > eta3) && (guess > 0.0);
+  bool fail = false;
+  double hi = guess * (1.0 + A.kappa) * (cold ? 0.25 : 1.0);
+  Cands c{0, true, 0.0, gas_only};
+  int grow = 0;
+  for (;;) {
+    const double R = wave_max(solvable ? 2.0 * hi : 0.0);
+    if (R <= 0.0) break;
+    s_snk[lane()] = make_double4(px, py, pz, solvable ? 2.0 * hi : 0.0);
+    __syncthreads();
+    c = gather(A, gb, R, gas_only, s_stack, s_leaf, s_snk, fail);
+    if (fail) break;
+    Sums s = pass<false>(A, gb, c, s_stack, s_leaf, s_snk, px, py, pz, vp, solvable ? hi : 1.0, false, false,
+                         nullptr, fail);
+    const bool need = solvable && (hi * hi * hi * s.n - eta3 < 0.0);
+    if (fail || !__any(need) || ++grow > 200) break;
+    if (need) hi *= 2.0;
+  }
+  double lo = 0.0, h = guess > 0.0 ? fmin(guess, hi) : 1.0, hinit = h;
+  bool done = !solvable || fail, ok = false;
+  for (int it = 0; it < A.maxit && __any(!done); it++) {
+    Sums s = pass<false>(A, gb, c, s_stack, s_leaf, s_snk, px, py, pz, vp, h, false, false, nullptr, fail);
+    if (!done) {
+      const double g = h * h * h * s.n - eta3;
+      const double gp = 3.0 * h * h * s.n + h * h * h * s.sdh;
+      if (g < 0.0) lo = h;
+      else hi = h;
+      double hn = h - g / gp;
+      if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+      if (fabs(hn - h) < A.h_tol * hinit) {
+        ok = true;
+        done = true;
+      }
+      h = hn;
+    }
+  }
+  o.h = h;
+  o.ok = ok && !fail;
+  o.s = pass<true>(A, gb, c, s_stack, s_leaf, s_snk, px, py, pz, vp, h, want_div, want_phi,
+                   sink ? dbg_row : nullptr, fail);
+  return o;
+}
+
+__device__ __forceinline__ double cold_guess(const DensArgs &A, int p, bool gas_only, double eta) {
+  int k = A.leaf_of[p];
+  NodeTopo nd = A.topo[k];
+  double cnt = (double)nd.count;
+  if (gas_only && A.nngas[k] > 0) cnt = (double)A.nngas[k];
+  double s = ldexp(A.root->side, -A.nlevel[k]);
+  return eta * cbrt(s * s * s / cnt);
+}
+
+__global__ __launch_bounds__(64) void k_density(DensArgs A) {
+  __shared__ int s_stack[kDensStackCap];
+  __shared__ int s_leaf[kDensLeafCap];
+  __shared__ double4 s_snk[kWave];
+  __shared__ int s_g;
+  const int ln = lane();
+  const int ng = *A.ngroups;
+  int nnoconv = 0;
+  for (;;) {
+    if (ln == 0) s_g = atomicAdd(&A.work[0], 1);
+    __syncthreads();
+    const int g = s_g;
+    __syncthreads();
+    if (g >= ng) break;
+    const int gk = A.groups[g];
+    const NodeTopo gnd = A.topo[gk];
+    const NodeBox gb = A.nbox[gk];
+    for (int c0 = 0; c0 < gnd.count; c0 += kWave) {
+      const bool act = c0 + ln < gnd.count;
+      const int p = gnd.first + c0 + (act ? ln : 0);
+      const double4 a = A.pm[p];
+      const double4 vp = A.vu[p];
+      const bool is_gas = act && A.gas[p];
+      const int ci = act ? A.perm[p] : 0;
+      int32_t *dbg0 = A.dbg ? A.dbg + ((int64_t)0 * A.cap_n + ci) * A.dbg_max : nullptr;
+      // ---- smoothing length over gas neighbours (gas sinks) ----
+      SolveOut oh;
+      oh.h = 0.0;
+      oh.ok = true;
+      oh.s = Sums{0, 0, 0, 0, 0, 0};
+      if (A.hydro) {
+        double g0 = A.hs[p];
+        double guess = g0 > 0.0 ? g0 : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
+        oh = solve_length(A, gb, is_gas, true, A.eta_h, guess, a.x, a.y, a.z, vp, true, A.shared != 0,
+                          s_stack, s_leaf, s_snk, !(g0 > 0.0), is_gas ? dbg0 : nullptr);
+        if (is_gas && !oh.ok) nnoconv++;
+      }
+      // ---- softening length over all neighbours (all sinks) ----
+      double eps = 0.0, neps = 0.0, ups = 1.0, xi = 0.0;
+      if (A.gravity) {
+        if (A.soft_mode == TSPH_SOFT_CONSTANT) {
+          eps = A.es[p];
+        } else if (A.shared) {
+          eps = oh.h;
+          neps = oh.s.n;
+          ups = 1.0 + (oh.h / (3.0 * oh.s.n)) * oh.s.sdh;
+          xi = (A.soft_mode == TSPH_SOFT_ADAPTIVE) ? -(oh.h / (3.0 * oh.s.n)) * oh.s.mdphi : 0.0;
+        } else {
+          double g0 = A.es[p];
+          double guess = g0 > 0.0 ? g0 : (act ? cold_guess(A, p, false, A.eta_eps) : 0.0);
+          SolveOut oe = solve_length(A, gb, act, false, A.eta_eps, guess, a.x, a.y, a.z, vp, false, true,
+                                     s_stack, s_leaf, s_snk, !(g0 > 0.0), nullptr);
+          if (act && !oe.ok) nnoconv++;
+          eps = oe.h;
+          neps = oe.s.n;
+          ups = 1.0 + (oe.h / (3.0 * oe.s.n)) * oe.s.sdh;
+          xi = (A.soft_mode == TSPH_SOFT_ADAPTIVE) ? -(oe.h / (3.0 * oe.s.n)) * oe.s.mdphi : 0.0;
+        }
+      }
+      if (act) {
+        double h = 0.0, rho = 0.0, omega = 0.0, zeta = 0.0, divv = 0.0, c = 0.0, pr2 = 0.0;
+        if (is_gas) {
+          h = oh.h;
+          rho = oh.s.rho;
+          omega = 1.0 + (h / (3.0 * oh.s.n)) * oh.s.sdh;
+          zeta = -(h / (3.0 * oh.s.n)) * oh.s.msdh;
+          divv = -oh.s.divv / (oh.s.n * omega);
+          c = sqrt(A.gamma * (A.gamma - 1.0) * vp.w);
+          pr2 = (A.gamma - 1.0) * vp.w / rho;  // P / rho^2 with P = (gamma - 1) rho u
+        }
+        A.hs[p] = h;
+        A.es[p] = eps;
+        A.sph[p] = make_double4(h, rho, c, pr2);
+        A.zo[p] = is_gas ? zeta / omega : 0.0;
+        A.soft[p] = make_double2(eps, (A.gravity && A.soft_mode == TSPH_SOFT_ADAPTIVE) ? xi / ups : 0.0);
+        double *S = A.solve;
+        S[kNh * A.cap_n + p] = is_gas ? oh.s.n : 0.0;
+        S[kOmega * A.cap_n + p] = omega;
+        S[kZeta * A.cap_n + p] = zeta;
+        S[kDivv * A.cap_n + p] = divv;
+        S[kNeps * A.cap_n + p] = neps;
+        S[kUps * A.cap_n + p] = ups;
+        S[kXi * A.cap_n + p] = xi;
+      }
+    }
+  }
+  if (nnoconv) {
+    atomicAdd(A.noconv, nnoconv);
+    atomicOr(A.flags, TSPH_FLAG_NOCONV);
+  }
+}
+
+}  // namespace tsph
+
+using namespace tsph;
+
+tsph_status tsph_impl_refresh(Ctx *c, hipStream_t st);
+
+tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
+  DensArgs A;
+  A.n = c->n;
+  A.n_gas = c->n_gas;
+  A.cap_n = c->cap_n;
+  A.groups = c->groups;
+  A.ngroups = c->ngroups;
+  A.topo = c->topo;
+  A.nbox = c->nbox;
+  A.nngas = c->nngas;
+  A.nlevel = c->nlevel;
+  A.root = c->root;
+  A.pm = c->pm;
+  A.vu = c->vu;
+  A.gas = c->gas;
+  A.leaf_of = c->leaf_of;
+  A.perm = c->perm;
+  A.nnodes = c->lvl + 46;
+  A.hs = c->hs;
+  A.es = c->es;
+  A.sph = c->sph;
+  A.zo = c->zo;
+  A.soft = c->soft;
+  A.solve = c->solve;
+  A.work = c->work;
+  A.flags = c->flags;
+  A.noconv = c->noconv;
+  A.dbg = c->dbg_nbr;
+  A.dbg_max = c->dbg_max;
+  A.eta_h = c->p.eta_h;
+  A.eta_eps = c->p.eta_eps;
+  A.kappa = c->p.kappa;
+  A.h_tol = c->p.h_tol;
+  A.gamma = c->p.gamma;
+  A.maxit = c->p.h_maxit;
+  A.soft_mode = c->p.soft_mode;
+  A.hydro = c->p.hydro && c->n_gas > 0;
+  A.gravity = c->p.gravity;
+  A.shared = (A.hydro && A.gravity && c->n_gas == c->n && c->p.eta_h == c->p.eta_eps &&
+              c->p.soft_mode != TSPH_SOFT_CONSTANT)
+                 ? 1
+                 : 0;
+  int dev_cus = 256;
+  hipLaunchKernelGGL(k_density, dim3(dev_cus * 8), dim3(64), 0, st, A);
+  TSPH_HIP_CHECK(c, hipGetLastError());
+  return tsph_impl_refresh(c, st);
+}

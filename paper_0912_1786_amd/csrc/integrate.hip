@@ -1,0 +1,239 @@
+// integrate.hip -- output scatter, kick-drift-kick leapfrog, global
+// time-step and FP64 diagnostics.
+//
+// Merlin et al., arXiv:0912.1786: Sect. 4.1 (KDK with the predicted velocity
+// v_n + a_n dt used at the end of the step), Sect. 4.2 (time-step criteria),
+// Sect. 2.1 (potential of the softened system, Eqs. Lagrangian, potential).
+// All integrator arithmetic is FP64 and elementwise, so these kernels are
+// bound by HBM bandwidth.  Reductions run in a fixed tree order and are
+// bit-reproducible.
+#include <stdio.h>
+
+#include "tsph_internal.h"
+
+namespace tsph {
+
+constexpr int kRedBlocks = 1024;
+
+struct FinishArgs {
+  int64_t n, cap_n;
+  const int32_t *perm;
+  const uint8_t *gas;
+  const double *acc;
+  const double4 *sph;
+  const double4 *vu;
+  const double *hs, *es, *solve;
+  double *dt_i;
+  double *ax, *ay, *az, *pot, *dudt, *rho, *h, *eps;
+  double eta_dt, alpha, beta;
+  int32_t hydro;
+};
+
+__global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= A.n) return;
+  const int i = A.perm[p];
+  const bool g = A.gas[p];
+  const double ax = A.acc[p], ay = A.acc[A.cap_n + p], az = A.acc[2 * A.cap_n + p];
+  const double du = g ? A.acc[4 * A.cap_n + p] : 0.0;
+  const double4 s = A.sph[p];
+  A.ax[i] = ax;
+  A.ay[i] = ay;
+  A.az[i] = az;
+  if (A.pot) A.pot[i] = A.acc[3 * A.cap_n + p];
+  if (A.dudt) A.dudt[i] = du;
+  if (A.rho) A.rho[i] = g ? s.y : 0.0;
+  if (A.h) A.h[i] = g ? A.hs[p] : 0.0;
+  if (A.eps) A.eps[i] = A.es[p];
+  // time-step criteria (Sect. 4.2): acceleration, Courant, internal energy
+  double dt = INFINITY;
+  const double amag = sqrt(ax * ax + ay * ay + az * az);
+  double len = A.es[p] > 0.0 ? A.es[p] : INFINITY;
+  if (g && A.hs[p] < len) len = A.hs[p];
+  if (amag > 0.0 && len < INFINITY) dt = fmin(dt, A.eta_dt * sqrt(len / amag));
+  if (g && A.hydro) {
+    const double c = s.z, hh = s.x;
+    const double divv = A.solve[kDivv * A.cap_n + p], mumax = A.solve[kMaxmu * A.cap_n + p];
+    const double den = hh * fabs(divv) + c + 1.2 * (A.alpha * c + A.beta * mumax);
+    if (den > 0.0) dt = fmin(dt, A.eta_dt * hh / den);
+    const double u = A.vu[p].w;
+    if (du != 0.0) dt = fmin(dt, A.eta_dt * fabs(u / du));
+  }
+  A.dt_i[p] = dt;
+}
+
+__global__ __launch_bounds__(256) void k_kick_drift(int64_t n, int64_t n_gas, double dt, int phase, double *x,
+                                                    double *y, double *z, double *vx, double *vy, double *vz,
+                                                    double *u, const double *__restrict__ ax,
+                                                    const double *__restrict__ ay, const double *__restrict__ az,
+                                                    const double *__restrict__ dudt, double *vpx, double *vpy,
+                                                    double *vpz, double *up) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double hdt = 0.5 * dt;
+  const double a0 = ax[i], a1 = ay[i], a2 = az[i];
+  double v0 = vx[i], v1 = vy[i], v2 = vz[i];
+  if (phase == TSPH_KD_FIRST) {
+    if (vpx) {
+      vpx[i] = v0 + dt * a0;
+      vpy[i] = v1 + dt * a1;
+      vpz[i] = v2 + dt * a2;
+    }
+    v0 += hdt * a0;
+    v1 += hdt * a1;
+    v2 += hdt * a2;
+    x[i] += dt * v0;
+    y[i] += dt * v1;
+    z[i] += dt * v2;
+    if (i < n_gas) {
+      const double du = dudt[i];
+      if (up) up[i] = u[i] + dt * du;
+      u[i] += hdt * du;
+    }
+  } else {
+    v0 += hdt * a0;
+    v1 += hdt * a1;
+    v2 += hdt * a2;
+    if (i < n_gas) u[i] += hdt * dudt[i];
+  }
+  vx[i] = v0;
+  vy[i] = v1;
+  vz[i] = v2;
+}
+
+__global__ __launch_bounds__(256) void k_min_partial(int64_t n, const double *__restrict__ a, double *__restrict__ part) {
+  __shared__ double s[256];
+  double v = INFINITY;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v = fmin(v, a[i]);
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] = fmin(s[threadIdx.x], s[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_min_final(int nb, const double *__restrict__ part, double *__restrict__ out,
+                                                   double *__restrict__ keep) {
+  __shared__ double s[256];
+  double v = INFINITY;
+  for (int i = threadIdx.x; i < nb; i += 256) v = fmin(v, part[i]);
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] = fmin(s[threadIdx.x], s[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (out) *out = s[0];
+    if (keep) *keep = s[0];
+  }
+}
+
+constexpr int kNDiag = 9;
+
+__global__ __launch_bounds__(256) void k_diag_partial(int64_t n, int64_t n_gas, const double *__restrict__ x,
+                                                      const double *__restrict__ y, const double *__restrict__ z,
+                                                      const double *__restrict__ vx, const double *__restrict__ vy,
+                                                      const double *__restrict__ vz, const double *__restrict__ m,
+                                                      const double *__restrict__ u, const double *__restrict__ pot,
+                                                      double *__restrict__ part) {
+  double acc[kNDiag] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double mi = m[i], a = vx[i], b = vy[i], c = vz[i];
+    acc[0] += 0.5 * mi * (a * a + b * b + c * c);
+    if (i < n_gas && u) acc[1] += mi * u[i];
+    if (pot) acc[2] += 0.5 * mi * pot[i];
+    acc[3] += mi * a;
+    acc[4] += mi * b;
+    acc[5] += mi * c;
+    acc[6] += mi * (y[i] * c - z[i] * b);
+    acc[7] += mi * (z[i] * a - x[i] * c);
+    acc[8] += mi * (x[i] * b - y[i] * a);
+  }
+  __shared__ double s[kNDiag][256];
+  for (int k = 0; k < kNDiag; k++) s[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int k = 0; k < kNDiag; k++) s[k][threadIdx.x] += s[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < kNDiag) part[blockIdx.x * kNDiag + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_diag_final(int nb, const double *__restrict__ part, double *__restrict__ out) {
+  __shared__ double s[256];
+  for (int k = 0; k < kNDiag; k++) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) v += part[i * kNDiag + k];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = s[0];
+    __syncthreads();
+  }
+}
+
+}  // namespace tsph
+
+using namespace tsph;
+
+tsph_status tsph_impl_finish(Ctx *c, tsph_state *s, hipStream_t st) {
+  FinishArgs A;
+  A.n = c->n;
+  A.cap_n = c->cap_n;
+  A.perm = c->perm;
+  A.gas = c->gas;
+  A.acc = c->acc;
+  A.sph = c->sph;
+  A.vu = c->vu;
+  A.hs = c->hs;
+  A.es = c->es;
+  A.solve = c->solve;
+  A.dt_i = c->acc + 5 * c->cap_n;
+  A.ax = s->ax;
+  A.ay = s->ay;
+  A.az = s->az;
+  A.pot = s->pot;
+  A.dudt = s->dudt;
+  A.rho = s->rho;
+  A.h = s->h;
+  A.eps = s->eps;
+  A.eta_dt = c->p.eta_dt;
+  A.alpha = c->p.alpha;
+  A.beta = c->p.beta;
+  A.hydro = c->p.hydro;
+  hipLaunchKernelGGL(k_finish, dim3(blocks_for(c->n, 256, 1 << 20)), dim3(256), 0, st, A);
+  // global time-step kept on the device for tsph_timestep
+  hipLaunchKernelGGL(k_min_partial, dim3(kRedBlocks), dim3(256), 0, st, c->n, A.dt_i, c->red);
+  hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, st, kRedBlocks, c->red, (double *)nullptr, c->dt);
+  TSPH_HIP_CHECK(c, hipGetLastError());
+  return TSPH_OK;
+}
+
+tsph_status tsph_impl_kick_drift(Ctx *c, tsph_state *s, double dt, int phase, hipStream_t st) {
+  hipLaunchKernelGGL(k_kick_drift, dim3(blocks_for(s->n, 256, 1 << 20)), dim3(256), 0, st, s->n, s->n_gas, dt,
+                     phase, s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->ax, s->ay, s->az, s->dudt, s->vpx,
+                     s->vpy, s->vpz, s->up);
+  TSPH_HIP_CHECK(c, hipGetLastError());
+  return TSPH_OK;
+}
+
+tsph_status tsph_impl_timestep(Ctx *c, double *dt_device, hipStream_t st) {
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(dt_device, c->dt, sizeof(double), hipMemcpyDeviceToDevice, st));
+  return TSPH_OK;
+}
+
+tsph_status tsph_impl_diagnostics(Ctx *c, const tsph_state *s, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_partial, dim3(kRedBlocks), dim3(256), 0, st, s->n, s->n_gas, s->x, s->y, s->z, s->vx,
+                     s->vy, s->vz, s->m, s->u, s->pot, c->red);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, kRedBlocks, c->red, out);
+  TSPH_HIP_CHECK(c, hipGetLastError());
+  return TSPH_OK;
+}

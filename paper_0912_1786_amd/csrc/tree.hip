@@ -1,0 +1,640 @@
+// tree.hip -- root cube, Morton keys, stable LSD radix sort, gather into key
+// order, canonical oct-tree in level order, bottom-up node moments and walk
+// groups (Sect. 2.2 of Merlin et al., arXiv:0912.1786: hierarchical cubes,
+// each split into eight half-size children, leaves holding up to leaf_size
+// particles, monopole + quadrupole moments, Dubinski opening radius).
+//
+// Every kernel is deterministic: reductions are either exact (min/max,
+// integer sums) or run in a fixed order, so a build is bit-reproducible.
+#include <stdio.h>
+
+#include "tsph_internal.h"
+
+namespace tsph {
+
+int blocks_for(int64_t n, int threads, int max_blocks) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return (int)b;
+}
+
+// ---------------------------------------------------------------------------
+// root cube
+// ---------------------------------------------------------------------------
+constexpr int kBBoxBlocks = 512;
+
+__global__ __launch_bounds__(256) void k_bbox_partial(int64_t n, const double *__restrict__ x,
+                                                      const double *__restrict__ y,
+                                                      const double *__restrict__ z,
+                                                      const double *__restrict__ m,
+                                                      double *__restrict__ part,
+                                                      uint32_t *__restrict__ flags) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double p[3] = {x[i], y[i], z[i]};
+    double mi = m[i];
+    bad |= !(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(mi) && mi > 0.0);
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      lo[d] = fmin(lo[d], p[d]);
+      hi[d] = fmax(hi[d], p[d]);
+    }
+  }
+  if (bad) atomicOr(flags, TSPH_FLAG_NONFINITE);
+  __shared__ double s[6][256];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    s[d][threadIdx.x] = lo[d];
+    s[3 + d][threadIdx.x] = hi[d];
+  }
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        s[d][threadIdx.x] = fmin(s[d][threadIdx.x], s[d][threadIdx.x + o]);
+        s[3 + d][threadIdx.x] = fmax(s[3 + d][threadIdx.x], s[3 + d][threadIdx.x + o]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// smallest power of two not below the largest extent; origin = minimum corner
+__global__ void k_bbox_final(int nb, const double *__restrict__ part, DevRoot *__restrict__ root) {
+  if (threadIdx.x != 0) return;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = 0; b < nb; b++)
+    for (int d = 0; d < 3; d++) {
+      lo[d] = fmin(lo[d], part[b * 6 + d]);
+      hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
+    }
+  double L = 0.0;
+  for (int d = 0; d < 3; d++) {
+    double ext = hi[d] - lo[d];
+    if (ext > L) L = ext;
+  }
+  int e = 0;
+  if (L > 0.0) {
+    int ex;
+    double f = frexp(L, &ex);
+    e = (f == 0.5) ? ex - 1 : ex;
+  }
+  root->x0 = lo[0];
+  root->y0 = lo[1];
+  root->z0 = lo[2];
+  root->side = ldexp(1.0, e);
+  root->scale = ldexp(1.0, kMaxLevel - e);
+  root->e = e;
+}
+
+// ---------------------------------------------------------------------------
+// Morton keys: x bit b -> key bit 3b+2, y -> 3b+1, z -> 3b
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t dilate3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+__device__ __forceinline__ uint64_t cell_of(double v, double v0, double scale) {
+#pragma clang fp contract(off)
+  double c = floor((v - v0) * scale);
+  c = fmax(c, 0.0);
+  c = fmin(c, 2097151.0);
+  return (uint64_t)c;
+}
+
+__global__ __launch_bounds__(256) void k_keys(int64_t n, const double *__restrict__ x,
+                                              const double *__restrict__ y,
+                                              const double *__restrict__ z,
+                                              const DevRoot *__restrict__ root,
+                                              uint64_t *__restrict__ key, int32_t *__restrict__ idx) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double sc = root->scale;
+  uint64_t cx = cell_of(x[i], root->x0, sc), cy = cell_of(y[i], root->y0, sc),
+           cz = cell_of(z[i], root->z0, sc);
+  key[i] = (dilate3(cx) << 2) | (dilate3(cy) << 1) | dilate3(cz);
+  idx[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// generic exclusive scan of int32 counts (three kernels; n may live on the
+// device).  out[i] = sum_{j<i} in[j]; *total (optional) = sum.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int block_excl_scan256(int v, int *s_tmp, int &total) {
+  // 256 threads = 4 waves
+  int incl = wave_incl_scan(v);
+  int w = threadIdx.x >> 6;
+  if (lane() == 63) s_tmp[w] = incl;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    int t = s_tmp[k];
+    if (k < w) off += t;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return off + incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const int32_t *__restrict__ in, int64_t n_host,
+                                                     const int32_t *__restrict__ n_dev,
+                                                     int32_t *__restrict__ part) {
+  int64_t n = n_dev ? *n_dev : n_host;
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n) {
+    if (threadIdx.x == 0) part[blockIdx.x] = 0;
+    return;
+  }
+  int s = 0;
+  for (int k = 0; k < kScanTile / 256; k++) {
+    int64_t i = base + k * 256 + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  __shared__ int tmp[4];
+  int tot;
+  block_excl_scan256(s, tmp, tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the block sums; the grand total goes to
+// *total.  In level mode the total becomes the next level's node count and
+// the node capacity is enforced.
+__global__ __launch_bounds__(256) void k_scan_top(int32_t *__restrict__ part, int nb,
+                                                  int32_t *__restrict__ total, int32_t *__restrict__ lvl,
+                                                  int level, int64_t cap_nodes,
+                                                  uint32_t *__restrict__ flags) {
+  __shared__ int tmp[4];
+  int carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += 256) {
+    int b = b0 + threadIdx.x;
+    int v = (b < nb) ? part[b] : 0;
+    int tot;
+    int ex = block_excl_scan256(v, tmp, tot);
+    if (b < nb) part[b] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    if (total) *total = carry;
+    if (lvl) {
+      // lvl[0..23) level begin, lvl[23..46) level count, lvl[46] total nodes
+      int begin_next = lvl[level] + lvl[23 + level];
+      if ((int64_t)begin_next + carry > cap_nodes) {
+        atomicOr(flags, TSPH_FLAG_NODE_CAPACITY);
+        carry = 0;
+      }
+      lvl[level + 1] = begin_next;
+      lvl[23 + level + 1] = carry;
+      lvl[46] = begin_next + carry;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const int32_t *__restrict__ in, int64_t n_host,
+                                                    const int32_t *__restrict__ n_dev,
+                                                    const int32_t *__restrict__ part,
+                                                    int32_t *__restrict__ out) {
+  int64_t n = n_dev ? *n_dev : n_host;
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n) return;
+  __shared__ int tmp[4];
+  int carry = part[blockIdx.x];
+  for (int k = 0; k < kScanTile / 256; k++) {
+    int64_t i = base + k * 256 + threadIdx.x;
+    int v = (i < n) ? in[i] : 0;
+    int tot;
+    int ex = block_excl_scan256(v, tmp, tot);
+    if (i < n) out[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+static void launch_scan(Ctx *c, const int32_t *in, int64_t n_host, const int32_t *n_dev,
+                        int64_t n_max, int32_t *out, int32_t *total, int32_t *lvl, int level,
+                        hipStream_t st) {
+  int nb = (int)((n_max + kScanTile - 1) / kScanTile);
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, st, in, n_host, n_dev, c->scan_part);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, c->scan_part, nb, total, lvl, level,
+                     c->cap_nodes, c->flags);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, st, in, n_host, n_dev, c->scan_part, out);
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (key, index), 8-bit digits, 8 passes
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sort_hist(int64_t n, const uint64_t *__restrict__ key, int shift,
+                                                   uint32_t *__restrict__ hist, int nb) {
+  __shared__ uint32_t s_h[kSortBins];
+  s_h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortTile / 256; k++) {
+    int64_t i = base + k * 256 + threadIdx.x;
+    if (i < n) atomicAdd(&s_h[(key[i] >> shift) & (kSortBins - 1)], 1u);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nb + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_sort_scatter(int64_t n, const uint64_t *__restrict__ kin,
+                                                      const int32_t *__restrict__ iin,
+                                                      uint64_t *__restrict__ kout,
+                                                      int32_t *__restrict__ iout, int shift,
+                                                      const int32_t *__restrict__ offs, int nb,
+                                                      uint32_t *__restrict__ flags) {
+  __shared__ int s_base[kSortBins];
+  __shared__ int s_run[kSortBins];
+  __shared__ int s_w[4][kSortBins];
+  int t = threadIdx.x, w = t >> 6;
+  s_base[t] = offs[t * nb + blockIdx.x];
+  s_run[t] = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) s_w[k][t] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortTile / 256; r++) {
+    int64_t i = base + r * 256 + t;
+    bool valid = i < n;
+    uint64_t k = valid ? kin[i] : 0;
+    int id = valid ? iin[i] : 0;
+    int d = (int)((k >> shift) & (kSortBins - 1));
+    // lanes of this wave holding the same digit
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kSortBits; b++) {
+      uint64_t mb = ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? mb : ~mb;
+    }
+    int rank = mbcnt(peers);
+    if (valid && rank == 0) s_w[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pos = s_base[d] + s_run[d] + rank;
+      for (int q = 0; q < w; q++) pos += s_w[q][d];
+      if (pos >= 0 && pos < n) {
+        kout[pos] = k;
+        iout[pos] = id;
+      } else {
+        atomicOr(flags, TSPH_FLAG_INTERNAL);
+      }
+    }
+    __syncthreads();
+    s_run[t] += s_w[0][t] + s_w[1][t] + s_w[2][t] + s_w[3][t];
+#pragma unroll
+    for (int q = 0; q < 4; q++) s_w[q][t] = 0;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gather the caller-order state into key order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gather(int64_t n, int64_t n_gas, const int32_t *__restrict__ perm,
+                                                const double *__restrict__ x, const double *__restrict__ y,
+                                                const double *__restrict__ z, const double *__restrict__ m,
+                                                const double *__restrict__ vpx, const double *__restrict__ vpy,
+                                                const double *__restrict__ vpz, const double *__restrict__ up,
+                                                const double *__restrict__ h, const double *__restrict__ eps,
+                                                double4 *__restrict__ pm, double4 *__restrict__ vu,
+                                                double *__restrict__ hs, double *__restrict__ es,
+                                                uint8_t *__restrict__ gas) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int i = perm[p];
+  bool g = i < n_gas;
+  pm[p] = make_double4(x[i], y[i], z[i], m[i]);
+  if (vpx) vu[p] = make_double4(vpx[i], vpy[i], vpz[i], (g && up) ? up[i] : 0.0);
+  hs[p] = (g && h) ? h[i] : 0.0;
+  es[p] = eps ? eps[i] : 0.0;
+  gas[p] = g ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// topology, one level at a time
+// ---------------------------------------------------------------------------
+__global__ void k_topo_init(int64_t n, NodeTopo *__restrict__ topo, int32_t *__restrict__ nlevel,
+                            int32_t *__restrict__ nparent, int32_t *__restrict__ lvl) {
+  int t = threadIdx.x;
+  if (t < 47) lvl[t] = 0;
+  if (t == 0) {
+    topo[0] = NodeTopo{0, (int32_t)n, -1, 0};
+    nlevel[0] = 0;
+    nparent[0] = -1;
+  }
+  __syncthreads();
+  if (t == 0) {
+    lvl[0] = 0;
+    lvl[23] = 1;
+    lvl[46] = 1;
+  }
+}
+
+// children of the nodes of one level: the non-empty octants, in octant order,
+// found by binary search on the sorted keys
+__global__ __launch_bounds__(256) void k_topo_split(int level, int leaf_size, const int32_t *__restrict__ lvl,
+                                                    const NodeTopo *__restrict__ topo,
+                                                    const uint64_t *__restrict__ key,
+                                                    int2 *__restrict__ ctmp, int32_t *__restrict__ ctmpn) {
+  int begin = lvl[level], count = lvl[23 + level];
+  int shift = 3 * (kMaxLevel - level - 1);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+    NodeTopo nd = topo[begin + t];
+    int nch = 0;
+    if (nd.count > leaf_size && level < kMaxLevel) {
+      int lo = nd.first, end = nd.first + nd.count;
+      for (int oct = 0; oct < 8; oct++) {
+        // first position in [lo, end) whose digit exceeds oct
+        int a = lo, b = end;
+        while (a < b) {
+          int mid = (a + b) >> 1;
+          if ((int)((key[mid] >> shift) & 7ull) <= oct) a = mid + 1;
+          else b = mid;
+        }
+        if (a > lo) ctmp[(int64_t)t * 8 + nch++] = make_int2(lo, a - lo);
+        lo = a;
+      }
+    }
+    ctmpn[t] = nch;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_topo_emit(int level, const int32_t *__restrict__ lvl,
+                                                   NodeTopo *__restrict__ topo, int32_t *__restrict__ nlevel,
+                                                   int32_t *__restrict__ nparent, const int2 *__restrict__ ctmp,
+                                                   const int32_t *__restrict__ ctmpn,
+                                                   const int32_t *__restrict__ cscan, int64_t cap_nodes,
+                                                   uint32_t *__restrict__ flags) {
+  int begin = lvl[level], count = lvl[23 + level];
+  int nbegin = lvl[level + 1], ncount = lvl[23 + level + 1];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+    int k = begin + t;
+    int nch = ncount > 0 ? ctmpn[t] : 0;  // capacity exhausted: the level stays leaves
+    int base = nbegin + cscan[t];
+    if (nch > 0 && (base < nbegin || (int64_t)base + nch > cap_nodes || cscan[t] + nch > ncount)) {
+      atomicOr(flags, TSPH_FLAG_INTERNAL);
+      nch = 0;
+    }
+    topo[k].child = nch ? base : -1;
+    topo[k].nchild = nch;
+    for (int j = 0; j < nch; j++) {
+      int2 fc = ctmp[(int64_t)t * 8 + j];
+      topo[base + j] = NodeTopo{fc.x, fc.y, -1, 0};
+      nlevel[base + j] = level + 1;
+      nparent[base + j] = k;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// moments, bottom-up one level at a time
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_moments(int level, double theta, const int32_t *__restrict__ lvl,
+                                                 const NodeTopo *__restrict__ topo,
+                                                 const double4 *__restrict__ pm,
+                                                 const uint8_t *__restrict__ gas,
+                                                 const uint64_t *__restrict__ key,
+                                                 const DevRoot *__restrict__ root,
+                                                 NodeFar *__restrict__ far, NodeBox *__restrict__ box,
+                                                 int32_t *__restrict__ nngas, int32_t *__restrict__ leaf_of) {
+  int begin = lvl[level], count = lvl[23 + level];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+    int k = begin + t;
+    NodeTopo nd = topo[k];
+    double M = 0, sx = 0, sy = 0, sz = 0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    int ng = 0;
+    if (nd.nchild == 0) {
+      for (int p = nd.first; p < nd.first + nd.count; p++) {
+        double4 a = pm[p];
+        M += a.w;
+        sx += a.w * a.x;
+        sy += a.w * a.y;
+        sz += a.w * a.z;
+        lo[0] = fmin(lo[0], a.x); hi[0] = fmax(hi[0], a.x);
+        lo[1] = fmin(lo[1], a.y); hi[1] = fmax(hi[1], a.y);
+        lo[2] = fmin(lo[2], a.z); hi[2] = fmax(hi[2], a.z);
+        ng += gas[p];
+        leaf_of[p] = k;
+      }
+      double cx = sx / M, cy = sy / M, cz = sz / M;
+      for (int p = nd.first; p < nd.first + nd.count; p++) {
+        double4 a = pm[p];
+        double dx = a.x - cx, dy = a.y - cy, dz = a.z - cz;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        q[0] += a.w * (3.0 * dx * dx - d2);
+        q[1] += a.w * (3.0 * dy * dy - d2);
+        q[2] += a.w * (3.0 * dz * dz - d2);
+        q[3] += a.w * 3.0 * dx * dy;
+        q[4] += a.w * 3.0 * dx * dz;
+        q[5] += a.w * 3.0 * dy * dz;
+      }
+      sx = cx; sy = cy; sz = cz;
+    } else {
+      for (int c = nd.child; c < nd.child + nd.nchild; c++) {
+        NodeFar f = far[c];
+        M += f.m;
+        sx += f.m * f.cx;
+        sy += f.m * f.cy;
+        sz += f.m * f.cz;
+        NodeBox b = box[c];
+        lo[0] = fmin(lo[0], b.lox); hi[0] = fmax(hi[0], b.hix);
+        lo[1] = fmin(lo[1], b.loy); hi[1] = fmax(hi[1], b.hiy);
+        lo[2] = fmin(lo[2], b.loz); hi[2] = fmax(hi[2], b.hiz);
+        ng += nngas[c];
+      }
+      double cx = sx / M, cy = sy / M, cz = sz / M;
+      // parallel-axis shift of each child's quadrupole to the parent's centre of mass
+      for (int c = nd.child; c < nd.child + nd.nchild; c++) {
+        NodeFar f = far[c];
+        double dx = f.cx - cx, dy = f.cy - cy, dz = f.cz - cz;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        q[0] += f.qxx + f.m * (3.0 * dx * dx - d2);
+        q[1] += f.qyy + f.m * (3.0 * dy * dy - d2);
+        q[2] += f.qzz + f.m * (3.0 * dz * dz - d2);
+        q[3] += f.qxy + f.m * 3.0 * dx * dy;
+        q[4] += f.qxz + f.m * 3.0 * dx * dz;
+        q[5] += f.qyz + f.m * 3.0 * dy * dz;
+      }
+      sx = cx; sy = cy; sz = cz;
+    }
+    // cube geometry from the level and the key prefix of the node
+    uint64_t pre = key[nd.first] >> (3 * (kMaxLevel - level));
+    uint64_t ix = 0, iy = 0, iz = 0;
+    for (int b = 0; b < level; b++) {
+      uint64_t dg = (pre >> (3 * b)) & 7ull;
+      ix |= ((dg >> 2) & 1ull) << b;
+      iy |= ((dg >> 1) & 1ull) << b;
+      iz |= (dg & 1ull) << b;
+    }
+    double s = ldexp(1.0, root->e - level);
+    double gx = root->x0 + (double)(2 * ix + 1) * (0.5 * s);
+    double gy = root->y0 + (double)(2 * iy + 1) * (0.5 * s);
+    double gz = root->z0 + (double)(2 * iz + 1) * (0.5 * s);
+    double ox = sx - gx, oy = sy - gy, oz = sz - gz;
+    double delta = sqrt(ox * ox + oy * oy + oz * oz);
+    NodeFar f;
+    f.cx = sx; f.cy = sy; f.cz = sz; f.m = M;
+    f.qxx = q[0]; f.qyy = q[1]; f.qzz = q[2]; f.qxy = q[3]; f.qxz = q[4]; f.qyz = q[5];
+    f.rmac = theta > 0.0 ? s / theta + delta : INFINITY;
+    f.pad = 0.0;
+    far[k] = f;
+    NodeBox b;
+    b.lox = lo[0]; b.loy = lo[1]; b.loz = lo[2];
+    b.hix = hi[0]; b.hiy = hi[1]; b.hiz = hi[2];
+    b.epsmax = 0.0; b.hmax = 0.0;
+    box[k] = b;
+    nngas[k] = ng;
+  }
+}
+
+// refresh of the per-node largest eps (all) and h (gas) after the solves
+__global__ __launch_bounds__(256) void k_refresh(int level, const int32_t *__restrict__ lvl,
+                                                 const NodeTopo *__restrict__ topo,
+                                                 const double *__restrict__ hs, const double *__restrict__ es,
+                                                 const uint8_t *__restrict__ gas, NodeBox *__restrict__ box) {
+  int begin = lvl[level], count = lvl[23 + level];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+    int k = begin + t;
+    NodeTopo nd = topo[k];
+    double em = 0.0, hm = 0.0;
+    if (nd.nchild == 0) {
+      for (int p = nd.first; p < nd.first + nd.count; p++) {
+        em = fmax(em, es[p]);
+        if (gas[p]) hm = fmax(hm, hs[p]);
+      }
+    } else {
+      for (int c = nd.child; c < nd.child + nd.nchild; c++) {
+        em = fmax(em, box[c].epsmax);
+        hm = fmax(hm, box[c].hmax);
+      }
+    }
+    box[k].epsmax = em;
+    box[k].hmax = hm;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// walk groups: maximal nodes with at most group_size particles (or leaves),
+// listed in order of their first particle
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_group_mark(int64_t n, int group_size, const int32_t *__restrict__ lvl,
+                                                    const NodeTopo *__restrict__ topo,
+                                                    const int32_t *__restrict__ nparent,
+                                                    int32_t *__restrict__ gstart, int32_t *__restrict__ gcnt) {
+  int nn = lvl[46];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
+    NodeTopo nd = topo[k];
+    bool fits = nd.count <= group_size || nd.nchild == 0;
+    int par = nparent[k];
+    bool top = par < 0 || topo[par].count > group_size;
+    if (fits && top) gstart[nd.first] = k;
+  }
+  (void)n;
+  (void)gcnt;
+}
+
+__global__ __launch_bounds__(256) void k_fill_i32(int64_t n, int32_t *__restrict__ a, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_group_flag(int64_t n, const int32_t *__restrict__ gstart,
+                                                    int32_t *__restrict__ f) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    f[i] = gstart[i] >= 0 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_group_compact(int64_t n, const int32_t *__restrict__ gstart,
+                                                       const int32_t *__restrict__ pos,
+                                                       int32_t *__restrict__ groups, int64_t cap_nodes,
+                                                       uint32_t *__restrict__ flags) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (gstart[i] >= 0) {
+      int q = pos[i];
+      if (q >= 0 && q < cap_nodes) groups[q] = gstart[i];
+      else atomicOr(flags, TSPH_FLAG_INTERNAL);
+    }
+}
+
+}  // namespace tsph
+
+using namespace tsph;
+
+tsph_status tsph_impl_build_tree(Ctx *c, const tsph_state *s, hipStream_t st) {
+  const int64_t n = s->n;
+  const int T = 256;
+  const int gb = blocks_for(n, T, 1 << 20);
+  // root cube
+  hipLaunchKernelGGL(k_bbox_partial, dim3(kBBoxBlocks), dim3(T), 0, st, n, s->x, s->y, s->z, s->m,
+                     c->bbox_part, c->flags);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, kBBoxBlocks, c->bbox_part, c->root);
+  // keys
+  hipLaunchKernelGGL(k_keys, dim3(gb), dim3(T), 0, st, n, s->x, s->y, s->z, c->root, c->key[0], c->idx[0]);
+  // sort: 8 passes of 8 bits, ping-pong, result back in buffer 0
+  int nb = (int)((n + kSortTile - 1) / kSortTile);
+  for (int pass = 0; pass < 8; pass++) {
+    int src = pass & 1, dst = src ^ 1, shift = pass * kSortBits;
+    hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(T), 0, st, n, c->key[src], shift, c->hist, nb);
+    launch_scan(c, (const int32_t *)c->hist, (int64_t)nb * kSortBins, nullptr, (int64_t)nb * kSortBins,
+                (int32_t *)c->hist, nullptr, nullptr, 0, st);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(T), 0, st, n, c->key[src], c->idx[src], c->key[dst],
+                       c->idx[dst], shift, (const int32_t *)c->hist, nb, c->flags);
+  }
+  c->perm = c->idx[0];
+  // gather
+  hipLaunchKernelGGL(k_gather, dim3(gb), dim3(T), 0, st, n, s->n_gas, c->perm, s->x, s->y, s->z, s->m,
+                     s->vpx, s->vpy, s->vpz, s->up, s->h, s->eps, c->pm, c->vu, c->hs, c->es, c->gas);
+  // topology
+  hipLaunchKernelGGL(k_topo_init, dim3(1), dim3(64), 0, st, n, c->topo, c->nlevel, c->nparent, c->lvl);
+  int64_t maxlev = (c->cap_nodes + 7) / 8;
+  int lb = blocks_for(maxlev, T, 4096);
+  for (int L = 0; L < kMaxLevel; L++) {
+    hipLaunchKernelGGL(k_topo_split, dim3(lb), dim3(T), 0, st, L, c->p.leaf_size, c->lvl, c->topo,
+                       c->key[0], c->ctmp, c->ctmpn);
+    launch_scan(c, c->ctmpn, 0, c->lvl + 23 + L, c->cap_nodes, c->cscan, nullptr, c->lvl, L, st);
+    hipLaunchKernelGGL(k_topo_emit, dim3(lb), dim3(T), 0, st, L, c->lvl, c->topo, c->nlevel, c->nparent,
+                       c->ctmp, c->ctmpn, c->cscan, c->cap_nodes, c->flags);
+  }
+  // moments, deepest level first
+  for (int L = kMaxLevel; L >= 0; L--)
+    hipLaunchKernelGGL(k_moments, dim3(lb), dim3(T), 0, st, L, c->p.theta, c->lvl, c->topo, c->pm, c->gas,
+                       c->key[0], c->root, c->nfar, c->nbox, c->nngas, c->leaf_of);
+  // groups
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, T, 8192)), dim3(T), 0, st, n, c->gflag, -1);
+  hipLaunchKernelGGL(k_group_mark, dim3(blocks_for(c->cap_nodes, T, 8192)), dim3(T), 0, st, n,
+                     c->p.group_size, c->lvl, c->topo, c->nparent, c->gflag, nullptr);
+  int32_t *flag01 = (int32_t *)c->solve;  // scratch: the solve outputs are written later
+  int32_t *pos = flag01 + c->cap_n;
+  hipLaunchKernelGGL(k_group_flag, dim3(blocks_for(n, T, 8192)), dim3(T), 0, st, n, c->gflag, flag01);
+  launch_scan(c, flag01, n, nullptr, n, pos, c->ngroups, nullptr, 0, st);
+  hipLaunchKernelGGL(k_group_compact, dim3(blocks_for(n, T, 8192)), dim3(T), 0, st, n, c->gflag, pos,
+                     c->groups, c->cap_nodes, c->flags);
+  TSPH_HIP_CHECK(c, hipGetLastError());
+  c->n = n;
+  c->n_gas = s->n_gas;
+  return TSPH_OK;
+}
+
+tsph_status tsph_impl_refresh(Ctx *c, hipStream_t st) {
+  int64_t maxlev = (c->cap_nodes + 7) / 8;
+  int lb = blocks_for(maxlev, 256, 4096);
+  for (int L = kMaxLevel; L >= 0; L--)
+    hipLaunchKernelGGL(k_refresh, dim3(lb), dim3(256), 0, st, L, c->lvl, c->topo, c->hs, c->es, c->gas,
+                       c->nbox);
+  TSPH_HIP_CHECK(c, hipGetLastError());
+  return TSPH_OK;
+}

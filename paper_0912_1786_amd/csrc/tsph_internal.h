@@ -1,0 +1,301 @@
+// tsph_internal.h -- context layout, node records, wave primitives and the
+// spline kernel functions of the HIP path (gfx950, wave64).
+//
+// Formulas: Merlin et al., arXiv:0912.1786 -- Sect. 2.1 (Eqs. spline,
+// softforce, softphi, dphidh), Sect. 3 (TC92 gradient), App. B.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tsph.h"
+
+namespace tsph {
+
+constexpr int kMaxLevel = 21;        // 3 x 21 key bits
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kSortBits = 8;         // radix digit
+constexpr int kSortBins = 1 << kSortBits;
+constexpr int kSortTile = 4096;      // keys per sort block (256 threads x 16)
+constexpr int kScanTile = 2048;      // elements per scan block (256 threads x 8)
+
+// Far-field record of a node (96 B): centre of mass, mass, traceless
+// quadrupole about the centre of mass (xx, yy, zz, xy, xz, yz), and the
+// opening radius l/theta + delta of the Dubinski criterion.
+struct NodeFar {
+  double cx, cy, cz, m;
+  double qxx, qyy, qzz, qxy;
+  double qxz, qyz, rmac, pad;
+};
+
+// Neighbour-search record of a node (64 B): tight bounding box of its
+// particles, the largest eps (all species) and the largest h (gas).
+struct NodeBox {
+  double lox, loy, loz, epsmax;
+  double hix, hiy, hiz, hmax;
+};
+
+// Topology of a node in level order; children of a node are contiguous.
+struct NodeTopo {
+  int32_t first, count, child, nchild;
+};
+
+struct DevRoot {
+  double x0, y0, z0, side;  // power-of-two root cube
+  double scale;             // 2^(21 - e): key = floor((x - x0) * scale)
+  int32_t e, pad;
+};
+
+// Per-particle solve outputs kept for export (sorted order).
+enum SolveField { kNh = 0, kOmega, kZeta, kDivv, kNeps, kUps, kXi, kMaxmu, kNumSolve };
+
+struct Ctx {
+  int device;
+  tsph_params p;
+  int64_t cap_n, cap_nodes;
+  int64_t n, n_gas;       // of the last tree build
+  void *arena;
+  size_t arena_bytes;
+  hipStream_t last_stream;
+  char err[512];
+
+  // ---- particles, sorted order (capacity cap_n) ----
+  uint64_t *key[2];
+  int32_t *idx[2];
+  int32_t *perm;          // = idx[final]: sorted -> caller
+  double4 *pm;            // x, y, z, m
+  double4 *vu;            // predicted vx, vy, vz, u
+  double *hs, *es;        // h, eps (guess in, solution out)
+  uint8_t *gas;
+  int32_t *leaf_of;
+  double4 *sph;           // h, rho, c, P/rho^2
+  double *zo;             // zeta / Omega*
+  double2 *soft;          // eps, xi / Upsilon
+  double *solve;          // kNumSolve x cap_n
+  double *acc;            // 6 x cap_n: ax, ay, az, pot, dudt, dt_i
+  int32_t *cnt;           // 3 x cap_n: far nodes, near pairs, SPH pairs
+
+  // ---- nodes, level order (capacity cap_nodes) ----
+  NodeTopo *topo;
+  int32_t *nlevel, *nparent, *nngas;
+  NodeFar *nfar;
+  NodeBox *nbox;
+  int2 *ctmp;             // 8 x cap_nodes child (first, count) scratch
+  int32_t *ctmpn;         // cap_nodes child counts of a level
+  int32_t *cscan;         // cap_nodes exclusive scan of ctmpn
+  int32_t *groups;        // cap_nodes group nodes
+  int32_t *gflag;         // cap_n group start flags / scan
+
+  // ---- small device state ----
+  DevRoot *root;
+  double *bbox_part;      // partial bbox (6 x max blocks)
+  int32_t *lvl;           // [0..23): level begin, [23..46): level count, [46]: total nodes
+  int32_t *ngroups;
+  uint32_t *hist;         // radix histograms kSortBins x sort blocks
+  int32_t *scan_part;     // scan block sums
+  int32_t *work;          // work-queue counters (16)
+  uint32_t *flags;        // device flag word
+  int32_t *noconv;        // unconverged solves
+  double *red;            // reduction scratch
+  double *dt;             // last global time-step
+
+  // ---- phase timing (ring of event sets) ----
+  int32_t timing;
+  int64_t t_calls, t_done;
+  hipEvent_t (*tev)[6];
+  double t_ms[5];
+
+  // ---- debug ----
+  int32_t dbg_max;
+  int32_t *dbg_nbr;       // 3 x cap_n x dbg_max (caller index), or null
+  uint32_t *h_flags;      // pinned host copy
+  int32_t *h_noconv;
+};
+
+// ---------------------------------------------------------------------------
+// wave primitives (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ int mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int t = __shfl_up(v, o, kWave);
+    if (lane() >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// spline kernel family (M4 cubic spline, support 2h)
+// q = r / h.  w(q) = 1 - 3/2 q^2 + 3/4 q^3 (q < 1), 1/4 (2 - q)^3 (q < 2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void m4(double q, double &w, double &dw) {
+  if (q < 1.0) {
+    w = 1.0 + q * q * (-1.5 + 0.75 * q);
+    dw = q * (-3.0 + 2.25 * q);
+  } else if (q < 2.0) {
+    double t = 2.0 - q;
+    w = 0.25 * t * t * t;
+    dw = -0.75 * t * t;
+  } else {
+    w = 0.0;
+    dw = 0.0;
+  }
+}
+
+// derivative of the M4 kernel used in the SPH pairs: the plain dw/dq or the
+// Thomas & Couchman (1992) form, constant inside q < 2/3 (Sect. 3).
+__device__ __forceinline__ double m4_grad(double q, bool tc92) {
+  if (q < 1.0) {
+    if (tc92 && q < (2.0 / 3.0)) return -1.0;
+    return q * (-3.0 + 2.25 * q);
+  }
+  if (q < 2.0) {
+    double t = 2.0 - q;
+    return -0.75 * t * t;
+  }
+  return 0.0;
+}
+
+// Softened gravity of a unit mass smoothed by the spline (Sect. 2.1):
+//   fr(r, e) = d phi / d r  (1/r^2 outside 2e)
+//   ph(r, e) = phi          (-1/r outside 2e)
+//   pe(r, e) = d phi / d e  (0 outside 2e)
+// Polynomials in q = r/e; for the outer branch the e-derivative is
+// -(f + q f')/e^2 with phi = f(q)/e.
+__device__ __forceinline__ double soft_fr(double r, double e) {
+  double q = r / e;
+  if (q >= 2.0) return 1.0 / (r * r);
+  double q2 = q * q, ie2 = 1.0 / (e * e);
+  if (q < 1.0) return ie2 * q * ((4.0 / 3.0) + q2 * (-1.2 + 0.5 * q));
+  return ie2 * (q * ((8.0 / 3.0) + q * (-3.0 + q * (1.2 - q / 6.0))) - 1.0 / (15.0 * q2));
+}
+
+__device__ __forceinline__ double soft_ph(double r, double e) {
+  double q = r / e;
+  if (q >= 2.0) return -1.0 / r;
+  double q2 = q * q;
+  if (q < 1.0) return (q2 * ((2.0 / 3.0) + q2 * (-0.3 + 0.1 * q)) - 1.4) / e;
+  return (q2 * ((4.0 / 3.0) + q * (-1.0 + q * (0.3 - q / 30.0))) - 1.6 + 1.0 / (15.0 * q)) / e;
+}
+
+__device__ __forceinline__ double soft_pe(double r, double e) {
+  double q = r / e;
+  if (q >= 2.0) return 0.0;
+  double q2 = q * q;
+  if (q < 1.0) return (1.4 + q2 * (-2.0 + q2 * (1.5 - 0.6 * q))) / (e * e);
+  return (1.6 + q2 * (-4.0 + q * (4.0 + q * (-1.5 + 0.2 * q)))) / (e * e);
+}
+
+// ---------------------------------------------------------------------------
+// exact geometric predicates (one rounding per operation, fixed order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double axis_gap_point(double lo, double hi, double p) {
+#pragma clang fp contract(off)
+  double d = 0.0;
+  if (p < lo) d = lo - p;
+  else if (p > hi) d = p - hi;
+  return d * d;
+}
+
+__device__ __forceinline__ double axis_gap_box(double lo1, double hi1, double lo2, double hi2) {
+#pragma clang fp contract(off)
+  double d = 0.0;
+  if (hi1 < lo2) d = lo2 - hi1;
+  else if (hi2 < lo1) d = lo1 - hi2;
+  return d * d;
+}
+
+__device__ __forceinline__ double dist2_pair(double xi, double yi, double zi, double xj, double yj,
+                                             double zj) {
+#pragma clang fp contract(off)
+  double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+  double s = dx * dx;
+  s = s + dy * dy;
+  s = s + dz * dz;
+  return s;
+}
+
+// Does some sink ball of the wave reach the box?  snk[s] = (x, y, z, R_s)
+// staged in LDS (R_s = 0 for lanes without a ball); the ball radius used for
+// sink s is max(R_s, r_node).  Every lane tests its own box against all
+// staged sinks (broadcast reads); the loop stops once every lane that still
+// needs an answer has one.
+__device__ __forceinline__ bool balls_reach_box(const double4 *snk, double lox, double loy, double loz,
+                                                double hix, double hiy, double hiz, double r_node, bool want) {
+  bool hit = false;
+  for (int s = 0; s < kWave; s++) {
+    const double4 q = snk[s];
+    if (q.w > 0.0) {
+      const double R = fmax(q.w, r_node);
+      double d2 = axis_gap_point(lox, hix, q.x);
+      d2 = d2 + axis_gap_point(loy, hiy, q.y);
+      d2 = d2 + axis_gap_point(loz, hiz, q.z);
+      hit = hit || (d2 < R * R);
+    }
+    if ((s & 7) == 7 && !__any(want && !hit)) break;
+  }
+  return hit;
+}
+
+// Nodes popped per walk round from an LDS stack of capacity cap holding sp
+// entries.  Each popped node pushes at most 8 children, so popping t nodes
+// grows the stack by at most 7 t.  Full 64-node rounds run while that fits
+// above a reserve of 160 entries; inside the reserve a single node is popped,
+// i.e. the walk continues depth first from the top, which needs at most
+// 7 x 21 more entries.  The stack therefore never exceeds cap.
+__device__ __forceinline__ int walk_take(int sp, int cap) {
+  const int room = cap - sp - 160;
+  int t = room >= 7 * kWave ? kWave : room / 7;
+  t = t < 1 ? 1 : t;
+  return t < sp ? t : sp;
+}
+
+// host-side launch helpers (defined in the translation units)
+int blocks_for(int64_t n, int threads, int max_blocks);
+
+}  // namespace tsph
+
+// implemented per translation unit, called by the ABI layer
+tsph_status tsph_impl_build_tree(tsph::Ctx *c, const tsph_state *s, hipStream_t st);
+tsph_status tsph_impl_density(tsph::Ctx *c, hipStream_t st);
+tsph_status tsph_impl_gravity(tsph::Ctx *c, bool want_pot, hipStream_t st);
+tsph_status tsph_impl_sph(tsph::Ctx *c, hipStream_t st);
+tsph_status tsph_impl_finish(tsph::Ctx *c, tsph_state *s, hipStream_t st);
+tsph_status tsph_impl_kick_drift(tsph::Ctx *c, tsph_state *s, double dt, int phase, hipStream_t st);
+tsph_status tsph_impl_timestep(tsph::Ctx *c, double *dt_device, hipStream_t st);
+tsph_status tsph_impl_diagnostics(tsph::Ctx *c, const tsph_state *s, double *out, hipStream_t st);
+tsph_status tsph_impl_reset_work(tsph::Ctx *c, hipStream_t st);
+
+#define TSPH_HIP_CHECK(c, call)                                                               \
+  do {                                                                                        \
+    hipError_t _e = (call);                                                                   \
+    if (_e != hipSuccess) {                                                                   \
+      snprintf((c)->err, sizeof((c)->err), "%s:%d %s: %s", __FILE__, __LINE__, #call,          \
+               hipGetErrorString(_e));                                                        \
+      return TSPH_EHIP;                                                                       \
+    }                                                                                         \
+  } while (0)

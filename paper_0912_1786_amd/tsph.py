@@ -1,0 +1,302 @@
+"""Thin ctypes binding of the HIP library (``libtsph.so``, C ABI in
+``include/tsph.h``).
+
+Every function here only marshals arguments: device pointers come from torch
+tensors (``data_ptr()``), streams from ``torch.cuda.current_stream()``.  The
+computation runs in the library's HIP kernels.  Loading fails loudly when the
+library is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsph.so")
+
+TSPH_OK, TSPH_EINVAL, TSPH_ENOMEM, TSPH_EHIP, TSPH_ECAPACITY, TSPH_ENOCONV, TSPH_EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
+SOFT_ADAPTIVE, SOFT_CONSTANT, SOFT_ADAPTIVE_NOCORR = 0, 1, 2
+FP64 = 0
+KD_FIRST, KD_SECOND = 0, 1
+FLAG_NODE_CAPACITY, FLAG_STACK_OVERFLOW, FLAG_LIST_OVERFLOW, FLAG_NOCONV, FLAG_NONFINITE, FLAG_INTERNAL = (
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20)
+DBG_KEYS, DBG_PERM, DBG_NODES, DBG_NNODES, DBG_MOMENTS, DBG_GROUPS, DBG_NGROUPS, DBG_COUNTS, DBG_NBR, DBG_ROOT, \
+    DBG_SOLVE = range(11)
+SOLVE_FIELDS = ("nh", "omega", "zeta", "divv", "neps", "ups", "xi", "maxmu")
+
+
+class TsphError(RuntimeError):
+    def __init__(self, fn, status, msg=""):
+        super().__init__(f"{fn} failed with status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("G", C.c_double), ("theta", C.c_double), ("quadrupole", C.c_int32), ("soft_mode", C.c_int32),
+                ("eta_h", C.c_double), ("eta_eps", C.c_double), ("gamma", C.c_double), ("alpha", C.c_double),
+                ("beta", C.c_double), ("av_eps2", C.c_double), ("tc92", C.c_int32), ("h_maxit", C.c_int32),
+                ("h_tol", C.c_double), ("kappa", C.c_double), ("leaf_size", C.c_int32),
+                ("group_size", C.c_int32), ("precision", C.c_int32), ("gravity", C.c_int32),
+                ("hydro", C.c_int32), ("reserved", C.c_int32), ("eta_dt", C.c_double)]
+
+
+_P = C.c_void_p
+
+
+class State(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_gas", C.c_int64),
+                ("x", _P), ("y", _P), ("z", _P), ("vx", _P), ("vy", _P), ("vz", _P), ("m", _P), ("u", _P),
+                ("vpx", _P), ("vpy", _P), ("vpz", _P), ("up", _P), ("h", _P), ("eps", _P),
+                ("ax", _P), ("ay", _P), ("az", _P), ("dudt", _P), ("rho", _P), ("pot", _P)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libtsph.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0912_1786_amd/build.py "
+                               "(or __graft_entry__.build()); there is no fallback path")
+        L = C.CDLL(LIB_PATH)
+        P, S = C.POINTER(Params), C.POINTER(State)
+        sig = {
+            "tsph_create": ([C.POINTER(C.c_void_p), C.c_int64, P], C.c_int),
+            "tsph_destroy": ([_P], C.c_int),
+            "tsph_set_params": ([_P, P], C.c_int),
+            "tsph_default_params": ([P], None),
+            "tsph_bytes_required": ([C.c_int64, P, C.POINTER(C.c_size_t)], C.c_int),
+            "tsph_build_tree": ([_P, S, _P], C.c_int),
+            "tsph_compute_forces": ([_P, S, _P], C.c_int),
+            "tsph_kick_drift": ([_P, S, C.c_double, C.c_int32, _P], C.c_int),
+            "tsph_timestep": ([_P, S, _P, _P], C.c_int),
+            "tsph_diagnostics": ([_P, S, _P, _P], C.c_int),
+            "tsph_read_flags": ([_P, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)], C.c_int),
+            "tsph_debug_lists": ([_P, C.c_int32], C.c_int),
+            "tsph_timing": ([_P, C.c_int32], C.c_int),
+            "tsph_phase_times": ([_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+            "tsph_debug_export": ([_P, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+            "tsph_last_error": ([_P], C.c_char_p),
+            "tsph_version": ([], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = L
+    return _LIB
+
+
+EXPORTED = ("tsph_create", "tsph_destroy", "tsph_set_params", "tsph_default_params", "tsph_bytes_required",
+            "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_timestep", "tsph_diagnostics",
+            "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
+            "tsph_timing", "tsph_phase_times")
+PHASES = ("tree", "density", "gravity", "sph", "finish")
+
+
+def _check(fn, rc, ctx=None):
+    if rc != TSPH_OK:
+        msg = ""
+        if ctx is not None:
+            m = lib().tsph_last_error(ctx)
+            msg = m.decode() if m else ""
+        raise TsphError(fn, rc, msg)
+
+
+def eta_from_nnei(nnei: float) -> float:
+    """eta with N_nei = (4 pi / 3) (2 eta)^3."""
+    import math
+    return 0.5 * (3.0 * nnei / (4.0 * math.pi)) ** (1.0 / 3.0)
+
+
+def tsph_default_params(**kw) -> Params:
+    p = Params()
+    lib().tsph_default_params(C.byref(p))
+    if "nnei" in kw:
+        e = eta_from_nnei(kw.pop("nnei"))
+        p.eta_h = p.eta_eps = e
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def tsph_bytes_required(capacity_n: int, p: Params) -> int:
+    b = C.c_size_t(0)
+    _check("tsph_bytes_required", lib().tsph_bytes_required(int(capacity_n), C.byref(p), C.byref(b)))
+    return int(b.value)
+
+
+def tsph_create(capacity_n: int, p: Params):
+    ctx = C.c_void_p()
+    _check("tsph_create", lib().tsph_create(C.byref(ctx), int(capacity_n), C.byref(p)))
+    return ctx
+
+
+def tsph_destroy(ctx):
+    _check("tsph_destroy", lib().tsph_destroy(ctx))
+
+
+def tsph_set_params(ctx, p: Params):
+    _check("tsph_set_params", lib().tsph_set_params(ctx, C.byref(p)), ctx)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def tsph_build_tree(ctx, st: State, stream=None):
+    _check("tsph_build_tree", lib().tsph_build_tree(ctx, C.byref(st), _stream(stream)), ctx)
+
+
+def tsph_compute_forces(ctx, st: State, stream=None):
+    _check("tsph_compute_forces", lib().tsph_compute_forces(ctx, C.byref(st), _stream(stream)), ctx)
+
+
+def tsph_kick_drift(ctx, st: State, dt: float, phase: int, stream=None):
+    _check("tsph_kick_drift", lib().tsph_kick_drift(ctx, C.byref(st), float(dt), int(phase), _stream(stream)), ctx)
+
+
+def tsph_timestep(ctx, st: State, dt_ptr: int, stream=None):
+    _check("tsph_timestep", lib().tsph_timestep(ctx, C.byref(st), C.c_void_p(dt_ptr), _stream(stream)), ctx)
+
+
+def tsph_diagnostics(ctx, st: State, out_ptr: int, stream=None):
+    _check("tsph_diagnostics", lib().tsph_diagnostics(ctx, C.byref(st), C.c_void_p(out_ptr), _stream(stream)), ctx)
+
+
+def tsph_read_flags(ctx):
+    f = C.c_uint32(0)
+    nc = C.c_int64(0)
+    _check("tsph_read_flags", lib().tsph_read_flags(ctx, C.byref(f), C.byref(nc)), ctx)
+    return int(f.value), int(nc.value)
+
+
+def tsph_timing(ctx, enable: bool):
+    _check("tsph_timing", lib().tsph_timing(ctx, int(bool(enable))), ctx)
+
+
+def tsph_phase_times(ctx):
+    """Summed milliseconds per phase (tree, density, gravity, sph, finish) and call count."""
+    ms = (C.c_double * 5)()
+    calls = C.c_int64(0)
+    _check("tsph_phase_times", lib().tsph_phase_times(ctx, ms, C.byref(calls)), ctx)
+    return dict(zip(PHASES, list(ms))), int(calls.value)
+
+
+def tsph_debug_lists(ctx, max_per_particle: int):
+    _check("tsph_debug_lists", lib().tsph_debug_lists(ctx, int(max_per_particle)), ctx)
+
+
+def tsph_debug_export(ctx, what: int, nbytes: int):
+    """Copy a debug array to a host bytes buffer (see TSPH_DBG_* in tsph.h)."""
+    buf = C.create_string_buffer(max(int(nbytes), 8))
+    w = C.c_size_t(0)
+    _check("tsph_debug_export", lib().tsph_debug_export(ctx, int(what), buf, len(buf), C.byref(w)), ctx)
+    return buf.raw[:w.value]
+
+
+def tsph_last_error(ctx) -> str:
+    m = lib().tsph_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def tsph_version() -> str:
+    return lib().tsph_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# convenience: a particle set held in torch device tensors
+# ---------------------------------------------------------------------------
+class Simulation:
+    """Caller-owned FP64 device arrays for one particle system plus a context.
+
+    ``ic`` is a dict from :mod:`paper_0912_1786_amd.inputs`.  The predicted
+    velocity/energy arrays start as copies of v and u (first evaluation).
+    """
+
+    FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "vpx", "vpy", "vpz", "up", "h", "eps", "ax", "ay", "az",
+              "dudt", "rho", "pot")
+
+    def __init__(self, ic: dict, params: Params | None = None, capacity: int | None = None, device: str = "cuda",
+                 want_pot: bool = True, eps_const=None):
+        import torch
+        self.torch = torch
+        self.n = int(ic["n"])
+        self.n_gas = int(ic["n_gas"])
+        self.params = params if params is not None else tsph_default_params()
+        dev = torch.device(device)
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
+        z = lambda: torch.zeros(self.n, dtype=torch.float64, device=dev)
+        self.a = {}
+        for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u"):
+            self.a[k] = t(ic[k])
+        self.a["vpx"], self.a["vpy"], self.a["vpz"] = (self.a[k].clone() for k in ("vx", "vy", "vz"))
+        self.a["up"] = self.a["u"].clone()
+        self.a["h"] = z()
+        self.a["eps"] = z() if eps_const is None else t(eps_const)
+        for k in ("ax", "ay", "az", "dudt", "rho"):
+            self.a[k] = z()
+        self.a["pot"] = z() if want_pot else None
+        self.ctx = tsph_create(capacity or self.n, self.params)
+        self.state = self._state()
+        self.diag_buf = torch.zeros(9, dtype=torch.float64, device=dev)
+        self.dt_buf = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def _state(self) -> State:
+        st = State()
+        st.n, st.n_gas = self.n, self.n_gas
+        for k in self.FIELDS:
+            v = self.a[k]
+            setattr(st, k, None if v is None else v.data_ptr())
+        return st
+
+    def compute_forces(self, stream=None):
+        tsph_compute_forces(self.ctx, self.state, stream)
+
+    def kick_drift(self, dt: float, phase: int, stream=None):
+        tsph_kick_drift(self.ctx, self.state, dt, phase, stream)
+
+    def timestep(self, stream=None) -> float:
+        tsph_timestep(self.ctx, self.state, self.dt_buf.data_ptr(), stream)
+        return float(self.dt_buf.item())
+
+    def diagnostics(self, stream=None):
+        tsph_diagnostics(self.ctx, self.state, self.diag_buf.data_ptr(), stream)
+        return self.diag_buf.cpu().numpy()
+
+    def step(self, dt: float, stream=None):
+        """One KDK step; assumes forces of the current state are present."""
+        self.kick_drift(dt, KD_FIRST, stream)
+        self.compute_forces(stream)
+        self.kick_drift(dt, KD_SECOND, stream)
+
+    def flags(self):
+        return tsph_read_flags(self.ctx)
+
+    def host(self, k):
+        return self.a[k].cpu().numpy()
+
+    def export(self, what: int, dtype, count: int):
+        import numpy as np
+        raw = tsph_debug_export(self.ctx, what, count * np.dtype(dtype).itemsize)
+        return np.frombuffer(raw, dtype=dtype).copy()
+
+    def close(self):
+        if self.ctx is not None:
+            tsph_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

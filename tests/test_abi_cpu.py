@@ -1,0 +1,50 @@
+"""The C-ABI library loads on a CPU-only machine and exports every symbol that
+include/tsph.h declares; host-only entry points work without a GPU."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "tsph.h")).read()
+    return sorted(set(re.findall(r"\b(tsph_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_0912_1786_amd import tsph
+    if not os.path.exists(tsph.LIB_PATH):
+        from paper_0912_1786_amd import build
+        build.build()
+    return tsph
+
+
+def test_every_declared_symbol_is_exported(T):
+    L = T.lib()
+    names = _declared()
+    assert "tsph_compute_forces" in names and "tsph_kick_drift" in names and "tsph_build_tree" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(T.EXPORTED) == set(names)
+
+
+def test_host_only_entry_points(T):
+    p = T.tsph_default_params()
+    assert p.theta == 0.5 and p.quadrupole == 1 and p.leaf_size == 16 and p.group_size == 64
+    assert abs(p.eta_h - T.eta_from_nnei(50)) < 1e-12
+    b = T.tsph_bytes_required(1 << 21, p)
+    assert 300 * (1 << 21) < b < 2000 * (1 << 21)  # a few hundred bytes per particle
+    bad = T.tsph_default_params(leaf_size=0)
+    with pytest.raises(T.TsphError):
+        T.tsph_bytes_required(1000, bad)
+    assert "gfx950" in T.tsph_version()
+
+
+def test_param_struct_layout_matches_header(T):
+    import ctypes as C
+    # field order and padding of tsph_params / tsph_state as declared
+    assert C.sizeof(T.Params) == 8 * 2 + 4 * 2 + 8 * 6 + 4 * 2 + 8 * 2 + 4 * 6 + 8
+    assert C.sizeof(T.State) == 8 * 2 + 8 * 20
