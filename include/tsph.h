@@ -128,7 +128,7 @@ tsph_status tsph_destroy(void *ctx);
 tsph_status tsph_set_params(void *ctx, const tsph_params *p);
 /* Fill p with the defaults: G=1, theta=0.5, quadrupoles, adaptive softening,
  * 50 neighbours, gamma=5/3, alpha=1, beta=2, av_eps2=0.01, TC92 on,
- * h_tol=1e-6, kappa=0.1, leaf 16, group 64, eta_dt=0.1. */
+ * h_tol=1e-10, kappa=0.1, leaf 16, group 64, eta_dt=0.1. */
 void tsph_default_params(tsph_params *p);
 /* Device bytes a context of this capacity reserves (host-only, no GPU). */
 tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t *bytes);
@@ -178,8 +178,11 @@ enum { TSPH_DBG_KEYS = 0,      /* uint64[n] sorted Morton keys                  
                                 * SPH pairs per particle in the last force pass        */
        TSPH_DBG_NBR = 8,       /* int32[3][n][max] neighbour lists, see below          */
        TSPH_DBG_ROOT = 9,      /* double[4] x0, y0, z0, side                            */
-       TSPH_DBG_SOLVE = 10     /* double[8][n] (caller order) nh, omega, zeta, divv,   *
-                                * neps, ups, xi, maxmu                                  */ };
+       TSPH_DBG_SOLVE = 10,    /* double[8][n] (caller order) nh, omega, zeta, divv,   *
+                                * neps, ups, xi, maxmu                                  */
+       TSPH_DBG_BATCHES = 11,  /* int32[nbatches][2] walk batches: group-list ranges   *
+                                * [g0, g1) of consecutive sibling groups packed to <= 64 */
+       TSPH_DBG_NBATCHES = 12  /* int64[1]                                             */ };
 /* Enable per-particle neighbour-list recording (up to max_per_particle
  * entries per particle and kind: density gather r < 2h_i, SPH pairs
  * r < 2max(h_i,h_j), gravity-correction pairs r < 2max(eps_i,eps_j)); lists

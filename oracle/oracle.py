@@ -31,7 +31,8 @@ class Params(C.Structure):
                 ("av_eps2", C.c_double), ("tc92", C.c_int32), ("h_maxit", C.c_int32),
                 ("h_tol", C.c_double), ("kappa", C.c_double), ("leaf_size", C.c_int32),
                 ("group_size", C.c_int32), ("walk_mode", C.c_int32), ("nbr_mode", C.c_int32),
-                ("gravity", C.c_int32), ("hydro", C.c_int32)]
+                ("gravity", C.c_int32), ("hydro", C.c_int32), ("batch_size", C.c_int32),
+                ("batch_mode", C.c_int32)]
 
 
 class Run(C.Structure):
@@ -71,6 +72,8 @@ def lib():
         L.orc_tree_moments.argtypes = [C.c_void_p, D, D, D, D, D, D, D, D]
         L.orc_tree_groups.argtypes = [C.c_void_p, C.c_int32, I64]
         L.orc_tree_groups.restype = C.c_int64
+        L.orc_tree_batches.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, I64, I64]
+        L.orc_tree_batches.restype = C.c_int64
         L.orc_neighbours.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_int64, D, D, D, D, C.c_int32,
                                      I64, I64, C.c_int64]
         L.orc_neighbours.restype = C.c_int64
@@ -104,8 +107,9 @@ def params(**kw) -> Params:
     eta_AV^2 = 0.01 hbar^2, TC92 gradient on, Newton tolerance 1e-6."""
     d = dict(G=1.0, theta=0.5, quadrupole=1, soft_mode=SOFT_ADAPTIVE,
              eta_h=eta_from_nnei(50.0), eta_eps=eta_from_nnei(50.0), gamma=5.0 / 3.0, alpha=1.0,
-             beta=2.0, av_eps2=0.01, tc92=1, h_maxit=60, h_tol=1e-6, kappa=0.1, leaf_size=8,
-             group_size=32, walk_mode=WALK_GROUP, nbr_mode=NBR_TREE, gravity=1, hydro=1)
+             beta=2.0, av_eps2=0.01, tc92=1, h_maxit=60, h_tol=1e-10, kappa=0.1, leaf_size=8,
+             group_size=32, walk_mode=WALK_GROUP, nbr_mode=NBR_TREE, gravity=1, hydro=1, batch_size=64,
+             batch_mode=0)
     if "nnei" in kw:
         e = eta_from_nnei(kw.pop("nnei"))
         d["eta_h"] = d["eta_eps"] = e
@@ -156,7 +160,8 @@ def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=No
     return out
 
 
-def tree(ic_or_xyz, leaf_size: int, m=None, group_size: int | None = None) -> dict:
+def tree(ic_or_xyz, leaf_size: int, m=None, group_size: int | None = None, batch_size: int = 64,
+         batch_mode: int = 0) -> dict:
     if isinstance(ic_or_xyz, dict):
         x, y, z = (_f64(ic_or_xyz[k]) for k in ("x", "y", "z"))
         m = ic_or_xyz.get("m") if m is None else m
@@ -195,6 +200,10 @@ def tree(ic_or_xyz, leaf_size: int, m=None, group_size: int | None = None) -> di
             gn = np.zeros(max(ng, 1), np.int64)
             L.orc_tree_groups(t, group_size, _p(gn, I64))
             out["groups"] = gn[:ng]
+            nb = L.orc_tree_batches(t, group_size, batch_size, batch_mode, I64(), I64())
+            b0, b1 = np.zeros(max(nb, 1), np.int64), np.zeros(max(nb, 1), np.int64)
+            L.orc_tree_batches(t, group_size, batch_size, batch_mode, _p(b0, I64), _p(b1, I64))
+            out["batches"] = np.stack([b0[:nb], b1[:nb]], 1)
         return out
     finally:
         L.orc_tree_free(t)

@@ -448,6 +448,38 @@ int64_t orc_tree_groups(const orc_tree *t, int32_t G, int64_t *group_node)
   return ng;
 }
 
+/* Walk batches: consecutive groups that are consecutive children of the same
+ * parent are packed greedily, in octant order, into batches of at most B
+ * particles.  A batch is the node range [k0, k1) of its member siblings; its
+ * particles are one contiguous range and its box is the union of the
+ * members' boxes.  Returns the number of batches. */
+int64_t orc_tree_batches(const orc_tree *t, int32_t G, int32_t B, int32_t mode, int64_t *bg0, int64_t *bg1)
+{
+  /* batches are ranges [g0, g1) of the group list (ordered by first
+   * particle); mode 0 packs only consecutive children of one parent, mode 1
+   * any consecutive groups */
+  int64_t ng = orc_tree_groups(t, G, NULL);
+  int64_t *gn = malloc((ng + 1) * sizeof(int64_t));
+  orc_tree_groups(t, G, gn);
+  int64_t nb = 0, fill = 0;
+  for (int64_t i = 0; i < ng; i++) {
+    int64_t u = gn[i];
+    int join = nb > 0 && fill + t->count[u] <= B;
+    if (join && mode == 0) join = (u == gn[i - 1] + 1) && t->parent[u] == t->parent[gn[i - 1]];
+    if (join) {
+      fill += t->count[u];
+      if (bg1) bg1[nb - 1] = i + 1;
+    } else {
+      fill = t->count[u];
+      if (bg0) bg0[nb] = i;
+      if (bg1) bg1[nb] = i + 1;
+      nb++;
+    }
+  }
+  free(gn);
+  return nb;
+}
+
 /* ===================================================================== */
 /* Geometry predicates (one rounding per operation, fixed order)           */
 /* ===================================================================== */
@@ -598,42 +630,63 @@ static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, 
  * below tol times the starting value.  Candidates are gathered once within
  * 2 h_guess (1 + kappa) and the search radius is doubled when the root lies
  * beyond it (Sect. 3.1, enlarged search radius). */
-static int solve_length(const ctx_t *C, int64_t p, int gas_only, double eta, double guess,
-                        cand_t *c, double *h_out, int32_t *iters)
+static int solve_length(const ctx_t *C, int64_t p, int gas_only, int mode, double eta, double guess,
+                        int cold, cand_t *c, double *h_out, sums_t *s_out, int32_t *iters)
 {
   const orc_params *P = C->p;
   int64_t set_size = gas_only ? C->n_gas : C->n;
   double eta3 = eta * eta * eta;
   if (!((double)set_size / M_PI > eta3) || !(guess > 0.0)) {
-    *h_out = guess > 0.0 ? guess : 0.0;
+    double h = guess > 0.0 ? guess : 1.0;
+    collect(C, p, 2.0 * h, gas_only, c);
+    *s_out = kernel_sums(C, p, h, c, 1, mode);
+    *h_out = h;
     return 0;
   }
-  double hi = guess * (1.0 + P->kappa);
-  int grow = 0;
-  for (;;) {
-    collect(C, p, 2.0 * hi, gas_only, c);
-    sums_t s = kernel_sums(C, p, hi, c, 0, 0);
-    (*iters)++;
-    if (hi * hi * hi * s.n - eta3 >= 0.0) break;
-    hi *= 2.0;
-    if (++grow > 200) { *h_out = hi; return 0; }
-  }
-  double lo = 0.0, h = guess, hinit = guess;
-  int ok = 0;
+  /* Newton from the starting value (half the volume guess on a cold start);
+   * the candidates cover r < 2 rc and are gathered again, with the margin
+   * kappa, whenever an iterate leaves that radius.  The bracket [lo, hi] of
+   * the monotone g catches steps that leave it (bisection, or doubling while
+   * no upper end is known, which also bounds every step then). */
+  double h = cold ? 0.5 * guess : guess, lo = 0.0, hi = INFINITY, dx_old = INFINITY;
+  double rc = h * (1.0 + P->kappa);
+  collect(C, p, 2.0 * rc, gas_only, c);
+  sums_t s = {0, 0, 0, 0, 0, 0};
+  double h_eval = h;
   for (int it = 0; it < P->h_maxit; it++) {
-    sums_t s = kernel_sums(C, p, h, c, 0, 0);
+    if (h > rc) {
+      rc = h * (1.0 + P->kappa);
+      collect(C, p, 2.0 * rc, gas_only, c);
+    }
+    s = kernel_sums(C, p, h, c, 1, mode);
+    h_eval = h;
     (*iters)++;
     double g = h * h * h * s.n - eta3;
     double gp = 3.0 * h * h * s.n + h * h * h * s.sdh;
     if (g < 0.0) lo = h;
     else hi = h;
-    double hn = h - g / gp;
-    if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
-    if (fabs(hn - h) < P->h_tol * hinit) { h = hn; ok = 1; break; }
+    /* converged when the Newton step is below the tolerance; otherwise a
+     * safeguarded Newton step: one that leaves the bracket, does not halve
+     * the previous step, or more than doubles h while no upper end is known
+     * (g' vanishes when only the particle itself lies within 2h) is replaced
+     * by bisection, or by doubling while no upper end is known */
+    double dx = g / gp;
+    if (fabs(dx) < P->h_tol * h) {
+      /* converged: the step is below tolerance; the quantities are those of
+       * the last evaluated length */
+      *h_out = h;
+      *s_out = s;
+      return 1;
+    }
+    double hn = h - dx;
+    if (!(hn > lo && hn < hi) || fabs(dx) > 0.5 * dx_old || (isinf(hi) && hn > 2.0 * h))
+      hn = isinf(hi) ? 2.0 * h : 0.5 * (lo + hi);
+    dx_old = fabs(hn - h);
     h = hn;
   }
-  *h_out = h;
-  return ok;
+  *h_out = h_eval;
+  *s_out = s;
+  return 0;
 }
 
 static double cold_guess(const ctx_t *C, int64_t p, int gas_only, double eta)
@@ -663,12 +716,11 @@ static void density_phase(ctx_t *C, const double *h_in, const double *eps_in)
       int64_t i = t->perm[p];
       /* gas: smoothing length over gas neighbours (Sect. 3, Eqs. hn, nsum) */
       if (P->hydro && C->gas[p]) {
-        double guess = (h_in && h_in[i] > 0.0) ? h_in[i] : cold_guess(C, p, 1, P->eta_h);
+        int cold = !(h_in && h_in[i] > 0.0);
+        double guess = cold ? cold_guess(C, p, 1, P->eta_h) : h_in[i];
         double h;
-        if (!solve_length(C, p, 1, P->eta_h, guess, &c, &h, &C->iters[p])) noconv++;
-        double hr = h * (1.0 + P->kappa);
-        collect(C, p, 2.0 * hr, 1, &c);
-        sums_t s = kernel_sums(C, p, h, &c, 1, 0);
+        sums_t s;
+        if (!solve_length(C, p, 1, 0, P->eta_h, guess, cold, &c, &h, &s, &C->iters[p])) noconv++;
         C->h[p] = h;
         C->nh[p] = s.n;
         C->rho[p] = s.rho;
@@ -689,12 +741,11 @@ static void density_phase(ctx_t *C, const double *h_in, const double *eps_in)
           C->xi[p] = 0.0;
           C->neps[p] = 0.0;
         } else {
-          double guess = (eps_in && eps_in[i] > 0.0) ? eps_in[i] : cold_guess(C, p, 0, P->eta_eps);
+          int cold = !(eps_in && eps_in[i] > 0.0);
+          double guess = cold ? cold_guess(C, p, 0, P->eta_eps) : eps_in[i];
           double e;
-          if (!solve_length(C, p, 0, P->eta_eps, guess, &c, &e, &C->iters[p])) noconv++;
-          double er = e * (1.0 + P->kappa);
-          collect(C, p, 2.0 * er, 0, &c);
-          sums_t s = kernel_sums(C, p, e, &c, 1, 1);
+          sums_t s;
+          if (!solve_length(C, p, 0, 1, P->eta_eps, guess, cold, &c, &e, &s, &C->iters[p])) noconv++;
           C->eps[p] = e;
           C->neps[p] = s.n;
           /* Upsilon = 1 - (d eps/dn) sum dW/d eps; xi~ = (d eps/dn) sum m dphi/deps
@@ -861,28 +912,42 @@ static void gravity_particle_walk(ctx_t *C)
   }
 }
 
-/* Group mode: every sink of a group (a maximal node of at most group_size
- * particles) receives the interaction set found with the group's bounding box
- * and its largest eps in the opening test.  The set is a superset of each
- * member's per-particle set, so accuracy is at least that of the
- * per-particle walk. */
+/* Group mode: every sink of a walk batch (consecutive sibling groups, each a
+ * maximal node of at most group_size particles, packed up to batch_size
+ * particles) receives the interaction set found with the batch's bounding box
+ * (union of the members' boxes) and its largest eps in the opening test.  The
+ * set is a superset of each member's per-particle set, so accuracy is at
+ * least that of the per-particle walk. */
 static void gravity_group_walk(ctx_t *C)
 {
   const orc_tree *t = C->t;
-  int32_t G = C->p->group_size;
+  int32_t G = C->p->group_size, B = C->p->batch_size;
+  int64_t nb = orc_tree_batches(t, G, B, C->p->batch_mode, NULL, NULL);
   int64_t ng = orc_tree_groups(t, G, NULL);
   int64_t *gn = malloc((ng + 1) * sizeof(int64_t));
   orc_tree_groups(t, G, gn);
+  int64_t *bk0 = malloc((nb + 1) * sizeof(int64_t)), *bk1 = malloc((nb + 1) * sizeof(int64_t));
+  orc_tree_batches(t, G, B, C->p->batch_mode, bk0, bk1);
 #pragma omp parallel
   {
     int64_t *stack = malloc((8 * 22 * 8 + t->nnodes + 16) * sizeof(int64_t));
     int64_t *acc = malloc((t->nnodes + 1) * sizeof(int64_t));
     int64_t *lvs = malloc((t->nnodes + 1) * sizeof(int64_t));
 #pragma omp for schedule(dynamic, 4)
-    for (int64_t g = 0; g < ng; g++) {
-      int64_t kg = gn[g];
-      const double *lo = &t->bmin[3 * kg], *hi = &t->bmax[3 * kg];
-      double emax = C->epsmax[kg];
+    for (int64_t g = 0; g < nb; g++) {
+      double lo[3], hi[3], emax = 0.0;
+      int64_t k0 = gn[bk0[g]], kl = gn[bk1[g] - 1];
+      for (int d = 0; d < 3; d++) { lo[d] = t->bmin[3 * k0 + d]; hi[d] = t->bmax[3 * k0 + d]; }
+      for (int64_t i = bk0[g]; i < bk1[g]; i++) {
+        int64_t k = gn[i];
+        for (int d = 0; d < 3; d++) {
+          if (t->bmin[3 * k + d] < lo[d]) lo[d] = t->bmin[3 * k + d];
+          if (t->bmax[3 * k + d] > hi[d]) hi[d] = t->bmax[3 * k + d];
+        }
+        if (C->epsmax[k] > emax) emax = C->epsmax[k];
+      }
+      int64_t pfirst = t->first[k0];
+      int64_t pend = t->first[kl] + t->count[kl];
       int64_t na = 0, nl = 0, sp = 0;
       stack[sp++] = 0;
       while (sp > 0) {
@@ -891,7 +956,7 @@ static void gravity_group_walk(ctx_t *C)
         else if (t->nchild[k] == 0) lvs[nl++] = k;
         else for (int32_t b = t->nchild[k] - 1; b >= 0; b--) stack[sp++] = t->child[k] + b;
       }
-      for (int64_t p = t->first[kg]; p < t->first[kg] + t->count[kg]; p++) {
+      for (int64_t p = pfirst; p < pend; p++) {
         double a[3] = {0, 0, 0}, pot = 0.0;
         int64_t npair = 0;
         double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
@@ -910,6 +975,8 @@ static void gravity_group_walk(ctx_t *C)
     }
     free(stack); free(acc); free(lvs);
   }
+  free(bk0);
+  free(bk1);
   free(gn);
 }
 

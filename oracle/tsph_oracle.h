@@ -53,6 +53,8 @@ typedef struct {
   int32_t leaf_size, group_size;
   int32_t walk_mode, nbr_mode;
   int32_t gravity, hydro;       /* switches (1 = on)                            */
+  int32_t batch_size;           /* walk batches: groups packed up to this size  */
+  int32_t batch_mode;           /* 0: siblings only, 1: any consecutive groups  */
 } orc_params;
 
 /* All arrays are in caller order, length n unless noted.  Gas particles are
@@ -99,6 +101,11 @@ void orc_tree_moments(const orc_tree *t, double *mass, double *com, double *quad
                       double *centre, double *side, double *delta, double *bmin, double *bmax);
 /* groups: maximal nodes holding at most group_size particles, by first particle */
 int64_t orc_tree_groups(const orc_tree *t, int32_t group_size, int64_t *group_node);
+/* walk batches: runs of consecutive groups (mode 0: consecutive children of
+ * one parent only) packed greedily up to batch_size particles; ranges
+ * [g0, g1) of the group list */
+int64_t orc_tree_batches(const orc_tree *t, int32_t group_size, int32_t batch_size, int32_t mode, int64_t *g0,
+                         int64_t *g1);
 
 /* ---- neighbour sets (bit-exact list tests) ---------------------------------
  * kind 0: density gather  {j in gas : r_ij < 2 h_i}, sinks = gas

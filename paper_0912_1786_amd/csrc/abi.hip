@@ -77,6 +77,8 @@ size_t layout_bytes(int64_t N, int64_t M, Layout *L) {
   L->add(8 * 6 * N);    // 14 acc
   L->add(4 * 3 * N);    // 15 cnt
   L->add(4 * N);        // 16 gflag
+  L->add(sizeof(GravRec) * N);  // grec
+  L->add(sizeof(SphRec) * N);   // srec
   // nodes
   L->add(sizeof(NodeTopo) * M);  // 17 topo
   L->add(4 * M);        // 18 nlevel
@@ -88,6 +90,8 @@ size_t layout_bytes(int64_t N, int64_t M, Layout *L) {
   L->add(4 * M);        // 24 ctmpn
   L->add(4 * M);        // 25 cscan
   L->add(4 * M);        // 26 groups
+  L->add(8 * M);        // batches
+  L->add(4 * 16);       // nbatches
   // small
   L->add(sizeof(DevRoot));           // 27 root
   L->add(8 * 6 * 512);               // 28 bbox_part
@@ -110,6 +114,20 @@ __global__ void k_reset(int32_t *work, int n) {
 __global__ void k_fill_dbg(int64_t n, int32_t *a) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = -1;
+}
+
+// text of the last tsph_create failure (no context exists to hold it)
+char g_create_err[256] = "";
+
+tsph_status create_fail(Ctx *c, tsph_status s, const char *what, hipError_t e) {
+  snprintf(g_create_err, sizeof(g_create_err), "tsph_create: %s: %s", what,
+           e == hipSuccess ? "failed" : hipGetErrorString(e));
+  if (c) {
+    if (c->h_flags) (void)hipHostFree(c->h_flags);
+    if (c->arena) (void)hipFree(c->arena);
+    delete c;
+  }
+  return s;
 }
 
 tsph_status set_err(Ctx *c, tsph_status s, const char *msg) {
@@ -156,7 +174,7 @@ void tsph_default_params(tsph_params *p) {
   p->av_eps2 = 0.01;
   p->tc92 = 1;
   p->h_maxit = 60;
-  p->h_tol = 1e-6;
+  p->h_tol = 1e-10;
   p->kappa = 0.1;
   p->leaf_size = 16;
   p->group_size = 64;
@@ -177,24 +195,31 @@ tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t
 tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   if (!out) return TSPH_EINVAL;
   *out = nullptr;
-  if (capacity_n < 1 || capacity_n > (int64_t)1 << 30) return TSPH_EINVAL;
-  if (param_error(p)) return TSPH_EINVAL;
+  if (capacity_n < 1 || capacity_n > (int64_t)1 << 30) {
+    snprintf(g_create_err, sizeof(g_create_err), "tsph_create: capacity_n must be in [1, 2^30]");
+    return TSPH_EINVAL;
+  }
+  if (const char *pe = param_error(p)) {
+    snprintf(g_create_err, sizeof(g_create_err), "tsph_create: %s", pe);
+    return TSPH_EINVAL;
+  }
   Ctx *c = new (std::nothrow) Ctx();
   if (!c) return TSPH_ENOMEM;
   memset(c, 0, sizeof(*c));
   c->p = *p;
   c->cap_n = capacity_n;
   c->cap_nodes = node_capacity(capacity_n, p->leaf_size);
-  if (hipGetDevice(&c->device) != hipSuccess) {
-    delete c;
-    return TSPH_EHIP;
-  }
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) return create_fail(c, TSPH_EHIP, "hipGetDevice", e);
+  e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e != hipSuccess) return create_fail(c, TSPH_EHIP, "hipDeviceGetAttribute", e);
   Layout L;
   size_t bytes = layout_bytes(c->cap_n, c->cap_nodes, &L);
-  if (hipMalloc(&c->arena, bytes) != hipSuccess) {
+  e = hipMalloc(&c->arena, bytes);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
-    delete c;
-    return TSPH_ENOMEM;
+    c->arena = nullptr;
+    return create_fail(c, TSPH_ENOMEM, "hipMalloc of the arena", e);
   }
   c->arena_bytes = bytes;
   char *b = (char *)c->arena;
@@ -217,6 +242,8 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->acc = AT(double *);
   c->cnt = AT(int32_t *);
   c->gflag = AT(int32_t *);
+  c->grec = AT(GravRec *);
+  c->srec = AT(SphRec *);
   c->topo = AT(NodeTopo *);
   c->nlevel = AT(int32_t *);
   c->nparent = AT(int32_t *);
@@ -227,6 +254,8 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->ctmpn = AT(int32_t *);
   c->cscan = AT(int32_t *);
   c->groups = AT(int32_t *);
+  c->batches = AT(int2 *);
+  c->nbatches = AT(int32_t *);
   c->root = AT(DevRoot *);
   c->bbox_part = AT(double *);
   c->lvl = AT(int32_t *);
@@ -240,20 +269,16 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->dt = AT(double *);
 #undef AT
   c->perm = c->idx[0];
-  if (hipHostMalloc((void **)&c->h_flags, 64, hipHostMallocDefault) != hipSuccess) {
-    (void)hipFree(c->arena);
-    delete c;
-    return TSPH_ENOMEM;
+  e = hipHostMalloc((void **)&c->h_flags, 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    c->h_flags = nullptr;
+    return create_fail(c, TSPH_ENOMEM, "hipHostMalloc of the flag block", e);
   }
   c->h_noconv = (int32_t *)(c->h_flags + 4);
-  if (hipMemset(c->flags, 0, 64) != hipSuccess || hipMemset(c->noconv, 0, 64) != hipSuccess ||
-      hipMemset(c->lvl, 0, 256) != hipSuccess || hipMemset(c->ngroups, 0, 64) != hipSuccess ||
-      hipDeviceSynchronize() != hipSuccess) {
-    (void)hipHostFree(c->h_flags);
-    (void)hipFree(c->arena);
-    delete c;
-    return TSPH_EHIP;
-  }
+  if ((e = hipMemset(c->flags, 0, 64)) != hipSuccess || (e = hipMemset(c->noconv, 0, 64)) != hipSuccess ||
+      (e = hipMemset(c->lvl, 0, 256)) != hipSuccess || (e = hipMemset(c->ngroups, 0, 64)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess)
+    return create_fail(c, TSPH_EHIP, "clearing the control block", e);
   *out = c;
   return TSPH_OK;
 }
@@ -455,8 +480,9 @@ tsph_status tsph_debug_export(void *ctx, int32_t what, void *host, size_t cap_by
   int32_t lvl[64];
   TSPH_HIP_CHECK(c, hipMemcpy(lvl, c->lvl, sizeof(lvl), hipMemcpyDeviceToHost));
   const int64_t nn = lvl[46];
-  int32_t ngr = 0;
+  int32_t ngr = 0, nbat = 0;
   TSPH_HIP_CHECK(c, hipMemcpy(&ngr, c->ngroups, 4, hipMemcpyDeviceToHost));
+  TSPH_HIP_CHECK(c, hipMemcpy(&nbat, c->nbatches, 4, hipMemcpyDeviceToHost));
   size_t need = 0;
   switch (what) {
     case TSPH_DBG_KEYS: need = 8 * n; break;
@@ -470,6 +496,8 @@ tsph_status tsph_debug_export(void *ctx, int32_t what, void *host, size_t cap_by
     case TSPH_DBG_NBR: need = (size_t)4 * 3 * n * c->dbg_max; break;
     case TSPH_DBG_ROOT: need = 8 * 4; break;
     case TSPH_DBG_SOLVE: need = 8 * (size_t)kNumSolve * n; break;
+    case TSPH_DBG_BATCHES: need = 8 * (size_t)nbat; break;
+    case TSPH_DBG_NBATCHES: need = 8; break;
     default: return set_err(c, TSPH_EINVAL, "unknown export");
   }
   if (written) *written = need;
@@ -479,6 +507,8 @@ tsph_status tsph_debug_export(void *ctx, int32_t what, void *host, size_t cap_by
     case TSPH_DBG_PERM: TSPH_HIP_CHECK(c, hipMemcpy(host, c->perm, need, hipMemcpyDeviceToHost)); break;
     case TSPH_DBG_NNODES: *(int64_t *)host = nn; break;
     case TSPH_DBG_NGROUPS: *(int64_t *)host = ngr; break;
+    case TSPH_DBG_NBATCHES: *(int64_t *)host = nbat; break;
+    case TSPH_DBG_BATCHES: TSPH_HIP_CHECK(c, hipMemcpy(host, c->batches, need, hipMemcpyDeviceToHost)); break;
     case TSPH_DBG_GROUPS: TSPH_HIP_CHECK(c, hipMemcpy(host, c->groups, need, hipMemcpyDeviceToHost)); break;
     case TSPH_DBG_NODES: {
       std::vector<NodeTopo> t(nn);
@@ -550,7 +580,8 @@ tsph_status tsph_debug_export(void *ctx, int32_t what, void *host, size_t cap_by
 
 const char *tsph_last_error(const void *ctx) {
   const Ctx *c = (const Ctx *)ctx;
-  return c ? c->err : "no context";
+  if (c) return c->err;
+  return g_create_err[0] ? g_create_err : "no context";
 }
 
 }  // extern "C"

@@ -28,6 +28,8 @@ struct DensArgs {
   int64_t n, n_gas, cap_n;
   const int32_t *groups;
   const int32_t *ngroups;
+  const int2 *batches;
+  const int32_t *nbatches;
   const NodeTopo *topo;
   const NodeBox *nbox;
   const int32_t *nngas;
@@ -43,6 +45,8 @@ struct DensArgs {
   double4 *sph;
   double *zo;
   double2 *soft;
+  GravRec *grec;
+  SphRec *srec;
   double *solve;
   int32_t *work;
   uint32_t *flags;
@@ -132,18 +136,17 @@ __device__ void leaf_sums(const DensArgs &A, int nleaf, const int *s_leaf, bool 
   const double two_h = 2.0 * h;
   const double R2 = two_h * two_h;
   for (int j = 0; j < nleaf; j++) {
-    const int k = uniform(s_leaf[j]);
-    const NodeTopo nd = A.topo[k];
+    const NodeTopo nd = sload(A.topo + uniform(s_leaf[j]));
     for (int q = nd.first; q < nd.first + nd.count; q++) {
-      if (gas_only && !A.gas[q]) continue;
-      const double4 a = A.pm[q];
+      if (gas_only && !sload_u8(A.gas + q)) continue;
+      const double4 a = sload(A.pm + q);
       const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
       if (kFull && dbg_row && r2 < R2) {
         if (ndbg < A.dbg_max) dbg_row[ndbg] = A.perm[q];
         ndbg++;
       }
       if (!(r2 < R2)) continue;
-      const double r = sqrt(r2);
+      const double r = r2 > 0.0 ? r2 * rsqrt(r2) : 0.0;
       const double qq = r * ih;
       double w, dw;
       m4(qq, w, dw);
@@ -154,10 +157,10 @@ __device__ void leaf_sums(const DensArgs &A, int nleaf, const int *s_leaf, bool 
       if (kFull) {
         s.rho += a.w * W;
         s.msdh += a.w * dWdh;
-        if (want_phi) s.mdphi += a.w * soft_pe(r, h);
+        if (want_phi) s.mdphi += a.w * soft_pe_q(qq, ih);
         if (want_div && r > 0.0) {
-          const double4 v = A.vu[q];
-          const double g = dw * ih4 / r;  // dW/dr / r
+          const double4 v = sload(A.vu + q);
+          const double g = dw * ih4 * (ih / qq);  // dW/dr / r
           s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
         }
       }
@@ -199,9 +202,9 @@ __device__ Cands gather(const DensArgs &A, const NodeBox &gb, double R, bool gas
 template <bool kFull>
 __device__ Sums pass(const DensArgs &A, const NodeBox &gb, const Cands &c, int *s_stack, int *s_leaf,
                      const double4 *s_snk, double px, double py, double pz, const double4 &vp, double h,
-                     bool want_div, bool want_phi, int32_t *dbg_row, bool &fail) {
+                     bool want_div, bool want_phi, int32_t *dbg_row, int &ndbg, bool &fail) {
   Sums s{0, 0, 0, 0, 0, 0};
-  int ndbg = 0;
+  ndbg = 0;
   if (c.cached) {
     leaf_sums<kFull>(A, c.nleaf, s_leaf, c.gas_only, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
   } else {
@@ -211,7 +214,6 @@ __device__ Sums pass(const DensArgs &A, const NodeBox &gb, const Cands &c, int *
     });
     if (!ok) fail = true;
   }
-  if (kFull && dbg_row && ndbg > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
   return s;
 }
 
@@ -235,44 +237,72 @@ __device__ SolveOut solve_length(const DensArgs &A, const NodeBox &gb, bool sink
   const int64_t set_size = gas_only ? A.n_gas : A.n;
   const bool solvable = sink && ((double)set_size / kPi > eta3) && (guess > 0.0);
   bool fail = false;
-  double hi = guess * (1.0 + A.kappa) * (cold ? 0.25 : 1.0);
+  // Newton from the starting value (half the volume guess on a cold start);
+  // candidates cover r < 2 rc and are gathered again, with the margin kappa,
+  // when some lane's iterate leaves its radius.  A step that leaves the
+  // bracket [lo, hi], does not halve the previous step, or more than doubles
+  // h while no upper end is known (g' vanishes when only the particle itself
+  // lies within 2h) is replaced by bisection, or by doubling while no upper
+  // end is known.  Converged when the Newton step is below h_tol h; the
+  // result is the last evaluated length.
+  double h = guess > 0.0 ? (solvable && cold ? 0.5 * guess : guess) : 1.0;
+  double lo = 0.0, hi = INFINITY, dx_old = INFINITY, rc = h * (1.0 + A.kappa);
   Cands c{0, true, 0.0, gas_only};
-  int grow = 0;
-  for (;;) {
-    const double R = wave_max(solvable ? 2.0 * hi : 0.0);
-    if (R <= 0.0) break;
-    s_snk[lane()] = make_double4(px, py, pz, solvable ? 2.0 * hi : 0.0);
-    __syncthreads();
-    c = gather(A, gb, R, gas_only, s_stack, s_leaf, s_snk, fail);
-    if (fail) break;
-    Sums s = pass<false>(A, gb, c, s_stack, s_leaf, s_snk, px, py, pz, vp, solvable ? hi : 1.0, false, false,
-                         nullptr, fail);
-    const bool need = solvable && (hi * hi * hi * s.n - eta3 < 0.0);
-    if (fail || !__any(need) || ++grow > 200) break;
-    if (need) hi *= 2.0;
-  }
-  double lo = 0.0, h = guess > 0.0 ? fmin(guess, hi) : 1.0, hinit = h;
-  bool done = !solvable || fail, ok = false;
+  bool done = !sink, ok = false, gathered = false;
+  int ndbg_keep = 0, ndbg_max = 0;
+  Sums keep{0, 0, 0, 0, 0, 0};
+  double h_keep = h;
   for (int it = 0; it < A.maxit && __any(!done); it++) {
-    Sums s = pass<false>(A, gb, c, s_stack, s_leaf, s_snk, px, py, pz, vp, h, false, false, nullptr, fail);
+    bool need = !gathered;
+    if (!done && h > rc) {
+      rc = h * (1.0 + A.kappa);
+      need = true;
+    }
+    if (__any(need)) {
+      const double R = wave_max(done ? 0.0 : 2.0 * rc);
+      s_snk[lane()] = make_double4(px, py, pz, done ? 0.0 : 2.0 * rc);
+      __syncthreads();
+      c = gather(A, gb, R, gas_only, s_stack, s_leaf, s_snk, fail);
+      gathered = true;
+      if (fail) break;
+    }
+    int ndbg = 0;
+    const Sums s = pass<true>(A, gb, c, s_stack, s_leaf, s_snk, px, py, pz, vp, h, want_div, want_phi,
+                              done ? nullptr : dbg_row, ndbg, fail);
+    if (fail) break;
     if (!done) {
+      keep = s;
+      h_keep = h;
+      ndbg_keep = ndbg;
+      ndbg_max = max(ndbg_max, ndbg);
       const double g = h * h * h * s.n - eta3;
       const double gp = 3.0 * h * h * s.n + h * h * h * s.sdh;
       if (g < 0.0) lo = h;
       else hi = h;
-      double hn = h - g / gp;
-      if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
-      if (fabs(hn - h) < A.h_tol * hinit) {
-        ok = true;
+      const double dx = g / gp;
+      if (!solvable) {
         done = true;
+      } else if (fabs(dx) < A.h_tol * h) {
+        done = true;
+        ok = true;
+      } else {
+        double hn = h - dx;
+        if (!(hn > lo && hn < hi) || fabs(dx) > 0.5 * dx_old || (isinf(hi) && hn > 2.0 * h))
+          hn = isinf(hi) ? 2.0 * h : 0.5 * (lo + hi);
+        dx_old = fabs(hn - h);
+        h = hn;
       }
-      h = hn;
     }
   }
-  o.h = h;
+  // the exported list is that of the last evaluated length; earlier passes
+  // may have been longer
+  if (dbg_row) {
+    for (int k = ndbg_keep; k < min(ndbg_max, A.dbg_max); k++) dbg_row[k] = -1;
+    if (ndbg_keep > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
+  }
+  o.h = h_keep;
   o.ok = ok && !fail;
-  o.s = pass<true>(A, gb, c, s_stack, s_leaf, s_snk, px, py, pz, vp, h, want_div, want_phi,
-                   sink ? dbg_row : nullptr, fail);
+  o.s = keep;
   return o;
 }
 
@@ -291,7 +321,7 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
   __shared__ double4 s_snk[kWave];
   __shared__ int s_g;
   const int ln = lane();
-  const int ng = *A.ngroups;
+  const int ng = *A.nbatches;
   int nnoconv = 0;
   for (;;) {
     if (ln == 0) s_g = atomicAdd(&A.work[0], 1);
@@ -299,9 +329,9 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
     const int g = s_g;
     __syncthreads();
     if (g >= ng) break;
-    const int gk = A.groups[g];
-    const NodeTopo gnd = A.topo[gk];
-    const NodeBox gb = A.nbox[gk];
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
+    const NodeTopo gnd{bt.first, bt.count, -1, 0};
+    const NodeBox gb = bt.box;
     for (int c0 = 0; c0 < gnd.count; c0 += kWave) {
       const bool act = c0 + ln < gnd.count;
       const int p = gnd.first + c0 + (act ? ln : 0);
@@ -358,8 +388,22 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
         A.hs[p] = h;
         A.es[p] = eps;
         A.sph[p] = make_double4(h, rho, c, pr2);
-        A.zo[p] = is_gas ? zeta / omega : 0.0;
-        A.soft[p] = make_double2(eps, (A.gravity && A.soft_mode == TSPH_SOFT_ADAPTIVE) ? xi / ups : 0.0);
+        const double zo = is_gas ? zeta / omega : 0.0;
+        A.zo[p] = zo;
+        const double xiu = (A.gravity && A.soft_mode == TSPH_SOFT_ADAPTIVE) ? xi / ups : 0.0;
+        A.soft[p] = make_double2(eps, xiu);
+        GravRec gr;
+        gr.x = a.x; gr.y = a.y; gr.z = a.z; gr.m = a.w;
+        gr.eps = eps; gr.ieps = eps > 0.0 ? 1.0 / eps : 0.0; gr.xiu = xiu; gr.pad = 0.0;
+        A.grec[p] = gr;
+        if (is_gas) {
+          SphRec sr;
+          sr.x = a.x; sr.y = a.y; sr.z = a.z; sr.m = a.w;
+          sr.vx = vp.x; sr.vy = vp.y; sr.vz = vp.z; sr.im = 1.0 / a.w;
+          sr.h = h; sr.ih = 1.0 / h; sr.rho = rho; sr.c = c;
+          sr.pr2 = pr2; sr.zo = zo; sr.pad0 = 0.0; sr.pad1 = 0.0;
+          A.srec[p] = sr;
+        }
         double *S = A.solve;
         S[kNh * A.cap_n + p] = is_gas ? oh.s.n : 0.0;
         S[kOmega * A.cap_n + p] = omega;
@@ -390,6 +434,8 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
   A.cap_n = c->cap_n;
   A.groups = c->groups;
   A.ngroups = c->ngroups;
+  A.batches = c->batches;
+  A.nbatches = c->nbatches;
   A.topo = c->topo;
   A.nbox = c->nbox;
   A.nngas = c->nngas;
@@ -406,6 +452,8 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
   A.sph = c->sph;
   A.zo = c->zo;
   A.soft = c->soft;
+  A.grec = c->grec;
+  A.srec = c->srec;
   A.solve = c->solve;
   A.work = c->work;
   A.flags = c->flags;
@@ -426,7 +474,8 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
                  ? 1
                  : 0;
   int dev_cus = 256;
-  hipLaunchKernelGGL(k_density, dim3(dev_cus * 8), dim3(64), 0, st, A);
+  (void)dev_cus;
+  hipLaunchKernelGGL(k_density, dim3(persistent_blocks(c, (const void *)k_density)), dim3(64), 0, st, A);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return tsph_impl_refresh(c, st);
 }

@@ -11,8 +11,9 @@
 // the softening reach 2 max(eps) of the group), and appends accepted nodes and
 // opened leaves to LDS lists.  Full lists are flushed: every lane (sink)
 // evaluates every listed interaction, the node or particle record being read
-// with wave-uniform loads.  Accepted nodes act unsoftened through their
-// monopole and quadrupole; particles of opened leaves interact through
+// with scalar loads (four records in flight).  Accepted nodes act unsoftened
+// through their monopole and quadrupole; particles of opened leaves interact
+// through
 //   a_i -= G m_j 1/2 [phi'(r, eps_i) + phi'(r, eps_j)] r_hat
 //   a_i -= G/2 [xi_i/Ups_i W'(r, eps_i) + (m_j/m_i) xi_j/Ups_j W'(r, eps_j)] r_hat
 // (r_hat = (x_i - x_j)/r, xi carrying the neighbour masses).
@@ -26,17 +27,19 @@ constexpr int kGStackCap = 2048;
 constexpr int kGListCap = 128;
 constexpr int kGCellFlush = 64;
 constexpr int kGLeafFlush = 32;
-constexpr double kPiG = 3.14159265358979323846;
+constexpr double kInvPiG = 0.31830988618379067154;
 
 struct GravArgs {
   int64_t cap_n;
   const int32_t *groups;
   const int32_t *ngroups;
+  const int2 *batches;
+  const int32_t *nbatches;
+  const int32_t *nngas;
   const NodeTopo *topo;
   const NodeBox *nbox;
   const NodeFar *nfar;
-  const double4 *pm;
-  const double2 *soft;
+  const GravRec *grec;
   const int32_t *perm;
   const int32_t *nnodes;
   double *acc;
@@ -50,7 +53,7 @@ struct GravArgs {
 };
 
 struct Sink {
-  double x, y, z, m, eps, xiu;
+  double x, y, z, m, im, eps, ieps, xiu;
   double ax, ay, az, pot;
   int p;
   bool act;
@@ -58,16 +61,20 @@ struct Sink {
   int ndbg;
 };
 
+// kernel variants: bit 0 quadrupoles, bit 1 correction terms, bit 2 potential
+constexpr int kQuad = 1, kCorr = 2, kPot = 4;
+
+template <int M>
 __device__ __forceinline__ void far_field(const GravArgs &A, Sink &s, const NodeFar &f) {
   const double dx = s.x - f.cx, dy = s.y - f.cy, dz = s.z - f.cz;
   const double r2 = dx * dx + dy * dy + dz * dz;
-  const double ir = 1.0 / sqrt(r2);
+  const double ir = rsqrt(r2);
   const double ir2 = ir * ir;
   const double ir3 = ir * ir2;
   double fm = f.m * ir3;
   double ph = f.m * ir;
   double ex = 0.0, ey = 0.0, ez = 0.0;
-  if (A.quadrupole) {
+  if (M & kQuad) {
     const double qx = f.qxx * dx + f.qxy * dy + f.qxz * dz;
     const double qy = f.qxy * dx + f.qyy * dy + f.qyz * dz;
     const double qz = f.qxz * dx + f.qyz * dy + f.qzz * dz;
@@ -83,71 +90,101 @@ __device__ __forceinline__ void far_field(const GravArgs &A, Sink &s, const Node
   s.ax += A.G * (ex - fm * dx);
   s.ay += A.G * (ey - fm * dy);
   s.az += A.G * (ez - fm * dz);
-  s.pot -= A.G * ph;
+  if (M & kPot) s.pot -= A.G * ph;
 }
 
-__device__ __forceinline__ void near_pair(const GravArgs &A, Sink &s, const double4 &b, const double2 &sb) {
+// Newtonian pair (both lengths reached): the common case, branch free
+template <int M>
+__device__ __forceinline__ void newton_pair(const GravArgs &A, Sink &s, const GravRec &b) {
   const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
   const double r2 = dx * dx + dy * dy + dz * dz;
-  const double ei = s.eps, ej = sb.x;
-  const double em = fmax(ei, ej);
+  const double ir = rsqrt(r2);
+  const double mr = b.m * ir;
+  const double f = A.G * mr * ir * ir;
+  s.ax -= f * dx;
+  s.ay -= f * dy;
+  s.az -= f * dz;
+  if (M & kPot) s.pot -= A.G * mr;
+}
+
+__device__ __forceinline__ bool softened(const Sink &s, const GravRec &b) {
+  const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double em = fmax(s.eps, b.eps);
+  return r2 < 4.0 * em * em;
+}
+
+template <int M>
+__device__ __forceinline__ void near_pair(const GravArgs &A, Sink &s, const GravRec &b) {
+  const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double em = fmax(s.eps, b.eps);
   if (r2 >= 4.0 * em * em) {
-    const double ir = 1.0 / sqrt(r2);
-    const double mr = b.w * ir;
-    const double f = mr * ir * ir;
-    s.ax -= A.G * f * dx;
-    s.ay -= A.G * f * dy;
-    s.az -= A.G * f * dz;
-    s.pot -= A.G * mr;
+    const double ir = rsqrt(r2);
+    const double mr = b.m * ir;
+    const double f = A.G * mr * ir * ir;
+    s.ax -= f * dx;
+    s.ay -= f * dy;
+    s.az -= f * dz;
+    if (M & kPot) s.pot -= A.G * mr;
     return;
   }
   if (r2 > 0.0) {
-    const double r = sqrt(r2);
-    double F = 0.5 * b.w * (soft_fr(r, ei) + soft_fr(r, ej));
-    if (A.corr) {
-      double wi, dwi, wj, dwj;
-      m4(r / ei, wi, dwi);
-      m4(r / ej, wj, dwj);
-      const double Wi = dwi / (kPiG * ei * ei * ei * ei);
-      const double Wj = dwj / (kPiG * ej * ej * ej * ej);
-      F += 0.5 * (s.xiu * Wi + (b.w / s.m) * sb.y * Wj);
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
+    const double qi = r * s.ieps, qj = r * b.ieps;
+    double F = 0.5 * b.m * (soft_fr_q(qi, s.ieps, ir) + soft_fr_q(qj, b.ieps, ir));
+    if (M & kCorr) {
+      const double ii2 = s.ieps * s.ieps, ij2 = b.ieps * b.ieps;
+      const double Wi = m4_dw(qi) * (ii2 * ii2) * kInvPiG;
+      const double Wj = m4_dw(qj) * (ij2 * ij2) * kInvPiG;
+      F += 0.5 * (s.xiu * Wi + (b.m * s.im) * b.xiu * Wj);
     }
-    const double fr = A.G * F / r;
+    const double fr = A.G * F * ir;
     s.ax -= fr * dx;
     s.ay -= fr * dy;
     s.az -= fr * dz;
-    if (A.want_pot) s.pot += A.G * b.w * 0.5 * (soft_ph(r, ei) + soft_ph(r, ej));
-  } else if (A.want_pot) {
-    s.pot += A.G * b.w * 0.5 * (-1.4 / ei - 1.4 / ej);
+    if (M & kPot) s.pot += A.G * b.m * 0.5 * (soft_ph_q(qi, s.ieps, ir) + soft_ph_q(qj, b.ieps, ir));
+  } else if (M & kPot) {
+    s.pot += A.G * b.m * 0.5 * (-1.4 * s.ieps - 1.4 * b.ieps);
   }
 }
 
+__device__ __forceinline__ void debug_pair(const GravArgs &A, Sink &s, const GravRec &b, int q) {
+  const double r2 = dist2_pair(s.x, s.y, s.z, b.x, b.y, b.z);
+  const double R = 2.0 * fmax(s.eps, b.eps);
+  if (r2 < R * R) {
+    if (s.ndbg < A.dbg_max) s.dbg[s.ndbg] = A.perm[q];
+    s.ndbg++;
+  }
+}
+
+template <int M>
 __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
   __shared__ int s_stack[kGStackCap];
   __shared__ int s_cell[kGListCap];
   __shared__ int s_leaf[kGListCap];
   __shared__ int s_g;
   const int ln = lane();
-  const int ng = *A.ngroups;
+  const int ng = *A.nbatches;
   for (;;) {
     if (ln == 0) s_g = atomicAdd(&A.work[1], 1);
     __syncthreads();
     const int g = s_g;
     __syncthreads();
     if (g >= ng) break;
-    const int gk = A.groups[g];
-    const NodeTopo gnd = A.topo[gk];
-    const NodeBox gb = A.nbox[gk];
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
+    const NodeTopo gnd{bt.first, bt.count, -1, 0};
+    const NodeBox gb = bt.box;
     const double gemax = gb.epsmax;
     for (int c0 = 0; c0 < gnd.count; c0 += kWave) {
       Sink s;
       s.act = c0 + ln < gnd.count;
       s.p = gnd.first + c0 + (s.act ? ln : 0);
       {
-        const double4 a = A.pm[s.p];
-        const double2 e = A.soft[s.p];
-        s.x = a.x; s.y = a.y; s.z = a.z; s.m = a.w;
-        s.eps = e.x; s.xiu = e.y;
+        const GravRec r = A.grec[s.p];
+        s.x = r.x; s.y = r.y; s.z = r.z; s.m = r.m; s.im = 1.0 / r.m;
+        s.eps = r.eps; s.ieps = r.ieps; s.xiu = r.xiu;
       }
       s.ax = s.ay = s.az = s.pot = 0.0;
       s.dbg = (A.dbg && s.act) ? A.dbg + ((int64_t)2 * A.cap_n + A.perm[s.p]) * A.dbg_max : nullptr;
@@ -208,31 +245,55 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
         }
         const bool last = (sp == 0) || overflow;
         if (ncell >= kGCellFlush || (last && ncell > 0)) {
-          for (int j = 0; j < ncell; j++) {
-            const int k = uniform(s_cell[j]);
-            const NodeFar f = A.nfar[k];
-            far_field(A, s, f);
+          int j = 0;
+          for (; j + 4 <= ncell; j += 4) {
+            const NodeFar f0 = sload(A.nfar + uniform(s_cell[j]));
+            const NodeFar f1 = sload(A.nfar + uniform(s_cell[j + 1]));
+            const NodeFar f2 = sload(A.nfar + uniform(s_cell[j + 2]));
+            const NodeFar f3 = sload(A.nfar + uniform(s_cell[j + 3]));
+            far_field<M>(A, s, f0);
+            far_field<M>(A, s, f1);
+            far_field<M>(A, s, f2);
+            far_field<M>(A, s, f3);
           }
+          for (; j < ncell; j++) far_field<M>(A, s, sload(A.nfar + uniform(s_cell[j])));
           nfar += ncell;
           ncell = 0;
         }
         if (nleaf >= kGLeafFlush || (last && nleaf > 0)) {
           for (int j = 0; j < nleaf; j++) {
-            const int k = uniform(s_leaf[j]);
-            const NodeTopo nd = A.topo[k];
-            for (int q = nd.first; q < nd.first + nd.count; q++) {
-              const double4 b = A.pm[q];
-              const double2 sb = A.soft[q];
+            const NodeTopo nd = sload(A.topo + uniform(s_leaf[j]));
+            int q = nd.first;
+            const int qe = nd.first + nd.count;
+            for (; q + 4 <= qe; q += 4) {
+              const GravRec b0 = sload(A.grec + q), b1 = sload(A.grec + q + 1);
+              const GravRec b2 = sload(A.grec + q + 2), b3 = sload(A.grec + q + 3);
+              // the self pair and every pair inside 2 max(eps) take the general path
+              const bool slow = (q <= s.p && s.p < q + 4) || softened(s, b0) || softened(s, b1) ||
+                                softened(s, b2) || softened(s, b3);
+              if (!__any(slow)) {
+                newton_pair<M>(A, s, b0);
+                newton_pair<M>(A, s, b1);
+                newton_pair<M>(A, s, b2);
+                newton_pair<M>(A, s, b3);
+              } else {
+                if (q != s.p) near_pair<M>(A, s, b0);
+                if (q + 1 != s.p) near_pair<M>(A, s, b1);
+                if (q + 2 != s.p) near_pair<M>(A, s, b2);
+                if (q + 3 != s.p) near_pair<M>(A, s, b3);
+              }
+              if (s.dbg) {
+                if (q != s.p) debug_pair(A, s, b0, q);
+                if (q + 1 != s.p) debug_pair(A, s, b1, q + 1);
+                if (q + 2 != s.p) debug_pair(A, s, b2, q + 2);
+                if (q + 3 != s.p) debug_pair(A, s, b3, q + 3);
+              }
+            }
+            for (; q < qe; q++) {
+              const GravRec b = sload(A.grec + q);
               if (q != s.p) {
-                near_pair(A, s, b, sb);
-                if (s.dbg) {
-                  const double r2 = dist2_pair(s.x, s.y, s.z, b.x, b.y, b.z);
-                  const double R = 2.0 * fmax(s.eps, sb.x);
-                  if (r2 < R * R) {
-                    if (s.ndbg < A.dbg_max) s.dbg[s.ndbg] = A.perm[q];
-                    s.ndbg++;
-                  }
-                }
+                near_pair<M>(A, s, b);
+                if (s.dbg) debug_pair(A, s, b, q);
               }
             }
             npair += nd.count;
@@ -245,7 +306,7 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
       if (overflow) atomicOr(A.flags, TSPH_FLAG_STACK_OVERFLOW);
       if (s.dbg && s.ndbg > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
       if (s.act) {
-        if (A.want_pot) s.pot += A.G * s.m * (-1.4 / s.eps);  // self term phi(0, eps_i)
+        if (M & kPot) s.pot += A.G * s.m * (-1.4 * s.ieps);  // self term phi(0, eps_i)
         A.acc[0 * A.cap_n + s.p] = s.ax;
         A.acc[1 * A.cap_n + s.p] = s.ay;
         A.acc[2 * A.cap_n + s.p] = s.az;
@@ -282,11 +343,13 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
   A.cap_n = c->cap_n;
   A.groups = c->groups;
   A.ngroups = c->ngroups;
+  A.batches = c->batches;
+  A.nbatches = c->nbatches;
+  A.nngas = c->nngas;
   A.topo = c->topo;
   A.nbox = c->nbox;
   A.nfar = c->nfar;
-  A.pm = c->pm;
-  A.soft = c->soft;
+  A.grec = c->grec;
   A.perm = c->perm;
   A.nnodes = c->lvl + 46;
   A.acc = c->acc;
@@ -299,7 +362,19 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
   A.quadrupole = c->p.quadrupole;
   A.corr = c->p.soft_mode == TSPH_SOFT_ADAPTIVE ? 1 : 0;
   A.want_pot = want_pot ? 1 : 0;
-  hipLaunchKernelGGL(k_gravity, dim3(256 * 8), dim3(64), 0, st, A);
+  const int mode = (A.quadrupole ? kQuad : 0) | (A.corr ? kCorr : 0) | (A.want_pot ? kPot : 0);
+  void (*kern)(GravArgs) = nullptr;
+  switch (mode) {
+    case 0: kern = k_gravity<0>; break;
+    case 1: kern = k_gravity<1>; break;
+    case 2: kern = k_gravity<2>; break;
+    case 3: kern = k_gravity<3>; break;
+    case 4: kern = k_gravity<4>; break;
+    case 5: kern = k_gravity<5>; break;
+    case 6: kern = k_gravity<6>; break;
+    default: kern = k_gravity<7>; break;
+  }
+  hipLaunchKernelGGL(kern, dim3(persistent_blocks(c, (const void *)kern)), dim3(64), 0, st, A);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

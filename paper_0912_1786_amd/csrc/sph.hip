@@ -25,12 +25,14 @@ namespace tsph {
 constexpr int kSStackCap = 1536;
 constexpr int kSListCap = 128;
 constexpr int kSLeafFlush = 32;
-constexpr double kPiS = 3.14159265358979323846;
+constexpr double kInvPiS = 0.31830988618379067154;
 
 struct SphArgs {
   int64_t cap_n;
   const int32_t *groups;
   const int32_t *ngroups;
+  const int2 *batches;
+  const int32_t *nbatches;
   const NodeTopo *topo;
   const NodeBox *nbox;
   const int32_t *nngas;
@@ -38,6 +40,7 @@ struct SphArgs {
   const double4 *vu;
   const double4 *sph;   // h, rho, c, P/rho^2
   const double *zo;     // zeta / Omega*
+  const SphRec *srec;
   const uint8_t *gas;
   const int32_t *perm;
   const int32_t *nnodes;
@@ -58,7 +61,7 @@ __global__ __launch_bounds__(64) void k_sph(SphArgs A) {
   __shared__ double4 s_snk[kWave];
   __shared__ int s_g;
   const int ln = lane();
-  const int ng = *A.ngroups;
+  const int ng = *A.nbatches;
   const bool tc = A.tc92 != 0;
   for (;;) {
     if (ln == 0) s_g = atomicAdd(&A.work[2], 1);
@@ -66,10 +69,10 @@ __global__ __launch_bounds__(64) void k_sph(SphArgs A) {
     const int g = s_g;
     __syncthreads();
     if (g >= ng) break;
-    const int gk = A.groups[g];
-    if (A.nngas[gk] == 0) continue;
-    const NodeTopo gnd = A.topo[gk];
-    const NodeBox gb = A.nbox[gk];
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
+    if (bt.ngas == 0) continue;
+    const NodeTopo gnd{bt.first, bt.count, -1, 0};
+    const NodeBox gb = bt.box;
     const double ghmax = gb.hmax;
     for (int c0 = 0; c0 < gnd.count; c0 += kWave) {
       const bool act = c0 + ln < gnd.count;
@@ -134,15 +137,15 @@ __global__ __launch_bounds__(64) void k_sph(SphArgs A) {
         }
         const bool last = (sp == 0) || overflow;
         if (nleaf >= kSLeafFlush || (last && nleaf > 0)) {
+          const double ihi = 1.0 / hi, imi = 1.0 / mi;
+          const double ihi4 = ihi * ihi * ihi * ihi * kInvPiS;
           for (int j = 0; j < nleaf; j++) {
-            const int k = uniform(s_leaf[j]);
-            const NodeTopo nd = A.topo[k];
+            const NodeTopo nd = sload(A.topo + uniform(s_leaf[j]));
             for (int q = nd.first; q < nd.first + nd.count; q++) {
-              if (!A.gas[q]) continue;
-              const double4 b = A.pm[q];
-              const double4 hj4 = A.sph[q];
+              if (!sload_u8(A.gas + q)) continue;
+              const SphRec b = sload(A.srec + q);
               const double r2x = dist2_pair(a.x, a.y, a.z, b.x, b.y, b.z);
-              const double R = 2.0 * fmax(hi, hj4.x);
+              const double R = 2.0 * fmax(hi, b.h);
               if (!(sink && q != p && r2x < R * R)) continue;
               if (dbg) {
                 if (ndbg < A.dbg_max) dbg[ndbg] = A.perm[q];
@@ -152,27 +155,25 @@ __global__ __launch_bounds__(64) void k_sph(SphArgs A) {
               const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
               const double r2 = r2x;
               if (!(r2 > 0.0)) continue;
-              const double r = sqrt(r2);
-              const double hj = hj4.x;
-              const double ihi = 1.0 / hi, ihj = 1.0 / hj;
-              const double gi = m4_grad(r * ihi, tc) * (ihi * ihi * ihi * ihi) / (kPiS * r);
-              const double gj = m4_grad(r * ihj, tc) * (ihj * ihj * ihj * ihj) / (kPiS * r);
-              const double mj = b.w;
-              const double zj = A.zo[q];
-              const double fij = 1.0 + zi / mj;
-              const double fji = 1.0 + zj / mi;
+              const double ir = rsqrt(r2);
+              const double r = r2 * ir;
+              const double ihj2 = b.ih * b.ih;
+              const double gi = m4_grad(r * ihi, tc) * ihi4 * ir;
+              const double gj = m4_grad(r * b.ih, tc) * (ihj2 * ihj2 * kInvPiS) * ir;
+              const double mj = b.m;
+              const double fij = 1.0 + zi * b.im;
+              const double fji = 1.0 + b.zo * imi;
               const double Ai = hd.w * fij;
-              const double Aj = hj4.w * fji;
-              const double4 vj = A.vu[q];
-              const double vx = v.x - vj.x, vy = v.y - vj.y, vz = v.z - vj.z;
+              const double Aj = b.pr2 * fji;
+              const double vx = v.x - b.vx, vy = v.y - b.vy, vz = v.z - b.vz;
               const double vd = vx * dx + vy * dy + vz * dz;
               double sf = mj * (Ai * gi + Aj * gj);
               double e = mj * Ai * gi * vd;
               if (vd < 0.0) {
-                const double hb = 0.5 * (hi + hj);
+                const double hb = 0.5 * (hi + b.h);
                 const double mu = hb * vd / (r2 + A.av_eps2 * hb * hb);
-                const double cb = 0.5 * (hd.z + hj4.z);
-                const double rb = 0.5 * (hd.y + hj4.y);
+                const double cb = 0.5 * (hd.z + b.c);
+                const double rb = 0.5 * (hd.y + b.rho);
                 const double Pi = (-A.alpha * cb * mu + A.beta * mu * mu) / rb;
                 const double Gb = 0.5 * (fij * gi + fji * gj);
                 sf += mj * Pi * Gb;
@@ -229,6 +230,8 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   A.cap_n = c->cap_n;
   A.groups = c->groups;
   A.ngroups = c->ngroups;
+  A.batches = c->batches;
+  A.nbatches = c->nbatches;
   A.topo = c->topo;
   A.nbox = c->nbox;
   A.nngas = c->nngas;
@@ -236,6 +239,7 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   A.vu = c->vu;
   A.sph = c->sph;
   A.zo = c->zo;
+  A.srec = c->srec;
   A.gas = c->gas;
   A.perm = c->perm;
   A.nnodes = c->lvl + 46;
@@ -250,7 +254,7 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   A.beta = c->p.beta;
   A.av_eps2 = c->p.av_eps2;
   A.tc92 = c->p.tc92;
-  hipLaunchKernelGGL(k_sph, dim3(256 * 8), dim3(64), 0, st, A);
+  hipLaunchKernelGGL(k_sph, dim3(persistent_blocks(c, (const void *)k_sph)), dim3(64), 0, st, A);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

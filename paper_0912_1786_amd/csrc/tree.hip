@@ -19,6 +19,24 @@ int blocks_for(int64_t n, int threads, int max_blocks) {
   return (int)b;
 }
 
+int persistent_blocks(Ctx *c, const void *kernel) {
+  for (int i = 0; i < 16; i++)
+    if (c->occ_kernel[i] == kernel) return c->occ_blocks[i];
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess || per_cu < 1) {
+    (void)hipGetLastError();
+    per_cu = 8;
+  }
+  const int blocks = (c->n_cu > 0 ? c->n_cu : 256) * per_cu;
+  for (int i = 0; i < 16; i++)
+    if (!c->occ_kernel[i]) {
+      c->occ_kernel[i] = kernel;
+      c->occ_blocks[i] = blocks;
+      break;
+    }
+  return blocks;
+}
+
 // ---------------------------------------------------------------------------
 // root cube
 // ---------------------------------------------------------------------------
@@ -570,6 +588,47 @@ __global__ __launch_bounds__(256) void k_group_compact(int64_t n, const int32_t 
     }
 }
 
+// Walk batches: a run of consecutive groups that are consecutive children of
+// one parent is packed greedily, in octant order, into batches of at most
+// batch_size particles.  One thread per run start marks the batch starts.
+__device__ __forceinline__ bool next_sibling(const int32_t *groups, const int32_t *nparent, int g) {
+  const int u = groups[g], v = groups[g - 1];
+  return u == v + 1 && nparent[u] == nparent[v];
+}
+
+__global__ __launch_bounds__(256) void k_batch_mark(const int32_t *__restrict__ ngroups,
+                                                    const int32_t *__restrict__ groups,
+                                                    const int32_t *__restrict__ nparent,
+                                                    const NodeTopo *__restrict__ topo, int batch_size,
+                                                    int32_t *__restrict__ bstart) {
+  const int ng = *ngroups;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
+    if (g > 0 && next_sibling(groups, nparent, g)) continue;  // not a run start
+    int fill = 0;
+    for (int h = g; h < ng && (h == g || next_sibling(groups, nparent, h)); h++) {
+      const int c = topo[groups[h]].count;
+      const bool start = (h == g) || (fill + c > batch_size);
+      bstart[h] = start ? 1 : 0;
+      fill = start ? c : fill + c;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_emit(const int32_t *__restrict__ ngroups,
+                                                    const int32_t *__restrict__ bstart,
+                                                    const int32_t *__restrict__ bpos, int2 *__restrict__ batches,
+                                                    int64_t cap, uint32_t *__restrict__ flags) {
+  const int ng = *ngroups;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
+    if (!bstart[g]) continue;
+    int e = g + 1;
+    while (e < ng && !bstart[e]) e++;
+    const int b = bpos[g];
+    if (b >= 0 && b < cap) batches[b] = make_int2(g, e);
+    else atomicOr(flags, TSPH_FLAG_INTERNAL);
+  }
+}
+
 }  // namespace tsph
 
 using namespace tsph;
@@ -623,6 +682,13 @@ tsph_status tsph_impl_build_tree(Ctx *c, const tsph_state *s, hipStream_t st) {
   launch_scan(c, flag01, n, nullptr, n, pos, c->ngroups, nullptr, 0, st);
   hipLaunchKernelGGL(k_group_compact, dim3(blocks_for(n, T, 8192)), dim3(T), 0, st, n, c->gflag, pos,
                      c->groups, c->cap_nodes, c->flags);
+  // walk batches of sibling groups
+  const int gbl = blocks_for(c->cap_nodes, T, 8192);
+  hipLaunchKernelGGL(k_batch_mark, dim3(gbl), dim3(T), 0, st, c->ngroups, c->groups, c->nparent, c->topo,
+                     kWave, c->ctmpn);
+  launch_scan(c, c->ctmpn, 0, c->ngroups, c->cap_nodes, c->cscan, c->nbatches, nullptr, 0, st);
+  hipLaunchKernelGGL(k_batch_emit, dim3(gbl), dim3(T), 0, st, c->ngroups, c->ctmpn, c->cscan, c->batches,
+                     c->cap_nodes, c->flags);
   TSPH_HIP_CHECK(c, hipGetLastError());
   c->n = n;
   c->n_gas = s->n_gas;

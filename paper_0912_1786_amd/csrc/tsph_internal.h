@@ -41,6 +41,20 @@ struct NodeTopo {
   int32_t first, count, child, nchild;
 };
 
+// Source record of a particle for the gravity walk (64 B, one scalar load).
+struct GravRec {
+  double x, y, z, m;
+  double eps, ieps, xiu, pad;  // eps, 1/eps, xi~ / Upsilon
+};
+
+// Source record of a gas particle for the SPH pairs (128 B).
+struct SphRec {
+  double x, y, z, m;
+  double vx, vy, vz, im;       // predicted velocity, 1/m
+  double h, ih, rho, c;        // h, 1/h, density, sound speed
+  double pr2, zo, pad0, pad1;  // P / rho^2, zeta / Omega*
+};
+
 struct DevRoot {
   double x0, y0, z0, side;  // power-of-two root cube
   double scale;             // 2^(21 - e): key = floor((x - x0) * scale)
@@ -72,6 +86,8 @@ struct Ctx {
   double4 *sph;           // h, rho, c, P/rho^2
   double *zo;             // zeta / Omega*
   double2 *soft;          // eps, xi / Upsilon
+  GravRec *grec;          // gravity source records
+  SphRec *srec;           // SPH source records (gas entries)
   double *solve;          // kNumSolve x cap_n
   double *acc;            // 6 x cap_n: ax, ay, az, pot, dudt, dt_i
   int32_t *cnt;           // 3 x cap_n: far nodes, near pairs, SPH pairs
@@ -85,6 +101,8 @@ struct Ctx {
   int32_t *ctmpn;         // cap_nodes child counts of a level
   int32_t *cscan;         // cap_nodes exclusive scan of ctmpn
   int32_t *groups;        // cap_nodes group nodes
+  int2 *batches;          // cap_nodes walk batches: group ranges [g0, g1)
+  int32_t *nbatches;
   int32_t *gflag;         // cap_n group start flags / scan
 
   // ---- small device state ----
@@ -106,6 +124,11 @@ struct Ctx {
   hipEvent_t (*tev)[6];
   double t_ms[5];
 
+  // ---- launch shapes ----
+  int32_t n_cu;
+  const void *occ_kernel[16];
+  int32_t occ_blocks[16];
+
   // ---- debug ----
   int32_t dbg_max;
   int32_t *dbg_nbr;       // 3 x cap_n x dbg_max (caller index), or null
@@ -126,6 +149,30 @@ __device__ __forceinline__ int mbcnt(uint64_t m) {
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Load through the constant address space: with a wave-uniform address the
+// backend emits scalar (SMEM) loads into SGPRs, one per wave instead of one
+// per lane.  Only for data no kernel of the same launch writes.
+typedef const __attribute__((address_space(4))) uint32_t *cdword_ptr;
+
+template <class T>
+__device__ __forceinline__ T sload(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "records are whole dwords");
+  T v;
+  cdword_ptr src = (cdword_ptr)(p);
+  uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); i++) dst[i] = src[i];
+  return v;
+}
+
+// byte variant: reads the aligned dword holding the byte (arena buffers are
+// padded to 256 bytes, so the dword never leaves the allocation)
+__device__ __forceinline__ uint32_t sload_u8(const uint8_t *p) {
+  const uintptr_t a = (uintptr_t)p;
+  cdword_ptr w = (cdword_ptr)(a & ~(uintptr_t)3);
+  return (*w >> (8 * (a & 3))) & 0xffu;
+}
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
 #pragma unroll
@@ -210,6 +257,38 @@ __device__ __forceinline__ double soft_pe(double r, double e) {
   return (1.6 + q2 * (-4.0 + q * (4.0 + q * (-1.5 + 0.2 * q)))) / (e * e);
 }
 
+// The same softened kernels in division-free form for the inner loops:
+// q = r / e with ie = 1/e and ir = 1/r given (1/(15 q^2 e^2) = ir^2 / 15).
+__device__ __forceinline__ double soft_fr_q(double q, double ie, double ir) {
+  if (q >= 2.0) return ir * ir;
+  const double q2 = q * q, ie2 = ie * ie;
+  if (q < 1.0) return ie2 * q * ((4.0 / 3.0) + q2 * (-1.2 + 0.5 * q));
+  return ie2 * (q * ((8.0 / 3.0) + q * (-3.0 + q * (1.2 - q * (1.0 / 6.0))))) - ir * ir * (1.0 / 15.0);
+}
+
+__device__ __forceinline__ double soft_ph_q(double q, double ie, double ir) {
+  if (q >= 2.0) return -ir;
+  const double q2 = q * q;
+  if (q < 1.0) return ie * (q2 * ((2.0 / 3.0) + q2 * (-0.3 + 0.1 * q)) - 1.4);
+  return ie * (q2 * ((4.0 / 3.0) + q * (-1.0 + q * (0.3 - q * (1.0 / 30.0)))) - 1.6) + ir * (1.0 / 15.0);
+}
+
+__device__ __forceinline__ double soft_pe_q(double q, double ie) {
+  if (q >= 2.0) return 0.0;
+  const double q2 = q * q;
+  if (q < 1.0) return (1.4 + q2 * (-2.0 + q2 * (1.5 - 0.6 * q))) * (ie * ie);
+  return (1.6 + q2 * (-4.0 + q * (4.0 + q * (-1.5 + 0.2 * q)))) * (ie * ie);
+}
+
+__device__ __forceinline__ double m4_dw(double q) {
+  if (q < 1.0) return q * (-3.0 + 2.25 * q);
+  if (q < 2.0) {
+    const double t = 2.0 - q;
+    return -0.75 * t * t;
+  }
+  return 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // exact geometric predicates (one rounding per operation, fixed order)
 // ---------------------------------------------------------------------------
@@ -274,8 +353,47 @@ __device__ __forceinline__ int walk_take(int sp, int cap) {
   return t < sp ? t : sp;
 }
 
+// A walk batch: a run of sibling groups [g0, g1) of the group list; its
+// particles are one contiguous key-order range and its box the union of the
+// members' boxes (max eps and h over the members, summed gas counts).
+struct Batch {
+  int first, count, ngas;
+  NodeBox box;
+};
+
+__device__ __forceinline__ Batch load_batch(const int2 *batches, const int32_t *groups, const NodeTopo *topo,
+                                            const NodeBox *nbox, const int32_t *nngas, int b) {
+  const int2 r = sload(batches + b);
+  Batch B;
+  const int k0 = uniform(sload(groups + r.x));
+  const NodeTopo t0 = sload(topo + k0);
+  B.first = t0.first;
+  B.count = 0;
+  B.ngas = 0;
+  B.box = sload(nbox + k0);
+  for (int g = r.x; g < r.y; g++) {
+    const int k = uniform(sload(groups + g));
+    const NodeTopo t = sload(topo + k);
+    const NodeBox x = sload(nbox + k);
+    B.count += t.count;
+    B.ngas += sload(nngas + k);
+    B.box.lox = fmin(B.box.lox, x.lox);
+    B.box.loy = fmin(B.box.loy, x.loy);
+    B.box.loz = fmin(B.box.loz, x.loz);
+    B.box.hix = fmax(B.box.hix, x.hix);
+    B.box.hiy = fmax(B.box.hiy, x.hiy);
+    B.box.hiz = fmax(B.box.hiz, x.hiz);
+    B.box.epsmax = fmax(B.box.epsmax, x.epsmax);
+    B.box.hmax = fmax(B.box.hmax, x.hmax);
+  }
+  return B;
+}
+
 // host-side launch helpers (defined in the translation units)
 int blocks_for(int64_t n, int threads, int max_blocks);
+// grid of a persistent one-wave-per-workgroup kernel: resident workgroups per
+// CU (from its register and LDS use) times the CU count
+int persistent_blocks(Ctx *c, const void *kernel);
 
 }  // namespace tsph
 

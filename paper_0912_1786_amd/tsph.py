@@ -21,7 +21,7 @@ KD_FIRST, KD_SECOND = 0, 1
 FLAG_NODE_CAPACITY, FLAG_STACK_OVERFLOW, FLAG_LIST_OVERFLOW, FLAG_NOCONV, FLAG_NONFINITE, FLAG_INTERNAL = (
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20)
 DBG_KEYS, DBG_PERM, DBG_NODES, DBG_NNODES, DBG_MOMENTS, DBG_GROUPS, DBG_NGROUPS, DBG_COUNTS, DBG_NBR, DBG_ROOT, \
-    DBG_SOLVE = range(11)
+    DBG_SOLVE, DBG_BATCHES, DBG_NBATCHES = range(13)
 SOLVE_FIELDS = ("nh", "omega", "zeta", "divv", "neps", "ups", "xi", "maxmu")
 
 
@@ -60,6 +60,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0912_1786_amd/build.py "
                                "(or __graft_entry__.build()); there is no fallback path")
+        # torch ships its own HIP runtime and loads it into the global symbol
+        # scope; importing it first makes the library's HIP calls bind to that
+        # same runtime, so torch's device pointers and streams are valid here.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P, S = C.POINTER(Params), C.POINTER(State)
         sig = {
@@ -98,11 +102,9 @@ PHASES = ("tree", "density", "gravity", "sph", "finish")
 
 def _check(fn, rc, ctx=None):
     if rc != TSPH_OK:
-        msg = ""
-        if ctx is not None:
-            m = lib().tsph_last_error(ctx)
-            msg = m.decode() if m else ""
-        raise TsphError(fn, rc, msg)
+        # a NULL context reads the text of the last tsph_create failure
+        m = lib().tsph_last_error(ctx)
+        raise TsphError(fn, rc, m.decode() if m else "")
 
 
 def eta_from_nnei(nnei: float) -> float:

@@ -16,7 +16,8 @@ def oracle_params(orc, gp, walk_mode=None):
                       av_eps2=gp.av_eps2, tc92=gp.tc92, h_maxit=gp.h_maxit, h_tol=gp.h_tol, kappa=gp.kappa,
                       leaf_size=gp.leaf_size, group_size=gp.group_size,
                       walk_mode=orc.WALK_GROUP if walk_mode is None else walk_mode,
-                      nbr_mode=orc.NBR_TREE, gravity=gp.gravity, hydro=gp.hydro)
+                      nbr_mode=orc.NBR_TREE, gravity=gp.gravity, hydro=gp.hydro, batch_size=64,
+                      batch_mode=0)
 
 
 def run_gpu(ic, gp, lists=0, eps_const=None):

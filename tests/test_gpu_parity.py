@@ -61,11 +61,13 @@ def test_keys_perm_topology_groups_bit_exact(orc_mod, case, leaf, group):
     nodes = sim.export(tsph.DBG_NODES, np.int32, 7 * nn).reshape(7, nn)
     ng = int(sim.export(tsph.DBG_NGROUPS, np.int64, 1)[0])
     groups = sim.export(tsph.DBG_GROUPS, np.int32, ng)
+    nbt = int(sim.export(tsph.DBG_NBATCHES, np.int64, 1)[0])
+    batches = sim.export(tsph.DBG_BATCHES, np.int32, 2 * nbt).reshape(nbt, 2)
     mom = sim.export(tsph.DBG_MOMENTS, np.float64, 16 * nn).reshape(16, nn)
     root = sim.export(tsph.DBG_ROOT, np.float64, 4)
     flags, _ = sim.flags()
     sim.close()
-    t = orc_mod.tree(ic, leaf_size=leaf, group_size=group)
+    t = orc_mod.tree(ic, leaf_size=leaf, group_size=group, batch_size=64, batch_mode=0)
     assert flags == 0
     assert np.array_equal(root[:3], t["x0"]) and root[3] == 2.0 ** t["e"]
     assert np.array_equal(keys, t["keys"])
@@ -78,6 +80,7 @@ def test_keys_perm_topology_groups_bit_exact(orc_mod, case, leaf, group):
     assert np.array_equal(nodes[4], t["nchild"])
     assert np.array_equal(nodes[5], t["parent"])
     assert np.array_equal(groups.astype(np.int64), t["groups"])
+    assert np.array_equal(batches.astype(np.int64), t["batches"])
     # moments: masses and centres to round-off, bounding boxes exact
     assert np.allclose(mom[0], t["mass"], rtol=1e-12, atol=0)
     assert np.allclose(mom[1:4].T, t["com"], rtol=0, atol=1e-12 * 2.0 ** t["e"])
@@ -208,8 +211,8 @@ def test_neighbour_lists_bit_exact(orc_mod, case):
         gl = g["lists"][kind]
         for i in range(n):
             got = np.sort(gl[i][gl[i] >= 0])
-            ref = idx[off[i]:off[i + 1]]
-            assert np.array_equal(got, ref), (kind, i)
+            want = idx[off[i]:off[i + 1]]
+            assert np.array_equal(got, want), (kind, i)
 
 
 def test_kdk_step_matches_oracle(orc_mod):
