@@ -38,10 +38,73 @@ PEAK_HBM_GBS = 8000.0
 #   near pair beyond 2 max(eps) (Newtonian branch) ............ 27
 #   near pair inside 2 max(eps) (softened + correction terms) . 110
 F_NODE, F_PAIR, F_SOFT = 60.0, 27.0, 110.0
+# density solves, per candidate inside the kernel support at the converged
+# length (one evaluation per solve and step is the least the method needs):
+#   h solve over gas (W, dW/dh, rho, mass-weighted dW/dh, div v) ....... 45
+#   eps solve over all species (W, dW/dh, mass-weighted d phi/d eps) ... 40
+F_DENS_H, F_DENS_EPS = 45.0, 40.0
+# SPH force pair (two kernel gradients, grad-h factors, pressure, AV) ..... 100
+F_SPH = 100.0
+
+# phase timed by the library -> kernel that dominates it and its source files
+PHASE_KERNEL = {"density": ("k_density", "density.hip"), "gravity": ("k_gravity", "gravity.hip"),
+                "sph": ("k_sph", "sph.hip")}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_two_species_field_2M.txt")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_id(src: str) -> str:
+    """Hash of a kernel's source file and the shared header: a traffic figure
+    measured on other source is stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in (src, "tsph_internal.h"):
+        with open(os.path.join(ROOT, "paper_0912_1786_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, src: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration), or None
+    when absent or taken on different source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    sid = kernel_source_id(src)
+    for line in open(TRAFFIC_FILE):
+        f = line.split()
+        if len(f) >= 2 and f[0] == "kernel" and f[1] == kernel:
+            kv = dict(x.split("=", 1) for x in f[2:] if "=" in x)
+            if kv.get("source_id") == sid and "hbm_bytes_per_launch" in kv:
+                return float(kv["hbm_bytes_per_launch"])
+    return None
+
+
+def algorithmic_flops(c: dict, phase: str, n: int, n_gas: int) -> float:
+    if phase == "gravity":
+        soft = c["softened_pairs_per_particle"]
+        return n * (c["far_nodes_per_particle"] * F_NODE + (c["near_pairs_per_particle"] - soft) * F_PAIR
+                    + soft * F_SOFT)
+    if phase == "density":
+        return (n_gas * c["density_h_candidates_per_gas_particle"] * F_DENS_H
+                + n * c["density_eps_candidates_per_particle"] * F_DENS_EPS)
+    return n_gas * c["sph_pairs_per_gas_particle"] * F_SPH
+
+
+def copy_probe(mib: int):
+    """A plain copy-like kernel of known size (float32 y = 1 * x over `mib`
+    MiB, three launches): the calibration run for the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
 
 
 def cpu_baseline(nps: int, seed: int):
@@ -68,14 +131,16 @@ def cpu_baseline(nps: int, seed: int):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nps", type=int, default=1 << 20, help="particles per species")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--leaf", type=int, default=16)
     ap.add_argument("--group", type=int, default=64)
     ap.add_argument("--cpu-nps", type=int, default=1 << 18, help="per-species size of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run the copy kernel used to calibrate the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this engine has no multi-GPU path (each GPU would run its own "
@@ -86,6 +151,9 @@ def main():
     from paper_0912_1786_amd import inputs, tsph
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     t0 = time.time()
     ic = inputs.two_species_field(n_dm=args.nps, n_gas=args.nps, n_halo=64, seed=args.seed)
     n = ic["n"]
@@ -121,23 +189,21 @@ def main():
     log("[bench] phase ms/step: " + ", ".join(f"{k}={v / calls:.2f}" for k, v in phases.items()))
     value = n * args.steps / (total_ms / 1e3)
 
-    # roofline of the dominant kernel (the gravity walk)
-    dom = max(phases, key=lambda k: phases[k])
-    grav_ms = phases["gravity"] / calls
+    # roofline of the dominant walk kernel
+    dom = max(PHASE_KERNEL, key=lambda k: phases[k])
+    kern, src = PHASE_KERNEL[dom]
+    dom_ms = phases[dom] / calls
     roof = None
     cpath = os.path.join(ROOT, "oracle", "algorithmic_counts.json")
     if os.path.exists(cpath):
         c = json.load(open(cpath))
         if c["n"] == n and c["leaf_size"] == args.leaf:
-            soft = c["softened_pairs_per_particle"]
-            per_particle = (c["far_nodes_per_particle"] * F_NODE
-                            + (c["near_pairs_per_particle"] - soft) * F_PAIR + soft * F_SOFT)
-            flops = n * per_particle
-            achieved = flops / (grav_ms / 1e3) / 1e12
-            roof = {"kernel": "k_gravity", "bound": "alu", "achieved": round(achieved, 3),
+            flops = algorithmic_flops(c, dom, n, ic["n_gas"])
+            achieved = flops / (dom_ms / 1e3) / 1e12
+            roof = {"kernel": kern, "bound": "alu", "achieved": round(achieved, 3),
                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                    "traffic": None, "algorithmic_flop_per_launch": flops, "avg_launch_ms": round(grav_ms, 3),
-                    "dominant_phase": dom}
+                    "traffic": measured_traffic(kern, src), "algorithmic_flop_per_launch": flops,
+                    "avg_launch_ms": round(dom_ms, 3), "source_id": kernel_source_id(src)}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_ms / args.steps, 3),

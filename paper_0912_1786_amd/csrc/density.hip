@@ -123,48 +123,103 @@ __device__ bool walk_leaves(const DensArgs &A, const NodeBox &gb, double R, bool
   return ok;
 }
 
-// kernel sums over a batch of candidate leaves at length h (per lane).  kFull
-// adds the mass density, the mass-weighted h-derivative, the velocity
-// divergence (gas solve) and the mass-weighted d phi / d eps (softening).
+// Candidate particles staged in LDS: position and mass (a species filtered
+// out is moved to infinity), predicted velocity, particle index.
+struct DensTile {
+  double4 pm[kWave];
+  double4 vu[kWave];
+  int q[kWave];
+};
+
+// Per-lane kernel sums over the nt staged candidates at length h.
 template <bool kFull>
-__device__ void leaf_sums(const DensArgs &A, int nleaf, const int *s_leaf, bool gas_only, double px,
-                          double py, double pz, const double4 &vp, double h, bool want_div, bool want_phi,
-                          int32_t *dbg_row, int &ndbg, Sums &s) {
+__device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, int nt, double px, double py,
+                                          double pz, const double4 &vp, double h, bool want_div, bool want_phi,
+                                          int32_t *dbg_row, int &ndbg, Sums &s) {
   const double ih = 1.0 / h;
   const double ih3 = ih * ih * ih / kPi;
   const double ih4 = ih3 * ih;
   const double two_h = 2.0 * h;
   const double R2 = two_h * two_h;
-  for (int j = 0; j < nleaf; j++) {
-    const NodeTopo nd = sload(A.topo + uniform(s_leaf[j]));
-    for (int q = nd.first; q < nd.first + nd.count; q++) {
-      if (gas_only && !sload_u8(A.gas + q)) continue;
-      const double4 a = sload(A.pm + q);
-      const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
-      if (kFull && dbg_row && r2 < R2) {
-        if (ndbg < A.dbg_max) dbg_row[ndbg] = A.perm[q];
-        ndbg++;
+  for (int j = 0; j < nt; j++) {
+    const double4 a = T.pm[j];
+    const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+    if (!(r2 < R2)) continue;
+    if (kFull && dbg_row) {
+      if (ndbg < A.dbg_max) dbg_row[ndbg] = A.perm[T.q[j]];
+      ndbg++;
+    }
+    const double r = r2 > 0.0 ? r2 * rsqrt(r2) : 0.0;
+    const double qq = r * ih;
+    double w, dw;
+    m4(qq, w, dw);
+    const double W = w * ih3;
+    const double dWdh = -(3.0 * w + qq * dw) * ih4;
+    s.n += W;
+    s.sdh += dWdh;
+    if (kFull) {
+      s.rho += a.w * W;
+      s.msdh += a.w * dWdh;
+      if (want_phi) s.mdphi += a.w * soft_pe_q(qq, ih);
+      if (want_div && r > 0.0) {
+        const double4 v = T.vu[j];
+        const double g = dw * ih4 * (ih / qq);  // dW/dr / r
+        s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
       }
-      if (!(r2 < R2)) continue;
-      const double r = r2 > 0.0 ? r2 * rsqrt(r2) : 0.0;
-      const double qq = r * ih;
-      double w, dw;
-      m4(qq, w, dw);
-      const double W = w * ih3;
-      const double dWdh = -(3.0 * w + qq * dw) * ih4;
-      s.n += W;
-      s.sdh += dWdh;
-      if (kFull) {
-        s.rho += a.w * W;
-        s.msdh += a.w * dWdh;
-        if (want_phi) s.mdphi += a.w * soft_pe_q(qq, ih);
-        if (want_div && r > 0.0) {
-          const double4 v = sload(A.vu + q);
-          const double g = dw * ih4 * (ih / qq);  // dW/dr / r
-          s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
+    }
+  }
+}
+
+// Loads the candidate of this lane's slot (lanes below nt) into the tile.
+__device__ __forceinline__ void stage_tile(const DensArgs &A, DensTile &T, int nt, int q, bool gas_only,
+                                           bool want_div) {
+  const int ln = lane();
+  if (ln < nt) {
+    double4 a = A.pm[q];
+    if (gas_only && !A.gas[q]) a = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+    T.pm[ln] = a;
+    if (want_div) T.vu[ln] = A.vu[q];
+    T.q[ln] = q;
+  }
+  __syncthreads();
+}
+
+// Kernel sums over the particles of a batch of candidate leaves at length h
+// (per lane).  The leaves are scanned in order and their particles packed 64
+// to a tile, each lane loading the particle of its slot; every lane then
+// evaluates the whole tile.  kFull adds the mass density, the mass-weighted
+// h-derivative, the velocity divergence (gas solve) and the mass-weighted
+// d phi / d eps (softening).
+template <bool kFull>
+__device__ void leaf_sums(const DensArgs &A, int nleaf, const int *s_leaf, DensTile &T, bool gas_only, double px,
+                          double py, double pz, const double4 &vp, double h, bool want_div, bool want_phi,
+                          int32_t *dbg_row, int &ndbg, Sums &s) {
+  const int ln = lane();
+  int fill = 0, rq = 0;
+  for (int c1 = 0; c1 < nleaf; c1 += kWave) {
+    const int nc = min(kWave, nleaf - c1);
+    const NodeTopo my = ln < nc ? A.topo[s_leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
+    for (int j = 0; j < nc; j++) {
+      const int first = __builtin_amdgcn_readlane(my.first, j);
+      const int count = __builtin_amdgcn_readlane(my.count, j);
+      for (int off = 0; off < count;) {
+        const int tk = min(count - off, kWave - fill);
+        if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
+        fill += tk;
+        off += tk;
+        if (fill == kWave) {
+          stage_tile(A, T, kWave, rq, gas_only, kFull && want_div);
+          tile_sums<kFull>(A, T, kWave, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
+          __syncthreads();
+          fill = 0;
         }
       }
     }
+  }
+  if (fill > 0) {
+    stage_tile(A, T, fill, rq, gas_only, kFull && want_div);
+    tile_sums<kFull>(A, T, fill, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
+    __syncthreads();
   }
 }
 
@@ -201,15 +256,15 @@ __device__ Cands gather(const DensArgs &A, const NodeBox &gb, double R, bool gas
 
 template <bool kFull>
 __device__ Sums pass(const DensArgs &A, const NodeBox &gb, const Cands &c, int *s_stack, int *s_leaf,
-                     const double4 *s_snk, double px, double py, double pz, const double4 &vp, double h,
+                     DensTile &T, const double4 *s_snk, double px, double py, double pz, const double4 &vp, double h,
                      bool want_div, bool want_phi, int32_t *dbg_row, int &ndbg, bool &fail) {
   Sums s{0, 0, 0, 0, 0, 0};
   ndbg = 0;
   if (c.cached) {
-    leaf_sums<kFull>(A, c.nleaf, s_leaf, c.gas_only, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
+    leaf_sums<kFull>(A, c.nleaf, s_leaf, T, c.gas_only, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
   } else {
     bool ok = walk_leaves(A, gb, c.R, c.gas_only, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
-      leaf_sums<kFull>(A, nl, s_leaf, c.gas_only, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
+      leaf_sums<kFull>(A, nl, s_leaf, T, c.gas_only, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
       return true;
     });
     if (!ok) fail = true;
@@ -230,7 +285,7 @@ struct SolveOut {
 // |dh| < h_tol h_start.  Quantities are then evaluated at the final h.
 __device__ SolveOut solve_length(const DensArgs &A, const NodeBox &gb, bool sink, bool gas_only, double eta,
                                  double guess, double px, double py, double pz, double4 vp, bool want_div,
-                                 bool want_phi, int *s_stack, int *s_leaf, double4 *s_snk, bool cold,
+                                 bool want_phi, int *s_stack, int *s_leaf, DensTile &T, double4 *s_snk, bool cold,
                                  int32_t *dbg_row) {
   SolveOut o;
   const double eta3 = eta * eta * eta;
@@ -267,7 +322,7 @@ __device__ SolveOut solve_length(const DensArgs &A, const NodeBox &gb, bool sink
       if (fail) break;
     }
     int ndbg = 0;
-    const Sums s = pass<true>(A, gb, c, s_stack, s_leaf, s_snk, px, py, pz, vp, h, want_div, want_phi,
+    const Sums s = pass<true>(A, gb, c, s_stack, s_leaf, T, s_snk, px, py, pz, vp, h, want_div, want_phi,
                               done ? nullptr : dbg_row, ndbg, fail);
     if (fail) break;
     if (!done) {
@@ -319,6 +374,7 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
   __shared__ int s_stack[kDensStackCap];
   __shared__ int s_leaf[kDensLeafCap];
   __shared__ double4 s_snk[kWave];
+  __shared__ DensTile s_dt;
   __shared__ int s_g;
   const int ln = lane();
   const int ng = *A.nbatches;
@@ -349,7 +405,7 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
         double g0 = A.hs[p];
         double guess = g0 > 0.0 ? g0 : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
         oh = solve_length(A, gb, is_gas, true, A.eta_h, guess, a.x, a.y, a.z, vp, true, A.shared != 0,
-                          s_stack, s_leaf, s_snk, !(g0 > 0.0), is_gas ? dbg0 : nullptr);
+                          s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0), is_gas ? dbg0 : nullptr);
         if (is_gas && !oh.ok) nnoconv++;
       }
       // ---- softening length over all neighbours (all sinks) ----
@@ -366,7 +422,7 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
           double g0 = A.es[p];
           double guess = g0 > 0.0 ? g0 : (act ? cold_guess(A, p, false, A.eta_eps) : 0.0);
           SolveOut oe = solve_length(A, gb, act, false, A.eta_eps, guess, a.x, a.y, a.z, vp, false, true,
-                                     s_stack, s_leaf, s_snk, !(g0 > 0.0), nullptr);
+                                     s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0), nullptr);
           if (act && !oe.ok) nnoconv++;
           eps = oe.h;
           neps = oe.s.n;

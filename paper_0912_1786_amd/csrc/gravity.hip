@@ -9,9 +9,10 @@
 // an LDS stack, tests each against the group's bounding box (opening radius
 // l/theta + delta from the centre of mass, and no particle of the node within
 // the softening reach 2 max(eps) of the group), and appends accepted nodes and
-// opened leaves to LDS lists.  Full lists are flushed: every lane (sink)
-// evaluates every listed interaction, the node or particle record being read
-// with scalar loads (four records in flight).  Accepted nodes act unsoftened
+// opened leaves to LDS lists.  Full lists are flushed through an LDS tile:
+// the lanes load 64 node (or particle) records at once with vector loads,
+// then every lane (sink) evaluates every staged interaction from broadcast
+// LDS reads.  Accepted nodes act unsoftened
 // through their monopole and quadrupole; particles of opened leaves interact
 // through
 //   a_i -= G m_j 1/2 [phi'(r, eps_i) + phi'(r, eps_j)] r_hat
@@ -23,7 +24,7 @@
 
 namespace tsph {
 
-constexpr int kGStackCap = 2048;
+constexpr int kGStackCap = 1024;
 constexpr int kGListCap = 128;
 constexpr int kGCellFlush = 64;
 constexpr int kGLeafFlush = 32;
@@ -159,12 +160,52 @@ __device__ __forceinline__ void debug_pair(const GravArgs &A, Sink &s, const Gra
   }
 }
 
+// Evaluates the nt particle records staged in rec (indices in tq) on sink s.
+template <int M>
+__device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const GravRec *rec, const int *tq, int nt) {
+  int j = 0;
+  for (; j + 2 <= nt; j += 2) {
+    const GravRec b0 = rec[j], b1 = rec[j + 1];
+    const int q0 = tq[j], q1 = tq[j + 1];
+    // the self pair and every pair inside 2 max(eps) take the general path
+    const bool slow = q0 == s.p || q1 == s.p || softened(s, b0) || softened(s, b1);
+    if (!__any(slow)) {
+      newton_pair<M>(A, s, b0);
+      newton_pair<M>(A, s, b1);
+    } else {
+      if (q0 != s.p) near_pair<M>(A, s, b0);
+      if (q1 != s.p) near_pair<M>(A, s, b1);
+    }
+    if (s.dbg) {
+      if (q0 != s.p) debug_pair(A, s, b0, q0);
+      if (q1 != s.p) debug_pair(A, s, b1, q1);
+    }
+  }
+  if (j < nt) {
+    const GravRec b = rec[j];
+    const int q = tq[j];
+    if (q != s.p) {
+      near_pair<M>(A, s, b);
+      if (s.dbg) debug_pair(A, s, b, q);
+    }
+  }
+}
+
 template <int M>
 __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
   __shared__ int s_stack[kGStackCap];
   __shared__ int s_cell[kGListCap];
   __shared__ int s_leaf[kGListCap];
+  // staging tile: 64 node records (far flush) or 64 particle records (near
+  // flush), filled with one vector load per lane and read back as broadcasts
+  __shared__ union {
+    NodeFar far[kWave];
+    GravRec rec[kWave];
+  } s_t;
+  __shared__ int s_tq[kWave];
   __shared__ int s_g;
+  NodeFar *const s_tile = s_t.far;
+  GravRec *const s_rec = s_t.rec;
   const int ln = lane();
   const int ng = *A.nbatches;
   for (;;) {
@@ -196,6 +237,7 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
       const int guard = *A.nnodes + 2;
       if (ln == 0) s_stack[0] = 0;
       __syncthreads();
+
       for (;;) {
         if (sp > 0 && ++rounds > guard) {
           atomicOr(A.flags, TSPH_FLAG_INTERNAL);
@@ -245,58 +287,53 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
         }
         const bool last = (sp == 0) || overflow;
         if (ncell >= kGCellFlush || (last && ncell > 0)) {
-          int j = 0;
-          for (; j + 4 <= ncell; j += 4) {
-            const NodeFar f0 = sload(A.nfar + uniform(s_cell[j]));
-            const NodeFar f1 = sload(A.nfar + uniform(s_cell[j + 1]));
-            const NodeFar f2 = sload(A.nfar + uniform(s_cell[j + 2]));
-            const NodeFar f3 = sload(A.nfar + uniform(s_cell[j + 3]));
-            far_field<M>(A, s, f0);
-            far_field<M>(A, s, f1);
-            far_field<M>(A, s, f2);
-            far_field<M>(A, s, f3);
+          // accepted nodes, 64 per tile
+          for (int t0 = 0; t0 < ncell; t0 += kWave) {
+            const int nt = min(kWave, ncell - t0);
+            if (ln < nt) s_tile[ln] = A.nfar[s_cell[t0 + ln]];
+            __syncthreads();
+            for (int j = 0; j < nt; j++) far_field<M>(A, s, s_tile[j]);
+            __syncthreads();
           }
-          for (; j < ncell; j++) far_field<M>(A, s, sload(A.nfar + uniform(s_cell[j])));
           nfar += ncell;
           ncell = 0;
         }
         if (nleaf >= kGLeafFlush || (last && nleaf > 0)) {
-          for (int j = 0; j < nleaf; j++) {
-            const NodeTopo nd = sload(A.topo + uniform(s_leaf[j]));
-            int q = nd.first;
-            const int qe = nd.first + nd.count;
-            for (; q + 4 <= qe; q += 4) {
-              const GravRec b0 = sload(A.grec + q), b1 = sload(A.grec + q + 1);
-              const GravRec b2 = sload(A.grec + q + 2), b3 = sload(A.grec + q + 3);
-              // the self pair and every pair inside 2 max(eps) take the general path
-              const bool slow = (q <= s.p && s.p < q + 4) || softened(s, b0) || softened(s, b1) ||
-                                softened(s, b2) || softened(s, b3);
-              if (!__any(slow)) {
-                newton_pair<M>(A, s, b0);
-                newton_pair<M>(A, s, b1);
-                newton_pair<M>(A, s, b2);
-                newton_pair<M>(A, s, b3);
-              } else {
-                if (q != s.p) near_pair<M>(A, s, b0);
-                if (q + 1 != s.p) near_pair<M>(A, s, b1);
-                if (q + 2 != s.p) near_pair<M>(A, s, b2);
-                if (q + 3 != s.p) near_pair<M>(A, s, b3);
-              }
-              if (s.dbg) {
-                if (q != s.p) debug_pair(A, s, b0, q);
-                if (q + 1 != s.p) debug_pair(A, s, b1, q + 1);
-                if (q + 2 != s.p) debug_pair(A, s, b2, q + 2);
-                if (q + 3 != s.p) debug_pair(A, s, b3, q + 3);
+          // particles of the opened leaves, packed 64 per tile: the leaves are
+          // scanned in order, each lane noting the particle of its slot, and a
+          // full tile is loaded with one vector load per lane
+          int fill = 0, rq = -1;
+          for (int c1 = 0; c1 < nleaf; c1 += kWave) {
+            const int nc = min(kWave, nleaf - c1);
+            const NodeTopo my = ln < nc ? A.topo[s_leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
+            for (int j = 0; j < nc; j++) {
+              const int first = __builtin_amdgcn_readlane(my.first, j);
+              const int count = __builtin_amdgcn_readlane(my.count, j);
+              npair += count;
+              for (int off = 0; off < count;) {
+                const int tk = min(count - off, kWave - fill);
+                if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
+                fill += tk;
+                off += tk;
+                if (fill == kWave) {
+                  s_rec[ln] = A.grec[rq];
+                  s_tq[ln] = rq;
+                  __syncthreads();
+                  near_tile<M>(A, s, s_rec, s_tq, kWave);
+                  __syncthreads();
+                  fill = 0;
+                }
               }
             }
-            for (; q < qe; q++) {
-              const GravRec b = sload(A.grec + q);
-              if (q != s.p) {
-                near_pair<M>(A, s, b);
-                if (s.dbg) debug_pair(A, s, b, q);
-              }
+          }
+          if (fill > 0) {
+            if (ln < fill) {
+              s_rec[ln] = A.grec[rq];
+              s_tq[ln] = rq;
             }
-            npair += nd.count;
+            __syncthreads();
+            near_tile<M>(A, s, s_rec, s_tq, fill);
+            __syncthreads();
           }
           nleaf = 0;
         }
