@@ -111,7 +111,7 @@ typedef struct {
    * caller copies v and u here */
   double *vpx, *vpy, *vpz, *up;
   /* lengths: in = guess (<= 0: cold start; constant eps in TSPH_SOFT_CONSTANT),
-   * out = solved value */
+   * out = solved value; carried along the drift by tsph_kick_drift */
   double *h, *eps;
   /* outputs */
   double *ax, *ay, *az;      /* total acceleration                              */
@@ -140,7 +140,12 @@ tsph_status tsph_build_tree(void *ctx, const tsph_state *s, void *stream);
  * forces.  Reads x, v^p, u^p, m, h, eps; writes h, eps, a, dudt, rho, pot. */
 tsph_status tsph_compute_forces(void *ctx, tsph_state *s, void *stream);
 /* Leapfrog half steps (Sect. 4.1).  TSPH_KD_FIRST: v^p = v + dt a,
- * u^p = u + dt du/dt, then v += dt/2 a, x += dt v, u += dt/2 du/dt.
+ * u^p = u + dt du/dt, then v += dt/2 a, x += dt v, u += dt/2 du/dt; when
+ * the last tsph_compute_forces on this context had the same n, the positive
+ * lengths h (gas) and eps follow the drift through the continuity equation
+ * (Sect. 2.1: h n^(1/3) = eta, dn/dt = -n div v): h *= 1 + dt/3 div v, with
+ * div v from that evaluation (h kernel for h, eps kernel for eps) and the
+ * factor clamped to [1/2, 2].  They are starting values for the next solve.
  * TSPH_KD_SECOND: v += dt/2 a, u += dt/2 du/dt. */
 tsph_status tsph_kick_drift(void *ctx, tsph_state *s, double dt, int32_t phase, void *stream);
 /* Global time-step (Sect. 4.2) from the last tsph_compute_forces: min over
@@ -178,8 +183,8 @@ enum { TSPH_DBG_KEYS = 0,      /* uint64[n] sorted Morton keys                  
                                 * SPH pairs per particle in the last force pass        */
        TSPH_DBG_NBR = 8,       /* int32[3][n][max] neighbour lists, see below          */
        TSPH_DBG_ROOT = 9,      /* double[4] x0, y0, z0, side                            */
-       TSPH_DBG_SOLVE = 10,    /* double[8][n] (caller order) nh, omega, zeta, divv,   *
-                                * neps, ups, xi, maxmu                                  */
+       TSPH_DBG_SOLVE = 10,    /* double[9][n] (caller order) nh, omega, zeta, divv,   *
+                                * neps, ups, xi, maxmu, divv with the eps kernel        */
        TSPH_DBG_BATCHES = 11,  /* int32[nbatches][2] walk batches: group-list ranges   *
                                 * [g0, g1) of consecutive sibling groups packed to <= 64 */
        TSPH_DBG_NBATCHES = 12  /* int64[1]                                             */ };

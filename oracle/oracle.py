@@ -43,7 +43,8 @@ class Run(C.Structure):
                 ("eps", D), ("neps", D), ("ups", D), ("xi", D),
                 ("ax", D), ("ay", D), ("az", D), ("pot", D), ("dudt", D), ("maxmu", D),
                 ("cnt_node", I64), ("cnt_pair", I64), ("cnt_sph", I64), ("iters", I32),
-                ("n_noconv", C.c_int64), ("sinks", I64), ("n_sinks", C.c_int64), ("cnt_soft", I64)]
+                ("n_noconv", C.c_int64), ("sinks", I64), ("n_sinks", C.c_int64), ("cnt_soft", I64),
+                ("divv_eps", D)]
 
 
 def eta_from_nnei(nnei: float) -> float:
@@ -79,7 +80,7 @@ def lib():
         L.orc_neighbours.restype = C.c_int64
         L.orc_potential_energy.argtypes = [C.c_int64, D, D, D, D, D, C.c_double]
         L.orc_potential_energy.restype = C.c_double
-        L.orc_kick_drift.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_int32] + [D] * 15
+        L.orc_kick_drift.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_int32] + [D] * 19
         L.orc_timestep.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64] + [D] * 12 + [C.c_double]
         L.orc_timestep.restype = C.c_double
         L.orc_diagnostics.argtypes = [C.c_int64, C.c_int64] + [D] * 10
@@ -143,7 +144,7 @@ def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=No
     hin = None if h_in is None else _f64(h_in)
     ein = None if eps_in is None else _f64(eps_in)
     out = {k: np.zeros(n) for k in ("h", "nh", "rho", "omega", "zeta", "divv", "eps", "neps", "ups",
-                                     "xi", "ax", "ay", "az", "pot", "dudt", "maxmu")}
+                                     "xi", "ax", "ay", "az", "pot", "dudt", "maxmu", "divv_eps")}
     cnt = {k: np.zeros(n, np.int64) for k in ("cnt_node", "cnt_pair", "cnt_sph", "cnt_soft")}
     snk = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
     iters = np.zeros(n, np.int32)
@@ -230,14 +231,24 @@ def potential_energy(x, y, z, m, eps, G: float = 1.0) -> float:
     return lib().orc_potential_energy(x.size, _p(x), _p(y), _p(z), _p(m), _p(eps), G)
 
 
-def kick_drift(st: dict, dt: float, phase: int, acc, dudt, pred: dict | None = None):
-    """In-place KDK half step on a state dict (x, y, z, vx, vy, vz, u)."""
+def kick_drift(st: dict, dt: float, phase: int, acc, dudt, pred: dict | None = None,
+               lengths: dict | None = None):
+    """In-place KDK half step on a state dict (x, y, z, vx, vy, vz, u).
+
+    ``lengths`` (phase 0): arrays "h" and "eps", updated in place along the
+    drift from the divergences "divv" and "divv_eps" of the last force
+    evaluation."""
     ax, ay, az = (_f64(a) for a in acc)
     du = _f64(dudt)
     n, n_gas = int(st["n"]), int(st["n_gas"])
     vp = [None] * 4 if pred is None else [pred["vx"], pred["vy"], pred["vz"], pred["u"]]
+    ln = [None] * 4
+    if lengths is not None:
+        ln = [lengths["h"], lengths["eps"], _f64(lengths["divv"]), _f64(lengths["divv_eps"])]
+        for a in ln[:2]:
+            assert a.dtype == np.float64 and a.flags.c_contiguous
     lib().orc_kick_drift(n, n_gas, dt, phase, *(_p(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "u")),
-                         _p(ax), _p(ay), _p(az), _p(du), *(_p(v) for v in vp))
+                         _p(ax), _p(ay), _p(az), _p(du), *(_p(v) for v in vp), *(_p(v) for v in ln))
 
 
 def timestep(prm: Params, st: dict, out: dict, eta_dt: float = 0.1) -> float:

@@ -533,7 +533,7 @@ typedef struct {
   /* sorted-order per-particle data */
   double *vx, *vy, *vz, *u;
   char *gas;
-  double *h, *nh, *rho, *omega, *zeta, *divv;
+  double *h, *nh, *rho, *omega, *zeta, *divv, *divv_e;
   double *eps, *neps, *ups, *xi;
   double *ax, *ay, *az, *pot, *dudt, *maxmu;
   double *P, *cs;
@@ -613,8 +613,14 @@ static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, 
           s.divv += g * (dvx * (px - t->xs[q]) + dvy * (py - t->ys[q]) + dvz * (pz - t->zs[q]));
         }
       } else {
-        /* softening: mass-weighted d phi / d eps (Eq. zeta) */
+        /* softening: mass-weighted d phi / d eps (Eq. zeta), and the
+         * velocity divergence with the eps kernel */
         s.mdphi += mq * orc_dphideps(r, h);
+        if (r > 0.0) {
+          double g = orc_dWdr(r, h) / r;
+          double dvx = C->vx[p] - C->vx[q], dvy = C->vy[p] - C->vy[q], dvz = C->vz[p] - C->vz[q];
+          s.divv += g * (dvx * (px - t->xs[q]) + dvy * (py - t->ys[q]) + dvz * (pz - t->zs[q]));
+        }
       }
     }
   }
@@ -625,11 +631,11 @@ static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, 
  * Eq. (iter); Sect. 3 Eq. (hn)).  The relation eta = h n^(1/3) is solved as
  * g(h) = h^3 n(h) - eta^3 = 0; g is non-decreasing in h (each h^3 W term is),
  * so the root is unique and a bracket is kept.  g'(h) = 3 h^2 n Omega*, the
- * printed f' = -(3 n/h) Upsilon rescaled by -h^3.  Newton steps that
- * leave the bracket fall back to bisection; iteration stops when the step is
- * below tol times the starting value.  Candidates are gathered once within
- * 2 h_guess (1 + kappa) and the search radius is doubled when the root lies
- * beyond it (Sect. 3.1, enlarged search radius). */
+ * printed f' = -(3 n/h) Upsilon rescaled by -h^3.  Safeguarded Newton
+ * steps (below); iteration stops when the Newton step is below tol h, and
+ * the result is the last evaluated length with its sums.  Candidates cover
+ * r < 2 rc, rc = h (1 + kappa), and are gathered again whenever an iterate
+ * exceeds rc (Sect. 3.1, enlarged search radius). */
 static int solve_length(const ctx_t *C, int64_t p, int gas_only, int mode, double eta, double guess,
                         int cold, cand_t *c, double *h_out, sums_t *s_out, int32_t *iters)
 {
@@ -754,6 +760,7 @@ static void density_phase(ctx_t *C, const double *h_in, const double *eps_in)
            * masses) */
           C->ups[p] = 1.0 + (e / (3.0 * s.n)) * s.sdh;
           C->xi[p] = (P->soft_mode == ORC_SOFT_ADAPTIVE) ? -(e / (3.0 * s.n)) * s.mdphi : 0.0;
+          C->divv_e[p] = -s.divv / (s.n * C->ups[p]);
         }
       }
     }
@@ -1140,6 +1147,7 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   }
   C.h = calloc(n, sizeof(double)); C.nh = calloc(n, sizeof(double)); C.rho = calloc(n, sizeof(double));
   C.omega = calloc(n, sizeof(double)); C.zeta = calloc(n, sizeof(double)); C.divv = calloc(n, sizeof(double));
+  C.divv_e = calloc(n, sizeof(double));
   C.eps = calloc(n, sizeof(double)); C.neps = calloc(n, sizeof(double)); C.ups = calloc(n, sizeof(double));
   C.xi = calloc(n, sizeof(double));
   C.ax = calloc(n, sizeof(double)); C.ay = calloc(n, sizeof(double)); C.az = calloc(n, sizeof(double));
@@ -1185,7 +1193,7 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   for (int64_t q = 0; q < n; q++) {
     int64_t i = t->perm[q];
 #define OUT(arr, src) if (r->arr) r->arr[i] = C.src[q]
-    OUT(h, h); OUT(nh, nh); OUT(rho, rho); OUT(omega, omega); OUT(zeta, zeta); OUT(divv, divv);
+    OUT(h, h); OUT(nh, nh); OUT(rho, rho); OUT(omega, omega); OUT(zeta, zeta); OUT(divv, divv); OUT(divv_eps, divv_e);
     OUT(eps, eps); OUT(neps, neps); OUT(ups, ups); OUT(xi, xi);
     OUT(ax, ax); OUT(ay, ay); OUT(az, az); OUT(pot, pot); OUT(dudt, dudt); OUT(maxmu, maxmu);
     OUT(cnt_node, cnt_node); OUT(cnt_pair, cnt_pair); OUT(cnt_sph, cnt_sph); OUT(iters, iters);
@@ -1193,7 +1201,7 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
 #undef OUT
   }
   free(C.vx); free(C.vy); free(C.vz); free(C.u); free(C.gas);
-  free(C.h); free(C.nh); free(C.rho); free(C.omega); free(C.zeta); free(C.divv);
+  free(C.h); free(C.nh); free(C.rho); free(C.omega); free(C.zeta); free(C.divv); free(C.divv_e);
   free(C.eps); free(C.neps); free(C.ups); free(C.xi);
   free(C.ax); free(C.ay); free(C.az); free(C.pot); free(C.dudt); free(C.maxmu);
   free(C.P); free(C.cs); free(C.cnt_node); free(C.cnt_pair); free(C.cnt_sph); free(C.iters);
@@ -1322,13 +1330,26 @@ double orc_potential_energy(int64_t n, const double *x, const double *y, const d
 /* Kick-drift-kick leapfrog (Sect. 4.1).  phase 0: first half kick and drift,
  * plus the predicted end-of-step velocity v_n + a_n dt (and u_n + du_n dt)
  * used by the next force evaluation; phase 1: closing half kick. */
+static double predict_factor(double dt, double divv)
+{
+  double f = 1.0 + (dt / 3.0) * divv;
+  if (!(f >= 0.5)) f = 0.5;
+  else if (f > 2.0) f = 2.0;
+  return f;
+}
+
 void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
                     double *x, double *y, double *z, double *vx, double *vy, double *vz,
                     double *u, const double *ax, const double *ay, const double *az,
-                    const double *dudt, double *vpx, double *vpy, double *vpz, double *up)
+                    const double *dudt, double *vpx, double *vpy, double *vpz, double *up,
+                    double *h, double *eps, const double *divv_h, const double *divv_e)
 {
   for (int64_t i = 0; i < n; i++) {
     if (phase == 0) {
+      /* lengths along the drift: h n^(1/3) = eta with dn/dt = -n div v gives
+       * dh/dt = (h/3) div v (Sect. 2.1); a starting value for the next solve */
+      if (h && divv_h && i < n_gas && h[i] > 0.0) h[i] *= predict_factor(dt, divv_h[i]);
+      if (eps && divv_e && eps[i] > 0.0) eps[i] *= predict_factor(dt, divv_e[i]);
       if (vpx) { vpx[i] = vx[i] + dt * ax[i]; vpy[i] = vy[i] + dt * ay[i]; vpz[i] = vz[i] + dt * az[i]; }
       vx[i] += 0.5 * dt * ax[i];
       vy[i] += 0.5 * dt * ay[i];

@@ -80,6 +80,7 @@ typedef struct {
   const int64_t *sinks;
   int64_t n_sinks;
   int64_t *cnt_soft;                               /* near pairs inside 2 max(eps) */
+  double *divv_eps;                                /* div v with the eps kernel    */
 } orc_run;
 
 /* Full force evaluation: tree, h/eps solves, gravity walk, SPH forces.
@@ -122,11 +123,15 @@ int64_t orc_neighbours(int kind, int mode, int64_t n, int64_t n_gas, const doubl
 /* V = (G/2) sum_i sum_j m_i m_j phi(r_ij, eps_i), self terms included        */
 double orc_potential_energy(int64_t n, const double *x, const double *y, const double *z,
                             const double *m, const double *eps, double G);
-/* kick-drift-kick leapfrog; phase 0 = K1/2 + D (+ predicted v, u), 1 = K1/2 */
+/* kick-drift-kick leapfrog; phase 0 = K1/2 + D (+ predicted v, u, and the
+ * lengths h (gas) and eps (all) carried along the drift by the continuity
+ * equation, h <- h (1 + dt/3 div v) clamped to [1/2, 2], when h / divv_h or
+ * eps / divv_e are given), 1 = K1/2 */
 void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
                     double *x, double *y, double *z, double *vx, double *vy, double *vz,
                     double *u, const double *ax, const double *ay, const double *az,
-                    const double *dudt, double *vpx, double *vpy, double *vpz, double *up);
+                    const double *dudt, double *vpx, double *vpy, double *vpz, double *up,
+                    double *h, double *eps, const double *divv_h, const double *divv_e);
 double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double *vx,
                     const double *vy, const double *vz, const double *u, const double *h,
                     const double *eps, const double *ax, const double *ay, const double *az,

@@ -79,6 +79,7 @@ size_t layout_bytes(int64_t N, int64_t M, Layout *L) {
   L->add(4 * N);        // 16 gflag
   L->add(sizeof(GravRec) * N);  // grec
   L->add(sizeof(SphRec) * N);   // srec
+  L->add(8 * 2 * N);            // pdiv
   // nodes
   L->add(sizeof(NodeTopo) * M);  // 17 topo
   L->add(4 * M);        // 18 nlevel
@@ -244,6 +245,7 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->gflag = AT(int32_t *);
   c->grec = AT(GravRec *);
   c->srec = AT(SphRec *);
+  c->pdiv = AT(double *);
   c->topo = AT(NodeTopo *);
   c->nlevel = AT(int32_t *);
   c->nparent = AT(int32_t *);
@@ -366,6 +368,7 @@ tsph_status tsph_compute_forces(void *ctx, tsph_state *s, void *stream) {
   if ((r = tsph_impl_sph(c, st)) != TSPH_OK) return r;
   MARK(4);
   if ((r = tsph_impl_finish(c, s, st)) != TSPH_OK) return r;
+  c->pdiv_n = s->n;
   MARK(5);
 #undef MARK
   return TSPH_OK;

@@ -409,7 +409,7 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
         if (is_gas && !oh.ok) nnoconv++;
       }
       // ---- softening length over all neighbours (all sinks) ----
-      double eps = 0.0, neps = 0.0, ups = 1.0, xi = 0.0;
+      double eps = 0.0, neps = 0.0, ups = 1.0, xi = 0.0, divve = 0.0;
       if (A.gravity) {
         if (A.soft_mode == TSPH_SOFT_CONSTANT) {
           eps = A.es[p];
@@ -418,16 +418,18 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
           neps = oh.s.n;
           ups = 1.0 + (oh.h / (3.0 * oh.s.n)) * oh.s.sdh;
           xi = (A.soft_mode == TSPH_SOFT_ADAPTIVE) ? -(oh.h / (3.0 * oh.s.n)) * oh.s.mdphi : 0.0;
+          divve = -oh.s.divv / (oh.s.n * ups);
         } else {
           double g0 = A.es[p];
           double guess = g0 > 0.0 ? g0 : (act ? cold_guess(A, p, false, A.eta_eps) : 0.0);
-          SolveOut oe = solve_length(A, gb, act, false, A.eta_eps, guess, a.x, a.y, a.z, vp, false, true,
+          SolveOut oe = solve_length(A, gb, act, false, A.eta_eps, guess, a.x, a.y, a.z, vp, true, true,
                                      s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0), nullptr);
           if (act && !oe.ok) nnoconv++;
           eps = oe.h;
           neps = oe.s.n;
           ups = 1.0 + (oe.h / (3.0 * oe.s.n)) * oe.s.sdh;
           xi = (A.soft_mode == TSPH_SOFT_ADAPTIVE) ? -(oe.h / (3.0 * oe.s.n)) * oe.s.mdphi : 0.0;
+          divve = -oe.s.divv / (oe.s.n * ups);
         }
       }
       if (act) {
@@ -468,6 +470,7 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
         S[kNeps * A.cap_n + p] = neps;
         S[kUps * A.cap_n + p] = ups;
         S[kXi * A.cap_n + p] = xi;
+        S[kDivvE * A.cap_n + p] = divve;
       }
     }
   }

@@ -25,6 +25,7 @@ struct FinishArgs {
   const double *hs, *es, *solve;
   double *dt_i;
   double *ax, *ay, *az, *pot, *dudt, *rho, *h, *eps;
+  double *pdiv;  // 2 x cap_n, caller order
   double eta_dt, alpha, beta;
   int32_t hydro;
 };
@@ -45,6 +46,8 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
   if (A.rho) A.rho[i] = g ? s.y : 0.0;
   if (A.h) A.h[i] = g ? A.hs[p] : 0.0;
   if (A.eps) A.eps[i] = A.es[p];
+  A.pdiv[i] = g ? A.solve[kDivv * A.cap_n + p] : 0.0;
+  A.pdiv[A.cap_n + i] = A.solve[kDivvE * A.cap_n + p];
   // time-step criteria (Sect. 4.2): acceleration, Courant, internal energy
   double dt = INFINITY;
   const double amag = sqrt(ax * ax + ay * ay + az * az);
@@ -62,12 +65,21 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
   A.dt_i[p] = dt;
 }
 
+// growth factor of a length over a drift of dt, clamped to [1/2, 2]
+__device__ __forceinline__ double predict_factor(double dt, double divv) {
+  double f = 1.0 + (dt / 3.0) * divv;
+  if (!(f >= 0.5)) f = 0.5;
+  else if (f > 2.0) f = 2.0;
+  return f;
+}
+
 __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, int64_t n_gas, double dt, int phase, double *x,
                                                     double *y, double *z, double *vx, double *vy, double *vz,
                                                     double *u, const double *__restrict__ ax,
                                                     const double *__restrict__ ay, const double *__restrict__ az,
                                                     const double *__restrict__ dudt, double *vpx, double *vpy,
-                                                    double *vpz, double *up) {
+                                                    double *vpz, double *up, double *h, double *eps,
+                                                    const double *__restrict__ pdiv, int64_t cap_n) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double hdt = 0.5 * dt;
@@ -85,6 +97,12 @@ __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, int64_t n_gas, do
     x[i] += dt * v0;
     y[i] += dt * v1;
     z[i] += dt * v2;
+    // lengths along the drift: h n^(1/3) = eta with dn/dt = -n div v gives
+    // dh/dt = (h/3) div v (Sect. 2.1); the next solve starts from them
+    if (pdiv) {
+      if (h && i < n_gas && h[i] > 0.0) h[i] *= predict_factor(dt, pdiv[i]);
+      if (eps && eps[i] > 0.0) eps[i] *= predict_factor(dt, pdiv[cap_n + i]);
+    }
     if (i < n_gas) {
       const double du = dudt[i];
       if (up) up[i] = u[i] + dt * du;
@@ -205,6 +223,7 @@ tsph_status tsph_impl_finish(Ctx *c, tsph_state *s, hipStream_t st) {
   A.rho = s->rho;
   A.h = s->h;
   A.eps = s->eps;
+  A.pdiv = c->pdiv;
   A.eta_dt = c->p.eta_dt;
   A.alpha = c->p.alpha;
   A.beta = c->p.beta;
@@ -220,7 +239,7 @@ tsph_status tsph_impl_finish(Ctx *c, tsph_state *s, hipStream_t st) {
 tsph_status tsph_impl_kick_drift(Ctx *c, tsph_state *s, double dt, int phase, hipStream_t st) {
   hipLaunchKernelGGL(k_kick_drift, dim3(blocks_for(s->n, 256, 1 << 20)), dim3(256), 0, st, s->n, s->n_gas, dt,
                      phase, s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->ax, s->ay, s->az, s->dudt, s->vpx,
-                     s->vpy, s->vpz, s->up);
+                     s->vpy, s->vpz, s->up, s->h, s->eps, c->pdiv_n == s->n ? c->pdiv : nullptr, c->cap_n);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

@@ -62,7 +62,7 @@ struct DevRoot {
 };
 
 // Per-particle solve outputs kept for export (sorted order).
-enum SolveField { kNh = 0, kOmega, kZeta, kDivv, kNeps, kUps, kXi, kMaxmu, kNumSolve };
+enum SolveField { kNh = 0, kOmega, kZeta, kDivv, kNeps, kUps, kXi, kMaxmu, kDivvE, kNumSolve };
 
 struct Ctx {
   int device;
@@ -89,6 +89,8 @@ struct Ctx {
   GravRec *grec;          // gravity source records
   SphRec *srec;           // SPH source records (gas entries)
   double *solve;          // kNumSolve x cap_n
+  double *pdiv;           // 2 x cap_n, caller order: div v with the h kernel (gas) and the eps kernel
+  int64_t pdiv_n;         // particle count the divergences belong to (0: none yet)
   double *acc;            // 6 x cap_n: ax, ay, az, pot, dudt, dt_i
   int32_t *cnt;           // 3 x cap_n: far nodes, near pairs, SPH pairs
 

@@ -22,7 +22,7 @@ FLAG_NODE_CAPACITY, FLAG_STACK_OVERFLOW, FLAG_LIST_OVERFLOW, FLAG_NOCONV, FLAG_N
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20)
 DBG_KEYS, DBG_PERM, DBG_NODES, DBG_NNODES, DBG_MOMENTS, DBG_GROUPS, DBG_NGROUPS, DBG_COUNTS, DBG_NBR, DBG_ROOT, \
     DBG_SOLVE, DBG_BATCHES, DBG_NBATCHES = range(13)
-SOLVE_FIELDS = ("nh", "omega", "zeta", "divv", "neps", "ups", "xi", "maxmu")
+SOLVE_FIELDS = ("nh", "omega", "zeta", "divv", "neps", "ups", "xi", "maxmu", "divv_eps")
 
 
 class TsphError(RuntimeError):

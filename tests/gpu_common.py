@@ -28,7 +28,8 @@ def run_gpu(ic, gp, lists=0, eps_const=None):
     flags, noconv = sim.flags()
     out = {k: sim.host(k) for k in ("ax", "ay", "az", "dudt", "rho", "pot", "h", "eps")}
     n = ic["n"]
-    solve = sim.export(tsph.DBG_SOLVE, np.float64, 8 * n).reshape(8, n)
+    nf = len(tsph.SOLVE_FIELDS)
+    solve = sim.export(tsph.DBG_SOLVE, np.float64, nf * n).reshape(nf, n)
     for i, name in enumerate(tsph.SOLVE_FIELDS):
         out[name] = solve[i]
     cnt = sim.export(tsph.DBG_COUNTS, np.int32, 3 * n).reshape(3, n)

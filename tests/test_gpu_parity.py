@@ -108,6 +108,8 @@ def _compare_full(orc_mod, ic, gp, lists=0, direct=False, tol_acc=1e-5):
         assert maxrel(g["eps"], o["eps"]) < 1e-9
         assert maxrel(g["ups"], o["ups"]) < 1e-8
         assert np.allclose(g["xi"], o["xi"], rtol=1e-8, atol=1e-14 * np.abs(o["xi"]).max())
+        assert np.allclose(g["divv_eps"], o["divv_eps"], rtol=1e-7,
+                           atol=1e-9 * max(np.abs(o["divv_eps"]).max(), 1e-300))
     e = relrms(acc(g), acc(o))
     _say(f"    acc relRMS vs oracle group walk = {e:.3e}")
     assert e < tol_acc
@@ -215,10 +217,14 @@ def test_neighbour_lists_bit_exact(orc_mod, case):
             assert np.array_equal(got, want), (kind, i)
 
 
-def test_kdk_step_matches_oracle(orc_mod):
-    _say("[kdk]")
-    ic = inputs.evrard(2048, seed=12, v_sigma=0.05)
-    gp = gpu_params()
+@pytest.mark.parametrize("case", ["evrard2048", "field2x1500"])
+def test_kdk_step_matches_oracle(orc_mod, case):
+    _say(f"[kdk] case={case}")
+    if case == "evrard2048":
+        ic, gp = inputs.evrard(2048, seed=12, v_sigma=0.05), gpu_params()
+    else:
+        ic = inputs.two_species_field(n_dm=1500, n_gas=1500, n_halo=4, seed=15)
+        gp = gpu_params(nnei=60)
     op = oracle_params(orc_mod, gp)
     sim = tsph.Simulation(ic, gp)
     sim.compute_forces()
@@ -228,16 +234,25 @@ def test_kdk_step_matches_oracle(orc_mod):
     assert dt == pytest.approx(dt_o, rel=1e-8)
     st = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ic.items()}
     pred = {"vx": st["vx"].copy(), "vy": st["vy"].copy(), "vz": st["vz"].copy(), "u": st["u"].copy()}
-    orc_mod.kick_drift(st, dt_o, 0, (o0["ax"], o0["ay"], o0["az"]), o0["dudt"], pred)
-    o1 = orc_mod.compute_forces(st, op, h_in=o0["h"], eps_in=o0["eps"], vel=(pred["vx"], pred["vy"], pred["vz"]),
-                                u=pred["u"])
+    lengths = {"h": o0["h"].copy(), "eps": o0["eps"].copy(), "divv": o0["divv"], "divv_eps": o0["divv_eps"]}
+    orc_mod.kick_drift(st, dt_o, 0, (o0["ax"], o0["ay"], o0["az"]), o0["dudt"], pred, lengths)
+    sim.kick_drift(dt_o, tsph.KD_FIRST)
+    # lengths carried along the drift (starting values of the next solve)
+    n_gas = ic["n_gas"]
+    assert maxrel(sim.host("h")[:n_gas], lengths["h"][:n_gas]) < 1e-11
+    assert maxrel(sim.host("eps"), lengths["eps"]) < 1e-11
+    o1 = orc_mod.compute_forces(st, op, h_in=lengths["h"], eps_in=lengths["eps"],
+                                vel=(pred["vx"], pred["vy"], pred["vz"]), u=pred["u"])
     orc_mod.kick_drift(st, dt_o, 1, (o1["ax"], o1["ay"], o1["az"]), o1["dudt"])
-    sim.step(dt_o)
-    flags, _ = sim.flags()
-    assert flags == 0
+    sim.compute_forces()
+    sim.kick_drift(dt_o, tsph.KD_SECOND)
+    flags, noconv = sim.flags()
+    assert flags == 0 and noconv == 0 and o1["n_noconv"] == 0
     for k in ("x", "y", "z", "vx", "vy", "vz", "u"):
         a, b = sim.host(k), st[k]
         assert np.max(np.abs(a - b)) < 1e-9 * max(np.abs(b).max(), 1e-3), k
+    assert maxrel(sim.host("h")[:n_gas], o1["h"][:n_gas]) < 1e-9
+    assert maxrel(sim.host("eps"), o1["eps"]) < 1e-9
     d_gpu = sim.diagnostics()
     d_orc = orc_mod.diagnostics(st, o1["pot"])
     assert np.allclose(d_gpu[:3], d_orc[:3], rtol=1e-8)

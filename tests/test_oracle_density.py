@@ -124,3 +124,49 @@ def test_equal_mass_grad_h_reduction(orc):
     out = orc.compute_forces(ic, orc.params(gravity=0))
     m = ic["m"][0]
     assert np.allclose(out["zeta"], m * (1.0 - out["omega"]), rtol=1e-9, atol=1e-15)
+
+
+def test_divergence_of_a_homologous_flow_is_exact(orc):
+    """With the grad-h normalisation, div v_i = -(1/(n_i Omega*_i)) sum_j
+    v_ij . grad_i W_ij reproduces div v = 3H exactly for v = H x, for any
+    particle arrangement: sum_j r W'(r) = -(3 n + h dn/dh), and Omega*_i =
+    1 + (h/3n) dn/dh cancels the rest.  Holds for the h kernel (gas) and the
+    eps kernel (all species)."""
+    ic = inputs.two_species_field(n_dm=1500, n_gas=1500, n_halo=4, seed=21)
+    H = 0.37
+    for k, v in (("x", "vx"), ("y", "vy"), ("z", "vz")):
+        ic[v] = H * ic[k]
+    p = orc.params(nnei=60, h_tol=1e-12)
+    out = orc.compute_forces(ic, p)
+    gas = np.arange(ic["n"]) < ic["n_gas"]
+    assert np.allclose(out["divv"][gas], 3 * H, rtol=1e-10, atol=0)
+    assert np.allclose(out["divv_eps"], 3 * H, rtol=1e-10, atol=0)
+
+
+def test_length_predictor_is_second_order(orc):
+    """Carrying h and eps along a drift with dh/dt = (h/3) div v (continuity
+    equation with h n^(1/3) = eta) leaves an error O(dt^2) against the
+    re-solved lengths, where the unpredicted lengths are off by O(dt)."""
+    ic = inputs.two_species_field(n_dm=1500, n_gas=1500, n_halo=4, seed=22)
+    rng = np.random.default_rng(5)
+    for v in ("vx", "vy", "vz"):
+        ic[v] = rng.normal(0.0, 0.3, ic["n"])
+    p = orc.params(nnei=60, h_tol=1e-12)
+    o0 = orc.compute_forces(ic, p)
+    n_gas = ic["n_gas"]
+    zero = np.zeros(ic["n"])
+    err = {}
+    for dt in (2e-4, 1e-4):
+        st = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ic.items()}
+        ln = {"h": o0["h"].copy(), "eps": o0["eps"].copy(), "divv": o0["divv"], "divv_eps": o0["divv_eps"]}
+        orc.kick_drift(st, dt, 0, (zero, zero, zero), zero, None, ln)
+        o1 = orc.compute_forces(st, p, h_in=o0["h"], eps_in=o0["eps"])
+        rel = lambda a, b: np.abs(a - b) / b
+        err[dt] = (np.median(rel(ln["h"][:n_gas], o1["h"][:n_gas])), np.median(rel(o0["h"][:n_gas], o1["h"][:n_gas])),
+                   np.median(rel(ln["eps"], o1["eps"])), np.median(rel(o0["eps"], o1["eps"])))
+    (ph2, oh2, pe2, oe2), (ph1, oh1, pe1, oe1) = err[2e-4], err[1e-4]
+    # predicted: far below the unpredicted error, and quartered when dt halves
+    assert ph2 < 0.05 * oh2 and pe2 < 0.05 * oe2
+    assert 3.0 < ph2 / ph1 < 5.0 and 3.0 < pe2 / pe1 < 5.0
+    # unpredicted: halved when dt halves
+    assert 1.7 < oh2 / oh1 < 2.3 and 1.7 < oe2 / oe1 < 2.3
