@@ -4,8 +4,10 @@
 Workload: the two-species clustered field -- 1,048,576 gas + 1,048,576 dark
 matter particles (DM:gas particle mass 5:1) in 64 Plummer halos inside a unit
 cube, theta = 0.5 with quadrupoles, 60 neighbours for both h and eps,
-adaptive softening with correction terms, FP64.  Inputs are seeded and
-synthetic (paper_0912_1786_amd.inputs) and resident in HBM before timing.
+adaptive softening with correction terms.  Inputs are seeded and synthetic
+(paper_0912_1786_amd.inputs) and resident in HBM before timing.  Two
+arithmetic forms are timed one after the other: the FP32-bulk form (gravity
+interactions in single precision, the headline) and the plain FP64 form.
 
 A step is one leapfrog step through the C ABI: kick-drift (half kick, drift,
 predicted v and u), tsph_compute_forces (root cube, keys, radix sort, tree,
@@ -30,6 +32,8 @@ METRIC = "particle-steps/s (tree gravity+SPH) at N=2M, 1 GPU; served p50/p99 ste
 
 # FP64 vector peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6
+# FP32 vector peak of MI355X (published, with packed FP32 issue)
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 # Floating-point operations per interaction in the gravity walk kernel,
@@ -107,6 +111,65 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
 
 
+def run_form(args, ic, form: str, torch, tsph) -> dict:
+    """Times args.steps KDK steps of one arithmetic form on resident inputs."""
+    n = ic["n"]
+    prec = tsph.FP32_BULK if form == "fp32_bulk" else tsph.FP64
+    prm = tsph.tsph_default_params(nnei=60, theta=0.5, leaf_size=args.leaf, group_size=args.group,
+                                   precision=prec)
+    sim = tsph.Simulation(ic, prm, want_pot=False)
+    log(f"[bench] {form}: N={n}; arena {tsph.tsph_bytes_required(n, prm) / 2**30:.2f} GiB")
+    # first evaluation (cold start of h and eps) and the global time-step
+    sim.compute_forces()
+    dt = sim.timestep()
+    flags, noconv = sim.flags()
+    log(f"[bench] {form}: first force pass done: dt={dt:.3e} flags={flags:#x} noconv={noconv}")
+    for w in range(args.warmup):
+        sim.step(dt)
+        torch.cuda.synchronize()
+        log(f"[bench] {form}: warmup step {w + 1}/{args.warmup} done")
+    tsph.tsph_timing(sim.ctx, True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k].record()
+        sim.step(dt)
+    evs[args.steps].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    phases, calls = tsph.tsph_phase_times(sim.ctx)
+    flags, noconv = sim.flags()
+    sim.close()
+    total_ms = sum(step_ms)
+    log(f"[bench] {form}: timed {args.steps} steps: {total_ms:.1f} ms (wall {wall * 1e3:.1f} ms); per step "
+        + ", ".join(f"{m:.1f}" for m in step_ms))
+    log(f"[bench] {form}: phase ms/step: " + ", ".join(f"{k}={v / calls:.2f}" for k, v in phases.items()))
+    # roofline of the dominant walk kernel
+    dom = max(PHASE_KERNEL, key=lambda k: phases[k])
+    kern, src = PHASE_KERNEL[dom]
+    dom_ms = phases[dom] / calls
+    roof = None
+    cpath = os.path.join(ROOT, "oracle", "algorithmic_counts.json")
+    if os.path.exists(cpath):
+        c = json.load(open(cpath))
+        if c["n"] == n and c["leaf_size"] == args.leaf:
+            flops = algorithmic_flops(c, dom, n, ic["n_gas"])
+            achieved = flops / (dom_ms / 1e3) / 1e12
+            f32 = form == "fp32_bulk" and dom == "gravity"
+            peak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
+            roof = {"kernel": kern, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                    "traffic": measured_traffic(f"{kern}/{form}", src), "algorithmic_flop_per_launch": flops,
+                    "avg_launch_ms": round(dom_ms, 3), "arithmetic": "fp32" if f32 else "fp64",
+                    "source_id": kernel_source_id(src)}
+    return {"value": round(n * args.steps / (total_ms / 1e3), 1), "ms_per_step": round(total_ms / args.steps, 3),
+            "median_step_ms": round(sorted(step_ms)[len(step_ms) // 2], 3),
+            "phase_ms_per_step": {k: round(v / calls, 3) for k, v in phases.items()},
+            "device_flags": flags, "roofline": roof}
+
+
 def cpu_baseline(nps: int, seed: int):
     """The FP64 oracle, as it stands, on the same recipe at a reduced size:
     one full force evaluation plus the two half kicks."""
@@ -139,6 +202,8 @@ def main():
     ap.add_argument("--group", type=int, default=64)
     ap.add_argument("--cpu-nps", type=int, default=1 << 18, help="per-species size of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["both", "fp32_bulk", "fp64"], default="both",
+                    help="arithmetic form(s) to time; with both, the FP32-bulk form is the headline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel used to calibrate the HBM byte counters")
     args = ap.parse_args()
@@ -157,68 +222,30 @@ def main():
     t0 = time.time()
     ic = inputs.two_species_field(n_dm=args.nps, n_gas=args.nps, n_halo=64, seed=args.seed)
     n = ic["n"]
-    prm = tsph.tsph_default_params(nnei=60, theta=0.5, leaf_size=args.leaf, group_size=args.group)
-    sim = tsph.Simulation(ic, prm, want_pot=False)
-    log(f"[bench] N={n} inputs ready in {time.time() - t0:.1f}s; arena "
-        f"{tsph.tsph_bytes_required(n, prm) / 2**30:.2f} GiB")
-    # first evaluation (cold start of h and eps) and the global time-step
-    sim.compute_forces()
-    dt = sim.timestep()
-    flags, noconv = sim.flags()
-    log(f"[bench] first force pass done: dt={dt:.3e} flags={flags:#x} noconv={noconv}")
-    for w in range(args.warmup):
-        sim.step(dt)
-        torch.cuda.synchronize()
-        log(f"[bench] warmup step {w + 1}/{args.warmup} done")
-    tsph.tsph_timing(sim.ctx, True)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t_wall0 = time.perf_counter()
-    for k in range(args.steps):
-        evs[k].record()
-        sim.step(dt)
-    evs[args.steps].record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall0
-    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
-    phases, calls = tsph.tsph_phase_times(sim.ctx)
-    flags, noconv = sim.flags()
-    total_ms = sum(step_ms)
-    log(f"[bench] timed {args.steps} steps: {total_ms:.1f} ms (wall {wall * 1e3:.1f} ms); per step "
-        + ", ".join(f"{m:.1f}" for m in step_ms))
-    log("[bench] phase ms/step: " + ", ".join(f"{k}={v / calls:.2f}" for k, v in phases.items()))
-    value = n * args.steps / (total_ms / 1e3)
-
-    # roofline of the dominant walk kernel
-    dom = max(PHASE_KERNEL, key=lambda k: phases[k])
-    kern, src = PHASE_KERNEL[dom]
-    dom_ms = phases[dom] / calls
-    roof = None
-    cpath = os.path.join(ROOT, "oracle", "algorithmic_counts.json")
-    if os.path.exists(cpath):
-        c = json.load(open(cpath))
-        if c["n"] == n and c["leaf_size"] == args.leaf:
-            flops = algorithmic_flops(c, dom, n, ic["n_gas"])
-            achieved = flops / (dom_ms / 1e3) / 1e12
-            roof = {"kernel": kern, "bound": "alu", "achieved": round(achieved, 3),
-                    "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                    "traffic": measured_traffic(kern, src), "algorithmic_flop_per_launch": flops,
-                    "avg_launch_ms": round(dom_ms, 3), "source_id": kernel_source_id(src)}
+    log(f"[bench] N={n} inputs ready in {time.time() - t0:.1f}s")
+    forms = {}
+    for form in (["fp64", "fp32_bulk"] if args.precision == "both" else [args.precision]):
+        forms[form] = run_form(args, ic, form, torch, tsph)
+    head = forms["fp32_bulk"] if "fp32_bulk" in forms else forms["fp64"]
+    headline = "fp32_bulk" if "fp32_bulk" in forms else "fp64"
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_ms / args.steps, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "metric": METRIC, "value": head["value"], "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if headline == "fp32_bulk" else "f64",
         "data": "synthetic",
         "config": {"workload": "two_species_field_2M", "n": n, "n_gas": ic["n_gas"], "n_dm": n - ic["n_gas"],
                    "halos": 64, "mass_ratio_dm_gas": 5, "theta": 0.5, "quadrupole": True, "nnei": 60,
                    "softening": "adaptive+corrections", "leaf_size": args.leaf, "group_size": args.group,
-                   "precision": "fp64", "seed": args.seed},
-        "phase_ms_per_step": {k: round(v / calls, 3) for k, v in phases.items()},
-        "median_step_ms": round(sorted(step_ms)[len(step_ms) // 2], 3),
-        "device_flags": flags,
-        "roofline": roof,
+                   "precision": headline, "seed": args.seed},
+        "phase_ms_per_step": head["phase_ms_per_step"],
+        "median_step_ms": head["median_step_ms"],
+        "device_flags": head["device_flags"],
+        "roofline": head["roofline"],
     }
-    sim.close()
+    for form, r in forms.items():
+        if form != headline:
+            out[f"{form}_form"] = r
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_nps, args.seed)

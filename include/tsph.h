@@ -65,7 +65,13 @@ typedef enum {
 enum { TSPH_SOFT_ADAPTIVE = 0,        /* eps solved, correction terms on (Sect. 2.1) */
        TSPH_SOFT_CONSTANT = 1,        /* eps given by the caller, no corrections     */
        TSPH_SOFT_ADAPTIVE_NOCORR = 2  /* eps solved, correction terms off            */ };
-enum { TSPH_FP64 = 0 };
+/* Arithmetic of the walks (Sect. 2.2 gravity).  TSPH_FP32_BULK evaluates the
+ * gravity interactions (far nodes and particle pairs) in single precision on
+ * coordinates taken relative to the walk batch's centre, with single-
+ * precision sums per staged tile of 64 interactions carried into double-
+ * precision totals; positions, velocities, node centres of mass, the walk's
+ * acceptance tests, the integrator and the diagnostics stay FP64. */
+enum { TSPH_FP64 = 0, TSPH_FP32_BULK = 1 };
 enum { TSPH_KD_FIRST = 0, TSPH_KD_SECOND = 1 };
 
 /* device flag bits */
@@ -92,10 +98,13 @@ typedef struct {
   double kappa;        /* candidate search radius 2 h_guess (1 + kappa)        */
   int32_t leaf_size;   /* particles per tree leaf (1..64)                      */
   int32_t group_size;  /* sinks per walk group (leaf_size..64)                 */
-  int32_t precision;   /* TSPH_FP64                                             */
+  int32_t precision;   /* TSPH_FP64 or TSPH_FP32_BULK                           */
   int32_t gravity;     /* 1: self-gravity on                                   */
   int32_t hydro;       /* 1: SPH on                                            */
-  int32_t reserved;
+  int32_t split_leaves; /* a walk batch evaluates at most this many opened leaves
+                          * of its gravity near field itself; the rest go, in
+                          * work items of 64 to 127 leaves, to other wavefronts
+                          * and are summed back in a fixed order (0: never)   */
   double eta_dt;       /* time-step coefficient of the Sect. 4.2 criteria      */
 } tsph_params;
 
@@ -128,7 +137,7 @@ tsph_status tsph_destroy(void *ctx);
 tsph_status tsph_set_params(void *ctx, const tsph_params *p);
 /* Fill p with the defaults: G=1, theta=0.5, quadrupoles, adaptive softening,
  * 50 neighbours, gamma=5/3, alpha=1, beta=2, av_eps2=0.01, TC92 on,
- * h_tol=1e-10, kappa=0.1, leaf 16, group 64, eta_dt=0.1. */
+ * h_tol=1e-10, kappa=0.1, leaf 16, group 64, eta_dt=0.1, split_leaves 512. */
 void tsph_default_params(tsph_params *p);
 /* Device bytes a context of this capacity reserves (host-only, no GPU). */
 tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t *bytes);

@@ -46,10 +46,11 @@ const char *param_error(const tsph_params *p) {
   if (!(p->h_tol > 0.0) || p->h_maxit < 1) return "h_tol must be > 0 and h_maxit >= 1";
   if (!(p->kappa >= 0.0)) return "kappa must be >= 0";
   if (p->soft_mode < 0 || p->soft_mode > 2) return "unknown soft_mode";
-  if (p->precision != TSPH_FP64) return "unknown precision";
+  if (p->precision != TSPH_FP64 && p->precision != TSPH_FP32_BULK) return "unknown precision";
   if (!(p->alpha >= 0.0) || !(p->beta >= 0.0) || !(p->av_eps2 > 0.0)) return "bad viscosity parameters";
   if (!(p->G > 0.0)) return "G must be > 0";
   if (!(p->eta_dt > 0.0)) return "eta_dt must be > 0";
+  if (p->split_leaves < 0) return "split_leaves must be >= 0";
   return nullptr;
 }
 
@@ -93,6 +94,11 @@ size_t layout_bytes(int64_t N, int64_t M, Layout *L) {
   L->add(4 * M);        // 26 groups
   L->add(8 * M);        // batches
   L->add(4 * 16);       // nbatches
+  const int64_t icap = split_item_cap(M);
+  L->add(4 * (size_t)icap * kSplitItemLeaves);  // split_leaf
+  L->add(sizeof(SplitItem) * (size_t)icap);     // split_item
+  L->add(32 * 64 * (size_t)icap);               // split_part
+  L->add(4 * M);                                // split_head
   // small
   L->add(sizeof(DevRoot));           // 27 root
   L->add(8 * 6 * 512);               // 28 bbox_part
@@ -183,6 +189,7 @@ void tsph_default_params(tsph_params *p) {
   p->gravity = 1;
   p->hydro = 1;
   p->eta_dt = 0.1;
+  p->split_leaves = 512;
 }
 
 tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t *bytes) {
@@ -258,6 +265,11 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->groups = AT(int32_t *);
   c->batches = AT(int2 *);
   c->nbatches = AT(int32_t *);
+  c->split_leaf = AT(int32_t *);
+  c->split_item = AT(SplitItem *);
+  c->split_part = AT(double4 *);
+  c->split_head = AT(int32_t *);
+  c->split_cap = split_item_cap(c->cap_nodes);
   c->root = AT(DevRoot *);
   c->bbox_part = AT(double *);
   c->lvl = AT(int32_t *);

@@ -20,6 +20,8 @@
 // (r_hat = (x_i - x_j)/r, xi carrying the neighbour masses).
 #include <stdio.h>
 
+#include <type_traits>
+
 #include "tsph_internal.h"
 
 namespace tsph {
@@ -28,6 +30,7 @@ constexpr int kGStackCap = 1024;
 constexpr int kGListCap = 128;
 constexpr int kGCellFlush = 64;
 constexpr int kGLeafFlush = 32;
+constexpr int kGSplitFlush = 64;  // leaves per handed-off work item (64 to 127)
 constexpr double kInvPiG = 0.31830988618379067154;
 
 struct GravArgs {
@@ -51,6 +54,13 @@ struct GravArgs {
   int32_t dbg_max;
   double G;
   int32_t quadrupole, corr, want_pot;
+  // near-field hand-off (0 split_leaves: none)
+  int32_t split_leaves;
+  int64_t split_cap;
+  int32_t *split_leaf;
+  SplitItem *split_item;
+  double4 *split_part;
+  int32_t *split_head;
 };
 
 struct Sink {
@@ -191,21 +201,241 @@ __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const Grav
   }
 }
 
+// ---- FP32-bulk form: interactions in single precision on coordinates
+// relative to the batch centre, partial sums per staged tile in single
+// precision carried into double-precision totals after every tile.
+
+// node record staged for the FP32 form (48 B): COM relative to the batch
+// centre, mass, traceless quadrupole
+struct NodeF32 {
+  float cx, cy, cz, m;
+  float qxx, qyy, qzz, qxy;
+  float qxz, qyz, pad0, pad1;
+};
+
+// particle record staged for the FP32 form (32 B)
+struct RecF32 {
+  float x, y, z, m;
+  float eps, ieps, xiu, pad;
+};
+
+// LDS staging tiles of the two forms
+union Tile64 {
+  NodeFar far[kWave];
+  GravRec rec[kWave];
+};
+union Tile32 {
+  NodeF32 far32[kWave];
+  RecF32 rec32[kWave];
+};
+
+struct Sink32 {
+  float x, y, z, m, im, eps, ieps, xiu;  // position relative to the batch centre
+  float tax, tay, taz, tpot;             // sums over the current tile
+  double ax, ay, az, pot;                // totals (in units of G)
+  int p;
+  bool act;
+};
+
+__device__ __forceinline__ void carry_tile(Sink32 &s) {
+  s.ax += (double)s.tax;
+  s.ay += (double)s.tay;
+  s.az += (double)s.taz;
+  s.pot += (double)s.tpot;
+  s.tax = s.tay = s.taz = s.tpot = 0.0f;
+}
+
 template <int M>
+__device__ __forceinline__ void far_field32(Sink32 &s, const NodeF32 &f) {
+  const float dx = s.x - f.cx, dy = s.y - f.cy, dz = s.z - f.cz;
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  const float ir = rsqrtf(r2);
+  const float ir2 = ir * ir;
+  const float ir3 = ir * ir2;
+  float fm = f.m * ir3;
+  float ph = f.m * ir;
+  float ex = 0.0f, ey = 0.0f, ez = 0.0f;
+  if (M & kQuad) {
+    const float qx = f.qxx * dx + f.qxy * dy + f.qxz * dz;
+    const float qy = f.qxy * dx + f.qyy * dy + f.qyz * dz;
+    const float qz = f.qxz * dx + f.qyz * dy + f.qzz * dz;
+    const float rqr = dx * qx + dy * qy + dz * qz;
+    const float ir5 = ir3 * ir2;
+    const float ir7 = ir5 * ir2;
+    fm += 2.5f * rqr * ir7;
+    ex = qx * ir5;
+    ey = qy * ir5;
+    ez = qz * ir5;
+    ph += 0.5f * rqr * ir5;
+  }
+  s.tax += ex - fm * dx;
+  s.tay += ey - fm * dy;
+  s.taz += ez - fm * dz;
+  if (M & kPot) s.tpot -= ph;
+}
+
+template <int M>
+__device__ __forceinline__ void newton_pair32(Sink32 &s, const RecF32 &b) {
+  const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  const float ir = rsqrtf(r2);
+  const float mr = b.m * ir;
+  const float f = mr * ir * ir;
+  s.tax -= f * dx;
+  s.tay -= f * dy;
+  s.taz -= f * dz;
+  if (M & kPot) s.tpot -= mr;
+}
+
+__device__ __forceinline__ bool softened32(const Sink32 &s, const RecF32 &b) {
+  const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  const float em = fmaxf(s.eps, b.eps);
+  return r2 < 4.0f * em * em;
+}
+
+template <int M>
+__device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b) {
+  const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  const float em = fmaxf(s.eps, b.eps);
+  if (r2 >= 4.0f * em * em) {
+    newton_pair32<M>(s, b);
+    return;
+  }
+  if (r2 > 0.0f) {
+    const float ir = rsqrtf(r2);
+    const float r = r2 * ir;
+    const float qi = r * s.ieps, qj = r * b.ieps;
+    float F = 0.5f * b.m * (soft_fr_q(qi, s.ieps, ir) + soft_fr_q(qj, b.ieps, ir));
+    if (M & kCorr) {
+      const float ii2 = s.ieps * s.ieps, ij2 = b.ieps * b.ieps;
+      const float Wi = m4_dw(qi) * (ii2 * ii2) * (float)kInvPiG;
+      const float Wj = m4_dw(qj) * (ij2 * ij2) * (float)kInvPiG;
+      F += 0.5f * (s.xiu * Wi + (b.m * s.im) * b.xiu * Wj);
+    }
+    const float fr = F * ir;
+    s.tax -= fr * dx;
+    s.tay -= fr * dy;
+    s.taz -= fr * dz;
+    if (M & kPot) s.tpot += b.m * 0.5f * (soft_ph_q(qi, s.ieps, ir) + soft_ph_q(qj, b.ieps, ir));
+  } else if (M & kPot) {
+    s.tpot += b.m * 0.5f * (-1.4f * s.ieps - 1.4f * b.ieps);
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void near_tile32(Sink32 &s, const RecF32 *rec, const int *tq, int nt) {
+  int j = 0;
+  for (; j + 2 <= nt; j += 2) {
+    const RecF32 b0 = rec[j], b1 = rec[j + 1];
+    const int q0 = tq[j], q1 = tq[j + 1];
+    const bool slow = q0 == s.p || q1 == s.p || softened32(s, b0) || softened32(s, b1);
+    if (!__any(slow)) {
+      newton_pair32<M>(s, b0);
+      newton_pair32<M>(s, b1);
+    } else {
+      if (q0 != s.p) near_pair32<M>(s, b0);
+      if (q1 != s.p) near_pair32<M>(s, b1);
+    }
+  }
+  if (j < nt && tq[j] != s.p) near_pair32<M>(s, rec[j]);
+}
+
+// LDS staging tiles of the two forms
+template <bool F32>
+using TileT = typename std::conditional<F32, Tile32, Tile64>::type;
+template <bool F32>
+using SinkT = typename std::conditional<F32, Sink32, Sink>::type;
+
+// Near field of the opened leaves leaf[0, nleaf) on sink s: their particles
+// are packed 64 to a tile while the leaves are scanned in order (each lane
+// noting the particle of its slot), loaded with one vector load per lane and
+// evaluated by every lane.  Returns the number of particles visited.
+template <int M, bool F32>
+__device__ __forceinline__ int near_leaves(const GravArgs &A, SinkT<F32> &s, const int *leaf, int nleaf,
+                                           TileT<F32> &T, int *tq, double cx, double cy, double cz) {
+  const int ln = lane();
+  int fill = 0, rq = -1, visited = 0;
+  auto flush = [&](int nt) {
+    if (ln < nt) {
+      const GravRec r = A.grec[rq];
+      if constexpr (F32) {
+        RecF32 h;
+        h.x = (float)(r.x - cx); h.y = (float)(r.y - cy); h.z = (float)(r.z - cz);
+        h.m = (float)r.m; h.eps = (float)r.eps; h.ieps = (float)r.ieps; h.xiu = (float)r.xiu;
+        h.pad = 0.0f;
+        T.rec32[ln] = h;
+      } else {
+        T.rec[ln] = r;
+      }
+      tq[ln] = rq;
+    }
+    __syncthreads();
+    if constexpr (F32) {
+      near_tile32<M>(s, T.rec32, tq, nt);
+      carry_tile(s);
+    } else {
+      near_tile<M>(A, s, T.rec, tq, nt);
+    }
+    __syncthreads();
+  };
+  for (int c1 = 0; c1 < nleaf; c1 += kWave) {
+    const int nc = min(kWave, nleaf - c1);
+    const NodeTopo my = ln < nc ? A.topo[leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
+    for (int j = 0; j < nc; j++) {
+      const int first = __builtin_amdgcn_readlane(my.first, j);
+      const int count = __builtin_amdgcn_readlane(my.count, j);
+      visited += count;
+      for (int off = 0; off < count;) {
+        const int tk = min(count - off, kWave - fill);
+        if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
+        fill += tk;
+        off += tk;
+        if (fill == kWave) {
+          flush(kWave);
+          fill = 0;
+        }
+      }
+    }
+  }
+  if (fill > 0) flush(fill);
+  return visited;
+}
+
+// Loads sink chunk c0 of a batch (coordinates relative to the batch centre
+// in the FP32 form).
+template <bool F32>
+__device__ __forceinline__ void load_sink(const GravArgs &A, SinkT<F32> &s, const NodeTopo &gnd, int c0, double cx,
+                                          double cy, double cz, bool dbg) {
+  const int ln = lane();
+  s.act = c0 + ln < gnd.count;
+  s.p = gnd.first + c0 + (s.act ? ln : 0);
+  const GravRec r = A.grec[s.p];
+  if constexpr (F32) {
+    s.x = (float)(r.x - cx); s.y = (float)(r.y - cy); s.z = (float)(r.z - cz);
+    s.m = (float)r.m; s.im = (float)(1.0 / r.m);
+    s.eps = (float)r.eps; s.ieps = (float)r.ieps; s.xiu = (float)r.xiu;
+    s.tax = s.tay = s.taz = s.tpot = 0.0f;
+  } else {
+    s.x = r.x; s.y = r.y; s.z = r.z; s.m = r.m; s.im = 1.0 / r.m;
+    s.eps = r.eps; s.ieps = r.ieps; s.xiu = r.xiu;
+    s.dbg = (dbg && A.dbg && s.act) ? A.dbg + ((int64_t)2 * A.cap_n + A.perm[s.p]) * A.dbg_max : nullptr;
+    s.ndbg = 0;
+  }
+  s.ax = s.ay = s.az = s.pot = 0.0;
+}
+
+template <int M, bool F32>
 __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
   __shared__ int s_stack[kGStackCap];
   __shared__ int s_cell[kGListCap];
   __shared__ int s_leaf[kGListCap];
   // staging tile: 64 node records (far flush) or 64 particle records (near
   // flush), filled with one vector load per lane and read back as broadcasts
-  __shared__ union {
-    NodeFar far[kWave];
-    GravRec rec[kWave];
-  } s_t;
+  __shared__ TileT<F32> s_t;
   __shared__ int s_tq[kWave];
   __shared__ int s_g;
-  NodeFar *const s_tile = s_t.far;
-  GravRec *const s_rec = s_t.rec;
   const int ln = lane();
   const int ng = *A.nbatches;
   for (;;) {
@@ -218,18 +448,13 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
     const NodeTopo gnd{bt.first, bt.count, -1, 0};
     const NodeBox gb = bt.box;
     const double gemax = gb.epsmax;
+    // batch centre: origin of the single-precision coordinates
+    const double cx = 0.5 * (gb.lox + gb.hix), cy = 0.5 * (gb.loy + gb.hiy), cz = 0.5 * (gb.loz + gb.hiz);
+    int prev_item = -1;  // last handed-off item of this batch
     for (int c0 = 0; c0 < gnd.count; c0 += kWave) {
-      Sink s;
-      s.act = c0 + ln < gnd.count;
-      s.p = gnd.first + c0 + (s.act ? ln : 0);
-      {
-        const GravRec r = A.grec[s.p];
-        s.x = r.x; s.y = r.y; s.z = r.z; s.m = r.m; s.im = 1.0 / r.m;
-        s.eps = r.eps; s.ieps = r.ieps; s.xiu = r.xiu;
-      }
-      s.ax = s.ay = s.az = s.pot = 0.0;
-      s.dbg = (A.dbg && s.act) ? A.dbg + ((int64_t)2 * A.cap_n + A.perm[s.p]) * A.dbg_max : nullptr;
-      s.ndbg = 0;
+      SinkT<F32> s;
+      load_sink<F32>(A, s, gnd, c0, cx, cy, cz, true);
+      int near_done = 0;  // opened leaves evaluated by this wave
       int nfar = 0, npair = 0;
       int sp = 1, ncell = 0, nleaf = 0;
       bool overflow = false;
@@ -290,50 +515,65 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
           // accepted nodes, 64 per tile
           for (int t0 = 0; t0 < ncell; t0 += kWave) {
             const int nt = min(kWave, ncell - t0);
-            if (ln < nt) s_tile[ln] = A.nfar[s_cell[t0 + ln]];
+            if (ln < nt) {
+              const NodeFar f = A.nfar[s_cell[t0 + ln]];
+              if constexpr (F32) {
+                NodeF32 h;
+                h.cx = (float)(f.cx - cx); h.cy = (float)(f.cy - cy); h.cz = (float)(f.cz - cz);
+                h.m = (float)f.m;
+                h.qxx = (float)f.qxx; h.qyy = (float)f.qyy; h.qzz = (float)f.qzz;
+                h.qxy = (float)f.qxy; h.qxz = (float)f.qxz; h.qyz = (float)f.qyz;
+                h.pad0 = h.pad1 = 0.0f;
+                s_t.far32[ln] = h;
+              } else {
+                s_t.far[ln] = f;
+              }
+            }
             __syncthreads();
-            for (int j = 0; j < nt; j++) far_field<M>(A, s, s_tile[j]);
+            if constexpr (F32) {
+              for (int j = 0; j < nt; j++) far_field32<M>(s, s_t.far32[j]);
+              carry_tile(s);
+            } else {
+              for (int j = 0; j < nt; j++) far_field<M>(A, s, s_t.far[j]);
+            }
             __syncthreads();
           }
           nfar += ncell;
           ncell = 0;
         }
-        if (nleaf >= kGLeafFlush || (last && nleaf > 0)) {
-          // particles of the opened leaves, packed 64 per tile: the leaves are
-          // scanned in order, each lane noting the particle of its slot, and a
-          // full tile is loaded with one vector load per lane
-          int fill = 0, rq = -1;
-          for (int c1 = 0; c1 < nleaf; c1 += kWave) {
-            const int nc = min(kWave, nleaf - c1);
-            const NodeTopo my = ln < nc ? A.topo[s_leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
-            for (int j = 0; j < nc; j++) {
-              const int first = __builtin_amdgcn_readlane(my.first, j);
-              const int count = __builtin_amdgcn_readlane(my.count, j);
-              npair += count;
-              for (int off = 0; off < count;) {
-                const int tk = min(count - off, kWave - fill);
-                if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
-                fill += tk;
-                off += tk;
-                if (fill == kWave) {
-                  s_rec[ln] = A.grec[rq];
-                  s_tq[ln] = rq;
-                  __syncthreads();
-                  near_tile<M>(A, s, s_rec, s_tq, kWave);
-                  __syncthreads();
-                  fill = 0;
-                }
+        const bool split = A.split_leaves > 0 && near_done >= A.split_leaves;
+        if (nleaf >= (split ? kGSplitFlush : kGLeafFlush) || (last && nleaf > 0)) {
+          bool handed = false;
+          if (split) {
+            // hand the leaves to another wavefront: reserve leaf space, then
+            // an item; items of a batch are chained in creation order
+            int base = 0, it = 0;
+            if (ln == 0) {
+              base = atomicAdd(&A.work[3], nleaf);
+              it = base + nleaf <= A.split_cap * kSplitItemLeaves ? atomicAdd(&A.work[4], 1) : INT32_MAX;
+            }
+            base = __shfl(base, 0, kWave);
+            it = __shfl(it, 0, kWave);
+            if (it < A.split_cap) {
+              int visited = 0;
+              for (int a = ln; a < nleaf; a += kWave) {
+                A.split_leaf[base + a] = s_leaf[a];
+                visited += A.topo[s_leaf[a]].count;
               }
+              const int incl = wave_incl_scan(visited);
+              npair += __shfl(incl, kWave - 1, kWave);
+              if (ln == 0) {
+                A.split_item[it] = SplitItem{g, c0, base, nleaf, -1, 0, 0, 0};
+                if (prev_item >= 0) A.split_item[prev_item].next = it;
+                else A.split_head[g] = it;
+              }
+              prev_item = it;
+              handed = true;
             }
           }
-          if (fill > 0) {
-            if (ln < fill) {
-              s_rec[ln] = A.grec[rq];
-              s_tq[ln] = rq;
-            }
-            __syncthreads();
-            near_tile<M>(A, s, s_rec, s_tq, fill);
-            __syncthreads();
+          if (!handed) {
+            npair += near_leaves<M, F32>(A, s, s_leaf, nleaf, s_t, s_tq, cx, cy, cz);
+            near_done += nleaf;
           }
           nleaf = 0;
         }
@@ -341,17 +581,89 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
         if (last) break;
       }
       if (overflow) atomicOr(A.flags, TSPH_FLAG_STACK_OVERFLOW);
-      if (s.dbg && s.ndbg > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
+      if constexpr (!F32) {
+        if (s.dbg && s.ndbg > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
+      }
       if (s.act) {
-        if (M & kPot) s.pot += A.G * s.m * (-1.4 * s.ieps);  // self term phi(0, eps_i)
-        A.acc[0 * A.cap_n + s.p] = s.ax;
-        A.acc[1 * A.cap_n + s.p] = s.ay;
-        A.acc[2 * A.cap_n + s.p] = s.az;
-        A.acc[3 * A.cap_n + s.p] = s.pot;
+        double ax = s.ax, ay = s.ay, az = s.az, pot = s.pot;
+        if constexpr (F32) {
+          ax *= A.G;
+          ay *= A.G;
+          az *= A.G;
+          pot *= A.G;
+        }
+        if (M & kPot) pot += A.G * (double)s.m * (-1.4 * (double)s.ieps);  // self term phi(0, eps_i)
+        A.acc[0 * A.cap_n + s.p] = ax;
+        A.acc[1 * A.cap_n + s.p] = ay;
+        A.acc[2 * A.cap_n + s.p] = az;
+        A.acc[3 * A.cap_n + s.p] = pot;
         const int ci = A.perm[s.p];
         A.cnt[0 * A.cap_n + ci] = nfar;
         A.cnt[1 * A.cap_n + ci] = npair - 1;
       }
+    }
+  }
+}
+
+// Handed-off near fields: one work item (a chunk of a batch's opened leaves)
+// per wavefront; its partial acceleration and potential of the batch's sinks
+// go to split_part, to be added in item order by k_split_reduce.
+template <int M, bool F32>
+__global__ __launch_bounds__(64) void k_gravity_split(GravArgs A) {
+  __shared__ int s_leaf[kSplitItemLeaves];
+  __shared__ TileT<F32> s_t;
+  __shared__ int s_tq[kWave];
+  __shared__ int s_g;
+  const int ln = lane();
+  const int nitems = min((int64_t)A.work[4], A.split_cap);
+  for (;;) {
+    if (ln == 0) s_g = atomicAdd(&A.work[5], 1);
+    __syncthreads();
+    const int it = s_g;
+    __syncthreads();
+    if (it >= nitems) break;
+    const SplitItem I = A.split_item[it];
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, I.g);
+    const NodeTopo gnd{bt.first, bt.count, -1, 0};
+    const NodeBox gb = bt.box;
+    const double cx = 0.5 * (gb.lox + gb.hix), cy = 0.5 * (gb.loy + gb.hiy), cz = 0.5 * (gb.loz + gb.hiz);
+    SinkT<F32> s;
+    load_sink<F32>(A, s, gnd, I.c0, cx, cy, cz, false);
+    for (int a = ln; a < I.count; a += kWave) s_leaf[a] = A.split_leaf[I.start + a];
+    __syncthreads();
+    near_leaves<M, F32>(A, s, s_leaf, I.count, s_t, s_tq, cx, cy, cz);
+    double4 part = make_double4(s.ax, s.ay, s.az, s.pot);
+    if constexpr (F32) {
+      part.x *= A.G;
+      part.y *= A.G;
+      part.z *= A.G;
+      part.w *= A.G;
+    }
+    A.split_part[(int64_t)it * kWave + ln] = part;
+  }
+}
+
+// Adds the handed-off partial sums to each batch's sinks, walking the batch's
+// item chain in creation order (a fixed summation order).
+__global__ __launch_bounds__(64) void k_split_reduce(GravArgs A) {
+  const int ln = lane();
+  const int ng = *A.nbatches;
+  for (int g = blockIdx.x; g < ng; g += gridDim.x) {
+    int it = A.split_head[g];
+    if (it < 0) continue;
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
+    int guard = 0;
+    while (it >= 0 && it < A.split_cap && ++guard <= A.split_cap) {
+      const SplitItem I = A.split_item[it];
+      if (I.c0 + ln < bt.count) {
+        const int64_t p = bt.first + I.c0 + ln;
+        const double4 v = A.split_part[(int64_t)it * kWave + ln];
+        A.acc[0 * A.cap_n + p] += v.x;
+        A.acc[1 * A.cap_n + p] += v.y;
+        A.acc[2 * A.cap_n + p] += v.z;
+        A.acc[3 * A.cap_n + p] += v.w;
+      }
+      it = I.next;
     }
   }
 }
@@ -399,19 +711,37 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
   A.quadrupole = c->p.quadrupole;
   A.corr = c->p.soft_mode == TSPH_SOFT_ADAPTIVE ? 1 : 0;
   A.want_pot = want_pot ? 1 : 0;
+  A.split_leaves = c->dbg_nbr ? 0 : c->p.split_leaves;  // debug lists are written by the batch's own wave
+  A.split_cap = c->split_cap;
+  A.split_leaf = c->split_leaf;
+  A.split_item = c->split_item;
+  A.split_part = c->split_part;
+  A.split_head = c->split_head;
   const int mode = (A.quadrupole ? kQuad : 0) | (A.corr ? kCorr : 0) | (A.want_pot ? kPot : 0);
-  void (*kern)(GravArgs) = nullptr;
-  switch (mode) {
-    case 0: kern = k_gravity<0>; break;
-    case 1: kern = k_gravity<1>; break;
-    case 2: kern = k_gravity<2>; break;
-    case 3: kern = k_gravity<3>; break;
-    case 4: kern = k_gravity<4>; break;
-    case 5: kern = k_gravity<5>; break;
-    case 6: kern = k_gravity<6>; break;
-    default: kern = k_gravity<7>; break;
-  }
+  void (*const k64[8])(GravArgs) = {k_gravity<0, false>, k_gravity<1, false>, k_gravity<2, false>,
+                                    k_gravity<3, false>, k_gravity<4, false>, k_gravity<5, false>,
+                                    k_gravity<6, false>, k_gravity<7, false>};
+  void (*const k32[8])(GravArgs) = {k_gravity<0, true>, k_gravity<1, true>, k_gravity<2, true>,
+                                    k_gravity<3, true>, k_gravity<4, true>, k_gravity<5, true>,
+                                    k_gravity<6, true>, k_gravity<7, true>};
+  void (*const s64[8])(GravArgs) = {k_gravity_split<0, false>, k_gravity_split<1, false>,
+                                    k_gravity_split<2, false>, k_gravity_split<3, false>,
+                                    k_gravity_split<4, false>, k_gravity_split<5, false>,
+                                    k_gravity_split<6, false>, k_gravity_split<7, false>};
+  void (*const s32[8])(GravArgs) = {k_gravity_split<0, true>, k_gravity_split<1, true>,
+                                    k_gravity_split<2, true>, k_gravity_split<3, true>,
+                                    k_gravity_split<4, true>, k_gravity_split<5, true>,
+                                    k_gravity_split<6, true>, k_gravity_split<7, true>};
+  const bool f32 = c->p.precision == TSPH_FP32_BULK;
+  void (*kern)(GravArgs) = f32 ? k32[mode] : k64[mode];
+  void (*skern)(GravArgs) = f32 ? s32[mode] : s64[mode];
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(c->cap_nodes, 256, 4096)), dim3(256), 0, st, c->cap_nodes,
+                     c->split_head, -1);
   hipLaunchKernelGGL(kern, dim3(persistent_blocks(c, (const void *)kern)), dim3(64), 0, st, A);
+  if (A.split_leaves > 0) {
+    hipLaunchKernelGGL(skern, dim3(persistent_blocks(c, (const void *)skern)), dim3(64), 0, st, A);
+    hipLaunchKernelGGL(k_split_reduce, dim3(4096), dim3(64), 0, st, A);
+  }
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

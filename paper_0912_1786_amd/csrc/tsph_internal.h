@@ -62,6 +62,22 @@ struct DevRoot {
 };
 
 // Per-particle solve outputs kept for export (sorted order).
+// A piece of a walk batch's near field evaluated by another wavefront: the
+// leaves split_leaf[start, start + count) acting on sink chunk c0 of batch g;
+// next chains the items of one batch in creation order.
+struct SplitItem {
+  int32_t g, c0, start, count, next, pad0, pad1, pad2;
+};
+// capacity in split items of a context with cap_nodes nodes; each item
+// holds at most kSplitItemLeaves leaves.  Past it, batches evaluate their
+// whole near field themselves (correct, but the summation order then
+// depends on which batches got items first).
+constexpr int kSplitItemLeaves = 128;
+inline int64_t split_item_cap(int64_t cap_nodes) {
+  const int64_t v = cap_nodes / 4;
+  return v < 4096 ? 4096 : (v > 262144 ? 262144 : v);
+}
+
 enum SolveField { kNh = 0, kOmega, kZeta, kDivv, kNeps, kUps, kXi, kMaxmu, kDivvE, kNumSolve };
 
 struct Ctx {
@@ -114,7 +130,12 @@ struct Ctx {
   int32_t *ngroups;
   uint32_t *hist;         // radix histograms kSortBins x sort blocks
   int32_t *scan_part;     // scan block sums
-  int32_t *work;          // work-queue counters (16)
+  int32_t *work;          // work-queue counters (16): 0-2 walks, 3 split leaves, 4 split items, 5 split walk
+  int32_t *split_leaf;    // split_cap x kSplitItemLeaves leaves handed from batches' near fields
+  SplitItem *split_item;  // split_cap work items over split_leaf
+  double4 *split_part;    // split_cap x 64 partial (ax, ay, az, pot) of the items
+  int64_t split_cap;
+  int32_t *split_head;    // cap_nodes: first item of each batch (-1: none), items chained in order
   uint32_t *flags;        // device flag word
   int32_t *noconv;        // unconverged solves
   double *red;            // reduction scratch
@@ -259,36 +280,41 @@ __device__ __forceinline__ double soft_pe(double r, double e) {
   return (1.6 + q2 * (-4.0 + q * (4.0 + q * (-1.5 + 0.2 * q)))) / (e * e);
 }
 
-// The same softened kernels in division-free form for the inner loops:
-// q = r / e with ie = 1/e and ir = 1/r given (1/(15 q^2 e^2) = ir^2 / 15).
-__device__ __forceinline__ double soft_fr_q(double q, double ie, double ir) {
-  if (q >= 2.0) return ir * ir;
-  const double q2 = q * q, ie2 = ie * ie;
-  if (q < 1.0) return ie2 * q * ((4.0 / 3.0) + q2 * (-1.2 + 0.5 * q));
-  return ie2 * (q * ((8.0 / 3.0) + q * (-3.0 + q * (1.2 - q * (1.0 / 6.0))))) - ir * ir * (1.0 / 15.0);
+// The same softened kernels in division-free form for the inner loops, in
+// either precision: q = r / e with ie = 1/e and ir = 1/r given
+// (1/(15 q^2 e^2) = ir^2 / 15).
+template <class T>
+__device__ __forceinline__ T soft_fr_q(T q, T ie, T ir) {
+  if (q >= T(2)) return ir * ir;
+  const T q2 = q * q, ie2 = ie * ie;
+  if (q < T(1)) return ie2 * q * (T(4.0 / 3.0) + q2 * (T(-1.2) + T(0.5) * q));
+  return ie2 * (q * (T(8.0 / 3.0) + q * (T(-3) + q * (T(1.2) - q * T(1.0 / 6.0))))) - ir * ir * T(1.0 / 15.0);
 }
 
-__device__ __forceinline__ double soft_ph_q(double q, double ie, double ir) {
-  if (q >= 2.0) return -ir;
-  const double q2 = q * q;
-  if (q < 1.0) return ie * (q2 * ((2.0 / 3.0) + q2 * (-0.3 + 0.1 * q)) - 1.4);
-  return ie * (q2 * ((4.0 / 3.0) + q * (-1.0 + q * (0.3 - q * (1.0 / 30.0)))) - 1.6) + ir * (1.0 / 15.0);
+template <class T>
+__device__ __forceinline__ T soft_ph_q(T q, T ie, T ir) {
+  if (q >= T(2)) return -ir;
+  const T q2 = q * q;
+  if (q < T(1)) return ie * (q2 * (T(2.0 / 3.0) + q2 * (T(-0.3) + T(0.1) * q)) - T(1.4));
+  return ie * (q2 * (T(4.0 / 3.0) + q * (T(-1) + q * (T(0.3) - q * T(1.0 / 30.0)))) - T(1.6)) + ir * T(1.0 / 15.0);
 }
 
-__device__ __forceinline__ double soft_pe_q(double q, double ie) {
-  if (q >= 2.0) return 0.0;
-  const double q2 = q * q;
-  if (q < 1.0) return (1.4 + q2 * (-2.0 + q2 * (1.5 - 0.6 * q))) * (ie * ie);
-  return (1.6 + q2 * (-4.0 + q * (4.0 + q * (-1.5 + 0.2 * q)))) * (ie * ie);
+template <class T>
+__device__ __forceinline__ T soft_pe_q(T q, T ie) {
+  if (q >= T(2)) return T(0);
+  const T q2 = q * q;
+  if (q < T(1)) return (T(1.4) + q2 * (T(-2) + q2 * (T(1.5) - T(0.6) * q))) * (ie * ie);
+  return (T(1.6) + q2 * (T(-4) + q * (T(4) + q * (T(-1.5) + T(0.2) * q)))) * (ie * ie);
 }
 
-__device__ __forceinline__ double m4_dw(double q) {
-  if (q < 1.0) return q * (-3.0 + 2.25 * q);
-  if (q < 2.0) {
-    const double t = 2.0 - q;
-    return -0.75 * t * t;
+template <class T>
+__device__ __forceinline__ T m4_dw(T q) {
+  if (q < T(1)) return q * (T(-3) + T(2.25) * q);
+  if (q < T(2)) {
+    const T t = T(2) - q;
+    return T(-0.75) * t * t;
   }
-  return 0.0;
+  return T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,6 +419,8 @@ __device__ __forceinline__ Batch load_batch(const int2 *batches, const int32_t *
 
 // host-side launch helpers (defined in the translation units)
 int blocks_for(int64_t n, int threads, int max_blocks);
+// a[0, n) = v (tree.hip)
+__global__ __launch_bounds__(256) void k_fill_i32(int64_t n, int32_t *__restrict__ a, int32_t v);
 // grid of a persistent one-wave-per-workgroup kernel: resident workgroups per
 // CU (from its register and LDS use) times the CU count
 int persistent_blocks(Ctx *c, const void *kernel);

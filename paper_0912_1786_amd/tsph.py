@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libtsph.so")
 
 TSPH_OK, TSPH_EINVAL, TSPH_ENOMEM, TSPH_EHIP, TSPH_ECAPACITY, TSPH_ENOCONV, TSPH_EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
 SOFT_ADAPTIVE, SOFT_CONSTANT, SOFT_ADAPTIVE_NOCORR = 0, 1, 2
-FP64 = 0
+FP64, FP32_BULK = 0, 1
 KD_FIRST, KD_SECOND = 0, 1
 FLAG_NODE_CAPACITY, FLAG_STACK_OVERFLOW, FLAG_LIST_OVERFLOW, FLAG_NOCONV, FLAG_NONFINITE, FLAG_INTERNAL = (
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20)
@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("beta", C.c_double), ("av_eps2", C.c_double), ("tc92", C.c_int32), ("h_maxit", C.c_int32),
                 ("h_tol", C.c_double), ("kappa", C.c_double), ("leaf_size", C.c_int32),
                 ("group_size", C.c_int32), ("precision", C.c_int32), ("gravity", C.c_int32),
-                ("hydro", C.c_int32), ("reserved", C.c_int32), ("eta_dt", C.c_double)]
+                ("hydro", C.c_int32), ("split_leaves", C.c_int32), ("eta_dt", C.c_double)]
 
 
 _P = C.c_void_p

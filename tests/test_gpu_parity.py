@@ -143,6 +143,35 @@ def test_forces_match_oracle(orc_mod, case):
     _compare_full(orc_mod, ic, gp, direct=True)
 
 
+@pytest.mark.parametrize("case,precision", [("field2x3000", "fp64"), ("evrard4096_v", "fp64"),
+                                            ("field2x3000", "fp32_bulk")])
+def test_forces_with_near_field_hand_off(orc_mod, case, precision):
+    """Batches whose near field exceeds split_leaves opened leaves hand the
+    rest to other wavefronts; forced here with a tiny threshold, the result
+    still matches the oracle and repeats bit for bit."""
+    _say(f"[split] case={case} precision={precision}")
+    ic = CASES[case]()
+    nnei = 60 if case.startswith("field") else 50
+    prec = tsph.FP32_BULK if precision == "fp32_bulk" else tsph.FP64
+    gp = gpu_params(nnei=nnei, leaf_size=16, group_size=64, split_leaves=2, precision=prec)
+    outs = []
+    for _ in range(2):
+        sim, g = run_gpu(ic, gp)
+        sim.close()
+        outs.append(g)
+    g = outs[0]
+    assert g["flags"] == 0 and g["noconv"] == 0
+    for k in ("ax", "ay", "az", "pot"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+    o = orc_mod.compute_forces(ic, oracle_params(orc_mod, gp))
+    e = relrms(acc(g), acc(o))
+    _say(f"    acc relRMS vs oracle group walk = {e:.3e}")
+    assert e < 1e-5
+    assert relrms(g["pot"], o["pot"]) < 1e-5
+    assert np.mean(g["cnt_pair"] != o["cnt_pair"]) < 1e-3
+    assert np.mean(g["cnt_node"] != o["cnt_node"]) < 1e-3
+
+
 @pytest.mark.parametrize("leaf,group", [(8, 32), (1, 8), (32, 16)])
 def test_forces_other_tree_shapes(orc_mod, leaf, group):
     _say(f"[forces-shape] leaf={leaf} group={group}")
