@@ -101,10 +101,14 @@ typedef struct {
   int32_t precision;   /* TSPH_FP64 or TSPH_FP32_BULK                           */
   int32_t gravity;     /* 1: self-gravity on                                   */
   int32_t hydro;       /* 1: SPH on                                            */
-  int32_t split_leaves; /* a walk batch evaluates at most this many opened leaves
-                          * of its gravity near field itself; the rest go, in
-                          * work items of 64 to 127 leaves, to other wavefronts
-                          * and are summed back in a fixed order (0: never)   */
+  int32_t split_leaves; /* load balance (0: off).  A walk batch evaluates at
+                          * most this many opened leaves of its gravity near
+                          * field itself; the rest go, in work items of 64 to
+                          * 127 leaves, to other wavefronts and are summed back
+                          * in a fixed order.  A batch whose density candidates
+                          * span more leaves (or overflow the on-chip list) is
+                          * solved one sink per wavefront, the lanes sharing
+                          * the sink's candidates.                            */
   double eta_dt;       /* time-step coefficient of the Sect. 4.2 criteria      */
 } tsph_params;
 

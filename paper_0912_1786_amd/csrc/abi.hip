@@ -99,6 +99,7 @@ size_t layout_bytes(int64_t N, int64_t M, Layout *L) {
   L->add(sizeof(SplitItem) * (size_t)icap);     // split_item
   L->add(32 * 64 * (size_t)icap);               // split_part
   L->add(4 * M);                                // split_head
+  L->add(4 * heavy_batch_cap(M));               // heavy
   // small
   L->add(sizeof(DevRoot));           // 27 root
   L->add(8 * 6 * 512);               // 28 bbox_part
@@ -270,6 +271,8 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->split_part = AT(double4 *);
   c->split_head = AT(int32_t *);
   c->split_cap = split_item_cap(c->cap_nodes);
+  c->heavy = AT(int32_t *);
+  c->heavy_cap = heavy_batch_cap(c->cap_nodes);
   c->root = AT(DevRoot *);
   c->bbox_part = AT(double *);
   c->lvl = AT(int32_t *);

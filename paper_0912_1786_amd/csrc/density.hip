@@ -53,6 +53,9 @@ struct DensArgs {
   int32_t *noconv;
   int32_t *dbg;
   int32_t dbg_max;
+  int32_t *heavy;      // batches handed to k_density_sink
+  int32_t heavy_cap;   // 0: no hand-off
+  int32_t split_leaves;  // hand off batches with more candidate leaves
   double eta_h, eta_eps, kappa, h_tol, gamma;
   int32_t maxit, soft_mode, hydro, gravity, shared;
 };
@@ -276,18 +279,47 @@ struct SolveOut {
   double h;
   Sums s;
   bool ok;
+  bool handed;  // the batch was handed to k_density_sink; nothing else is valid
 };
 
-// One self-consistent length per lane (inactive lanes follow along).  The
-// bracket [0, hi] starts at hi = h_guess (1 + kappa) (a quarter of it on a
-// cold start) and hi doubles until g(hi) >= 0 for every lane; Newton steps
-// that leave the bracket are replaced by bisection; iteration stops when
-// |dh| < h_tol h_start.  Quantities are then evaluated at the final h.
-__device__ SolveOut solve_length(const DensArgs &A, const NodeBox &gb, bool sink, bool gas_only, double eta,
+// Newton update of a length: safeguarded step on the monotone g(h) with the
+// bracket [lo, hi]; returns true when converged (step below h_tol h).
+__device__ __forceinline__ bool newton_update(double &h, double &lo, double &hi, double &dx_old, double n, double sdh,
+                                              double eta3, double tol) {
+  const double g = h * h * h * n - eta3;
+  const double gp = 3.0 * h * h * n + h * h * h * sdh;
+  if (g < 0.0) lo = h;
+  else hi = h;
+  const double dx = g / gp;
+  if (fabs(dx) < tol * h) return true;
+  double hn = h - dx;
+  if (!(hn > lo && hn < hi) || fabs(dx) > 0.5 * dx_old || (isinf(hi) && hn > 2.0 * h))
+    hn = isinf(hi) ? 2.0 * h : 0.5 * (lo + hi);
+  dx_old = fabs(hn - h);
+  h = hn;
+  return false;
+}
+
+// Hands batch g to k_density_sink when its candidate leaves exceed
+// split_leaves or overflow the LDS cache (sinks whose kernel reaches into a
+// dense neighbourhood); false when the hand-off list is full or disabled.
+__device__ __forceinline__ bool hand_off(const DensArgs &A, int g) {
+  if (A.heavy_cap <= 0 || A.dbg) return false;
+  int slot = 0;
+  if (lane() == 0) slot = atomicAdd(&A.work[6], 1);
+  slot = __shfl(slot, 0, kWave);
+  if (slot >= A.heavy_cap) return false;
+  if (lane() == 0) A.heavy[slot] = g;
+  return true;
+}
+
+// One self-consistent length per lane (inactive lanes follow along).
+__device__ SolveOut solve_length(const DensArgs &A, int g, const NodeBox &gb, bool sink, bool gas_only, double eta,
                                  double guess, double px, double py, double pz, double4 vp, bool want_div,
                                  bool want_phi, int *s_stack, int *s_leaf, DensTile &T, double4 *s_snk, bool cold,
                                  int32_t *dbg_row) {
   SolveOut o;
+  o.handed = false;
   const double eta3 = eta * eta * eta;
   const int64_t set_size = gas_only ? A.n_gas : A.n;
   const bool solvable = sink && ((double)set_size / kPi > eta3) && (guess > 0.0);
@@ -320,6 +352,10 @@ __device__ SolveOut solve_length(const DensArgs &A, const NodeBox &gb, bool sink
       c = gather(A, gb, R, gas_only, s_stack, s_leaf, s_snk, fail);
       gathered = true;
       if (fail) break;
+      if ((!c.cached || c.nleaf > A.split_leaves) && hand_off(A, g)) {
+        o.handed = true;
+        return o;
+      }
     }
     int ndbg = 0;
     const Sums s = pass<true>(A, gb, c, s_stack, s_leaf, T, s_snk, px, py, pz, vp, h, want_div, want_phi,
@@ -330,22 +366,11 @@ __device__ SolveOut solve_length(const DensArgs &A, const NodeBox &gb, bool sink
       h_keep = h;
       ndbg_keep = ndbg;
       ndbg_max = max(ndbg_max, ndbg);
-      const double g = h * h * h * s.n - eta3;
-      const double gp = 3.0 * h * h * s.n + h * h * h * s.sdh;
-      if (g < 0.0) lo = h;
-      else hi = h;
-      const double dx = g / gp;
       if (!solvable) {
         done = true;
-      } else if (fabs(dx) < A.h_tol * h) {
+      } else if (newton_update(h, lo, hi, dx_old, s.n, s.sdh, eta3, A.h_tol)) {
         done = true;
         ok = true;
-      } else {
-        double hn = h - dx;
-        if (!(hn > lo && hn < hi) || fabs(dx) > 0.5 * dx_old || (isinf(hi) && hn > 2.0 * h))
-          hn = isinf(hi) ? 2.0 * h : 0.5 * (lo + hi);
-        dx_old = fabs(hn - h);
-        h = hn;
       }
     }
   }
@@ -368,6 +393,51 @@ __device__ __forceinline__ double cold_guess(const DensArgs &A, int p, bool gas_
   if (gas_only && A.nngas[k] > 0) cnt = (double)A.nngas[k];
   double s = ldexp(A.root->side, -A.nlevel[k]);
   return eta * cbrt(s * s * s / cnt);
+}
+
+// Writes the solved lengths, densities and correction factors of particle p
+// (key order) and its gravity and SPH source records.
+__device__ __forceinline__ void store_outputs(const DensArgs &A, int p, bool is_gas, const double4 &a,
+                                              const double4 &vp, double h_gas, const Sums &sh, double eps,
+                                              double neps, double ups, double xi, double divve) {
+  double h = 0.0, rho = 0.0, omega = 0.0, zeta = 0.0, divv = 0.0, c = 0.0, pr2 = 0.0;
+  if (is_gas) {
+    h = h_gas;
+    rho = sh.rho;
+    omega = 1.0 + (h / (3.0 * sh.n)) * sh.sdh;
+    zeta = -(h / (3.0 * sh.n)) * sh.msdh;
+    divv = -sh.divv / (sh.n * omega);
+    c = sqrt(A.gamma * (A.gamma - 1.0) * vp.w);
+    pr2 = (A.gamma - 1.0) * vp.w / rho;  // P / rho^2 with P = (gamma - 1) rho u
+  }
+  A.hs[p] = h;
+  A.es[p] = eps;
+  A.sph[p] = make_double4(h, rho, c, pr2);
+  const double zo = is_gas ? zeta / omega : 0.0;
+  A.zo[p] = zo;
+  const double xiu = (A.gravity && A.soft_mode == TSPH_SOFT_ADAPTIVE) ? xi / ups : 0.0;
+  A.soft[p] = make_double2(eps, xiu);
+  GravRec gr;
+  gr.x = a.x; gr.y = a.y; gr.z = a.z; gr.m = a.w;
+  gr.eps = eps; gr.ieps = eps > 0.0 ? 1.0 / eps : 0.0; gr.xiu = xiu; gr.pad = 0.0;
+  A.grec[p] = gr;
+  if (is_gas) {
+    SphRec sr;
+    sr.x = a.x; sr.y = a.y; sr.z = a.z; sr.m = a.w;
+    sr.vx = vp.x; sr.vy = vp.y; sr.vz = vp.z; sr.im = 1.0 / a.w;
+    sr.h = h; sr.ih = 1.0 / h; sr.rho = rho; sr.c = c;
+    sr.pr2 = pr2; sr.zo = zo; sr.pad0 = 0.0; sr.pad1 = 0.0;
+    A.srec[p] = sr;
+  }
+  double *S = A.solve;
+  S[kNh * A.cap_n + p] = is_gas ? sh.n : 0.0;
+  S[kOmega * A.cap_n + p] = omega;
+  S[kZeta * A.cap_n + p] = zeta;
+  S[kDivv * A.cap_n + p] = divv;
+  S[kNeps * A.cap_n + p] = neps;
+  S[kUps * A.cap_n + p] = ups;
+  S[kXi * A.cap_n + p] = xi;
+  S[kDivvE * A.cap_n + p] = divve;
 }
 
 __global__ __launch_bounds__(64) void k_density(DensArgs A) {
@@ -397,20 +467,23 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
       const int ci = act ? A.perm[p] : 0;
       int32_t *dbg0 = A.dbg ? A.dbg + ((int64_t)0 * A.cap_n + ci) * A.dbg_max : nullptr;
       // ---- smoothing length over gas neighbours (gas sinks) ----
+      bool handed = false;
       SolveOut oh;
       oh.h = 0.0;
       oh.ok = true;
+      oh.handed = false;
       oh.s = Sums{0, 0, 0, 0, 0, 0};
       if (A.hydro) {
         double g0 = A.hs[p];
         double guess = g0 > 0.0 ? g0 : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
-        oh = solve_length(A, gb, is_gas, true, A.eta_h, guess, a.x, a.y, a.z, vp, true, A.shared != 0,
+        oh = solve_length(A, g, gb, is_gas, true, A.eta_h, guess, a.x, a.y, a.z, vp, true, A.shared != 0,
                           s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0), is_gas ? dbg0 : nullptr);
-        if (is_gas && !oh.ok) nnoconv++;
+        handed = oh.handed;
+        if (is_gas && !oh.ok && !handed) nnoconv++;
       }
       // ---- softening length over all neighbours (all sinks) ----
       double eps = 0.0, neps = 0.0, ups = 1.0, xi = 0.0, divve = 0.0;
-      if (A.gravity) {
+      if (A.gravity && !handed) {
         if (A.soft_mode == TSPH_SOFT_CONSTANT) {
           eps = A.es[p];
         } else if (A.shared) {
@@ -422,9 +495,10 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
         } else {
           double g0 = A.es[p];
           double guess = g0 > 0.0 ? g0 : (act ? cold_guess(A, p, false, A.eta_eps) : 0.0);
-          SolveOut oe = solve_length(A, gb, act, false, A.eta_eps, guess, a.x, a.y, a.z, vp, true, true,
+          SolveOut oe = solve_length(A, g, gb, act, false, A.eta_eps, guess, a.x, a.y, a.z, vp, true, true,
                                      s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0), nullptr);
-          if (act && !oe.ok) nnoconv++;
+          handed = oe.handed;
+          if (act && !oe.ok && !handed) nnoconv++;
           eps = oe.h;
           neps = oe.s.n;
           ups = 1.0 + (oe.h / (3.0 * oe.s.n)) * oe.s.sdh;
@@ -432,49 +506,200 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
           divve = -oe.s.divv / (oe.s.n * ups);
         }
       }
-      if (act) {
-        double h = 0.0, rho = 0.0, omega = 0.0, zeta = 0.0, divv = 0.0, c = 0.0, pr2 = 0.0;
-        if (is_gas) {
-          h = oh.h;
-          rho = oh.s.rho;
-          omega = 1.0 + (h / (3.0 * oh.s.n)) * oh.s.sdh;
-          zeta = -(h / (3.0 * oh.s.n)) * oh.s.msdh;
-          divv = -oh.s.divv / (oh.s.n * omega);
-          c = sqrt(A.gamma * (A.gamma - 1.0) * vp.w);
-          pr2 = (A.gamma - 1.0) * vp.w / rho;  // P / rho^2 with P = (gamma - 1) rho u
-        }
-        A.hs[p] = h;
-        A.es[p] = eps;
-        A.sph[p] = make_double4(h, rho, c, pr2);
-        const double zo = is_gas ? zeta / omega : 0.0;
-        A.zo[p] = zo;
-        const double xiu = (A.gravity && A.soft_mode == TSPH_SOFT_ADAPTIVE) ? xi / ups : 0.0;
-        A.soft[p] = make_double2(eps, xiu);
-        GravRec gr;
-        gr.x = a.x; gr.y = a.y; gr.z = a.z; gr.m = a.w;
-        gr.eps = eps; gr.ieps = eps > 0.0 ? 1.0 / eps : 0.0; gr.xiu = xiu; gr.pad = 0.0;
-        A.grec[p] = gr;
-        if (is_gas) {
-          SphRec sr;
-          sr.x = a.x; sr.y = a.y; sr.z = a.z; sr.m = a.w;
-          sr.vx = vp.x; sr.vy = vp.y; sr.vz = vp.z; sr.im = 1.0 / a.w;
-          sr.h = h; sr.ih = 1.0 / h; sr.rho = rho; sr.c = c;
-          sr.pr2 = pr2; sr.zo = zo; sr.pad0 = 0.0; sr.pad1 = 0.0;
-          A.srec[p] = sr;
-        }
-        double *S = A.solve;
-        S[kNh * A.cap_n + p] = is_gas ? oh.s.n : 0.0;
-        S[kOmega * A.cap_n + p] = omega;
-        S[kZeta * A.cap_n + p] = zeta;
-        S[kDivv * A.cap_n + p] = divv;
-        S[kNeps * A.cap_n + p] = neps;
-        S[kUps * A.cap_n + p] = ups;
-        S[kXi * A.cap_n + p] = xi;
-        S[kDivvE * A.cap_n + p] = divve;
-      }
+      if (handed) break;
+      if (act) store_outputs(A, p, is_gas, a, vp, oh.h, oh.s, eps, neps, ups, xi, divve);
     }
   }
   if (nnoconv) {
+    atomicAdd(A.noconv, nnoconv);
+    atomicOr(A.flags, TSPH_FLAG_NOCONV);
+  }
+}
+
+// ---- one sink per wavefront: sinks of handed-off batches, whose kernel
+// reaches into a dense neighbourhood.  The lanes share the candidates of the
+// one sink and their partial sums are reduced across the wave in a fixed
+// order; the iteration is that of solve_length.
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Contribution of candidate q to the sums of the sink at (px, py, pz).
+__device__ __forceinline__ void add_candidate(const DensArgs &A, int q, bool gas_only, double px, double py, double pz,
+                                              const double4 &vp, double ih, double ih3, double ih4, double R2,
+                                              bool want_div, bool want_phi, Sums &s) {
+  if (gas_only && !A.gas[q]) return;
+  const double4 a = A.pm[q];
+  const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+  if (!(r2 < R2)) return;
+  const double r = r2 > 0.0 ? r2 * rsqrt(r2) : 0.0;
+  const double qq = r * ih;
+  double w, dw;
+  m4(qq, w, dw);
+  const double W = w * ih3;
+  const double dWdh = -(3.0 * w + qq * dw) * ih4;
+  s.n += W;
+  s.sdh += dWdh;
+  s.rho += a.w * W;
+  s.msdh += a.w * dWdh;
+  if (want_phi) s.mdphi += a.w * soft_pe_q(qq, ih);
+  if (want_div && r > 0.0) {
+    const double4 v = A.vu[q];
+    const double g = dw * ih4 * (ih / qq);
+    s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
+  }
+}
+
+// Kernel sums of one sink over the particles of the leaves leaf[0, nleaf),
+// packed 64 to a round, one candidate per lane (per-lane partial sums).
+__device__ void sink_leaf_sums(const DensArgs &A, int nleaf, const int *leaf, bool gas_only, double px, double py,
+                               double pz, const double4 &vp, double h, bool want_div, bool want_phi, Sums &s) {
+  const int ln = lane();
+  const double ih = 1.0 / h;
+  const double ih3 = ih * ih * ih / kPi;
+  const double ih4 = ih3 * ih;
+  const double R2 = (2.0 * h) * (2.0 * h);
+  int fill = 0, rq = 0;
+  for (int c1 = 0; c1 < nleaf; c1 += kWave) {
+    const int nc = min(kWave, nleaf - c1);
+    const NodeTopo my = ln < nc ? A.topo[leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
+    for (int j = 0; j < nc; j++) {
+      const int first = __builtin_amdgcn_readlane(my.first, j);
+      const int count = __builtin_amdgcn_readlane(my.count, j);
+      for (int off = 0; off < count;) {
+        const int tk = min(count - off, kWave - fill);
+        if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
+        fill += tk;
+        off += tk;
+        if (fill == kWave) {
+          add_candidate(A, rq, gas_only, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+          fill = 0;
+        }
+      }
+    }
+  }
+  if (ln < fill) add_candidate(A, rq, gas_only, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+}
+
+// One self-consistent length of one sink (wave-uniform).
+__device__ SolveOut solve_one(const DensArgs &A, int p, bool gas_only, double eta, double guess, bool cold,
+                              const double4 &a, const double4 &vp, bool want_div, bool want_phi, int *s_stack,
+                              int *s_leaf, double4 *s_snk) {
+  SolveOut o;
+  o.handed = false;
+  const double eta3 = eta * eta * eta;
+  const int64_t set_size = gas_only ? A.n_gas : A.n;
+  const bool solvable = ((double)set_size / kPi > eta3) && (guess > 0.0);
+  const NodeBox pb{a.x, a.y, a.z, 0.0, a.x, a.y, a.z, 0.0};
+  double h = guess > 0.0 ? (solvable && cold ? 0.5 * guess : guess) : 1.0;
+  double lo = 0.0, hi = INFINITY, dx_old = INFINITY, rc = h * (1.0 + A.kappa);
+  bool fail = false, ok = false, gathered = false;
+  Cands c{0, true, 0.0, gas_only};
+  Sums keep{0, 0, 0, 0, 0, 0};
+  double h_keep = h;
+  for (int it = 0; it < A.maxit; it++) {
+    if (!gathered || h > rc) {
+      if (gathered) rc = h * (1.0 + A.kappa);
+      s_snk[lane()] = make_double4(a.x, a.y, a.z, lane() == 0 ? 2.0 * rc : 0.0);
+      __syncthreads();
+      c = gather(A, pb, 2.0 * rc, gas_only, s_stack, s_leaf, s_snk, fail);
+      gathered = true;
+      if (fail) break;
+    }
+    Sums s{0, 0, 0, 0, 0, 0};
+    if (c.cached) {
+      sink_leaf_sums(A, c.nleaf, s_leaf, gas_only, a.x, a.y, a.z, vp, h, want_div, want_phi, s);
+    } else {
+      const bool wok = walk_leaves(A, pb, c.R, gas_only, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
+        sink_leaf_sums(A, nl, s_leaf, gas_only, a.x, a.y, a.z, vp, h, want_div, want_phi, s);
+        return true;
+      });
+      if (!wok) {
+        fail = true;
+        break;
+      }
+    }
+    s.n = wave_sum(s.n);
+    s.sdh = wave_sum(s.sdh);
+    s.rho = wave_sum(s.rho);
+    s.msdh = wave_sum(s.msdh);
+    s.mdphi = wave_sum(s.mdphi);
+    s.divv = wave_sum(s.divv);
+    keep = s;
+    h_keep = h;
+    if (!solvable) break;
+    if (newton_update(h, lo, hi, dx_old, s.n, s.sdh, eta3, A.h_tol)) {
+      ok = true;
+      break;
+    }
+  }
+  o.h = h_keep;
+  o.ok = ok && !fail;
+  o.s = keep;
+  return o;
+}
+
+__global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
+  __shared__ int s_stack[kDensStackCap];
+  __shared__ int s_leaf[kDensLeafCap];
+  __shared__ double4 s_snk[kWave];
+  __shared__ int s_t;
+  const int ln = lane();
+  const int nslot = min(A.work[6], A.heavy_cap);
+  int nnoconv = 0;
+  for (;;) {
+    if (ln == 0) s_t = atomicAdd(&A.work[7], 1);
+    __syncthreads();
+    const int t = s_t;
+    __syncthreads();
+    if (t >= nslot * kWave) break;
+    const int g = A.heavy[t / kWave];
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
+    for (int j = t % kWave; j < bt.count; j += kWave) {
+      const int p = bt.first + j;
+      const double4 a = A.pm[p];
+      const double4 vp = A.vu[p];
+      const bool is_gas = A.gas[p] != 0;
+      SolveOut oh;
+      oh.h = 0.0;
+      oh.ok = true;
+      oh.s = Sums{0, 0, 0, 0, 0, 0};
+      if (A.hydro && is_gas) {
+        const double g0 = A.hs[p];
+        const double guess = g0 > 0.0 ? g0 : cold_guess(A, p, true, A.eta_h);
+        oh = solve_one(A, p, true, A.eta_h, guess, !(g0 > 0.0), a, vp, true, A.shared != 0, s_stack, s_leaf, s_snk);
+        if (!oh.ok) nnoconv++;
+      }
+      double eps = 0.0, neps = 0.0, ups = 1.0, xi = 0.0, divve = 0.0;
+      if (A.gravity) {
+        if (A.soft_mode == TSPH_SOFT_CONSTANT) {
+          eps = A.es[p];
+        } else if (A.shared) {
+          eps = oh.h;
+          neps = oh.s.n;
+          ups = 1.0 + (oh.h / (3.0 * oh.s.n)) * oh.s.sdh;
+          xi = (A.soft_mode == TSPH_SOFT_ADAPTIVE) ? -(oh.h / (3.0 * oh.s.n)) * oh.s.mdphi : 0.0;
+          divve = -oh.s.divv / (oh.s.n * ups);
+        } else {
+          const double g0 = A.es[p];
+          const double guess = g0 > 0.0 ? g0 : cold_guess(A, p, false, A.eta_eps);
+          const SolveOut oe =
+              solve_one(A, p, false, A.eta_eps, guess, !(g0 > 0.0), a, vp, true, true, s_stack, s_leaf, s_snk);
+          if (!oe.ok) nnoconv++;
+          eps = oe.h;
+          neps = oe.s.n;
+          ups = 1.0 + (oe.h / (3.0 * oe.s.n)) * oe.s.sdh;
+          xi = (A.soft_mode == TSPH_SOFT_ADAPTIVE) ? -(oe.h / (3.0 * oe.s.n)) * oe.s.mdphi : 0.0;
+          divve = -oe.s.divv / (oe.s.n * ups);
+        }
+      }
+      if (ln == 0) store_outputs(A, p, is_gas, a, vp, oh.h, oh.s, eps, neps, ups, xi, divve);
+    }
+  }
+  if (ln == 0 && nnoconv) {
     atomicAdd(A.noconv, nnoconv);
     atomicOr(A.flags, TSPH_FLAG_NOCONV);
   }
@@ -532,9 +757,14 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
               c->p.soft_mode != TSPH_SOFT_CONSTANT)
                  ? 1
                  : 0;
-  int dev_cus = 256;
-  (void)dev_cus;
+  A.heavy = c->heavy;
+  // debug lists are written by the batch's own wave
+  A.heavy_cap = (c->dbg_nbr || c->p.split_leaves == 0) ? 0 : (int32_t)c->heavy_cap;
+  A.split_leaves = c->p.split_leaves;
   hipLaunchKernelGGL(k_density, dim3(persistent_blocks(c, (const void *)k_density)), dim3(64), 0, st, A);
+  if (A.heavy_cap > 0)
+    hipLaunchKernelGGL(k_density_sink, dim3(persistent_blocks(c, (const void *)k_density_sink)), dim3(64), 0, st,
+                       A);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return tsph_impl_refresh(c, st);
 }

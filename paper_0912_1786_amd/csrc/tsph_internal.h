@@ -78,6 +78,9 @@ inline int64_t split_item_cap(int64_t cap_nodes) {
   return v < 4096 ? 4096 : (v > 262144 ? 262144 : v);
 }
 
+// capacity of the list of density batches solved one sink per wavefront
+inline int64_t heavy_batch_cap(int64_t cap_nodes) { return cap_nodes < 4096 ? 4096 : cap_nodes; }
+
 enum SolveField { kNh = 0, kOmega, kZeta, kDivv, kNeps, kUps, kXi, kMaxmu, kDivvE, kNumSolve };
 
 struct Ctx {
@@ -130,12 +133,15 @@ struct Ctx {
   int32_t *ngroups;
   uint32_t *hist;         // radix histograms kSortBins x sort blocks
   int32_t *scan_part;     // scan block sums
-  int32_t *work;          // work-queue counters (16): 0-2 walks, 3 split leaves, 4 split items, 5 split walk
+  int32_t *work;          // work-queue counters (16): 0-2 walks, 3 split leaves, 4 split items, 5 split walk,
+                          // 6 handed-off density batches, 7 their sinks
   int32_t *split_leaf;    // split_cap x kSplitItemLeaves leaves handed from batches' near fields
   SplitItem *split_item;  // split_cap work items over split_leaf
   double4 *split_part;    // split_cap x 64 partial (ax, ay, az, pot) of the items
   int64_t split_cap;
   int32_t *split_head;    // cap_nodes: first item of each batch (-1: none), items chained in order
+  int32_t *heavy;         // heavy_cap batches whose length solves run one sink per wavefront
+  int64_t heavy_cap;
   uint32_t *flags;        // device flag word
   int32_t *noconv;        // unconverged solves
   double *red;            // reduction scratch

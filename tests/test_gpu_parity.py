@@ -146,9 +146,11 @@ def test_forces_match_oracle(orc_mod, case):
 @pytest.mark.parametrize("case,precision", [("field2x3000", "fp64"), ("evrard4096_v", "fp64"),
                                             ("field2x3000", "fp32_bulk")])
 def test_forces_with_near_field_hand_off(orc_mod, case, precision):
-    """Batches whose near field exceeds split_leaves opened leaves hand the
-    rest to other wavefronts; forced here with a tiny threshold, the result
-    still matches the oracle and repeats bit for bit."""
+    """Batches whose gravity near field exceeds split_leaves opened leaves
+    hand the rest to other wavefronts, and batches with more density
+    candidate leaves are solved one sink per wavefront; forced here with a
+    tiny threshold, the results still match the oracle and repeat bit for
+    bit."""
     _say(f"[split] case={case} precision={precision}")
     ic = CASES[case]()
     nnei = 60 if case.startswith("field") else 50
@@ -161,9 +163,16 @@ def test_forces_with_near_field_hand_off(orc_mod, case, precision):
         outs.append(g)
     g = outs[0]
     assert g["flags"] == 0 and g["noconv"] == 0
-    for k in ("ax", "ay", "az", "pot"):
+    for k in ("ax", "ay", "az", "pot", "h", "eps", "rho", "dudt"):
         assert np.array_equal(outs[0][k], outs[1][k]), k
     o = orc_mod.compute_forces(ic, oracle_params(orc_mod, gp))
+    gas = np.arange(ic["n"]) < ic["n_gas"]
+    assert maxrel(g["h"], o["h"], gas) < 1e-9
+    assert maxrel(g["rho"], o["rho"], gas) < 1e-6
+    assert maxrel(g["eps"], o["eps"]) < 1e-9
+    assert np.allclose(g["xi"], o["xi"], rtol=1e-8, atol=1e-14 * np.abs(o["xi"]).max())
+    assert np.allclose(g["divv_eps"], o["divv_eps"], rtol=1e-7, atol=1e-9 * np.abs(o["divv_eps"]).max())
+    assert relrms(g["dudt"], o["dudt"]) < 1e-6
     e = relrms(acc(g), acc(o))
     _say(f"    acc relRMS vs oracle group walk = {e:.3e}")
     assert e < 1e-5
