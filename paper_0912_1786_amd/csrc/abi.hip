@@ -107,7 +107,7 @@ size_t layout_bytes(int64_t N, int64_t M, Layout *L) {
   L->add(4 * 16);                    // 30 ngroups
   L->add(4 * kSortBins * sort_blocks);  // 31 hist
   L->add(4 * scan_blocks);           // 32 scan_part
-  L->add(4 * 16);                    // 33 work
+  L->add(4 * kWorkCounters);         // 33 work
   L->add(4 * 16);                    // 34 flags
   L->add(4 * 16);                    // 35 noconv
   L->add(8 * 9 * 1024);              // 36 red
@@ -371,7 +371,7 @@ tsph_status tsph_compute_forces(void *ctx, tsph_state *s, void *stream) {
 #define MARK(i) \
   if (ev) TSPH_HIP_CHECK(c, hipEventRecord(ev[i], st));
   MARK(0);
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, c->work, 16);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(kWorkCounters), 0, st, c->work, kWorkCounters);
   if (c->dbg_nbr)
     hipLaunchKernelGGL(k_fill_dbg, dim3(1024), dim3(256), 0, st, (int64_t)3 * c->cap_n * c->dbg_max, c->dbg_nbr);
   if ((r = tsph_impl_build_tree(c, s, st)) != TSPH_OK) return r;

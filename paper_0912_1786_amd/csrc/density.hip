@@ -450,11 +450,11 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
   const int ng = *A.nbatches;
   int nnoconv = 0;
   for (;;) {
-    if (ln == 0) s_g = atomicAdd(&A.work[0], 1);
+    if (ln == 0) s_g = xcd_next(A.work + 8, ng);
     __syncthreads();
     const int g = s_g;
     __syncthreads();
-    if (g >= ng) break;
+    if (g < 0) break;
     const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
     const NodeTopo gnd{bt.first, bt.count, -1, 0};
     const NodeBox gb = bt.box;

@@ -439,11 +439,11 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
   const int ln = lane();
   const int ng = *A.nbatches;
   for (;;) {
-    if (ln == 0) s_g = atomicAdd(&A.work[1], 1);
+    if (ln == 0) s_g = xcd_next(A.work + 16, ng);
     __syncthreads();
     const int g = s_g;
     __syncthreads();
-    if (g >= ng) break;
+    if (g < 0) break;
     const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
     const NodeTopo gnd{bt.first, bt.count, -1, 0};
     const NodeBox gb = bt.box;

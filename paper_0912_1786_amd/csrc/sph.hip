@@ -64,11 +64,11 @@ __global__ __launch_bounds__(64) void k_sph(SphArgs A) {
   const int ng = *A.nbatches;
   const bool tc = A.tc92 != 0;
   for (;;) {
-    if (ln == 0) s_g = atomicAdd(&A.work[2], 1);
+    if (ln == 0) s_g = xcd_next(A.work + 24, ng);
     __syncthreads();
     const int g = s_g;
     __syncthreads();
-    if (g >= ng) break;
+    if (g < 0) break;
     const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
     if (bt.ngas == 0) continue;
     const NodeTopo gnd{bt.first, bt.count, -1, 0};

@@ -133,8 +133,9 @@ struct Ctx {
   int32_t *ngroups;
   uint32_t *hist;         // radix histograms kSortBins x sort blocks
   int32_t *scan_part;     // scan block sums
-  int32_t *work;          // work-queue counters (16): 0-2 walks, 3 split leaves, 4 split items, 5 split walk,
-                          // 6 handed-off density batches, 7 their sinks
+  int32_t *work;          // kWorkCounters work-queue counters: 3 split leaves, 4 split items, 5 split walk,
+                          // 6 handed-off density batches, 7 their sinks, 8/16/24 the XCD queues of the
+                          // density, gravity and SPH walks (8 each)
   int32_t *split_leaf;    // split_cap x kSplitItemLeaves leaves handed from batches' near fields
   SplitItem *split_item;  // split_cap work items over split_leaf
   double4 *split_part;    // split_cap x 64 partial (ax, ay, az, pot) of the items
@@ -385,6 +386,26 @@ __device__ __forceinline__ int walk_take(int sp, int cap) {
   int t = room >= 7 * kWave ? kWave : room / 7;
   t = t < 1 ? 1 : t;
   return t < sp ? t : sp;
+}
+
+// Work queues of the persistent walk kernels.  The batch list (Morton order)
+// is cut into one contiguous segment per XCD; a workgroup takes batches from
+// the segment of its XCD (workgroups are dispatched to the 8 XCDs round
+// robin), so that batches in flight on one XCD share nodes and particles in
+// that XCD's L2, and steals from the other segments once its own is empty.
+// ctr points at 8 counters; returns -1 when every segment is exhausted.
+constexpr int kWorkCounters = 64;
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_next(int32_t *ctr, int n) {
+  const int x = (int)(blockIdx.x % kXcds);
+  for (int k = 0; k < kXcds; k++) {
+    const int seg = (x + k) % kXcds;
+    const int lo = (int)((int64_t)n * seg / kXcds), hi = (int)((int64_t)n * (seg + 1) / kXcds);
+    if (lo >= hi) continue;
+    const int i = atomicAdd(&ctr[seg], 1);
+    if (lo + i < hi) return lo + i;
+  }
+  return -1;
 }
 
 // A walk batch: a run of sibling groups [g0, g1) of the group list; its
