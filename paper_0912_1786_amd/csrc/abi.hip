@@ -95,7 +95,7 @@ size_t layout_bytes(int64_t N, int64_t M, Layout *L) {
   L->add(8 * M);        // batches
   L->add(4 * 16);       // nbatches
   const int64_t icap = split_item_cap(M);
-  L->add(4 * (size_t)icap * kSplitItemLeaves);  // split_leaf
+  L->add(8 * (size_t)icap * kSplitItemRanges);  // split_rng
   L->add(sizeof(SplitItem) * (size_t)icap);     // split_item
   L->add(32 * 64 * (size_t)icap);               // split_part
   L->add(4 * M);                                // split_head
@@ -266,7 +266,7 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->groups = AT(int32_t *);
   c->batches = AT(int2 *);
   c->nbatches = AT(int32_t *);
-  c->split_leaf = AT(int32_t *);
+  c->split_rng = AT(int2 *);
   c->split_item = AT(SplitItem *);
   c->split_part = AT(double4 *);
   c->split_head = AT(int32_t *);

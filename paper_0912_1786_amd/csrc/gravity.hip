@@ -30,7 +30,7 @@ constexpr int kGStackCap = 1024;
 constexpr int kGListCap = 128;
 constexpr int kGCellFlush = 64;
 constexpr int kGLeafFlush = 32;
-constexpr int kGSplitFlush = 64;  // leaves per handed-off work item (64 to 127)
+constexpr int kGSplitFlush = 64;  // near entries collected before a hand-off
 constexpr double kInvPiG = 0.31830988618379067154;
 
 struct GravArgs {
@@ -54,10 +54,10 @@ struct GravArgs {
   int32_t dbg_max;
   double G;
   int32_t quadrupole, corr, want_pot;
-  // near-field hand-off (0 split_leaves: none)
-  int32_t split_leaves;
+  // near-field hand-off (0 split_particles: none)
+  int32_t split_particles;
   int64_t split_cap;
-  int32_t *split_leaf;
+  int2 *split_rng;
   SplitItem *split_item;
   double4 *split_part;
   int32_t *split_head;
@@ -348,13 +348,28 @@ using TileT = typename std::conditional<F32, Tile32, Tile64>::type;
 template <bool F32>
 using SinkT = typename std::conditional<F32, Sink32, Sink>::type;
 
-// Near field of the opened leaves leaf[0, nleaf) on sink s: their particles
-// are packed 64 to a tile while the leaves are scanned in order (each lane
-// noting the particle of its slot), loaded with one vector load per lane and
-// evaluated by every lane.  Returns the number of particles visited.
-template <int M, bool F32>
-__device__ __forceinline__ int near_leaves(const GravArgs &A, SinkT<F32> &s, const int *leaf, int nleaf,
-                                           TileT<F32> &T, int *tq, double cx, double cy, double cz) {
+// Near-field entries: particle ranges (first, count), given as tree nodes
+// (their particle range) or as explicit ranges.
+struct NodeSrc {
+  const NodeTopo *topo;
+  const int *node;
+  __device__ int2 operator()(int i) const {
+    const NodeTopo t = topo[node[i]];
+    return make_int2(t.first, t.count);
+  }
+};
+struct RangeSrc {
+  const int2 *rng;
+  __device__ int2 operator()(int i) const { return rng[i]; }
+};
+
+// Near field of the entries [0, n) on sink s: their particles are packed 64
+// to a tile while the entries are scanned in order (each lane noting the
+// particle of its slot), loaded with one vector load per lane and evaluated
+// by every lane.  Returns the number of particles visited.
+template <int M, bool F32, class Src>
+__device__ __forceinline__ int near_entries(const GravArgs &A, SinkT<F32> &s, const Src &src, int n, TileT<F32> &T,
+                                            int *tq, double cx, double cy, double cz) {
   const int ln = lane();
   int fill = 0, rq = -1, visited = 0;
   auto flush = [&](int nt) {
@@ -380,12 +395,12 @@ __device__ __forceinline__ int near_leaves(const GravArgs &A, SinkT<F32> &s, con
     }
     __syncthreads();
   };
-  for (int c1 = 0; c1 < nleaf; c1 += kWave) {
-    const int nc = min(kWave, nleaf - c1);
-    const NodeTopo my = ln < nc ? A.topo[leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
+  for (int c1 = 0; c1 < n; c1 += kWave) {
+    const int nc = min(kWave, n - c1);
+    const int2 my = ln < nc ? src(c1 + ln) : make_int2(0, 0);
     for (int j = 0; j < nc; j++) {
-      const int first = __builtin_amdgcn_readlane(my.first, j);
-      const int count = __builtin_amdgcn_readlane(my.count, j);
+      const int first = __builtin_amdgcn_readlane(my.x, j);
+      const int count = __builtin_amdgcn_readlane(my.y, j);
       visited += count;
       for (int off = 0; off < count;) {
         const int tk = min(count - off, kWave - fill);
@@ -401,6 +416,20 @@ __device__ __forceinline__ int near_leaves(const GravArgs &A, SinkT<F32> &s, con
   }
   if (fill > 0) flush(fill);
   return visited;
+}
+
+// Every point of box b within distance r of box a (farthest-point test).
+// A node passing it can only end as near pairs: each descendant's box gap
+// to a is at most this distance, below 2 max(eps) of the softening test.
+__device__ __forceinline__ bool box_within(const NodeBox &a, const NodeBox &b, double r) {
+#pragma clang fp contract(off)
+  const double ex = fmax(0.0, fmax(b.hix - a.hix, a.lox - b.lox));
+  const double ey = fmax(0.0, fmax(b.hiy - a.hiy, a.loy - b.loy));
+  const double ez = fmax(0.0, fmax(b.hiz - a.hiz, a.loz - b.loz));
+  double d = ex * ex;
+  d = d + ey * ey;
+  d = d + ez * ez;
+  return d < r * r;
 }
 
 // Loads sink chunk c0 of a batch (coordinates relative to the batch centre
@@ -427,7 +456,7 @@ __device__ __forceinline__ void load_sink(const GravArgs &A, SinkT<F32> &s, cons
 }
 
 template <int M, bool F32>
-__global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
+__global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
   __shared__ int s_stack[kGStackCap];
   __shared__ int s_cell[kGListCap];
   __shared__ int s_leaf[kGListCap];
@@ -454,7 +483,7 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
     for (int c0 = 0; c0 < gnd.count; c0 += kWave) {
       SinkT<F32> s;
       load_sink<F32>(A, s, gnd, c0, cx, cy, cz, true);
-      int near_done = 0;  // opened leaves evaluated by this wave
+      int near_done = 0;  // near-field particles evaluated by this wave
       int nfar = 0, npair = 0;
       int sp = 1, ncell = 0, nleaf = 0;
       bool overflow = false;
@@ -490,7 +519,9 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
             }
             if (!acc) {
               nd = A.topo[k];
-              leaf = nd.nchild == 0;
+              // a node wholly inside the softening reach of the batch is
+              // taken whole: all its particles are near pairs
+              leaf = nd.nchild == 0 || box_within(gb, b, 2.0 * gemax);
             }
           }
           const uint64_t am = ballot(acc);
@@ -541,39 +572,81 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
           nfar += ncell;
           ncell = 0;
         }
-        const bool split = A.split_leaves > 0 && near_done >= A.split_leaves;
-        if (nleaf >= (split ? kGSplitFlush : kGLeafFlush) || (last && nleaf > 0)) {
+        const bool splitting = A.split_particles > 0 && near_done >= A.split_particles;
+        if (nleaf >= (splitting ? kGSplitFlush : kGLeafFlush) || (last && nleaf > 0)) {
           bool handed = false;
-          if (split) {
-            // hand the leaves to another wavefront: reserve leaf space, then
-            // an item; items of a batch are chained in creation order
-            int base = 0, it = 0;
+          int tot = 0;
+          if (A.split_particles > 0) {
+            for (int a = ln; a < nleaf; a += kWave) tot += A.topo[s_leaf[a]].count;
+            tot = __shfl(wave_incl_scan(tot), kWave - 1, kWave);
+          }
+          if (A.split_particles > 0 && near_done + tot > A.split_particles) {
+            // hand the entries to other wavefronts as items of at most
+            // kSplitItemRanges ranges and kSplitItemParticles particles;
+            // ranges and items for the worst case are reserved up front
+            // an item closes at kSplitItemRanges ranges or kSplitItemParticles
+            // particles, and ranges are cut only at the latter
+            const int rmax = nleaf + tot / kSplitItemParticles + 1;
+            const int imax = (rmax + kSplitItemRanges - 1) / kSplitItemRanges + tot / kSplitItemParticles + 1;
+            int rbase = 0, ibase = 0;
             if (ln == 0) {
-              base = atomicAdd(&A.work[3], nleaf);
-              it = base + nleaf <= A.split_cap * kSplitItemLeaves ? atomicAdd(&A.work[4], 1) : INT32_MAX;
+              rbase = atomicAdd(&A.work[3], rmax);
+              ibase = rbase + rmax <= A.split_cap * kSplitItemRanges ? atomicAdd(&A.work[4], imax) : INT32_MAX;
             }
-            base = __shfl(base, 0, kWave);
-            it = __shfl(it, 0, kWave);
-            if (it < A.split_cap) {
-              int visited = 0;
-              for (int a = ln; a < nleaf; a += kWave) {
-                A.split_leaf[base + a] = s_leaf[a];
-                visited += A.topo[s_leaf[a]].count;
-              }
-              const int incl = wave_incl_scan(visited);
-              npair += __shfl(incl, kWave - 1, kWave);
-              if (ln == 0) {
-                A.split_item[it] = SplitItem{g, c0, base, nleaf, -1, 0, 0, 0};
-                if (prev_item >= 0) A.split_item[prev_item].next = it;
-                else A.split_head[g] = it;
-              }
-              prev_item = it;
+            rbase = __shfl(rbase, 0, kWave);
+            ibase = __shfl(ibase, 0, kWave);
+            if (ibase <= A.split_cap - imax) {
               handed = true;
+              near_done += tot;
+              npair += tot;
+              int nr = 0, parts = 0, ri = 0, ii = 0;  // ranges of the open item, totals used
+              for (int c1 = 0; c1 < nleaf; c1 += kWave) {
+                const int nc = min(kWave, nleaf - c1);
+                const NodeTopo my = ln < nc ? A.topo[s_leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
+                for (int j = 0; j < nc; j++) {
+                  const int first = __builtin_amdgcn_readlane(my.first, j);
+                  const int count = __builtin_amdgcn_readlane(my.count, j);
+                  for (int off = 0; off < count;) {
+                    const int tk = min(count - off, kSplitItemParticles - parts);
+                    if (ln == 0) A.split_rng[rbase + ri + nr] = make_int2(first + off, tk);
+                    nr++;
+                    parts += tk;
+                    off += tk;
+                    if (nr == kSplitItemRanges || parts == kSplitItemParticles) {
+                      const int it = ibase + ii;
+                      if (ln == 0) {
+                        A.split_item[it] = SplitItem{g, c0, rbase + ri, nr, -1, 0, 0, 0};
+                        if (prev_item >= 0) A.split_item[prev_item].next = it;
+                        else A.split_head[g] = it;
+                      }
+                      prev_item = it;
+                      ri += nr;
+                      ii++;
+                      nr = 0;
+                      parts = 0;
+                    }
+                  }
+                }
+              }
+              if (nr > 0) {
+                const int it = ibase + ii;
+                if (ln == 0) {
+                  A.split_item[it] = SplitItem{g, c0, rbase + ri, nr, -1, 0, 0, 0};
+                  if (prev_item >= 0) A.split_item[prev_item].next = it;
+                  else A.split_head[g] = it;
+                }
+                prev_item = it;
+                ii++;
+              }
+              // reserved items left over stay empty
+              for (int a = ii + ln; a < imax; a += kWave)
+                A.split_item[ibase + a] = SplitItem{-1, 0, 0, 0, -1, 0, 0, 0};
             }
           }
           if (!handed) {
-            npair += near_leaves<M, F32>(A, s, s_leaf, nleaf, s_t, s_tq, cx, cy, cz);
-            near_done += nleaf;
+            const int v = near_entries<M, F32>(A, s, NodeSrc{A.topo, s_leaf}, nleaf, s_t, s_tq, cx, cy, cz);
+            near_done += v;
+            npair += v;
           }
           nleaf = 0;
         }
@@ -610,7 +683,7 @@ __global__ __launch_bounds__(64) void k_gravity(GravArgs A) {
 // go to split_part, to be added in item order by k_split_reduce.
 template <int M, bool F32>
 __global__ __launch_bounds__(64) void k_gravity_split(GravArgs A) {
-  __shared__ int s_leaf[kSplitItemLeaves];
+  __shared__ int2 s_rng[kSplitItemRanges];
   __shared__ TileT<F32> s_t;
   __shared__ int s_tq[kWave];
   __shared__ int s_g;
@@ -623,15 +696,16 @@ __global__ __launch_bounds__(64) void k_gravity_split(GravArgs A) {
     __syncthreads();
     if (it >= nitems) break;
     const SplitItem I = A.split_item[it];
+    if (I.g < 0) continue;  // reserved but unused
     const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, I.g);
     const NodeTopo gnd{bt.first, bt.count, -1, 0};
     const NodeBox gb = bt.box;
     const double cx = 0.5 * (gb.lox + gb.hix), cy = 0.5 * (gb.loy + gb.hiy), cz = 0.5 * (gb.loz + gb.hiz);
     SinkT<F32> s;
     load_sink<F32>(A, s, gnd, I.c0, cx, cy, cz, false);
-    for (int a = ln; a < I.count; a += kWave) s_leaf[a] = A.split_leaf[I.start + a];
+    for (int a = ln; a < I.count; a += kWave) s_rng[a] = A.split_rng[I.start + a];
     __syncthreads();
-    near_leaves<M, F32>(A, s, s_leaf, I.count, s_t, s_tq, cx, cy, cz);
+    near_entries<M, F32>(A, s, RangeSrc{s_rng}, I.count, s_t, s_tq, cx, cy, cz);
     double4 part = make_double4(s.ax, s.ay, s.az, s.pot);
     if constexpr (F32) {
       part.x *= A.G;
@@ -711,9 +785,10 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
   A.quadrupole = c->p.quadrupole;
   A.corr = c->p.soft_mode == TSPH_SOFT_ADAPTIVE ? 1 : 0;
   A.want_pot = want_pot ? 1 : 0;
-  A.split_leaves = c->dbg_nbr ? 0 : c->p.split_leaves;  // debug lists are written by the batch's own wave
+  // debug lists are written by the batch's own wave
+  A.split_particles = c->dbg_nbr ? 0 : c->p.split_leaves * c->p.leaf_size;
   A.split_cap = c->split_cap;
-  A.split_leaf = c->split_leaf;
+  A.split_rng = c->split_rng;
   A.split_item = c->split_item;
   A.split_part = c->split_part;
   A.split_head = c->split_head;
@@ -738,7 +813,7 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(c->cap_nodes, 256, 4096)), dim3(256), 0, st, c->cap_nodes,
                      c->split_head, -1);
   hipLaunchKernelGGL(kern, dim3(persistent_blocks(c, (const void *)kern)), dim3(64), 0, st, A);
-  if (A.split_leaves > 0) {
+  if (A.split_particles > 0) {
     hipLaunchKernelGGL(skern, dim3(persistent_blocks(c, (const void *)skern)), dim3(64), 0, st, A);
     hipLaunchKernelGGL(k_split_reduce, dim3(4096), dim3(64), 0, st, A);
   }

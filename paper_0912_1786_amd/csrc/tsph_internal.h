@@ -63,16 +63,17 @@ struct DevRoot {
 
 // Per-particle solve outputs kept for export (sorted order).
 // A piece of a walk batch's near field evaluated by another wavefront: the
-// leaves split_leaf[start, start + count) acting on sink chunk c0 of batch g;
-// next chains the items of one batch in creation order.
+// particle ranges split_rng[start, start + count) = (first, count) acting on
+// sink chunk c0 of batch g; next chains the items of one batch in creation
+// order.
 struct SplitItem {
   int32_t g, c0, start, count, next, pad0, pad1, pad2;
 };
-// capacity in split items of a context with cap_nodes nodes; each item
-// holds at most kSplitItemLeaves leaves.  Past it, batches evaluate their
-// whole near field themselves (correct, but the summation order then
-// depends on which batches got items first).
-constexpr int kSplitItemLeaves = 128;
+constexpr int kSplitItemRanges = 128;      // ranges per item
+constexpr int kSplitItemParticles = 2048;  // particles per item; longer ranges are cut
+// capacity in split items of a context with cap_nodes nodes.  Past it,
+// batches evaluate their whole near field themselves (correct, but the
+// summation order then depends on which batches got items first).
 inline int64_t split_item_cap(int64_t cap_nodes) {
   const int64_t v = cap_nodes / 4;
   return v < 4096 ? 4096 : (v > 262144 ? 262144 : v);
@@ -136,8 +137,8 @@ struct Ctx {
   int32_t *work;          // kWorkCounters work-queue counters: 3 split leaves, 4 split items, 5 split walk,
                           // 6 handed-off density batches, 7 their sinks, 8/16/24 the XCD queues of the
                           // density, gravity and SPH walks (8 each)
-  int32_t *split_leaf;    // split_cap x kSplitItemLeaves leaves handed from batches' near fields
-  SplitItem *split_item;  // split_cap work items over split_leaf
+  int2 *split_rng;        // split_cap x kSplitItemRanges particle ranges handed from batches' near fields
+  SplitItem *split_item;  // split_cap work items over split_rng
   double4 *split_part;    // split_cap x 64 partial (ax, ay, az, pot) of the items
   int64_t split_cap;
   int32_t *split_head;    // cap_nodes: first item of each batch (-1: none), items chained in order
