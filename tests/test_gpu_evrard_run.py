@@ -1,0 +1,70 @@
+"""Evrard sphere at N = 262,144: 20 leapfrog steps with the global time-step
+rule in the FP32-bulk and FP64 forms, and the FP32-bulk form's errors at the
+first force evaluation against the FP64 oracle (same tree, same walk).
+
+Bars: |dE/E| after 20 steps below 4e-3 (the paper's Evrard runs keep the
+energy error within about 0.4% over the whole collapse, with a looser theta);
+the two forms' energy drifts within 1e-5 of each other (the FP32 interaction
+error is ~1e-8 relative); momentum drift |dP| / sum m|v| below 1e-2 (tree
+forces are not pairwise symmetric); FP32-bulk accelerations and potential
+within 1e-5 relative RMS of the oracle, densities and lengths to its FP64
+bars.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0912_1786_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # collected on CPU-only machines but never run there
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_0912_1786_amd import runs, tsph  # noqa: E402
+
+from gpu_common import acc, gpu_params, maxrel, oracle_params, relrms, run_gpu  # noqa: E402
+
+N = 262144
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_evrard_20_steps_energy_and_momentum():
+    _say(f"[evrard-run] N={N} 20 steps, both forms")
+    r32 = runs.evrard_run(N, 20, "fp32_bulk")
+    r64 = runs.evrard_run(N, 20, "fp64")
+    for r in (r32, r64):
+        _say(f"    {r['precision']}: dE/E step1 {r['dE_over_E_step1']:.3e} step20 {r['dE_over_E_step20']:.3e}; "
+             f"dP step1 {r['dP_rel_step1']:.3e} step20 {r['dP_rel_step20']:.3e}; median step {r['median_step_ms']:.2f} ms")
+        assert r["device_flags"] == 0 and r["noconv"] == 0
+        assert abs(r["dE_over_E_step20"]) < 4e-3
+        assert r["dP_rel_step20"] < 1e-2
+    assert abs(r32["dE_over_E_step20"] - r64["dE_over_E_step20"]) < 1e-5
+    assert r32["dt_first"] == pytest.approx(r64["dt_first"], rel=1e-6)
+
+
+def test_evrard_fp32_bulk_errors_against_oracle():
+    from oracle import oracle as O
+    _say(f"[evrard-oracle] N={N}")
+    ic = inputs.evrard(N, seed=1)
+    gp = gpu_params(precision=tsph.FP32_BULK)
+    sim, g = run_gpu(ic, gp)
+    sim.close()
+    assert g["flags"] == 0 and g["noconv"] == 0
+    o = O.compute_forces(ic, oracle_params(O, gp))
+    ea = relrms(acc(g), acc(o))
+    ep = relrms(g["pot"], o["pot"])
+    eu = relrms(g["dudt"], o["dudt"]) if np.any(o["dudt"]) else 0.0
+    er = maxrel(g["rho"], o["rho"])
+    eh = maxrel(g["h"], o["h"])
+    _say(f"    FP32 bulk vs FP64 oracle: a relRMS {ea:.2e}, pot relRMS {ep:.2e}, du/dt relRMS {eu:.2e}, "
+         f"rho max rel {er:.2e}, h max rel {eh:.2e}")
+    assert ea < 1e-5 and ep < 1e-5
+    assert er < 1e-6 and eh < 1e-9
+    assert eu < 1e-6
