@@ -161,6 +161,12 @@ tsph_status tsph_compute_forces(void *ctx, tsph_state *s, void *stream);
  * factor clamped to [1/2, 2].  They are starting values for the next solve.
  * TSPH_KD_SECOND: v += dt/2 a, u += dt/2 du/dt. */
 tsph_status tsph_kick_drift(void *ctx, tsph_state *s, double dt, int32_t phase, void *stream);
+/* The same with dt read on the device from dt_device (one double, e.g. the
+ * output of tsph_timestep), so that a captured HIP graph replays with the
+ * current time-step.  dt_device must stay valid while the work runs; a
+ * negative or non-finite value there makes the kernel do nothing (the
+ * state is left unchanged). */
+tsph_status tsph_kick_drift_dt(void *ctx, tsph_state *s, const double *dt_device, int32_t phase, void *stream);
 /* Global time-step (Sect. 4.2) from the last tsph_compute_forces: min over
  * particles of eta_dt sqrt(min(eps,h)/|a|), the Courant criterion and
  * eta_dt |u / du/dt|.  Writes one double to dt_device. */

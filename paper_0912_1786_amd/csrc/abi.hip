@@ -422,18 +422,35 @@ tsph_status tsph_phase_times(void *ctx, double *ms_out, int64_t *calls) {
   return TSPH_OK;
 }
 
-tsph_status tsph_kick_drift(void *ctx, tsph_state *s, double dt, int32_t phase, void *stream) {
-  Ctx *c = (Ctx *)ctx;
-  if (!c) return TSPH_EINVAL;
+static tsph_status kick_drift_checks(Ctx *c, tsph_state *s, int32_t phase) {
   if (!s || s->n < 1 || s->n_gas < 0 || s->n_gas > s->n) return set_err(c, TSPH_EINVAL, "bad state sizes");
   if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->ax || !s->ay || !s->az)
     return set_err(c, TSPH_EINVAL, "x, v and a are required");
   if (s->n_gas > 0 && (!s->u || !s->dudt)) return set_err(c, TSPH_EINVAL, "gas needs u and dudt");
   if (phase != TSPH_KD_FIRST && phase != TSPH_KD_SECOND) return set_err(c, TSPH_EINVAL, "unknown phase");
+  return TSPH_OK;
+}
+
+tsph_status tsph_kick_drift_dt(void *ctx, tsph_state *s, const double *dt_device, int32_t phase, void *stream) {
+  Ctx *c = (Ctx *)ctx;
+  if (!c) return TSPH_EINVAL;
+  if (!dt_device) return set_err(c, TSPH_EINVAL, "dt_device is NULL");
+  tsph_status r = kick_drift_checks(c, s, phase);
+  if (r != TSPH_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  return tsph_impl_kick_drift(c, s, 0.0, dt_device, phase, st);
+}
+
+tsph_status tsph_kick_drift(void *ctx, tsph_state *s, double dt, int32_t phase, void *stream) {
+  Ctx *c = (Ctx *)ctx;
+  if (!c) return TSPH_EINVAL;
+  tsph_status r = kick_drift_checks(c, s, phase);
+  if (r != TSPH_OK) return r;
   if (!(dt >= 0.0)) return set_err(c, TSPH_EINVAL, "dt must be >= 0");
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
-  return tsph_impl_kick_drift(c, s, dt, phase, st);
+  return tsph_impl_kick_drift(c, s, dt, nullptr, phase, st);
 }
 
 tsph_status tsph_timestep(void *ctx, const tsph_state *s, double *dt_device, void *stream) {

@@ -79,9 +79,14 @@ __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, int64_t n_gas, do
                                                     const double *__restrict__ ay, const double *__restrict__ az,
                                                     const double *__restrict__ dudt, double *vpx, double *vpy,
                                                     double *vpz, double *up, double *h, double *eps,
-                                                    const double *__restrict__ pdiv, int64_t cap_n) {
+                                                    const double *__restrict__ pdiv, int64_t cap_n,
+                                                    const double *__restrict__ dt_dev) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (dt_dev) {
+    dt = *dt_dev;
+    if (!(dt >= 0.0 && dt < INFINITY)) return;
+  }
   const double hdt = 0.5 * dt;
   const double a0 = ax[i], a1 = ay[i], a2 = az[i];
   double v0 = vx[i], v1 = vy[i], v2 = vz[i];
@@ -236,10 +241,12 @@ tsph_status tsph_impl_finish(Ctx *c, tsph_state *s, hipStream_t st) {
   return TSPH_OK;
 }
 
-tsph_status tsph_impl_kick_drift(Ctx *c, tsph_state *s, double dt, int phase, hipStream_t st) {
+tsph_status tsph_impl_kick_drift(Ctx *c, tsph_state *s, double dt, const double *dt_dev, int phase,
+                                 hipStream_t st) {
   hipLaunchKernelGGL(k_kick_drift, dim3(blocks_for(s->n, 256, 1 << 20)), dim3(256), 0, st, s->n, s->n_gas, dt,
                      phase, s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->ax, s->ay, s->az, s->dudt, s->vpx,
-                     s->vpy, s->vpz, s->up, s->h, s->eps, c->pdiv_n == s->n ? c->pdiv : nullptr, c->cap_n);
+                     s->vpy, s->vpz, s->up, s->h, s->eps, c->pdiv_n == s->n ? c->pdiv : nullptr, c->cap_n,
+                     dt_dev);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

@@ -461,7 +461,8 @@ tsph_status tsph_impl_density(tsph::Ctx *c, hipStream_t st);
 tsph_status tsph_impl_gravity(tsph::Ctx *c, bool want_pot, hipStream_t st);
 tsph_status tsph_impl_sph(tsph::Ctx *c, hipStream_t st);
 tsph_status tsph_impl_finish(tsph::Ctx *c, tsph_state *s, hipStream_t st);
-tsph_status tsph_impl_kick_drift(tsph::Ctx *c, tsph_state *s, double dt, int phase, hipStream_t st);
+tsph_status tsph_impl_kick_drift(tsph::Ctx *c, tsph_state *s, double dt, const double *dt_dev, int phase,
+                                 hipStream_t st);
 tsph_status tsph_impl_timestep(tsph::Ctx *c, double *dt_device, hipStream_t st);
 tsph_status tsph_impl_diagnostics(tsph::Ctx *c, const tsph_state *s, double *out, hipStream_t st);
 tsph_status tsph_impl_reset_work(tsph::Ctx *c, hipStream_t st);

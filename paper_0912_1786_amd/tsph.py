@@ -75,6 +75,7 @@ def lib():
             "tsph_build_tree": ([_P, S, _P], C.c_int),
             "tsph_compute_forces": ([_P, S, _P], C.c_int),
             "tsph_kick_drift": ([_P, S, C.c_double, C.c_int32, _P], C.c_int),
+            "tsph_kick_drift_dt": ([_P, S, _P, C.c_int32, _P], C.c_int),
             "tsph_timestep": ([_P, S, _P, _P], C.c_int),
             "tsph_diagnostics": ([_P, S, _P, _P], C.c_int),
             "tsph_read_flags": ([_P, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)], C.c_int),
@@ -94,8 +95,8 @@ def lib():
 
 
 EXPORTED = ("tsph_create", "tsph_destroy", "tsph_set_params", "tsph_default_params", "tsph_bytes_required",
-            "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_timestep", "tsph_diagnostics",
-            "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
+            "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_kick_drift_dt", "tsph_timestep",
+            "tsph_diagnostics", "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
             "tsph_timing", "tsph_phase_times")
 PHASES = ("tree", "density", "gravity", "sph", "finish")
 
@@ -165,6 +166,11 @@ def tsph_compute_forces(ctx, st: State, stream=None):
 
 def tsph_kick_drift(ctx, st: State, dt: float, phase: int, stream=None):
     _check("tsph_kick_drift", lib().tsph_kick_drift(ctx, C.byref(st), float(dt), int(phase), _stream(stream)), ctx)
+
+
+def tsph_kick_drift_dt(ctx, st: State, dt_ptr: int, phase: int, stream=None):
+    _check("tsph_kick_drift_dt",
+           lib().tsph_kick_drift_dt(ctx, C.byref(st), C.c_void_p(dt_ptr), int(phase), _stream(stream)), ctx)
 
 
 def tsph_timestep(ctx, st: State, dt_ptr: int, stream=None):
@@ -280,6 +286,15 @@ class Simulation:
         self.kick_drift(dt, KD_FIRST, stream)
         self.compute_forces(stream)
         self.kick_drift(dt, KD_SECOND, stream)
+
+    def device_step(self, stream=None):
+        """One KDK step with the global time-step taken and used on the device
+        (no host round trip; capturable in a HIP graph)."""
+        ptr = self.dt_buf.data_ptr()
+        tsph_timestep(self.ctx, self.state, ptr, stream)
+        tsph_kick_drift_dt(self.ctx, self.state, ptr, KD_FIRST, stream)
+        self.compute_forces(stream)
+        tsph_kick_drift_dt(self.ctx, self.state, ptr, KD_SECOND, stream)
 
     def flags(self):
         return tsph_read_flags(self.ctx)
