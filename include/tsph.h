@@ -167,6 +167,17 @@ tsph_status tsph_kick_drift(void *ctx, tsph_state *s, double dt, int32_t phase, 
  * negative or non-finite value there makes the kernel do nothing (the
  * state is left unchanged). */
 tsph_status tsph_kick_drift_dt(void *ctx, tsph_state *s, const double *dt_device, int32_t phase, void *stream);
+/* The carry of a context from one step to the next: the global time-step
+ * of the last force pass and the velocity divergences with which the next
+ * drift carries h and eps (2 n + 1 doubles for n particles).  Saving it and
+ * loading it into a context (the same or a new one) lets a simulation leave
+ * the device between steps and continue bit for bit: after tsph_carry_load
+ * the next tsph_timestep / tsph_kick_drift behave as if the force pass had
+ * run on that context.  Both are stream-ordered device-to-device copies;
+ * save fails with TSPH_EINVAL when the last force pass had a different n. */
+tsph_status tsph_carry_bytes(int64_t n, size_t *bytes);
+tsph_status tsph_carry_save(void *ctx, int64_t n, void *dst_device, void *stream);
+tsph_status tsph_carry_load(void *ctx, int64_t n, const void *src_device, void *stream);
 /* Global time-step (Sect. 4.2) from the last tsph_compute_forces: min over
  * particles of eta_dt sqrt(min(eps,h)/|a|), the Courant criterion and
  * eta_dt |u / du/dt|.  Writes one double to dt_device. */

@@ -431,6 +431,39 @@ static tsph_status kick_drift_checks(Ctx *c, tsph_state *s, int32_t phase) {
   return TSPH_OK;
 }
 
+tsph_status tsph_carry_bytes(int64_t n, size_t *bytes) {
+  if (!bytes || n < 1) return TSPH_EINVAL;
+  *bytes = sizeof(double) * (2 * (size_t)n + 1);
+  return TSPH_OK;
+}
+
+tsph_status tsph_carry_save(void *ctx, int64_t n, void *dst_device, void *stream) {
+  Ctx *c = (Ctx *)ctx;
+  if (!c) return TSPH_EINVAL;
+  if (!dst_device) return set_err(c, TSPH_EINVAL, "dst_device is NULL");
+  if (n < 1 || n != c->pdiv_n) return set_err(c, TSPH_EINVAL, "no force pass with this n to save");
+  hipStream_t st = (hipStream_t)stream;
+  double *d = (double *)dst_device;
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(d, c->dt, sizeof(double), hipMemcpyDeviceToDevice, st));
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(d + 1, c->pdiv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(d + 1 + n, c->pdiv + c->cap_n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  return TSPH_OK;
+}
+
+tsph_status tsph_carry_load(void *ctx, int64_t n, const void *src_device, void *stream) {
+  Ctx *c = (Ctx *)ctx;
+  if (!c) return TSPH_EINVAL;
+  if (!src_device) return set_err(c, TSPH_EINVAL, "src_device is NULL");
+  if (n < 1 || n > c->cap_n) return set_err(c, TSPH_ECAPACITY, "n exceeds the context capacity");
+  hipStream_t st = (hipStream_t)stream;
+  const double *d = (const double *)src_device;
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(c->dt, d, sizeof(double), hipMemcpyDeviceToDevice, st));
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(c->pdiv, d + 1, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(c->pdiv + c->cap_n, d + 1 + n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  c->pdiv_n = n;
+  return TSPH_OK;
+}
+
 tsph_status tsph_kick_drift_dt(void *ctx, tsph_state *s, const double *dt_device, int32_t phase, void *stream) {
   Ctx *c = (Ctx *)ctx;
   if (!c) return TSPH_EINVAL;

@@ -76,7 +76,7 @@ class Ensemble:
     """Independent simulations stepped together by one graph launch."""
 
     def __init__(self, ics, nnei: float = 50.0, precision: int = tsph.FP32_BULK, tuning: dict | None = None,
-                 streams: int = 8):
+                 streams: int = 16):
         import torch
         self.torch = torch
         self.members = []

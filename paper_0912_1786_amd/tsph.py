@@ -76,6 +76,9 @@ def lib():
             "tsph_compute_forces": ([_P, S, _P], C.c_int),
             "tsph_kick_drift": ([_P, S, C.c_double, C.c_int32, _P], C.c_int),
             "tsph_kick_drift_dt": ([_P, S, _P, C.c_int32, _P], C.c_int),
+            "tsph_carry_bytes": ([C.c_int64, C.POINTER(C.c_size_t)], C.c_int),
+            "tsph_carry_save": ([_P, C.c_int64, _P, _P], C.c_int),
+            "tsph_carry_load": ([_P, C.c_int64, _P, _P], C.c_int),
             "tsph_timestep": ([_P, S, _P, _P], C.c_int),
             "tsph_diagnostics": ([_P, S, _P, _P], C.c_int),
             "tsph_read_flags": ([_P, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)], C.c_int),
@@ -95,8 +98,8 @@ def lib():
 
 
 EXPORTED = ("tsph_create", "tsph_destroy", "tsph_set_params", "tsph_default_params", "tsph_bytes_required",
-            "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_kick_drift_dt", "tsph_timestep",
-            "tsph_diagnostics", "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
+            "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_kick_drift_dt", "tsph_carry_bytes",
+            "tsph_carry_save", "tsph_carry_load", "tsph_timestep", "tsph_diagnostics", "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
             "tsph_timing", "tsph_phase_times")
 PHASES = ("tree", "density", "gravity", "sph", "finish")
 
@@ -171,6 +174,20 @@ def tsph_kick_drift(ctx, st: State, dt: float, phase: int, stream=None):
 def tsph_kick_drift_dt(ctx, st: State, dt_ptr: int, phase: int, stream=None):
     _check("tsph_kick_drift_dt",
            lib().tsph_kick_drift_dt(ctx, C.byref(st), C.c_void_p(dt_ptr), int(phase), _stream(stream)), ctx)
+
+
+def tsph_carry_bytes(n: int) -> int:
+    b = C.c_size_t(0)
+    _check("tsph_carry_bytes", lib().tsph_carry_bytes(int(n), C.byref(b)))
+    return int(b.value)
+
+
+def tsph_carry_save(ctx, n: int, dst_ptr: int, stream=None):
+    _check("tsph_carry_save", lib().tsph_carry_save(ctx, int(n), C.c_void_p(dst_ptr), _stream(stream)), ctx)
+
+
+def tsph_carry_load(ctx, n: int, src_ptr: int, stream=None):
+    _check("tsph_carry_load", lib().tsph_carry_load(ctx, int(n), C.c_void_p(src_ptr), _stream(stream)), ctx)
 
 
 def tsph_timestep(ctx, st: State, dt_ptr: int, stream=None):
@@ -286,6 +303,20 @@ class Simulation:
         self.kick_drift(dt, KD_FIRST, stream)
         self.compute_forces(stream)
         self.kick_drift(dt, KD_SECOND, stream)
+
+    def carry(self):
+        """Host copy of the context's carry to the next step (see tsph_carry_save)."""
+        torch = self.torch
+        buf = torch.empty(tsph_carry_bytes(self.n) // 8, dtype=torch.float64, device=self.a["x"].device)
+        tsph_carry_save(self.ctx, self.n, buf.data_ptr())
+        torch.cuda.current_stream().synchronize()
+        return buf.cpu().numpy()
+
+    def load_carry(self, host):
+        torch = self.torch
+        buf = torch.from_numpy(host).to(self.a["x"].device)
+        tsph_carry_load(self.ctx, self.n, buf.data_ptr())
+        torch.cuda.current_stream().synchronize()
 
     def device_step(self, stream=None):
         """One KDK step with the global time-step taken and used on the device
