@@ -386,6 +386,221 @@ __device__ SolveOut solve_length(const DensArgs &A, int g, const NodeBox &gb, bo
   return o;
 }
 
+// ---- both lengths of a sink in one pass: the smoothing length over gas
+// neighbours (gas sinks) and the softening length over all neighbours (all
+// sinks) share the candidate walk and the staged tiles, each keeping the
+// Newton iteration of solve_length.
+
+// the sums each length needs: the gas one n, dn/dh, rho, mass-weighted
+// dW/dh and div v; the softening one n, dn/deps, mass-weighted d phi/d eps
+// and div v (kept in the same slots: rho <-> mdphi, msdh unused)
+struct Sums5 {
+  double n, sdh, rho, msdh, divv;
+};
+
+struct Solver {
+  double h, lo, hi, dx_old, rc, h_keep;
+  bool done, ok, solvable;
+  Sums5 keep;
+};
+
+__device__ __forceinline__ void solver_init(Solver &v, const DensArgs &A, bool sink, bool gas_only, double eta,
+                                            double guess, bool cold) {
+  const int64_t set_size = gas_only ? A.n_gas : A.n;
+  v.solvable = sink && ((double)set_size / kPi > eta * eta * eta) && (guess > 0.0);
+  v.h = guess > 0.0 ? (v.solvable && cold ? 0.5 * guess : guess) : 1.0;
+  v.lo = 0.0;
+  v.hi = INFINITY;
+  v.dx_old = INFINITY;
+  v.rc = v.h * (1.0 + A.kappa);
+  v.h_keep = v.h;
+  v.done = !sink;
+  v.ok = false;
+  v.keep = Sums5{0, 0, 0, 0, 0};
+}
+
+// one evaluation's sums into the solver
+__device__ __forceinline__ void solver_update(Solver &v, const DensArgs &A, const Sums5 &s, double eta) {
+  if (v.done) return;
+  v.keep = s;
+  v.h_keep = v.h;
+  if (!v.solvable) {
+    v.done = true;
+  } else if (newton_update(v.h, v.lo, v.hi, v.dx_old, s.n, s.sdh, eta * eta * eta, A.h_tol)) {
+    v.done = true;
+    v.ok = true;
+  }
+}
+
+// Per-lane sums of both lengths over the nt staged candidates (gas flag in
+// vu.w).  do_h / do_e: the solver still iterates.
+__device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T, int nt, double px, double py,
+                                           double pz, const double4 &vp, bool do_h, double hh, bool do_e, double he,
+                                           int32_t *dbg_row, int &ndbg, Sums5 &sh, Sums5 &se) {
+  const double ihh = 1.0 / hh, ihe = 1.0 / he;
+  const double ihh3 = ihh * ihh * ihh / kPi, ihe3 = ihe * ihe * ihe / kPi;
+  const double ihh4 = ihh3 * ihh, ihe4 = ihe3 * ihe;
+  const double R2h = do_h ? (2.0 * hh) * (2.0 * hh) : -1.0;
+  const double R2e = do_e ? (2.0 * he) * (2.0 * he) : -1.0;
+  for (int j = 0; j < nt; j++) {
+    const double4 a = T.pm[j];
+    const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+    const double4 v = T.vu[j];
+    const bool in_h = r2 < R2h && v.w != 0.0;
+    const bool in_e = r2 < R2e;
+    if (!(in_h || in_e)) continue;
+    const double r = r2 > 0.0 ? r2 * rsqrt(r2) : 0.0;
+    const double dot = (vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z);
+    if (in_h) {
+      if (dbg_row) {
+        if (ndbg < A.dbg_max) dbg_row[ndbg] = A.perm[T.q[j]];
+        ndbg++;
+      }
+      const double qq = r * ihh;
+      double w, dw;
+      m4(qq, w, dw);
+      const double W = w * ihh3;
+      const double dWdh = -(3.0 * w + qq * dw) * ihh4;
+      sh.n += W;
+      sh.sdh += dWdh;
+      sh.rho += a.w * W;
+      sh.msdh += a.w * dWdh;
+      if (r > 0.0) sh.divv += dw * ihh4 * (ihh / qq) * dot;
+    }
+    if (in_e) {
+      const double qq = r * ihe;
+      double w, dw;
+      m4(qq, w, dw);
+      const double W = w * ihe3;
+      se.n += W;
+      se.sdh += -(3.0 * w + qq * dw) * ihe4;
+      se.rho += a.w * soft_pe_q(qq, ihe);  // mass-weighted d phi / d eps
+      if (r > 0.0) se.divv += dw * ihe4 * (ihe / qq) * dot;
+    }
+  }
+}
+
+__device__ __forceinline__ void stage_tile2(const DensArgs &A, DensTile &T, int nt, int q) {
+  const int ln = lane();
+  if (ln < nt) {
+    T.pm[ln] = A.pm[q];
+    double4 v = A.vu[q];
+    v.w = A.gas[q] ? 1.0 : 0.0;
+    T.vu[ln] = v;
+    T.q[ln] = q;
+  }
+  __syncthreads();
+}
+
+__device__ void leaf_sums2(const DensArgs &A, int nleaf, const int *s_leaf, DensTile &T, double px, double py,
+                           double pz, const double4 &vp, bool do_h, double hh, bool do_e, double he, int32_t *dbg_row,
+                           int &ndbg, Sums5 &sh, Sums5 &se) {
+  const int ln = lane();
+  int fill = 0, rq = 0;
+  for (int c1 = 0; c1 < nleaf; c1 += kWave) {
+    const int nc = min(kWave, nleaf - c1);
+    const NodeTopo my = ln < nc ? A.topo[s_leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
+    for (int j = 0; j < nc; j++) {
+      const int first = __builtin_amdgcn_readlane(my.first, j);
+      const int count = __builtin_amdgcn_readlane(my.count, j);
+      for (int off = 0; off < count;) {
+        const int tk = min(count - off, kWave - fill);
+        if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
+        fill += tk;
+        off += tk;
+        if (fill == kWave) {
+          stage_tile2(A, T, kWave, rq);
+          tile_sums2(A, T, kWave, px, py, pz, vp, do_h, hh, do_e, he, dbg_row, ndbg, sh, se);
+          __syncthreads();
+          fill = 0;
+        }
+      }
+    }
+  }
+  if (fill > 0) {
+    stage_tile2(A, T, fill, rq);
+    tile_sums2(A, T, fill, px, py, pz, vp, do_h, hh, do_e, he, dbg_row, ndbg, sh, se);
+    __syncthreads();
+  }
+}
+
+struct BothOut {
+  SolveOut h, e;
+  bool handed;
+};
+
+__device__ BothOut solve_both(const DensArgs &A, int g, const NodeBox &gb, bool act, bool is_gas, double guess_h,
+                              bool cold_h, double guess_e, bool cold_e, double px, double py, double pz,
+                              const double4 &vp, int *s_stack, int *s_leaf, DensTile &T, double4 *s_snk,
+                              int32_t *dbg_row) {
+  BothOut o;
+  o.handed = false;
+  Solver H, E;
+  solver_init(H, A, is_gas, true, A.eta_h, guess_h, cold_h);
+  solver_init(E, A, act, false, A.eta_eps, guess_e, cold_e);
+  bool fail = false, gathered = false;
+  Cands c{0, true, 0.0, false};
+  int ndbg_keep = 0, ndbg_max = 0;
+  for (int it = 0; it < A.maxit && __any(!H.done || !E.done); it++) {
+    bool need = !gathered;
+    if (!H.done && H.h > H.rc) {
+      H.rc = H.h * (1.0 + A.kappa);
+      need = true;
+    }
+    if (!E.done && E.h > E.rc) {
+      E.rc = E.h * (1.0 + A.kappa);
+      need = true;
+    }
+    if (__any(need)) {
+      const double rad = fmax(H.done ? 0.0 : 2.0 * H.rc, E.done ? 0.0 : 2.0 * E.rc);
+      const double R = wave_max(rad);
+      s_snk[lane()] = make_double4(px, py, pz, rad);
+      __syncthreads();
+      c = gather(A, gb, R, false, s_stack, s_leaf, s_snk, fail);
+      gathered = true;
+      if (fail) break;
+      if ((!c.cached || c.nleaf > A.split_leaves) && hand_off(A, g)) {
+        o.handed = true;
+        return o;
+      }
+    }
+    Sums5 sh{0, 0, 0, 0, 0}, se{0, 0, 0, 0, 0};
+    int ndbg = 0;
+    int32_t *drow = H.done ? nullptr : dbg_row;
+    if (c.cached) {
+      leaf_sums2(A, c.nleaf, s_leaf, T, px, py, pz, vp, !H.done, H.h, !E.done, E.h, drow, ndbg, sh, se);
+    } else {
+      const bool ok = walk_leaves(A, gb, c.R, false, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
+        leaf_sums2(A, nl, s_leaf, T, px, py, pz, vp, !H.done, H.h, !E.done, E.h, drow, ndbg, sh, se);
+        return true;
+      });
+      if (!ok) {
+        fail = true;
+        break;
+      }
+    }
+    if (!H.done) {
+      ndbg_keep = ndbg;
+      ndbg_max = max(ndbg_max, ndbg);
+    }
+    solver_update(H, A, sh, A.eta_h);
+    solver_update(E, A, se, A.eta_eps);
+  }
+  if (dbg_row) {
+    for (int k = ndbg_keep; k < min(ndbg_max, A.dbg_max); k++) dbg_row[k] = -1;
+    if (ndbg_keep > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
+  }
+  o.h.h = H.h_keep;
+  o.h.s = Sums{H.keep.n, H.keep.sdh, H.keep.rho, H.keep.msdh, 0.0, H.keep.divv};
+  o.h.ok = H.ok && !fail;
+  o.h.handed = false;
+  o.e.h = E.h_keep;
+  o.e.s = Sums{E.keep.n, E.keep.sdh, 0.0, 0.0, E.keep.rho, E.keep.divv};
+  o.e.ok = E.ok && !fail;
+  o.e.handed = false;
+  return o;
+}
+
 __device__ __forceinline__ double cold_guess(const DensArgs &A, int p, bool gas_only, double eta) {
   int k = A.leaf_of[p];
   NodeTopo nd = A.topo[k];
@@ -440,7 +655,10 @@ __device__ __forceinline__ void store_outputs(const DensArgs &A, int p, bool is_
   S[kDivvE * A.cap_n + p] = divve;
 }
 
-__global__ __launch_bounds__(64) void k_density(DensArgs A) {
+// kFused: gas and softening lengths solved together (independent solves,
+// both species); otherwise one or the other (or one shared) separately.
+template <bool kFused>
+__global__ __launch_bounds__(64, 2) void k_density(DensArgs A) {
   __shared__ int s_stack[kDensStackCap];
   __shared__ int s_leaf[kDensLeafCap];
   __shared__ double4 s_snk[kWave];
@@ -473,7 +691,23 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
       oh.ok = true;
       oh.handed = false;
       oh.s = Sums{0, 0, 0, 0, 0, 0};
-      if (A.hydro) {
+      // both lengths solved in one pass when they are independent
+      constexpr bool fused = kFused;
+      SolveOut oe_f;
+      if constexpr (kFused) {
+        const double gh = A.hs[p], ge = A.es[p];
+        const double guess_h = gh > 0.0 ? gh : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
+        const double guess_e = ge > 0.0 ? ge : (act ? cold_guess(A, p, false, A.eta_eps) : 0.0);
+        const BothOut b = solve_both(A, g, gb, act, is_gas, guess_h, !(gh > 0.0), guess_e, !(ge > 0.0), a.x, a.y,
+                                     a.z, vp, s_stack, s_leaf, s_dt, s_snk, is_gas ? dbg0 : nullptr);
+        handed = b.handed;
+        oh = b.h;
+        oe_f = b.e;
+        if (!handed) {
+          if (is_gas && !oh.ok) nnoconv++;
+          if (act && !oe_f.ok) nnoconv++;
+        }
+      } else if (A.hydro) {  // (not kFused)
         double g0 = A.hs[p];
         double guess = g0 > 0.0 ? g0 : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
         oh = solve_length(A, g, gb, is_gas, true, A.eta_h, guess, a.x, a.y, a.z, vp, true, A.shared != 0,
@@ -483,7 +717,14 @@ __global__ __launch_bounds__(64) void k_density(DensArgs A) {
       }
       // ---- softening length over all neighbours (all sinks) ----
       double eps = 0.0, neps = 0.0, ups = 1.0, xi = 0.0, divve = 0.0;
-      if (A.gravity && !handed) {
+      if constexpr (fused) {
+        if (handed) break;
+        eps = oe_f.h;
+        neps = oe_f.s.n;
+        ups = 1.0 + (oe_f.h / (3.0 * oe_f.s.n)) * oe_f.s.sdh;
+        xi = (A.soft_mode == TSPH_SOFT_ADAPTIVE) ? -(oe_f.h / (3.0 * oe_f.s.n)) * oe_f.s.mdphi : 0.0;
+        divve = -oe_f.s.divv / (oe_f.s.n * ups);
+      } else if (A.gravity && !handed) {
         if (A.soft_mode == TSPH_SOFT_CONSTANT) {
           eps = A.es[p];
         } else if (A.shared) {
@@ -761,7 +1002,9 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
   // debug lists are written by the batch's own wave
   A.heavy_cap = (c->dbg_nbr || c->p.split_leaves == 0) ? 0 : (int32_t)c->heavy_cap;
   A.split_leaves = c->p.split_leaves;
-  hipLaunchKernelGGL(k_density, dim3(persistent_blocks(c, (const void *)k_density)), dim3(64), 0, st, A);
+  const bool fused = A.hydro && A.gravity && !A.shared && A.soft_mode != TSPH_SOFT_CONSTANT;
+  void (*kd)(DensArgs) = fused ? k_density<true> : k_density<false>;
+  hipLaunchKernelGGL(kd, dim3(persistent_blocks(c, (const void *)kd)), dim3(64), 0, st, A);
   if (A.heavy_cap > 0)
     hipLaunchKernelGGL(k_density_sink, dim3(persistent_blocks(c, (const void *)k_density_sink)), dim3(64), 0, st,
                        A);
