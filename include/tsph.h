@@ -141,7 +141,7 @@ tsph_status tsph_destroy(void *ctx);
 tsph_status tsph_set_params(void *ctx, const tsph_params *p);
 /* Fill p with the defaults: G=1, theta=0.5, quadrupoles, adaptive softening,
  * 50 neighbours, gamma=5/3, alpha=1, beta=2, av_eps2=0.01, TC92 on,
- * h_tol=1e-10, kappa=0.1, leaf 16, group 64, eta_dt=0.1, split_leaves 512. */
+ * h_tol=1e-10, kappa=0.1, leaf 16, group 64, eta_dt=0.1, split_leaves 256. */
 void tsph_default_params(tsph_params *p);
 /* Device bytes a context of this capacity reserves (host-only, no GPU). */
 tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t *bytes);

@@ -190,7 +190,7 @@ void tsph_default_params(tsph_params *p) {
   p->gravity = 1;
   p->hydro = 1;
   p->eta_dt = 0.1;
-  p->split_leaves = 512;
+  p->split_leaves = 256;
 }
 
 tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t *bytes) {

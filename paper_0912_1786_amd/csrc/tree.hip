@@ -19,9 +19,17 @@ int blocks_for(int64_t n, int threads, int max_blocks) {
   return (int)b;
 }
 
+// Workgroups of a persistent walk kernel: what the device holds at once,
+// but no more than one per 16 particles (walk batches hold ~45 on average),
+// so that small systems leave the device to work running beside them.
+static int persistent_cap(const Ctx *c, int blocks) {
+  const int64_t cap = c->n / 16 + 1;
+  return cap < blocks ? (int)cap : blocks;
+}
+
 int persistent_blocks(Ctx *c, const void *kernel) {
   for (int i = 0; i < 16; i++)
-    if (c->occ_kernel[i] == kernel) return c->occ_blocks[i];
+    if (c->occ_kernel[i] == kernel) return persistent_cap(c, c->occ_blocks[i]);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess || per_cu < 1) {
     (void)hipGetLastError();
@@ -34,7 +42,7 @@ int persistent_blocks(Ctx *c, const void *kernel) {
       c->occ_blocks[i] = blocks;
       break;
     }
-  return blocks;
+  return persistent_cap(c, blocks);
 }
 
 // ---------------------------------------------------------------------------
