@@ -955,6 +955,11 @@ static void gravity_group_walk(ctx_t *C)
       }
       int64_t pfirst = t->first[k0];
       int64_t pend = t->first[kl] + t->count[kl];
+      /* with a sink sample, only batches holding a sampled sink are walked
+       * (the lists are the batch's, so their values are those of a full run) */
+      int any = 0;
+      for (int64_t p = pfirst; p < pend && !any; p++) any = C->active[p];
+      if (!any) continue;
       int64_t na = 0, nl = 0, sp = 0;
       stack[sp++] = 0;
       while (sp > 0) {
@@ -964,6 +969,7 @@ static void gravity_group_walk(ctx_t *C)
         else for (int32_t b = t->nchild[k] - 1; b >= 0; b--) stack[sp++] = t->child[k] + b;
       }
       for (int64_t p = pfirst; p < pend; p++) {
+        if (!C->active[p]) continue;
         double a[3] = {0, 0, 0}, pot = 0.0;
         int64_t npair = 0;
         double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
@@ -1159,7 +1165,6 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   C.iters = calloc(n, sizeof(int32_t));
   C.active = malloc(n);
   if (r->n_sinks > 0) {
-    if (p->walk_mode == ORC_WALK_GROUP) { orc_tree_free(t); return -1; }
     int64_t *inv = malloc(n * sizeof(int64_t));
     for (int64_t q = 0; q < n; q++) inv[t->perm[q]] = q;
     memset(C.active, 0, n);

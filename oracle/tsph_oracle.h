@@ -75,7 +75,8 @@ typedef struct {
   int32_t *iters;                                  /* Newton passes per particle */
   int64_t n_noconv;                                /* out: unsolved lengths      */
   /* optional sink sample (caller indices): when n_sinks > 0 the gravity and
-   * SPH passes run for these sinks only (per-particle or direct walk); the
+   * SPH passes run for these sinks only (any walk mode; the batch walk visits
+   * only the batches holding a sampled sink); the
    * length solves still cover every particle */
   const int64_t *sinks;
   int64_t n_sinks;

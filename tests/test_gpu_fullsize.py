@@ -1,0 +1,69 @@
+"""Parity at the benchmark's full size and launch configuration: the
+two-species field with 1,048,576 gas + 1,048,576 dark-matter particles,
+theta = 0.5, quadrupoles, 60 neighbours, leaf 16, walk groups of 64, the
+default load-balancing threshold, in both arithmetic forms.
+
+The oracle solves every length (so h, eps and rho are compared for every
+particle) and evaluates gravity and SPH for a seeded sample of 2048 sinks
+with the same batch walk, and the direct sum for 512 of them.  Bars: h, eps
+to 1e-9 relative, rho to 1e-6; accelerations within 1e-5 relative RMS of
+the oracle's walk and 2e-3 of the direct sum; du/dt within 1e-6; the
+interaction counts of the sampled sinks equal to the oracle's.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0912_1786_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # collected on CPU-only machines but never run there
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_0912_1786_amd import tsph  # noqa: E402
+
+from gpu_common import acc, gpu_params, maxrel, oracle_params, relrms, run_gpu  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_two_species_field_2m_both_forms():
+    from oracle import oracle as O
+    ic = inputs.two_species_field(n_dm=1 << 20, n_gas=1 << 20, n_halo=64, seed=1)
+    n, n_gas = ic["n"], ic["n_gas"]
+    runs = {}
+    for name, prec in (("fp64", tsph.FP64), ("fp32_bulk", tsph.FP32_BULK)):
+        _say(f"[fullsize] GPU {name}")
+        gp = gpu_params(nnei=60, leaf_size=16, group_size=64, precision=prec)
+        sim, g = run_gpu(ic, gp)
+        sim.close()
+        assert g["flags"] == 0 and g["noconv"] == 0
+        runs[name] = (gp, g)
+    rng = np.random.default_rng(2024)
+    sinks = np.sort(rng.choice(n, 2048, replace=False))
+    gp = runs["fp64"][0]
+    _say("[fullsize] oracle: all lengths, batch walk for 2048 sinks")
+    o = O.compute_forces(ic, oracle_params(O, gp), sinks=sinks)
+    _say("[fullsize] oracle: direct sum for 512 sinks")
+    dsinks = sinks[::4]
+    od = O.compute_forces(ic, oracle_params(O, gp, walk_mode=O.WALK_DIRECT), sinks=dsinks)
+    gas = np.arange(n) < n_gas
+    gs = sinks[sinks < n_gas]
+    for name, (gp_, g) in runs.items():
+        eh, er, ee = maxrel(g["h"], o["h"], gas), maxrel(g["rho"], o["rho"], gas), maxrel(g["eps"], o["eps"])
+        ea = relrms(acc(g)[sinks], acc(o)[sinks])
+        ed = relrms(acc(g)[dsinks], acc(od)[dsinks])
+        eu = relrms(g["dudt"][gs], o["dudt"][gs])
+        _say(f"    {name}: h {eh:.2e} rho {er:.2e} eps {ee:.2e}; acc vs walk {ea:.2e}, vs direct {ed:.2e}; "
+             f"du/dt {eu:.2e}")
+        assert eh < 1e-9 and ee < 1e-9 and er < 1e-6
+        assert ea < 1e-5 and ed < 2e-3 and eu < 1e-6
+        assert np.array_equal(g["cnt_node"][sinks], o["cnt_node"][sinks])
+        assert np.array_equal(g["cnt_pair"][sinks], o["cnt_pair"][sinks])
+        assert np.array_equal(g["cnt_sph"][gs], o["cnt_sph"][gs])
