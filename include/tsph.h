@@ -110,6 +110,8 @@ typedef struct {
                           * solved one sink per wavefront, the lanes sharing
                           * the sink's candidates.                            */
   double eta_dt;       /* time-step coefficient of the Sect. 4.2 criteria      */
+  int32_t max_members; /* independent systems one context can hold
+                          * (tsph_set_members); 1 by default                  */
 } tsph_params;
 
 typedef struct {
@@ -141,10 +143,28 @@ tsph_status tsph_destroy(void *ctx);
 tsph_status tsph_set_params(void *ctx, const tsph_params *p);
 /* Fill p with the defaults: G=1, theta=0.5, quadrupoles, adaptive softening,
  * 50 neighbours, gamma=5/3, alpha=1, beta=2, av_eps2=0.01, TC92 on,
- * h_tol=1e-10, kappa=0.1, leaf 16, group 64, eta_dt=0.1, split_leaves 256. */
+ * h_tol=1e-10, kappa=0.1, leaf 16, group 64, eta_dt=0.1, split_leaves 256,
+ * max_members 1. */
 void tsph_default_params(tsph_params *p);
 /* Device bytes a context of this capacity reserves (host-only, no GPU). */
 tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t *bytes);
+
+/* Several independent systems in one context (an ensemble advanced by the
+ * same calls).  The state then holds them back to back: system k owns
+ * particles [off[k], off[k+1]) with its gas first, [off[k], off[k] + n_gas[k]);
+ * the state's n and n_gas must equal off[count] and the sum of n_gas, or the
+ * calls fail with TSPH_EINVAL.  Each system gets its own root cube and tree
+ * (the trees form one forest: one sort segmented by system, one walk launch
+ * over the walk batches of all of them), its own neighbour sets and its own
+ * time-step; nothing couples two systems, so each system's results are those
+ * it would get in a context of its own with the same parameters, as long as
+ * that context would take the same kernel form: the form follows the whole
+ * context (gas present, all particles gas).  off and n_gas are host arrays
+ * (count + 1 and count entries) copied by the call; count must not exceed
+ * max_members; every system needs at least one particle.  count = 1 returns
+ * to the single-system default, in which a state of any size is taken.
+ * Synchronous (not for a captured stream). */
+tsph_status tsph_set_members(void *ctx, int32_t count, const int64_t *off, const int64_t *n_gas);
 
 /* Root cube, Morton keys, radix sort, gather into key order, canonical
  * oct-tree in level order and node moments (Sect. 2.2). */
@@ -161,9 +181,9 @@ tsph_status tsph_compute_forces(void *ctx, tsph_state *s, void *stream);
  * factor clamped to [1/2, 2].  They are starting values for the next solve.
  * TSPH_KD_SECOND: v += dt/2 a, u += dt/2 du/dt. */
 tsph_status tsph_kick_drift(void *ctx, tsph_state *s, double dt, int32_t phase, void *stream);
-/* The same with dt read on the device from dt_device (one double, e.g. the
- * output of tsph_timestep), so that a captured HIP graph replays with the
- * current time-step.  dt_device must stay valid while the work runs; a
+/* The same with dt read on the device from dt_device (one double per
+ * system held, e.g. the output of tsph_timestep), so that a captured HIP
+ * graph replays with the current time-step.  dt_device must stay valid while the work runs; a
  * negative or non-finite value there makes the kernel do nothing (the
  * state is left unchanged). */
 tsph_status tsph_kick_drift_dt(void *ctx, tsph_state *s, const double *dt_device, int32_t phase, void *stream);
@@ -174,16 +194,18 @@ tsph_status tsph_kick_drift_dt(void *ctx, tsph_state *s, const double *dt_device
  * the device between steps and continue bit for bit: after tsph_carry_load
  * the next tsph_timestep / tsph_kick_drift behave as if the force pass had
  * run on that context.  Both are stream-ordered device-to-device copies;
- * save fails with TSPH_EINVAL when the last force pass had a different n. */
+ * save fails with TSPH_EINVAL when the last force pass had a different n.
+ * Only for a context holding one system (TSPH_EINVAL otherwise). */
 tsph_status tsph_carry_bytes(int64_t n, size_t *bytes);
 tsph_status tsph_carry_save(void *ctx, int64_t n, void *dst_device, void *stream);
 tsph_status tsph_carry_load(void *ctx, int64_t n, const void *src_device, void *stream);
 /* Global time-step (Sect. 4.2) from the last tsph_compute_forces: min over
  * particles of eta_dt sqrt(min(eps,h)/|a|), the Courant criterion and
- * eta_dt |u / du/dt|.  Writes one double to dt_device. */
+ * eta_dt |u / du/dt|.  Writes one double per system held to dt_device. */
 tsph_status tsph_timestep(void *ctx, const tsph_state *s, double *dt_device, void *stream);
 /* FP64 totals: out_device[0..8] = E_kin, E_th, V (= 1/2 sum m pot), Px, Py,
- * Pz, Lx, Ly, Lz.  Needs s->pot from the last force pass. */
+ * Pz, Lx, Ly, Lz; nine per system held (system k at out_device[9k]).
+ * Needs s->pot from the last force pass. */
 tsph_status tsph_diagnostics(void *ctx, const tsph_state *s, double *out_device, void *stream);
 /* Synchronise the context's last stream and return the OR of the device flag
  * bits since the previous call (then clear them); n_noconv receives the
@@ -212,7 +234,7 @@ enum { TSPH_DBG_KEYS = 0,      /* uint64[n] sorted Morton keys                  
        TSPH_DBG_COUNTS = 7,    /* int32[3][n] (caller order) far nodes, near pairs,    *
                                 * SPH pairs per particle in the last force pass        */
        TSPH_DBG_NBR = 8,       /* int32[3][n][max] neighbour lists, see below          */
-       TSPH_DBG_ROOT = 9,      /* double[4] x0, y0, z0, side                            */
+       TSPH_DBG_ROOT = 9,      /* double[4] x0, y0, z0, side (of the first system)     */
        TSPH_DBG_SOLVE = 10,    /* double[9][n] (caller order) nh, omega, zeta, divv,   *
                                 * neps, ups, xi, maxmu, divv with the eps kernel        */
        TSPH_DBG_BATCHES = 11,  /* int32[nbatches][2] walk batches: group-list ranges   *

@@ -17,6 +17,7 @@ tsph_status tsph_impl_refresh(Ctx *c, hipStream_t st);
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxMembers = 65535;  // members are a grid dimension of the per-member reductions
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -51,13 +52,14 @@ const char *param_error(const tsph_params *p) {
   if (!(p->G > 0.0)) return "G must be > 0";
   if (!(p->eta_dt > 0.0)) return "eta_dt must be > 0";
   if (p->split_leaves < 0) return "split_leaves must be >= 0";
+  if (p->max_members < 1 || p->max_members > kMaxMembers) return "max_members must be in [1, 65535]";
   return nullptr;
 }
 
-size_t layout_bytes(int64_t N, int64_t M, Layout *L) {
+size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->k = 0;
   L->total = 0;
-  int64_t sort_blocks = (N + kSortTile - 1) / kSortTile + 1;
+  int64_t sort_blocks = (N + kSortTile - 1) / kSortTile + 1 + S;
   int64_t scan_blocks = (std::max<int64_t>(std::max<int64_t>(N, M), sort_blocks * kSortBins) + kScanTile - 1) /
                             kScanTile + 16;
   // particles
@@ -101,8 +103,11 @@ size_t layout_bytes(int64_t N, int64_t M, Layout *L) {
   L->add(4 * M);                                // split_head
   L->add(4 * heavy_batch_cap(M));               // heavy
   // small
-  L->add(sizeof(DevRoot));           // 27 root
-  L->add(8 * 6 * 512);               // 28 bbox_part
+  L->add(8 * (S + 1));               // moff
+  L->add(8 * S);                     // mgas
+  L->add(4 * (S + 1));               // mtile
+  L->add(sizeof(DevRoot) * S);       // 27 root
+  L->add(8 * 6 * std::max<int64_t>(512, kMemberBlocks * S));  // 28 bbox_part
   L->add(4 * 64);                    // 29 lvl
   L->add(4 * 16);                    // 30 ngroups
   L->add(4 * kSortBins * sort_blocks);  // 31 hist
@@ -110,8 +115,8 @@ size_t layout_bytes(int64_t N, int64_t M, Layout *L) {
   L->add(4 * kWorkCounters);         // 33 work
   L->add(4 * 16);                    // 34 flags
   L->add(4 * 16);                    // 35 noconv
-  L->add(8 * 9 * 1024);              // 36 red
-  L->add(8 * 16);                    // 37 dt
+  L->add(8 * 9 * std::max<int64_t>(1024, kMemberBlocks * S));  // 36 red
+  L->add(8 * std::max<int64_t>(16, S));                         // 37 dt
   return L->total;
 }
 
@@ -133,6 +138,8 @@ tsph_status create_fail(Ctx *c, tsph_status s, const char *what, hipError_t e) {
   if (c) {
     if (c->h_flags) (void)hipHostFree(c->h_flags);
     if (c->arena) (void)hipFree(c->arena);
+    free(c->h_moff);
+    free(c->h_mgas);
     delete c;
   }
   return s;
@@ -143,11 +150,22 @@ tsph_status set_err(Ctx *c, tsph_status s, const char *msg) {
   return s;
 }
 
+// a context holding several members takes only states of their total size
+tsph_status check_members(Ctx *c, const tsph_state *s) {
+  if (c->nmem <= 1) return TSPH_OK;
+  int64_t ng = 0;
+  for (int k = 0; k < c->nmem; k++) ng += c->h_mgas[k];
+  if (s->n != c->h_moff[c->nmem] || s->n_gas != ng)
+    return set_err(c, TSPH_EINVAL, "n and n_gas must be the members' totals (tsph_set_members)");
+  return TSPH_OK;
+}
+
 tsph_status check_state(Ctx *c, const tsph_state *s, bool forces) {
   if (!s) return set_err(c, TSPH_EINVAL, "state is NULL");
   if (s->n < 1) return set_err(c, TSPH_EINVAL, "n must be >= 1");
   if (s->n > c->cap_n) return set_err(c, TSPH_ECAPACITY, "n exceeds the context capacity");
   if (s->n_gas < 0 || s->n_gas > s->n) return set_err(c, TSPH_EINVAL, "n_gas must be in [0, n]");
+  if (tsph_status r = check_members(c, s)) return r;
   if (!s->x || !s->y || !s->z || !s->m) return set_err(c, TSPH_EINVAL, "x, y, z, m are required");
   if (forces) {
     if (!s->ax || !s->ay || !s->az) return set_err(c, TSPH_EINVAL, "ax, ay, az are required");
@@ -191,13 +209,14 @@ void tsph_default_params(tsph_params *p) {
   p->hydro = 1;
   p->eta_dt = 0.1;
   p->split_leaves = 256;
+  p->max_members = 1;
 }
 
 tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t *bytes) {
   if (!bytes || capacity_n < 1) return TSPH_EINVAL;
   if (param_error(p)) return TSPH_EINVAL;
   Layout L;
-  *bytes = layout_bytes(capacity_n, node_capacity(capacity_n, p->leaf_size), &L);
+  *bytes = layout_bytes(capacity_n, node_capacity(capacity_n, p->leaf_size), p->max_members, &L);
   return TSPH_OK;
 }
 
@@ -223,7 +242,12 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e != hipSuccess) return create_fail(c, TSPH_EHIP, "hipDeviceGetAttribute", e);
   Layout L;
-  size_t bytes = layout_bytes(c->cap_n, c->cap_nodes, &L);
+  c->cap_mem = p->max_members;
+  c->nmem = 1;
+  c->h_moff = (int64_t *)calloc((size_t)c->cap_mem + 1, sizeof(int64_t));
+  c->h_mgas = (int64_t *)calloc((size_t)c->cap_mem, sizeof(int64_t));
+  if (!c->h_moff || !c->h_mgas) return create_fail(c, TSPH_ENOMEM, "member tables", hipSuccess);
+  size_t bytes = layout_bytes(c->cap_n, c->cap_nodes, c->cap_mem, &L);
   e = hipMalloc(&c->arena, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -273,6 +297,9 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->split_cap = split_item_cap(c->cap_nodes);
   c->heavy = AT(int32_t *);
   c->heavy_cap = heavy_batch_cap(c->cap_nodes);
+  c->moff = AT(int64_t *);
+  c->mgas = AT(int64_t *);
+  c->mtile = AT(int32_t *);
   c->root = AT(DevRoot *);
   c->bbox_part = AT(double *);
   c->lvl = AT(int32_t *);
@@ -312,7 +339,39 @@ tsph_status tsph_destroy(void *ctx) {
   }
   if (c->h_flags) (void)hipHostFree(c->h_flags);
   if (c->arena) (void)hipFree(c->arena);
+  free(c->h_moff);
+  free(c->h_mgas);
   delete c;
+  return TSPH_OK;
+}
+
+tsph_status tsph_set_members(void *ctx, int32_t count, const int64_t *off, const int64_t *n_gas) {
+  Ctx *c = (Ctx *)ctx;
+  if (!c) return TSPH_EINVAL;
+  if (count < 1 || count > c->cap_mem) return set_err(c, TSPH_ECAPACITY, "count must be in [1, max_members]");
+  if (!off || !n_gas) return set_err(c, TSPH_EINVAL, "off and n_gas are required");
+  if (off[0] != 0) return set_err(c, TSPH_EINVAL, "off[0] must be 0");
+  int64_t tiles = 0;
+  std::vector<int32_t> mt((size_t)count + 1);
+  for (int k = 0; k < count; k++) {
+    const int64_t nk = off[k + 1] - off[k];
+    if (nk < 1) return set_err(c, TSPH_EINVAL, "every member needs at least one particle");
+    if (n_gas[k] < 0 || n_gas[k] > nk) return set_err(c, TSPH_EINVAL, "n_gas[k] must be in [0, off[k+1] - off[k]]");
+    mt[k] = (int32_t)tiles;
+    tiles += (nk + kSortTile - 1) / kSortTile;
+  }
+  mt[count] = (int32_t)tiles;
+  if (off[count] > c->cap_n) return set_err(c, TSPH_ECAPACITY, "the members exceed the context capacity");
+  if (count > c->cap_nodes / 4) return set_err(c, TSPH_ECAPACITY, "too many members for the node capacity");
+  TSPH_HIP_CHECK(c, hipDeviceSynchronize());
+  TSPH_HIP_CHECK(c, hipMemcpy(c->moff, off, sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice));
+  TSPH_HIP_CHECK(c, hipMemcpy(c->mgas, n_gas, sizeof(int64_t) * count, hipMemcpyHostToDevice));
+  TSPH_HIP_CHECK(c, hipMemcpy(c->mtile, mt.data(), sizeof(int32_t) * (count + 1), hipMemcpyHostToDevice));
+  memcpy(c->h_moff, off, sizeof(int64_t) * (count + 1));
+  memcpy(c->h_mgas, n_gas, sizeof(int64_t) * count);
+  c->nmem = count;
+  c->sort_tiles = (int32_t)tiles;
+  c->pdiv_n = 0;
   return TSPH_OK;
 }
 
@@ -424,6 +483,7 @@ tsph_status tsph_phase_times(void *ctx, double *ms_out, int64_t *calls) {
 
 static tsph_status kick_drift_checks(Ctx *c, tsph_state *s, int32_t phase) {
   if (!s || s->n < 1 || s->n_gas < 0 || s->n_gas > s->n) return set_err(c, TSPH_EINVAL, "bad state sizes");
+  if (tsph_status r = check_members(c, s)) return r;
   if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->ax || !s->ay || !s->az)
     return set_err(c, TSPH_EINVAL, "x, v and a are required");
   if (s->n_gas > 0 && (!s->u || !s->dudt)) return set_err(c, TSPH_EINVAL, "gas needs u and dudt");
@@ -440,6 +500,7 @@ tsph_status tsph_carry_bytes(int64_t n, size_t *bytes) {
 tsph_status tsph_carry_save(void *ctx, int64_t n, void *dst_device, void *stream) {
   Ctx *c = (Ctx *)ctx;
   if (!c) return TSPH_EINVAL;
+  if (c->nmem > 1) return set_err(c, TSPH_EINVAL, "the carry covers a context holding one system");
   if (!dst_device) return set_err(c, TSPH_EINVAL, "dst_device is NULL");
   if (n < 1 || n != c->pdiv_n) return set_err(c, TSPH_EINVAL, "no force pass with this n to save");
   hipStream_t st = (hipStream_t)stream;
@@ -453,6 +514,7 @@ tsph_status tsph_carry_save(void *ctx, int64_t n, void *dst_device, void *stream
 tsph_status tsph_carry_load(void *ctx, int64_t n, const void *src_device, void *stream) {
   Ctx *c = (Ctx *)ctx;
   if (!c) return TSPH_EINVAL;
+  if (c->nmem > 1) return set_err(c, TSPH_EINVAL, "the carry covers a context holding one system");
   if (!src_device) return set_err(c, TSPH_EINVAL, "src_device is NULL");
   if (n < 1 || n > c->cap_n) return set_err(c, TSPH_ECAPACITY, "n exceeds the context capacity");
   hipStream_t st = (hipStream_t)stream;
@@ -500,6 +562,7 @@ tsph_status tsph_diagnostics(void *ctx, const tsph_state *s, double *out_device,
   if (!c || !out_device) return TSPH_EINVAL;
   if (!s || s->n < 1 || !s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->m)
     return set_err(c, TSPH_EINVAL, "diagnostics need x, v, m");
+  if (tsph_status r = check_members(c, s)) return r;
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
   return tsph_impl_diagnostics(c, s, out_device, st);

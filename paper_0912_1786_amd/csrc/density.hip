@@ -34,7 +34,8 @@ struct DensArgs {
   const NodeBox *nbox;
   const int32_t *nngas;
   const int32_t *nlevel;
-  const DevRoot *root;
+  const DevRoot *root;  // root cube of each member
+  Members mem;
   const double4 *pm;
   const double4 *vu;
   const uint8_t *gas;
@@ -71,12 +72,12 @@ struct Sums {
 // returns false to stop the walk.  Returns false if the walk was stopped or a
 // structural check failed.
 template <class V>
-__device__ bool walk_leaves(const DensArgs &A, const NodeBox &gb, double R, bool gas_only, int *s_stack,
+__device__ bool walk_leaves(const DensArgs &A, int root, const NodeBox &gb, double R, bool gas_only, int *s_stack,
                             int *s_leaf, const double4 *s_snk, int batch, V &&visit) {
   const int ln = lane();
   int nleaf = 0, sp = 1, rounds = 0;
   const int guard = *A.nnodes + 2;
-  if (ln == 0) s_stack[0] = 0;
+  if (ln == 0) s_stack[0] = root;
   __syncthreads();
   const double R2 = R * R;
   while (sp > 0) {
@@ -235,11 +236,11 @@ struct Cands {
   bool gas_only;
 };
 
-__device__ Cands gather(const DensArgs &A, const NodeBox &gb, double R, bool gas_only, int *s_stack, int *s_leaf,
+__device__ Cands gather(const DensArgs &A, int root, const NodeBox &gb, double R, bool gas_only, int *s_stack, int *s_leaf,
                         const double4 *s_snk, bool &fail) {
   Cands c{0, true, R, gas_only};
   bool full = false;
-  bool ok = walk_leaves(A, gb, R, gas_only, s_stack, s_leaf, s_snk, kDensLeafCap - kWave,
+  bool ok = walk_leaves(A, root, gb, R, gas_only, s_stack, s_leaf, s_snk, kDensLeafCap - kWave,
                         [&](int nl, bool last) {
                           if (!last) {
                             full = true;
@@ -258,7 +259,7 @@ __device__ Cands gather(const DensArgs &A, const NodeBox &gb, double R, bool gas
 }
 
 template <bool kFull>
-__device__ Sums pass(const DensArgs &A, const NodeBox &gb, const Cands &c, int *s_stack, int *s_leaf,
+__device__ Sums pass(const DensArgs &A, int root, const NodeBox &gb, const Cands &c, int *s_stack, int *s_leaf,
                      DensTile &T, const double4 *s_snk, double px, double py, double pz, const double4 &vp, double h,
                      bool want_div, bool want_phi, int32_t *dbg_row, int &ndbg, bool &fail) {
   Sums s{0, 0, 0, 0, 0, 0};
@@ -266,7 +267,7 @@ __device__ Sums pass(const DensArgs &A, const NodeBox &gb, const Cands &c, int *
   if (c.cached) {
     leaf_sums<kFull>(A, c.nleaf, s_leaf, T, c.gas_only, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
   } else {
-    bool ok = walk_leaves(A, gb, c.R, c.gas_only, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
+    bool ok = walk_leaves(A, root, gb, c.R, c.gas_only, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
       leaf_sums<kFull>(A, nl, s_leaf, T, c.gas_only, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
       return true;
     });
@@ -314,14 +315,14 @@ __device__ __forceinline__ bool hand_off(const DensArgs &A, int g) {
 }
 
 // One self-consistent length per lane (inactive lanes follow along).
-__device__ SolveOut solve_length(const DensArgs &A, int g, const NodeBox &gb, bool sink, bool gas_only, double eta,
+__device__ SolveOut solve_length(const DensArgs &A, int g, int root, const NodeBox &gb, bool sink, bool gas_only, double eta,
                                  double guess, double px, double py, double pz, double4 vp, bool want_div,
                                  bool want_phi, int *s_stack, int *s_leaf, DensTile &T, double4 *s_snk, bool cold,
                                  int32_t *dbg_row) {
   SolveOut o;
   o.handed = false;
   const double eta3 = eta * eta * eta;
-  const int64_t set_size = gas_only ? A.n_gas : A.n;
+  const int64_t set_size = gas_only ? A.nngas[root] : A.topo[root].count;
   const bool solvable = sink && ((double)set_size / kPi > eta3) && (guess > 0.0);
   bool fail = false;
   // Newton from the starting value (half the volume guess on a cold start);
@@ -349,7 +350,7 @@ __device__ SolveOut solve_length(const DensArgs &A, int g, const NodeBox &gb, bo
       const double R = wave_max(done ? 0.0 : 2.0 * rc);
       s_snk[lane()] = make_double4(px, py, pz, done ? 0.0 : 2.0 * rc);
       __syncthreads();
-      c = gather(A, gb, R, gas_only, s_stack, s_leaf, s_snk, fail);
+      c = gather(A, root, gb, R, gas_only, s_stack, s_leaf, s_snk, fail);
       gathered = true;
       if (fail) break;
       if ((!c.cached || c.nleaf > A.split_leaves) && hand_off(A, g)) {
@@ -358,7 +359,7 @@ __device__ SolveOut solve_length(const DensArgs &A, int g, const NodeBox &gb, bo
       }
     }
     int ndbg = 0;
-    const Sums s = pass<true>(A, gb, c, s_stack, s_leaf, T, s_snk, px, py, pz, vp, h, want_div, want_phi,
+    const Sums s = pass<true>(A, root, gb, c, s_stack, s_leaf, T, s_snk, px, py, pz, vp, h, want_div, want_phi,
                               done ? nullptr : dbg_row, ndbg, fail);
     if (fail) break;
     if (!done) {
@@ -404,9 +405,9 @@ struct Solver {
   Sums5 keep;
 };
 
-__device__ __forceinline__ void solver_init(Solver &v, const DensArgs &A, bool sink, bool gas_only, double eta,
+__device__ __forceinline__ void solver_init(Solver &v, const DensArgs &A, int root, bool sink, bool gas_only, double eta,
                                             double guess, bool cold) {
-  const int64_t set_size = gas_only ? A.n_gas : A.n;
+  const int64_t set_size = gas_only ? A.nngas[root] : A.topo[root].count;
   v.solvable = sink && ((double)set_size / kPi > eta * eta * eta) && (guess > 0.0);
   v.h = guess > 0.0 ? (v.solvable && cold ? 0.5 * guess : guess) : 1.0;
   v.lo = 0.0;
@@ -529,15 +530,15 @@ struct BothOut {
   bool handed;
 };
 
-__device__ BothOut solve_both(const DensArgs &A, int g, const NodeBox &gb, bool act, bool is_gas, double guess_h,
+__device__ BothOut solve_both(const DensArgs &A, int g, int root, const NodeBox &gb, bool act, bool is_gas, double guess_h,
                               bool cold_h, double guess_e, bool cold_e, double px, double py, double pz,
                               const double4 &vp, int *s_stack, int *s_leaf, DensTile &T, double4 *s_snk,
                               int32_t *dbg_row) {
   BothOut o;
   o.handed = false;
   Solver H, E;
-  solver_init(H, A, is_gas, true, A.eta_h, guess_h, cold_h);
-  solver_init(E, A, act, false, A.eta_eps, guess_e, cold_e);
+  solver_init(H, A, root, is_gas, true, A.eta_h, guess_h, cold_h);
+  solver_init(E, A, root, act, false, A.eta_eps, guess_e, cold_e);
   bool fail = false, gathered = false;
   Cands c{0, true, 0.0, false};
   int ndbg_keep = 0, ndbg_max = 0;
@@ -556,7 +557,7 @@ __device__ BothOut solve_both(const DensArgs &A, int g, const NodeBox &gb, bool 
       const double R = wave_max(rad);
       s_snk[lane()] = make_double4(px, py, pz, rad);
       __syncthreads();
-      c = gather(A, gb, R, false, s_stack, s_leaf, s_snk, fail);
+      c = gather(A, root, gb, R, false, s_stack, s_leaf, s_snk, fail);
       gathered = true;
       if (fail) break;
       if ((!c.cached || c.nleaf > A.split_leaves) && hand_off(A, g)) {
@@ -570,7 +571,7 @@ __device__ BothOut solve_both(const DensArgs &A, int g, const NodeBox &gb, bool 
     if (c.cached) {
       leaf_sums2(A, c.nleaf, s_leaf, T, px, py, pz, vp, !H.done, H.h, !E.done, E.h, drow, ndbg, sh, se);
     } else {
-      const bool ok = walk_leaves(A, gb, c.R, false, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
+      const bool ok = walk_leaves(A, root, gb, c.R, false, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
         leaf_sums2(A, nl, s_leaf, T, px, py, pz, vp, !H.done, H.h, !E.done, E.h, drow, ndbg, sh, se);
         return true;
       });
@@ -606,7 +607,7 @@ __device__ __forceinline__ double cold_guess(const DensArgs &A, int p, bool gas_
   NodeTopo nd = A.topo[k];
   double cnt = (double)nd.count;
   if (gas_only && A.nngas[k] > 0) cnt = (double)A.nngas[k];
-  double s = ldexp(A.root->side, -A.nlevel[k]);
+  double s = ldexp(A.root[member_of(A.mem, p)].side, -A.nlevel[k]);
   return eta * cbrt(s * s * s / cnt);
 }
 
@@ -673,7 +674,7 @@ __global__ __launch_bounds__(64, 2) void k_density(DensArgs A) {
     const int g = s_g;
     __syncthreads();
     if (g < 0) break;
-    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, g);
     const NodeTopo gnd{bt.first, bt.count, -1, 0};
     const NodeBox gb = bt.box;
     for (int c0 = 0; c0 < gnd.count; c0 += kWave) {
@@ -698,7 +699,7 @@ __global__ __launch_bounds__(64, 2) void k_density(DensArgs A) {
         const double gh = A.hs[p], ge = A.es[p];
         const double guess_h = gh > 0.0 ? gh : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
         const double guess_e = ge > 0.0 ? ge : (act ? cold_guess(A, p, false, A.eta_eps) : 0.0);
-        const BothOut b = solve_both(A, g, gb, act, is_gas, guess_h, !(gh > 0.0), guess_e, !(ge > 0.0), a.x, a.y,
+        const BothOut b = solve_both(A, g, bt.root, gb, act, is_gas, guess_h, !(gh > 0.0), guess_e, !(ge > 0.0), a.x, a.y,
                                      a.z, vp, s_stack, s_leaf, s_dt, s_snk, is_gas ? dbg0 : nullptr);
         handed = b.handed;
         oh = b.h;
@@ -710,7 +711,7 @@ __global__ __launch_bounds__(64, 2) void k_density(DensArgs A) {
       } else if (A.hydro) {  // (not kFused)
         double g0 = A.hs[p];
         double guess = g0 > 0.0 ? g0 : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
-        oh = solve_length(A, g, gb, is_gas, true, A.eta_h, guess, a.x, a.y, a.z, vp, true, A.shared != 0,
+        oh = solve_length(A, g, bt.root, gb, is_gas, true, A.eta_h, guess, a.x, a.y, a.z, vp, true, A.shared != 0,
                           s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0), is_gas ? dbg0 : nullptr);
         handed = oh.handed;
         if (is_gas && !oh.ok && !handed) nnoconv++;
@@ -736,7 +737,7 @@ __global__ __launch_bounds__(64, 2) void k_density(DensArgs A) {
         } else {
           double g0 = A.es[p];
           double guess = g0 > 0.0 ? g0 : (act ? cold_guess(A, p, false, A.eta_eps) : 0.0);
-          SolveOut oe = solve_length(A, g, gb, act, false, A.eta_eps, guess, a.x, a.y, a.z, vp, true, true,
+          SolveOut oe = solve_length(A, g, bt.root, gb, act, false, A.eta_eps, guess, a.x, a.y, a.z, vp, true, true,
                                      s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0), nullptr);
           handed = oe.handed;
           if (act && !oe.ok && !handed) nnoconv++;
@@ -826,13 +827,13 @@ __device__ void sink_leaf_sums(const DensArgs &A, int nleaf, const int *leaf, bo
 }
 
 // One self-consistent length of one sink (wave-uniform).
-__device__ SolveOut solve_one(const DensArgs &A, int p, bool gas_only, double eta, double guess, bool cold,
+__device__ SolveOut solve_one(const DensArgs &A, int p, int root, bool gas_only, double eta, double guess, bool cold,
                               const double4 &a, const double4 &vp, bool want_div, bool want_phi, int *s_stack,
                               int *s_leaf, double4 *s_snk) {
   SolveOut o;
   o.handed = false;
   const double eta3 = eta * eta * eta;
-  const int64_t set_size = gas_only ? A.n_gas : A.n;
+  const int64_t set_size = gas_only ? A.nngas[root] : A.topo[root].count;
   const bool solvable = ((double)set_size / kPi > eta3) && (guess > 0.0);
   const NodeBox pb{a.x, a.y, a.z, 0.0, a.x, a.y, a.z, 0.0};
   double h = guess > 0.0 ? (solvable && cold ? 0.5 * guess : guess) : 1.0;
@@ -846,7 +847,7 @@ __device__ SolveOut solve_one(const DensArgs &A, int p, bool gas_only, double et
       if (gathered) rc = h * (1.0 + A.kappa);
       s_snk[lane()] = make_double4(a.x, a.y, a.z, lane() == 0 ? 2.0 * rc : 0.0);
       __syncthreads();
-      c = gather(A, pb, 2.0 * rc, gas_only, s_stack, s_leaf, s_snk, fail);
+      c = gather(A, root, pb, 2.0 * rc, gas_only, s_stack, s_leaf, s_snk, fail);
       gathered = true;
       if (fail) break;
     }
@@ -854,7 +855,7 @@ __device__ SolveOut solve_one(const DensArgs &A, int p, bool gas_only, double et
     if (c.cached) {
       sink_leaf_sums(A, c.nleaf, s_leaf, gas_only, a.x, a.y, a.z, vp, h, want_div, want_phi, s);
     } else {
-      const bool wok = walk_leaves(A, pb, c.R, gas_only, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
+      const bool wok = walk_leaves(A, root, pb, c.R, gas_only, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
         sink_leaf_sums(A, nl, s_leaf, gas_only, a.x, a.y, a.z, vp, h, want_div, want_phi, s);
         return true;
       });
@@ -898,7 +899,7 @@ __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
     __syncthreads();
     if (t >= nslot * kWave) break;
     const int g = A.heavy[t / kWave];
-    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, g);
     for (int j = t % kWave; j < bt.count; j += kWave) {
       const int p = bt.first + j;
       const double4 a = A.pm[p];
@@ -911,7 +912,7 @@ __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
       if (A.hydro && is_gas) {
         const double g0 = A.hs[p];
         const double guess = g0 > 0.0 ? g0 : cold_guess(A, p, true, A.eta_h);
-        oh = solve_one(A, p, true, A.eta_h, guess, !(g0 > 0.0), a, vp, true, A.shared != 0, s_stack, s_leaf, s_snk);
+        oh = solve_one(A, p, bt.root, true, A.eta_h, guess, !(g0 > 0.0), a, vp, true, A.shared != 0, s_stack, s_leaf, s_snk);
         if (!oh.ok) nnoconv++;
       }
       double eps = 0.0, neps = 0.0, ups = 1.0, xi = 0.0, divve = 0.0;
@@ -928,7 +929,7 @@ __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
           const double g0 = A.es[p];
           const double guess = g0 > 0.0 ? g0 : cold_guess(A, p, false, A.eta_eps);
           const SolveOut oe =
-              solve_one(A, p, false, A.eta_eps, guess, !(g0 > 0.0), a, vp, true, true, s_stack, s_leaf, s_snk);
+              solve_one(A, p, bt.root, false, A.eta_eps, guess, !(g0 > 0.0), a, vp, true, true, s_stack, s_leaf, s_snk);
           if (!oe.ok) nnoconv++;
           eps = oe.h;
           neps = oe.s.n;
@@ -966,6 +967,7 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
   A.nngas = c->nngas;
   A.nlevel = c->nlevel;
   A.root = c->root;
+  A.mem = members_of(c, c->n, c->n_gas);
   A.pm = c->pm;
   A.vu = c->vu;
   A.gas = c->gas;

@@ -40,6 +40,7 @@ struct GravArgs {
   const int2 *batches;
   const int32_t *nbatches;
   const int32_t *nngas;
+  Members mem;
   const NodeTopo *topo;
   const NodeBox *nbox;
   const NodeFar *nfar;
@@ -473,7 +474,7 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
     const int g = s_g;
     __syncthreads();
     if (g < 0) break;
-    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, g);
     const NodeTopo gnd{bt.first, bt.count, -1, 0};
     const NodeBox gb = bt.box;
     const double gemax = gb.epsmax;
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
       bool overflow = false;
       int rounds = 0;
       const int guard = *A.nnodes + 2;
-      if (ln == 0) s_stack[0] = 0;
+      if (ln == 0) s_stack[0] = bt.root;
       __syncthreads();
 
       for (;;) {
@@ -697,7 +698,7 @@ __global__ __launch_bounds__(64) void k_gravity_split(GravArgs A) {
     if (it >= nitems) break;
     const SplitItem I = A.split_item[it];
     if (I.g < 0) continue;  // reserved but unused
-    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, I.g);
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, I.g);
     const NodeTopo gnd{bt.first, bt.count, -1, 0};
     const NodeBox gb = bt.box;
     const double cx = 0.5 * (gb.lox + gb.hix), cy = 0.5 * (gb.loy + gb.hiy), cz = 0.5 * (gb.loz + gb.hiz);
@@ -725,7 +726,7 @@ __global__ __launch_bounds__(64) void k_split_reduce(GravArgs A) {
   for (int g = blockIdx.x; g < ng; g += gridDim.x) {
     int it = A.split_head[g];
     if (it < 0) continue;
-    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, g);
     int guard = 0;
     while (it >= 0 && it < A.split_cap && ++guard <= A.split_cap) {
       const SplitItem I = A.split_item[it];
@@ -769,6 +770,7 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
   A.batches = c->batches;
   A.nbatches = c->nbatches;
   A.nngas = c->nngas;
+  A.mem = members_of(c, c->n, c->n_gas);
   A.topo = c->topo;
   A.nbox = c->nbox;
   A.nfar = c->nfar;

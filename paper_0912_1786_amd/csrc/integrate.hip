@@ -13,7 +13,7 @@
 
 namespace tsph {
 
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = 1024;       // partial reductions of a single system
 
 struct FinishArgs {
   int64_t n, cap_n;
@@ -73,7 +73,8 @@ __device__ __forceinline__ double predict_factor(double dt, double divv) {
   return f;
 }
 
-__global__ __launch_bounds__(256) void k_kick_drift(int64_t n, int64_t n_gas, double dt, int phase, double *x,
+// dt: the same for every member, or dt_dev[member] when dt_dev is given
+__global__ __launch_bounds__(256) void k_kick_drift(Members M, double dt, int phase, double *x,
                                                     double *y, double *z, double *vx, double *vy, double *vz,
                                                     double *u, const double *__restrict__ ax,
                                                     const double *__restrict__ ay, const double *__restrict__ az,
@@ -82,9 +83,11 @@ __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, int64_t n_gas, do
                                                     const double *__restrict__ pdiv, int64_t cap_n,
                                                     const double *__restrict__ dt_dev) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= M.n) return;
+  const int mem = member_of(M, i);
+  const bool gas = member_gas(M, mem, i);
   if (dt_dev) {
-    dt = *dt_dev;
+    dt = dt_dev[mem];
     if (!(dt >= 0.0 && dt < INFINITY)) return;
   }
   const double hdt = 0.5 * dt;
@@ -105,10 +108,10 @@ __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, int64_t n_gas, do
     // lengths along the drift: h n^(1/3) = eta with dn/dt = -n div v gives
     // dh/dt = (h/3) div v (Sect. 2.1); the next solve starts from them
     if (pdiv) {
-      if (h && i < n_gas && h[i] > 0.0) h[i] *= predict_factor(dt, pdiv[i]);
+      if (h && gas && h[i] > 0.0) h[i] *= predict_factor(dt, pdiv[i]);
       if (eps && eps[i] > 0.0) eps[i] *= predict_factor(dt, pdiv[cap_n + i]);
     }
-    if (i < n_gas) {
+    if (gas) {
       const double du = dudt[i];
       if (up) up[i] = u[i] + dt * du;
       u[i] += hdt * du;
@@ -117,17 +120,23 @@ __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, int64_t n_gas, do
     v0 += hdt * a0;
     v1 += hdt * a1;
     v2 += hdt * a2;
-    if (i < n_gas) u[i] += hdt * dudt[i];
+    if (gas) u[i] += hdt * dudt[i];
   }
   vx[i] = v0;
   vy[i] = v1;
   vz[i] = v2;
 }
 
-__global__ __launch_bounds__(256) void k_min_partial(int64_t n, const double *__restrict__ a, double *__restrict__ part) {
+// grid (blocks per member, members); a in key order, where member m holds
+// the same range as in caller order
+__global__ __launch_bounds__(256) void k_min_partial(Members M, const double *__restrict__ a,
+                                                     double *__restrict__ part) {
   __shared__ double s[256];
   double v = INFINITY;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+  const int mem = blockIdx.y;
+  const int64_t i1 = member_end(M, mem);
+  for (int64_t i = member_begin(M, mem) + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < i1;
+       i += (int64_t)gridDim.x * blockDim.x)
     v = fmin(v, a[i]);
   s[threadIdx.x] = v;
   __syncthreads();
@@ -135,13 +144,15 @@ __global__ __launch_bounds__(256) void k_min_partial(int64_t n, const double *__
     if ((int)threadIdx.x < o) s[threadIdx.x] = fmin(s[threadIdx.x], s[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+  if (threadIdx.x == 0) part[(int64_t)mem * gridDim.x + blockIdx.x] = s[0];
 }
 
+// one block per member over its nb partial minima
 __global__ __launch_bounds__(256) void k_min_final(int nb, const double *__restrict__ part, double *__restrict__ out,
                                                    double *__restrict__ keep) {
   __shared__ double s[256];
   double v = INFINITY;
+  part += (int64_t)blockIdx.x * nb;
   for (int i = threadIdx.x; i < nb; i += 256) v = fmin(v, part[i]);
   s[threadIdx.x] = v;
   __syncthreads();
@@ -150,24 +161,29 @@ __global__ __launch_bounds__(256) void k_min_final(int nb, const double *__restr
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    if (out) *out = s[0];
-    if (keep) *keep = s[0];
+    if (out) out[blockIdx.x] = s[0];
+    if (keep) keep[blockIdx.x] = s[0];
   }
 }
 
 constexpr int kNDiag = 9;
 
-__global__ __launch_bounds__(256) void k_diag_partial(int64_t n, int64_t n_gas, const double *__restrict__ x,
+// grid (blocks per member, members)
+__global__ __launch_bounds__(256) void k_diag_partial(Members M, const double *__restrict__ x,
                                                       const double *__restrict__ y, const double *__restrict__ z,
                                                       const double *__restrict__ vx, const double *__restrict__ vy,
                                                       const double *__restrict__ vz, const double *__restrict__ m,
                                                       const double *__restrict__ u, const double *__restrict__ pot,
                                                       double *__restrict__ part) {
   double acc[kNDiag] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  const int mem = blockIdx.y;
+  const int64_t i0 = member_begin(M, mem), i1 = member_end(M, mem);
+  const int64_t gas_end = i0 + (M.count <= 1 ? M.n_gas : M.ngas[mem]);
+  for (int64_t i = i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < i1;
+       i += (int64_t)gridDim.x * blockDim.x) {
     const double mi = m[i], a = vx[i], b = vy[i], c = vz[i];
     acc[0] += 0.5 * mi * (a * a + b * b + c * c);
-    if (i < n_gas && u) acc[1] += mi * u[i];
+    if (i < gas_end && u) acc[1] += mi * u[i];
     if (pot) acc[2] += 0.5 * mi * pot[i];
     acc[3] += mi * a;
     acc[4] += mi * b;
@@ -184,11 +200,14 @@ __global__ __launch_bounds__(256) void k_diag_partial(int64_t n, int64_t n_gas, 
       for (int k = 0; k < kNDiag; k++) s[k][threadIdx.x] += s[k][threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x < kNDiag) part[blockIdx.x * kNDiag + threadIdx.x] = s[threadIdx.x][0];
+  if (threadIdx.x < kNDiag) part[((int64_t)mem * gridDim.x + blockIdx.x) * kNDiag + threadIdx.x] = s[threadIdx.x][0];
 }
 
+// one block per member: out[member * 9 + k]
 __global__ __launch_bounds__(256) void k_diag_final(int nb, const double *__restrict__ part, double *__restrict__ out) {
   __shared__ double s[256];
+  part += (int64_t)blockIdx.x * nb * kNDiag;
+  out += (int64_t)blockIdx.x * kNDiag;
   for (int k = 0; k < kNDiag; k++) {
     double v = 0.0;
     for (int i = threadIdx.x; i < nb; i += 256) v += part[i * kNDiag + k];
@@ -234,17 +253,19 @@ tsph_status tsph_impl_finish(Ctx *c, tsph_state *s, hipStream_t st) {
   A.beta = c->p.beta;
   A.hydro = c->p.hydro;
   hipLaunchKernelGGL(k_finish, dim3(blocks_for(c->n, 256, 1 << 20)), dim3(256), 0, st, A);
-  // global time-step kept on the device for tsph_timestep
-  hipLaunchKernelGGL(k_min_partial, dim3(kRedBlocks), dim3(256), 0, st, c->n, A.dt_i, c->red);
-  hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, st, kRedBlocks, c->red, (double *)nullptr, c->dt);
+  // time-step of each member kept on the device for tsph_timestep
+  const Members M = members_of(c, c->n, c->n_gas);
+  const int rb = M.count > 1 ? kMemberBlocks : kRedBlocks;
+  hipLaunchKernelGGL(k_min_partial, dim3(rb, M.count), dim3(256), 0, st, M, A.dt_i, c->red);
+  hipLaunchKernelGGL(k_min_final, dim3(M.count), dim3(256), 0, st, rb, c->red, (double *)nullptr, c->dt);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }
 
 tsph_status tsph_impl_kick_drift(Ctx *c, tsph_state *s, double dt, const double *dt_dev, int phase,
                                  hipStream_t st) {
-  hipLaunchKernelGGL(k_kick_drift, dim3(blocks_for(s->n, 256, 1 << 20)), dim3(256), 0, st, s->n, s->n_gas, dt,
-                     phase, s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->ax, s->ay, s->az, s->dudt, s->vpx,
+  hipLaunchKernelGGL(k_kick_drift, dim3(blocks_for(s->n, 256, 1 << 20)), dim3(256), 0, st,
+                     members_of(c, s->n, s->n_gas), dt, phase, s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->ax, s->ay, s->az, s->dudt, s->vpx,
                      s->vpy, s->vpz, s->up, s->h, s->eps, c->pdiv_n == s->n ? c->pdiv : nullptr, c->cap_n,
                      dt_dev);
   TSPH_HIP_CHECK(c, hipGetLastError());
@@ -252,14 +273,16 @@ tsph_status tsph_impl_kick_drift(Ctx *c, tsph_state *s, double dt, const double 
 }
 
 tsph_status tsph_impl_timestep(Ctx *c, double *dt_device, hipStream_t st) {
-  TSPH_HIP_CHECK(c, hipMemcpyAsync(dt_device, c->dt, sizeof(double), hipMemcpyDeviceToDevice, st));
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(dt_device, c->dt, sizeof(double) * c->nmem, hipMemcpyDeviceToDevice, st));
   return TSPH_OK;
 }
 
 tsph_status tsph_impl_diagnostics(Ctx *c, const tsph_state *s, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_partial, dim3(kRedBlocks), dim3(256), 0, st, s->n, s->n_gas, s->x, s->y, s->z, s->vx,
-                     s->vy, s->vz, s->m, s->u, s->pot, c->red);
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, kRedBlocks, c->red, out);
+  const Members M = members_of(c, s->n, s->n_gas);
+  const int rb = M.count > 1 ? kMemberBlocks : kRedBlocks;
+  hipLaunchKernelGGL(k_diag_partial, dim3(rb, M.count), dim3(256), 0, st, M, s->x, s->y, s->z, s->vx, s->vy,
+                     s->vz, s->m, s->u, s->pot, c->red);
+  hipLaunchKernelGGL(k_diag_final, dim3(M.count), dim3(256), 0, st, rb, c->red, out);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

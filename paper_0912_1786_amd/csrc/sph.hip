@@ -36,6 +36,7 @@ struct SphArgs {
   const NodeTopo *topo;
   const NodeBox *nbox;
   const int32_t *nngas;
+  Members mem;
   const double4 *pm;
   const double4 *vu;
   const double4 *sph;   // h, rho, c, P/rho^2
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(64) void k_sph(SphArgs A) {
     const int g = s_g;
     __syncthreads();
     if (g < 0) break;
-    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, g);
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, g);
     if (bt.ngas == 0) continue;
     const NodeTopo gnd{bt.first, bt.count, -1, 0};
     const NodeBox gb = bt.box;
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(64) void k_sph(SphArgs A) {
       bool overflow = false;
       int rounds = 0;
       const int guard = *A.nnodes + 2;
-      if (ln == 0) s_stack[0] = 0;
+      if (ln == 0) s_stack[0] = bt.root;
       s_snk[ln] = make_double4(a.x, a.y, a.z, sink ? 2.0 * hi : 0.0);
       __syncthreads();
       for (;;) {
@@ -235,6 +236,7 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   A.topo = c->topo;
   A.nbox = c->nbox;
   A.nngas = c->nngas;
+  A.mem = members_of(c, c->n, c->n_gas);
   A.pm = c->pm;
   A.vu = c->vu;
   A.sph = c->sph;

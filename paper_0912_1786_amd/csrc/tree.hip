@@ -48,9 +48,11 @@ int persistent_blocks(Ctx *c, const void *kernel) {
 // ---------------------------------------------------------------------------
 // root cube
 // ---------------------------------------------------------------------------
-constexpr int kBBoxBlocks = 512;
+constexpr int kBBoxBlocks = 512;     // partial boxes of a single system
 
-__global__ __launch_bounds__(256) void k_bbox_partial(int64_t n, const double *__restrict__ x,
+// grid (blocks per member, members): block (b, m) reduces a strided share of
+// member m's particles into part[m * gridDim.x + b]
+__global__ __launch_bounds__(256) void k_bbox_partial(Members M, const double *__restrict__ x,
                                                       const double *__restrict__ y,
                                                       const double *__restrict__ z,
                                                       const double *__restrict__ m,
@@ -58,7 +60,9 @@ __global__ __launch_bounds__(256) void k_bbox_partial(int64_t n, const double *_
                                                       uint32_t *__restrict__ flags) {
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+  const int mem = blockIdx.y;
+  const int64_t i0 = member_begin(M, mem), i1 = member_end(M, mem);
+  for (int64_t i = i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < i1;
        i += (int64_t)gridDim.x * blockDim.x) {
     double p[3] = {x[i], y[i], z[i]};
     double mi = m[i];
@@ -87,12 +91,15 @@ __global__ __launch_bounds__(256) void k_bbox_partial(int64_t n, const double *_
     }
     __syncthreads();
   }
-  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+  if (threadIdx.x < 6) part[((int64_t)mem * gridDim.x + blockIdx.x) * 6 + threadIdx.x] = s[threadIdx.x][0];
 }
 
 // smallest power of two not below the largest extent; origin = minimum corner
-__global__ void k_bbox_final(int nb, const double *__restrict__ part, DevRoot *__restrict__ root) {
+// one block per member: nb partial boxes each
+__global__ void k_bbox_final(int nb, const double *__restrict__ part, DevRoot *__restrict__ roots) {
   if (threadIdx.x != 0) return;
+  part += (int64_t)blockIdx.x * nb * 6;
+  DevRoot *root = roots + blockIdx.x;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int b = 0; b < nb; b++)
     for (int d = 0; d < 3; d++) {
@@ -139,13 +146,15 @@ __device__ __forceinline__ uint64_t cell_of(double v, double v0, double scale) {
   return (uint64_t)c;
 }
 
-__global__ __launch_bounds__(256) void k_keys(int64_t n, const double *__restrict__ x,
+// key of particle i relative to the root cube of its member
+__global__ __launch_bounds__(256) void k_keys(Members M, const double *__restrict__ x,
                                               const double *__restrict__ y,
                                               const double *__restrict__ z,
-                                              const DevRoot *__restrict__ root,
+                                              const DevRoot *__restrict__ roots,
                                               uint64_t *__restrict__ key, int32_t *__restrict__ idx) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= M.n) return;
+  const DevRoot *root = roots + member_of(M, i);
   double sc = root->scale;
   uint64_t cx = cell_of(x[i], root->x0, sc), cy = cell_of(y[i], root->y0, sc),
            cz = cell_of(z[i], root->z0, sc);
@@ -259,41 +268,79 @@ static void launch_scan(Ctx *c, const int32_t *in, int64_t n_host, const int32_t
 }
 
 // ---------------------------------------------------------------------------
-// stable LSD radix sort of (key, index), 8-bit digits, 8 passes
+// stable LSD radix sort of (key, index), 8-bit digits, 8 passes, segmented
+// by member: every block sorts one tile of kSortTile keys of one member, and
+// the digit counts are laid out member by member ([member][digit][tile]), so
+// that one exclusive scan over all of them gives each member's keys the
+// positions of its own range.  A single system is the one-member case
+// ([digit][tile]).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_sort_hist(int64_t n, const uint64_t *__restrict__ key, int shift,
-                                                   uint32_t *__restrict__ hist, int nb) {
+struct SortTile {
+  int64_t lo, hi;  // keys [lo, hi) of this block
+  int64_t hbase;   // first count of its member
+  int ntile, t;    // the member's tiles, this block's tile among them
+};
+
+__device__ __forceinline__ SortTile sort_tile(const Members &M, const int32_t *__restrict__ mtile, int b) {
+  SortTile T;
+  if (M.count <= 1) {
+    T.lo = (int64_t)b * kSortTile;
+    T.hi = min(T.lo + kSortTile, M.n);
+    T.hbase = 0;
+    T.ntile = gridDim.x;
+    T.t = b;
+    return T;
+  }
+  int lo = 0, hi = M.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mtile[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  T.t = b - mtile[lo];
+  T.ntile = mtile[lo + 1] - mtile[lo];
+  T.hbase = (int64_t)mtile[lo] * kSortBins;
+  T.lo = M.off[lo] + (int64_t)T.t * kSortTile;
+  T.hi = min(T.lo + kSortTile, M.off[lo + 1]);
+  return T;
+}
+
+__global__ __launch_bounds__(256) void k_sort_hist(Members M, const int32_t *__restrict__ mtile,
+                                                   const uint64_t *__restrict__ key, int shift,
+                                                   uint32_t *__restrict__ hist) {
   __shared__ uint32_t s_h[kSortBins];
   s_h[threadIdx.x] = 0;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const SortTile T = sort_tile(M, mtile, blockIdx.x);
   for (int k = 0; k < kSortTile / 256; k++) {
-    int64_t i = base + k * 256 + threadIdx.x;
-    if (i < n) atomicAdd(&s_h[(key[i] >> shift) & (kSortBins - 1)], 1u);
+    int64_t i = T.lo + k * 256 + threadIdx.x;
+    if (i < T.hi) atomicAdd(&s_h[(key[i] >> shift) & (kSortBins - 1)], 1u);
   }
   __syncthreads();
-  hist[threadIdx.x * nb + blockIdx.x] = s_h[threadIdx.x];
+  hist[T.hbase + (int64_t)threadIdx.x * T.ntile + T.t] = s_h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_sort_scatter(int64_t n, const uint64_t *__restrict__ kin,
+__global__ __launch_bounds__(256) void k_sort_scatter(Members M, const int32_t *__restrict__ mtile,
+                                                      const uint64_t *__restrict__ kin,
                                                       const int32_t *__restrict__ iin,
                                                       uint64_t *__restrict__ kout,
                                                       int32_t *__restrict__ iout, int shift,
-                                                      const int32_t *__restrict__ offs, int nb,
+                                                      const int32_t *__restrict__ offs,
                                                       uint32_t *__restrict__ flags) {
   __shared__ int s_base[kSortBins];
   __shared__ int s_run[kSortBins];
   __shared__ int s_w[4][kSortBins];
   int t = threadIdx.x, w = t >> 6;
-  s_base[t] = offs[t * nb + blockIdx.x];
+  const SortTile T = sort_tile(M, mtile, blockIdx.x);
+  const int64_t n = M.n;
+  s_base[t] = offs[T.hbase + (int64_t)t * T.ntile + T.t];
   s_run[t] = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) s_w[k][t] = 0;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kSortTile;
   for (int r = 0; r < kSortTile / 256; r++) {
-    int64_t i = base + r * 256 + t;
-    bool valid = i < n;
+    int64_t i = T.lo + r * 256 + t;
+    bool valid = i < T.hi;
     uint64_t k = valid ? kin[i] : 0;
     int id = valid ? iin[i] : 0;
     int d = (int)((k >> shift) & (kSortBins - 1));
@@ -328,7 +375,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(int64_t n, const uint64_t 
 // ---------------------------------------------------------------------------
 // gather the caller-order state into key order
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gather(int64_t n, int64_t n_gas, const int32_t *__restrict__ perm,
+__global__ __launch_bounds__(256) void k_gather(Members M, const int32_t *__restrict__ perm,
                                                 const double *__restrict__ x, const double *__restrict__ y,
                                                 const double *__restrict__ z, const double *__restrict__ m,
                                                 const double *__restrict__ vpx, const double *__restrict__ vpy,
@@ -338,9 +385,9 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, int64_t n_gas, const 
                                                 double *__restrict__ hs, double *__restrict__ es,
                                                 uint8_t *__restrict__ gas) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p >= n) return;
+  if (p >= M.n) return;
   int i = perm[p];
-  bool g = i < n_gas;
+  bool g = member_gas(M, member_of(M, i), i);
   pm[p] = make_double4(x[i], y[i], z[i], m[i]);
   if (vpx) vu[p] = make_double4(vpx[i], vpy[i], vpz[i], (g && up) ? up[i] : 0.0);
   hs[p] = (g && h) ? h[i] : 0.0;
@@ -351,20 +398,22 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, int64_t n_gas, const 
 // ---------------------------------------------------------------------------
 // topology, one level at a time
 // ---------------------------------------------------------------------------
-__global__ void k_topo_init(int64_t n, NodeTopo *__restrict__ topo, int32_t *__restrict__ nlevel,
+// level 0: the root of each member, in member order
+__global__ void k_topo_init(Members M, NodeTopo *__restrict__ topo, int32_t *__restrict__ nlevel,
                             int32_t *__restrict__ nparent, int32_t *__restrict__ lvl) {
   int t = threadIdx.x;
   if (t < 47) lvl[t] = 0;
-  if (t == 0) {
-    topo[0] = NodeTopo{0, (int32_t)n, -1, 0};
-    nlevel[0] = 0;
-    nparent[0] = -1;
+  for (int m = t; m < M.count; m += blockDim.x) {
+    const int64_t b = member_begin(M, m);
+    topo[m] = NodeTopo{(int32_t)b, (int32_t)(member_end(M, m) - b), -1, 0};
+    nlevel[m] = 0;
+    nparent[m] = -1;
   }
   __syncthreads();
   if (t == 0) {
     lvl[0] = 0;
-    lvl[23] = 1;
-    lvl[46] = 1;
+    lvl[23] = M.count;
+    lvl[46] = M.count;
   }
 }
 
@@ -432,7 +481,7 @@ __global__ __launch_bounds__(256) void k_moments(int level, double theta, const 
                                                  const double4 *__restrict__ pm,
                                                  const uint8_t *__restrict__ gas,
                                                  const uint64_t *__restrict__ key,
-                                                 const DevRoot *__restrict__ root,
+                                                 const DevRoot *__restrict__ roots, Members mem,
                                                  NodeFar *__restrict__ far, NodeBox *__restrict__ box,
                                                  int32_t *__restrict__ nngas, int32_t *__restrict__ leaf_of) {
   int begin = lvl[level], count = lvl[23 + level];
@@ -497,7 +546,9 @@ __global__ __launch_bounds__(256) void k_moments(int level, double theta, const 
       }
       sx = cx; sy = cy; sz = cz;
     }
-    // cube geometry from the level and the key prefix of the node
+    // cube geometry from the level, the key prefix of the node and the root
+    // cube of its member
+    const DevRoot *root = roots + member_of(mem, nd.first);
     uint64_t pre = key[nd.first] >> (3 * (kMaxLevel - level));
     uint64_t ix = 0, iy = 0, iz = 0;
     for (int b = 0; b < level; b++) {
@@ -601,7 +652,7 @@ __global__ __launch_bounds__(256) void k_group_compact(int64_t n, const int32_t 
 // batch_size particles.  One thread per run start marks the batch starts.
 __device__ __forceinline__ bool next_sibling(const int32_t *groups, const int32_t *nparent, int g) {
   const int u = groups[g], v = groups[g - 1];
-  return u == v + 1 && nparent[u] == nparent[v];
+  return u == v + 1 && nparent[u] >= 0 && nparent[u] == nparent[v];
 }
 
 __global__ __launch_bounds__(256) void k_batch_mark(const int32_t *__restrict__ ngroups,
@@ -645,28 +696,30 @@ tsph_status tsph_impl_build_tree(Ctx *c, const tsph_state *s, hipStream_t st) {
   const int64_t n = s->n;
   const int T = 256;
   const int gb = blocks_for(n, T, 1 << 20);
-  // root cube
-  hipLaunchKernelGGL(k_bbox_partial, dim3(kBBoxBlocks), dim3(T), 0, st, n, s->x, s->y, s->z, s->m,
-                     c->bbox_part, c->flags);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, kBBoxBlocks, c->bbox_part, c->root);
+  const Members M = members_of(c, n, s->n_gas);
+  // root cube of each member
+  const int bbm = M.count > 1 ? kMemberBlocks : kBBoxBlocks;
+  hipLaunchKernelGGL(k_bbox_partial, dim3(bbm, M.count), dim3(T), 0, st, M, s->x, s->y, s->z, s->m, c->bbox_part,
+                     c->flags);
+  hipLaunchKernelGGL(k_bbox_final, dim3(M.count), dim3(64), 0, st, bbm, c->bbox_part, c->root);
   // keys
-  hipLaunchKernelGGL(k_keys, dim3(gb), dim3(T), 0, st, n, s->x, s->y, s->z, c->root, c->key[0], c->idx[0]);
+  hipLaunchKernelGGL(k_keys, dim3(gb), dim3(T), 0, st, M, s->x, s->y, s->z, c->root, c->key[0], c->idx[0]);
   // sort: 8 passes of 8 bits, ping-pong, result back in buffer 0
-  int nb = (int)((n + kSortTile - 1) / kSortTile);
+  const int nb = M.count > 1 ? c->sort_tiles : (int)((n + kSortTile - 1) / kSortTile);
   for (int pass = 0; pass < 8; pass++) {
     int src = pass & 1, dst = src ^ 1, shift = pass * kSortBits;
-    hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(T), 0, st, n, c->key[src], shift, c->hist, nb);
+    hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(T), 0, st, M, c->mtile, c->key[src], shift, c->hist);
     launch_scan(c, (const int32_t *)c->hist, (int64_t)nb * kSortBins, nullptr, (int64_t)nb * kSortBins,
                 (int32_t *)c->hist, nullptr, nullptr, 0, st);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(T), 0, st, n, c->key[src], c->idx[src], c->key[dst],
-                       c->idx[dst], shift, (const int32_t *)c->hist, nb, c->flags);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(T), 0, st, M, c->mtile, c->key[src], c->idx[src],
+                       c->key[dst], c->idx[dst], shift, (const int32_t *)c->hist, c->flags);
   }
   c->perm = c->idx[0];
   // gather
-  hipLaunchKernelGGL(k_gather, dim3(gb), dim3(T), 0, st, n, s->n_gas, c->perm, s->x, s->y, s->z, s->m,
-                     s->vpx, s->vpy, s->vpz, s->up, s->h, s->eps, c->pm, c->vu, c->hs, c->es, c->gas);
+  hipLaunchKernelGGL(k_gather, dim3(gb), dim3(T), 0, st, M, c->perm, s->x, s->y, s->z, s->m, s->vpx, s->vpy,
+                     s->vpz, s->up, s->h, s->eps, c->pm, c->vu, c->hs, c->es, c->gas);
   // topology
-  hipLaunchKernelGGL(k_topo_init, dim3(1), dim3(64), 0, st, n, c->topo, c->nlevel, c->nparent, c->lvl);
+  hipLaunchKernelGGL(k_topo_init, dim3(1), dim3(256), 0, st, M, c->topo, c->nlevel, c->nparent, c->lvl);
   int64_t maxlev = (c->cap_nodes + 7) / 8;
   int lb = blocks_for(maxlev, T, 4096);
   for (int L = 0; L < kMaxLevel; L++) {
@@ -679,7 +732,7 @@ tsph_status tsph_impl_build_tree(Ctx *c, const tsph_state *s, hipStream_t st) {
   // moments, deepest level first
   for (int L = kMaxLevel; L >= 0; L--)
     hipLaunchKernelGGL(k_moments, dim3(lb), dim3(T), 0, st, L, c->p.theta, c->lvl, c->topo, c->pm, c->gas,
-                       c->key[0], c->root, c->nfar, c->nbox, c->nngas, c->leaf_of);
+                       c->key[0], c->root, M, c->nfar, c->nbox, c->nngas, c->leaf_of);
   // groups
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, T, 8192)), dim3(T), 0, st, n, c->gflag, -1);
   hipLaunchKernelGGL(k_group_mark, dim3(blocks_for(c->cap_nodes, T, 8192)), dim3(T), 0, st, n,

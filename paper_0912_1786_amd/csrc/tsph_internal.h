@@ -55,6 +55,41 @@ struct SphRec {
   double pr2, zo, pad0, pad1;  // P / rho^2, zeta / Omega*
 };
 
+// The simulations a context holds (a forest of independent trees).  Member
+// m owns particles [off[m], off[m+1]) in caller order and, because the sort
+// is segmented by member, the same range in key order; its first ngas[m]
+// particles are gas.  Node m of level 0 is its root, and no walk, sum or
+// time-step crosses members.  count == 1: a single system of n particles
+// whose first n_gas are gas; the tables are then not read.
+struct Members {
+  const int64_t *off;   // count + 1 entries
+  const int64_t *ngas;  // count entries
+  int32_t count;
+  int64_t n, n_gas;
+};
+
+constexpr int kMemberBlocks = 16;  // blocks per member of the per-member reductions
+
+__device__ __forceinline__ int member_of(const Members &M, int64_t i) {
+  if (M.count <= 1) return 0;
+  int lo = 0, hi = M.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (M.off[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int64_t member_begin(const Members &M, int m) { return M.count <= 1 ? 0 : M.off[m]; }
+
+__device__ __forceinline__ int64_t member_end(const Members &M, int m) { return M.count <= 1 ? M.n : M.off[m + 1]; }
+
+// is particle i (caller order) of member m gas?
+__device__ __forceinline__ bool member_gas(const Members &M, int m, int64_t i) {
+  return M.count <= 1 ? i < M.n_gas : i - M.off[m] < M.ngas[m];
+}
+
 struct DevRoot {
   double x0, y0, z0, side;  // power-of-two root cube
   double scale;             // 2^(21 - e): key = floor((x - x0) * scale)
@@ -127,8 +162,15 @@ struct Ctx {
   int32_t *nbatches;
   int32_t *gflag;         // cap_n group start flags / scan
 
+  // ---- members (tsph_set_members) ----
+  int32_t nmem, cap_mem;  // members held (1: a single system), capacity
+  int64_t *moff, *mgas;   // device tables: cap_mem + 1 offsets, cap_mem gas counts
+  int32_t *mtile;         // device: cap_mem + 1 prefix of the members' sort tiles
+  int64_t *h_moff, *h_mgas;  // host copies
+  int32_t sort_tiles;     // sum of the members' sort tiles
+
   // ---- small device state ----
-  DevRoot *root;
+  DevRoot *root;          // cap_mem root cubes
   double *bbox_part;      // partial bbox (6 x max blocks)
   int32_t *lvl;           // [0..23): level begin, [23..46): level count, [46]: total nodes
   int32_t *ngroups;
@@ -147,7 +189,7 @@ struct Ctx {
   uint32_t *flags;        // device flag word
   int32_t *noconv;        // unconverged solves
   double *red;            // reduction scratch
-  double *dt;             // last global time-step
+  double *dt;             // cap_mem time-steps of the last force pass (one per member)
 
   // ---- phase timing (ring of event sets) ----
   int32_t timing;
@@ -166,6 +208,10 @@ struct Ctx {
   uint32_t *h_flags;      // pinned host copy
   int32_t *h_noconv;
 };
+
+inline Members members_of(const Ctx *c, int64_t n, int64_t n_gas) {
+  return Members{c->moff, c->mgas, c->nmem, n, n_gas};
+}
 
 // ---------------------------------------------------------------------------
 // wave primitives (wave64)
@@ -414,16 +460,18 @@ __device__ __forceinline__ int xcd_next(int32_t *ctr, int n) {
 // members' boxes (max eps and h over the members, summed gas counts).
 struct Batch {
   int first, count, ngas;
+  int root;  // root node of the batch's member: where its walks start
   NodeBox box;
 };
 
 __device__ __forceinline__ Batch load_batch(const int2 *batches, const int32_t *groups, const NodeTopo *topo,
-                                            const NodeBox *nbox, const int32_t *nngas, int b) {
+                                            const NodeBox *nbox, const int32_t *nngas, const Members &M, int b) {
   const int2 r = sload(batches + b);
   Batch B;
   const int k0 = uniform(sload(groups + r.x));
   const NodeTopo t0 = sload(topo + k0);
   B.first = t0.first;
+  B.root = uniform(member_of(M, t0.first));
   B.count = 0;
   B.ngas = 0;
   B.box = sload(nbox + k0);

@@ -1,13 +1,17 @@
 """Ensembles of independent simulations advanced by one HIP-graph launch per
 step, with the leaf and group sizes chosen by a measuring autotuner.
 
-Every member keeps its own context, device state and time-step.  The step
-of all members -- time-step criteria, kick-drift, force evaluation and the
-closing kick, with the time-step read on the device -- is captured once
-into a HIP graph across several streams (members spread over them) and
+The members live in one context as a forest (tsph_set_members): their
+particles are held back to back, every tree-build stage and every walk is
+one launch over all members (a sort segmented by member, one root per
+member, walk batches of all members in one work queue), and each member
+keeps its own time-step.  The step of all members -- time-step criteria,
+kick-drift, force evaluation and the closing kick, with each member's
+time-step read on the device -- is captured once into a HIP graph and
 replayed with a single launch per step.  Members share no data, so each
 member's result does not depend on the others: the tests require the
-ensemble step to equal the member stepped alone, bit for bit.
+ensemble step to equal the member stepped alone in a context of its own,
+bit for bit.
 
     python -m paper_0912_1786_amd.ensemble --members 256 --steps 10
 """
@@ -15,7 +19,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import time
 
 import numpy as np
@@ -33,91 +36,67 @@ def ensemble_ics(members: int, seed: int = 1000):
     return [inputs.evrard(int(n), seed=seed + k, u0=float(u)) for k, (n, u) in enumerate(zip(sizes, u0))]
 
 
-def size_class(n: int) -> int:
-    """Autotuner classes: one per factor of two in N."""
-    return int(math.floor(math.log2(max(n, 1))))
+def member_params(nnei: float = 50.0, precision: int = tsph.FP32_BULK, leaf: int = 16, group: int = 64):
+    return tsph.tsph_default_params(nnei=nnei, leaf_size=leaf, group_size=group, precision=precision)
 
 
 def autotune(ics, nnei: float = 50.0, precision: int = tsph.FP32_BULK, reps: int = 3) -> dict:
-    """For each size class of the ensemble, times one warm force evaluation
-    of its largest member under every candidate (leaf, group) and keeps the
-    fastest.  Returns {class: (leaf, group, {candidate: ms})}."""
+    """Times warm force evaluations of the whole ensemble (one context
+    holding every member) under each candidate (leaf, group) and keeps the
+    fastest.  Returns {"leaf", "group", "ms": {candidate: ms}}."""
     import torch
-    by_class = {}
-    for ic in ics:
-        c = size_class(ic["n"])
-        if c not in by_class or ic["n"] > by_class[c]["n"]:
-            by_class[c] = ic
-    choice = {}
-    for c, ic in sorted(by_class.items()):
-        times = {}
-        for leaf, group in CANDIDATES:
-            prm = tsph.tsph_default_params(nnei=nnei, leaf_size=leaf, group_size=group, precision=precision)
-            sim = tsph.Simulation(ic, prm, want_pot=False)
-            try:
+    big, members = tsph.concat_ics(ics)
+    times = {}
+    for leaf, group in CANDIDATES:
+        sim = tsph.Simulation(big, member_params(nnei, precision, leaf, group), want_pot=False, members=members)
+        try:
+            sim.compute_forces()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
                 sim.compute_forces()
-                torch.cuda.synchronize()
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                a.record()
-                for _ in range(reps):
-                    sim.compute_forces()
-                b.record()
-                torch.cuda.synchronize()
-                times[(leaf, group)] = a.elapsed_time(b) / reps
-            finally:
-                sim.close()
-        best = min(times, key=times.get)
-        choice[c] = (best[0], best[1], times)
-    return choice
+            b.record()
+            torch.cuda.synchronize()
+            times[(leaf, group)] = a.elapsed_time(b) / reps
+        finally:
+            sim.close()
+    best = min(times, key=times.get)
+    return {"leaf": best[0], "group": best[1], "ms": times}
 
 
 class Ensemble:
-    """Independent simulations stepped together by one graph launch."""
+    """Independent simulations in one context, stepped by one graph launch."""
 
-    def __init__(self, ics, nnei: float = 50.0, precision: int = tsph.FP32_BULK, tuning: dict | None = None,
-                 streams: int = 16):
+    def __init__(self, ics, nnei: float = 50.0, precision: int = tsph.FP32_BULK, leaf: int = 16, group: int = 64):
         import torch
         self.torch = torch
-        self.members = []
-        self.params = []
-        for ic in ics:
-            leaf, group = (16, 64)
-            if tuning is not None:
-                leaf, group = tuning[size_class(ic["n"])][:2]
-            prm = tsph.tsph_default_params(nnei=nnei, leaf_size=leaf, group_size=group, precision=precision)
-            self.params.append(prm)
-            self.members.append(tsph.Simulation(ic, prm, want_pot=False))
-        self.n_total = sum(m.n for m in self.members)
-        self.streams = [torch.cuda.Stream() for _ in range(max(1, streams))]
+        big, members = tsph.concat_ics(ics)
+        self.params = member_params(nnei, precision, leaf, group)
+        self.sim = tsph.Simulation(big, self.params, want_pot=False, members=members)
+        self.count = len(ics)
+        self.n_total = self.sim.n
         self.graph = None
+        self.stream = torch.cuda.Stream()
 
     def first_forces(self):
         """Cold-start force evaluation of every member (outside any graph)."""
-        for m in self.members:
-            m.compute_forces()
+        self.sim.compute_forces()
         self.torch.cuda.synchronize()
 
     def eager_step(self):
-        """One step of every member, issued member by member on the current
-        stream (the reference the graph is checked against)."""
-        for m in self.members:
-            m.device_step()
+        """One step of every member, issued call by call on the current
+        stream (what the graph replays)."""
+        self.sim.device_step()
 
     def capture(self):
-        """Captures one step of all members into a graph; members are spread
-        over the streams, which fork from and join the capture stream."""
+        """Captures one step of all members into a graph."""
         torch = self.torch
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
-        main = torch.cuda.Stream()
-        with torch.cuda.graph(g, stream=main):
-            for s in self.streams:
-                s.wait_stream(main)
-            for k, m in enumerate(self.members):
-                m.device_step(self.streams[k % len(self.streams)])
-            for s in self.streams:
-                main.wait_stream(s)
+        with torch.cuda.graph(g, stream=self.stream):
+            self.sim.device_step(self.stream)
         torch.cuda.synchronize()
         self.graph = g
         return g
@@ -125,17 +104,17 @@ class Ensemble:
     def step(self):
         self.graph.replay()
 
+    def member(self, k: int, key: str):
+        return self.sim.member(k, key)
+
     def flags(self):
-        out = []
-        for m in self.members:
-            out.append(m.flags())
-        return out
+        return self.sim.flags()
 
     def close(self):
-        for m in self.members:
-            m.close()
-        self.members = []
         self.graph = None
+        if self.sim is not None:
+            self.sim.close()
+            self.sim = None
 
 
 def run(members: int = 256, steps: int = 10, warmup: int = 2, seed: int = 1000, tune: bool = True,
@@ -146,7 +125,8 @@ def run(members: int = 256, steps: int = 10, warmup: int = 2, seed: int = 1000, 
     prec = tsph.FP32_BULK if precision == "fp32_bulk" else tsph.FP64
     tuning = autotune(ics, precision=prec) if tune else None
     t_tune = time.time() - t0
-    ens = Ensemble(ics, precision=prec, tuning=tuning)
+    leaf, group = (tuning["leaf"], tuning["group"]) if tuning else (16, 64)
+    ens = Ensemble(ics, precision=prec, leaf=leaf, group=group)
     try:
         ens.first_forces()
         ens.capture()
@@ -155,20 +135,21 @@ def run(members: int = 256, steps: int = 10, warmup: int = 2, seed: int = 1000, 
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
+        # replays are launched on the current stream
         a.record()
         for _ in range(steps):
             ens.step()
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
-        bad = [(i, f) for i, f in enumerate(ens.flags()) if f != (0, 0)]
+        flags, noconv = ens.flags()
         return {"workload": f"evrard_ensemble_{members}", "members": members, "n_total": ens.n_total,
                 "precision": precision, "steps": steps, "ms_per_step": round(ms, 3),
                 "particle_steps_per_s": round(ens.n_total / (ms / 1e3), 1), "graph_launches_per_step": 1,
-                "autotune": None if tuning is None else
-                {str(c): {"leaf": v[0], "group": v[1], "ms": {f"{l}x{g}": round(t, 3) for (l, g), t in v[2].items()}}
-                 for c, v in tuning.items()},
-                "autotune_s": round(t_tune, 1), "members_flagged": bad[:8]}
+                "leaf": leaf, "group": group,
+                "autotune_ms": None if tuning is None else
+                {f"{l}x{g}": round(t, 3) for (l, g), t in tuning["ms"].items()},
+                "autotune_s": round(t_tune, 1), "device_flags": flags, "noconv": noconv}
     finally:
         ens.close()
 

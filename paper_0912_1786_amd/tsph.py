@@ -37,7 +37,8 @@ class Params(C.Structure):
                 ("beta", C.c_double), ("av_eps2", C.c_double), ("tc92", C.c_int32), ("h_maxit", C.c_int32),
                 ("h_tol", C.c_double), ("kappa", C.c_double), ("leaf_size", C.c_int32),
                 ("group_size", C.c_int32), ("precision", C.c_int32), ("gravity", C.c_int32),
-                ("hydro", C.c_int32), ("split_leaves", C.c_int32), ("eta_dt", C.c_double)]
+                ("hydro", C.c_int32), ("split_leaves", C.c_int32), ("eta_dt", C.c_double),
+                ("max_members", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -72,6 +73,7 @@ def lib():
             "tsph_set_params": ([_P, P], C.c_int),
             "tsph_default_params": ([P], None),
             "tsph_bytes_required": ([C.c_int64, P, C.POINTER(C.c_size_t)], C.c_int),
+            "tsph_set_members": ([_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
             "tsph_build_tree": ([_P, S, _P], C.c_int),
             "tsph_compute_forces": ([_P, S, _P], C.c_int),
             "tsph_kick_drift": ([_P, S, C.c_double, C.c_int32, _P], C.c_int),
@@ -98,7 +100,7 @@ def lib():
 
 
 EXPORTED = ("tsph_create", "tsph_destroy", "tsph_set_params", "tsph_default_params", "tsph_bytes_required",
-            "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_kick_drift_dt", "tsph_carry_bytes",
+            "tsph_set_members", "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_kick_drift_dt", "tsph_carry_bytes",
             "tsph_carry_save", "tsph_carry_load", "tsph_timestep", "tsph_diagnostics", "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
             "tsph_timing", "tsph_phase_times")
 PHASES = ("tree", "density", "gravity", "sph", "finish")
@@ -157,6 +159,17 @@ def _stream(stream):
     if isinstance(stream, int):
         return C.c_void_p(stream)
     return C.c_void_p(stream.cuda_stream)
+
+
+def tsph_set_members(ctx, off, n_gas):
+    """Several independent systems in one context: system k owns particles
+    [off[k], off[k+1]) of the state, its first n_gas[k] being gas."""
+    count = len(n_gas)
+    if len(off) != count + 1:
+        raise ValueError("off needs len(n_gas) + 1 entries")
+    o = (C.c_int64 * (count + 1))(*[int(v) for v in off])
+    g = (C.c_int64 * count)(*[int(v) for v in n_gas])
+    _check("tsph_set_members", lib().tsph_set_members(ctx, count, o, g), ctx)
 
 
 def tsph_build_tree(ctx, st: State, stream=None):
@@ -241,23 +254,46 @@ def tsph_version() -> str:
 # ---------------------------------------------------------------------------
 # convenience: a particle set held in torch device tensors
 # ---------------------------------------------------------------------------
+def concat_ics(ics):
+    """One initial-condition dict holding the systems of ``ics`` back to back
+    (each with its gas first, as the inputs generate them), and the member
+    table [(n, n_gas), ...] for Simulation(members=...)."""
+    import numpy as np
+    keys = ("x", "y", "z", "vx", "vy", "vz", "m", "u")
+    out = {k: np.concatenate([np.asarray(ic[k], dtype=np.float64) for ic in ics]) for k in keys}
+    out["n"] = int(sum(int(ic["n"]) for ic in ics))
+    out["n_gas"] = int(sum(int(ic["n_gas"]) for ic in ics))
+    return out, [(int(ic["n"]), int(ic["n_gas"])) for ic in ics]
+
+
 class Simulation:
     """Caller-owned FP64 device arrays for one particle system plus a context.
 
     ``ic`` is a dict from :mod:`paper_0912_1786_amd.inputs`.  The predicted
     velocity/energy arrays start as copies of v and u (first evaluation).
+    With ``members`` = [(n, n_gas), ...] (see concat_ics) the arrays hold
+    that many independent systems back to back in one context; timestep()
+    and diagnostics() then return one entry per system.
     """
 
     FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "vpx", "vpy", "vpz", "up", "h", "eps", "ax", "ay", "az",
               "dudt", "rho", "pot")
 
     def __init__(self, ic: dict, params: Params | None = None, capacity: int | None = None, device: str = "cuda",
-                 want_pot: bool = True, eps_const=None):
+                 want_pot: bool = True, eps_const=None, members=None):
         import torch
         self.torch = torch
         self.n = int(ic["n"])
         self.n_gas = int(ic["n_gas"])
-        self.params = params if params is not None else tsph_default_params()
+        self.params = Params.from_buffer_copy(params if params is not None else tsph_default_params())
+        self.count = 1 if members is None else len(members)
+        self.off = [0]
+        for nk, _ in (members or [(self.n, self.n_gas)]):
+            self.off.append(self.off[-1] + int(nk))
+        if self.off[-1] != self.n:
+            raise ValueError("the members do not add up to n")
+        if members is not None:
+            self.params.max_members = max(int(self.params.max_members), self.count)
         dev = torch.device(device)
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
         z = lambda: torch.zeros(self.n, dtype=torch.float64, device=dev)
@@ -272,9 +308,15 @@ class Simulation:
             self.a[k] = z()
         self.a["pot"] = z() if want_pot else None
         self.ctx = tsph_create(capacity or self.n, self.params)
+        if members is not None:
+            try:
+                tsph_set_members(self.ctx, self.off, [g for _, g in members])
+            except Exception:
+                self.close()
+                raise
         self.state = self._state()
-        self.diag_buf = torch.zeros(9, dtype=torch.float64, device=dev)
-        self.dt_buf = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.diag_buf = torch.zeros(9 * self.count, dtype=torch.float64, device=dev)
+        self.dt_buf = torch.zeros(self.count, dtype=torch.float64, device=dev)
 
     def _state(self) -> State:
         st = State()
@@ -290,13 +332,21 @@ class Simulation:
     def kick_drift(self, dt: float, phase: int, stream=None):
         tsph_kick_drift(self.ctx, self.state, dt, phase, stream)
 
-    def timestep(self, stream=None) -> float:
+    def timestep(self, stream=None):
+        """The time-step of the last force pass: a float, or one per system."""
         tsph_timestep(self.ctx, self.state, self.dt_buf.data_ptr(), stream)
-        return float(self.dt_buf.item())
+        v = self.dt_buf.cpu().numpy()
+        return float(v[0]) if self.count == 1 else v
 
     def diagnostics(self, stream=None):
+        """E_kin, E_th, V, P, L: shape (9,), or (systems, 9)."""
         tsph_diagnostics(self.ctx, self.state, self.diag_buf.data_ptr(), stream)
-        return self.diag_buf.cpu().numpy()
+        v = self.diag_buf.cpu().numpy()
+        return v if self.count == 1 else v.reshape(self.count, 9)
+
+    def member(self, k: int, key: str):
+        """Host copy of array `key` of system k."""
+        return self.a[key][self.off[k]:self.off[k + 1]].cpu().numpy()
 
     def step(self, dt: float, stream=None):
         """One KDK step; assumes forces of the current state are present."""

@@ -37,6 +37,12 @@ def test_host_only_entry_points(T):
     assert abs(p.eta_h - T.eta_from_nnei(50)) < 1e-12
     b = T.tsph_bytes_required(1 << 21, p)
     assert 300 * (1 << 21) < b < 2000 * (1 << 21)  # a few hundred bytes per particle
+    assert p.max_members == 1
+    # room for the member tables of a forest of 256 systems: small
+    b256 = T.tsph_bytes_required(1 << 21, T.tsph_default_params(max_members=256))
+    assert b < b256 < b + (1 << 20)
+    with pytest.raises(T.TsphError):
+        T.tsph_bytes_required(1000, T.tsph_default_params(max_members=0))
     bad = T.tsph_default_params(leaf_size=0)
     with pytest.raises(T.TsphError):
         T.tsph_bytes_required(1000, bad)
@@ -46,5 +52,7 @@ def test_host_only_entry_points(T):
 def test_param_struct_layout_matches_header(T):
     import ctypes as C
     # field order and padding of tsph_params / tsph_state as declared
-    assert C.sizeof(T.Params) == 8 * 2 + 4 * 2 + 8 * 6 + 4 * 2 + 8 * 2 + 4 * 6 + 8
+    # ... max_members (int32) last, padded to the struct's 8-byte alignment
+    assert C.sizeof(T.Params) == 8 * 2 + 4 * 2 + 8 * 6 + 4 * 2 + 8 * 2 + 4 * 6 + 8 + 4 + 4
+    assert T.Params.max_members.offset == C.sizeof(T.Params) - 8
     assert C.sizeof(T.State) == 8 * 2 + 8 * 20
