@@ -135,7 +135,13 @@ struct DensTile {
   int q[kWave];
 };
 
-// Per-lane kernel sums over the nt staged candidates at length h.
+// Per-lane kernel sums over the nt staged candidates at length h.  The
+// distance tests of all candidates come first (broadcast reads) and leave
+// each lane a mask of its neighbours in the tile; each lane then evaluates
+// only its own neighbours, in tile order, so the lanes of the wave do not
+// all step through every candidate some other lane needs.  The sums are
+// the same, term for term and in the same order, as a plain loop over the
+// tile that skips the candidates out of range.
 template <bool kFull>
 __device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, int nt, double px, double py,
                                           double pz, const double4 &vp, double h, bool want_div, bool want_phi,
@@ -145,10 +151,16 @@ __device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, 
   const double ih4 = ih3 * ih;
   const double two_h = 2.0 * h;
   const double R2 = two_h * two_h;
+  uint64_t mask = 0;
   for (int j = 0; j < nt; j++) {
     const double4 a = T.pm[j];
+    if (dist2_pair(px, py, pz, a.x, a.y, a.z) < R2) mask |= 1ull << j;
+  }
+  while (mask) {
+    const int j = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const double4 a = T.pm[j];
     const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
-    if (!(r2 < R2)) continue;
     if (kFull && dbg_row) {
       if (ndbg < A.dbg_max) dbg_row[ndbg] = A.perm[T.q[j]];
       ndbg++;
@@ -443,13 +455,22 @@ __device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T,
   const double ihh4 = ihh3 * ihh, ihe4 = ihe3 * ihe;
   const double R2h = do_h ? (2.0 * hh) * (2.0 * hh) : -1.0;
   const double R2e = do_e ? (2.0 * he) * (2.0 * he) : -1.0;
+  // neighbour mask first, then each lane's own neighbours in tile order
+  // (as in tile_sums)
+  uint64_t mask = 0;
   for (int j = 0; j < nt; j++) {
+    const double4 a = T.pm[j];
+    const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+    if ((r2 < R2h && T.vu[j].w != 0.0) || r2 < R2e) mask |= 1ull << j;
+  }
+  while (mask) {
+    const int j = __builtin_ctzll(mask);
+    mask &= mask - 1;
     const double4 a = T.pm[j];
     const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
     const double4 v = T.vu[j];
     const bool in_h = r2 < R2h && v.w != 0.0;
     const bool in_e = r2 < R2e;
-    if (!(in_h || in_e)) continue;
     const double r = r2 > 0.0 ? r2 * rsqrt(r2) : 0.0;
     const double dot = (vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z);
     if (in_h) {

@@ -15,17 +15,27 @@
 //
 // One wavefront per walk group that holds gas; the wave walks the tree once
 // (opening nodes with gas within 2 max(h_group, h_node) of the group box),
-// lists the candidate leaves in LDS and flushes them in batches.
+// lists the candidate leaves in LDS and flushes them in batches.  A flush
+// stages the candidates 64 at a time in LDS (position and h), every lane
+// tests the whole tile and keeps a mask of its own pairs, and then each lane
+// evaluates only its own pairs, in candidate order, reading the partner's
+// record itself; lanes do not step through pairs that only other lanes have.
 #include <stdio.h>
 
 #include "tsph_internal.h"
 
 namespace tsph {
 
-constexpr int kSStackCap = 1536;
+constexpr int kSStackCap = 1024;
 constexpr int kSListCap = 128;
 constexpr int kSLeafFlush = 32;
 constexpr double kInvPiS = 0.31830988618379067154;
+
+// candidates of a flush staged for the pair tests
+struct SphTile {
+  double4 pos[kWave];  // x, y, z, h (non-gas candidates at infinity)
+  int q[kWave];
+};
 
 struct SphArgs {
   int64_t cap_n;
@@ -56,10 +66,11 @@ struct SphArgs {
   int32_t tc92;
 };
 
-__global__ __launch_bounds__(64) void k_sph(SphArgs A) {
+__global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
   __shared__ int s_stack[kSStackCap];
   __shared__ int s_leaf[kSListCap];
   __shared__ double4 s_snk[kWave];
+  __shared__ SphTile s_t;
   __shared__ int s_g;
   const int ln = lane();
   const int ng = *A.nbatches;
@@ -140,21 +151,27 @@ __global__ __launch_bounds__(64) void k_sph(SphArgs A) {
         if (nleaf >= kSLeafFlush || (last && nleaf > 0)) {
           const double ihi = 1.0 / hi, imi = 1.0 / mi;
           const double ihi4 = ihi * ihi * ihi * ihi * kInvPiS;
-          for (int j = 0; j < nleaf; j++) {
-            const NodeTopo nd = sload(A.topo + uniform(s_leaf[j]));
-            for (int q = nd.first; q < nd.first + nd.count; q++) {
-              if (!sload_u8(A.gas + q)) continue;
-              const SphRec b = sload(A.srec + q);
+          // pairs of this lane among nt staged candidates
+          auto tile_pairs = [&](int nt) {
+            uint64_t mask = 0;
+            for (int j = 0; j < nt; j++) {
+              const double4 b = s_t.pos[j];
               const double r2x = dist2_pair(a.x, a.y, a.z, b.x, b.y, b.z);
-              const double R = 2.0 * fmax(hi, b.h);
-              if (!(sink && q != p && r2x < R * R)) continue;
+              const double R = 2.0 * fmax(hi, b.w);
+              if (sink && s_t.q[j] != p && r2x < R * R) mask |= 1ull << j;
+            }
+            while (mask) {
+              const int j = __builtin_ctzll(mask);
+              mask &= mask - 1;
+              const int q = s_t.q[j];
+              const SphRec b = A.srec[q];
               if (dbg) {
                 if (ndbg < A.dbg_max) dbg[ndbg] = A.perm[q];
                 ndbg++;
               }
               npair++;
               const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-              const double r2 = r2x;
+              const double r2 = dist2_pair(a.x, a.y, a.z, b.x, b.y, b.z);
               if (!(r2 > 0.0)) continue;
               const double ir = rsqrt(r2);
               const double r = r2 * ir;
@@ -186,6 +203,41 @@ __global__ __launch_bounds__(64) void k_sph(SphArgs A) {
               az -= sf * dz;
               du += e;
             }
+            __syncthreads();
+          };
+          // candidates in leaf order, packed 64 to a tile, one per lane
+          auto stage = [&](int nt, int q) {
+            if (ln < nt) {
+              const bool g = A.gas[q] != 0;
+              const SphRec *r = A.srec + q;
+              s_t.pos[ln] = g ? make_double4(r->x, r->y, r->z, r->h) : make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+              s_t.q[ln] = g ? q : -1;
+            }
+            __syncthreads();
+          };
+          int fill = 0, rq = 0;
+          for (int c1 = 0; c1 < nleaf; c1 += kWave) {
+            const int nc = min(kWave, nleaf - c1);
+            const NodeTopo my = ln < nc ? A.topo[s_leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
+            for (int j = 0; j < nc; j++) {
+              const int first = __builtin_amdgcn_readlane(my.first, j);
+              const int count = __builtin_amdgcn_readlane(my.count, j);
+              for (int off = 0; off < count;) {
+                const int tk = min(count - off, kWave - fill);
+                if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
+                fill += tk;
+                off += tk;
+                if (fill == kWave) {
+                  stage(kWave, rq);
+                  tile_pairs(kWave);
+                  fill = 0;
+                }
+              }
+            }
+          }
+          if (fill > 0) {
+            stage(fill, rq);
+            tile_pairs(fill);
           }
           nleaf = 0;
         }
