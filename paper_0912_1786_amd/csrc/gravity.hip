@@ -105,27 +105,6 @@ __device__ __forceinline__ void far_field(const GravArgs &A, Sink &s, const Node
   if (M & kPot) s.pot -= A.G * ph;
 }
 
-// Newtonian pair (both lengths reached): the common case, branch free
-template <int M>
-__device__ __forceinline__ void newton_pair(const GravArgs &A, Sink &s, const GravRec &b) {
-  const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
-  const double r2 = dx * dx + dy * dy + dz * dz;
-  const double ir = rsqrt(r2);
-  const double mr = b.m * ir;
-  const double f = A.G * mr * ir * ir;
-  s.ax -= f * dx;
-  s.ay -= f * dy;
-  s.az -= f * dz;
-  if (M & kPot) s.pot -= A.G * mr;
-}
-
-__device__ __forceinline__ bool softened(const Sink &s, const GravRec &b) {
-  const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
-  const double r2 = dx * dx + dy * dy + dz * dz;
-  const double em = fmax(s.eps, b.eps);
-  return r2 < 4.0 * em * em;
-}
-
 template <int M>
 __device__ __forceinline__ void near_pair(const GravArgs &A, Sink &s, const GravRec &b) {
   const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
@@ -172,33 +151,34 @@ __device__ __forceinline__ void debug_pair(const GravArgs &A, Sink &s, const Gra
 }
 
 // Evaluates the nt particle records staged in rec (indices in tq) on sink s.
+// First every pair of the tile as a Newtonian pair, in tile order, with the
+// pairs inside 2 max(eps) (and the self pair) given zero weight; each lane
+// notes those in a mask and then evaluates only its own softened pairs, in
+// tile order.  The wave thus does not run the softened formula for a pair
+// that only some other lane needs.
 template <int M>
 __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const GravRec *rec, const int *tq, int nt) {
-  int j = 0;
-  for (; j + 2 <= nt; j += 2) {
-    const GravRec b0 = rec[j], b1 = rec[j + 1];
-    const int q0 = tq[j], q1 = tq[j + 1];
-    // the self pair and every pair inside 2 max(eps) take the general path
-    const bool slow = q0 == s.p || q1 == s.p || softened(s, b0) || softened(s, b1);
-    if (!__any(slow)) {
-      newton_pair<M>(A, s, b0);
-      newton_pair<M>(A, s, b1);
-    } else {
-      if (q0 != s.p) near_pair<M>(A, s, b0);
-      if (q1 != s.p) near_pair<M>(A, s, b1);
-    }
-    if (s.dbg) {
-      if (q0 != s.p) debug_pair(A, s, b0, q0);
-      if (q1 != s.p) debug_pair(A, s, b1, q1);
-    }
-  }
-  if (j < nt) {
+  uint64_t soft = 0;
+  for (int j = 0; j < nt; j++) {
     const GravRec b = rec[j];
-    const int q = tq[j];
-    if (q != s.p) {
-      near_pair<M>(A, s, b);
-      if (s.dbg) debug_pair(A, s, b, q);
-    }
+    const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double em = fmax(s.eps, b.eps);
+    const bool near = r2 < 4.0 * em * em;
+    soft |= (uint64_t)near << j;
+    const double ir = near ? 0.0 : rsqrt(r2);
+    const double mr = b.m * ir;
+    const double f = A.G * mr * ir * ir;
+    s.ax -= f * dx;
+    s.ay -= f * dy;
+    s.az -= f * dz;
+    if (M & kPot) s.pot -= A.G * mr;
+    if (s.dbg && tq[j] != s.p) debug_pair(A, s, b, tq[j]);
+  }
+  while (soft) {
+    const int j = __builtin_ctzll(soft);
+    soft &= soft - 1;
+    if (tq[j] != s.p) near_pair<M>(A, s, rec[j]);
   }
 }
 
@@ -288,13 +268,6 @@ __device__ __forceinline__ void newton_pair32(Sink32 &s, const RecF32 &b) {
   if (M & kPot) s.tpot -= mr;
 }
 
-__device__ __forceinline__ bool softened32(const Sink32 &s, const RecF32 &b) {
-  const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
-  const float r2 = dx * dx + dy * dy + dz * dz;
-  const float em = fmaxf(s.eps, b.eps);
-  return r2 < 4.0f * em * em;
-}
-
 template <int M>
 __device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b) {
   const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
@@ -325,22 +298,31 @@ __device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b) {
   }
 }
 
+// As near_tile: Newtonian pass over the tile, then each lane's own
+// softened pairs.
 template <int M>
 __device__ __forceinline__ void near_tile32(Sink32 &s, const RecF32 *rec, const int *tq, int nt) {
-  int j = 0;
-  for (; j + 2 <= nt; j += 2) {
-    const RecF32 b0 = rec[j], b1 = rec[j + 1];
-    const int q0 = tq[j], q1 = tq[j + 1];
-    const bool slow = q0 == s.p || q1 == s.p || softened32(s, b0) || softened32(s, b1);
-    if (!__any(slow)) {
-      newton_pair32<M>(s, b0);
-      newton_pair32<M>(s, b1);
-    } else {
-      if (q0 != s.p) near_pair32<M>(s, b0);
-      if (q1 != s.p) near_pair32<M>(s, b1);
-    }
+  uint64_t soft = 0;
+  for (int j = 0; j < nt; j++) {
+    const RecF32 b = rec[j];
+    const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float em = fmaxf(s.eps, b.eps);
+    const bool near = r2 < 4.0f * em * em;
+    soft |= (uint64_t)near << j;
+    const float ir = near ? 0.0f : rsqrtf(r2);
+    const float mr = b.m * ir;
+    const float f = mr * ir * ir;
+    s.tax -= f * dx;
+    s.tay -= f * dy;
+    s.taz -= f * dz;
+    if (M & kPot) s.tpot -= mr;
   }
-  if (j < nt && tq[j] != s.p) near_pair32<M>(s, rec[j]);
+  while (soft) {
+    const int j = __builtin_ctzll(soft);
+    soft &= soft - 1;
+    if (tq[j] != s.p) near_pair32<M>(s, rec[j]);
+  }
 }
 
 // LDS staging tiles of the two forms
