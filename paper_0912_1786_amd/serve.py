@@ -7,9 +7,11 @@ steps of different simulations concurrently on several streams
 simulation are free, while others are still running).
 
 A step request runs one leapfrog step with the time-step taken on the
-device (tsph_timestep, tsph_kick_drift_dt, tsph_compute_forces).  Requests
-of one simulation run in arrival order; a simulation's result does not
-depend on the mix it is served in.
+device (tsph_timestep, tsph_kick_drift_dt, tsph_compute_forces).  The step
+of each resident simulation is captured once into a HIP graph when it is
+admitted, so a request costs one graph launch on the host.  Requests of one
+simulation run in arrival order; a simulation's result does not depend on
+the mix it is served in.
 
     python -m paper_0912_1786_amd.serve --sims 64 --requests 400
 """
@@ -62,6 +64,7 @@ class Resident:
     def __init__(self, sid: int, ic: dict, params):
         self.sid, self.ic, self.params = sid, ic, params
         self.sim = None          # tsph.Simulation while resident
+        self.graph = None        # its captured step while resident
         self.saved = None        # host copy of the state while evicted
         self.busy = False
         self.steps = 0
@@ -74,7 +77,7 @@ class Resident:
     def bytes(self) -> int:
         return tsph.tsph_bytes_required(self.n, self.params) + 8 * len(HOST_KEYS) * self.n
 
-    def admit(self):
+    def admit(self, capture_stream=None):
         import torch
         if self.sim is not None:
             return
@@ -89,6 +92,20 @@ class Resident:
             self.sim.load_carry(self.saved["carry"])
             self.saved = None
         torch.cuda.synchronize()
+        if capture_stream is not None:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=capture_stream):
+                self.sim.device_step(capture_stream)
+            self.graph = g
+
+    def launch(self, stream):
+        """Issues one step on `stream`: the captured graph, or the calls."""
+        import torch
+        if self.graph is not None:
+            with torch.cuda.stream(stream):
+                self.graph.replay()
+        else:
+            self.sim.device_step(stream)
 
     def evict(self):
         """Moves the state to host memory and frees the device context."""
@@ -96,12 +113,14 @@ class Resident:
             return
         self.saved = {k: self.sim.host(k) for k in HOST_KEYS}
         self.saved["carry"] = self.sim.carry()
+        self.graph = None
         self.sim.close()
         self.sim = None
 
 
 class Server:
-    def __init__(self, ics, streams: int = 8, hbm_budget: int | None = None, precision: int = tsph.FP32_BULK):
+    def __init__(self, ics, streams: int = 8, hbm_budget: int | None = None, precision: int = tsph.FP32_BULK,
+                 graphs: bool = True):
         import torch
         self.torch = torch
         self.res = []
@@ -109,6 +128,7 @@ class Server:
             prm = tsph.tsph_default_params(nnei=50.0, precision=precision)
             self.res.append(Resident(k, ic, prm))
         self.streams = [torch.cuda.Stream() for _ in range(max(1, streams))]
+        self.capture_stream = torch.cuda.Stream() if graphs else None
         self.free = list(range(len(self.streams)))
         self.budget = hbm_budget
         self.resident_bytes = 0
@@ -130,7 +150,7 @@ class Server:
                 self.evictions += 1
             if self.resident_bytes + need > self.budget and any(x.sim is not None for x in self.res):
                 return False
-        r.admit()
+        r.admit(self.capture_stream)
         self.resident_bytes += need
         self.admissions += 1
         return True
@@ -197,7 +217,7 @@ class Server:
                 stream = self.streams[slot]
                 r.busy = True
                 st = time.perf_counter() - t0
-                r.sim.device_step(stream)
+                r.launch(stream)
                 ev = torch.cuda.Event()
                 ev.record(stream)
                 inflight.append((ev, slot, r, a, st))
@@ -214,6 +234,7 @@ class Server:
 
     def close(self):
         for r in self.res:
+            r.graph = None
             if r.sim is not None:
                 r.sim.close()
                 r.sim = None
@@ -238,10 +259,11 @@ def summarize(done, label: str) -> dict:
 
 
 def run(n_sim: int = 64, requests: int = 400, streams: int = 8, budget_fraction: float = 0.5, seed: int = 2000,
-        saturation_s: float = 3.0) -> dict:
-    """Closed-loop saturation throughput, then open-loop Poisson arrivals at
-    0.5x and 0.8x of it; the HBM budget is budget_fraction of what the whole
-    population would hold."""
+        saturation_s: float = 3.0, warmup_s: float = 2.0) -> dict:
+    """Closed-loop saturation throughput (after a closed-loop warm-up that
+    admits the first simulations and takes their cold starts), then
+    open-loop Poisson arrivals at 0.5x and 0.8x of it; the HBM budget is
+    budget_fraction of what the whole population would hold."""
     import torch
     ics = population(n_sim, seed)
     probe = Server(ics, streams)
@@ -250,6 +272,8 @@ def run(n_sim: int = 64, requests: int = 400, streams: int = 8, budget_fraction:
     probe.close()
     srv = Server(ics, streams, hbm_budget=budget)
     try:
+        if warmup_s > 0:
+            srv.run([], closed_loop=True, duration=warmup_s, seed=seed + 7)
         sat = srv.run([], closed_loop=True, duration=saturation_s)
         s0 = summarize(sat, "closed_loop_saturation")
         out = {"workload": f"serving_{n_sim}_sims", "sims": n_sim, "n_total": int(sum(ic["n"] for ic in ics)),
