@@ -680,7 +680,7 @@ __device__ __forceinline__ void store_outputs(const DensArgs &A, int p, bool is_
 // kFused: gas and softening lengths solved together (independent solves,
 // both species); otherwise one or the other (or one shared) separately.
 template <bool kFused>
-__global__ __launch_bounds__(64, 2) void k_density(DensArgs A) {
+__global__ __launch_bounds__(64, 3) void k_density(DensArgs A) {
   __shared__ int s_stack[kDensStackCap];
   __shared__ int s_leaf[kDensLeafCap];
   __shared__ double4 s_snk[kWave];
