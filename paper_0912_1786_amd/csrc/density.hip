@@ -70,10 +70,13 @@ struct Sums {
 // is a cheap first filter.  Leaves are handed to visit(count, last) in
 // batches of at least `batch` held in s_leaf (capacity batch + 64); visit
 // returns false to stop the walk.  Returns false if the walk was stopped or a
-// structural check failed.
+// structural check failed.  whole (a walk for the single sink at the corner
+// of the point box gb): a node lying entirely inside the ball of radius R is
+// listed as it is, its particle range standing for all its leaves, instead
+// of being opened.
 template <class V>
 __device__ bool walk_leaves(const DensArgs &A, int root, const NodeBox &gb, double R, bool gas_only, int *s_stack,
-                            int *s_leaf, const double4 *s_snk, int batch, V &&visit) {
+                            int *s_leaf, const double4 *s_snk, int batch, V &&visit, bool whole = false) {
   const int ln = lane();
   int nleaf = 0, sp = 1, rounds = 0;
   const int guard = *A.nnodes + 2;
@@ -102,6 +105,12 @@ __device__ bool walk_leaves(const DensArgs &A, int root, const NodeBox &gb, doub
     if (hit) {
       nd = A.topo[k];
       leaf = nd.nchild == 0;
+      if (whole && !leaf) {
+        const double fx = fmax(fabs(gb.lox - b.lox), fabs(b.hix - gb.lox));
+        const double fy = fmax(fabs(gb.loy - b.loy), fabs(b.hiy - gb.loy));
+        const double fz = fmax(fabs(gb.loz - b.loz), fabs(b.hiz - gb.loz));
+        leaf = fx * fx + fy * fy + fz * fz < R2;
+      }
     }
     const uint64_t lm = ballot(leaf);
     if (leaf) s_leaf[nleaf + mbcnt(lm)] = k;
@@ -249,7 +258,7 @@ struct Cands {
 };
 
 __device__ Cands gather(const DensArgs &A, int root, const NodeBox &gb, double R, bool gas_only, int *s_stack, int *s_leaf,
-                        const double4 *s_snk, bool &fail) {
+                        const double4 *s_snk, bool &fail, bool whole = false) {
   Cands c{0, true, R, gas_only};
   bool full = false;
   bool ok = walk_leaves(A, root, gb, R, gas_only, s_stack, s_leaf, s_snk, kDensLeafCap - kWave,
@@ -260,7 +269,8 @@ __device__ Cands gather(const DensArgs &A, int root, const NodeBox &gb, double R
                           }
                           c.nleaf = nl;
                           return true;
-                        });
+                        },
+                        whole);
   if (full) {
     c.cached = false;
     c.nleaf = 0;
@@ -868,7 +878,7 @@ __device__ SolveOut solve_one(const DensArgs &A, int p, int root, bool gas_only,
       if (gathered) rc = h * (1.0 + A.kappa);
       s_snk[lane()] = make_double4(a.x, a.y, a.z, lane() == 0 ? 2.0 * rc : 0.0);
       __syncthreads();
-      c = gather(A, root, pb, 2.0 * rc, gas_only, s_stack, s_leaf, s_snk, fail);
+      c = gather(A, root, pb, 2.0 * rc, gas_only, s_stack, s_leaf, s_snk, fail, true);
       gathered = true;
       if (fail) break;
     }
@@ -876,10 +886,13 @@ __device__ SolveOut solve_one(const DensArgs &A, int p, int root, bool gas_only,
     if (c.cached) {
       sink_leaf_sums(A, c.nleaf, s_leaf, gas_only, a.x, a.y, a.z, vp, h, want_div, want_phi, s);
     } else {
-      const bool wok = walk_leaves(A, root, pb, c.R, gas_only, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
-        sink_leaf_sums(A, nl, s_leaf, gas_only, a.x, a.y, a.z, vp, h, want_div, want_phi, s);
-        return true;
-      });
+      const bool wok = walk_leaves(
+          A, root, pb, c.R, gas_only, s_stack, s_leaf, s_snk, kWave,
+          [&](int nl, bool) {
+            sink_leaf_sums(A, nl, s_leaf, gas_only, a.x, a.y, a.z, vp, h, want_div, want_phi, s);
+            return true;
+          },
+          true);
       if (!wok) {
         fail = true;
         break;
