@@ -800,12 +800,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Contribution of candidate q to the sums of the sink at (px, py, pz).
-__device__ __forceinline__ void add_candidate(const DensArgs &A, int q, bool gas_only, double px, double py, double pz,
-                                              const double4 &vp, double ih, double ih3, double ih4, double R2,
-                                              bool want_div, bool want_phi, Sums &s) {
-  if (gas_only && !A.gas[q]) return;
-  const double4 a = A.pm[q];
+// Contribution of a candidate (position and mass a, predicted velocity v;
+// skip: filtered out) to the sums of the sink at (px, py, pz).
+__device__ __forceinline__ void add_candidate(const double4 &a, const double4 &v, bool skip, double px, double py,
+                                              double pz, const double4 &vp, double ih, double ih3, double ih4,
+                                              double R2, bool want_div, bool want_phi, Sums &s) {
+  if (skip) return;
   const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
   if (!(r2 < R2)) return;
   const double r = r2 > 0.0 ? r2 * rsqrt(r2) : 0.0;
@@ -820,22 +820,40 @@ __device__ __forceinline__ void add_candidate(const DensArgs &A, int q, bool gas
   s.msdh += a.w * dWdh;
   if (want_phi) s.mdphi += a.w * soft_pe_q(qq, ih);
   if (want_div && r > 0.0) {
-    const double4 v = A.vu[q];
     const double g = dw * ih4 * (ih / qq);
     s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
   }
 }
 
+// Loads of one candidate (position and mass, predicted velocity, filter).
+struct CandLoad {
+  double4 a, v;
+  bool skip;
+};
+
+__device__ __forceinline__ CandLoad load_candidate(const DensArgs &A, int q, bool gas_only, bool want_div) {
+  CandLoad c;
+  c.skip = gas_only && !A.gas[q];
+  c.a = A.pm[q];
+  c.v = want_div ? A.vu[q] : make_double4(0.0, 0.0, 0.0, 0.0);
+  return c;
+}
+
 // Kernel sums of one sink over the particles of the leaves leaf[0, nleaf),
-// packed 64 to a round, one candidate per lane (per-lane partial sums).
-__device__ void sink_leaf_sums(const DensArgs &A, int nleaf, const int *leaf, bool gas_only, double px, double py,
-                               double pz, const double4 &vp, double h, bool want_div, bool want_phi, Sums &s) {
+// packed 64 to a round, one candidate per lane (per-lane partial sums).  The
+// candidates of four rounds are loaded together before any of them is
+// evaluated (more loads in flight per lane); the rounds are evaluated in
+// order, so the sums do not depend on the grouping.
+__device__ __forceinline__ void sink_leaf_sums(const DensArgs &A, int nleaf, const int *leaf, bool gas_only,
+                                               double px, double py, double pz, const double4 &vp, double h,
+                                               bool want_div, bool want_phi, Sums &s) {
   const int ln = lane();
   const double ih = 1.0 / h;
   const double ih3 = ih * ih * ih / kPi;
   const double ih4 = ih3 * ih;
   const double R2 = (2.0 * h) * (2.0 * h);
-  int fill = 0, rq = 0;
+  int fill = 0, rq = 0, nr = 0;
+  int q0 = 0, q1 = 0, q2 = 0;  // candidates of the pending full rounds
   for (int c1 = 0; c1 < nleaf; c1 += kWave) {
     const int nc = min(kWave, nleaf - c1);
     const NodeTopo my = ln < nc ? A.topo[leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
@@ -848,17 +866,46 @@ __device__ void sink_leaf_sums(const DensArgs &A, int nleaf, const int *leaf, bo
         fill += tk;
         off += tk;
         if (fill == kWave) {
-          add_candidate(A, rq, gas_only, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
           fill = 0;
+          if (nr == 0) q0 = rq;
+          else if (nr == 1) q1 = rq;
+          else if (nr == 2) q2 = rq;
+          if (++nr == 4) {
+            const CandLoad c0 = load_candidate(A, q0, gas_only, want_div);
+            const CandLoad c1 = load_candidate(A, q1, gas_only, want_div);
+            const CandLoad c2 = load_candidate(A, q2, gas_only, want_div);
+            const CandLoad c3 = load_candidate(A, rq, gas_only, want_div);
+            add_candidate(c0.a, c0.v, c0.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+            add_candidate(c1.a, c1.v, c1.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+            add_candidate(c2.a, c2.v, c2.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+            add_candidate(c3.a, c3.v, c3.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+            nr = 0;
+          }
         }
       }
     }
   }
-  if (ln < fill) add_candidate(A, rq, gas_only, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+  // pending full rounds, in order, then the partial round
+  if (nr > 0) {
+    const CandLoad c = load_candidate(A, q0, gas_only, want_div);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+  }
+  if (nr > 1) {
+    const CandLoad c = load_candidate(A, q1, gas_only, want_div);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+  }
+  if (nr > 2) {
+    const CandLoad c = load_candidate(A, q2, gas_only, want_div);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+  }
+  if (ln < fill) {
+    const CandLoad c = load_candidate(A, rq, gas_only, want_div);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+  }
 }
 
 // One self-consistent length of one sink (wave-uniform).
-__device__ SolveOut solve_one(const DensArgs &A, int p, int root, bool gas_only, double eta, double guess, bool cold,
+__device__ __forceinline__ SolveOut solve_one(const DensArgs &A, int p, int root, bool gas_only, double eta, double guess, bool cold,
                               const double4 &a, const double4 &vp, bool want_div, bool want_phi, int *s_stack,
                               int *s_leaf, double4 *s_snk) {
   SolveOut o;
