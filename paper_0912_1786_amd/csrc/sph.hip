@@ -20,6 +20,10 @@
 // tests the whole tile and keeps a mask of its own pairs, and then each lane
 // evaluates only its own pairs, in candidate order, reading the partner's
 // record itself; lanes do not step through pairs that only other lanes have.
+// Once a batch has evaluated split_leaves x leaf_size candidates itself, its
+// further flushes go as work items (the flush's leaf ranges) to
+// k_sph_split, and k_sph_reduce adds the items' partial sums to the batch's
+// sinks along each batch's item chain, in creation order.
 #include <stdio.h>
 
 #include "tsph_internal.h"
@@ -64,7 +68,160 @@ struct SphArgs {
   int32_t dbg_max;
   double alpha, beta, av_eps2;
   int32_t tc92;
+  // hand-off of flushes (0 split_particles: none); the buffers are those of
+  // the gravity walk's near-field hand-off, free again by now
+  int32_t split_particles;
+  int64_t split_cap;  // items; each keeps two partial records per lane
+  int2 *split_rng;
+  SplitItem *split_item;
+  double4 *split_part;
+  int32_t *split_head;
 };
+
+// The sink side of the pairs of one lane: particle p (a gas sink when
+// `sink`), its accumulated sums and its debug list.
+struct SphLane {
+  double4 a;   // x, y, z, m
+  double4 v;   // predicted velocity, u
+  double4 hd;  // h, rho, c, P/rho^2
+  double zi;   // zeta / Omega*
+  double ax, ay, az, du, mumax;
+  int p, npair, ndbg;
+  bool sink;
+  int32_t *dbg;
+};
+
+__device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bool sink) {
+  L.p = p;
+  L.sink = sink;
+  L.a = A.pm[p];
+  L.v = A.vu[p];
+  L.hd = A.sph[p];
+  L.zi = A.zo[p];
+  L.ax = L.ay = L.az = L.du = L.mumax = 0.0;
+  L.npair = 0;
+  L.ndbg = 0;
+  L.dbg = (A.dbg && sink) ? A.dbg + ((int64_t)1 * A.cap_n + A.perm[p]) * A.dbg_max : nullptr;
+}
+
+// Pairs of the lane's sink among the nt staged candidates: the distance
+// tests of the whole tile first, then the lane's own pairs in tile order.
+__device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const SphTile &T, int nt, bool tc) {
+  const double hi = L.hd.x;
+  uint64_t mask = 0;
+  for (int j = 0; j < nt; j++) {
+    const double4 b = T.pos[j];
+    const double r2x = dist2_pair(L.a.x, L.a.y, L.a.z, b.x, b.y, b.z);
+    const double R = 2.0 * fmax(hi, b.w);
+    if (L.sink && T.q[j] != L.p && r2x < R * R) mask |= 1ull << j;
+  }
+  const double ihi = 1.0 / hi, imi = 1.0 / L.a.w;
+  const double ihi4 = ihi * ihi * ihi * ihi * kInvPiS;
+  while (mask) {
+    const int j = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const int q = T.q[j];
+    const SphRec b = A.srec[q];
+    if (L.dbg) {
+      if (L.ndbg < A.dbg_max) L.dbg[L.ndbg] = A.perm[q];
+      L.ndbg++;
+    }
+    L.npair++;
+    const double dx = L.a.x - b.x, dy = L.a.y - b.y, dz = L.a.z - b.z;
+    const double r2 = dist2_pair(L.a.x, L.a.y, L.a.z, b.x, b.y, b.z);
+    if (!(r2 > 0.0)) continue;
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
+    const double ihj2 = b.ih * b.ih;
+    const double gi = m4_grad(r * ihi, tc) * ihi4 * ir;
+    const double gj = m4_grad(r * b.ih, tc) * (ihj2 * ihj2 * kInvPiS) * ir;
+    const double mj = b.m;
+    const double fij = 1.0 + L.zi * b.im;
+    const double fji = 1.0 + b.zo * imi;
+    const double Ai = L.hd.w * fij;
+    const double Aj = b.pr2 * fji;
+    const double vx = L.v.x - b.vx, vy = L.v.y - b.vy, vz = L.v.z - b.vz;
+    const double vd = vx * dx + vy * dy + vz * dz;
+    double sf = mj * (Ai * gi + Aj * gj);
+    double e = mj * Ai * gi * vd;
+    if (vd < 0.0) {
+      const double hb = 0.5 * (hi + b.h);
+      const double mu = hb * vd / (r2 + A.av_eps2 * hb * hb);
+      const double cb = 0.5 * (L.hd.z + b.c);
+      const double rb = 0.5 * (L.hd.y + b.rho);
+      const double Pi = (-A.alpha * cb * mu + A.beta * mu * mu) / rb;
+      const double Gb = 0.5 * (fij * gi + fji * gj);
+      sf += mj * Pi * Gb;
+      e += 0.5 * mj * Pi * Gb * vd;
+      L.mumax = fmax(L.mumax, fabs(mu));
+    }
+    L.ax -= sf * dx;
+    L.ay -= sf * dy;
+    L.az -= sf * dz;
+    L.du += e;
+  }
+  __syncthreads();
+}
+
+// Candidate q of this lane's slot staged for the pair tests (non-gas at
+// infinity).
+__device__ __forceinline__ void stage_sph(const SphArgs &A, SphTile &T, int nt, int q) {
+  const int ln = lane();
+  if (ln < nt) {
+    const bool g = A.gas[q] != 0;
+    const SphRec *r = A.srec + q;
+    T.pos[ln] = g ? make_double4(r->x, r->y, r->z, r->h) : make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+    T.q[ln] = g ? q : -1;
+  }
+  __syncthreads();
+}
+
+// particle ranges (first, count) of listed leaves, or given explicitly
+struct SphLeafSrc {
+  const NodeTopo *topo;
+  const int *leaf;
+  __device__ int2 operator()(int i) const {
+    const NodeTopo t = topo[leaf[i]];
+    return make_int2(t.first, t.count);
+  }
+};
+struct SphRangeSrc {
+  const int2 *rng;
+  __device__ int2 operator()(int i) const { return rng[i]; }
+};
+
+// Pairs of the lane's sink with the particles of ranges [0, n), packed 64
+// to a tile in range order.  Returns the number of particles scanned.
+template <class Src>
+__device__ __forceinline__ int sph_ranges(const SphArgs &A, SphLane &L, SphTile &T, const Src &src, int n, bool tc) {
+  const int ln = lane();
+  int fill = 0, rq = 0, scanned = 0;
+  for (int c1 = 0; c1 < n; c1 += kWave) {
+    const int nc = min(kWave, n - c1);
+    const int2 my = ln < nc ? src(c1 + ln) : make_int2(0, 0);
+    for (int j = 0; j < nc; j++) {
+      const int first = __builtin_amdgcn_readlane(my.x, j);
+      const int count = __builtin_amdgcn_readlane(my.y, j);
+      scanned += count;
+      for (int off = 0; off < count;) {
+        const int tk = min(count - off, kWave - fill);
+        if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
+        fill += tk;
+        off += tk;
+        if (fill == kWave) {
+          stage_sph(A, T, kWave, rq);
+          tile_pairs(A, L, T, kWave, tc);
+          fill = 0;
+        }
+      }
+    }
+  }
+  if (fill > 0) {
+    stage_sph(A, T, fill, rq);
+    tile_pairs(A, L, T, fill, tc);
+  }
+  return scanned;
+}
 
 __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
   __shared__ int s_stack[kSStackCap];
@@ -86,26 +243,20 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
     const NodeTopo gnd{bt.first, bt.count, -1, 0};
     const NodeBox gb = bt.box;
     const double ghmax = gb.hmax;
+    int prev_item = -1;  // last handed-off item of this batch
     for (int c0 = 0; c0 < gnd.count; c0 += kWave) {
       const bool act = c0 + ln < gnd.count;
       const int p = gnd.first + c0 + (act ? ln : 0);
-      const bool sink = act && A.gas[p];
-      const double4 a = A.pm[p];
-      const double4 v = A.vu[p];
-      const double4 hd = A.sph[p];  // h, rho, c, P/rho^2
-      const double zi = A.zo[p];
-      const double hi = hd.x;
-      const double mi = a.w;
-      double ax = 0.0, ay = 0.0, az = 0.0, du = 0.0, mumax = 0.0;
-      int npair = 0;
-      int32_t *dbg = (A.dbg && sink) ? A.dbg + ((int64_t)1 * A.cap_n + A.perm[p]) * A.dbg_max : nullptr;
-      int ndbg = 0;
+      SphLane L;
+      sph_lane(A, L, p, act && A.gas[p]);
+      const double hi = L.hd.x;
+      int done = 0;  // candidates evaluated by this wave
       int sp = 1, nleaf = 0;
       bool overflow = false;
       int rounds = 0;
       const int guard = *A.nnodes + 2;
       if (ln == 0) s_stack[0] = bt.root;
-      s_snk[ln] = make_double4(a.x, a.y, a.z, sink ? 2.0 * hi : 0.0);
+      s_snk[ln] = make_double4(L.a.x, L.a.y, L.a.z, L.sink ? 2.0 * hi : 0.0);
       __syncthreads();
       for (;;) {
         if (sp > 0 && ++rounds > guard) {
@@ -149,111 +300,104 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
         }
         const bool last = (sp == 0) || overflow;
         if (nleaf >= kSLeafFlush || (last && nleaf > 0)) {
-          const double ihi = 1.0 / hi, imi = 1.0 / mi;
-          const double ihi4 = ihi * ihi * ihi * ihi * kInvPiS;
-          // pairs of this lane among nt staged candidates
-          auto tile_pairs = [&](int nt) {
-            uint64_t mask = 0;
-            for (int j = 0; j < nt; j++) {
-              const double4 b = s_t.pos[j];
-              const double r2x = dist2_pair(a.x, a.y, a.z, b.x, b.y, b.z);
-              const double R = 2.0 * fmax(hi, b.w);
-              if (sink && s_t.q[j] != p && r2x < R * R) mask |= 1ull << j;
+          bool handed = false;
+          if (A.split_particles > 0 && done >= A.split_particles) {
+            // this flush's leaves as one work item for k_sph_split
+            int rb = 0, it = 0;
+            if (ln == 0) {
+              rb = atomicAdd(&A.work[34], nleaf);
+              it = rb + nleaf <= A.split_cap * kSplitItemRanges ? atomicAdd(&A.work[35], 1) : INT32_MAX;
             }
-            while (mask) {
-              const int j = __builtin_ctzll(mask);
-              mask &= mask - 1;
-              const int q = s_t.q[j];
-              const SphRec b = A.srec[q];
-              if (dbg) {
-                if (ndbg < A.dbg_max) dbg[ndbg] = A.perm[q];
-                ndbg++;
+            rb = __shfl(rb, 0, kWave);
+            it = __shfl(it, 0, kWave);
+            if (it < A.split_cap) {
+              for (int a = ln; a < nleaf; a += kWave) {
+                const NodeTopo t = A.topo[s_leaf[a]];
+                A.split_rng[rb + a] = make_int2(t.first, t.count);
               }
-              npair++;
-              const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-              const double r2 = dist2_pair(a.x, a.y, a.z, b.x, b.y, b.z);
-              if (!(r2 > 0.0)) continue;
-              const double ir = rsqrt(r2);
-              const double r = r2 * ir;
-              const double ihj2 = b.ih * b.ih;
-              const double gi = m4_grad(r * ihi, tc) * ihi4 * ir;
-              const double gj = m4_grad(r * b.ih, tc) * (ihj2 * ihj2 * kInvPiS) * ir;
-              const double mj = b.m;
-              const double fij = 1.0 + zi * b.im;
-              const double fji = 1.0 + b.zo * imi;
-              const double Ai = hd.w * fij;
-              const double Aj = b.pr2 * fji;
-              const double vx = v.x - b.vx, vy = v.y - b.vy, vz = v.z - b.vz;
-              const double vd = vx * dx + vy * dy + vz * dz;
-              double sf = mj * (Ai * gi + Aj * gj);
-              double e = mj * Ai * gi * vd;
-              if (vd < 0.0) {
-                const double hb = 0.5 * (hi + b.h);
-                const double mu = hb * vd / (r2 + A.av_eps2 * hb * hb);
-                const double cb = 0.5 * (hd.z + b.c);
-                const double rb = 0.5 * (hd.y + b.rho);
-                const double Pi = (-A.alpha * cb * mu + A.beta * mu * mu) / rb;
-                const double Gb = 0.5 * (fij * gi + fji * gj);
-                sf += mj * Pi * Gb;
-                e += 0.5 * mj * Pi * Gb * vd;
-                mumax = fmax(mumax, fabs(mu));
+              if (ln == 0) {
+                A.split_item[it] = SplitItem{g, c0, rb, nleaf, -1, 0, 0, 0};
+                if (prev_item >= 0) A.split_item[prev_item].next = it;
+                else A.split_head[g] = it;
               }
-              ax -= sf * dx;
-              ay -= sf * dy;
-              az -= sf * dz;
-              du += e;
-            }
-            __syncthreads();
-          };
-          // candidates in leaf order, packed 64 to a tile, one per lane
-          auto stage = [&](int nt, int q) {
-            if (ln < nt) {
-              const bool g = A.gas[q] != 0;
-              const SphRec *r = A.srec + q;
-              s_t.pos[ln] = g ? make_double4(r->x, r->y, r->z, r->h) : make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-              s_t.q[ln] = g ? q : -1;
-            }
-            __syncthreads();
-          };
-          int fill = 0, rq = 0;
-          for (int c1 = 0; c1 < nleaf; c1 += kWave) {
-            const int nc = min(kWave, nleaf - c1);
-            const NodeTopo my = ln < nc ? A.topo[s_leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
-            for (int j = 0; j < nc; j++) {
-              const int first = __builtin_amdgcn_readlane(my.first, j);
-              const int count = __builtin_amdgcn_readlane(my.count, j);
-              for (int off = 0; off < count;) {
-                const int tk = min(count - off, kWave - fill);
-                if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
-                fill += tk;
-                off += tk;
-                if (fill == kWave) {
-                  stage(kWave, rq);
-                  tile_pairs(kWave);
-                  fill = 0;
-                }
-              }
+              prev_item = it;
+              handed = true;
             }
           }
-          if (fill > 0) {
-            stage(fill, rq);
-            tile_pairs(fill);
-          }
+          if (!handed) done += sph_ranges(A, L, s_t, SphLeafSrc{A.topo, s_leaf}, nleaf, tc);
           nleaf = 0;
         }
         __syncthreads();
         if (last) break;
       }
       if (overflow) atomicOr(A.flags, TSPH_FLAG_STACK_OVERFLOW);
-      if (dbg && ndbg > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
-      if (sink) {
-        A.acc[0 * A.cap_n + p] += ax;
-        A.acc[1 * A.cap_n + p] += ay;
-        A.acc[2 * A.cap_n + p] += az;
-        A.acc[4 * A.cap_n + p] = du;
-        A.solve[kMaxmu * A.cap_n + p] = mumax;
-        A.cnt[2 * A.cap_n + A.perm[p]] = npair;
+      if (L.dbg && L.ndbg > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
+      if (L.sink) {
+        A.acc[0 * A.cap_n + p] += L.ax;
+        A.acc[1 * A.cap_n + p] += L.ay;
+        A.acc[2 * A.cap_n + p] += L.az;
+        A.acc[4 * A.cap_n + p] = L.du;
+        A.solve[kMaxmu * A.cap_n + p] = L.mumax;
+        A.cnt[2 * A.cap_n + A.perm[p]] = L.npair;
       }
+    }
+  }
+}
+
+// The handed-off flushes: each item's ranges on the sinks of its batch
+// chunk; per-lane partial sums to split_part (two records per lane).
+__global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
+  __shared__ int2 s_rng[kSplitItemRanges];
+  __shared__ SphTile s_t;
+  __shared__ int s_i;
+  const int ln = lane();
+  const bool tc = A.tc92 != 0;
+  const int nitems = (int)min((int64_t)A.work[35], A.split_cap);
+  for (;;) {
+    if (ln == 0) s_i = atomicAdd(&A.work[36], 1);
+    __syncthreads();
+    const int it = s_i;
+    __syncthreads();
+    if (it >= nitems) break;
+    const SplitItem I = A.split_item[it];
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, I.g);
+    const bool act = I.c0 + ln < bt.count;
+    const int p = bt.first + I.c0 + (act ? ln : 0);
+    SphLane L;
+    sph_lane(A, L, p, act && A.gas[p]);
+    L.dbg = nullptr;
+    for (int a = ln; a < I.count; a += kWave) s_rng[a] = A.split_rng[I.start + a];
+    __syncthreads();
+    sph_ranges(A, L, s_t, SphRangeSrc{s_rng}, I.count, tc);
+    A.split_part[(int64_t)(2 * it) * kWave + ln] = make_double4(L.ax, L.ay, L.az, L.du);
+    A.split_part[(int64_t)(2 * it + 1) * kWave + ln] = make_double4(L.mumax, (double)L.npair, 0.0, 0.0);
+  }
+}
+
+// Adds the items' partial sums to each batch's sinks along the batch's item
+// chain (creation order).
+__global__ __launch_bounds__(64) void k_sph_reduce(SphArgs A) {
+  const int ln = lane();
+  const int ng = *A.nbatches;
+  for (int g = blockIdx.x; g < ng; g += gridDim.x) {
+    int it = A.split_head[g];
+    if (it < 0) continue;
+    const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, g);
+    int guard = 0;
+    while (it >= 0 && it < A.split_cap && ++guard <= A.split_cap) {
+      const SplitItem I = A.split_item[it];
+      const int p = bt.first + I.c0 + ln;
+      if (I.c0 + ln < bt.count && A.gas[p]) {
+        const double4 v = A.split_part[(int64_t)(2 * it) * kWave + ln];
+        const double4 w = A.split_part[(int64_t)(2 * it + 1) * kWave + ln];
+        A.acc[0 * A.cap_n + p] += v.x;
+        A.acc[1 * A.cap_n + p] += v.y;
+        A.acc[2 * A.cap_n + p] += v.z;
+        A.acc[4 * A.cap_n + p] += v.w;
+        A.solve[kMaxmu * A.cap_n + p] = fmax(A.solve[kMaxmu * A.cap_n + p], w.x);
+        A.cnt[2 * A.cap_n + A.perm[p]] += (int)w.y;
+      }
+      it = I.next;
     }
   }
 }
@@ -308,7 +452,21 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   A.beta = c->p.beta;
   A.av_eps2 = c->p.av_eps2;
   A.tc92 = c->p.tc92;
+  // debug lists are written in the batch's own order: no hand-off then
+  A.split_particles = c->dbg_nbr ? 0 : c->p.split_leaves * c->p.leaf_size;
+  A.split_cap = c->split_cap / 2;
+  A.split_rng = c->split_rng;
+  A.split_item = c->split_item;
+  A.split_part = c->split_part;
+  A.split_head = c->split_head;
+  if (A.split_particles > 0)
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(c->cap_nodes, 256, 4096)), dim3(256), 0, st, c->cap_nodes,
+                       c->split_head, -1);
   hipLaunchKernelGGL(k_sph, dim3(persistent_blocks(c, (const void *)k_sph)), dim3(64), 0, st, A);
+  if (A.split_particles > 0) {
+    hipLaunchKernelGGL(k_sph_split, dim3(persistent_blocks(c, (const void *)k_sph_split)), dim3(64), 0, st, A);
+    hipLaunchKernelGGL(k_sph_reduce, dim3(4096), dim3(64), 0, st, A);
+  }
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

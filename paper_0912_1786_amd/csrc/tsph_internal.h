@@ -178,7 +178,7 @@ struct Ctx {
   int32_t *scan_part;     // scan block sums
   int32_t *work;          // kWorkCounters work-queue counters: 3 split leaves, 4 split items, 5 split walk,
                           // 6 handed-off density batches, 7 their sinks, 8/16/24 the XCD queues of the
-                          // density, gravity and SPH walks (8 each)
+                          // density, gravity and SPH walks (8 each), 34/35/36 SPH hand-off ranges, items, split walk
   int2 *split_rng;        // split_cap x kSplitItemRanges particle ranges handed from batches' near fields
   SplitItem *split_item;  // split_cap work items over split_rng
   double4 *split_part;    // split_cap x 64 partial (ax, ay, az, pot) of the items
