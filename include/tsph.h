@@ -108,7 +108,10 @@ typedef struct {
                           * in a fixed order.  A batch whose density candidates
                           * span more leaves (or overflow the on-chip list) is
                           * solved one sink per wavefront, the lanes sharing
-                          * the sink's candidates.                            */
+                          * the sink's candidates.  An SPH batch evaluates a
+                          * quarter of that many candidate particles itself
+                          * and hands its further leaves on in the same way
+                          * as the gravity near field.                        */
   double eta_dt;       /* time-step coefficient of the Sect. 4.2 criteria      */
   int32_t max_members; /* independent systems one context can hold
                           * (tsph_set_members); 1 by default                  */

@@ -20,8 +20,8 @@
 // tests the whole tile and keeps a mask of its own pairs, and then each lane
 // evaluates only its own pairs, in candidate order, reading the partner's
 // record itself; lanes do not step through pairs that only other lanes have.
-// Once a batch has evaluated split_leaves x leaf_size candidates itself, its
-// further flushes go as work items (the flush's leaf ranges) to
+// Once a batch has evaluated split_leaves x leaf_size / 4 candidates itself,
+// its further flushes go as work items (the flush's leaf ranges) to
 // k_sph_split, and k_sph_reduce adds the items' partial sums to the batch's
 // sinks along each batch's item chain, in creation order.
 #include <stdio.h>
@@ -452,8 +452,10 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   A.beta = c->p.beta;
   A.av_eps2 = c->p.av_eps2;
   A.tc92 = c->p.tc92;
-  // debug lists are written in the batch's own order: no hand-off then
-  A.split_particles = c->dbg_nbr ? 0 : c->p.split_leaves * c->p.leaf_size;
+  // debug lists are written in the batch's own order: no hand-off then.  The
+  // SPH pairs cost more per candidate than the near-field gravity pairs, so
+  // the batch keeps a quarter of the gravity walk's share.
+  A.split_particles = c->dbg_nbr ? 0 : c->p.split_leaves * c->p.leaf_size / 4;
   A.split_cap = c->split_cap / 2;
   A.split_rng = c->split_rng;
   A.split_item = c->split_item;
