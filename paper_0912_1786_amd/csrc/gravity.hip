@@ -83,26 +83,26 @@ __device__ __forceinline__ void far_field(const GravArgs &A, Sink &s, const Node
   const double ir = rsqrt(r2);
   const double ir2 = ir * ir;
   const double ir3 = ir * ir2;
-  double fm = f.m * ir3;
-  double ph = f.m * ir;
-  double ex = 0.0, ey = 0.0, ez = 0.0;
   if (M & kQuad) {
     const double qx = f.qxx * dx + f.qxy * dy + f.qxz * dz;
     const double qy = f.qxy * dx + f.qyy * dy + f.qyz * dz;
     const double qz = f.qxz * dx + f.qyz * dy + f.qzz * dz;
     const double rqr = dx * qx + dy * qy + dz * qz;
     const double ir5 = ir3 * ir2;
-    const double ir7 = ir5 * ir2;
-    fm += 2.5 * rqr * ir7;
-    ex = qx * ir5;
-    ey = qy * ir5;
-    ez = qz * ir5;
-    ph += 0.5 * rqr * ir5;
+    const double t = rqr * (ir2 * ir2);  // r.Q.r / r^4
+    // a = G [Q.r / r^5 - (m + 5/2 r.Q.r / r^4) r / r^3], as fused steps
+    const double fm = ir3 * fma(2.5, t, f.m);
+    s.ax = fma(A.G, fma(qx, ir5, -fm * dx), s.ax);
+    s.ay = fma(A.G, fma(qy, ir5, -fm * dy), s.ay);
+    s.az = fma(A.G, fma(qz, ir5, -fm * dz), s.az);
+    if (M & kPot) s.pot -= A.G * (ir * fma(0.5, t, f.m));
+  } else {
+    const double fm = A.G * f.m * ir3;
+    s.ax = fma(-fm, dx, s.ax);
+    s.ay = fma(-fm, dy, s.ay);
+    s.az = fma(-fm, dz, s.az);
+    if (M & kPot) s.pot -= A.G * f.m * ir;
   }
-  s.ax += A.G * (ex - fm * dx);
-  s.ay += A.G * (ey - fm * dy);
-  s.az += A.G * (ez - fm * dz);
-  if (M & kPot) s.pot -= A.G * ph;
 }
 
 template <int M>
@@ -233,26 +233,26 @@ __device__ __forceinline__ void far_field32(Sink32 &s, const NodeF32 &f) {
   const float ir = rsqrtf(r2);
   const float ir2 = ir * ir;
   const float ir3 = ir * ir2;
-  float fm = f.m * ir3;
-  float ph = f.m * ir;
-  float ex = 0.0f, ey = 0.0f, ez = 0.0f;
   if (M & kQuad) {
     const float qx = f.qxx * dx + f.qxy * dy + f.qxz * dz;
     const float qy = f.qxy * dx + f.qyy * dy + f.qyz * dz;
     const float qz = f.qxz * dx + f.qyz * dy + f.qzz * dz;
     const float rqr = dx * qx + dy * qy + dz * qz;
     const float ir5 = ir3 * ir2;
-    const float ir7 = ir5 * ir2;
-    fm += 2.5f * rqr * ir7;
-    ex = qx * ir5;
-    ey = qy * ir5;
-    ez = qz * ir5;
-    ph += 0.5f * rqr * ir5;
+    const float t = rqr * (ir2 * ir2);  // r.Q.r / r^4
+    // a = Q.r / r^5 - (m + 5/2 r.Q.r / r^4) r / r^3, as fused steps
+    const float fm = ir3 * fmaf(2.5f, t, f.m);
+    s.tax = fmaf(qx, ir5, fmaf(-fm, dx, s.tax));
+    s.tay = fmaf(qy, ir5, fmaf(-fm, dy, s.tay));
+    s.taz = fmaf(qz, ir5, fmaf(-fm, dz, s.taz));
+    if (M & kPot) s.tpot -= ir * fmaf(0.5f, t, f.m);
+  } else {
+    const float fm = f.m * ir3;
+    s.tax = fmaf(-fm, dx, s.tax);
+    s.tay = fmaf(-fm, dy, s.tay);
+    s.taz = fmaf(-fm, dz, s.taz);
+    if (M & kPot) s.tpot -= f.m * ir;
   }
-  s.tax += ex - fm * dx;
-  s.tay += ey - fm * dy;
-  s.taz += ez - fm * dz;
-  if (M & kPot) s.tpot -= ph;
 }
 
 template <int M>
