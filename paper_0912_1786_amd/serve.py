@@ -57,15 +57,53 @@ def population(n_sim: int = 64, seed: int = 2000, lo_log2: float = 12.0, hi_log2
     return out
 
 
+def capacity_class(n: int) -> int:
+    """Shell capacity for a simulation of n particles: the next power of two
+    (at least 2^12), so that simulations of similar size share shells."""
+    return 1 << max(12, (int(n) - 1).bit_length())
+
+
+class Shell:
+    """A context and device buffers for up to `cap` particles, reused by the
+    simulations admitted into it one after another (no allocation, no
+    device-wide synchronisation on admission or eviction).  Keeps the
+    captured step of each simulation that has run in it."""
+
+    NAMES = tuple(k for k in tsph.Simulation.FIELDS if k != "pot")
+
+    def __init__(self, cap: int, params):
+        import torch
+        self.cap = cap
+        self.ctx = tsph.tsph_create(cap, params)
+        dev = torch.device("cuda")
+        self.bufs = {k: torch.zeros(cap, dtype=torch.float64, device=dev) for k in self.NAMES}
+        self.bufs["dt"] = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.bufs["diag"] = torch.zeros(9, dtype=torch.float64, device=dev)
+        self.graphs = {}  # simulation id -> its captured step in this shell
+        self.last_use = 0.0
+
+    @staticmethod
+    def bytes_for(cap: int, params) -> int:
+        return tsph.tsph_bytes_required(cap, params) + 8 * (len(Shell.NAMES) * cap + 10)
+
+    def close(self):
+        self.graphs.clear()
+        if self.ctx is not None:
+            tsph.tsph_destroy(self.ctx)
+            self.ctx = None
+        self.bufs = None
+
+
 class Resident:
-    """One simulation: its initial conditions, and while admitted its
-    device state and context."""
+    """One simulation: its initial conditions, and while admitted the shell
+    holding its device state."""
 
     def __init__(self, sid: int, ic: dict, params):
         self.sid, self.ic, self.params = sid, ic, params
-        self.sim = None          # tsph.Simulation while resident
+        self.sim = None          # tsph.Simulation in a shell while resident
+        self.shell = None
         self.graph = None        # its captured step while resident
-        self.saved = None        # host copy of the state while evicted
+        self.saved = None        # pinned host copy of the state while evicted
         self.busy = False
         self.steps = 0
         self.last_use = 0.0
@@ -75,28 +113,34 @@ class Resident:
         return int(self.ic["n"])
 
     def bytes(self) -> int:
-        return tsph.tsph_bytes_required(self.n, self.params) + 8 * len(HOST_KEYS) * self.n
+        return Shell.bytes_for(capacity_class(self.n), self.params)
 
-    def admit(self, capture_stream=None):
+    def admit(self, shell: Shell, capture_stream=None):
         import torch
         if self.sim is not None:
             return
-        self.sim = tsph.Simulation(self.ic, self.params, want_pot=False)
         if self.saved is None:
+            self.sim = tsph.Simulation(self.ic, self.params, want_pot=False, ctx=shell.ctx, bufs=shell.bufs)
             self.sim.compute_forces()  # cold start: lengths and forces of the initial state
         else:
             # the state and the context's carry to the next step: the
             # simulation continues exactly where it left the device
+            src = dict(self.saved, n=self.n, n_gas=int(self.ic["n_gas"]))
+            self.sim = tsph.Simulation(src, self.params, want_pot=False, ctx=shell.ctx, bufs=shell.bufs)
             for k in HOST_KEYS:
-                self.sim.a[k].copy_(torch.from_numpy(self.saved[k]))
+                self.sim.a[k].copy_(self.saved[k])
             self.sim.load_carry(self.saved["carry"])
-            self.saved = None
-        torch.cuda.synchronize()
-        if capture_stream is not None:
+        self.shell = shell
+        g = shell.graphs.get(self.sid) if capture_stream is not None else None
+        if g is None and capture_stream is not None:
+            capture_stream.wait_stream(torch.cuda.current_stream())
             g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=capture_stream):
+            with torch.cuda.stream(capture_stream):
+                g.capture_begin()
                 self.sim.device_step(capture_stream)
-            self.graph = g
+                g.capture_end()
+            shell.graphs[self.sid] = g
+        self.graph = g
 
     def launch(self, stream):
         """Issues one step on `stream`: the captured graph, or the calls."""
@@ -107,15 +151,22 @@ class Resident:
         else:
             self.sim.device_step(stream)
 
-    def evict(self):
-        """Moves the state to host memory and frees the device context."""
-        if self.sim is None:
-            return
-        self.saved = {k: self.sim.host(k) for k in HOST_KEYS}
-        self.saved["carry"] = self.sim.carry()
-        self.graph = None
-        self.sim.close()
-        self.sim = None
+    def evict(self) -> Shell:
+        """Moves the state to pinned host memory and hands back the shell."""
+        import torch
+        if self.saved is None:
+            self.saved = {k: torch.empty(self.n, dtype=torch.float64, pin_memory=True) for k in HOST_KEYS}
+        for k in HOST_KEYS:
+            self.saved[k].copy_(self.sim.a[k], non_blocking=True)
+        self.saved["carry"] = self.sim.carry()  # synchronises the stream: the copies are done too
+        shell = self.shell
+        self.sim.close()  # borrowed context: left as it is
+        self.sim, self.shell, self.graph = None, None, None
+        return shell
+
+    def host(self, k):
+        """Host copy of array k of the state, resident or not."""
+        return self.sim.host(k) if self.sim is not None else self.saved[k].numpy().copy()
 
 
 class Server:
@@ -124,34 +175,62 @@ class Server:
         import torch
         self.torch = torch
         self.res = []
+        self.params = tsph.tsph_default_params(nnei=50.0, precision=precision)
         for k, ic in enumerate(ics):
-            prm = tsph.tsph_default_params(nnei=50.0, precision=precision)
-            self.res.append(Resident(k, ic, prm))
+            self.res.append(Resident(k, ic, self.params))
         self.streams = [torch.cuda.Stream() for _ in range(max(1, streams))]
         self.capture_stream = torch.cuda.Stream() if graphs else None
         self.free = list(range(len(self.streams)))
         self.budget = hbm_budget
-        self.resident_bytes = 0
+        self.pool = []            # shells not holding a simulation
+        self.shell_bytes = 0      # all shells, in use or pooled
         self.evictions = 0
         self.admissions = 0
+        self.shells_made = 0
+
+    def _drop_pooled(self) -> bool:
+        """Destroys the least recently used pooled shell."""
+        if not self.pool:
+            return False
+        sh = min(self.pool, key=lambda x: x.last_use)
+        self.pool.remove(sh)
+        self.shell_bytes -= Shell.bytes_for(sh.cap, self.params)
+        sh.close()
+        return True
 
     def _ensure_resident(self, r: Resident, now: float) -> bool:
         """Admits r if needed; False when the budget cannot make room now."""
         if r.sim is not None:
             return True
-        need = r.bytes()
-        if self.budget is not None:
-            idle = sorted((x for x in self.res if x.sim is not None and not x.busy), key=lambda x: x.last_use)
-            while self.resident_bytes + need > self.budget and idle:
-                v = idle.pop(0)
-                self.torch.cuda.synchronize()
-                v.evict()
-                self.resident_bytes -= v.bytes()
-                self.evictions += 1
-            if self.resident_bytes + need > self.budget and any(x.sim is not None for x in self.res):
-                return False
-        r.admit(self.capture_stream)
-        self.resident_bytes += need
+        cap = capacity_class(r.n)
+        shell = next((x for x in self.pool if x.cap == cap), None)
+        if shell is None:
+            need = Shell.bytes_for(cap, self.params)
+            if self.budget is not None:
+                while self.shell_bytes + need > self.budget:
+                    if self._drop_pooled():
+                        continue
+                    idle = [x for x in self.res if x.sim is not None and not x.busy]
+                    if not idle:
+                        break
+                    v = min(idle, key=lambda x: x.last_use)
+                    sh = v.evict()
+                    sh.last_use = now
+                    self.evictions += 1
+                    if sh.cap == cap:
+                        shell = sh
+                        break
+                    self.pool.append(sh)
+                if shell is None and self.shell_bytes + need > self.budget and any(
+                        x.sim is not None for x in self.res):
+                    return False
+            if shell is None:
+                shell = Shell(cap, self.params)
+                self.shell_bytes += need
+                self.shells_made += 1
+        else:
+            self.pool.remove(shell)
+        r.admit(shell, self.capture_stream)
         self.admissions += 1
         return True
 
@@ -217,6 +296,7 @@ class Server:
                 stream = self.streams[slot]
                 r.busy = True
                 st = time.perf_counter() - t0
+                stream.wait_stream(torch.cuda.current_stream())  # the admission's own work
                 r.launch(stream)
                 ev = torch.cuda.Event()
                 ev.record(stream)
@@ -233,11 +313,14 @@ class Server:
         return [(r.sid, r.sim.flags()) for r in self.res if r.sim is not None]
 
     def close(self):
+        self.torch.cuda.synchronize()
         for r in self.res:
-            r.graph = None
             if r.sim is not None:
                 r.sim.close()
-                r.sim = None
+                self.pool.append(r.shell)
+                r.sim, r.shell, r.graph = None, None, None
+        while self._drop_pooled():
+            pass
 
 
 def poisson_arrivals(rate: float, count: int, n_sim: int, seed: int = 3):

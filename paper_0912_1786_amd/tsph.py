@@ -273,14 +273,17 @@ class Simulation:
     velocity/energy arrays start as copies of v and u (first evaluation).
     With ``members`` = [(n, n_gas), ...] (see concat_ics) the arrays hold
     that many independent systems back to back in one context; timestep()
-    and diagnostics() then return one entry per system.
+    and diagnostics() then return one entry per system.  With ``ctx`` and
+    ``bufs`` (a context of capacity >= n and one device float64 tensor of
+    length >= n per name of FIELDS, plus "dt" and "diag") the system lives
+    in that borrowed memory: nothing is allocated and close() leaves it.
     """
 
     FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "vpx", "vpy", "vpz", "up", "h", "eps", "ax", "ay", "az",
               "dudt", "rho", "pot")
 
     def __init__(self, ic: dict, params: Params | None = None, capacity: int | None = None, device: str = "cuda",
-                 want_pot: bool = True, eps_const=None, members=None):
+                 want_pot: bool = True, eps_const=None, members=None, ctx=None, bufs=None):
         import torch
         self.torch = torch
         self.n = int(ic["n"])
@@ -295,19 +298,27 @@ class Simulation:
         if members is not None:
             self.params.max_members = max(int(self.params.max_members), self.count)
         dev = torch.device(device)
-        t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
-        z = lambda: torch.zeros(self.n, dtype=torch.float64, device=dev)
+        n = self.n
+        if bufs is not None:
+            if ctx is None:
+                raise ValueError("bufs need the context they belong to")
+            t = lambda a, k: bufs[k][:n].copy_(torch.as_tensor(a, dtype=torch.float64), non_blocking=False)
+            z = lambda k: bufs[k][:n].zero_()
+        else:
+            t = lambda a, k: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
+            z = lambda k: torch.zeros(n, dtype=torch.float64, device=dev)
         self.a = {}
         for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u"):
-            self.a[k] = t(ic[k])
-        self.a["vpx"], self.a["vpy"], self.a["vpz"] = (self.a[k].clone() for k in ("vx", "vy", "vz"))
-        self.a["up"] = self.a["u"].clone()
-        self.a["h"] = z()
-        self.a["eps"] = z() if eps_const is None else t(eps_const)
+            self.a[k] = t(ic[k], k)
+        for k, src in (("vpx", "vx"), ("vpy", "vy"), ("vpz", "vz"), ("up", "u")):
+            self.a[k] = bufs[k][:n].copy_(self.a[src]) if bufs is not None else self.a[src].clone()
+        self.a["h"] = z("h")
+        self.a["eps"] = z("eps") if eps_const is None else t(eps_const, "eps")
         for k in ("ax", "ay", "az", "dudt", "rho"):
-            self.a[k] = z()
-        self.a["pot"] = z() if want_pot else None
-        self.ctx = tsph_create(capacity or self.n, self.params)
+            self.a[k] = z(k)
+        self.a["pot"] = z("pot") if want_pot else None
+        self.owns_ctx = ctx is None
+        self.ctx = ctx if ctx is not None else tsph_create(capacity or self.n, self.params)
         if members is not None:
             try:
                 tsph_set_members(self.ctx, self.off, [g for _, g in members])
@@ -315,8 +326,12 @@ class Simulation:
                 self.close()
                 raise
         self.state = self._state()
-        self.diag_buf = torch.zeros(9 * self.count, dtype=torch.float64, device=dev)
-        self.dt_buf = torch.zeros(self.count, dtype=torch.float64, device=dev)
+        if bufs is not None:
+            self.diag_buf = bufs["diag"][:9 * self.count]
+            self.dt_buf = bufs["dt"][:self.count]
+        else:
+            self.diag_buf = torch.zeros(9 * self.count, dtype=torch.float64, device=dev)
+            self.dt_buf = torch.zeros(self.count, dtype=torch.float64, device=dev)
 
     def _state(self) -> State:
         st = State()
@@ -390,7 +405,8 @@ class Simulation:
 
     def close(self):
         if self.ctx is not None:
-            tsph_destroy(self.ctx)
+            if getattr(self, "owns_ctx", True):
+                tsph_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):

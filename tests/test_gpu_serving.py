@@ -41,7 +41,7 @@ def test_served_results_equal_alone():
         for r in srv.res:
             if r.steps == 0:
                 continue
-            state = r.saved if r.sim is None else {k: r.sim.host(k) for k in KEYS}
+            state = {k: r.host(k) for k in KEYS}
             alone = tsph.Simulation(r.ic, r.params, want_pot=False)
             try:
                 alone.compute_forces()
