@@ -37,11 +37,12 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 # Floating-point operations per interaction in the gravity walk kernel,
-# counted from its source with FMA = 2, add/mul/div/sqrt = 1:
-#   far node, monopole + quadrupole ........................... 60
+# counted from its source with FMA = 2, add/mul/div/sqrt/rsqrt = 1:
+#   far node, monopole + quadrupole ........................... 49
+#     (FP32-bulk form; the FP64 form's extra products by G are not counted)
 #   near pair beyond 2 max(eps) (Newtonian branch) ............ 27
 #   near pair inside 2 max(eps) (softened + correction terms) . 110
-F_NODE, F_PAIR, F_SOFT = 60.0, 27.0, 110.0
+F_NODE, F_PAIR, F_SOFT = 49.0, 27.0, 110.0
 # density solves, per candidate inside the kernel support at the converged
 # length (one evaluation per solve and step is the least the method needs):
 #   h solve over gas (W, dW/dh, rho, mass-weighted dW/dh, div v) ....... 45
