@@ -27,7 +27,7 @@
 namespace tsph {
 
 constexpr int kGStackCap = 1024;
-constexpr int kGListCap = 128;
+constexpr int kGListCap = 192;  // below a flush threshold (64) plus one round (128)
 constexpr int kGCellFlush = 64;
 constexpr int kGLeafFlush = 32;
 constexpr int kGSplitFlush = 64;  // near entries collected before a hand-off
@@ -438,6 +438,42 @@ __device__ __forceinline__ void load_sink(const GravArgs &A, SinkT<F32> &s, cons
   s.ax = s.ay = s.az = s.pot = 0.0;
 }
 
+// Walk decision for node k (k < 0: none) of the batch with box gb: accepted
+// as a far node (Dubinski radius cleared and the softening reach of batch and
+// node apart), taken whole as near particles (a leaf, or a node lying within
+// the softening reach of the batch), or opened.
+struct GClass {
+  bool acc, leaf, open;
+  int child, nchild;
+};
+
+__device__ __forceinline__ GClass classify(const GravArgs &A, const NodeBox &gb, double gemax, int k) {
+  GClass c{false, false, false, -1, 0};
+  if (k < 0) return c;
+  const NodeFar f = A.nfar[k];
+  const NodeBox b = A.nbox[k];
+  double d2 = axis_gap_point(gb.lox, gb.hix, f.cx);
+  d2 = d2 + axis_gap_point(gb.loy, gb.hiy, f.cy);
+  d2 = d2 + axis_gap_point(gb.loz, gb.hiz, f.cz);
+  if (d2 > f.rmac * f.rmac) {
+    double c2 = axis_gap_box(gb.lox, gb.hix, b.lox, b.hix);
+    c2 = c2 + axis_gap_box(gb.loy, gb.hiy, b.loy, b.hiy);
+    c2 = c2 + axis_gap_box(gb.loz, gb.hiz, b.loz, b.hiz);
+    const double sr = 2.0 * fmax(gemax, b.epsmax);
+    c.acc = c2 >= sr * sr;
+  }
+  if (!c.acc) {
+    const NodeTopo nd = A.topo[k];
+    // a node wholly inside the softening reach of the batch is taken whole:
+    // all its particles are near pairs
+    c.leaf = nd.nchild == 0 || box_within(gb, b, 2.0 * gemax);
+    c.open = !c.leaf;
+    c.child = nd.child;
+    c.nchild = nd.nchild;
+  }
+  return c;
+}
+
 template <int M, bool F32>
 __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
   __shared__ int s_stack[kGStackCap];
@@ -481,45 +517,35 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
           overflow = true;
         }
         if (sp > 0 && !overflow) {
-          const int take = walk_take(sp, kGStackCap);
-          const int k = ln < take ? s_stack[sp - take + ln] : -1;
+          // up to two nodes per lane: the loads of both are in flight together
+          const int take = walk_take(sp, kGStackCap, 2 * kWave);
+          const int k0 = ln < take ? s_stack[sp - take + ln] : -1;
+          const int k1 = ln + kWave < take ? s_stack[sp - take + kWave + ln] : -1;
           sp -= take;
           __syncthreads();
-          bool acc = false, leaf = false;
-          NodeTopo nd{0, 0, -1, 0};
-          if (k >= 0) {
-            const NodeFar f = A.nfar[k];
-            const NodeBox b = A.nbox[k];
-            double d2 = axis_gap_point(gb.lox, gb.hix, f.cx);
-            d2 = d2 + axis_gap_point(gb.loy, gb.hiy, f.cy);
-            d2 = d2 + axis_gap_point(gb.loz, gb.hiz, f.cz);
-            if (d2 > f.rmac * f.rmac) {
-              double c2 = axis_gap_box(gb.lox, gb.hix, b.lox, b.hix);
-              c2 = c2 + axis_gap_box(gb.loy, gb.hiy, b.loy, b.hiy);
-              c2 = c2 + axis_gap_box(gb.loz, gb.hiz, b.loz, b.hiz);
-              const double sr = 2.0 * fmax(gemax, b.epsmax);
-              acc = c2 >= sr * sr;
-            }
-            if (!acc) {
-              nd = A.topo[k];
-              // a node wholly inside the softening reach of the batch is
-              // taken whole: all its particles are near pairs
-              leaf = nd.nchild == 0 || box_within(gb, b, 2.0 * gemax);
-            }
-          }
-          const uint64_t am = ballot(acc);
-          if (acc) s_cell[ncell + mbcnt(am)] = k;
-          ncell += __popcll(am);
-          const uint64_t lm = ballot(leaf);
-          if (leaf) s_leaf[nleaf + mbcnt(lm)] = k;
-          nleaf += __popcll(lm);
-          const int nch = (k >= 0 && !acc && !leaf) ? nd.nchild : 0;
-          const int incl = wave_incl_scan(nch);
+          const GClass c0 = classify(A, gb, gemax, k0);
+          const GClass c1 = classify(A, gb, gemax, k1);
+          uint64_t m = ballot(c0.acc);
+          if (c0.acc) s_cell[ncell + mbcnt(m)] = k0;
+          ncell += __popcll(m);
+          m = ballot(c1.acc);
+          if (c1.acc) s_cell[ncell + mbcnt(m)] = k1;
+          ncell += __popcll(m);
+          m = ballot(c0.leaf);
+          if (c0.leaf) s_leaf[nleaf + mbcnt(m)] = k0;
+          nleaf += __popcll(m);
+          m = ballot(c1.leaf);
+          if (c1.leaf) s_leaf[nleaf + mbcnt(m)] = k1;
+          nleaf += __popcll(m);
+          const int n0 = c0.open ? c0.nchild : 0, n1 = c1.open ? c1.nchild : 0;
+          const int incl = wave_incl_scan(n0 + n1);
           const int tot = __shfl(incl, kWave - 1, kWave);
           if (sp + tot > kGStackCap) {
             overflow = true;
           } else {
-            for (int a = 0; a < nch; a++) s_stack[sp + incl - nch + a] = nd.child + a;
+            const int base = sp + incl - n0 - n1;
+            for (int a = 0; a < n0; a++) s_stack[base + a] = c0.child + a;
+            for (int a = 0; a < n1; a++) s_stack[base + n0 + a] = c1.child + a;
             sp += tot;
           }
           __syncthreads();

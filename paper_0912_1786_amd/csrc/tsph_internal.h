@@ -422,15 +422,15 @@ __device__ __forceinline__ bool balls_reach_box(const double4 *snk, double lox, 
   return hit;
 }
 
-// Nodes popped per walk round from an LDS stack of capacity cap holding sp
-// entries.  Each popped node pushes at most 8 children, so popping t nodes
-// grows the stack by at most 7 t.  Full 64-node rounds run while that fits
+// Nodes popped per walk round (at most `most`) from an LDS stack of capacity
+// cap holding sp entries.  Each popped node pushes at most 8 children, so
+// popping t nodes grows the stack by at most 7 t.  Full rounds run while that fits
 // above a reserve of 160 entries; inside the reserve a single node is popped,
 // i.e. the walk continues depth first from the top, which needs at most
 // 7 x 21 more entries.  The stack therefore never exceeds cap.
-__device__ __forceinline__ int walk_take(int sp, int cap) {
+__device__ __forceinline__ int walk_take(int sp, int cap, int most = kWave) {
   const int room = cap - sp - 160;
-  int t = room >= 7 * kWave ? kWave : room / 7;
+  int t = room >= 7 * most ? most : room / 7;
   t = t < 1 ? 1 : t;
   return t < sp ? t : sp;
 }
