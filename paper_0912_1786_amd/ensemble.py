@@ -1,5 +1,6 @@
 """Ensembles of independent simulations advanced by one HIP-graph launch per
-step, with the leaf and group sizes chosen by a measuring autotuner.
+step, with the leaf and group sizes and the hand-off share chosen by a measuring
+autotuner.
 
 The members live in one context as a forest (tsph_set_members): their
 particles are held back to back, every tree-build stage and every walk is
@@ -25,8 +26,10 @@ import numpy as np
 
 from . import inputs, tsph
 
-# leaf and group sizes tried by the autotuner
-CANDIDATES = ((8, 32), (16, 32), (16, 64), (32, 64))
+# (leaf size, walk-group size, split_leaves) tried by the autotuner: the tree
+# leaves, the sinks sharing a walk, and how much of a batch's near field or
+# candidate set its own wavefront evaluates before handing the rest on
+CANDIDATES = ((8, 32, 256), (16, 32, 256), (16, 64, 256), (32, 64, 256), (16, 64, 128), (16, 64, 512))
 
 
 def ensemble_ics(members: int, seed: int = 1000):
@@ -36,19 +39,24 @@ def ensemble_ics(members: int, seed: int = 1000):
     return [inputs.evrard(int(n), seed=seed + k, u0=float(u)) for k, (n, u) in enumerate(zip(sizes, u0))]
 
 
-def member_params(nnei: float = 50.0, precision: int = tsph.FP32_BULK, leaf: int = 16, group: int = 64):
-    return tsph.tsph_default_params(nnei=nnei, leaf_size=leaf, group_size=group, precision=precision)
+def member_params(nnei: float = 50.0, precision: int = tsph.FP32_BULK, leaf: int = 16, group: int = 64,
+                  split: int = 256):
+    return tsph.tsph_default_params(nnei=nnei, leaf_size=leaf, group_size=group, precision=precision,
+                                    split_leaves=split)
 
 
 def autotune(ics, nnei: float = 50.0, precision: int = tsph.FP32_BULK, reps: int = 3) -> dict:
     """Times warm force evaluations of the whole ensemble (one context
-    holding every member) under each candidate (leaf, group) and keeps the
-    fastest.  Returns {"leaf", "group", "ms": {candidate: ms}}."""
+    holding every member) under each candidate (leaf, group, split_leaves)
+    and keeps the fastest.  Returns {"leaf", "group", "split", "ms":
+    {candidate: ms}}."""
     import torch
     big, members = tsph.concat_ics(ics)
     times = {}
-    for leaf, group in CANDIDATES:
-        sim = tsph.Simulation(big, member_params(nnei, precision, leaf, group), want_pot=False, members=members)
+    for cand in CANDIDATES:
+        leaf, group, split = cand
+        sim = tsph.Simulation(big, member_params(nnei, precision, leaf, group, split), want_pot=False,
+                              members=members)
         try:
             sim.compute_forces()
             torch.cuda.synchronize()
@@ -59,21 +67,22 @@ def autotune(ics, nnei: float = 50.0, precision: int = tsph.FP32_BULK, reps: int
                 sim.compute_forces()
             b.record()
             torch.cuda.synchronize()
-            times[(leaf, group)] = a.elapsed_time(b) / reps
+            times[cand] = a.elapsed_time(b) / reps
         finally:
             sim.close()
     best = min(times, key=times.get)
-    return {"leaf": best[0], "group": best[1], "ms": times}
+    return {"leaf": best[0], "group": best[1], "split": best[2], "ms": times}
 
 
 class Ensemble:
     """Independent simulations in one context, stepped by one graph launch."""
 
-    def __init__(self, ics, nnei: float = 50.0, precision: int = tsph.FP32_BULK, leaf: int = 16, group: int = 64):
+    def __init__(self, ics, nnei: float = 50.0, precision: int = tsph.FP32_BULK, leaf: int = 16, group: int = 64,
+                 split: int = 256):
         import torch
         self.torch = torch
         big, members = tsph.concat_ics(ics)
-        self.params = member_params(nnei, precision, leaf, group)
+        self.params = member_params(nnei, precision, leaf, group, split)
         self.sim = tsph.Simulation(big, self.params, want_pot=False, members=members)
         self.count = len(ics)
         self.n_total = self.sim.n
@@ -125,8 +134,8 @@ def run(members: int = 256, steps: int = 10, warmup: int = 2, seed: int = 1000, 
     prec = tsph.FP32_BULK if precision == "fp32_bulk" else tsph.FP64
     tuning = autotune(ics, precision=prec) if tune else None
     t_tune = time.time() - t0
-    leaf, group = (tuning["leaf"], tuning["group"]) if tuning else (16, 64)
-    ens = Ensemble(ics, precision=prec, leaf=leaf, group=group)
+    leaf, group, split = (tuning["leaf"], tuning["group"], tuning["split"]) if tuning else (16, 64, 256)
+    ens = Ensemble(ics, precision=prec, leaf=leaf, group=group, split=split)
     try:
         ens.first_forces()
         ens.capture()
@@ -146,9 +155,9 @@ def run(members: int = 256, steps: int = 10, warmup: int = 2, seed: int = 1000, 
         return {"workload": f"evrard_ensemble_{members}", "members": members, "n_total": ens.n_total,
                 "precision": precision, "steps": steps, "ms_per_step": round(ms, 3),
                 "particle_steps_per_s": round(ens.n_total / (ms / 1e3), 1), "graph_launches_per_step": 1,
-                "leaf": leaf, "group": group,
+                "leaf": leaf, "group": group, "split_leaves": split,
                 "autotune_ms": None if tuning is None else
-                {f"{l}x{g}": round(t, 3) for (l, g), t in tuning["ms"].items()},
+                {f"{l}x{g}x{sp}": round(t, 3) for (l, g, sp), t in tuning["ms"].items()},
                 "autotune_s": round(t_tune, 1), "device_flags": flags, "noconv": noconv}
     finally:
         ens.close()

@@ -151,8 +151,9 @@ def test_member_table_validation():
 def test_autotuner_picks_a_candidate():
     ics = ensemble.ensemble_ics(6, seed=78)
     tuning = ensemble.autotune(ics, reps=1)
-    assert (tuning["leaf"], tuning["group"]) in ensemble.CANDIDATES
+    best = (tuning["leaf"], tuning["group"], tuning["split"])
+    assert best in ensemble.CANDIDATES
     times = tuning["ms"]
     assert set(times) == set(ensemble.CANDIDATES)
-    assert times[(tuning["leaf"], tuning["group"])] == min(times.values())
+    assert times[best] == min(times.values())
     assert all(t > 0 for t in times.values())
