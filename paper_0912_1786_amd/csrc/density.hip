@@ -20,8 +20,12 @@
 
 namespace tsph {
 
-constexpr int kDensLeafCap = 1024;  // cached candidate leaves (>= 2 x 64)
-constexpr int kDensStackCap = 1536;
+// LDS lists of a density wavefront: cached candidate leaves (a batch with
+// more than split_leaves of them is handed on, so the batch walk needs little
+// room; the one-sink walk of k_density_sink caches more) and the walk stack
+constexpr int kDensLeafCap = 512;
+constexpr int kDensSinkLeafCap = 1024;
+constexpr int kDensStackCap = 1024;
 constexpr double kPi = 3.14159265358979323846;
 
 struct DensArgs {
@@ -258,10 +262,10 @@ struct Cands {
 };
 
 __device__ Cands gather(const DensArgs &A, int root, const NodeBox &gb, double R, bool gas_only, int *s_stack, int *s_leaf,
-                        const double4 *s_snk, bool &fail, bool whole = false) {
+                        const double4 *s_snk, bool &fail, bool whole = false, int leaf_cap = kDensLeafCap) {
   Cands c{0, true, R, gas_only};
   bool full = false;
-  bool ok = walk_leaves(A, root, gb, R, gas_only, s_stack, s_leaf, s_snk, kDensLeafCap - kWave,
+  bool ok = walk_leaves(A, root, gb, R, gas_only, s_stack, s_leaf, s_snk, leaf_cap - kWave,
                         [&](int nl, bool last) {
                           if (!last) {
                             full = true;
@@ -925,7 +929,7 @@ __device__ __forceinline__ SolveOut solve_one(const DensArgs &A, int p, int root
       if (gathered) rc = h * (1.0 + A.kappa);
       s_snk[lane()] = make_double4(a.x, a.y, a.z, lane() == 0 ? 2.0 * rc : 0.0);
       __syncthreads();
-      c = gather(A, root, pb, 2.0 * rc, gas_only, s_stack, s_leaf, s_snk, fail, true);
+      c = gather(A, root, pb, 2.0 * rc, gas_only, s_stack, s_leaf, s_snk, fail, true, kDensSinkLeafCap);
       gathered = true;
       if (fail) break;
     }
@@ -967,7 +971,7 @@ __device__ __forceinline__ SolveOut solve_one(const DensArgs &A, int p, int root
 
 __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
   __shared__ int s_stack[kDensStackCap];
-  __shared__ int s_leaf[kDensLeafCap];
+  __shared__ int s_leaf[kDensSinkLeafCap];
   __shared__ double4 s_snk[kWave];
   __shared__ int s_t;
   const int ln = lane();
