@@ -418,31 +418,45 @@ __global__ void k_topo_init(Members M, NodeTopo *__restrict__ topo, int32_t *__r
 }
 
 // children of the nodes of one level: the non-empty octants, in octant order,
-// found by binary search on the sorted keys
+// found by binary search on the sorted keys.  Eight threads per node (a
+// group of eight lanes of one wavefront), one per octant, search their
+// boundaries side by side: a long node costs one search of its range, not
+// eight in a row.
 __global__ __launch_bounds__(256) void k_topo_split(int level, int leaf_size, const int32_t *__restrict__ lvl,
                                                     const NodeTopo *__restrict__ topo,
                                                     const uint64_t *__restrict__ key,
                                                     int2 *__restrict__ ctmp, int32_t *__restrict__ ctmpn) {
-  int begin = lvl[level], count = lvl[23 + level];
-  int shift = 3 * (kMaxLevel - level - 1);
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-    NodeTopo nd = topo[begin + t];
-    int nch = 0;
-    if (nd.count > leaf_size && level < kMaxLevel) {
-      int lo = nd.first, end = nd.first + nd.count;
-      for (int oct = 0; oct < 8; oct++) {
-        // first position in [lo, end) whose digit exceeds oct
-        int a = lo, b = end;
-        while (a < b) {
-          int mid = (a + b) >> 1;
-          if ((int)((key[mid] >> shift) & 7ull) <= oct) a = mid + 1;
-          else b = mid;
-        }
-        if (a > lo) ctmp[(int64_t)t * 8 + nch++] = make_int2(lo, a - lo);
-        lo = a;
+  const int begin = lvl[level], count = lvl[23 + level];
+  const int shift = 3 * (kMaxLevel - level - 1);
+  const int oct = threadIdx.x & 7;
+  // whole groups of eight walk the node list together (blockDim and the
+  // grid stride are multiples of eight)
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u - oct < (int64_t)count * 8;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(u >> 3);
+    const bool valid = t < count;
+    const NodeTopo nd = valid ? topo[begin + t] : NodeTopo{0, 0, -1, 0};
+    const bool split = valid && nd.count > leaf_size && level < kMaxLevel;
+    const int lo = nd.first, end = nd.first + nd.count;
+    // first position in [lo, end) whose digit exceeds oct
+    int a = lo, b = end;
+    if (split) {
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        if ((int)((key[mid] >> shift) & 7ull) <= oct) a = mid + 1;
+        else b = mid;
       }
     }
-    ctmpn[t] = nch;
+    // start of this octant = end of the previous one (lane - 1 of the group)
+    const int prev = __shfl_up(a, 1, 8);
+    const int start = oct == 0 ? lo : prev;
+    const bool has = split && a > start;
+    const uint64_t m = ballot(has);
+    const int gshift = lane() & ~7;
+    const uint32_t gm = (uint32_t)((m >> gshift) & 0xffull);
+    const int idx = __popc(gm & ((1u << oct) - 1u));
+    if (has) ctmp[(int64_t)t * 8 + idx] = make_int2(start, a - start);
+    if (valid && oct == 0) ctmpn[t] = split ? __popc(gm) : 0;
   }
 }
 
