@@ -95,17 +95,32 @@ __global__ __launch_bounds__(256) void k_bbox_partial(Members M, const double *_
 }
 
 // smallest power of two not below the largest extent; origin = minimum corner
-// one block per member: nb partial boxes each
-__global__ void k_bbox_final(int nb, const double *__restrict__ part, DevRoot *__restrict__ roots) {
-  if (threadIdx.x != 0) return;
+// one block (256 threads) per member: nb partial boxes each, reduced in
+// parallel (min and max are exact in any order)
+__global__ __launch_bounds__(256) void k_bbox_final(int nb, const double *__restrict__ part,
+                                                    DevRoot *__restrict__ roots) {
   part += (int64_t)blockIdx.x * nb * 6;
-  DevRoot *root = roots + blockIdx.x;
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = 0; b < nb; b++)
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
     for (int d = 0; d < 3; d++) {
-      lo[d] = fmin(lo[d], part[b * 6 + d]);
-      hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
+      v[d] = fmin(v[d], part[b * 6 + d]);
+      v[3 + d] = fmax(v[3 + d], part[b * 6 + 3 + d]);
     }
+  __shared__ double s[6][256];
+  for (int k = 0; k < 6; k++) s[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int d = 0; d < 3; d++) {
+        s[d][threadIdx.x] = fmin(s[d][threadIdx.x], s[d][threadIdx.x + o]);
+        s[3 + d][threadIdx.x] = fmax(s[3 + d][threadIdx.x], s[3 + d][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  DevRoot *root = roots + blockIdx.x;
+  double lo[3] = {s[0][0], s[1][0], s[2][0]}, hi[3] = {s[3][0], s[4][0], s[5][0]};
+  // smallest power of two not below the largest extent; origin = minimum corner
   double L = 0.0;
   for (int d = 0; d < 3; d++) {
     double ext = hi[d] - lo[d];
@@ -204,24 +219,30 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const int32_t *__restrict__
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// single block: exclusive scan of the block sums; the grand total goes to
-// *total.  In level mode the total becomes the next level's node count and
-// the node capacity is enforced.
-__global__ __launch_bounds__(256) void k_scan_top(int32_t *__restrict__ part, int nb,
-                                                  int32_t *__restrict__ total, int32_t *__restrict__ lvl,
-                                                  int level, int64_t cap_nodes,
-                                                  uint32_t *__restrict__ flags) {
+// exclusive scan of the input of each block, offset by the sum of the
+// blocks before it (read from the block sums, no separate pass).  Block 0
+// also writes the grand total to *total; in level mode the total becomes the
+// next level's node count and the node capacity is enforced.
+__global__ __launch_bounds__(256) void k_scan_apply(const int32_t *__restrict__ in, int64_t n_host,
+                                                    const int32_t *__restrict__ n_dev,
+                                                    const int32_t *__restrict__ part, int nb,
+                                                    int32_t *__restrict__ out, int32_t *__restrict__ total,
+                                                    int32_t *__restrict__ lvl, int level, int64_t cap_nodes,
+                                                    uint32_t *__restrict__ flags) {
+  int64_t n = n_dev ? *n_dev : n_host;
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
   __shared__ int tmp[4];
-  int carry = 0;
-  for (int b0 = 0; b0 < nb; b0 += 256) {
-    int b = b0 + threadIdx.x;
-    int v = (b < nb) ? part[b] : 0;
-    int tot;
-    int ex = block_excl_scan256(v, tmp, tot);
-    if (b < nb) part[b] = carry + ex;
-    carry += tot;
+  int pre = 0, all = 0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    const int v = part[b];
+    all += v;
+    if (b < (int)blockIdx.x) pre += v;
   }
-  if (threadIdx.x == 0) {
+  int pre_tot, all_tot;
+  block_excl_scan256(pre, tmp, pre_tot);
+  block_excl_scan256(all, tmp, all_tot);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int carry = all_tot;
     if (total) *total = carry;
     if (lvl) {
       // lvl[0..23) level begin, lvl[23..46) level count, lvl[46] total nodes
@@ -235,17 +256,8 @@ __global__ __launch_bounds__(256) void k_scan_top(int32_t *__restrict__ part, in
       lvl[46] = begin_next + carry;
     }
   }
-}
-
-__global__ __launch_bounds__(256) void k_scan_apply(const int32_t *__restrict__ in, int64_t n_host,
-                                                    const int32_t *__restrict__ n_dev,
-                                                    const int32_t *__restrict__ part,
-                                                    int32_t *__restrict__ out) {
-  int64_t n = n_dev ? *n_dev : n_host;
-  int64_t base = (int64_t)blockIdx.x * kScanTile;
   if (base >= n) return;
-  __shared__ int tmp[4];
-  int carry = part[blockIdx.x];
+  int carry = pre_tot;
   for (int k = 0; k < kScanTile / 256; k++) {
     int64_t i = base + k * 256 + threadIdx.x;
     int v = (i < n) ? in[i] : 0;
@@ -262,9 +274,8 @@ static void launch_scan(Ctx *c, const int32_t *in, int64_t n_host, const int32_t
   int nb = (int)((n_max + kScanTile - 1) / kScanTile);
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, st, in, n_host, n_dev, c->scan_part);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, c->scan_part, nb, total, lvl, level,
-                     c->cap_nodes, c->flags);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, st, in, n_host, n_dev, c->scan_part, out);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, st, in, n_host, n_dev, c->scan_part, nb, out, total,
+                     lvl, level, c->cap_nodes, c->flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -715,7 +726,7 @@ tsph_status tsph_impl_build_tree(Ctx *c, const tsph_state *s, hipStream_t st) {
   const int bbm = M.count > 1 ? kMemberBlocks : kBBoxBlocks;
   hipLaunchKernelGGL(k_bbox_partial, dim3(bbm, M.count), dim3(T), 0, st, M, s->x, s->y, s->z, s->m, c->bbox_part,
                      c->flags);
-  hipLaunchKernelGGL(k_bbox_final, dim3(M.count), dim3(64), 0, st, bbm, c->bbox_part, c->root);
+  hipLaunchKernelGGL(k_bbox_final, dim3(M.count), dim3(256), 0, st, bbm, c->bbox_part, c->root);
   // keys
   hipLaunchKernelGGL(k_keys, dim3(gb), dim3(T), 0, st, M, s->x, s->y, s->z, c->root, c->key[0], c->idx[0]);
   // sort: 8 passes of 8 bits, ping-pong, result back in buffer 0
