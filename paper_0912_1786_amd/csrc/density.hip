@@ -909,9 +909,9 @@ __device__ __forceinline__ void sink_leaf_sums(const DensArgs &A, int nleaf, con
 }
 
 // One self-consistent length of one sink (wave-uniform).
-__device__ __forceinline__ SolveOut solve_one(const DensArgs &A, int p, int root, bool gas_only, double eta, double guess, bool cold,
-                              const double4 &a, const double4 &vp, bool want_div, bool want_phi, int *s_stack,
-                              int *s_leaf, double4 *s_snk) {
+__device__ __forceinline__ SolveOut solve_one(const DensArgs &A, int root, bool gas_only, double eta, double guess,
+                                              bool cold, const double4 &a, const double4 &vp, bool want_div,
+                                              bool want_phi, int *s_stack, int *s_leaf, double4 *s_snk) {
   SolveOut o;
   o.handed = false;
   const double eta3 = eta * eta * eta;
@@ -997,7 +997,8 @@ __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
       if (A.hydro && is_gas) {
         const double g0 = A.hs[p];
         const double guess = g0 > 0.0 ? g0 : cold_guess(A, p, true, A.eta_h);
-        oh = solve_one(A, p, bt.root, true, A.eta_h, guess, !(g0 > 0.0), a, vp, true, A.shared != 0, s_stack, s_leaf, s_snk);
+        oh = solve_one(A, bt.root, true, A.eta_h, guess, !(g0 > 0.0), a, vp, true, A.shared != 0, s_stack, s_leaf,
+                       s_snk);
         if (!oh.ok) nnoconv++;
       }
       double eps = 0.0, neps = 0.0, ups = 1.0, xi = 0.0, divve = 0.0;
@@ -1014,7 +1015,7 @@ __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
           const double g0 = A.es[p];
           const double guess = g0 > 0.0 ? g0 : cold_guess(A, p, false, A.eta_eps);
           const SolveOut oe =
-              solve_one(A, p, bt.root, false, A.eta_eps, guess, !(g0 > 0.0), a, vp, true, true, s_stack, s_leaf, s_snk);
+              solve_one(A, bt.root, false, A.eta_eps, guess, !(g0 > 0.0), a, vp, true, true, s_stack, s_leaf, s_snk);
           if (!oe.ok) nnoconv++;
           eps = oe.h;
           neps = oe.s.n;
