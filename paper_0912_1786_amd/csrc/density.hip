@@ -178,7 +178,8 @@ __device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, 
       if (ndbg < A.dbg_max) dbg_row[ndbg] = A.perm[T.q[j]];
       ndbg++;
     }
-    const double r = r2 > 0.0 ? r2 * rsqrt(r2) : 0.0;
+    const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double r = r2 * ir;
     const double qq = r * ih;
     double w, dw;
     m4(qq, w, dw);
@@ -192,7 +193,7 @@ __device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, 
       if (want_phi) s.mdphi += a.w * soft_pe_q(qq, ih);
       if (want_div && r > 0.0) {
         const double4 v = T.vu[j];
-        const double g = dw * ih4 * (ih / qq);  // dW/dr / r
+        const double g = dw * ih4 * ir;  // dW/dr / r
         s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
       }
     }
@@ -461,22 +462,24 @@ __device__ __forceinline__ void solver_update(Solver &v, const DensArgs &A, cons
 
 // Per-lane sums of both lengths over the nt staged candidates (gas flag in
 // vu.w).  do_h / do_e: the solver still iterates.
-__device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T, int nt, double px, double py,
-                                           double pz, const double4 &vp, bool do_h, double hh, bool do_e, double he,
-                                           int32_t *dbg_row, int &ndbg, Sums5 &sh, Sums5 &se) {
+__device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T, int nt, uint64_t gas, double px,
+                                           double py, double pz, const double4 &vp, bool do_h, double hh, bool do_e,
+                                           double he, int32_t *dbg_row, int &ndbg, Sums5 &sh, Sums5 &se) {
   const double ihh = 1.0 / hh, ihe = 1.0 / he;
   const double ihh3 = ihh * ihh * ihh / kPi, ihe3 = ihe * ihe * ihe / kPi;
   const double ihh4 = ihh3 * ihh, ihe4 = ihe3 * ihe;
   const double R2h = do_h ? (2.0 * hh) * (2.0 * hh) : -1.0;
   const double R2e = do_e ? (2.0 * he) * (2.0 * he) : -1.0;
   // neighbour mask first, then each lane's own neighbours in tile order
-  // (as in tile_sums)
-  uint64_t mask = 0;
-  for (int j = 0; j < nt; j++) {
+  // (as in tile_sums).  A gas candidate is a neighbour within the larger of
+  // the two radii, any other within the softening radius: the gas bit of
+  // candidate j (bit j of gas) is the same for every lane.
+  const double R2g = fmax(R2h, R2e);
+  uint64_t mask = tile_mask(nt, [&](int j) {
     const double4 a = T.pm[j];
     const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
-    if ((r2 < R2h && T.vu[j].w != 0.0) || r2 < R2e) mask |= 1ull << j;
-  }
+    return r2 < (((gas >> j) & 1) ? R2g : R2e);
+  });
   while (mask) {
     const int j = __builtin_ctzll(mask);
     mask &= mask - 1;
@@ -485,7 +488,8 @@ __device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T,
     const double4 v = T.vu[j];
     const bool in_h = r2 < R2h && v.w != 0.0;
     const bool in_e = r2 < R2e;
-    const double r = r2 > 0.0 ? r2 * rsqrt(r2) : 0.0;
+    const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double r = r2 * ir;
     const double dot = (vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z);
     if (in_h) {
       if (dbg_row) {
@@ -501,7 +505,7 @@ __device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T,
       sh.sdh += dWdh;
       sh.rho += a.w * W;
       sh.msdh += a.w * dWdh;
-      if (r > 0.0) sh.divv += dw * ihh4 * (ihh / qq) * dot;
+      if (r > 0.0) sh.divv += dw * ihh4 * ir * dot;
     }
     if (in_e) {
       const double qq = r * ihe;
@@ -511,21 +515,26 @@ __device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T,
       se.n += W;
       se.sdh += -(3.0 * w + qq * dw) * ihe4;
       se.rho += a.w * soft_pe_q(qq, ihe);  // mass-weighted d phi / d eps
-      if (r > 0.0) se.divv += dw * ihe4 * (ihe / qq) * dot;
+      if (r > 0.0) se.divv += dw * ihe4 * ir * dot;
     }
   }
 }
 
-__device__ __forceinline__ void stage_tile2(const DensArgs &A, DensTile &T, int nt, int q) {
+// Returns the gas bits of the staged candidates (bit j: candidate j is gas).
+__device__ __forceinline__ uint64_t stage_tile2(const DensArgs &A, DensTile &T, int nt, int q) {
   const int ln = lane();
+  bool g = false;
   if (ln < nt) {
     T.pm[ln] = A.pm[q];
     double4 v = A.vu[q];
-    v.w = A.gas[q] ? 1.0 : 0.0;
+    g = A.gas[q] != 0;
+    v.w = g ? 1.0 : 0.0;
     T.vu[ln] = v;
     T.q[ln] = q;
   }
+  const uint64_t gas = ballot(g);
   __syncthreads();
+  return gas;
 }
 
 __device__ void leaf_sums2(const DensArgs &A, int nleaf, const int *s_leaf, DensTile &T, double px, double py,
@@ -545,8 +554,8 @@ __device__ void leaf_sums2(const DensArgs &A, int nleaf, const int *s_leaf, Dens
         fill += tk;
         off += tk;
         if (fill == kWave) {
-          stage_tile2(A, T, kWave, rq);
-          tile_sums2(A, T, kWave, px, py, pz, vp, do_h, hh, do_e, he, dbg_row, ndbg, sh, se);
+          const uint64_t gas = stage_tile2(A, T, kWave, rq);
+          tile_sums2(A, T, kWave, gas, px, py, pz, vp, do_h, hh, do_e, he, dbg_row, ndbg, sh, se);
           __syncthreads();
           fill = 0;
         }
@@ -554,8 +563,8 @@ __device__ void leaf_sums2(const DensArgs &A, int nleaf, const int *s_leaf, Dens
     }
   }
   if (fill > 0) {
-    stage_tile2(A, T, fill, rq);
-    tile_sums2(A, T, fill, px, py, pz, vp, do_h, hh, do_e, he, dbg_row, ndbg, sh, se);
+    const uint64_t gas = stage_tile2(A, T, fill, rq);
+    tile_sums2(A, T, fill, gas, px, py, pz, vp, do_h, hh, do_e, he, dbg_row, ndbg, sh, se);
     __syncthreads();
   }
 }
@@ -812,7 +821,8 @@ __device__ __forceinline__ void add_candidate(const double4 &a, const double4 &v
   if (skip) return;
   const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
   if (!(r2 < R2)) return;
-  const double r = r2 > 0.0 ? r2 * rsqrt(r2) : 0.0;
+  const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
+  const double r = r2 * ir;
   const double qq = r * ih;
   double w, dw;
   m4(qq, w, dw);
@@ -824,7 +834,7 @@ __device__ __forceinline__ void add_candidate(const double4 &a, const double4 &v
   s.msdh += a.w * dWdh;
   if (want_phi) s.mdphi += a.w * soft_pe_q(qq, ih);
   if (want_div && r > 0.0) {
-    const double g = dw * ih4 * (ih / qq);
+    const double g = dw * ih4 * ir;
     s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
   }
 }

@@ -158,14 +158,12 @@ __device__ __forceinline__ void debug_pair(const GravArgs &A, Sink &s, const Gra
 // that only some other lane needs.
 template <int M>
 __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const GravRec *rec, const int *tq, int nt) {
-  uint64_t soft = 0;
-  for (int j = 0; j < nt; j++) {
+  uint64_t soft = tile_mask(nt, [&](int j) {
     const GravRec b = rec[j];
     const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double em = fmax(s.eps, b.eps);
     const bool near = r2 < 4.0 * em * em;
-    soft |= (uint64_t)near << j;
     const double ir = near ? 0.0 : rsqrt(r2);
     const double mr = b.m * ir;
     const double f = A.G * mr * ir * ir;
@@ -174,7 +172,8 @@ __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const Grav
     s.az -= f * dz;
     if (M & kPot) s.pot -= A.G * mr;
     if (s.dbg && tq[j] != s.p) debug_pair(A, s, b, tq[j]);
-  }
+    return near;
+  });
   while (soft) {
     const int j = __builtin_ctzll(soft);
     soft &= soft - 1;
@@ -188,16 +187,29 @@ __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const Grav
 
 // node record staged for the FP32 form (48 B): COM relative to the batch
 // centre, mass, traceless quadrupole
-struct NodeF32 {
+// 1/sqrt(x) of the FP32 form: the hardware reciprocal square root.  For
+// normal x it is what rsqrtf returns; rsqrtf's extra scaling of denormal
+// arguments is left out (a squared distance never lies in that range: the
+// positions are relative to the batch centre, and zero gives +inf either way).
+__device__ __forceinline__ float rsq32(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// fmaxf of two non-negative floats, as the larger bit pattern (no NaN
+// canonicalisation).  With e2 = 2 eps, (max e2)^2 rounds to the same value
+// as 4 max(eps)^2: both are the one rounding of the exact 4 max(eps)^2.
+__device__ __forceinline__ float max_nonneg(float a, float b) {
+  return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
+
+struct alignas(16) NodeF32 {
   float cx, cy, cz, m;
   float qxx, qyy, qzz, qxy;
   float qxz, qyz, pad0, pad1;
 };
 
 // particle record staged for the FP32 form (32 B)
-struct RecF32 {
+struct alignas(16) RecF32 {
   float x, y, z, m;
-  float eps, ieps, xiu, pad;
+  float eps, ieps, xiu, e2;  // e2 = 2 eps
 };
 
 // LDS staging tiles of the two forms
@@ -212,6 +224,7 @@ union Tile32 {
 
 struct Sink32 {
   float x, y, z, m, im, eps, ieps, xiu;  // position relative to the batch centre
+  float e2;                              // 2 eps
   float tax, tay, taz, tpot;             // sums over the current tile
   double ax, ay, az, pot;                // totals (in units of G)
   int p;
@@ -230,7 +243,7 @@ template <int M>
 __device__ __forceinline__ void far_field32(Sink32 &s, const NodeF32 &f) {
   const float dx = s.x - f.cx, dy = s.y - f.cy, dz = s.z - f.cz;
   const float r2 = dx * dx + dy * dy + dz * dz;
-  const float ir = rsqrtf(r2);
+  const float ir = rsq32(r2);
   const float ir2 = ir * ir;
   const float ir3 = ir * ir2;
   if (M & kQuad) {
@@ -259,7 +272,7 @@ template <int M>
 __device__ __forceinline__ void newton_pair32(Sink32 &s, const RecF32 &b) {
   const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
   const float r2 = dx * dx + dy * dy + dz * dz;
-  const float ir = rsqrtf(r2);
+  const float ir = rsq32(r2);
   const float mr = b.m * ir;
   const float f = mr * ir * ir;
   s.tax -= f * dx;
@@ -272,13 +285,13 @@ template <int M>
 __device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b) {
   const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
   const float r2 = dx * dx + dy * dy + dz * dz;
-  const float em = fmaxf(s.eps, b.eps);
-  if (r2 >= 4.0f * em * em) {
+  const float e2 = max_nonneg(s.e2, b.e2);
+  if (r2 >= e2 * e2) {
     newton_pair32<M>(s, b);
     return;
   }
   if (r2 > 0.0f) {
-    const float ir = rsqrtf(r2);
+    const float ir = rsq32(r2);
     const float r = r2 * ir;
     const float qi = r * s.ieps, qj = r * b.ieps;
     float F = 0.5f * b.m * (soft_fr_q(qi, s.ieps, ir) + soft_fr_q(qj, b.ieps, ir));
@@ -302,22 +315,21 @@ __device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b) {
 // softened pairs.
 template <int M>
 __device__ __forceinline__ void near_tile32(Sink32 &s, const RecF32 *rec, const int *tq, int nt) {
-  uint64_t soft = 0;
-  for (int j = 0; j < nt; j++) {
+  uint64_t soft = tile_mask(nt, [&](int j) {
     const RecF32 b = rec[j];
     const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
-    const float em = fmaxf(s.eps, b.eps);
-    const bool near = r2 < 4.0f * em * em;
-    soft |= (uint64_t)near << j;
-    const float ir = near ? 0.0f : rsqrtf(r2);
+    const float e2 = max_nonneg(s.e2, b.e2);
+    const bool near = r2 < e2 * e2;
+    const float ir = near ? 0.0f : rsq32(r2);
     const float mr = b.m * ir;
     const float f = mr * ir * ir;
     s.tax -= f * dx;
     s.tay -= f * dy;
     s.taz -= f * dz;
     if (M & kPot) s.tpot -= mr;
-  }
+    return near;
+  });
   while (soft) {
     const int j = __builtin_ctzll(soft);
     soft &= soft - 1;
@@ -362,7 +374,7 @@ __device__ __forceinline__ int near_entries(const GravArgs &A, SinkT<F32> &s, co
         RecF32 h;
         h.x = (float)(r.x - cx); h.y = (float)(r.y - cy); h.z = (float)(r.z - cz);
         h.m = (float)r.m; h.eps = (float)r.eps; h.ieps = (float)r.ieps; h.xiu = (float)r.xiu;
-        h.pad = 0.0f;
+        h.e2 = 2.0f * h.eps;
         T.rec32[ln] = h;
       } else {
         T.rec[ln] = r;
@@ -428,6 +440,7 @@ __device__ __forceinline__ void load_sink(const GravArgs &A, SinkT<F32> &s, cons
     s.x = (float)(r.x - cx); s.y = (float)(r.y - cy); s.z = (float)(r.z - cz);
     s.m = (float)r.m; s.im = (float)(1.0 / r.m);
     s.eps = (float)r.eps; s.ieps = (float)r.ieps; s.xiu = (float)r.xiu;
+    s.e2 = 2.0f * s.eps;
     s.tax = s.tay = s.taz = s.tpot = 0.0f;
   } else {
     s.x = r.x; s.y = r.y; s.z = r.z; s.m = r.m; s.im = 1.0 / r.m;

@@ -108,19 +108,19 @@ __device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bo
 // tests of the whole tile first, then the lane's own pairs in tile order.
 __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const SphTile &T, int nt, bool tc) {
   const double hi = L.hd.x;
-  uint64_t mask = 0;
-  for (int j = 0; j < nt; j++) {
+  uint64_t mask = tile_mask(nt, [&](int j) {
     const double4 b = T.pos[j];
     const double r2x = dist2_pair(L.a.x, L.a.y, L.a.z, b.x, b.y, b.z);
     const double R = 2.0 * fmax(hi, b.w);
-    if (L.sink && T.q[j] != L.p && r2x < R * R) mask |= 1ull << j;
-  }
+    return L.sink && r2x < R * R;
+  });
   const double ihi = 1.0 / hi, imi = 1.0 / L.a.w;
   const double ihi4 = ihi * ihi * ihi * ihi * kInvPiS;
   while (mask) {
     const int j = __builtin_ctzll(mask);
     mask &= mask - 1;
     const int q = T.q[j];
+    if (q == L.p) continue;  // the sink itself
     const SphRec b = A.srec[q];
     if (L.dbg) {
       if (L.ndbg < A.dbg_max) L.dbg[L.ndbg] = A.perm[q];

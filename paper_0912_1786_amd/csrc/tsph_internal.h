@@ -220,6 +220,18 @@ __device__ __forceinline__ int lane() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Per-lane mask of the tile entries j < nt (nt <= 64) for which f(j) holds,
+// f called for j = 0, 1, ... in order.  Built as two 32-bit halves, so that
+// the bit of entry j is a wave-uniform constant.
+template <class F>
+__device__ __forceinline__ uint64_t tile_mask(int nt, F &&f) {
+  uint32_t lo = 0, hi = 0;
+  const int n0 = nt < 32 ? nt : 32;
+  for (int j = 0; j < n0; j++) lo |= f(j) ? 1u << j : 0u;
+  for (int j = 32; j < nt; j++) hi |= f(j) ? 1u << (j - 32) : 0u;
+  return (uint64_t)hi << 32 | lo;
+}
+
 // number of set bits of m below this lane
 __device__ __forceinline__ int mbcnt(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
