@@ -178,7 +178,7 @@ __device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, 
       if (ndbg < A.dbg_max) dbg_row[ndbg] = A.perm[T.q[j]];
       ndbg++;
     }
-    const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double ir = r2 > 0.0 ? rsq64(r2) : 0.0;
     const double r = r2 * ir;
     const double qq = r * ih;
     double w, dw;
@@ -488,7 +488,7 @@ __device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T,
     const double4 v = T.vu[j];
     const bool in_h = r2 < R2h && v.w != 0.0;
     const bool in_e = r2 < R2e;
-    const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double ir = r2 > 0.0 ? rsq64(r2) : 0.0;
     const double r = r2 * ir;
     const double dot = (vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z);
     if (in_h) {
@@ -821,7 +821,7 @@ __device__ __forceinline__ void add_candidate(const double4 &a, const double4 &v
   if (skip) return;
   const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
   if (!(r2 < R2)) return;
-  const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
+  const double ir = r2 > 0.0 ? rsq64(r2) : 0.0;
   const double r = r2 * ir;
   const double qq = r * ih;
   double w, dw;

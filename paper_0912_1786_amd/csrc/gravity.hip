@@ -80,7 +80,7 @@ template <int M>
 __device__ __forceinline__ void far_field(const GravArgs &A, Sink &s, const NodeFar &f) {
   const double dx = s.x - f.cx, dy = s.y - f.cy, dz = s.z - f.cz;
   const double r2 = dx * dx + dy * dy + dz * dz;
-  const double ir = rsqrt(r2);
+  const double ir = rsq64(r2);
   const double ir2 = ir * ir;
   const double ir3 = ir * ir2;
   if (M & kQuad) {
@@ -111,7 +111,7 @@ __device__ __forceinline__ void near_pair(const GravArgs &A, Sink &s, const Grav
   const double r2 = dx * dx + dy * dy + dz * dz;
   const double em = fmax(s.eps, b.eps);
   if (r2 >= 4.0 * em * em) {
-    const double ir = rsqrt(r2);
+    const double ir = rsq64(r2);
     const double mr = b.m * ir;
     const double f = A.G * mr * ir * ir;
     s.ax -= f * dx;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void near_pair(const GravArgs &A, Sink &s, const Grav
     return;
   }
   if (r2 > 0.0) {
-    const double ir = rsqrt(r2);
+    const double ir = rsq64(r2);
     const double r = r2 * ir;
     const double qi = r * s.ieps, qj = r * b.ieps;
     double F = 0.5 * b.m * (soft_fr_q(qi, s.ieps, ir) + soft_fr_q(qj, b.ieps, ir));
@@ -164,7 +164,7 @@ __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const Grav
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double em = fmax(s.eps, b.eps);
     const bool near = r2 < 4.0 * em * em;
-    const double ir = near ? 0.0 : rsqrt(r2);
+    const double ir = near ? 0.0 : rsq64(r2);
     const double mr = b.m * ir;
     const double f = A.G * mr * ir * ir;
     s.ax -= f * dx;
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
         if (ncell >= kGCellFlush || (last && ncell > 0)) {
           // accepted nodes, 64 per tile
           for (int t0 = 0; t0 < ncell; t0 += kWave) {
-            const int nt = min(kWave, ncell - t0);
+            const int nt = uniform(min(kWave, ncell - t0));
             if (ln < nt) {
               const NodeFar f = A.nfar[s_cell[t0 + ln]];
               if constexpr (F32) {
@@ -584,6 +584,7 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
             }
             __syncthreads();
             if constexpr (F32) {
+#pragma unroll 2
               for (int j = 0; j < nt; j++) far_field32<M>(s, s_t.far32[j]);
               carry_tile(s);
             } else {

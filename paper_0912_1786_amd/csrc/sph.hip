@@ -130,7 +130,7 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
     const double dx = L.a.x - b.x, dy = L.a.y - b.y, dz = L.a.z - b.z;
     const double r2 = dist2_pair(L.a.x, L.a.y, L.a.z, b.x, b.y, b.z);
     if (!(r2 > 0.0)) continue;
-    const double ir = rsqrt(r2);
+    const double ir = rsq64(r2);
     const double r = r2 * ir;
     const double ihj2 = b.ih * b.ih;
     const double gi = m4_grad(r * ihi, tc) * ihi4 * ir;

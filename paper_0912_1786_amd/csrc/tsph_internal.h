@@ -220,6 +220,18 @@ __device__ __forceinline__ int lane() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// 1/sqrt(x) in FP64 for positive, finite, normal x: the hardware estimate y
+// refined by one second-order step, y (1 + e/2 + 3 e^2/8) with
+// e = 1 - x y^2 (the Taylor series of (1 - e)^(-1/2)), written as
+// y + (y e)(1/2 + 3e/8).  Zero, infinity and NaN are not special-cased: the
+// callers pass positive squared distances, or discard the result.
+__device__ __forceinline__ double rsq64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(y * -x, y, 1.0);
+  const double u = y * e;
+  return fma(u, fma(e, 0.375, 0.5), y);
+}
+
 // Per-lane mask of the tile entries j < nt (nt <= 64) for which f(j) holds,
 // f called for j = 0, 1, ... in order.  Built as two 32-bit halves, so that
 // the bit of entry j is a wave-uniform constant.
