@@ -63,13 +63,18 @@ def log(*a):
 
 
 def kernel_source_id(src: str) -> str:
-    """Hash of a kernel's source file and the shared header: a traffic figure
-    measured on other source is stale."""
+    """Hash of a kernel's source file and the shared header, without their
+    // comments and blank lines: a traffic figure measured on other code is
+    stale, one measured before a comment changed is not."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in (src, "tsph_internal.h"):
-        with open(os.path.join(ROOT, "paper_0912_1786_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_0912_1786_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = re.sub(r"//.*$", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -461,7 +461,7 @@ __device__ __forceinline__ void solver_update(Solver &v, const DensArgs &A, cons
 }
 
 // Per-lane sums of both lengths over the nt staged candidates (gas flag in
-// vu.w).  do_h / do_e: the solver still iterates.
+// vu.w and in bit j of gas).  do_h / do_e: the solver still iterates.
 __device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T, int nt, uint64_t gas, double px,
                                            double py, double pz, const double4 &vp, bool do_h, double hh, bool do_e,
                                            double he, int32_t *dbg_row, int &ndbg, Sums5 &sh, Sums5 &se) {

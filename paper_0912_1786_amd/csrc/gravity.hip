@@ -185,8 +185,6 @@ __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const Grav
 // relative to the batch centre, partial sums per staged tile in single
 // precision carried into double-precision totals after every tile.
 
-// node record staged for the FP32 form (48 B): COM relative to the batch
-// centre, mass, traceless quadrupole
 // 1/sqrt(x) of the FP32 form: the hardware reciprocal square root.  For
 // normal x it is what rsqrtf returns; rsqrtf's extra scaling of denormal
 // arguments is left out (a squared distance never lies in that range: the
@@ -200,6 +198,8 @@ __device__ __forceinline__ float max_nonneg(float a, float b) {
   return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
 }
 
+// node record staged for the FP32 form (48 B): COM relative to the batch
+// centre, mass, traceless quadrupole
 struct alignas(16) NodeF32 {
   float cx, cy, cz, m;
   float qxx, qyy, qzz, qxy;
