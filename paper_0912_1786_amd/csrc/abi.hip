@@ -101,7 +101,7 @@ size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->add(sizeof(SplitItem) * (size_t)icap);     // split_item
   L->add(32 * 64 * (size_t)icap);               // split_part
   L->add(4 * M);                                // split_head
-  L->add(4 * heavy_batch_cap(M));               // heavy
+  L->add(4 * 3 * heavy_batch_cap(M));           // heavy: batches, keys, ordered batches
   // small
   L->add(8 * (S + 1));               // moff
   L->add(8 * S);                     // mgas

@@ -58,7 +58,9 @@ struct DensArgs {
   int32_t *noconv;
   int32_t *dbg;
   int32_t dbg_max;
-  int32_t *heavy;      // batches handed to k_density_sink
+  int32_t *heavy;      // batches handed to k_density_sink, in hand-off order
+  int32_t *heavy_key;  // their candidate-leaf counts (a list that overflowed: INT32_MAX)
+  int32_t *heavy_ord;  // the same batches, largest key class first
   int32_t heavy_cap;   // 0: no hand-off
   int32_t split_leaves;  // hand off batches with more candidate leaves
   double eta_h, eta_eps, kappa, h_tol, gamma;
@@ -331,13 +333,16 @@ __device__ __forceinline__ bool newton_update(double &h, double &lo, double &hi,
 // Hands batch g to k_density_sink when its candidate leaves exceed
 // split_leaves or overflow the LDS cache (sinks whose kernel reaches into a
 // dense neighbourhood); false when the hand-off list is full or disabled.
-__device__ __forceinline__ bool hand_off(const DensArgs &A, int g) {
+__device__ __forceinline__ bool hand_off(const DensArgs &A, int g, const Cands &c) {
   if (A.heavy_cap <= 0 || A.dbg) return false;
   int slot = 0;
   if (lane() == 0) slot = atomicAdd(&A.work[6], 1);
   slot = __shfl(slot, 0, kWave);
   if (slot >= A.heavy_cap) return false;
-  if (lane() == 0) A.heavy[slot] = g;
+  if (lane() == 0) {
+    A.heavy[slot] = g;
+    A.heavy_key[slot] = c.cached ? c.nleaf : INT32_MAX;
+  }
   return true;
 }
 
@@ -380,7 +385,7 @@ __device__ SolveOut solve_length(const DensArgs &A, int g, int root, const NodeB
       c = gather(A, root, gb, R, gas_only, s_stack, s_leaf, s_snk, fail);
       gathered = true;
       if (fail) break;
-      if ((!c.cached || c.nleaf > A.split_leaves) && hand_off(A, g)) {
+      if ((!c.cached || c.nleaf > A.split_leaves) && hand_off(A, g, c)) {
         o.handed = true;
         return o;
       }
@@ -604,7 +609,7 @@ __device__ BothOut solve_both(const DensArgs &A, int g, int root, const NodeBox 
       c = gather(A, root, gb, R, false, s_stack, s_leaf, s_snk, fail);
       gathered = true;
       if (fail) break;
-      if ((!c.cached || c.nleaf > A.split_leaves) && hand_off(A, g)) {
+      if ((!c.cached || c.nleaf > A.split_leaves) && hand_off(A, g, c)) {
         o.handed = true;
         return o;
       }
@@ -979,6 +984,33 @@ __device__ __forceinline__ SolveOut solve_one(const DensArgs &A, int root, bool 
   return o;
 }
 
+// Power-of-two class of a hand-off key.
+__device__ __forceinline__ int key_class(int32_t key) { return 31 - __clz(key > 1 ? key : 1); }
+
+// Orders the handed-off batches by the class of their candidate-leaf count,
+// largest first, so that the longest one-sink solves start first instead of
+// trailing the kernel.  The order within a class is arbitrary: the sinks'
+// solves are independent of one another and of the order they run in.
+__global__ __launch_bounds__(1024) void k_heavy_order(DensArgs A) {
+  __shared__ int s_cnt[32];
+  const int n = min(A.work[6], A.heavy_cap);
+  const int t = threadIdx.x;
+  if (t < 32) s_cnt[t] = 0;
+  __syncthreads();
+  for (int i = t; i < n; i += blockDim.x) atomicAdd(&s_cnt[key_class(A.heavy_key[i])], 1);
+  __syncthreads();
+  if (t == 0) {
+    int off = 0;
+    for (int b = 31; b >= 0; b--) {
+      const int k = s_cnt[b];
+      s_cnt[b] = off;
+      off += k;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += blockDim.x) A.heavy_ord[atomicAdd(&s_cnt[key_class(A.heavy_key[i])], 1)] = A.heavy[i];
+}
+
 __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
   __shared__ int s_stack[kDensStackCap];
   __shared__ int s_leaf[kDensSinkLeafCap];
@@ -993,7 +1025,7 @@ __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
     const int t = s_t;
     __syncthreads();
     if (t >= nslot * kWave) break;
-    const int g = A.heavy[t / kWave];
+    const int g = A.heavy_ord[t / kWave];
     const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, g);
     for (int j = t % kWave; j < bt.count; j += kWave) {
       const int p = bt.first + j;
@@ -1097,15 +1129,19 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
                  ? 1
                  : 0;
   A.heavy = c->heavy;
+  A.heavy_key = c->heavy + c->heavy_cap;
+  A.heavy_ord = c->heavy + 2 * c->heavy_cap;
   // debug lists are written by the batch's own wave
   A.heavy_cap = (c->dbg_nbr || c->p.split_leaves == 0) ? 0 : (int32_t)c->heavy_cap;
   A.split_leaves = c->p.split_leaves;
   const bool fused = A.hydro && A.gravity && !A.shared && A.soft_mode != TSPH_SOFT_CONSTANT;
   void (*kd)(DensArgs) = fused ? k_density<true> : k_density<false>;
   hipLaunchKernelGGL(kd, dim3(persistent_blocks(c, (const void *)kd)), dim3(64), 0, st, A);
-  if (A.heavy_cap > 0)
+  if (A.heavy_cap > 0) {
+    hipLaunchKernelGGL(k_heavy_order, dim3(1), dim3(1024), 0, st, A);
     hipLaunchKernelGGL(k_density_sink, dim3(persistent_blocks(c, (const void *)k_density_sink)), dim3(64), 0, st,
                        A);
+  }
   TSPH_HIP_CHECK(c, hipGetLastError());
   return tsph_impl_refresh(c, st);
 }

@@ -184,7 +184,8 @@ struct Ctx {
   double4 *split_part;    // split_cap x 64 partial (ax, ay, az, pot) of the items
   int64_t split_cap;
   int32_t *split_head;    // cap_nodes: first item of each batch (-1: none), items chained in order
-  int32_t *heavy;         // heavy_cap batches whose length solves run one sink per wavefront
+  int32_t *heavy;         // heavy_cap batches whose length solves run one sink per wavefront,
+                          // then heavy_cap sort keys, then heavy_cap batches in processing order
   int64_t heavy_cap;
   uint32_t *flags;        // device flag word
   int32_t *noconv;        // unconverged solves
