@@ -17,13 +17,36 @@ def _centre(ic, c):
     return int(np.argmin(np.sum((pos - c) ** 2, 1)))
 
 
+def _lattice_length(eta):
+    """Self-consistent h of an interior particle of an infinite simple-cubic
+    lattice of unit spacing and unit masses: the lattice sum of the cubic
+    spline kernel, n(h) = sum_v w(|v|/h) / (pi h^3), and a bracketed root of
+    h^3 n(h) = eta^3 (Sect. 2.1 Eq. etan, Sect. 3 Eq. nsum), written here
+    from the definitions, independently of the oracle.  Returns (h, n - 1)."""
+    from scipy.optimize import brentq
+    g = np.arange(-5, 6)
+    v = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3).astype(float)
+    r = np.sqrt((v ** 2).sum(1))
+
+    def n_of(h):
+        q = r / h
+        w = np.where(q < 1, 1 - 1.5 * q ** 2 + 0.75 * q ** 3, np.where(q < 2, 0.25 * (2 - q) ** 3, 0.0))
+        return w.sum() / (np.pi * h ** 3)
+
+    h = brentq(lambda h: h ** 3 * n_of(h) - eta ** 3, 0.9, 1.6, xtol=1e-15)
+    return h, n_of(h) - 1.0
+
+
 @pytest.mark.parametrize("eta", ["1.2", "1.2143", "1.1428"])
 def test_lattice_self_consistent_length(orc, eta):
     ic = inputs.cubic_lattice(14)
     p = orc.params(eta_h=float(eta), eta_eps=float(eta), gravity=0, hydro=1, h_tol=1e-12)
     out = orc.compute_forces(ic, p)
     c = _centre(ic, 7.0)
-    assert out["h"][c] == pytest.approx(LAT["h_over_delta"][eta], abs=2e-6)
+    h_ref, excess = _lattice_length(float(eta))
+    assert LAT["h_over_delta"][eta] == pytest.approx(h_ref, abs=1e-6)  # the stored fixture agrees
+    assert out["h"][c] == pytest.approx(h_ref, abs=1e-10)
+    assert out["rho"][c] - 1.0 == pytest.approx(excess, rel=1e-6)
     assert out["rho"][c] - 1.0 == pytest.approx(LAT["rho_excess"][eta], rel=0.1)
     # every interior particle equal to round-off
     pos = np.stack([ic["x"], ic["y"], ic["z"]], 1)
