@@ -177,6 +177,33 @@ def run_form(args, ic, form: str, torch, tsph) -> dict:
             "device_flags": flags, "roofline": roof}
 
 
+def machine_probes(torch, tsph) -> dict:
+    """Measured denominators on this GPU: the issue rate of independent FMA
+    chains built as the walk kernels are (FP32 without packed issue, FP64)
+    and the HBM bandwidth of a stream triad, each over three timed launches."""
+    sink = torch.zeros(1, dtype=torch.float64, device="cuda")
+    res = {}
+
+    def timed(kind, n, *ptrs):
+        tsph.tsph_probe(kind, n, *ptrs)  # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        work = sum(tsph.tsph_probe(kind, n, *ptrs) for _ in range(3))
+        e1.record()
+        torch.cuda.synchronize()
+        return work / (e0.elapsed_time(e1) / 1e3)
+
+    res["fp32_fma_tflops"] = round(timed(tsph.PROBE_FMA32, 256, sink.data_ptr()) / 1e12, 2)
+    res["fp64_fma_tflops"] = round(timed(tsph.PROBE_FMA64, 256, sink.data_ptr()) / 1e12, 2)
+    n = 1 << 26
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b, c = torch.ones_like(a), torch.ones_like(a)
+    res["hbm_triad_tbps"] = round(timed(tsph.PROBE_TRIAD, n, a.data_ptr(), b.data_ptr(), c.data_ptr()) / 1e12, 2)
+    res["triad_bytes_per_launch"] = 24 * n
+    del a, b, c
+    return res
+
+
 def cpu_baseline(nps: int, seed: int):
     """The FP64 oracle, as it stands, on the same recipe at a reduced size:
     one full force evaluation plus the two half kicks."""
@@ -253,6 +280,14 @@ def main():
     for form, r in forms.items():
         if form != headline:
             out[f"{form}_form"] = r
+    probe = machine_probes(torch, tsph)
+    log(f"[bench] probes: {probe}")
+    out["machine_probe"] = probe
+    for r in [out["roofline"]] + [out[f"{f}_form"]["roofline"] for f in forms if f != headline]:
+        if r:
+            mp = probe["fp32_fma_tflops"] if r["arithmetic"] == "fp32" else probe["fp64_fma_tflops"]
+            r["measured_peak"] = mp
+            r["frac_of_measured_peak"] = round(r["achieved"] / mp, 4)
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_nps, args.seed)

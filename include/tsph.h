@@ -224,6 +224,21 @@ tsph_status tsph_read_flags(void *ctx, uint32_t *flags, int64_t *n_noconv);
 tsph_status tsph_timing(void *ctx, int32_t enable);
 tsph_status tsph_phase_times(void *ctx, double *ms_out /* [5] */, int64_t *calls);
 
+/* Machine probes for the roofline denominators; they measure the machine,
+ * not an operation of the paper.  TSPH_PROBE_FMA32 / TSPH_PROBE_FMA64:
+ * 4096 x 256 threads each run n rounds (1 <= n <= 2^20) of 8 independent
+ * FMA chains in FP32 / FP64, compiled as the walk kernels are (packed FP32
+ * off); *work = the flops executed; a is one device double that is never
+ * written in practice (it keeps the chains alive).  TSPH_PROBE_TRIAD:
+ * a[i] = b[i] + 0.5 c[i] for i < n over caller-owned device arrays of n
+ * doubles; *work = 24 n bytes moved.  Enqueued on stream (NULL: the default
+ * stream) and asynchronous: time it with events on that stream.  TSPH_EINVAL
+ * for an unknown kind, a bad n or a null pointer; TSPH_EHIP if the launch
+ * fails. */
+enum { TSPH_PROBE_FMA32 = 0, TSPH_PROBE_FMA64 = 1, TSPH_PROBE_TRIAD = 2 };
+tsph_status tsph_probe(int32_t kind, int64_t n, double *a, const double *b, const double *c, void *stream,
+                       double *work);
+
 /* Debug exports (synchronous copies to host memory, for the tests). */
 enum { TSPH_DBG_KEYS = 0,      /* uint64[n] sorted Morton keys                         */
        TSPH_DBG_PERM = 1,      /* int32[n] sorted position -> caller index             */

@@ -90,6 +90,7 @@ def lib():
             "tsph_debug_export": ([_P, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
             "tsph_last_error": ([_P], C.c_char_p),
             "tsph_version": ([], C.c_char_p),
+            "tsph_probe": ([C.c_int32, C.c_int64, _P, _P, _P, _P, C.POINTER(C.c_double)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -102,7 +103,7 @@ def lib():
 EXPORTED = ("tsph_create", "tsph_destroy", "tsph_set_params", "tsph_default_params", "tsph_bytes_required",
             "tsph_set_members", "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_kick_drift_dt", "tsph_carry_bytes",
             "tsph_carry_save", "tsph_carry_load", "tsph_timestep", "tsph_diagnostics", "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
-            "tsph_timing", "tsph_phase_times")
+            "tsph_timing", "tsph_phase_times", "tsph_probe")
 PHASES = ("tree", "density", "gravity", "sph", "finish")
 
 
@@ -228,6 +229,18 @@ def tsph_phase_times(ctx):
     calls = C.c_int64(0)
     _check("tsph_phase_times", lib().tsph_phase_times(ctx, ms, C.byref(calls)), ctx)
     return dict(zip(PHASES, list(ms))), int(calls.value)
+
+
+PROBE_FMA32, PROBE_FMA64, PROBE_TRIAD = 0, 1, 2
+
+
+def tsph_probe(kind: int, n: int, a_ptr: int, b_ptr: int = 0, c_ptr: int = 0, stream=None) -> float:
+    """Enqueue a machine probe (FMA chains or a stream triad) on the stream;
+    returns the flops or bytes it performs."""
+    work = C.c_double(0.0)
+    _check("tsph_probe", lib().tsph_probe(int(kind), int(n), C.c_void_p(a_ptr), C.c_void_p(b_ptr),
+                                          C.c_void_p(c_ptr), _stream(stream), C.byref(work)))
+    return work.value
 
 
 def tsph_debug_lists(ctx, max_per_particle: int):

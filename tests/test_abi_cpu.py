@@ -56,3 +56,12 @@ def test_param_struct_layout_matches_header(T):
     assert C.sizeof(T.Params) == 8 * 2 + 4 * 2 + 8 * 6 + 4 * 2 + 8 * 2 + 4 * 6 + 8 + 4 + 4
     assert T.Params.max_members.offset == C.sizeof(T.Params) - 8
     assert C.sizeof(T.State) == 8 * 2 + 8 * 20
+
+
+def test_probe_argument_checks(T):
+    # validated on the host before any launch (the pointers are never used)
+    for kind, n, a, b in ((7, 1, 8, 8), (T.PROBE_FMA32, 0, 8, 8), (T.PROBE_FMA64, (1 << 20) + 1, 8, 8),
+                          (T.PROBE_FMA32, 1, 0, 8), (T.PROBE_TRIAD, 10, 8, 0)):
+        with pytest.raises(T.TsphError) as e:
+            T.tsph_probe(kind, n, a, b, 8, stream=0)
+        assert e.value.status == T.TSPH_EINVAL, (kind, n)
