@@ -984,6 +984,163 @@ __device__ __forceinline__ SolveOut solve_one(const DensArgs &A, int root, bool 
   return o;
 }
 
+// Contribution of a candidate to both lengths' sums of the sink at
+// (px, py, pz): the gas length over gas candidates within 2h (R2h < 0: that
+// solve is done), the softening length over all candidates within 2 eps
+// (R2e < 0: done); the terms of each are those of add_candidate, the
+// softening length's mass-weighted d phi / d eps kept in the rho slot.
+__device__ __forceinline__ void add_candidate2(const CandLoad &c, double px, double py, double pz, const double4 &vp,
+                                               double R2h, double ih, double ih3, double ih4, double R2e, double ie,
+                                               double ie3, double ie4, Sums5 &sh, Sums5 &se) {
+  const double4 &a = c.a, &v = c.v;
+  const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+  const bool in_h = !c.skip && r2 < R2h;
+  const bool in_e = r2 < R2e;
+  if (!in_h && !in_e) return;
+  const double ir = r2 > 0.0 ? rsq64(r2) : 0.0;
+  const double r = r2 * ir;
+  const double dot = (vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z);
+  if (in_h) {
+    const double qq = r * ih;
+    double w, dw;
+    m4(qq, w, dw);
+    const double W = w * ih3;
+    const double dWdh = -(3.0 * w + qq * dw) * ih4;
+    sh.n += W;
+    sh.sdh += dWdh;
+    sh.rho += a.w * W;
+    sh.msdh += a.w * dWdh;
+    if (r > 0.0) sh.divv += dw * ih4 * ir * dot;
+  }
+  if (in_e) {
+    const double qq = r * ie;
+    double w, dw;
+    m4(qq, w, dw);
+    se.n += w * ie3;
+    se.sdh += -(3.0 * w + qq * dw) * ie4;
+    se.rho += a.w * soft_pe_q(qq, ie);
+    if (r > 0.0) se.divv += dw * ie4 * ir * dot;
+  }
+}
+
+// Both lengths' sums of one sink over the particles of leaf[0, nleaf), 64
+// candidates to a round (per-lane partial sums; the gas flag marks the
+// candidates of the gas length), two rounds loaded before they are
+// evaluated, in order.
+__device__ __forceinline__ void sink_leaf_sums2(const DensArgs &A, int nleaf, const int *leaf, double px, double py,
+                                                double pz, const double4 &vp, bool do_h, double hh, bool do_e,
+                                                double he, Sums5 &sh, Sums5 &se) {
+  const int ln = lane();
+  const double ih = 1.0 / hh, ie = 1.0 / he;
+  const double ih3 = ih * ih * ih / kPi, ie3 = ie * ie * ie / kPi;
+  const double ih4 = ih3 * ih, ie4 = ie3 * ie;
+  const double R2h = do_h ? (2.0 * hh) * (2.0 * hh) : -1.0;
+  const double R2e = do_e ? (2.0 * he) * (2.0 * he) : -1.0;
+  int fill = 0, rq = 0, q0 = 0;
+  bool pending = false;
+  for (int c1 = 0; c1 < nleaf; c1 += kWave) {
+    const int nc = min(kWave, nleaf - c1);
+    const NodeTopo my = ln < nc ? A.topo[leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
+    for (int j = 0; j < nc; j++) {
+      const int first = __builtin_amdgcn_readlane(my.first, j);
+      const int count = __builtin_amdgcn_readlane(my.count, j);
+      for (int off = 0; off < count;) {
+        const int tk = min(count - off, kWave - fill);
+        if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
+        fill += tk;
+        off += tk;
+        if (fill == kWave) {
+          fill = 0;
+          if (!pending) {
+            q0 = rq;
+            pending = true;
+          } else {
+            const CandLoad c0 = load_candidate(A, q0, true, true);
+            const CandLoad c1 = load_candidate(A, rq, true, true);
+            add_candidate2(c0, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, sh, se);
+            add_candidate2(c1, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, sh, se);
+            pending = false;
+          }
+        }
+      }
+    }
+  }
+  if (pending) {
+    const CandLoad c = load_candidate(A, q0, true, true);
+    add_candidate2(c, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, sh, se);
+  }
+  if (ln < fill) {
+    const CandLoad c = load_candidate(A, rq, true, true);
+    add_candidate2(c, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, sh, se);
+  }
+}
+
+__device__ __forceinline__ Sums5 wave_sum5(const Sums5 &s) {
+  return Sums5{wave_sum(s.n), wave_sum(s.sdh), wave_sum(s.rho), wave_sum(s.msdh), wave_sum(s.divv)};
+}
+
+// Both self-consistent lengths of one gas sink when they are independent
+// (as solve_both for a batch): one candidate set for the larger search
+// ball, each length iterating until its own Newton step is small.
+__device__ __forceinline__ BothOut solve_one_both(const DensArgs &A, int root, double guess_h, bool cold_h,
+                                                  double guess_e, bool cold_e, const double4 &a, const double4 &vp,
+                                                  int *s_stack, int *s_leaf, double4 *s_snk) {
+  BothOut o;
+  o.handed = false;
+  Solver H, E;
+  solver_init(H, A, root, true, true, A.eta_h, guess_h, cold_h);
+  solver_init(E, A, root, true, false, A.eta_eps, guess_e, cold_e);
+  const NodeBox pb{a.x, a.y, a.z, 0.0, a.x, a.y, a.z, 0.0};
+  bool fail = false, gathered = false;
+  Cands c{0, true, 0.0, false};
+  for (int it = 0; it < A.maxit && (!H.done || !E.done); it++) {
+    bool need = !gathered;
+    if (!H.done && H.h > H.rc) {
+      H.rc = H.h * (1.0 + A.kappa);
+      need = true;
+    }
+    if (!E.done && E.h > E.rc) {
+      E.rc = E.h * (1.0 + A.kappa);
+      need = true;
+    }
+    if (need) {
+      const double R = fmax(H.done ? 0.0 : 2.0 * H.rc, E.done ? 0.0 : 2.0 * E.rc);
+      s_snk[lane()] = make_double4(a.x, a.y, a.z, lane() == 0 ? R : 0.0);
+      __syncthreads();
+      c = gather(A, root, pb, R, false, s_stack, s_leaf, s_snk, fail, true, kDensSinkLeafCap);
+      gathered = true;
+      if (fail) break;
+    }
+    Sums5 sh{0, 0, 0, 0, 0}, se{0, 0, 0, 0, 0};
+    if (c.cached) {
+      sink_leaf_sums2(A, c.nleaf, s_leaf, a.x, a.y, a.z, vp, !H.done, H.h, !E.done, E.h, sh, se);
+    } else {
+      const bool wok = walk_leaves(
+          A, root, pb, c.R, false, s_stack, s_leaf, s_snk, kWave,
+          [&](int nl, bool) {
+            sink_leaf_sums2(A, nl, s_leaf, a.x, a.y, a.z, vp, !H.done, H.h, !E.done, E.h, sh, se);
+            return true;
+          },
+          true);
+      if (!wok) {
+        fail = true;
+        break;
+      }
+    }
+    solver_update(H, A, wave_sum5(sh), A.eta_h);
+    solver_update(E, A, wave_sum5(se), A.eta_eps);
+  }
+  o.h.h = H.h_keep;
+  o.h.s = Sums{H.keep.n, H.keep.sdh, H.keep.rho, H.keep.msdh, 0.0, H.keep.divv};
+  o.h.ok = H.ok && !fail;
+  o.h.handed = false;
+  o.e.h = E.h_keep;
+  o.e.s = Sums{E.keep.n, E.keep.sdh, 0.0, 0.0, E.keep.rho, E.keep.divv};
+  o.e.ok = E.ok && !fail;
+  o.e.handed = false;
+  return o;
+}
+
 // Power-of-two class of a hand-off key.
 __device__ __forceinline__ int key_class(int32_t key) { return 31 - __clz(key > 1 ? key : 1); }
 
@@ -1036,7 +1193,20 @@ __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
       oh.h = 0.0;
       oh.ok = true;
       oh.s = Sums{0, 0, 0, 0, 0, 0};
-      if (A.hydro && is_gas) {
+      const bool fused = A.hydro && A.gravity && !A.shared && A.soft_mode != TSPH_SOFT_CONSTANT;
+      SolveOut oe_f;
+      bool both = false;
+      if (fused && is_gas) {  // both lengths of a gas sink in one candidate scan per pass
+        const double gh = A.hs[p], ge = A.es[p];
+        const BothOut b = solve_one_both(A, bt.root, gh > 0.0 ? gh : cold_guess(A, p, true, A.eta_h), !(gh > 0.0),
+                                         ge > 0.0 ? ge : cold_guess(A, p, false, A.eta_eps), !(ge > 0.0), a, vp,
+                                         s_stack, s_leaf, s_snk);
+        oh = b.h;
+        oe_f = b.e;
+        both = true;
+        if (!oh.ok) nnoconv++;
+        if (!oe_f.ok) nnoconv++;
+      } else if (A.hydro && is_gas) {
         const double g0 = A.hs[p];
         const double guess = g0 > 0.0 ? g0 : cold_guess(A, p, true, A.eta_h);
         oh = solve_one(A, bt.root, true, A.eta_h, guess, !(g0 > 0.0), a, vp, true, A.shared != 0, s_stack, s_leaf,
@@ -1054,11 +1224,16 @@ __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
           xi = (A.soft_mode == TSPH_SOFT_ADAPTIVE) ? -(oh.h / (3.0 * oh.s.n)) * oh.s.mdphi : 0.0;
           divve = -oh.s.divv / (oh.s.n * ups);
         } else {
-          const double g0 = A.es[p];
-          const double guess = g0 > 0.0 ? g0 : cold_guess(A, p, false, A.eta_eps);
-          const SolveOut oe =
-              solve_one(A, bt.root, false, A.eta_eps, guess, !(g0 > 0.0), a, vp, true, true, s_stack, s_leaf, s_snk);
-          if (!oe.ok) nnoconv++;
+          SolveOut oe;
+          if (both) {
+            oe = oe_f;
+          } else {
+            const double g0 = A.es[p];
+            const double guess = g0 > 0.0 ? g0 : cold_guess(A, p, false, A.eta_eps);
+            oe = solve_one(A, bt.root, false, A.eta_eps, guess, !(g0 > 0.0), a, vp, true, true, s_stack, s_leaf,
+                           s_snk);
+            if (!oe.ok) nnoconv++;
+          }
           eps = oe.h;
           neps = oe.s.n;
           ups = 1.0 + (oe.h / (3.0 * oe.s.n)) * oe.s.sdh;
