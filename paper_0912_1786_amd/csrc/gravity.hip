@@ -192,8 +192,9 @@ __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const Grav
 __device__ __forceinline__ float rsq32(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // fmaxf of two non-negative floats, as the larger bit pattern (no NaN
-// canonicalisation).  With e2 = 2 eps, (max e2)^2 rounds to the same value
-// as 4 max(eps)^2: both are the one rounding of the exact 4 max(eps)^2.
+// canonicalisation).  With s4 = (2 eps)^2 rounded, max(s4_i, s4_j) is the
+// value 4 max(eps_i, eps_j)^2 rounds to: rounding the square is monotone,
+// and both are the one rounding of the exact 4 max(eps)^2.
 __device__ __forceinline__ float max_nonneg(float a, float b) {
   return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
 }
@@ -209,7 +210,7 @@ struct alignas(16) NodeF32 {
 // particle record staged for the FP32 form (32 B)
 struct alignas(16) RecF32 {
   float x, y, z, m;
-  float eps, ieps, xiu, e2;  // e2 = 2 eps
+  float eps, ieps, xiu, s4;  // s4 = (2 eps)^2
 };
 
 // LDS staging tiles of the two forms
@@ -224,7 +225,7 @@ union Tile32 {
 
 struct Sink32 {
   float x, y, z, m, im, eps, ieps, xiu;  // position relative to the batch centre
-  float e2;                              // 2 eps
+  float s4;                              // (2 eps)^2
   float tax, tay, taz, tpot;             // sums over the current tile
   double ax, ay, az, pot;                // totals (in units of G)
   int p;
@@ -285,8 +286,7 @@ template <int M>
 __device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b) {
   const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
   const float r2 = dx * dx + dy * dy + dz * dz;
-  const float e2 = max_nonneg(s.e2, b.e2);
-  if (r2 >= e2 * e2) {
+  if (r2 >= max_nonneg(s.s4, b.s4)) {
     newton_pair32<M>(s, b);
     return;
   }
@@ -319,8 +319,7 @@ __device__ __forceinline__ void near_tile32(Sink32 &s, const RecF32 *rec, const 
     const RecF32 b = rec[j];
     const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
-    const float e2 = max_nonneg(s.e2, b.e2);
-    const bool near = r2 < e2 * e2;
+    const bool near = r2 < max_nonneg(s.s4, b.s4);
     const float ir = near ? 0.0f : rsq32(r2);
     const float mr = b.m * ir;
     const float f = mr * ir * ir;
@@ -374,7 +373,7 @@ __device__ __forceinline__ int near_entries(const GravArgs &A, SinkT<F32> &s, co
         RecF32 h;
         h.x = (float)(r.x - cx); h.y = (float)(r.y - cy); h.z = (float)(r.z - cz);
         h.m = (float)r.m; h.eps = (float)r.eps; h.ieps = (float)r.ieps; h.xiu = (float)r.xiu;
-        h.e2 = 2.0f * h.eps;
+        h.s4 = (2.0f * h.eps) * (2.0f * h.eps);
         T.rec32[ln] = h;
       } else {
         T.rec[ln] = r;
@@ -440,7 +439,7 @@ __device__ __forceinline__ void load_sink(const GravArgs &A, SinkT<F32> &s, cons
     s.x = (float)(r.x - cx); s.y = (float)(r.y - cy); s.z = (float)(r.z - cz);
     s.m = (float)r.m; s.im = (float)(1.0 / r.m);
     s.eps = (float)r.eps; s.ieps = (float)r.ieps; s.xiu = (float)r.xiu;
-    s.e2 = 2.0f * s.eps;
+    s.s4 = (2.0f * s.eps) * (2.0f * s.eps);
     s.tax = s.tay = s.taz = s.tpot = 0.0f;
   } else {
     s.x = r.x; s.y = r.y; s.z = r.z; s.m = r.m; s.im = 1.0 / r.m;
