@@ -684,7 +684,8 @@ __device__ __forceinline__ void store_outputs(const DensArgs &A, int p, bool is_
   A.soft[p] = make_double2(eps, xiu);
   GravRec gr;
   gr.x = a.x; gr.y = a.y; gr.z = a.z; gr.m = a.w;
-  gr.eps = eps; gr.ieps = eps > 0.0 ? 1.0 / eps : 0.0; gr.xiu = xiu; gr.pad = 0.0;
+  gr.eps = eps; gr.ieps = eps > 0.0 ? 1.0 / eps : 0.0; gr.xiu = xiu;
+  gr.s4 = (2.0 * eps) * (2.0 * eps);
   A.grec[p] = gr;
   if (is_gas) {
     SphRec sr;

@@ -66,6 +66,7 @@ struct GravArgs {
 
 struct Sink {
   double x, y, z, m, im, eps, ieps, xiu;
+  double s4;  // (2 eps)^2: the squared softening reach of a pair is the larger s4
   double ax, ay, az, pot;
   int p;
   bool act;
@@ -109,8 +110,7 @@ template <int M>
 __device__ __forceinline__ void near_pair(const GravArgs &A, Sink &s, const GravRec &b) {
   const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
   const double r2 = dx * dx + dy * dy + dz * dz;
-  const double em = fmax(s.eps, b.eps);
-  if (r2 >= 4.0 * em * em) {
+  if (r2 >= fmax(s.s4, b.s4)) {
     const double ir = rsq64(r2);
     const double mr = b.m * ir;
     const double f = A.G * mr * ir * ir;
@@ -162,8 +162,7 @@ __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const Grav
     const GravRec b = rec[j];
     const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const double em = fmax(s.eps, b.eps);
-    const bool near = r2 < 4.0 * em * em;
+    const bool near = r2 < fmax(s.s4, b.s4);
     const double ir = near ? 0.0 : rsq64(r2);
     const double mr = b.m * ir;
     const double f = A.G * mr * ir * ir;
@@ -443,7 +442,7 @@ __device__ __forceinline__ void load_sink(const GravArgs &A, SinkT<F32> &s, cons
     s.tax = s.tay = s.taz = s.tpot = 0.0f;
   } else {
     s.x = r.x; s.y = r.y; s.z = r.z; s.m = r.m; s.im = 1.0 / r.m;
-    s.eps = r.eps; s.ieps = r.ieps; s.xiu = r.xiu;
+    s.eps = r.eps; s.ieps = r.ieps; s.xiu = r.xiu; s.s4 = r.s4;
     s.dbg = (dbg && A.dbg && s.act) ? A.dbg + ((int64_t)2 * A.cap_n + A.perm[s.p]) * A.dbg_max : nullptr;
     s.ndbg = 0;
   }

@@ -44,7 +44,7 @@ struct NodeTopo {
 // Source record of a particle for the gravity walk (64 B, one scalar load).
 struct GravRec {
   double x, y, z, m;
-  double eps, ieps, xiu, pad;  // eps, 1/eps, xi~ / Upsilon
+  double eps, ieps, xiu, s4;  // eps, 1/eps, xi~ / Upsilon, (2 eps)^2
 };
 
 // Source record of a gas particle for the SPH pairs (128 B).
