@@ -220,7 +220,14 @@ def cpu_baseline(nps: int, seed: int):
     O.kick_drift(st, 1e-4, 1, (out["ax"], out["ay"], out["az"]), out["dudt"])
     dt = time.perf_counter() - t0
     n = ic["n"]
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "particle-steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": f"same recipe at N={n} (2x{nps}, seed {seed}): one force evaluation "
                       f"(tree, h/eps solves, group walk, SPH) + KDK kicks, {dt:.2f} s wall"}
 
