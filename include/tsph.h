@@ -79,8 +79,15 @@ enum { TSPH_KD_FIRST = 0, TSPH_KD_SECOND = 1 };
 #define TSPH_FLAG_STACK_OVERFLOW 0x2u /* a walk stack overflowed (result invalid)    */
 #define TSPH_FLAG_LIST_OVERFLOW 0x4u  /* a candidate list overflowed (result invalid) */
 #define TSPH_FLAG_NOCONV 0x8u         /* an h/eps solve did not converge             */
-#define TSPH_FLAG_NONFINITE 0x10u     /* a non-finite input position or mass         */
+#define TSPH_FLAG_NONFINITE 0x10u     /* a non-finite input position or mass, or a   *
+                                       * constant softening length that is not > 0  *
+                                       * (results invalid)                          */
 #define TSPH_FLAG_INTERNAL 0x20u      /* an internal index check failed (bug)        */
+/* The work-item store of the near-field hand-off (split_leaves) ran out: some
+ * walk batches evaluated their whole gravity near field or SPH candidate set
+ * themselves.  The results stay valid, but their last bits then depend on
+ * which batches got items first (not bitwise reproducible from run to run). */
+#define TSPH_FLAG_HANDOFF_CAPACITY 0x40u
 
 typedef struct {
   double G;            /* gravitational constant                               */
@@ -210,9 +217,10 @@ tsph_status tsph_timestep(void *ctx, const tsph_state *s, double *dt_device, voi
  * Pz, Lx, Ly, Lz; nine per system held (system k at out_device[9k]).
  * Needs s->pot from the last force pass. */
 tsph_status tsph_diagnostics(void *ctx, const tsph_state *s, double *out_device, void *stream);
-/* Synchronise the context's last stream and return the OR of the device flag
- * bits since the previous call (then clear them); n_noconv receives the
- * number of unconverged length solves. */
+/* Return the OR of the device flag bits since the previous call (then clear
+ * them); n_noconv receives the number of unconverged length solves.  The
+ * copies and the clearing are ordered on the context's last stream, and the
+ * call waits for that stream only (not for the whole device). */
 tsph_status tsph_read_flags(void *ctx, uint32_t *flags, int64_t *n_noconv);
 
 /* Per-phase timing with HIP events recorded on the stream of each
@@ -267,8 +275,18 @@ tsph_status tsph_debug_lists(void *ctx, int32_t max_per_particle);
 tsph_status tsph_debug_export(void *ctx, int32_t what, void *host, size_t cap_bytes,
                               size_t *written);
 
+/* Limit the near-field hand-off (tsph_params.split_leaves) of the following
+ * force passes to at most `items` work items (0: the context's full store),
+ * so that tests can exhaust it on small inputs; exhaustion raises
+ * TSPH_FLAG_HANDOFF_CAPACITY.  Host-only, takes effect at the next call. */
+tsph_status tsph_debug_handoff_cap(void *ctx, int64_t items);
+
 const char *tsph_last_error(const void *ctx);
 const char *tsph_version(void);
+/* Identity of the sources the library was built from: the first 16 hex
+ * digits of a SHA-256 over the HIP sources and this header (the binding
+ * refuses a library whose identity differs from the sources beside it). */
+const char *tsph_source_id(void);
 
 #ifdef __cplusplus
 }

@@ -44,7 +44,7 @@ class Run(C.Structure):
                 ("ax", D), ("ay", D), ("az", D), ("pot", D), ("dudt", D), ("maxmu", D),
                 ("cnt_node", I64), ("cnt_pair", I64), ("cnt_sph", I64), ("iters", I32),
                 ("n_noconv", C.c_int64), ("sinks", I64), ("n_sinks", C.c_int64), ("cnt_soft", I64),
-                ("divv_eps", D)]
+                ("divv_eps", D), ("t_phase", C.c_double * 4)]
 
 
 def eta_from_nnei(nnei: float) -> float:
@@ -52,10 +52,21 @@ def eta_from_nnei(nnei: float) -> float:
     return 0.5 * (3.0 * nnei / (4.0 * np.pi)) ** (1.0 / 3.0)
 
 
+_LIB_PATH = None
+
+
+def use_library(path: str):
+    """Load the oracle from another build of the same source (for example
+    one compiled for the host CPU); later calls go to it."""
+    global _LIB, _LIB_PATH
+    _LIB, _LIB_PATH = None, path
+    return lib()
+
+
 def lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle.so")
+        path = _LIB_PATH or os.path.join(_HERE, "liboracle.so")
         if not os.path.exists(path):
             from . import build as _b  # noqa: F401  (package-relative when imported as oracle.oracle)
             _b.build()
@@ -158,6 +169,7 @@ def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=No
     out.update(cnt)
     out["iters"] = iters
     out["n_noconv"] = int(r.n_noconv)
+    out["t_phase"] = dict(zip(("tree", "density", "gravity", "sph"), list(r.t_phase)))
     return out
 
 

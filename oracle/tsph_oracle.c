@@ -19,8 +19,13 @@
  *                    softened Lagrangian (correction terms), momentum pinned
  *   SPH forces       finite differences of the thermal energy at fixed
  *                    entropy, exact dE/dt = 0 identity, momentum      pinned
+ *   walk batches     defining properties of the greedy sibling packing
+ *                    (partition, siblings, size, forced cuts)        pinned
  *   integrator       energy drift scaling with dt^2                   pinned
- *   timestep rule    criteria of Sect. 4.2 with the adopted etas    parity unpinned
+ *   timestep rule    each criterion of Sect. 4.2 deciding in turn on
+ *                    hand-worked values; minimum over particles       pinned
+ *   diagnostics      rigid rotation + drift: P = M V, L = M R x V + I w,
+ *                    E_kin from the inertia tensor                    pinned
  *
  * Plain loops, no blocking or fusion; OpenMP only distributes independent
  * sinks over threads.
@@ -539,6 +544,7 @@ typedef struct {
   double *P, *cs;
   int64_t *cnt_node, *cnt_pair, *cnt_sph, *cnt_soft;
   int32_t *iters;
+  int64_t noconv;             /* length solves that did not converge        */
   char *active;               /* sinks of the gravity/SPH passes            */
   /* per-node maxima after the solves */
   double *epsmax, *hmax;
@@ -705,8 +711,6 @@ static double cold_guess(const ctx_t *C, int64_t p, int gas_only, double eta)
   return eta * cbrt(s * s * s / cnt);
 }
 
-static int64_t total_noconv = 0;
-
 static void density_phase(ctx_t *C, const double *h_in, const double *eps_in)
 {
   const orc_params *P = C->p;
@@ -767,7 +771,7 @@ static void density_phase(ctx_t *C, const double *h_in, const double *eps_in)
     free(c.idx);
     free(c.stack);
   }
-  total_noconv = noconv;
+  C->noconv = noconv;
 }
 
 /* per-node maxima of eps (all) and h (gas), gas counts */
@@ -1126,12 +1130,22 @@ int orc_num_threads(void)
 #endif
 }
 
+static double wall_seconds(void)
+{
+#ifdef _OPENMP
+  return omp_get_wtime();
+#else
+  return 0.0;
+#endif
+}
+
 int orc_compute_forces(const orc_params *p, orc_run *r)
 {
   if (!p || !r || r->n <= 0 || r->n_gas < 0 || r->n_gas > r->n) return -1;
   if (!r->x || !r->y || !r->z || !r->m) return -1;
   if (p->gravity && p->soft_mode == ORC_SOFT_CONSTANT && !r->eps_in) return -1;
   int64_t n = r->n;
+  double t0 = wall_seconds();
   orc_tree *t = orc_tree_build(n, r->x, r->y, r->z, r->m, p->leaf_size);
   if (!t) return -2;
   ctx_t C;
@@ -1182,18 +1196,26 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
     for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++) g += C.gas[q];
     C.ngas[k] = g;
   }
+  double t1 = wall_seconds();
   /* 1. densities and lengths (Sect. 3.1: first, gather, walk) */
   density_phase(&C, r->h_in, r->eps_in);
   node_maxima(&C);
+  double t2 = wall_seconds();
   /* 2. gravity with the softened near field and its corrections */
   if (p->gravity) {
     if (p->walk_mode == ORC_WALK_DIRECT) gravity_direct(&C);
     else if (p->walk_mode == ORC_WALK_GROUP) gravity_group_walk(&C);
     else gravity_particle_walk(&C);
   }
+  double t3 = wall_seconds();
   /* 3. SPH pressure, viscosity and heating (Sect. 3.1: second walk) */
   if (p->hydro) sph_phase(&C);
-  r->n_noconv = total_noconv;
+  double t4 = wall_seconds();
+  r->t_phase[0] = t1 - t0;
+  r->t_phase[1] = t2 - t1;
+  r->t_phase[2] = t3 - t2;
+  r->t_phase[3] = t4 - t3;
+  r->n_noconv = C.noconv;
   /* scatter to caller order */
   for (int64_t q = 0; q < n; q++) {
     int64_t i = t->perm[q];

@@ -82,6 +82,8 @@ typedef struct {
   int64_t n_sinks;
   int64_t *cnt_soft;                               /* near pairs inside 2 max(eps) */
   double *divv_eps;                                /* div v with the eps kernel    */
+  double t_phase[4];   /* out: wall seconds of tree, length solves + densities,
+                        * gravity and SPH (instrumentation only)              */
 } orc_run;
 
 /* Full force evaluation: tree, h/eps solves, gravity walk, SPH forces.

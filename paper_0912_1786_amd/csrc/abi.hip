@@ -181,7 +181,12 @@ tsph_status check_state(Ctx *c, const tsph_state *s, bool forces) {
 
 extern "C" {
 
-const char *tsph_version(void) { return "tsph 0.1 (gfx950, FP64)"; }
+#ifndef TSPH_SOURCE_ID
+#define TSPH_SOURCE_ID "unknown"
+#endif
+const char *tsph_version(void) { return "tsph 0.2 (gfx950) sources " TSPH_SOURCE_ID; }
+
+const char *tsph_source_id(void) { return TSPH_SOURCE_ID; }
 
 void tsph_default_params(tsph_params *p) {
   if (!p) return;
@@ -321,6 +326,8 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->h_noconv = (int32_t *)(c->h_flags + 4);
   if ((e = hipMemset(c->flags, 0, 64)) != hipSuccess || (e = hipMemset(c->noconv, 0, 64)) != hipSuccess ||
       (e = hipMemset(c->lvl, 0, 256)) != hipSuccess || (e = hipMemset(c->ngroups, 0, 64)) != hipSuccess ||
+      (e = hipMemset(c->split_item, 0xff, sizeof(SplitItem) * (size_t)c->split_cap)) != hipSuccess ||
+      (e = hipMemset(c->split_head, 0xff, 4 * (size_t)c->cap_nodes)) != hipSuccess ||
       (e = hipDeviceSynchronize()) != hipSuccess)
     return create_fail(c, TSPH_EHIP, "clearing the control block", e);
   *out = c;
@@ -571,14 +578,15 @@ tsph_status tsph_diagnostics(void *ctx, const tsph_state *s, double *out_device,
 tsph_status tsph_read_flags(void *ctx, uint32_t *flags, int64_t *n_noconv) {
   Ctx *c = (Ctx *)ctx;
   if (!c) return TSPH_EINVAL;
-  TSPH_HIP_CHECK(c, hipStreamSynchronize(c->last_stream));
-  TSPH_HIP_CHECK(c, hipMemcpy(c->h_flags, c->flags, 4, hipMemcpyDeviceToHost));
-  TSPH_HIP_CHECK(c, hipMemcpy(c->h_noconv, c->noconv, 4, hipMemcpyDeviceToHost));
+  // ordered on the context's last stream only: other streams keep running
+  hipStream_t st = c->last_stream;
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(c->h_flags, c->flags, 4, hipMemcpyDeviceToHost, st));
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(c->h_noconv, c->noconv, 4, hipMemcpyDeviceToHost, st));
+  TSPH_HIP_CHECK(c, hipMemsetAsync(c->flags, 0, 4, st));
+  TSPH_HIP_CHECK(c, hipMemsetAsync(c->noconv, 0, 4, st));
+  TSPH_HIP_CHECK(c, hipStreamSynchronize(st));
   if (flags) *flags = c->h_flags[0];
   if (n_noconv) *n_noconv = c->h_noconv[0];
-  TSPH_HIP_CHECK(c, hipMemset(c->flags, 0, 4));
-  TSPH_HIP_CHECK(c, hipMemset(c->noconv, 0, 4));
-  TSPH_HIP_CHECK(c, hipDeviceSynchronize());
   return TSPH_OK;
 }
 
@@ -706,6 +714,13 @@ tsph_status tsph_debug_export(void *ctx, int32_t what, void *host, size_t cap_by
       break;
     }
   }
+  return TSPH_OK;
+}
+
+tsph_status tsph_debug_handoff_cap(void *ctx, int64_t items) {
+  Ctx *c = (Ctx *)ctx;
+  if (!c || items < 0) return TSPH_EINVAL;
+  c->split_cap_limit = items;
   return TSPH_OK;
 }
 

@@ -778,6 +778,7 @@ __global__ __launch_bounds__(64, 3) void k_density(DensArgs A) {
       } else if (A.gravity && !handed) {
         if (A.soft_mode == TSPH_SOFT_CONSTANT) {
           eps = A.es[p];
+          if (act && !(eps > 0.0 && eps < INFINITY)) atomicOr(A.flags, TSPH_FLAG_NONFINITE);
         } else if (A.shared) {
           eps = oh.h;
           neps = oh.s.n;
@@ -1218,6 +1219,7 @@ __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
       if (A.gravity) {
         if (A.soft_mode == TSPH_SOFT_CONSTANT) {
           eps = A.es[p];
+          if (!(eps > 0.0 && eps < INFINITY)) atomicOr(A.flags, TSPH_FLAG_NONFINITE);
         } else if (A.shared) {
           eps = oh.h;
           neps = oh.s.n;

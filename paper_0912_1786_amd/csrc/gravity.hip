@@ -616,7 +616,14 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
             }
             rbase = __shfl(rbase, 0, kWave);
             ibase = __shfl(ibase, 0, kWave);
-            if (ibase <= A.split_cap - imax) {
+            if (ibase > A.split_cap - imax) {
+              // capacity exhausted: the batch keeps these entries.  Item slots
+              // reserved below the capacity are marked unused, since
+              // k_gravity_split reads every slot up to the capacity.
+              for (int64_t a = (int64_t)ibase + ln; a < A.split_cap; a += kWave)
+                A.split_item[a] = SplitItem{-1, 0, 0, 0, -1, 0, 0, 0};
+              if (ln == 0) atomicOr(A.flags, TSPH_FLAG_HANDOFF_CAPACITY);
+            } else {
               handed = true;
               near_done += tot;
               npair += tot;
@@ -809,7 +816,7 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
   A.want_pot = want_pot ? 1 : 0;
   // debug lists are written by the batch's own wave
   A.split_particles = c->dbg_nbr ? 0 : c->p.split_leaves * c->p.leaf_size;
-  A.split_cap = c->split_cap;
+  A.split_cap = split_cap_used(c);
   A.split_rng = c->split_rng;
   A.split_item = c->split_item;
   A.split_part = c->split_part;

@@ -322,6 +322,8 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
               }
               prev_item = it;
               handed = true;
+            } else if (ln == 0) {
+              atomicOr(A.flags, TSPH_FLAG_HANDOFF_CAPACITY);
             }
           }
           if (!handed) done += sph_ranges(A, L, s_t, SphLeafSrc{A.topo, s_leaf}, nleaf, tc);
@@ -456,7 +458,7 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   // SPH pairs cost more per candidate than the near-field gravity pairs, so
   // the batch keeps a quarter of the gravity walk's share.
   A.split_particles = c->dbg_nbr ? 0 : c->p.split_leaves * c->p.leaf_size / 4;
-  A.split_cap = c->split_cap / 2;
+  A.split_cap = split_cap_used(c) / 2;
   A.split_rng = c->split_rng;
   A.split_item = c->split_item;
   A.split_part = c->split_part;

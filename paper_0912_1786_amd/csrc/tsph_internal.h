@@ -183,6 +183,7 @@ struct Ctx {
   SplitItem *split_item;  // split_cap work items over split_rng
   double4 *split_part;    // split_cap x 64 partial (ax, ay, az, pot) of the items
   int64_t split_cap;
+  int64_t split_cap_limit; // > 0: hand-off items used at most (tsph_debug_handoff_cap)
   int32_t *split_head;    // cap_nodes: first item of each batch (-1: none), items chained in order
   int32_t *heavy;         // heavy_cap batches whose length solves run one sink per wavefront,
                           // then heavy_cap sort keys, then heavy_cap batches in processing order
@@ -209,6 +210,11 @@ struct Ctx {
   uint32_t *h_flags;      // pinned host copy
   int32_t *h_noconv;
 };
+
+// hand-off items a force pass may use
+inline int64_t split_cap_used(const Ctx *c) {
+  return c->split_cap_limit > 0 && c->split_cap_limit < c->split_cap ? c->split_cap_limit : c->split_cap;
+}
 
 inline Members members_of(const Ctx *c, int64_t n, int64_t n_gas) {
   return Members{c->moff, c->mgas, c->nmem, n, n_gas};

@@ -107,6 +107,8 @@ class Resident:
         self.busy = False
         self.steps = 0
         self.last_use = 0.0
+        self.flag_bits = 0       # device flags raised while it was resident in earlier shells
+        self.noconv = 0
 
     @property
     def n(self) -> int:
@@ -159,6 +161,10 @@ class Resident:
         for k in HOST_KEYS:
             self.saved[k].copy_(self.sim.a[k], non_blocking=True)
         self.saved["carry"] = self.sim.carry()  # synchronises the stream: the copies are done too
+        # its device flags go with it, and the shell's next occupant starts clean
+        f, nc = self.sim.flags()
+        self.flag_bits |= f
+        self.noconv += nc
         shell = self.shell
         self.sim.close()  # borrowed context: left as it is
         self.sim, self.shell, self.graph = None, None, None
@@ -310,7 +316,15 @@ class Server:
         return done
 
     def flags(self):
-        return [(r.sid, r.sim.flags()) for r in self.res if r.sim is not None]
+        """(sid, (flag bits, unconverged solves)) of every simulation since
+        the previous call: what its shells raised while it was resident,
+        including earlier residencies."""
+        out = []
+        for r in self.res:
+            f, nc = r.sim.flags() if r.sim is not None else (0, 0)
+            out.append((r.sid, (r.flag_bits | f, r.noconv + nc)))
+            r.flag_bits, r.noconv = 0, 0
+        return out
 
     def close(self):
         self.torch.cuda.synchronize()

@@ -20,6 +20,7 @@ FP64, FP32_BULK = 0, 1
 KD_FIRST, KD_SECOND = 0, 1
 FLAG_NODE_CAPACITY, FLAG_STACK_OVERFLOW, FLAG_LIST_OVERFLOW, FLAG_NOCONV, FLAG_NONFINITE, FLAG_INTERNAL = (
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20)
+FLAG_HANDOFF_CAPACITY = 0x40
 DBG_KEYS, DBG_PERM, DBG_NODES, DBG_NNODES, DBG_MOMENTS, DBG_GROUPS, DBG_NGROUPS, DBG_COUNTS, DBG_NBR, DBG_ROOT, \
     DBG_SOLVE, DBG_BATCHES, DBG_NBATCHES = range(13)
 SOLVE_FIELDS = ("nh", "omega", "zeta", "divv", "neps", "ups", "xi", "maxmu", "divv_eps")
@@ -88,14 +89,21 @@ def lib():
             "tsph_timing": ([_P, C.c_int32], C.c_int),
             "tsph_phase_times": ([_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
             "tsph_debug_export": ([_P, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+            "tsph_debug_handoff_cap": ([_P, C.c_int64], C.c_int),
             "tsph_last_error": ([_P], C.c_char_p),
             "tsph_version": ([], C.c_char_p),
+            "tsph_source_id": ([], C.c_char_p),
             "tsph_probe": ([C.c_int32, C.c_int64, _P, _P, _P, _P, C.POINTER(C.c_double)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
+        from .srcid import source_id
+        built, here = L.tsph_source_id().decode(), source_id()
+        if built != here:
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (id {built}) than those beside it "
+                               f"(id {here}): rebuild it with paper_0912_1786_amd/build.py")
         _LIB = L
     return _LIB
 
@@ -103,7 +111,7 @@ def lib():
 EXPORTED = ("tsph_create", "tsph_destroy", "tsph_set_params", "tsph_default_params", "tsph_bytes_required",
             "tsph_set_members", "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_kick_drift_dt", "tsph_carry_bytes",
             "tsph_carry_save", "tsph_carry_load", "tsph_timestep", "tsph_diagnostics", "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
-            "tsph_timing", "tsph_phase_times", "tsph_probe")
+            "tsph_timing", "tsph_phase_times", "tsph_probe", "tsph_debug_handoff_cap", "tsph_source_id")
 PHASES = ("tree", "density", "gravity", "sph", "finish")
 
 
@@ -253,6 +261,10 @@ def tsph_debug_export(ctx, what: int, nbytes: int):
     w = C.c_size_t(0)
     _check("tsph_debug_export", lib().tsph_debug_export(ctx, int(what), buf, len(buf), C.byref(w)), ctx)
     return buf.raw[:w.value]
+
+
+def tsph_debug_handoff_cap(ctx, items: int):
+    _check("tsph_debug_handoff_cap", lib().tsph_debug_handoff_cap(ctx, int(items)), ctx)
 
 
 def tsph_last_error(ctx) -> str:

@@ -157,3 +157,46 @@ def test_autotuner_picks_a_candidate():
     assert set(times) == set(ensemble.CANDIDATES)
     assert times[best] == min(times.values())
     assert all(t > 0 for t in times.values())
+
+
+@pytest.mark.timeout(600)
+def test_256_members_equal_alone_on_a_seeded_sample():
+    """The full 256-member Evrard ensemble (about 2.3M particles) in one
+    context, stepped by graph replays; a seeded sample of 12 members (and
+    the smallest and largest) stepped alone equals its forest copy bit for
+    bit after the first forces and after two replays."""
+    _say("[ensemble] 256 members")
+    ics = ensemble.ensemble_ics(256, seed=1000)
+    prec = tsph.FP32_BULK
+    ens = ensemble.Ensemble(ics, precision=prec)
+    prm = ensemble.member_params(precision=prec)
+    sizes = np.array([ic["n"] for ic in ics])
+    rng = np.random.default_rng(256)
+    pick = sorted(set(rng.choice(256, 12, replace=False).tolist()) | {int(sizes.argmin()), int(sizes.argmax())})
+    alone = [tsph.Simulation(ics[k], prm, want_pot=False) for k in pick]
+
+    def check(tag):
+        for sim, k in zip(alone, pick):
+            for key in KEYS:
+                a, b = ens.member(k, key), sim.host(key)
+                assert np.array_equal(a, b), (tag, k, key, int(np.sum(a != b)))
+
+    try:
+        ens.first_forces()
+        for s in alone:
+            s.compute_forces()
+        torch.cuda.synchronize()
+        check("first forces")
+        ens.capture()
+        for r in range(2):
+            ens.step()
+            for s in alone:
+                s.device_step()
+            torch.cuda.synchronize()
+            check(f"replay {r}")
+        assert ens.flags() == (0, 0)
+        _say(f"    members {pick} equal alone ({ens.n_total} particles in the forest)")
+    finally:
+        ens.close()
+        for s in alone:
+            s.close()

@@ -2,13 +2,13 @@
 rule in the FP32-bulk and FP64 forms, and the FP32-bulk form's errors at the
 first force evaluation against the FP64 oracle (same tree, same walk).
 
-Bars: |dE/E| after 20 steps below 4e-3 (the paper's Evrard runs keep the
-energy error within about 0.4% over the whole collapse, with a looser theta);
-the two forms' energy drifts within 1e-5 of each other (the FP32 interaction
-error is ~1e-8 relative); momentum drift |dP| / sum m|v| below 1e-2 (tree
-forces are not pairwise symmetric); FP32-bulk accelerations and potential
-within 1e-5 relative RMS of the oracle, densities and lengths to its FP64
-bars.
+Bars, about ten times the drifts measured on the MI355X (dE/E -3.8e-8 and
+|dP| / sum m|v| 9.2e-7 after 20 steps, both forms): |dE/E| below 4e-7 and
+momentum drift below 1e-5 (tree forces are not pairwise symmetric, so
+momentum drifts at the tree-error level); the two forms' energy drifts
+within 1e-8 of each other (the FP32 interaction error is ~1e-8 relative);
+FP32-bulk accelerations and potential within 1e-5 relative RMS of the
+oracle, densities and lengths to its FP64 bars.
 """
 import sys
 
@@ -43,9 +43,10 @@ def test_evrard_20_steps_energy_and_momentum():
         _say(f"    {r['precision']}: dE/E step1 {r['dE_over_E_step1']:.3e} step20 {r['dE_over_E_step20']:.3e}; "
              f"dP step1 {r['dP_rel_step1']:.3e} step20 {r['dP_rel_step20']:.3e}; median step {r['median_step_ms']:.2f} ms")
         assert r["device_flags"] == 0 and r["noconv"] == 0
-        assert abs(r["dE_over_E_step20"]) < 4e-3
-        assert r["dP_rel_step20"] < 1e-2
-    assert abs(r32["dE_over_E_step20"] - r64["dE_over_E_step20"]) < 1e-5
+        # about ten times the measured drifts (-3.8e-8 and 9.2e-7 over 20 steps)
+        assert abs(r["dE_over_E_step20"]) < 4e-7
+        assert r["dP_rel_step20"] < 1e-5
+    assert abs(r32["dE_over_E_step20"] - r64["dE_over_E_step20"]) < 1e-8
     assert r32["dt_first"] == pytest.approx(r64["dt_first"], rel=1e-6)
 
 

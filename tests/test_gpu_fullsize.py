@@ -5,7 +5,7 @@ default load-balancing threshold, in both arithmetic forms.
 
 The oracle solves every length (so h, eps and rho are compared for every
 particle) and evaluates gravity and SPH for a seeded sample of 2048 sinks
-with the same batch walk, and the direct sum for 512 of them.  Bars: h, eps
+with the same batch walk, and the direct sum for 4096 of them.  Bars: h, eps
 to 1e-9 relative, rho to 1e-6; accelerations within 1e-5 relative RMS of
 the oracle's walk and 2e-3 of the direct sum; du/dt within 1e-6; the
 interaction counts of the sampled sinks equal to the oracle's.
@@ -33,10 +33,11 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def test_two_species_field_2m_both_forms():
+@pytest.fixture(scope="module")
+def field2m():
     from oracle import oracle as O
     ic = inputs.two_species_field(n_dm=1 << 20, n_gas=1 << 20, n_halo=64, seed=1)
-    n, n_gas = ic["n"], ic["n_gas"]
+    n = ic["n"]
     runs = {}
     for name, prec in (("fp64", tsph.FP64), ("fp32_bulk", tsph.FP32_BULK)):
         _say(f"[fullsize] GPU {name}")
@@ -46,24 +47,42 @@ def test_two_species_field_2m_both_forms():
         assert g["flags"] == 0 and g["noconv"] == 0
         runs[name] = (gp, g)
     rng = np.random.default_rng(2024)
-    sinks = np.sort(rng.choice(n, 2048, replace=False))
+    sinks = np.sort(rng.choice(n, 4096, replace=False))
     gp = runs["fp64"][0]
     _say("[fullsize] oracle: all lengths, batch walk for 2048 sinks")
-    o = O.compute_forces(ic, oracle_params(O, gp), sinks=sinks)
-    _say("[fullsize] oracle: direct sum for 512 sinks")
-    dsinks = sinks[::4]
-    od = O.compute_forces(ic, oracle_params(O, gp, walk_mode=O.WALK_DIRECT), sinks=dsinks)
+    o = O.compute_forces(ic, oracle_params(O, gp), sinks=sinks[::2])
+    return O, ic, runs, sinks, o
+
+
+@pytest.mark.timeout(900)
+def test_two_species_field_2m_both_forms(field2m):
+    O, ic, runs, sinks4k, o = field2m
+    n, n_gas = ic["n"], ic["n_gas"]
+    sinks = sinks4k[::2]
     gas = np.arange(n) < n_gas
     gs = sinks[sinks < n_gas]
     for name, (gp_, g) in runs.items():
         eh, er, ee = maxrel(g["h"], o["h"], gas), maxrel(g["rho"], o["rho"], gas), maxrel(g["eps"], o["eps"])
         ea = relrms(acc(g)[sinks], acc(o)[sinks])
-        ed = relrms(acc(g)[dsinks], acc(od)[dsinks])
         eu = relrms(g["dudt"][gs], o["dudt"][gs])
-        _say(f"    {name}: h {eh:.2e} rho {er:.2e} eps {ee:.2e}; acc vs walk {ea:.2e}, vs direct {ed:.2e}; "
-             f"du/dt {eu:.2e}")
+        _say(f"    {name}: h {eh:.2e} rho {er:.2e} eps {ee:.2e}; acc vs walk {ea:.2e}; du/dt {eu:.2e}")
         assert eh < 1e-9 and ee < 1e-9 and er < 1e-6
-        assert ea < 1e-5 and ed < 2e-3 and eu < 1e-6
+        assert ea < 1e-5 and eu < 1e-6
         assert np.array_equal(g["cnt_node"][sinks], o["cnt_node"][sinks])
         assert np.array_equal(g["cnt_pair"][sinks], o["cnt_pair"][sinks])
         assert np.array_equal(g["cnt_sph"][gs], o["cnt_sph"][gs])
+
+
+@pytest.mark.timeout(900)
+def test_two_species_field_2m_against_direct_sum(field2m):
+    """Both forms within 2e-3 relative RMS of the O(N^2) sum (every pair
+    softened and corrected) on 4096 seeded sinks: the stated accuracy at
+    which the two forms are compared."""
+    O, ic, runs, sinks, o = field2m
+    gp = runs["fp64"][0]
+    _say("[fullsize] oracle: direct sum for 4096 sinks")
+    od = O.compute_forces(ic, oracle_params(O, gp, walk_mode=O.WALK_DIRECT), sinks=sinks)
+    for name, (gp_, g) in runs.items():
+        ed = relrms(acc(g)[sinks], acc(od)[sinks])
+        _say(f"    {name}: acc vs direct {ed:.3e}")
+        assert ed < 2e-3

@@ -141,3 +141,47 @@ def test_moments_closed_forms(orc):
         if t["nchild"][k]:
             c0 = t["child"][k]
             assert t["mass"][k] == pytest.approx(t["mass"][c0:c0 + t["nchild"][k]].sum(), rel=1e-14)
+
+
+@pytest.mark.parametrize("leaf,group,case", [(16, 64, "evrard"), (8, 32, "evrard"), (1, 8, "field"), (4, 16, "field")])
+def test_walk_batches_are_the_greedy_sibling_packing(orc, leaf, group, case):
+    """The walk batches (a reading of the grouped walk: runs of consecutive
+    sibling groups packed greedily to at most 64 sinks) checked by their
+    defining properties, not by re-running the packing:
+    the batches cut the group list into consecutive runs; the groups of a
+    run are consecutive children of one parent; a run of several groups
+    holds at most 64 particles; and every cut is forced -- the next group
+    is not the following sibling of the run's last group, or adding it
+    would exceed 64.  These properties fix the greedy packing uniquely."""
+    if case == "evrard":
+        ic = inputs.evrard(5000, seed=21)
+    else:
+        ic = inputs.two_species_field(n_dm=2500, n_gas=2500, n_halo=6, seed=22)
+    t = orc.tree(ic, leaf_size=leaf, group_size=group, batch_size=64, batch_mode=0)
+    groups, batches = t["groups"], t["batches"]
+    count, parent = t["count"], t["parent"]
+    # groups: maximal nodes of <= group particles (or leaves), tiling the particles in order
+    first = t["first"][groups]
+    assert first[0] == 0 and np.array_equal(first[1:], first[:-1] + count[groups][:-1])
+    assert first[-1] + count[groups][-1] == ic["n"]
+    for k in groups:
+        assert count[k] <= group or t["nchild"][k] == 0
+        assert parent[k] < 0 or count[parent[k]] > group
+    # batches partition the group list into consecutive runs
+    assert batches[0, 0] == 0 and batches[-1, 1] == len(groups)
+    assert np.array_equal(batches[1:, 0], batches[:-1, 1])
+    assert np.all(batches[:, 1] > batches[:, 0])
+
+    def sibling_next(a, b):
+        return b == a + 1 and parent[a] == parent[b] and parent[a] >= 0
+
+    for b0, b1 in batches:
+        ks = groups[b0:b1]
+        fill = int(count[ks].sum())
+        if b1 - b0 > 1:
+            assert fill <= 64
+        for a, b in zip(ks[:-1], ks[1:]):
+            assert sibling_next(a, b)
+        if b1 < len(groups):
+            nxt = groups[b1]
+            assert not sibling_next(ks[-1], nxt) or fill + count[nxt] > 64
