@@ -17,7 +17,14 @@ scatter and time-step criteria) and the closing half kick.
 Prints ONE JSON line: particle-steps/s = N * steps / wall time of the timed
 steps, with a roofline entry for the dominant kernel (its duration measured
 with HIP events recorded on its own stream inside the timed region) and the
-FP64 oracle timed on the host's cores on a bounded sample of the same recipe.
+FP64 oracle (built -O3 -march=native on this host) timed on the host's cores
+for one step of the same workload.  "rows" adds the other configurations:
+c1 (Evrard 4096, FP64: step and per-phase times, GPU and oracle), c2 (Evrard
+262,144, 20 steps in both forms: step time, energy and momentum drift), c4
+(256-member ensemble, one graph launch per step, autotuned leaf, group and
+hand-off sizes) and c5 (serving: closed-loop saturation, then p50/p99
+latency under Poisson arrivals at 0.5x and 0.8x of it); "served_p50_ms" and
+"served_p99_ms" are those at 0.5x.
 """
 import argparse
 import json
@@ -204,32 +211,117 @@ def machine_probes(torch, tsph) -> dict:
     return res
 
 
-def cpu_baseline(nps: int, seed: int):
-    """The FP64 oracle, as it stands, on the same recipe at a reduced size:
-    one full force evaluation plus the two half kicks."""
+def load_native_oracle():
+    """The FP64 oracle built -O3 -march=native for this host (into the
+    ignored scratch folder gpurun_out/, or a temporary directory)."""
+    import tempfile
     from oracle import build as obuild, oracle as O
-    from paper_0912_1786_amd import inputs
-    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
-        obuild.build()
-    ic = inputs.two_species_field(n_dm=nps, n_gas=nps, n_halo=64, seed=seed)
-    prm = O.params(nnei=60, theta=0.5, leaf_size=16, group_size=64, walk_mode=O.WALK_GROUP)
+    d = os.path.join(ROOT, "gpurun_out")
+    try:
+        os.makedirs(d, exist_ok=True)
+    except OSError:
+        d = tempfile.mkdtemp()
+    path = obuild.build(out=os.path.join(d, "liboracle_native.so"), native=True)
+    O.use_library(path)
+    return O, "gcc -O3 -march=native -fopenmp -ffp-contract=off"
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
+def oracle_step(O, ic, prm, dt: float = 1e-4):
+    """One oracle step as the GPU runs it: force evaluation and the two half
+    kicks.  Returns (wall seconds, per-phase seconds)."""
     t0 = time.perf_counter()
     out = O.compute_forces(ic, prm)
     st = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in ic.items()}
-    O.kick_drift(st, 1e-4, 0, (out["ax"], out["ay"], out["az"]), out["dudt"])
-    O.kick_drift(st, 1e-4, 1, (out["ax"], out["ay"], out["az"]), out["dudt"])
-    dt = time.perf_counter() - t0
+    O.kick_drift(st, dt, 0, (out["ax"], out["ay"], out["az"]), out["dudt"])
+    O.kick_drift(st, dt, 1, (out["ax"], out["ay"], out["az"]), out["dudt"])
+    return time.perf_counter() - t0, out["t_phase"]
+
+
+def cpu_baseline(O, build: str, nps: int, seed: int):
+    """The FP64 oracle, as it stands, on the benchmark workload itself (the
+    2M field by default): one full force evaluation plus the two half kicks."""
+    from paper_0912_1786_amd import inputs
+    ic = inputs.two_species_field(n_dm=nps, n_gas=nps, n_halo=64, seed=seed)
+    prm = O.params(nnei=60, theta=0.5, leaf_size=16, group_size=64, walk_mode=O.WALK_GROUP)
+    dt, ph = oracle_step(O, ic, prm)
     n = ic["n"]
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-    except OSError:
-        pass
     return {"value": n / dt, "unit": "particle-steps/s", "cores": O.num_threads(), "kind": "oracle",
-            "cpu_model": model, "host_cpus": os.cpu_count(),
-            "sample": f"same recipe at N={n} (2x{nps}, seed {seed}): one force evaluation "
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "build": build,
+            "phase_s": {k: round(v, 3) for k, v in ph.items()},
+            "sample": f"one step of the benchmark recipe at N={n} (2x{nps}, seed {seed}): force evaluation "
                       f"(tree, h/eps solves, group walk, SPH) + KDK kicks, {dt:.2f} s wall"}
+
+
+def row_c1(torch, tsph, O, steps: int = 20) -> dict:
+    """Evrard sphere, 4096 gas particles, plain FP64: per-step time and the
+    per-phase times of the GPU and of the oracle."""
+    from paper_0912_1786_amd import inputs
+    ic = inputs.evrard(4096, seed=1)
+    prm = tsph.tsph_default_params(nnei=50, precision=tsph.FP64)
+    sim = tsph.Simulation(ic, prm, want_pot=False)
+    try:
+        sim.compute_forces()
+        dt = sim.timestep()
+        for _ in range(3):
+            sim.step(dt)
+        tsph.tsph_timing(sim.ctx, True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            sim.step(dt)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        phases, calls = tsph.tsph_phase_times(sim.ctx)
+        flags, _ = sim.flags()
+    finally:
+        sim.close()
+    od = O.params(nnei=50, theta=0.5, leaf_size=16, group_size=64, walk_mode=O.WALK_GROUP)
+    wall, oph = oracle_step(O, ic, od)
+    return {"workload": "evrard_4096_fp64", "n": 4096, "ms_per_step": round(ms, 3),
+            "particle_steps_per_s": round(4096 / (ms / 1e3), 1),
+            "phase_ms_per_step": {k: round(v / calls, 4) for k, v in phases.items()}, "device_flags": flags,
+            "oracle_step_ms": round(wall * 1e3, 2), "oracle_phase_ms": {k: round(v * 1e3, 2) for k, v in oph.items()}}
+
+
+def row_c2(n: int = 262144, steps: int = 20) -> dict:
+    from paper_0912_1786_amd import runs
+    out = {"workload": f"evrard_{n}_{steps}_steps"}
+    for form in ("fp32_bulk", "fp64"):
+        r = runs.evrard_run(n, steps, form)
+        out[form] = {k: r[k] for k in ("median_step_ms", "particle_steps_per_s", "dE_over_E_step1",
+                                         "dE_over_E_step20", "dP_rel_step1", "dP_rel_step20", "device_flags")}
+    return out
+
+
+def row_c4(members: int = 256, steps: int = 10) -> dict:
+    from paper_0912_1786_amd import ensemble
+    r = ensemble.run(members=members, steps=steps, warmup=2, tune=True, precision="fp32_bulk")
+    return {k: r[k] for k in ("workload", "members", "n_total", "ms_per_step", "particle_steps_per_s",
+                              "graph_launches_per_step", "leaf", "group", "split_leaves", "autotune_ms",
+                              "device_flags")}
+
+
+def row_c5(requests: int = 400) -> dict:
+    from paper_0912_1786_amd import serve
+    r = serve.run(n_sim=64, requests=requests)
+    out = {k: r[k] for k in ("workload", "sims", "n_total", "streams", "hbm_budget_bytes", "evictions",
+                             "admissions", "flagged")}
+    out["saturation_requests_per_s"] = r["saturation"]["requests_per_s"]
+    out["saturation_particle_steps_per_s"] = r["saturation"]["particle_steps_per_s"]
+    for o in r["open_loop"]:
+        tag = f"load_{o['rate_fraction']}"
+        out[tag] = {k: o[k] for k in ("rate_per_s", "p50_ms", "p99_ms", "requests_per_s", "particle_steps_per_s")}
+    return out
 
 
 def main():
@@ -241,8 +333,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--leaf", type=int, default=16)
     ap.add_argument("--group", type=int, default=64)
-    ap.add_argument("--cpu-nps", type=int, default=1 << 18, help="per-species size of the oracle sample")
+    ap.add_argument("--cpu-nps", type=int, default=1 << 20, help="per-species size of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="time only the 2M field (skip the Evrard, ensemble and serving configurations)")
     ap.add_argument("--precision", choices=["both", "fp32_bulk", "fp64"], default="both",
                     help="arithmetic form(s) to time; with both, the FP32-bulk form is the headline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -295,9 +389,32 @@ def main():
             mp = probe["fp32_fma_tflops"] if r["arithmetic"] == "fp32" else probe["fp64_fma_tflops"]
             r["measured_peak"] = mp
             r["frac_of_measured_peak"] = round(r["achieved"] / mp, 4)
+    O = obuild = None
+    if not args.no_cpu_baseline or not args.no_rows:
+        try:
+            O, obuild = load_native_oracle()
+        except Exception as e:  # no compiler on the host: the portable build
+            log(f"[bench] native oracle build failed ({e}); using the portable -O2 build")
+            from oracle import oracle as O
+            obuild = "gcc -O2 -fopenmp -ffp-contract=off (native build failed)"
+    if not args.no_rows:
+        rows = {}
+        for name, fn in (("c1", lambda: row_c1(torch, tsph, O)), ("c2", row_c2), ("c4", row_c4), ("c5", row_c5)):
+            t1 = time.time()
+            log(f"[bench] row {name} ...")
+            try:
+                rows[name] = fn()
+            except Exception as e:  # a failing row is reported, not hidden, and does not drop the line
+                rows[name] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] row {name} done in {time.time() - t1:.1f}s: {json.dumps(rows[name])[:300]}")
+        out["rows"] = rows
+        c5 = rows.get("c5", {})
+        if "load_0.5" in c5:
+            out["served_p50_ms"] = c5["load_0.5"]["p50_ms"]
+            out["served_p99_ms"] = c5["load_0.5"]["p99_ms"]
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host ...")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_nps, args.seed)
+        out["cpu_baseline"] = cpu_baseline(O, obuild, args.cpu_nps, args.seed)
         log(f"[bench] oracle: {out['cpu_baseline']['value']:.3e} particle-steps/s on "
             f"{out['cpu_baseline']['cores']} threads")
     print(json.dumps(out), flush=True)

@@ -32,7 +32,7 @@ class Params(C.Structure):
                 ("h_tol", C.c_double), ("kappa", C.c_double), ("leaf_size", C.c_int32),
                 ("group_size", C.c_int32), ("walk_mode", C.c_int32), ("nbr_mode", C.c_int32),
                 ("gravity", C.c_int32), ("hydro", C.c_int32), ("batch_size", C.c_int32),
-                ("batch_mode", C.c_int32)]
+                ("batch_mode", C.c_int32), ("grav_corr_literal", C.c_int32), ("soften_cells", C.c_int32)]
 
 
 class Run(C.Structure):
@@ -121,7 +121,7 @@ def params(**kw) -> Params:
              eta_h=eta_from_nnei(50.0), eta_eps=eta_from_nnei(50.0), gamma=5.0 / 3.0, alpha=1.0,
              beta=2.0, av_eps2=0.01, tc92=1, h_maxit=60, h_tol=1e-10, kappa=0.1, leaf_size=8,
              group_size=32, walk_mode=WALK_GROUP, nbr_mode=NBR_TREE, gravity=1, hydro=1, batch_size=64,
-             batch_mode=0)
+             batch_mode=0, grav_corr_literal=0, soften_cells=0)
     if "nnei" in kw:
         e = eta_from_nnei(kw.pop("nnei"))
         d["eta_h"] = d["eta_eps"] = e

@@ -549,6 +549,8 @@ typedef struct {
   /* per-node maxima after the solves */
   double *epsmax, *hmax;
   int64_t *ngas;
+  /* per-node softened-cell data: mass-weighted mean eps, sum of m xi/Ups */
+  double *epsbar, *xsum;
 } ctx_t;
 
 typedef struct {
@@ -590,14 +592,14 @@ static void collect(const ctx_t *C, int64_t p, double R, int gas_only, cand_t *c
   }
 }
 
-typedef struct { double n, sdh, rho, msdh, mdphi, divv; } sums_t;
+typedef struct { double n, sdh, rho, msdh, mdphi, divv, dphi; } sums_t;
 
 /* number-density sum and its h-derivative over the candidates, Eqs. (rho0),
  * (nsum); self term included (j = i) */
 static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, int full, int mode)
 {
   const orc_tree *t = C->t;
-  sums_t s = {0, 0, 0, 0, 0, 0};
+  sums_t s = {0, 0, 0, 0, 0, 0, 0};
   double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
   for (int64_t a = 0; a < c->n; a++) {
     int64_t q = c->idx[a];
@@ -622,6 +624,7 @@ static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, 
         /* softening: mass-weighted d phi / d eps (Eq. zeta), and the
          * velocity divergence with the eps kernel */
         s.mdphi += mq * orc_dphideps(r, h);
+        s.dphi += orc_dphideps(r, h);
         if (r > 0.0) {
           double g = orc_dWdr(r, h) / r;
           double dvx = C->vx[p] - C->vx[q], dvy = C->vy[p] - C->vy[q], dvz = C->vz[p] - C->vz[q];
@@ -663,7 +666,7 @@ static int solve_length(const ctx_t *C, int64_t p, int gas_only, int mode, doubl
   double h = cold ? 0.5 * guess : guess, lo = 0.0, hi = INFINITY, dx_old = INFINITY;
   double rc = h * (1.0 + P->kappa);
   collect(C, p, 2.0 * rc, gas_only, c);
-  sums_t s = {0, 0, 0, 0, 0, 0};
+  sums_t s = {0, 0, 0, 0, 0, 0, 0};
   double h_eval = h;
   for (int it = 0; it < P->h_maxit; it++) {
     if (h > rc) {
@@ -763,7 +766,10 @@ static void density_phase(ctx_t *C, const double *h_in, const double *eps_in)
            * force is the gradient of the softened Lagrangian for unequal
            * masses) */
           C->ups[p] = 1.0 + (e / (3.0 * s.n)) * s.sdh;
-          C->xi[p] = (P->soft_mode == ORC_SOFT_ADAPTIVE) ? -(e / (3.0 * s.n)) * s.mdphi : 0.0;
+          /* the printed Eq. zeta sums d phi / d eps without masses; that
+           * weighting is kept under grav_corr_literal */
+          double sphi = P->grav_corr_literal ? s.dphi : s.mdphi;
+          C->xi[p] = (P->soft_mode == ORC_SOFT_ADAPTIVE) ? -(e / (3.0 * s.n)) * sphi : 0.0;
           C->divv_e[p] = -s.divv / (s.n * C->ups[p]);
         }
       }
@@ -787,6 +793,16 @@ static void node_maxima(ctx_t *C)
     }
     C->epsmax[k] = em;
     C->hmax[k] = hm;
+    /* a softened cell's own length and correction weight (Sect. 2.2: a
+     * node treated as one particle): the mass-weighted mean eps, and the
+     * sum of m_j xi_j / Ups_j over its particles */
+    double me = 0.0, mx = 0.0;
+    for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++) {
+      me += t->ms[q] * C->eps[q];
+      mx += t->ms[q] * (C->xi[q] / C->ups[q]);
+    }
+    C->epsbar[k] = me / t->mass[k];
+    C->xsum[k] = mx;
   }
 }
 
@@ -841,8 +857,40 @@ static void near_pair(const ctx_t *C, int64_t p, int64_t q, double *a, double *p
   if (!(r > 0.0)) return;
   double f = G * mj * 0.5 * (orc_dphidr(r, ei) + orc_dphidr(r, ej));
   if (C->p->soft_mode == ORC_SOFT_ADAPTIVE) {
-    f += 0.5 * G * ((C->xi[p] / C->ups[p]) * orc_dWdr(r, ei) +
-                    (mj / t->ms[p]) * (C->xi[q] / C->ups[q]) * orc_dWdr(r, ej));
+    if (C->p->grav_corr_literal)
+      /* Eq. dLgravdr as printed: m_j [xi_i/Ups_i W'(eps_i) + xi_j/Ups_j W'(eps_j)]
+       * with xi of Eq. zeta (no masses), the j-gradient taken with eps_j */
+      f += 0.5 * G * mj * ((C->xi[p] / C->ups[p]) * orc_dWdr(r, ei) + (C->xi[q] / C->ups[q]) * orc_dWdr(r, ej));
+    else
+      f += 0.5 * G * ((C->xi[p] / C->ups[p]) * orc_dWdr(r, ei) +
+                      (mj / t->ms[p]) * (C->xi[q] / C->ups[q]) * orc_dWdr(r, ej));
+  }
+  a[0] -= f * dx / r;
+  a[1] -= f * dy / r;
+  a[2] -= f * dz / r;
+}
+
+/* Softened cell k acting on sink p (Sect. 2.2): the node taken as one
+ * particle of mass M at its centre of mass with the mass-weighted mean eps
+ * of its particles, through the symmetrised softened pair, and the
+ * correction terms of its particles gathered there: the sink's term counts
+ * each particle of the cell (N of them; with the printed weighting, their
+ * mass M), the cell's term is the sum of m_j xi_j / Ups_j. */
+static void soft_cell(const ctx_t *C, int64_t k, int64_t p, double *a, double *pot)
+{
+  const orc_tree *t = C->t;
+  double G = C->p->G;
+  double dx = t->xs[p] - t->com[3 * k], dy = t->ys[p] - t->com[3 * k + 1], dz = t->zs[p] - t->com[3 * k + 2];
+  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  double ei = C->eps[p], ek = C->epsbar[k], M = t->mass[k];
+  *pot += G * M * 0.5 * (orc_phi(r, ei) + orc_phi(r, ek));
+  double f = G * M * 0.5 * (orc_dphidr(r, ei) + orc_dphidr(r, ek));
+  if (C->p->soft_mode == ORC_SOFT_ADAPTIVE) {
+    double wi = orc_dWdr(r, ei), wk = orc_dWdr(r, ek), xu = C->xi[p] / C->ups[p];
+    if (C->p->grav_corr_literal)
+      f += 0.5 * G * (M * xu * wi + C->xsum[k] * wk);
+    else
+      f += 0.5 * G * ((double)t->count[k] * xu * wi + (C->xsum[k] / t->ms[p]) * wk);
   }
   a[0] -= f * dx / r;
   a[1] -= f * dy / r;
@@ -853,6 +901,9 @@ static void near_pair(const ctx_t *C, int64_t p, int64_t q, double *a, double *p
  * is farther from its centre of mass than l/theta + delta (strictly), and no
  * particle of the node can lie within the softening reach 2 max(eps_i,
  * eps_node) of the sink ("softening-clear"); accepted nodes are unsoftened. */
+/* returns 1 for an accepted (unsoftened) node, 2 for a softened cell (with
+ * soften_cells: the opening test passes but the node lies within the
+ * softening reach), 0 to open it */
 static int accept_point(const ctx_t *C, int64_t k, double px, double py, double pz, double ei)
 {
   const orc_params *P = C->p;
@@ -862,7 +913,8 @@ static int accept_point(const ctx_t *C, int64_t k, double px, double py, double 
   double d2 = pair_r2(px, py, pz, t->com[3 * k], t->com[3 * k + 1], t->com[3 * k + 2]);
   if (!(d2 > rm * rm)) return 0;
   double s = 2.0 * (ei > C->epsmax[k] ? ei : C->epsmax[k]);
-  return box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz) >= s * s;
+  if (box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz) >= s * s) return 1;
+  return P->soften_cells ? 2 : 0;
 }
 
 static int accept_box(const ctx_t *C, int64_t k, const double *lo, const double *hi, double emax)
@@ -874,7 +926,8 @@ static int accept_box(const ctx_t *C, int64_t k, const double *lo, const double 
   double d2 = box_point_d2(lo, hi, t->com[3 * k], t->com[3 * k + 1], t->com[3 * k + 2]);
   if (!(d2 > rm * rm)) return 0;
   double s = 2.0 * (emax > C->epsmax[k] ? emax : C->epsmax[k]);
-  return box_box_d2(lo, hi, &t->bmin[3 * k], &t->bmax[3 * k]) >= s * s;
+  if (box_box_d2(lo, hi, &t->bmin[3 * k], &t->bmax[3 * k]) >= s * s) return 1;
+  return P->soften_cells ? 2 : 0;
 }
 
 static void self_term(const ctx_t *C, int64_t p, double *pot)
@@ -897,8 +950,12 @@ static void gravity_particle_walk(ctx_t *C)
       stack[sp++] = 0;
       while (sp > 0) {
         int64_t k = stack[--sp];
-        if (accept_point(C, k, px, py, pz, C->eps[p])) {
+        int acc = accept_point(C, k, px, py, pz, C->eps[p]);
+        if (acc == 1) {
           far_node(C, k, px, py, pz, a, &pot);
+          nnode++;
+        } else if (acc == 2) {
+          soft_cell(C, k, p, a, &pot);
           nnode++;
         } else if (t->nchild[k] == 0) {
           for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++)
@@ -944,6 +1001,7 @@ static void gravity_group_walk(ctx_t *C)
     int64_t *stack = malloc((8 * 22 * 8 + t->nnodes + 16) * sizeof(int64_t));
     int64_t *acc = malloc((t->nnodes + 1) * sizeof(int64_t));
     int64_t *lvs = malloc((t->nnodes + 1) * sizeof(int64_t));
+    int64_t *scl = malloc((t->nnodes + 1) * sizeof(int64_t));
 #pragma omp for schedule(dynamic, 4)
     for (int64_t g = 0; g < nb; g++) {
       double lo[3], hi[3], emax = 0.0;
@@ -964,11 +1022,13 @@ static void gravity_group_walk(ctx_t *C)
       int any = 0;
       for (int64_t p = pfirst; p < pend && !any; p++) any = C->active[p];
       if (!any) continue;
-      int64_t na = 0, nl = 0, sp = 0;
+      int64_t na = 0, nl = 0, ns = 0, sp = 0;
       stack[sp++] = 0;
       while (sp > 0) {
         int64_t k = stack[--sp];
-        if (accept_box(C, k, lo, hi, emax)) acc[na++] = k;
+        int ab = accept_box(C, k, lo, hi, emax);
+        if (ab == 1) acc[na++] = k;
+        else if (ab == 2) scl[ns++] = k;
         else if (t->nchild[k] == 0) lvs[nl++] = k;
         else for (int32_t b = t->nchild[k] - 1; b >= 0; b--) stack[sp++] = t->child[k] + b;
       }
@@ -978,6 +1038,7 @@ static void gravity_group_walk(ctx_t *C)
         int64_t npair = 0;
         double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
         for (int64_t b = 0; b < na; b++) far_node(C, acc[b], px, py, pz, a, &pot);
+        for (int64_t b = 0; b < ns; b++) soft_cell(C, scl[b], p, a, &pot);
         for (int64_t b = 0; b < nl; b++) {
           int64_t k = lvs[b];
           for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++)
@@ -986,11 +1047,11 @@ static void gravity_group_walk(ctx_t *C)
         self_term(C, p, &pot);
         C->ax[p] = a[0]; C->ay[p] = a[1]; C->az[p] = a[2];
         C->pot[p] = pot;
-        C->cnt_node[p] = na;
+        C->cnt_node[p] = na + ns;
         C->cnt_pair[p] = npair;
       }
     }
-    free(stack); free(acc); free(lvs);
+    free(stack); free(acc); free(lvs); free(scl);
   }
   free(bk0);
   free(bk1);
@@ -1190,6 +1251,8 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   }
   C.epsmax = calloc(t->nnodes, sizeof(double));
   C.hmax = calloc(t->nnodes, sizeof(double));
+  C.epsbar = calloc(t->nnodes, sizeof(double));
+  C.xsum = calloc(t->nnodes, sizeof(double));
   C.ngas = calloc(t->nnodes, sizeof(int64_t));
   for (int64_t k = 0; k < t->nnodes; k++) {
     int64_t g = 0;
@@ -1233,7 +1296,7 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   free(C.ax); free(C.ay); free(C.az); free(C.pot); free(C.dudt); free(C.maxmu);
   free(C.P); free(C.cs); free(C.cnt_node); free(C.cnt_pair); free(C.cnt_sph); free(C.iters);
   free(C.cnt_soft); free(C.active);
-  free(C.epsmax); free(C.hmax); free(C.ngas);
+  free(C.epsmax); free(C.hmax); free(C.ngas); free(C.epsbar); free(C.xsum);
   orc_tree_free(t);
   return 0;
 }

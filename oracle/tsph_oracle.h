@@ -55,6 +55,12 @@ typedef struct {
   int32_t gravity, hydro;       /* switches (1 = on)                            */
   int32_t batch_size;           /* walk batches: groups packed up to this size  */
   int32_t batch_mode;           /* 0: siblings only, 1: any consecutive groups  */
+  int32_t grav_corr_literal;    /* correction terms with the printed mass
+                                 * weighting of Eqs. dLgravdr, zeta            */
+  int32_t soften_cells;         /* softened cells (Sect. 2.2): a node that
+                                 * passes the opening test but lies within the
+                                 * softening reach acts as one softened
+                                 * particle at its centre of mass              */
 } orc_params;
 
 /* All arrays are in caller order, length n unless noted.  Gas particles are

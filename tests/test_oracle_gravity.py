@@ -141,3 +141,83 @@ def test_force_is_gradient_of_softened_lagrangian(orc, soft_mode, tol):
         assert max(errs) < tol, max(errs)
     else:
         assert max(errs) > 1e-3, max(errs)
+
+
+def test_printed_correction_weighting(orc):
+    """The printed mass weighting of the correction terms (Eq. dLgravdr with
+    xi of Eq. zeta, no masses inside xi): equal to the energy-consistent
+    form for equal masses, and not the gradient of the softened Lagrangian
+    for unequal masses (1 : 5), where the energy-consistent form is."""
+    base = dict(walk_mode=orc.WALK_DIRECT, hydro=0, eta_eps=0.9, eta_h=0.9, h_tol=1e-14)
+    eq = inputs.random_cloud(300, seed=8, masses=(1.0, 1.0), n_gas=0)
+    a_ec = _acc(orc.compute_forces(eq, orc.params(**base)))
+    a_lit = _acc(orc.compute_forces(eq, orc.params(grav_corr_literal=1, **base)))
+    assert _relrms(a_lit, a_ec) < 1e-13
+    ic = inputs.random_cloud(120, seed=5, masses=(1.0, 5.0), n_gas=0)
+    prm = orc.params(grav_corr_literal=1, **base)
+    o = orc.compute_forces(ic, prm)
+    acc = _acc(o)
+    d, scale, errs = 1e-5, np.abs(acc).mean(), []
+    for i in range(0, 120, 12):
+        for k, ax in enumerate("xyz"):
+            vals = []
+            for s in (+1, -1):
+                q = {kk: (v.copy() if isinstance(v, np.ndarray) else v) for kk, v in ic.items()}
+                q[ax][i] += s * d
+                eps = _eps_of(orc, q, prm)
+                vals.append(orc.potential_energy(q["x"], q["y"], q["z"], q["m"], eps))
+            fd = -(vals[0] - vals[1]) / (2 * d) / ic["m"][i]
+            errs.append(abs(fd - acc[i, k]) / scale)
+    assert max(errs) > 1e-3, max(errs)
+
+
+def _cluster_and_sink(size, seed):
+    """64 particles (masses 1 and 5) inside a ball of radius `size` at the
+    origin and one particle at distance 1: the lone particle's softening
+    (solved from its neighbour count) reaches the cluster, while the opening
+    test passes for the cluster's nodes."""
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=(64, 3))
+    v *= (rng.uniform(0.0, 1.0, 64) ** (1 / 3) / np.linalg.norm(v, axis=1))[:, None]
+    d = rng.normal(size=3)
+    pos = np.concatenate([v * size, (d / np.linalg.norm(d))[None, :]])
+    m = np.where(np.arange(65) % 2 == 0, 1.0, 5.0) / 65.0
+    return {"n": 65, "n_gas": 0, "x": pos[:, 0].copy(), "y": pos[:, 1].copy(), "z": pos[:, 2].copy(),
+            "vx": np.zeros(65), "vy": np.zeros(65), "vz": np.zeros(65), "m": m, "u": np.zeros(65)}
+
+
+@pytest.mark.parametrize("literal", [0, 1])
+def test_softened_cells_converge_to_the_pair_sum(orc, literal):
+    """A softened cell stands for its particles gathered at their centre of
+    mass (Sect. 2.2), correction terms included: as the cluster shrinks, the
+    force on the lone particle converges to the exact softened, corrected
+    pair sum, linearly or faster in the cluster size."""
+    prm = dict(hydro=0, nnei=30, leaf_size=8, theta=0.5, grav_corr_literal=literal, h_tol=1e-13)
+    errs = []
+    for size in (4e-3, 2e-3, 1e-3, 5e-4):
+        e = []
+        for seed in range(4):
+            ic = _cluster_and_sink(size, seed)
+            o = orc.compute_forces(ic, orc.params(soften_cells=1, walk_mode=orc.WALK_PARTICLE, **prm))
+            od = orc.compute_forces(ic, orc.params(walk_mode=orc.WALK_DIRECT, **prm))
+            assert o["cnt_pair"][64] == 0 and o["cnt_node"][64] > 0  # the cluster came as softened cells
+            assert o["eps"][64] > 0.5  # the lone particle's softening reaches the cluster
+            a, ad = _acc(o)[64], _acc(od)[64]
+            e.append(np.linalg.norm(a - ad) / np.linalg.norm(ad))
+        errs.append(np.mean(e))
+    errs = np.array(errs)
+    assert np.all(errs[1:] < 0.6 * errs[:-1]), errs
+    assert errs[-1] < 1e-3, errs
+
+
+def test_softened_cells_theta_zero_and_accuracy(orc):
+    ic = inputs.two_species_field(n_dm=1500, n_gas=1500, n_halo=6, seed=10)
+    od = orc.compute_forces(ic, orc.params(walk_mode=orc.WALK_DIRECT, hydro=0, nnei=40))
+    o0 = orc.compute_forces(ic, orc.params(walk_mode=orc.WALK_GROUP, theta=0.0, soften_cells=1, hydro=0, nnei=40))
+    assert _relrms(_acc(o0), _acc(od)) < 1e-13
+    for mode in (orc.WALK_PARTICLE, orc.WALK_GROUP):
+        o = orc.compute_forces(ic, orc.params(walk_mode=mode, soften_cells=1, hydro=0, nnei=40))
+        on = orc.compute_forces(ic, orc.params(walk_mode=mode, soften_cells=0, hydro=0, nnei=40))
+        assert _relrms(_acc(o), _acc(od)) < 2e-3
+        # softened cells replace near pairs (fewer pair interactions)
+        assert o["cnt_pair"].sum() < on["cnt_pair"].sum()
