@@ -22,6 +22,9 @@ U64 = C.POINTER(C.c_uint64)
 SOFT_ADAPTIVE, SOFT_CONSTANT, SOFT_ADAPTIVE_NOCORR = 0, 1, 2
 WALK_PARTICLE, WALK_GROUP, WALK_DIRECT = 0, 1, 2
 NBR_TREE, NBR_BRUTE = 0, 1
+VISC_MG, VISC_SIGNAL = 0, 1
+H_LAGRANGIAN, H_STANDARD = 0, 1
+HW_NUMBER, HW_MASS = 0, 1
 
 
 class Params(C.Structure):
@@ -32,7 +35,9 @@ class Params(C.Structure):
                 ("h_tol", C.c_double), ("kappa", C.c_double), ("leaf_size", C.c_int32),
                 ("group_size", C.c_int32), ("walk_mode", C.c_int32), ("nbr_mode", C.c_int32),
                 ("gravity", C.c_int32), ("hydro", C.c_int32), ("batch_size", C.c_int32),
-                ("batch_mode", C.c_int32), ("grav_corr_literal", C.c_int32), ("soften_cells", C.c_int32)]
+                ("batch_mode", C.c_int32), ("grav_corr_literal", C.c_int32), ("soften_cells", C.c_int32),
+                ("visc_form", C.c_int32), ("entropy", C.c_int32), ("xsph_eta", C.c_double),
+                ("h_scheme", C.c_int32), ("h_weight", C.c_int32)]
 
 
 class Run(C.Structure):
@@ -44,7 +49,8 @@ class Run(C.Structure):
                 ("ax", D), ("ay", D), ("az", D), ("pot", D), ("dudt", D), ("maxmu", D),
                 ("cnt_node", I64), ("cnt_pair", I64), ("cnt_sph", I64), ("iters", I32),
                 ("n_noconv", C.c_int64), ("sinks", I64), ("n_sinks", C.c_int64), ("cnt_soft", I64),
-                ("divv_eps", D), ("t_phase", C.c_double * 4)]
+                ("divv_eps", D), ("t_phase", C.c_double * 4), ("xsph_x", D), ("xsph_y", D), ("xsph_z", D),
+                ("vsig", D)]
 
 
 def eta_from_nnei(nnei: float) -> float:
@@ -91,10 +97,10 @@ def lib():
         L.orc_neighbours.restype = C.c_int64
         L.orc_potential_energy.argtypes = [C.c_int64, D, D, D, D, D, C.c_double]
         L.orc_potential_energy.restype = C.c_double
-        L.orc_kick_drift.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_int32] + [D] * 19
-        L.orc_timestep.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64] + [D] * 12 + [C.c_double]
+        L.orc_kick_drift.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_int32] + [D] * 22
+        L.orc_timestep.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64] + [D] * 12 + [C.c_double, D]
         L.orc_timestep.restype = C.c_double
-        L.orc_diagnostics.argtypes = [C.c_int64, C.c_int64] + [D] * 10
+        L.orc_diagnostics.argtypes = [C.c_int64, C.c_int64] + [D] * 10 + [D, C.c_double, C.c_int32]
         L.orc_eval_kernel.argtypes = [C.c_int, C.c_int64, D, D, D]
         L.orc_num_threads.restype = C.c_int
         L.orc_multipole_field.argtypes = [C.c_int64, D, D, D, D, C.c_double, C.c_double, C.c_double,
@@ -121,7 +127,8 @@ def params(**kw) -> Params:
              eta_h=eta_from_nnei(50.0), eta_eps=eta_from_nnei(50.0), gamma=5.0 / 3.0, alpha=1.0,
              beta=2.0, av_eps2=0.01, tc92=1, h_maxit=60, h_tol=1e-10, kappa=0.1, leaf_size=8,
              group_size=32, walk_mode=WALK_GROUP, nbr_mode=NBR_TREE, gravity=1, hydro=1, batch_size=64,
-             batch_mode=0, grav_corr_literal=0, soften_cells=0)
+             batch_mode=0, grav_corr_literal=0, soften_cells=0, visc_form=VISC_MG, entropy=0, xsph_eta=0.0,
+             h_scheme=H_LAGRANGIAN, h_weight=HW_NUMBER)
     if "nnei" in kw:
         e = eta_from_nnei(kw.pop("nnei"))
         d["eta_h"] = d["eta_eps"] = e
@@ -155,7 +162,8 @@ def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=No
     hin = None if h_in is None else _f64(h_in)
     ein = None if eps_in is None else _f64(eps_in)
     out = {k: np.zeros(n) for k in ("h", "nh", "rho", "omega", "zeta", "divv", "eps", "neps", "ups",
-                                     "xi", "ax", "ay", "az", "pot", "dudt", "maxmu", "divv_eps")}
+                                     "xi", "ax", "ay", "az", "pot", "dudt", "maxmu", "divv_eps", "xsph_x",
+                                     "xsph_y", "xsph_z", "vsig")}
     cnt = {k: np.zeros(n, np.int64) for k in ("cnt_node", "cnt_pair", "cnt_sph", "cnt_soft")}
     snk = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
     iters = np.zeros(n, np.int32)
@@ -244,12 +252,13 @@ def potential_energy(x, y, z, m, eps, G: float = 1.0) -> float:
 
 
 def kick_drift(st: dict, dt: float, phase: int, acc, dudt, pred: dict | None = None,
-               lengths: dict | None = None):
+               lengths: dict | None = None, xsph=None):
     """In-place KDK half step on a state dict (x, y, z, vx, vy, vz, u).
 
     ``lengths`` (phase 0): arrays "h" and "eps", updated in place along the
     drift from the divergences "divv" and "divv_eps" of the last force
-    evaluation."""
+    evaluation.  ``xsph`` (phase 0): the X-SPH velocity corrections (three
+    arrays) added to the drift velocity of the gas."""
     ax, ay, az = (_f64(a) for a in acc)
     du = _f64(dudt)
     n, n_gas = int(st["n"]), int(st["n_gas"])
@@ -260,7 +269,8 @@ def kick_drift(st: dict, dt: float, phase: int, acc, dudt, pred: dict | None = N
         for a in ln[:2]:
             assert a.dtype == np.float64 and a.flags.c_contiguous
     lib().orc_kick_drift(n, n_gas, dt, phase, *(_p(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "u")),
-                         _p(ax), _p(ay), _p(az), _p(du), *(_p(v) for v in vp), *(_p(v) for v in ln))
+                         _p(ax), _p(ay), _p(az), _p(du), *(_p(v) for v in vp), *(_p(v) for v in ln),
+                         *((_p(_f64(v)) for v in xsph) if xsph is not None else (D(), D(), D())))
 
 
 def timestep(prm: Params, st: dict, out: dict, eta_dt: float = 0.1) -> float:
@@ -268,14 +278,18 @@ def timestep(prm: Params, st: dict, out: dict, eta_dt: float = 0.1) -> float:
     arrs = [st["vx"], st["vy"], st["vz"], st["u"], out["h"], out["eps"], out["ax"], out["ay"],
             out["az"], out["dudt"], out["divv"], out["maxmu"]]
     arrs = [_f64(a) for a in arrs]
-    return lib().orc_timestep(C.byref(prm), n, n_gas, *(_p(a) for a in arrs), eta_dt)
+    rho = _f64(out["rho"]) if "rho" in out else None
+    return lib().orc_timestep(C.byref(prm), n, n_gas, *(_p(a) for a in arrs), eta_dt, _p(rho))
 
 
-def diagnostics(st: dict, pot) -> np.ndarray:
+def diagnostics(st: dict, pot, rho=None, gamma: float = 5.0 / 3.0, entropy: bool = False) -> np.ndarray:
+    """E_kin, E_th, V, P, L; with entropy, u holds A and E_th needs rho."""
     out = np.zeros(9)
     a = [_f64(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u")]
     p = _f64(pot)
-    lib().orc_diagnostics(int(st["n"]), int(st["n_gas"]), *(_p(v) for v in a), _p(p), _p(out))
+    r = None if rho is None else _f64(rho)
+    lib().orc_diagnostics(int(st["n"]), int(st["n_gas"]), *(_p(v) for v in a), _p(p), _p(out), _p(r),
+                          float(gamma), int(bool(entropy)))
     return out
 
 

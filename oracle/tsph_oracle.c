@@ -542,6 +542,8 @@ typedef struct {
   double *eps, *neps, *ups, *xi;
   double *ax, *ay, *az, *pot, *dudt, *maxmu;
   double *P, *cs;
+  double *fa;                 /* grad-h factor f_ij = fa_i + zeta_i / (m_j Omega*_i) */
+  double *xsx, *xsy, *xsz, *vsig;  /* X-SPH velocity correction, max signal velocity */
   int64_t *cnt_node, *cnt_pair, *cnt_sph, *cnt_soft;
   int32_t *iters;
   int64_t noconv;             /* length solves that did not converge        */
@@ -648,6 +650,9 @@ static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, 
 static int solve_length(const ctx_t *C, int64_t p, int gas_only, int mode, double eta, double guess,
                         int cold, cand_t *c, double *h_out, sums_t *s_out, int32_t *iters)
 {
+  /* with the mass-density relation every neighbour counts m_j / m_i */
+  const int mass_w = mode == 0 && C->p->h_weight == ORC_HW_MASS;
+  const double imi = 1.0 / C->t->ms[p];
   const orc_params *P = C->p;
   int64_t set_size = gas_only ? C->n_gas : C->n;
   double eta3 = eta * eta * eta;
@@ -676,8 +681,9 @@ static int solve_length(const ctx_t *C, int64_t p, int gas_only, int mode, doubl
     s = kernel_sums(C, p, h, c, 1, mode);
     h_eval = h;
     (*iters)++;
-    double g = h * h * h * s.n - eta3;
-    double gp = 3.0 * h * h * s.n + h * h * h * s.sdh;
+    double nw = mass_w ? s.rho * imi : s.n, sdw = mass_w ? s.msdh * imi : s.sdh;
+    double g = h * h * h * nw - eta3;
+    double gp = 3.0 * h * h * nw + h * h * h * sdw;
     if (g < 0.0) lo = h;
     else hi = h;
     /* converged when the Newton step is below the tolerance; otherwise a
@@ -702,6 +708,65 @@ static int solve_length(const ctx_t *C, int64_t p, int gas_only, int mode, doubl
   *h_out = h_eval;
   *s_out = s;
   return 0;
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+  double x = *(const double *)a, y = *(const double *)b;
+  return (x > y) - (x < y);
+}
+
+/* Standard SPH (Sect. 3): h from a fixed neighbour count instead of the
+ * kernel-weighted relation.  With the gas candidates sorted by squared
+ * distance, the count reaches nstd at the first shell (all candidates at
+ * one distance) whose cumulative weight is at least nstd -- every neighbour
+ * counts 1, or m_j / m_i with the mass-density relation -- and 2h lies
+ * midway between that shell's distance and the next larger distance.  The
+ * neighbour set inside 2h is then that cumulative set: exactly nstd
+ * particles, the sink included, unless the shell holds several (a lattice).
+ * Returns 0 when there are too few gas particles. */
+static int solve_count(const ctx_t *C, int64_t p, int64_t nstd, double guess, cand_t *c, double *h_out,
+                       sums_t *s_out)
+{
+  const orc_tree *t = C->t;
+  const int mass_w = C->p->h_weight == ORC_HW_MASS;
+  double R = 2.0 * (guess > 0.0 ? guess : 1.0);
+  for (;;) {
+    collect(C, p, R, 1, c);
+    /* (squared distance, weight) sorted by distance */
+    double *d = malloc(2 * (c->n + 1) * sizeof(double));
+    for (int64_t a = 0; a < c->n; a++) {
+      int64_t q = c->idx[a];
+      d[2 * a] = pair_r2(t->xs[p], t->ys[p], t->zs[p], t->xs[q], t->ys[q], t->zs[q]);
+      d[2 * a + 1] = mass_w ? t->ms[q] / t->ms[p] : 1.0;
+    }
+    qsort(d, c->n, 2 * sizeof(double), cmp_double);
+    double cum = 0.0;
+    int64_t k = 0;
+    while (k < c->n) {
+      /* the whole shell at distance d[2k] */
+      double r2k = d[2 * k];
+      while (k < c->n && d[2 * k] == r2k) cum += d[2 * k++ + 1];
+      if (cum >= (double)nstd) {
+        if (k < c->n) {
+          double h = 0.25 * (sqrt(r2k) + sqrt(d[2 * k]));
+          free(d);
+          *h_out = h;
+          *s_out = kernel_sums(C, p, h, c, 1, 0);
+          return 1;
+        }
+        break;  /* the next distance lies beyond the gathered radius */
+      }
+    }
+    free(d);
+    if ((cum < (double)nstd && c->n >= C->n_gas) || R > 1e30) {
+      /* fewer gas particles (or less weight) than the count needs */
+      *h_out = 0.5 * R;
+      *s_out = kernel_sums(C, p, 0.5 * R, c, 1, 0);
+      return 0;
+    }
+    R *= 2.0;
+  }
 }
 
 static double cold_guess(const ctx_t *C, int64_t p, int gas_only, double eta)
@@ -733,15 +798,35 @@ static void density_phase(ctx_t *C, const double *h_in, const double *eps_in)
         double guess = cold ? cold_guess(C, p, 1, P->eta_h) : h_in[i];
         double h;
         sums_t s;
-        if (!solve_length(C, p, 1, 0, P->eta_h, guess, cold, &c, &h, &s, &C->iters[p])) noconv++;
+        if (P->h_scheme == ORC_H_STANDARD) {
+          /* the neighbour number of the relation eta = h n^(1/3) */
+          int64_t nstd = llround(4.0 / 3.0 * M_PI * pow(2.0 * P->eta_h, 3.0));
+          if (!solve_count(C, p, nstd, guess, &c, &h, &s)) noconv++;
+        } else if (!solve_length(C, p, 1, 0, P->eta_h, guess, cold, &c, &h, &s, &C->iters[p])) {
+          noconv++;
+        }
         C->h[p] = h;
         C->nh[p] = s.n;
-        C->rho[p] = s.rho;
+        C->rho[p] = s.rho;  /* Eq. densitySPH in every scheme */
         /* grad-h terms, Sect. 3 Eq. (drhodr) and the definitions after it:
          * Omega* = 1 - (dh/dn) sum dW/dh, zeta = (dh/dn) sum m dW/dh,
-         * dh/dn = -h/(3 n) */
-        C->omega[p] = 1.0 + (h / (3.0 * s.n)) * s.sdh;
-        C->zeta[p] = -(h / (3.0 * s.n)) * s.msdh;
+         * dh/dn = -h/(3 n); the standard scheme neglects them */
+        if (P->h_scheme == ORC_H_STANDARD) {
+          C->omega[p] = 1.0;
+          C->zeta[p] = 0.0;
+          C->fa[p] = 1.0;
+        } else if (P->h_weight == ORC_HW_MASS) {
+          /* h from the mass density: the correction of Springel & Hernquist,
+           * f_ij = 1 / Omega_i with Omega_i = 1 + (h/(3 rho)) sum m dW/dh */
+          double om = 1.0 + (h / (3.0 * s.rho)) * s.msdh;
+          C->omega[p] = om;
+          C->zeta[p] = 0.0;
+          C->fa[p] = 1.0 / om;
+        } else {
+          C->omega[p] = 1.0 + (h / (3.0 * s.n)) * s.sdh;
+          C->zeta[p] = -(h / (3.0 * s.n)) * s.msdh;
+          C->fa[p] = 1.0;
+        }
         /* velocity divergence (Sect. 2.1), with the gas kernel */
         C->divv[p] = -s.divv / (s.n * C->omega[p]);
       }
@@ -1089,7 +1174,23 @@ static void gravity_direct(ctx_t *C)
  * made consistent (pressure repulsive, compression heating).  Pi_ij is the
  * Monaghan-Gingold term with hbar, cbar, rhobar the arithmetic pair means and
  * eta^2 = av_eps2 hbar^2; it acts only on approaching pairs. */
-static void sph_pair(const ctx_t *C, int64_t p, int64_t q, double *a, double *du, double *mumax)
+typedef struct {
+  double a[3], du, du_v, mumax, vsig, xs[3];  /* du: pressure + viscous; du_v: viscous */
+} sph_acc_t;
+
+/* Variants (flags of orc_params):
+ *   visc_form SIGNAL: Pi_ij = -alpha v_sig w_ij / rhobar with w_ij = v_ij . x_ij / r
+ *     and v_sig = 2 cbar - w_ij (Sect. 3.3.1, Eqs. pvsig, vsig), approaching pairs;
+ *     mu is still formed for the time-step criterion;
+ *   entropy: the energy variable is A = P / rho^gamma and its rate is the
+ *     viscous term only, dA_i = (gamma - 1) rho_i^(1 - gamma) sum_j 1/2 m_j
+ *     Pi_ij v_ij . Gbar_ij (Sect. 3.4, Eq. SPHentr);
+ *   xsph_eta > 0: the X-SPH velocity correction eta sum_j m_j (v_j - v_i)
+ *     Wbar_ij / rhobar_ij with Wbar_ij = 1/2 [W(r, h_i) + W(r, h_j)] over the
+ *     same pairs (Sect. 3.5, Eq. xsph).
+ * The signal velocity of every pair, 2 cbar - min(w_ij, 0), gives the
+ * largest one per particle (vsig). */
+static void sph_pair(const ctx_t *C, int64_t p, int64_t q, sph_acc_t *acc)
 {
   const orc_params *P = C->p;
   const orc_tree *t = C->t;
@@ -1100,29 +1201,41 @@ static void sph_pair(const ctx_t *C, int64_t p, int64_t q, double *a, double *du
   double hi = C->h[p], hj = C->h[q], mi = t->ms[p], mj = t->ms[q];
   double gi = (P->tc92 ? orc_dWdr_tc92(r, hi) : orc_dWdr(r, hi)) / r;
   double gj = (P->tc92 ? orc_dWdr_tc92(r, hj) : orc_dWdr(r, hj)) / r;
-  double fij = 1.0 + C->zeta[p] / (mj * C->omega[p]);
-  double fji = 1.0 + C->zeta[q] / (mi * C->omega[q]);
+  double fij = C->fa[p] + C->zeta[p] / (mj * C->omega[p]);
+  double fji = C->fa[q] + C->zeta[q] / (mi * C->omega[q]);
   double Ai = C->P[p] * fij / (C->rho[p] * C->rho[p]);
   double Aj = C->P[q] * fji / (C->rho[q] * C->rho[q]);
   double vx = C->vx[p] - C->vx[q], vy = C->vy[p] - C->vy[q], vz = C->vz[p] - C->vz[q];
   double vd = vx * dx + vy * dy + vz * dz;
   double s = mj * (Ai * gi + Aj * gj);
+  double cb = 0.5 * (C->cs[p] + C->cs[q]);
+  double rb = 0.5 * (C->rho[p] + C->rho[q]);
+  double w = vd / r;
   double e = mj * Ai * gi * vd;
   if (vd < 0.0) {
     double hb = 0.5 * (hi + hj);
     double mu = hb * vd / (r2 + P->av_eps2 * hb * hb);
-    double cb = 0.5 * (C->cs[p] + C->cs[q]);
-    double rb = 0.5 * (C->rho[p] + C->rho[q]);
-    double Pi = (-P->alpha * cb * mu + P->beta * mu * mu) / rb;
+    double Pi = P->visc_form == ORC_VISC_SIGNAL ? -P->alpha * (2.0 * cb - w) * w / rb
+                                                : (-P->alpha * cb * mu + P->beta * mu * mu) / rb;
     double Gb = 0.5 * (fij * gi + fji * gj);
     s += mj * Pi * Gb;
-    e += 0.5 * mj * Pi * Gb * vd;
-    if (fabs(mu) > *mumax) *mumax = fabs(mu);
+    double ev = 0.5 * mj * Pi * Gb * vd;
+    e += ev;
+    acc->du_v += ev;
+    if (fabs(mu) > acc->mumax) acc->mumax = fabs(mu);
   }
-  a[0] -= s * dx;
-  a[1] -= s * dy;
-  a[2] -= s * dz;
-  *du += e;
+  acc->du += e;
+  double vs = 2.0 * cb - (w < 0.0 ? w : 0.0);
+  if (vs > acc->vsig) acc->vsig = vs;
+  if (P->xsph_eta > 0.0) {
+    double wb = 0.5 * (orc_W(r, hi) + orc_W(r, hj)) / rb;
+    acc->xs[0] -= mj * vx * wb;
+    acc->xs[1] -= mj * vy * wb;
+    acc->xs[2] -= mj * vz * wb;
+  }
+  acc->a[0] -= s * dx;
+  acc->a[1] -= s * dy;
+  acc->a[2] -= s * dz;
 }
 
 /* symmetric neighbour condition r < 2 max(h_i, h_j) (Sect. 3.1) */
@@ -1140,8 +1253,14 @@ static void sph_phase(ctx_t *C)
   const orc_tree *t = C->t;
   for (int64_t p = 0; p < C->n; p++) {
     if (!C->gas[p]) continue;
-    C->P[p] = (P->gamma - 1.0) * C->rho[p] * C->u[p];
-    C->cs[p] = sqrt(P->gamma * (P->gamma - 1.0) * C->u[p]);
+    if (P->entropy) {
+      /* the energy variable is A: P = A rho^gamma, c^2 = gamma P / rho */
+      C->P[p] = C->u[p] * pow(C->rho[p], P->gamma);
+      C->cs[p] = sqrt(P->gamma * C->u[p] * pow(C->rho[p], P->gamma - 1.0));
+    } else {
+      C->P[p] = (P->gamma - 1.0) * C->rho[p] * C->u[p];
+      C->cs[p] = sqrt(P->gamma * (P->gamma - 1.0) * C->u[p]);
+    }
   }
 #pragma omp parallel
   {
@@ -1149,11 +1268,12 @@ static void sph_phase(ctx_t *C)
 #pragma omp for schedule(dynamic, 16)
     for (int64_t p = 0; p < C->n; p++) {
       if (!C->gas[p] || !C->active[p]) continue;
-      double a[3] = {0, 0, 0}, du = 0.0, mumax = 0.0;
+      sph_acc_t acc;
+      memset(&acc, 0, sizeof(acc));
       int64_t npair = 0;
       if (P->nbr_mode == ORC_NBR_BRUTE) {
         for (int64_t q = 0; q < C->n; q++)
-          if (q != p && C->gas[q] && sph_nbr(C, p, q)) { sph_pair(C, p, q, a, &du, &mumax); npair++; }
+          if (q != p && C->gas[q] && sph_nbr(C, p, q)) { sph_pair(C, p, q, &acc); npair++; }
       } else {
         int64_t sp = 0;
         double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
@@ -1165,17 +1285,21 @@ static void sph_phase(ctx_t *C)
           if (!(box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz) < R * R)) continue;
           if (t->nchild[k] == 0) {
             for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++)
-              if (q != p && C->gas[q] && sph_nbr(C, p, q)) { sph_pair(C, p, q, a, &du, &mumax); npair++; }
+              if (q != p && C->gas[q] && sph_nbr(C, p, q)) { sph_pair(C, p, q, &acc); npair++; }
           } else {
             for (int32_t b = t->nchild[k] - 1; b >= 0; b--) stack[sp++] = t->child[k] + b;
           }
         }
       }
-      C->ax[p] += a[0];
-      C->ay[p] += a[1];
-      C->az[p] += a[2];
-      C->dudt[p] = du;
-      C->maxmu[p] = mumax;
+      C->ax[p] += acc.a[0];
+      C->ay[p] += acc.a[1];
+      C->az[p] += acc.a[2];
+      C->dudt[p] = P->entropy ? (P->gamma - 1.0) * pow(C->rho[p], 1.0 - P->gamma) * acc.du_v : acc.du;
+      C->maxmu[p] = acc.mumax;
+      C->vsig[p] = acc.vsig;
+      C->xsx[p] = P->xsph_eta * acc.xs[0];
+      C->xsy[p] = P->xsph_eta * acc.xs[1];
+      C->xsz[p] = P->xsph_eta * acc.xs[2];
       C->cnt_sph[p] = npair;
     }
     free(stack);
@@ -1234,6 +1358,10 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   C.ax = calloc(n, sizeof(double)); C.ay = calloc(n, sizeof(double)); C.az = calloc(n, sizeof(double));
   C.pot = calloc(n, sizeof(double)); C.dudt = calloc(n, sizeof(double)); C.maxmu = calloc(n, sizeof(double));
   C.P = calloc(n, sizeof(double)); C.cs = calloc(n, sizeof(double));
+  C.fa = calloc(n, sizeof(double));
+  for (int64_t q = 0; q < n; q++) C.fa[q] = 1.0;
+  C.xsx = calloc(n, sizeof(double)); C.xsy = calloc(n, sizeof(double)); C.xsz = calloc(n, sizeof(double));
+  C.vsig = calloc(n, sizeof(double));
   C.cnt_node = calloc(n, sizeof(int64_t)); C.cnt_pair = calloc(n, sizeof(int64_t));
   C.cnt_sph = calloc(n, sizeof(int64_t));
   C.cnt_soft = calloc(n, sizeof(int64_t));
@@ -1288,13 +1416,14 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
     OUT(ax, ax); OUT(ay, ay); OUT(az, az); OUT(pot, pot); OUT(dudt, dudt); OUT(maxmu, maxmu);
     OUT(cnt_node, cnt_node); OUT(cnt_pair, cnt_pair); OUT(cnt_sph, cnt_sph); OUT(iters, iters);
     OUT(cnt_soft, cnt_soft);
+    OUT(xsph_x, xsx); OUT(xsph_y, xsy); OUT(xsph_z, xsz); OUT(vsig, vsig);
 #undef OUT
   }
   free(C.vx); free(C.vy); free(C.vz); free(C.u); free(C.gas);
   free(C.h); free(C.nh); free(C.rho); free(C.omega); free(C.zeta); free(C.divv); free(C.divv_e);
   free(C.eps); free(C.neps); free(C.ups); free(C.xi);
   free(C.ax); free(C.ay); free(C.az); free(C.pot); free(C.dudt); free(C.maxmu);
-  free(C.P); free(C.cs); free(C.cnt_node); free(C.cnt_pair); free(C.cnt_sph); free(C.iters);
+  free(C.P); free(C.cs); free(C.fa); free(C.xsx); free(C.xsy); free(C.xsz); free(C.vsig); free(C.cnt_node); free(C.cnt_pair); free(C.cnt_sph); free(C.iters);
   free(C.cnt_soft); free(C.active);
   free(C.epsmax); free(C.hmax); free(C.ngas); free(C.epsbar); free(C.xsum);
   orc_tree_free(t);
@@ -1432,7 +1561,8 @@ void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
                     double *x, double *y, double *z, double *vx, double *vy, double *vz,
                     double *u, const double *ax, const double *ay, const double *az,
                     const double *dudt, double *vpx, double *vpy, double *vpz, double *up,
-                    double *h, double *eps, const double *divv_h, const double *divv_e)
+                    double *h, double *eps, const double *divv_h, const double *divv_e,
+                    const double *xsx, const double *xsy, const double *xsz)
 {
   for (int64_t i = 0; i < n; i++) {
     if (phase == 0) {
@@ -1444,9 +1574,17 @@ void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
       vx[i] += 0.5 * dt * ax[i];
       vy[i] += 0.5 * dt * ay[i];
       vz[i] += 0.5 * dt * az[i];
-      x[i] += dt * vx[i];
-      y[i] += dt * vy[i];
-      z[i] += dt * vz[i];
+      if (xsx && i < n_gas) {
+        /* X-SPH (Sect. 3.5, Eq. xsph): the particle drifts with the smoothed
+         * velocity v + dv of the last force evaluation */
+        x[i] += dt * (vx[i] + xsx[i]);
+        y[i] += dt * (vy[i] + xsy[i]);
+        z[i] += dt * (vz[i] + xsz[i]);
+      } else {
+        x[i] += dt * vx[i];
+        y[i] += dt * vy[i];
+        z[i] += dt * vz[i];
+      }
       if (i < n_gas) {
         if (up) up[i] = u[i] + dt * dudt[i];
         u[i] += 0.5 * dt * dudt[i];
@@ -1465,7 +1603,8 @@ void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
 double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double *vx,
                     const double *vy, const double *vz, const double *u, const double *h,
                     const double *eps, const double *ax, const double *ay, const double *az,
-                    const double *dudt, const double *divv, const double *maxmu, double eta_dt)
+                    const double *dudt, const double *divv, const double *maxmu, double eta_dt,
+                    const double *rho)
 {
   (void)vx; (void)vy; (void)vz;
   double dt = INFINITY;
@@ -1478,7 +1617,10 @@ double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double 
       if (t < dt) dt = t;
     }
     if (i < n_gas && p->hydro) {
-      double c = sqrt(p->gamma * (p->gamma - 1.0) * u[i]);
+      /* with the entropy variable A (Sect. 3.4): c^2 = gamma A rho^(gamma - 1),
+       * and the last criterion bounds the change of A */
+      double c = p->entropy ? sqrt(p->gamma * u[i] * pow(rho[i], p->gamma - 1.0))
+                            : sqrt(p->gamma * (p->gamma - 1.0) * u[i]);
       double den = h[i] * fabs(divv[i]) + c + 1.2 * (p->alpha * c + p->beta * maxmu[i]);
       if (den > 0.0) {
         double t = eta_dt * h[i] / den;
@@ -1495,12 +1637,14 @@ double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double 
 
 void orc_diagnostics(int64_t n, int64_t n_gas, const double *x, const double *y, const double *z,
                      const double *vx, const double *vy, const double *vz, const double *m,
-                     const double *u, const double *pot, double *out)
+                     const double *u, const double *pot, double *out,
+                     const double *rho, double gamma, int32_t entropy)
 {
   double ek = 0, eth = 0, V = 0, P[3] = {0, 0, 0}, L[3] = {0, 0, 0};
   for (int64_t i = 0; i < n; i++) {
     ek += 0.5 * m[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
-    if (i < n_gas && u) eth += m[i] * u[i];
+    /* u = A rho^(gamma - 1) / (gamma - 1) with the entropy variable (Sect. 3.4) */
+    if (i < n_gas && u) eth += m[i] * (entropy ? u[i] * pow(rho[i], gamma - 1.0) / (gamma - 1.0) : u[i]);
     if (pot) V += 0.5 * m[i] * pot[i];
     P[0] += m[i] * vx[i];
     P[1] += m[i] * vy[i];

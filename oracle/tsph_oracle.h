@@ -61,7 +61,25 @@ typedef struct {
                                  * passes the opening test but lies within the
                                  * softening reach acts as one softened
                                  * particle at its centre of mass              */
+  /* scheme variants (Sect. 3, 3.3.1, 3.4, 3.5) */
+  int32_t visc_form;            /* ORC_VISC_MG (Eq. mu_visc) or ORC_VISC_SIGNAL
+                                 * (Eqs. pvsig, vsig)                          */
+  int32_t entropy;              /* 1: the energy variable is the entropic
+                                 * function A = P / rho^gamma (Eq. SPHentr)    */
+  double xsph_eta;              /* X-SPH velocity smoothing (Eq. xsph); 0: off */
+  int32_t h_scheme;             /* ORC_H_LAGRANGIAN (eta = h n^(1/3)) or
+                                 * ORC_H_STANDARD (a fixed neighbour count, no
+                                 * grad-h terms)                               */
+  int32_t h_weight;             /* the density that sets h (Sect. 3, the four
+                                 * schemes of the mixed-mass test): ORC_HW_NUMBER
+                                 * (number density, Eq. nsum; every neighbour
+                                 * counts 1) or ORC_HW_MASS (mass density,
+                                 * Eq. densitySPH; neighbour j counts
+                                 * m_j / m_i).  rho is Eq. densitySPH either way */
 } orc_params;
+enum { ORC_VISC_MG = 0, ORC_VISC_SIGNAL = 1 };
+enum { ORC_H_LAGRANGIAN = 0, ORC_H_STANDARD = 1 };
+enum { ORC_HW_NUMBER = 0, ORC_HW_MASS = 1 };
 
 /* All arrays are in caller order, length n unless noted.  Gas particles are
  * the indices [0, n_gas).  Output arrays may be NULL when not wanted.       */
@@ -90,6 +108,8 @@ typedef struct {
   double *divv_eps;                                /* div v with the eps kernel    */
   double t_phase[4];   /* out: wall seconds of tree, length solves + densities,
                         * gravity and SPH (instrumentation only)              */
+  double *xsph_x, *xsph_y, *xsph_z;  /* X-SPH velocity correction (gas)       */
+  double *vsig;                      /* max over pairs of the signal velocity  */
 } orc_run;
 
 /* Full force evaluation: tree, h/eps solves, gravity walk, SPH forces.
@@ -140,15 +160,18 @@ void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
                     double *x, double *y, double *z, double *vx, double *vy, double *vz,
                     double *u, const double *ax, const double *ay, const double *az,
                     const double *dudt, double *vpx, double *vpy, double *vpz, double *up,
-                    double *h, double *eps, const double *divv_h, const double *divv_e);
+                    double *h, double *eps, const double *divv_h, const double *divv_e,
+                    const double *xsx, const double *xsy, const double *xsz);
 double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double *vx,
                     const double *vy, const double *vz, const double *u, const double *h,
                     const double *eps, const double *ax, const double *ay, const double *az,
-                    const double *dudt, const double *divv, const double *maxmu, double eta_dt);
+                    const double *dudt, const double *divv, const double *maxmu, double eta_dt,
+                    const double *rho /* entropy form: c from A and rho */);
 /* out[9] = E_kin, E_th, V, Px, Py, Pz, Lx, Ly, Lz (V from pot: 0.5 sum m pot) */
 void orc_diagnostics(int64_t n, int64_t n_gas, const double *x, const double *y, const double *z,
                      const double *vx, const double *vy, const double *vz, const double *m,
-                     const double *u, const double *pot, double *out);
+                     const double *u, const double *pot, double *out,
+                     const double *rho, double gamma, int32_t entropy /* E_th from A and rho */);
 
 void orc_multipole_field(int64_t n, const double *x, const double *y, const double *z,
                          const double *m, double px, double py, double pz, int32_t quadrupole,

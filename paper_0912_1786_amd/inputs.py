@@ -236,3 +236,30 @@ def random_cloud(n: int, seed: int = 1, masses=(1.0, 5.0), n_gas: int | None = N
     vx, vy, vz = (v_sigma * normal(seed, 710 + k, n) for k in range(3))
     u = np.where(np.arange(n) < n_gas, u_range[0] + (u_range[1] - u_range[0]) * uniform(seed, 704, n), 0.0)
     return _pack(x, y, z, vx, vy, vz, m, u, n_gas=n_gas, workload="random_cloud", seed=seed)
+
+
+def mixed_mass_lattice(spacing: float = 0.01, lx: float = 1.0, ly: float = 0.1, lz: float = 0.1,
+                       u: float = 1.0) -> dict:
+    """The mixed-mass density test (Sect. 3): two simple-cubic lattices of
+    the same spacing in the slab 0 < x < lx, 0 < y < ly, 0 < z < lz, the
+    second shifted by half a spacing along every axis (5e-3 for the 0.01
+    spacing, as printed).  Masses per lattice and side: 0.9e-6 and 0.1e-6
+    for x < 0.5, 2.25e-7 and 0.25e-7 for x >= 0.5, so that the densities are
+    1 and 0.25 with a spacing of 0.01 (a reading: the spacing is not
+    printed).  All gas, at rest; the heavy lattice first."""
+    def grid(off):
+        gx = np.arange(int(round(lx / spacing))) * spacing + off
+        gy = np.arange(int(round(ly / spacing))) * spacing + off
+        gz = np.arange(int(round(lz / spacing))) * spacing + off
+        X, Y, Z = np.meshgrid(gx, gy, gz, indexing="ij")
+        return X.ravel(), Y.ravel(), Z.ravel()
+    x1, y1, z1 = grid(0.25 * spacing)
+    x2, y2, z2 = grid(0.75 * spacing)
+    x, y, z = np.concatenate([x1, x2]), np.concatenate([y1, y2]), np.concatenate([z1, z2])
+    heavy = np.arange(x.size) < x1.size
+    left = x < 0.5 * lx
+    m = np.where(heavy, np.where(left, 0.9e-6, 2.25e-7), np.where(left, 0.1e-6, 0.25e-7))
+    n = x.size
+    zero = np.zeros(n)
+    return _pack(x.copy(), y.copy(), z.copy(), zero, zero, zero, m, np.full(n, u), n_gas=n,
+                 workload="mixed_mass_lattice", seed=0)
