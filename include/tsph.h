@@ -209,6 +209,29 @@ tsph_status tsph_kick_drift_dt(void *ctx, tsph_state *s, const double *dt_device
 tsph_status tsph_carry_bytes(int64_t n, size_t *bytes);
 tsph_status tsph_carry_save(void *ctx, int64_t n, void *dst_device, void *stream);
 tsph_status tsph_carry_load(void *ctx, int64_t n, const void *src_device, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * totals of tsph_diagnostics without a context.  No memory is allocated:
+ * the partial sums go to a static device buffer of
+ * TSPH_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
+ * the process ends; every call on a GPU shares that GPU's buffer, so calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  count systems lie back to back in the state:
+ * system k = particles [off[k], off[k+1]) with its first ngas[k] gas, where
+ * off_device (count + 1 int64) and ngas_device (count int64) are DEVICE
+ * arrays the host does not read (ranges are clamped to [0, n)); count = 1
+ * takes the whole state (s->n particles, the first s->n_gas gas) and
+ * ignores the tables.  Writes nine FP64 totals per system to out_device
+ * exactly as tsph_diagnostics does (same kernels, same summation order).
+ * Errors: TSPH_EINVAL for null pointers or bad sizes, TSPH_ECAPACITY for
+ * count > TSPH_NOALLOC_MAX_SYSTEMS, TSPH_EHIP for a failed launch;
+ * tsph_noalloc_last_error gives the text (per host thread). */
+#define TSPH_NOALLOC_SCRATCH_BYTES (1 << 20)
+#define TSPH_NOALLOC_MAX_SYSTEMS 910
+tsph_status tsph_diagnostics_noalloc(const tsph_state *s, int32_t count, const int64_t *off_device,
+                                     const int64_t *ngas_device, double *out_device, void *stream);
+const char *tsph_noalloc_last_error(void);
+
 /* Global time-step (Sect. 4.2) from the last tsph_compute_forces: min over
  * particles of eta_dt sqrt(min(eps,h)/|a|), the Courant criterion and
  * eta_dt |u / du/dt|.  Writes one double per system held to dt_device. */

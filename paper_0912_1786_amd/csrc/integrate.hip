@@ -9,6 +9,8 @@
 // bit-reproducible.
 #include <stdio.h>
 
+#include <mutex>
+
 #include "tsph_internal.h"
 
 namespace tsph {
@@ -177,7 +179,9 @@ __global__ __launch_bounds__(256) void k_diag_partial(Members M, const double *_
                                                       double *__restrict__ part) {
   double acc[kNDiag] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int mem = blockIdx.y;
-  const int64_t i0 = member_begin(M, mem), i1 = member_end(M, mem);
+  // member ranges clamped to [0, n): tables the host never read stay in bounds
+  const int64_t i0 = max((int64_t)0, min(member_begin(M, mem), M.n));
+  const int64_t i1 = max(i0, min(member_end(M, mem), M.n));
   const int64_t gas_end = i0 + (M.count <= 1 ? M.n_gas : M.ngas[mem]);
   for (int64_t i = i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < i1;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -277,12 +281,78 @@ tsph_status tsph_impl_timestep(Ctx *c, double *dt_device, hipStream_t st) {
   return TSPH_OK;
 }
 
-tsph_status tsph_impl_diagnostics(Ctx *c, const tsph_state *s, double *out, hipStream_t st) {
-  const Members M = members_of(c, s->n, s->n_gas);
+// diagnostics of the systems of M: partial sums per block to part, totals to out
+static hipError_t launch_diagnostics(const Members &M, const tsph_state *s, double *part, double *out,
+                                     hipStream_t st) {
   const int rb = M.count > 1 ? kMemberBlocks : kRedBlocks;
   hipLaunchKernelGGL(k_diag_partial, dim3(rb, M.count), dim3(256), 0, st, M, s->x, s->y, s->z, s->vx, s->vy,
-                     s->vz, s->m, s->u, s->pot, c->red);
-  hipLaunchKernelGGL(k_diag_final, dim3(M.count), dim3(256), 0, st, rb, c->red, out);
-  TSPH_HIP_CHECK(c, hipGetLastError());
+                     s->vz, s->m, s->u, s->pot, part);
+  hipLaunchKernelGGL(k_diag_final, dim3(M.count), dim3(256), 0, st, rb, part, out);
+  return hipGetLastError();
+}
+
+tsph_status tsph_impl_diagnostics(Ctx *c, const tsph_state *s, double *out, hipStream_t st) {
+  TSPH_HIP_CHECK(c, launch_diagnostics(members_of(c, s->n, s->n_gas), s, c->red, out, st));
   return TSPH_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Diagnostics without a context and without allocation: the partial sums go
+// to a static device array (one copy per GPU, held until the process ends).
+// In host code `scratch` names a host-side stand-in, so its device address on
+// each GPU is taken once with hipGetSymbolAddress and used from then on.
+// ---------------------------------------------------------------------------
+constexpr int64_t kScratchDoubles = TSPH_NOALLOC_SCRATCH_BYTES / 8;
+static_assert(TSPH_NOALLOC_MAX_SYSTEMS * kMemberBlocks * kNDiag <= kScratchDoubles, "scratch too small");
+static_assert(kRedBlocks * kNDiag <= kScratchDoubles, "scratch too small");
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices];
+
+// device address of this GPU's scratch array (taken on first use)
+hipError_t scratch_for_device(double **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+thread_local char g_noalloc_err[256] = "";
+}  // namespace
+
+extern "C" tsph_status tsph_diagnostics_noalloc(const tsph_state *s, int32_t count, const int64_t *off_device,
+                                                const int64_t *ngas_device, double *out_device, void *stream) {
+  auto fail = [](tsph_status r, const char *msg) {
+    snprintf(g_noalloc_err, sizeof(g_noalloc_err), "tsph_diagnostics_noalloc: %s", msg);
+    return r;
+  };
+  if (!s || !out_device) return fail(TSPH_EINVAL, "state and out_device are required");
+  if (s->n < 1 || s->n_gas < 0 || s->n_gas > s->n) return fail(TSPH_EINVAL, "bad state sizes");
+  if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->m)
+    return fail(TSPH_EINVAL, "diagnostics need x, v, m");
+  if (count < 1) return fail(TSPH_EINVAL, "count must be >= 1");
+  if (count > TSPH_NOALLOC_MAX_SYSTEMS) return fail(TSPH_ECAPACITY, "count exceeds TSPH_NOALLOC_MAX_SYSTEMS");
+  if (count > 1 && (!off_device || !ngas_device))
+    return fail(TSPH_EINVAL, "several systems need off_device and ngas_device");
+  double *part = nullptr;
+  hipError_t e = scratch_for_device(&part);
+  if (e != hipSuccess) return fail(TSPH_EHIP, hipGetErrorString(e));
+  const Members M{count > 1 ? off_device : nullptr, count > 1 ? ngas_device : nullptr, count, s->n, s->n_gas};
+  e = launch_diagnostics(M, s, part, out_device, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(TSPH_EHIP, hipGetErrorString(e));
+  return TSPH_OK;
+}
+
+extern "C" const char *tsph_noalloc_last_error(void) { return g_noalloc_err; }

@@ -93,6 +93,8 @@ def lib():
             "tsph_last_error": ([_P], C.c_char_p),
             "tsph_version": ([], C.c_char_p),
             "tsph_source_id": ([], C.c_char_p),
+            "tsph_diagnostics_noalloc": ([S, C.c_int32, _P, _P, _P, _P], C.c_int),
+            "tsph_noalloc_last_error": ([], C.c_char_p),
             "tsph_probe": ([C.c_int32, C.c_int64, _P, _P, _P, _P, C.POINTER(C.c_double)], C.c_int),
         }
         for name, (args, res) in sig.items():
@@ -111,7 +113,8 @@ def lib():
 EXPORTED = ("tsph_create", "tsph_destroy", "tsph_set_params", "tsph_default_params", "tsph_bytes_required",
             "tsph_set_members", "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_kick_drift_dt", "tsph_carry_bytes",
             "tsph_carry_save", "tsph_carry_load", "tsph_timestep", "tsph_diagnostics", "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
-            "tsph_timing", "tsph_phase_times", "tsph_probe", "tsph_debug_handoff_cap", "tsph_source_id")
+            "tsph_timing", "tsph_phase_times", "tsph_probe", "tsph_debug_handoff_cap", "tsph_source_id",
+            "tsph_diagnostics_noalloc", "tsph_noalloc_last_error")
 PHASES = ("tree", "density", "gravity", "sph", "finish")
 
 
@@ -218,6 +221,18 @@ def tsph_timestep(ctx, st: State, dt_ptr: int, stream=None):
 
 def tsph_diagnostics(ctx, st: State, out_ptr: int, stream=None):
     _check("tsph_diagnostics", lib().tsph_diagnostics(ctx, C.byref(st), C.c_void_p(out_ptr), _stream(stream)), ctx)
+
+
+NOALLOC_MAX_SYSTEMS = 910
+
+
+def tsph_diagnostics_noalloc(st: State, count: int, off_ptr: int, ngas_ptr: int, out_ptr: int, stream=None):
+    """Context-free diagnostics into out_ptr (9 per system); off_ptr and
+    ngas_ptr are device int64 tables (ignored for count = 1)."""
+    rc = lib().tsph_diagnostics_noalloc(C.byref(st), int(count), C.c_void_p(off_ptr or None),
+                                        C.c_void_p(ngas_ptr or None), C.c_void_p(out_ptr), _stream(stream))
+    if rc != TSPH_OK:
+        raise TsphError("tsph_diagnostics_noalloc", rc, lib().tsph_noalloc_last_error().decode())
 
 
 def tsph_read_flags(ctx):
