@@ -122,7 +122,50 @@ typedef struct {
   double eta_dt;       /* time-step coefficient of the Sect. 4.2 criteria      */
   int32_t max_members; /* independent systems one context can hold
                           * (tsph_set_members); 1 by default                  */
+  int32_t grav_corr_literal; /* 1: the correction terms with the mass weighting
+                          * printed in Sect. 2.1 (Eq. zeta sums d phi/d eps
+                          * without masses; Eq. dLgravdr weights both terms of
+                          * a pair by m_j); 0 (default): the weighting that
+                          * makes the force the gradient of the softened
+                          * Lagrangian for unequal masses (the two agree for
+                          * equal masses)                                     */
+  int32_t soften_cells;  /* 1: softened cells (Sect. 2.2): a node that passes
+                          * the opening test but lies within the softening
+                          * reach 2 max(eps) acts as one softened particle at
+                          * its centre of mass, with the mass-weighted mean
+                          * eps of its particles and their correction terms
+                          * gathered there, instead of being opened; 0
+                          * (default): such nodes are opened down to exact
+                          * particle pairs                                    */
+  /* scheme variants (Sect. 3 to 3.5) */
+  int32_t visc_form;   /* TSPH_VISC_MG: Monaghan-Gingold (Eq. mu_visc);
+                          TSPH_VISC_SIGNAL: signal velocity, Pi_ij = -alpha
+                          v_sig w_ij / rhobar with w_ij = v_ij . x_ij / r and
+                          v_sig = 2 cbar - w_ij (Eqs. pvsig, vsig)            */
+  int32_t entropy;     /* 1: the state's u holds the entropic function
+                          A = P / rho^gamma and dudt its rate, the viscous
+                          term of Eq. SPHentr; P = A rho^gamma              */
+  double xsph_eta;     /* X-SPH (Eq. xsph): gas particles drift with
+                          v + eta sum_j m_j (v_j - v_i) Wbar_ij / rhobar_ij,
+                          Wbar the mean of W(r, h_i) and W(r, h_j), taken from
+                          the last force pass; 0 (default): plain drift     */
+  int32_t h_scheme;    /* TSPH_H_LAGRANGIAN (default): eta = h n^(1/3) with
+                          the grad-h terms; TSPH_H_STANDARD: h puts a fixed
+                          number N = 4 pi/3 (2 eta_h)^3 (rounded) of gas
+                          particles, the sink included, inside 2h (2h midway
+                          between the N-th and the next larger distance;
+                          equal distances are taken whole), no grad-h terms  */
+  int32_t h_weight;    /* density that sets h: TSPH_HW_NUMBER (default,
+                          Eq. nsum) or TSPH_HW_MASS (Eq. densitySPH: a
+                          neighbour counts m_j / m_i; the grad-h factor is
+                          then 1 / Omega_i with Omega_i = 1 + h/(3 rho)
+                          sum m dW/dh).  The mass form is taken with
+                          TSPH_H_LAGRANGIAN only (TSPH_EINVAL otherwise).
+                          rho is Eq. densitySPH in every scheme              */
 } tsph_params;
+enum { TSPH_VISC_MG = 0, TSPH_VISC_SIGNAL = 1 };
+enum { TSPH_H_LAGRANGIAN = 0, TSPH_H_STANDARD = 1 };
+enum { TSPH_HW_NUMBER = 0, TSPH_HW_MASS = 1 };
 
 typedef struct {
   int64_t n, n_gas;
@@ -156,7 +199,11 @@ tsph_status tsph_set_params(void *ctx, const tsph_params *p);
  * h_tol=1e-10, kappa=0.1, leaf 16, group 64, eta_dt=0.1, split_leaves 256,
  * max_members 1. */
 void tsph_default_params(tsph_params *p);
-/* Device bytes a context of this capacity reserves (host-only, no GPU). */
+/* Device bytes a context of this capacity reserves (host-only, no GPU).  The
+ * arena is laid out per particle for any mix of species (gas records are
+ * reserved for every particle), so that one context -- a pooled serving
+ * shell, an ensemble -- can hold systems of any gas fraction up to its
+ * capacity; the gas count therefore does not enter. */
 tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t *bytes);
 
 /* Several independent systems in one context (an ensemble advanced by the
@@ -197,9 +244,20 @@ tsph_status tsph_kick_drift(void *ctx, tsph_state *s, double dt, int32_t phase, 
  * negative or non-finite value there makes the kernel do nothing (the
  * state is left unchanged). */
 tsph_status tsph_kick_drift_dt(void *ctx, tsph_state *s, const double *dt_device, int32_t phase, void *stream);
+/* One leapfrog step of every system the context holds (one, or the members
+ * of tsph_set_members), each with its own global time-step, with no host
+ * synchronisation: tsph_timestep into dt_device (one double per system,
+ * device memory owned by the caller), tsph_kick_drift_dt(TSPH_KD_FIRST),
+ * tsph_compute_forces and tsph_kick_drift_dt(TSPH_KD_SECOND) on the stream.
+ * Needs a previous force pass on the context (its time-steps and
+ * accelerations); enqueues only, so a HIP graph can capture it (a batch of
+ * independent simulations advanced by one graph launch per step). */
+tsph_status tsph_batch_step(void *ctx, tsph_state *s, double *dt_device, void *stream);
+
 /* The carry of a context from one step to the next: the global time-step
- * of the last force pass and the velocity divergences with which the next
- * drift carries h and eps (2 n + 1 doubles for n particles).  Saving it and
+ * of the last force pass, the velocity divergences with which the next
+ * drift carries h and eps, and the X-SPH velocity correction of that drift
+ * (5 n + 1 doubles for n particles).  Saving it and
  * loading it into a context (the same or a new one) lets a simulation leave
  * the device between steps and continue bit for bit: after tsph_carry_load
  * the next tsph_timestep / tsph_kick_drift behave as if the force pass had

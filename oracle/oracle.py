@@ -37,7 +37,9 @@ class Params(C.Structure):
                 ("gravity", C.c_int32), ("hydro", C.c_int32), ("batch_size", C.c_int32),
                 ("batch_mode", C.c_int32), ("grav_corr_literal", C.c_int32), ("soften_cells", C.c_int32),
                 ("visc_form", C.c_int32), ("entropy", C.c_int32), ("xsph_eta", C.c_double),
-                ("h_scheme", C.c_int32), ("h_weight", C.c_int32)]
+                ("h_scheme", C.c_int32), ("h_weight", C.c_int32), ("balsara", C.c_int32),
+                ("alpha_switch", C.c_int32), ("alpha_min", C.c_double), ("conduction", C.c_int32),
+                ("alpha_u_min", C.c_double)]
 
 
 class Run(C.Structure):
@@ -50,7 +52,8 @@ class Run(C.Structure):
                 ("cnt_node", I64), ("cnt_pair", I64), ("cnt_sph", I64), ("iters", I32),
                 ("n_noconv", C.c_int64), ("sinks", I64), ("n_sinks", C.c_int64), ("cnt_soft", I64),
                 ("divv_eps", D), ("t_phase", C.c_double * 4), ("xsph_x", D), ("xsph_y", D), ("xsph_z", D),
-                ("vsig", D)]
+                ("vsig", D), ("alpha_in", D), ("alpha_u_in", D), ("dalpha", D), ("dalpha_u", D), ("curlx", D),
+                ("curly", D), ("curlz", D), ("fbal", D), ("lapu", D)]
 
 
 def eta_from_nnei(nnei: float) -> float:
@@ -97,8 +100,9 @@ def lib():
         L.orc_neighbours.restype = C.c_int64
         L.orc_potential_energy.argtypes = [C.c_int64, D, D, D, D, D, C.c_double]
         L.orc_potential_energy.restype = C.c_double
-        L.orc_kick_drift.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_int32] + [D] * 22
-        L.orc_timestep.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64] + [D] * 12 + [C.c_double, D]
+        L.orc_kick_drift.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_int32] + [D] * 22 + \
+            [D, D, C.c_double, D, D, C.c_double]
+        L.orc_timestep.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64] + [D] * 12 + [C.c_double, D, D]
         L.orc_timestep.restype = C.c_double
         L.orc_diagnostics.argtypes = [C.c_int64, C.c_int64] + [D] * 10 + [D, C.c_double, C.c_int32]
         L.orc_eval_kernel.argtypes = [C.c_int, C.c_int64, D, D, D]
@@ -128,7 +132,8 @@ def params(**kw) -> Params:
              beta=2.0, av_eps2=0.01, tc92=1, h_maxit=60, h_tol=1e-10, kappa=0.1, leaf_size=8,
              group_size=32, walk_mode=WALK_GROUP, nbr_mode=NBR_TREE, gravity=1, hydro=1, batch_size=64,
              batch_mode=0, grav_corr_literal=0, soften_cells=0, visc_form=VISC_MG, entropy=0, xsph_eta=0.0,
-             h_scheme=H_LAGRANGIAN, h_weight=HW_NUMBER)
+             h_scheme=H_LAGRANGIAN, h_weight=HW_NUMBER, balsara=0, alpha_switch=0, alpha_min=0.01,
+             conduction=0, alpha_u_min=0.0)
     if "nnei" in kw:
         e = eta_from_nnei(kw.pop("nnei"))
         d["eta_h"] = d["eta_eps"] = e
@@ -147,7 +152,8 @@ def kernel(name: str, r, h):
     return out
 
 
-def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=None, sinks=None) -> dict:
+def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=None, sinks=None, alpha=None,
+                   alpha_u=None) -> dict:
     """Full oracle force evaluation on an initial-condition dict.
 
     ``vel``/``u`` override the velocities and internal energies used in the
@@ -163,11 +169,14 @@ def compute_forces(ic: dict, prm: Params, h_in=None, eps_in=None, vel=None, u=No
     ein = None if eps_in is None else _f64(eps_in)
     out = {k: np.zeros(n) for k in ("h", "nh", "rho", "omega", "zeta", "divv", "eps", "neps", "ups",
                                      "xi", "ax", "ay", "az", "pot", "dudt", "maxmu", "divv_eps", "xsph_x",
-                                     "xsph_y", "xsph_z", "vsig")}
+                                     "xsph_y", "xsph_z", "vsig", "dalpha", "dalpha_u", "curlx", "curly",
+                                     "curlz", "fbal", "lapu")}
     cnt = {k: np.zeros(n, np.int64) for k in ("cnt_node", "cnt_pair", "cnt_sph", "cnt_soft")}
     snk = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
     iters = np.zeros(n, np.int32)
-    r = Run(n=n, n_gas=n_gas, x=_p(x), y=_p(y), z=_p(z), vx=_p(vx), vy=_p(vy), vz=_p(vz), m=_p(m),
+    al = None if alpha is None else _f64(alpha)
+    alu = None if alpha_u is None else _f64(alpha_u)
+    r = Run(alpha_in=_p(al), alpha_u_in=_p(alu), n=n, n_gas=n_gas, x=_p(x), y=_p(y), z=_p(z), vx=_p(vx), vy=_p(vy), vz=_p(vz), m=_p(m),
             u=_p(uu), h_in=_p(hin), eps_in=_p(ein), iters=_p(iters, I32), sinks=_p(snk, I64),
             n_sinks=0 if snk is None else snk.size,
             **{k: _p(v) for k, v in out.items()}, **{k: _p(v, I64) for k, v in cnt.items()})
@@ -252,13 +261,15 @@ def potential_energy(x, y, z, m, eps, G: float = 1.0) -> float:
 
 
 def kick_drift(st: dict, dt: float, phase: int, acc, dudt, pred: dict | None = None,
-               lengths: dict | None = None, xsph=None):
+               lengths: dict | None = None, xsph=None, alphas: dict | None = None):
     """In-place KDK half step on a state dict (x, y, z, vx, vy, vz, u).
 
     ``lengths`` (phase 0): arrays "h" and "eps", updated in place along the
     drift from the divergences "divv" and "divv_eps" of the last force
     evaluation.  ``xsph`` (phase 0): the X-SPH velocity corrections (three
-    arrays) added to the drift velocity of the gas."""
+    arrays) added to the drift velocity of the gas.  ``alphas``: arrays
+    "alpha", "alpha_u" (updated in place), their rates "dalpha", "dalpha_u"
+    and floors "alpha_min", "alpha_u_min"."""
     ax, ay, az = (_f64(a) for a in acc)
     du = _f64(dudt)
     n, n_gas = int(st["n"]), int(st["n_gas"])
@@ -270,7 +281,10 @@ def kick_drift(st: dict, dt: float, phase: int, acc, dudt, pred: dict | None = N
             assert a.dtype == np.float64 and a.flags.c_contiguous
     lib().orc_kick_drift(n, n_gas, dt, phase, *(_p(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "u")),
                          _p(ax), _p(ay), _p(az), _p(du), *(_p(v) for v in vp), *(_p(v) for v in ln),
-                         *((_p(_f64(v)) for v in xsph) if xsph is not None else (D(), D(), D())))
+                         *((_p(_f64(v)) for v in xsph) if xsph is not None else (D(), D(), D())),
+                         *((_p(alphas["alpha"]), _p(_f64(alphas["dalpha"])), float(alphas["alpha_min"]),
+                            _p(alphas["alpha_u"]), _p(_f64(alphas["dalpha_u"])), float(alphas["alpha_u_min"]))
+                           if alphas is not None else (D(), D(), 0.0, D(), D(), 0.0)))
 
 
 def timestep(prm: Params, st: dict, out: dict, eta_dt: float = 0.1) -> float:
@@ -279,7 +293,8 @@ def timestep(prm: Params, st: dict, out: dict, eta_dt: float = 0.1) -> float:
             out["az"], out["dudt"], out["divv"], out["maxmu"]]
     arrs = [_f64(a) for a in arrs]
     rho = _f64(out["rho"]) if "rho" in out else None
-    return lib().orc_timestep(C.byref(prm), n, n_gas, *(_p(a) for a in arrs), eta_dt, _p(rho))
+    al = _f64(st["alpha"]) if st.get("alpha") is not None else None
+    return lib().orc_timestep(C.byref(prm), n, n_gas, *(_p(a) for a in arrs), eta_dt, _p(rho), _p(al))
 
 
 def diagnostics(st: dict, pot, rho=None, gamma: float = 5.0 / 3.0, entropy: bool = False) -> np.ndarray:

@@ -544,6 +544,7 @@ typedef struct {
   double *P, *cs;
   double *fa;                 /* grad-h factor f_ij = fa_i + zeta_i / (m_j Omega*_i) */
   double *xsx, *xsy, *xsz, *vsig;  /* X-SPH velocity correction, max signal velocity */
+  double *curl, *fbal, *lapu, *alpha, *alpha_u, *dalpha, *dalpha_u;  /* dissipation switches */
   int64_t *cnt_node, *cnt_pair, *cnt_sph, *cnt_soft;
   int32_t *iters;
   int64_t noconv;             /* length solves that did not converge        */
@@ -594,7 +595,7 @@ static void collect(const ctx_t *C, int64_t p, double R, int gas_only, cand_t *c
   }
 }
 
-typedef struct { double n, sdh, rho, msdh, mdphi, divv, dphi; } sums_t;
+typedef struct { double n, sdh, rho, msdh, mdphi, divv, dphi, curl[3]; } sums_t;
 
 /* number-density sum and its h-derivative over the candidates, Eqs. (rho0),
  * (nsum); self term included (j = i) */
@@ -621,6 +622,11 @@ static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, 
           double g = orc_dWdr(r, h) / r; /* grad_i W = g (x_i - x_j) */
           double dvx = C->vx[p] - C->vx[q], dvy = C->vy[p] - C->vy[q], dvz = C->vz[p] - C->vz[q];
           s.divv += g * (dvx * (px - t->xs[q]) + dvy * (py - t->ys[q]) + dvz * (pz - t->zs[q]));
+          /* curl: v_ij x grad_i W_ij */
+          double ex = px - t->xs[q], ey = py - t->ys[q], ez = pz - t->zs[q];
+          s.curl[0] += g * (dvy * ez - dvz * ey);
+          s.curl[1] += g * (dvz * ex - dvx * ez);
+          s.curl[2] += g * (dvx * ey - dvy * ex);
         }
       } else {
         /* softening: mass-weighted d phi / d eps (Eq. zeta), and the
@@ -829,6 +835,9 @@ static void density_phase(ctx_t *C, const double *h_in, const double *eps_in)
         }
         /* velocity divergence (Sect. 2.1), with the gas kernel */
         C->divv[p] = -s.divv / (s.n * C->omega[p]);
+        /* velocity curl with the normalisation of the divergence:
+         * curl_i = (1/(n_i Omega_i)) sum_j v_ij x grad_i W_ij(h_i) */
+        for (int d = 0; d < 3; d++) C->curl[3 * p + d] = s.curl[d] / (s.n * C->omega[p]);
       }
       /* all species: adaptive softening length over all neighbours
        * (Sect. 2.1, Eq. etan; Sect. 3.2, independent eps and h) */
@@ -1176,6 +1185,7 @@ static void gravity_direct(ctx_t *C)
  * eta^2 = av_eps2 hbar^2; it acts only on approaching pairs. */
 typedef struct {
   double a[3], du, du_v, mumax, vsig, xs[3];  /* du: pressure + viscous; du_v: viscous */
+  double lapu;                                /* Laplacian of u (Brookshaw)              */
 } sph_acc_t;
 
 /* Variants (flags of orc_params):
@@ -1215,8 +1225,11 @@ static void sph_pair(const ctx_t *C, int64_t p, int64_t q, sph_acc_t *acc)
   if (vd < 0.0) {
     double hb = 0.5 * (hi + hj);
     double mu = hb * vd / (r2 + P->av_eps2 * hb * hb);
-    double Pi = P->visc_form == ORC_VISC_SIGNAL ? -P->alpha * (2.0 * cb - w) * w / rb
-                                                : (-P->alpha * cb * mu + P->beta * mu * mu) / rb;
+    /* per-particle alpha: the pair mean replaces alpha (Sect. 3.3.1) */
+    double al = P->alpha_switch ? 0.5 * (C->alpha[p] + C->alpha[q]) : P->alpha;
+    double Pi = P->visc_form == ORC_VISC_SIGNAL ? -al * (2.0 * cb - w) * w / rb
+                                                : (-al * cb * mu + P->beta * mu * mu) / rb;
+    if (P->balsara) Pi *= 0.5 * (C->fbal[p] + C->fbal[q]);
     double Gb = 0.5 * (fij * gi + fji * gj);
     s += mj * Pi * Gb;
     double ev = 0.5 * mj * Pi * Gb * vd;
@@ -1227,6 +1240,20 @@ static void sph_pair(const ctx_t *C, int64_t p, int64_t q, sph_acc_t *acc)
   acc->du += e;
   double vs = 2.0 * cb - (w < 0.0 ? w : 0.0);
   if (vs > acc->vsig) acc->vsig = vs;
+  if (P->conduction) {
+    /* artificial conductivity (Sect. 3.3.2): Pi^u = -alphabar^u v^u_sig
+     * (u_i - u_j) / rhobar with v^u_sig = sqrt(|P_i - P_j| / rhobar), acting
+     * through the averaged gradient's magnitude |Gbar| = |Gb| r; and the
+     * Laplacian of u (Brookshaw), -sum_j 2 m_j (u_i - u_j) / rho_j |Gbar| / r:
+     * the printed sum without the minus sign is minus the Laplacian, which
+     * the source term's |lap u| does not see */
+    double Gbm = fabs(0.5 * (fij * gi + fji * gj)) * r;
+    double du_ij = C->u[p] - C->u[q];
+    double vsu = sqrt(fabs(C->P[p] - C->P[q]) / rb);
+    double Piu = -0.5 * (C->alpha_u[p] + C->alpha_u[q]) * vsu * du_ij / rb;
+    acc->du += mj * Piu * Gbm;
+    acc->lapu -= 2.0 * mj * du_ij / C->rho[q] * Gbm / r;
+  }
   if (P->xsph_eta > 0.0) {
     double wb = 0.5 * (orc_W(r, hi) + orc_W(r, hj)) / rb;
     acc->xs[0] -= mj * vx * wb;
@@ -1261,6 +1288,14 @@ static void sph_phase(ctx_t *C)
       C->P[p] = (P->gamma - 1.0) * C->rho[p] * C->u[p];
       C->cs[p] = sqrt(P->gamma * (P->gamma - 1.0) * C->u[p]);
     }
+  }
+  /* Balsara limiter (Sect. 3.3.1): f = |div v| / (|div v| + |curl v| + 1e-4 c / h) */
+  for (int64_t p = 0; p < C->n; p++) {
+    if (!C->gas[p]) continue;
+    double cu = sqrt(C->curl[3 * p] * C->curl[3 * p] + C->curl[3 * p + 1] * C->curl[3 * p + 1] +
+                     C->curl[3 * p + 2] * C->curl[3 * p + 2]);
+    double dv = fabs(C->divv[p]);
+    C->fbal[p] = dv / (dv + cu + 1e-4 * C->cs[p] / C->h[p]);
   }
 #pragma omp parallel
   {
@@ -1300,6 +1335,19 @@ static void sph_phase(ctx_t *C)
       C->xsx[p] = P->xsph_eta * acc.xs[0];
       C->xsy[p] = P->xsph_eta * acc.xs[1];
       C->xsz[p] = P->xsph_eta * acc.xs[2];
+      C->lapu[p] = acc.lapu;
+      /* the coefficients' rates (Sect. 3.3.1, 3.3.2): relaxation to the floor
+       * over tau = h / (0.1 v_sig), sources 0.75 f max(0, -div v) and
+       * h |lap u| / sqrt(u) */
+      double tau = acc.vsig > 0.0 ? C->h[p] / (0.1 * acc.vsig) : INFINITY;
+      if (P->alpha_switch) {
+        double src = 0.75 * C->fbal[p] * (C->divv[p] < 0.0 ? -C->divv[p] : 0.0);
+        C->dalpha[p] = -(C->alpha[p] - P->alpha_min) / tau + src;
+      }
+      if (P->conduction) {
+        double src = C->u[p] > 0.0 ? C->h[p] * fabs(acc.lapu) / sqrt(C->u[p]) : 0.0;
+        C->dalpha_u[p] = -(C->alpha_u[p] - P->alpha_u_min) / tau + src;
+      }
       C->cnt_sph[p] = npair;
     }
     free(stack);
@@ -1329,6 +1377,7 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   if (!p || !r || r->n <= 0 || r->n_gas < 0 || r->n_gas > r->n) return -1;
   if (!r->x || !r->y || !r->z || !r->m) return -1;
   if (p->gravity && p->soft_mode == ORC_SOFT_CONSTANT && !r->eps_in) return -1;
+  if (p->conduction && p->entropy) return -1;  /* conduction acts on u */
   int64_t n = r->n;
   double t0 = wall_seconds();
   orc_tree *t = orc_tree_build(n, r->x, r->y, r->z, r->m, p->leaf_size);
@@ -1362,6 +1411,14 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   for (int64_t q = 0; q < n; q++) C.fa[q] = 1.0;
   C.xsx = calloc(n, sizeof(double)); C.xsy = calloc(n, sizeof(double)); C.xsz = calloc(n, sizeof(double));
   C.vsig = calloc(n, sizeof(double));
+  C.curl = calloc(3 * n, sizeof(double)); C.fbal = calloc(n, sizeof(double)); C.lapu = calloc(n, sizeof(double));
+  C.alpha = calloc(n, sizeof(double)); C.alpha_u = calloc(n, sizeof(double));
+  C.dalpha = calloc(n, sizeof(double)); C.dalpha_u = calloc(n, sizeof(double));
+  for (int64_t q = 0; q < n; q++) {
+    int64_t i = t->perm[q];
+    C.alpha[q] = r->alpha_in ? r->alpha_in[i] : p->alpha;
+    C.alpha_u[q] = r->alpha_u_in ? r->alpha_u_in[i] : 0.0;
+  }
   C.cnt_node = calloc(n, sizeof(int64_t)); C.cnt_pair = calloc(n, sizeof(int64_t));
   C.cnt_sph = calloc(n, sizeof(int64_t));
   C.cnt_soft = calloc(n, sizeof(int64_t));
@@ -1417,13 +1474,16 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
     OUT(cnt_node, cnt_node); OUT(cnt_pair, cnt_pair); OUT(cnt_sph, cnt_sph); OUT(iters, iters);
     OUT(cnt_soft, cnt_soft);
     OUT(xsph_x, xsx); OUT(xsph_y, xsy); OUT(xsph_z, xsz); OUT(vsig, vsig);
+    OUT(fbal, fbal); OUT(lapu, lapu); OUT(dalpha, dalpha); OUT(dalpha_u, dalpha_u);
+    if (r->curlx) { r->curlx[i] = C.curl[3 * q]; r->curly[i] = C.curl[3 * q + 1]; r->curlz[i] = C.curl[3 * q + 2]; }
 #undef OUT
   }
   free(C.vx); free(C.vy); free(C.vz); free(C.u); free(C.gas);
   free(C.h); free(C.nh); free(C.rho); free(C.omega); free(C.zeta); free(C.divv); free(C.divv_e);
   free(C.eps); free(C.neps); free(C.ups); free(C.xi);
   free(C.ax); free(C.ay); free(C.az); free(C.pot); free(C.dudt); free(C.maxmu);
-  free(C.P); free(C.cs); free(C.fa); free(C.xsx); free(C.xsy); free(C.xsz); free(C.vsig); free(C.cnt_node); free(C.cnt_pair); free(C.cnt_sph); free(C.iters);
+  free(C.P); free(C.cs); free(C.fa); free(C.xsx); free(C.xsy); free(C.xsz); free(C.vsig);
+  free(C.curl); free(C.fbal); free(C.lapu); free(C.alpha); free(C.alpha_u); free(C.dalpha); free(C.dalpha_u); free(C.cnt_node); free(C.cnt_pair); free(C.cnt_sph); free(C.iters);
   free(C.cnt_soft); free(C.active);
   free(C.epsmax); free(C.hmax); free(C.ngas); free(C.epsbar); free(C.xsum);
   orc_tree_free(t);
@@ -1562,7 +1622,9 @@ void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
                     double *u, const double *ax, const double *ay, const double *az,
                     const double *dudt, double *vpx, double *vpy, double *vpz, double *up,
                     double *h, double *eps, const double *divv_h, const double *divv_e,
-                    const double *xsx, const double *xsy, const double *xsz)
+                    const double *xsx, const double *xsy, const double *xsz,
+                    double *alpha, const double *dalpha, double alpha_min,
+                    double *alpha_u, const double *dalpha_u, double alpha_u_min)
 {
   for (int64_t i = 0; i < n; i++) {
     if (phase == 0) {
@@ -1595,6 +1657,16 @@ void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
       vz[i] += 0.5 * dt * az[i];
       if (i < n_gas) u[i] += 0.5 * dt * dudt[i];
     }
+    /* the dissipation coefficients follow the half kicks with the rates of
+     * the last force evaluation, kept at or above their floors */
+    if (i < n_gas && alpha && dalpha) {
+      alpha[i] += 0.5 * dt * dalpha[i];
+      if (!(alpha[i] >= alpha_min)) alpha[i] = alpha_min;
+    }
+    if (i < n_gas && alpha_u && dalpha_u) {
+      alpha_u[i] += 0.5 * dt * dalpha_u[i];
+      if (!(alpha_u[i] >= alpha_u_min)) alpha_u[i] = alpha_u_min;
+    }
   }
 }
 
@@ -1604,7 +1676,7 @@ double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double 
                     const double *vy, const double *vz, const double *u, const double *h,
                     const double *eps, const double *ax, const double *ay, const double *az,
                     const double *dudt, const double *divv, const double *maxmu, double eta_dt,
-                    const double *rho)
+                    const double *rho, const double *alpha)
 {
   (void)vx; (void)vy; (void)vz;
   double dt = INFINITY;
@@ -1621,7 +1693,8 @@ double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double 
        * and the last criterion bounds the change of A */
       double c = p->entropy ? sqrt(p->gamma * u[i] * pow(rho[i], p->gamma - 1.0))
                             : sqrt(p->gamma * (p->gamma - 1.0) * u[i]);
-      double den = h[i] * fabs(divv[i]) + c + 1.2 * (p->alpha * c + p->beta * maxmu[i]);
+      double al = alpha ? alpha[i] : p->alpha;
+      double den = h[i] * fabs(divv[i]) + c + 1.2 * (al * c + p->beta * maxmu[i]);
       if (den > 0.0) {
         double t = eta_dt * h[i] / den;
         if (t < dt) dt = t;

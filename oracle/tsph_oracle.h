@@ -76,6 +76,12 @@ typedef struct {
                                  * counts 1) or ORC_HW_MASS (mass density,
                                  * Eq. densitySPH; neighbour j counts
                                  * m_j / m_i).  rho is Eq. densitySPH either way */
+  /* dissipation switches (Sect. 3.3.1, 3.3.2) */
+  int32_t balsara;              /* Pi_ij times (f_i + f_j)/2, the Balsara limiter */
+  int32_t alpha_switch;         /* per-particle alpha (Eq. alphaswitch)         */
+  double alpha_min;             /* its floor (0.01)                             */
+  int32_t conduction;           /* artificial thermal conductivity              */
+  double alpha_u_min;           /* floor of the conductivity coefficient (0)    */
 } orc_params;
 enum { ORC_VISC_MG = 0, ORC_VISC_SIGNAL = 1 };
 enum { ORC_H_LAGRANGIAN = 0, ORC_H_STANDARD = 1 };
@@ -110,6 +116,10 @@ typedef struct {
                         * gravity and SPH (instrumentation only)              */
   double *xsph_x, *xsph_y, *xsph_z;  /* X-SPH velocity correction (gas)       */
   double *vsig;                      /* max over pairs of the signal velocity  */
+  /* dissipation switches: per-particle coefficients in (gas), their rates,
+   * the velocity curl (h kernel), the Balsara factor and the Laplacian of u */
+  const double *alpha_in, *alpha_u_in;
+  double *dalpha, *dalpha_u, *curlx, *curly, *curlz, *fbal, *lapu;
 } orc_run;
 
 /* Full force evaluation: tree, h/eps solves, gravity walk, SPH forces.
@@ -161,12 +171,15 @@ void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
                     double *u, const double *ax, const double *ay, const double *az,
                     const double *dudt, double *vpx, double *vpy, double *vpz, double *up,
                     double *h, double *eps, const double *divv_h, const double *divv_e,
-                    const double *xsx, const double *xsy, const double *xsz);
+                    const double *xsx, const double *xsy, const double *xsz,
+                    double *alpha, const double *dalpha, double alpha_min,
+                    double *alpha_u, const double *dalpha_u, double alpha_u_min);
 double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double *vx,
                     const double *vy, const double *vz, const double *u, const double *h,
                     const double *eps, const double *ax, const double *ay, const double *az,
                     const double *dudt, const double *divv, const double *maxmu, double eta_dt,
-                    const double *rho /* entropy form: c from A and rho */);
+                    const double *rho /* entropy form: c from A and rho */,
+                    const double *alpha /* per-particle alpha, or NULL */);
 /* out[9] = E_kin, E_th, V, Px, Py, Pz, Lx, Ly, Lz (V from pot: 0.5 sum m pot) */
 void orc_diagnostics(int64_t n, int64_t n_gas, const double *x, const double *y, const double *z,
                      const double *vx, const double *vy, const double *vz, const double *m,

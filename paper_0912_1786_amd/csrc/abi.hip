@@ -53,6 +53,15 @@ const char *param_error(const tsph_params *p) {
   if (!(p->eta_dt > 0.0)) return "eta_dt must be > 0";
   if (p->split_leaves < 0) return "split_leaves must be >= 0";
   if (p->max_members < 1 || p->max_members > kMaxMembers) return "max_members must be in [1, 65535]";
+  if (p->grav_corr_literal != 0 && p->grav_corr_literal != 1) return "grav_corr_literal must be 0 or 1";
+  if (p->soften_cells != 0 && p->soften_cells != 1) return "soften_cells must be 0 or 1";
+  if (p->visc_form != TSPH_VISC_MG && p->visc_form != TSPH_VISC_SIGNAL) return "unknown visc_form";
+  if (p->entropy != 0 && p->entropy != 1) return "entropy must be 0 or 1";
+  if (!(p->xsph_eta >= 0.0 && p->xsph_eta <= 1.0)) return "xsph_eta must be in [0, 1]";
+  if (p->h_scheme != TSPH_H_LAGRANGIAN && p->h_scheme != TSPH_H_STANDARD) return "unknown h_scheme";
+  if (p->h_weight != TSPH_HW_NUMBER && p->h_weight != TSPH_HW_MASS) return "unknown h_weight";
+  if (p->h_weight == TSPH_HW_MASS && p->h_scheme != TSPH_H_LAGRANGIAN)
+    return "the mass-density relation is taken with the Lagrangian scheme only";
   return nullptr;
 }
 
@@ -82,7 +91,7 @@ size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->add(4 * N);        // 16 gflag
   L->add(sizeof(GravRec) * N);  // grec
   L->add(sizeof(SphRec) * N);   // srec
-  L->add(8 * 2 * N);            // pdiv
+  L->add(8 * kCarryRows * N);   // pdiv: the carry to the next drift
   // nodes
   L->add(sizeof(NodeTopo) * M);  // 17 topo
   L->add(4 * M);        // 18 nlevel
@@ -90,6 +99,7 @@ size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->add(4 * M);        // 20 nngas
   L->add(sizeof(NodeFar) * M);   // 21 nfar
   L->add(sizeof(NodeBox) * M);   // 22 nbox
+  L->add(16 * M);                // nsoft
   L->add(8 * 8 * M);    // 23 ctmp
   L->add(4 * M);        // 24 ctmpn
   L->add(4 * M);        // 25 cscan
@@ -289,6 +299,7 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->nngas = AT(int32_t *);
   c->nfar = AT(NodeFar *);
   c->nbox = AT(NodeBox *);
+  c->nsoft = AT(double2 *);
   c->ctmp = AT(int2 *);
   c->ctmpn = AT(int32_t *);
   c->cscan = AT(int32_t *);
@@ -500,7 +511,7 @@ static tsph_status kick_drift_checks(Ctx *c, tsph_state *s, int32_t phase) {
 
 tsph_status tsph_carry_bytes(int64_t n, size_t *bytes) {
   if (!bytes || n < 1) return TSPH_EINVAL;
-  *bytes = sizeof(double) * (2 * (size_t)n + 1);
+  *bytes = sizeof(double) * (kCarryRows * (size_t)n + 1);
   return TSPH_OK;
 }
 
@@ -513,8 +524,9 @@ tsph_status tsph_carry_save(void *ctx, int64_t n, void *dst_device, void *stream
   hipStream_t st = (hipStream_t)stream;
   double *d = (double *)dst_device;
   TSPH_HIP_CHECK(c, hipMemcpyAsync(d, c->dt, sizeof(double), hipMemcpyDeviceToDevice, st));
-  TSPH_HIP_CHECK(c, hipMemcpyAsync(d + 1, c->pdiv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-  TSPH_HIP_CHECK(c, hipMemcpyAsync(d + 1 + n, c->pdiv + c->cap_n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  for (int k = 0; k < kCarryRows; k++)
+    TSPH_HIP_CHECK(c, hipMemcpyAsync(d + 1 + k * n, c->pdiv + k * c->cap_n, sizeof(double) * n,
+                                     hipMemcpyDeviceToDevice, st));
   return TSPH_OK;
 }
 
@@ -527,8 +539,9 @@ tsph_status tsph_carry_load(void *ctx, int64_t n, const void *src_device, void *
   hipStream_t st = (hipStream_t)stream;
   const double *d = (const double *)src_device;
   TSPH_HIP_CHECK(c, hipMemcpyAsync(c->dt, d, sizeof(double), hipMemcpyDeviceToDevice, st));
-  TSPH_HIP_CHECK(c, hipMemcpyAsync(c->pdiv, d + 1, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-  TSPH_HIP_CHECK(c, hipMemcpyAsync(c->pdiv + c->cap_n, d + 1 + n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  for (int k = 0; k < kCarryRows; k++)
+    TSPH_HIP_CHECK(c, hipMemcpyAsync(c->pdiv + k * c->cap_n, d + 1 + k * n, sizeof(double) * n,
+                                     hipMemcpyDeviceToDevice, st));
   c->pdiv_n = n;
   return TSPH_OK;
 }
@@ -553,6 +566,21 @@ tsph_status tsph_kick_drift(void *ctx, tsph_state *s, double dt, int32_t phase, 
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
   return tsph_impl_kick_drift(c, s, dt, nullptr, phase, st);
+}
+
+tsph_status tsph_batch_step(void *ctx, tsph_state *s, double *dt_device, void *stream) {
+  Ctx *c = (Ctx *)ctx;
+  if (!c) return TSPH_EINVAL;
+  if (!dt_device) return set_err(c, TSPH_EINVAL, "dt_device is NULL");
+  tsph_status r = check_state(c, s, true);
+  if (r != TSPH_OK) return r;
+  if ((r = kick_drift_checks(c, s, TSPH_KD_FIRST)) != TSPH_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  if ((r = tsph_impl_timestep(c, dt_device, st)) != TSPH_OK) return r;
+  if ((r = tsph_impl_kick_drift(c, s, 0.0, dt_device, TSPH_KD_FIRST, st)) != TSPH_OK) return r;
+  if ((r = tsph_compute_forces(ctx, s, stream)) != TSPH_OK) return r;
+  return tsph_impl_kick_drift(c, s, 0.0, dt_device, TSPH_KD_SECOND, st);
 }
 
 tsph_status tsph_timestep(void *ctx, const tsph_state *s, double *dt_device, void *stream) {

@@ -65,6 +65,11 @@ struct DensArgs {
   int32_t split_leaves;  // hand off batches with more candidate leaves
   double eta_h, eta_eps, kappa, h_tol, gamma;
   int32_t maxit, soft_mode, hydro, gravity, shared;
+  int32_t corr_lit;  // d phi / d eps summed without masses (the printed Eq. zeta)
+  int32_t hmass;     // h from the mass density: a gas neighbour counts m_j / m_i
+  int32_t hstd;      // standard scheme: h from a fixed neighbour count nstd
+  int32_t nstd;
+  int32_t entropy;   // vu.w holds the entropic function A = P / rho^gamma
 };
 
 struct Sums {
@@ -192,7 +197,7 @@ __device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, 
     if (kFull) {
       s.rho += a.w * W;
       s.msdh += a.w * dWdh;
-      if (want_phi) s.mdphi += a.w * soft_pe_q(qq, ih);
+      if (want_phi) s.mdphi += (A.corr_lit ? 1.0 : a.w) * soft_pe_q(qq, ih);
       if (want_div && r > 0.0) {
         const double4 v = T.vu[j];
         const double g = dw * ih4 * ir;  // dW/dr / r
@@ -350,7 +355,7 @@ __device__ __forceinline__ bool hand_off(const DensArgs &A, int g, const Cands &
 __device__ SolveOut solve_length(const DensArgs &A, int g, int root, const NodeBox &gb, bool sink, bool gas_only, double eta,
                                  double guess, double px, double py, double pz, double4 vp, bool want_div,
                                  bool want_phi, int *s_stack, int *s_leaf, DensTile &T, double4 *s_snk, bool cold,
-                                 int32_t *dbg_row) {
+                                 int32_t *dbg_row, double imi = 0.0) {
   SolveOut o;
   o.handed = false;
   const double eta3 = eta * eta * eta;
@@ -401,7 +406,8 @@ __device__ SolveOut solve_length(const DensArgs &A, int g, int root, const NodeB
       ndbg_max = max(ndbg_max, ndbg);
       if (!solvable) {
         done = true;
-      } else if (newton_update(h, lo, hi, dx_old, s.n, s.sdh, eta3, A.h_tol)) {
+      } else if (newton_update(h, lo, hi, dx_old, imi > 0.0 ? s.rho * imi : s.n, imi > 0.0 ? s.msdh * imi : s.sdh,
+                               eta3, A.h_tol)) {
         done = true;
         ok = true;
       }
@@ -416,6 +422,163 @@ __device__ SolveOut solve_length(const DensArgs &A, int g, int root, const NodeB
   o.h = h_keep;
   o.ok = ok && !fail;
   o.s = keep;
+  return o;
+}
+
+// ---- standard scheme (Sect. 3): h from a fixed number nstd of gas
+// neighbours, the sink included, instead of the kernel-weighted relation.
+// Bisection on h over the count of gas candidates inside 2h.  The count is
+// reached at the first distance shell (candidates at one distance) whose
+// cumulative count is at least nstd, and 2h is put midway between that
+// shell's distance and the next larger distance, so that the shell is
+// taken whole.  A pass gives, per lane, the count inside 2h, the largest
+// squared distance inside with the count at it, and the smallest squared
+// distance outside within the gathered radius.
+struct CountOut {
+  double c, r2in, cin, r2out;
+};
+
+__device__ __forceinline__ void tile_count(const DensTile &T, int nt, double px, double py, double pz, double R2,
+                                           CountOut &k) {
+  for (int j = 0; j < nt; j++) {
+    const double4 a = T.pm[j];
+    const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);  // non-gas: at infinity
+    if (r2 < R2) {
+      k.c += 1.0;
+      if (r2 > k.r2in) {
+        k.r2in = r2;
+        k.cin = 1.0;
+      } else if (r2 == k.r2in) {
+        k.cin += 1.0;
+      }
+    } else if (r2 < k.r2out) {
+      k.r2out = r2;
+    }
+  }
+}
+
+__device__ void leaf_count(const DensArgs &A, int nleaf, const int *s_leaf, DensTile &T, double px, double py,
+                           double pz, double R2, CountOut &k) {
+  const int ln = lane();
+  int fill = 0, rq = 0;
+  for (int c1 = 0; c1 < nleaf; c1 += kWave) {
+    const int nc = min(kWave, nleaf - c1);
+    const NodeTopo my = ln < nc ? A.topo[s_leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
+    for (int j = 0; j < nc; j++) {
+      const int first = __builtin_amdgcn_readlane(my.first, j);
+      const int count = __builtin_amdgcn_readlane(my.count, j);
+      for (int off = 0; off < count;) {
+        const int tk = min(count - off, kWave - fill);
+        if (ln >= fill && ln < fill + tk) rq = first + off + (ln - fill);
+        fill += tk;
+        off += tk;
+        if (fill == kWave) {
+          stage_tile(A, T, kWave, rq, true, false);
+          tile_count(T, kWave, px, py, pz, R2, k);
+          __syncthreads();
+          fill = 0;
+        }
+      }
+    }
+  }
+  if (fill > 0) {
+    stage_tile(A, T, fill, rq, true, false);
+    tile_count(T, fill, px, py, pz, R2, k);
+    __syncthreads();
+  }
+}
+
+__device__ SolveOut solve_count(const DensArgs &A, int root, const NodeBox &gb, bool sink, double guess, double px,
+                                double py, double pz, double4 vp, int *s_stack, int *s_leaf, DensTile &T,
+                                double4 *s_snk, int32_t *dbg_row) {
+  SolveOut o;
+  o.handed = false;
+  o.s = Sums{0, 0, 0, 0, 0, 0};
+  const bool solvable = sink && A.nngas[root] > A.nstd && guess > 0.0;
+  // the iteration runs on the squared radius R2 = (2h)^2 of the count: a
+  // bracket [lo2, hi2] on the crossing shell's squared distance, bisection
+  // while it makes progress, otherwise a step to the next shell (shells a
+  // rounding apart are then still separated)
+  double R2 = 4.0 * (guess > 0.0 ? guess * guess : 1.0), lo2 = 0.0, hi2 = INFINITY, h = 0.5 * sqrt(R2);
+  double rc = h * (1.0 + A.kappa);
+  bool done = !sink, ok = false, gathered = false, fail = false, grow = false;
+  Cands c{0, true, 0.0, true};
+  const double N = (double)A.nstd;
+  const int maxit = A.maxit > 400 ? A.maxit : 400;
+  for (int it = 0; it < maxit && __any(!done); it++) {
+    bool need = !gathered || grow;
+    grow = false;
+    if (!done && sqrt(R2) > 2.0 * rc) {
+      rc = 0.5 * sqrt(R2) * (1.0 + A.kappa);
+      need = true;
+    }
+    if (__any(need)) {
+      const double R = wave_max(done ? 0.0 : 2.0 * rc);
+      s_snk[lane()] = make_double4(px, py, pz, done ? 0.0 : 2.0 * rc);
+      __syncthreads();
+      c = gather(A, root, gb, R, true, s_stack, s_leaf, s_snk, fail);
+      gathered = true;
+      if (fail) break;
+    }
+    CountOut k{0.0, -1.0, 0.0, INFINITY};
+    if (c.cached) {
+      leaf_count(A, c.nleaf, s_leaf, T, px, py, pz, R2, k);
+    } else {
+      const bool wok = walk_leaves(A, root, gb, c.R, true, s_stack, s_leaf, s_snk, kWave, [&](int nl, bool) {
+        leaf_count(A, nl, s_leaf, T, px, py, pz, R2, k);
+        return true;
+      });
+      if (!wok) {
+        fail = true;
+        break;
+      }
+    }
+    if (done) continue;
+    if (!solvable) {
+      done = true;
+    } else if (k.c >= N && k.c - k.cin < N) {
+      // the crossing shell is the outermost one inside
+      if (k.r2out < INFINITY) {
+        h = 0.25 * (sqrt(k.r2in) + sqrt(k.r2out));
+        done = true;
+        ok = true;
+      } else {
+        rc *= 2.0;  // the next distance lies beyond the gathered radius
+        grow = true;
+      }
+    } else if (k.c < N) {
+      // the crossing shell lies at or beyond the nearest distance outside
+      lo2 = k.r2out < INFINITY ? k.r2out : R2;
+      if (isinf(hi2)) {
+        R2 = 4.0 * R2;
+        if (k.r2out < INFINITY && R2 <= k.r2out) R2 = nextafter(k.r2out, INFINITY);
+      } else {
+        const double mid = 0.5 * (lo2 + hi2);
+        R2 = (mid > lo2 && mid < hi2) ? mid : nextafter(lo2, INFINITY);
+      }
+    } else {
+      // too many: the crossing shell lies below the largest distance inside
+      hi2 = k.r2in;
+      const double mid = 0.5 * (lo2 + hi2);
+      R2 = (mid > lo2 && mid < hi2) ? mid : hi2;
+    }
+  }
+  // the sums at the final lengths, over candidates gathered again for every
+  // sink (lanes that finished early dropped out of the last gathers); each
+  // final 2h lies below a distance found inside that lane's radius 2 rc
+  if (!fail) {
+    const double rad = sink ? 2.0 * rc : 0.0;
+    const double R = wave_max(rad);
+    s_snk[lane()] = make_double4(px, py, pz, rad);
+    __syncthreads();
+    c = gather(A, root, gb, R, true, s_stack, s_leaf, s_snk, fail);
+  }
+  int ndbg = 0;
+  if (!fail)
+    o.s = pass<true>(A, root, gb, c, s_stack, s_leaf, T, s_snk, px, py, pz, vp, h, true, false, dbg_row, ndbg, fail);
+  if (dbg_row && ndbg > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
+  o.h = h;
+  o.ok = ok && !fail;
   return o;
 }
 
@@ -453,13 +616,16 @@ __device__ __forceinline__ void solver_init(Solver &v, const DensArgs &A, int ro
 }
 
 // one evaluation's sums into the solver
-__device__ __forceinline__ void solver_update(Solver &v, const DensArgs &A, const Sums5 &s, double eta) {
+// imi > 0: the mass-density relation (a neighbour counts m_j / m_i, 1/m_i = imi)
+__device__ __forceinline__ void solver_update(Solver &v, const DensArgs &A, const Sums5 &s, double eta,
+                                              double imi = 0.0) {
   if (v.done) return;
   v.keep = s;
   v.h_keep = v.h;
   if (!v.solvable) {
     v.done = true;
-  } else if (newton_update(v.h, v.lo, v.hi, v.dx_old, s.n, s.sdh, eta * eta * eta, A.h_tol)) {
+  } else if (newton_update(v.h, v.lo, v.hi, v.dx_old, imi > 0.0 ? s.rho * imi : s.n,
+                           imi > 0.0 ? s.msdh * imi : s.sdh, eta * eta * eta, A.h_tol)) {
     v.done = true;
     v.ok = true;
   }
@@ -519,7 +685,7 @@ __device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T,
       const double W = w * ihe3;
       se.n += W;
       se.sdh += -(3.0 * w + qq * dw) * ihe4;
-      se.rho += a.w * soft_pe_q(qq, ihe);  // mass-weighted d phi / d eps
+      se.rho += (A.corr_lit ? 1.0 : a.w) * soft_pe_q(qq, ihe);  // mass-weighted d phi / d eps
       if (r > 0.0) se.divv += dw * ihe4 * ir * dot;
     }
   }
@@ -582,7 +748,7 @@ struct BothOut {
 __device__ BothOut solve_both(const DensArgs &A, int g, int root, const NodeBox &gb, bool act, bool is_gas, double guess_h,
                               bool cold_h, double guess_e, bool cold_e, double px, double py, double pz,
                               const double4 &vp, int *s_stack, int *s_leaf, DensTile &T, double4 *s_snk,
-                              int32_t *dbg_row) {
+                              int32_t *dbg_row, double imi) {
   BothOut o;
   o.handed = false;
   Solver H, E;
@@ -633,7 +799,7 @@ __device__ BothOut solve_both(const DensArgs &A, int g, int root, const NodeBox 
       ndbg_keep = ndbg;
       ndbg_max = max(ndbg_max, ndbg);
     }
-    solver_update(H, A, sh, A.eta_h);
+    solver_update(H, A, sh, A.eta_h, imi);
     solver_update(E, A, se, A.eta_eps);
   }
   if (dbg_row) {
@@ -665,15 +831,34 @@ __device__ __forceinline__ double cold_guess(const DensArgs &A, int p, bool gas_
 __device__ __forceinline__ void store_outputs(const DensArgs &A, int p, bool is_gas, const double4 &a,
                                               const double4 &vp, double h_gas, const Sums &sh, double eps,
                                               double neps, double ups, double xi, double divve) {
-  double h = 0.0, rho = 0.0, omega = 0.0, zeta = 0.0, divv = 0.0, c = 0.0, pr2 = 0.0;
+  double h = 0.0, rho = 0.0, omega = 0.0, zeta = 0.0, divv = 0.0, c = 0.0, pr2 = 0.0, fa = 1.0;
   if (is_gas) {
     h = h_gas;
     rho = sh.rho;
-    omega = 1.0 + (h / (3.0 * sh.n)) * sh.sdh;
-    zeta = -(h / (3.0 * sh.n)) * sh.msdh;
+    // grad-h factor f_ij = fa_i + zeta_i / (m_j Omega*_i): the number-density
+    // relation's Omega*, zeta (fa = 1); the mass-density relation's 1/Omega
+    // (zeta = 0); none in the standard scheme
+    if (A.hstd) {
+      omega = 1.0;
+      zeta = 0.0;
+    } else if (A.hmass) {
+      omega = 1.0 + (h / (3.0 * rho)) * sh.msdh;
+      zeta = 0.0;
+      fa = 1.0 / omega;
+    } else {
+      omega = 1.0 + (h / (3.0 * sh.n)) * sh.sdh;
+      zeta = -(h / (3.0 * sh.n)) * sh.msdh;
+    }
     divv = -sh.divv / (sh.n * omega);
-    c = sqrt(A.gamma * (A.gamma - 1.0) * vp.w);
-    pr2 = (A.gamma - 1.0) * vp.w / rho;  // P / rho^2 with P = (gamma - 1) rho u
+    if (A.entropy) {
+      // the energy variable is A: P = A rho^gamma, c^2 = gamma A rho^(gamma - 1)
+      const double P = vp.w * pow(rho, A.gamma);
+      c = sqrt(A.gamma * vp.w * pow(rho, A.gamma - 1.0));
+      pr2 = P / (rho * rho);
+    } else {
+      c = sqrt(A.gamma * (A.gamma - 1.0) * vp.w);
+      pr2 = (A.gamma - 1.0) * vp.w / rho;  // P / rho^2 with P = (gamma - 1) rho u
+    }
   }
   A.hs[p] = h;
   A.es[p] = eps;
@@ -692,7 +877,7 @@ __device__ __forceinline__ void store_outputs(const DensArgs &A, int p, bool is_
     sr.x = a.x; sr.y = a.y; sr.z = a.z; sr.m = a.w;
     sr.vx = vp.x; sr.vy = vp.y; sr.vz = vp.z; sr.im = 1.0 / a.w;
     sr.h = h; sr.ih = 1.0 / h; sr.rho = rho; sr.c = c;
-    sr.pr2 = pr2; sr.zo = zo; sr.pad0 = 0.0; sr.pad1 = 0.0;
+    sr.pr2 = pr2; sr.zo = zo; sr.fa = fa; sr.pad1 = 0.0;
     A.srec[p] = sr;
   }
   double *S = A.solve;
@@ -750,7 +935,8 @@ __global__ __launch_bounds__(64, 3) void k_density(DensArgs A) {
         const double guess_h = gh > 0.0 ? gh : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
         const double guess_e = ge > 0.0 ? ge : (act ? cold_guess(A, p, false, A.eta_eps) : 0.0);
         const BothOut b = solve_both(A, g, bt.root, gb, act, is_gas, guess_h, !(gh > 0.0), guess_e, !(ge > 0.0), a.x, a.y,
-                                     a.z, vp, s_stack, s_leaf, s_dt, s_snk, is_gas ? dbg0 : nullptr);
+                                     a.z, vp, s_stack, s_leaf, s_dt, s_snk, is_gas ? dbg0 : nullptr,
+                                     A.hmass ? 1.0 / a.w : 0.0);
         handed = b.handed;
         oh = b.h;
         oe_f = b.e;
@@ -761,8 +947,13 @@ __global__ __launch_bounds__(64, 3) void k_density(DensArgs A) {
       } else if (A.hydro) {  // (not kFused)
         double g0 = A.hs[p];
         double guess = g0 > 0.0 ? g0 : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
-        oh = solve_length(A, g, bt.root, gb, is_gas, true, A.eta_h, guess, a.x, a.y, a.z, vp, true, A.shared != 0,
-                          s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0), is_gas ? dbg0 : nullptr);
+        if (A.hstd)
+          oh = solve_count(A, bt.root, gb, is_gas, guess, a.x, a.y, a.z, vp, s_stack, s_leaf, s_dt, s_snk,
+                           is_gas ? dbg0 : nullptr);
+        else
+          oh = solve_length(A, g, bt.root, gb, is_gas, true, A.eta_h, guess, a.x, a.y, a.z, vp, true, A.shared != 0,
+                            s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0), is_gas ? dbg0 : nullptr,
+                            A.hmass ? 1.0 / a.w : 0.0);
         handed = oh.handed;
         if (is_gas && !oh.ok && !handed) nnoconv++;
       }
@@ -824,7 +1015,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // skip: filtered out) to the sums of the sink at (px, py, pz).
 __device__ __forceinline__ void add_candidate(const double4 &a, const double4 &v, bool skip, double px, double py,
                                               double pz, const double4 &vp, double ih, double ih3, double ih4,
-                                              double R2, bool want_div, bool want_phi, Sums &s) {
+                                              double R2, bool want_div, bool want_phi, bool lit, Sums &s) {
   if (skip) return;
   const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
   if (!(r2 < R2)) return;
@@ -839,7 +1030,7 @@ __device__ __forceinline__ void add_candidate(const double4 &a, const double4 &v
   s.sdh += dWdh;
   s.rho += a.w * W;
   s.msdh += a.w * dWdh;
-  if (want_phi) s.mdphi += a.w * soft_pe_q(qq, ih);
+  if (want_phi) s.mdphi += (lit ? 1.0 : a.w) * soft_pe_q(qq, ih);
   if (want_div && r > 0.0) {
     const double g = dw * ih4 * ir;
     s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
@@ -896,10 +1087,10 @@ __device__ __forceinline__ void sink_leaf_sums(const DensArgs &A, int nleaf, con
             const CandLoad c1 = load_candidate(A, q1, gas_only, want_div);
             const CandLoad c2 = load_candidate(A, q2, gas_only, want_div);
             const CandLoad c3 = load_candidate(A, rq, gas_only, want_div);
-            add_candidate(c0.a, c0.v, c0.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
-            add_candidate(c1.a, c1.v, c1.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
-            add_candidate(c2.a, c2.v, c2.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
-            add_candidate(c3.a, c3.v, c3.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+            add_candidate(c0.a, c0.v, c0.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
+            add_candidate(c1.a, c1.v, c1.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
+            add_candidate(c2.a, c2.v, c2.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
+            add_candidate(c3.a, c3.v, c3.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
             nr = 0;
           }
         }
@@ -909,19 +1100,19 @@ __device__ __forceinline__ void sink_leaf_sums(const DensArgs &A, int nleaf, con
   // pending full rounds, in order, then the partial round
   if (nr > 0) {
     const CandLoad c = load_candidate(A, q0, gas_only, want_div);
-    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
   }
   if (nr > 1) {
     const CandLoad c = load_candidate(A, q1, gas_only, want_div);
-    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
   }
   if (nr > 2) {
     const CandLoad c = load_candidate(A, q2, gas_only, want_div);
-    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
   }
   if (ln < fill) {
     const CandLoad c = load_candidate(A, rq, gas_only, want_div);
-    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, s);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
   }
 }
 
@@ -975,7 +1166,9 @@ __device__ __forceinline__ SolveOut solve_one(const DensArgs &A, int root, bool 
     keep = s;
     h_keep = h;
     if (!solvable) break;
-    if (newton_update(h, lo, hi, dx_old, s.n, s.sdh, eta3, A.h_tol)) {
+    // the mass-density relation counts a gas neighbour m_j / m_i
+    const bool mw = gas_only && A.hmass;
+    if (newton_update(h, lo, hi, dx_old, mw ? s.rho / a.w : s.n, mw ? s.msdh / a.w : s.sdh, eta3, A.h_tol)) {
       ok = true;
       break;
     }
@@ -993,7 +1186,7 @@ __device__ __forceinline__ SolveOut solve_one(const DensArgs &A, int root, bool 
 // softening length's mass-weighted d phi / d eps kept in the rho slot.
 __device__ __forceinline__ void add_candidate2(const CandLoad &c, double px, double py, double pz, const double4 &vp,
                                                double R2h, double ih, double ih3, double ih4, double R2e, double ie,
-                                               double ie3, double ie4, Sums5 &sh, Sums5 &se) {
+                                               double ie3, double ie4, bool lit, Sums5 &sh, Sums5 &se) {
   const double4 &a = c.a, &v = c.v;
   const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
   const bool in_h = !c.skip && r2 < R2h;
@@ -1020,7 +1213,7 @@ __device__ __forceinline__ void add_candidate2(const CandLoad &c, double px, dou
     m4(qq, w, dw);
     se.n += w * ie3;
     se.sdh += -(3.0 * w + qq * dw) * ie4;
-    se.rho += a.w * soft_pe_q(qq, ie);
+    se.rho += (lit ? 1.0 : a.w) * soft_pe_q(qq, ie);
     if (r > 0.0) se.divv += dw * ie4 * ir * dot;
   }
 }
@@ -1059,8 +1252,8 @@ __device__ __forceinline__ void sink_leaf_sums2(const DensArgs &A, int nleaf, co
           } else {
             const CandLoad c0 = load_candidate(A, q0, true, true);
             const CandLoad c1 = load_candidate(A, rq, true, true);
-            add_candidate2(c0, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, sh, se);
-            add_candidate2(c1, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, sh, se);
+            add_candidate2(c0, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se);
+            add_candidate2(c1, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se);
             pending = false;
           }
         }
@@ -1069,11 +1262,11 @@ __device__ __forceinline__ void sink_leaf_sums2(const DensArgs &A, int nleaf, co
   }
   if (pending) {
     const CandLoad c = load_candidate(A, q0, true, true);
-    add_candidate2(c, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, sh, se);
+    add_candidate2(c, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se);
   }
   if (ln < fill) {
     const CandLoad c = load_candidate(A, rq, true, true);
-    add_candidate2(c, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, sh, se);
+    add_candidate2(c, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se);
   }
 }
 
@@ -1129,7 +1322,7 @@ __device__ __forceinline__ BothOut solve_one_both(const DensArgs &A, int root, d
         break;
       }
     }
-    solver_update(H, A, wave_sum5(sh), A.eta_h);
+    solver_update(H, A, wave_sum5(sh), A.eta_h, A.hmass ? 1.0 / a.w : 0.0);
     solver_update(E, A, wave_sum5(se), A.eta_eps);
   }
   o.h.h = H.h_keep;
@@ -1300,19 +1493,26 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
   A.gamma = c->p.gamma;
   A.maxit = c->p.h_maxit;
   A.soft_mode = c->p.soft_mode;
+  A.corr_lit = c->p.grav_corr_literal;
+  A.hmass = c->p.h_weight == TSPH_HW_MASS;
+  A.hstd = c->p.h_scheme == TSPH_H_STANDARD;
+  A.nstd = (int32_t)llround(4.0 / 3.0 * 3.14159265358979323846 * pow(2.0 * c->p.eta_h, 3.0));
+  A.entropy = c->p.entropy;
   A.hydro = c->p.hydro && c->n_gas > 0;
   A.gravity = c->p.gravity;
+  // one shared length when the two solves are the same equation (pure gas,
+  // equal eta, the number-density relation of the Lagrangian scheme)
   A.shared = (A.hydro && A.gravity && c->n_gas == c->n && c->p.eta_h == c->p.eta_eps &&
-              c->p.soft_mode != TSPH_SOFT_CONSTANT)
+              c->p.soft_mode != TSPH_SOFT_CONSTANT && !A.hmass && !A.hstd)
                  ? 1
                  : 0;
   A.heavy = c->heavy;
   A.heavy_key = c->heavy + c->heavy_cap;
   A.heavy_ord = c->heavy + 2 * c->heavy_cap;
   // debug lists are written by the batch's own wave
-  A.heavy_cap = (c->dbg_nbr || c->p.split_leaves == 0) ? 0 : (int32_t)c->heavy_cap;
+  A.heavy_cap = (c->dbg_nbr || c->p.split_leaves == 0 || A.hstd) ? 0 : (int32_t)c->heavy_cap;
   A.split_leaves = c->p.split_leaves;
-  const bool fused = A.hydro && A.gravity && !A.shared && A.soft_mode != TSPH_SOFT_CONSTANT;
+  const bool fused = A.hydro && A.gravity && !A.shared && A.soft_mode != TSPH_SOFT_CONSTANT && !A.hstd;
   void (*kd)(DensArgs) = fused ? k_density<true> : k_density<false>;
   hipLaunchKernelGGL(kd, dim3(persistent_blocks(c, (const void *)kd)), dim3(64), 0, st, A);
   if (A.heavy_cap > 0) {

@@ -53,8 +53,11 @@ struct GravArgs {
   uint32_t *flags;
   int32_t *dbg;
   int32_t dbg_max;
+  const double2 *nsoft;  // softened cells: per node sum of m eps, sum of m xi/Upsilon
   double G;
   int32_t quadrupole, corr, want_pot;
+  int32_t lit;     // correction terms with the printed mass weighting
+  int32_t soften;  // softened cells
   // near-field hand-off (0 split_particles: none)
   int32_t split_particles;
   int64_t split_cap;
@@ -129,7 +132,10 @@ __device__ __forceinline__ void near_pair(const GravArgs &A, Sink &s, const Grav
       const double ii2 = s.ieps * s.ieps, ij2 = b.ieps * b.ieps;
       const double Wi = m4_dw(qi) * (ii2 * ii2) * kInvPiG;
       const double Wj = m4_dw(qj) * (ij2 * ij2) * kInvPiG;
-      F += 0.5 * (s.xiu * Wi + (b.m * s.im) * b.xiu * Wj);
+      if (A.lit)
+        F += 0.5 * b.m * (s.xiu * Wi + b.xiu * Wj);
+      else
+        F += 0.5 * (s.xiu * Wi + (b.m * s.im) * b.xiu * Wj);
     }
     const double fr = A.G * F * ir;
     s.ax -= fr * dx;
@@ -139,6 +145,34 @@ __device__ __forceinline__ void near_pair(const GravArgs &A, Sink &s, const Grav
   } else if (M & kPot) {
     s.pot += A.G * b.m * 0.5 * (-1.4 * s.ieps - 1.4 * b.ieps);
   }
+}
+
+// Softened cell acting on a sink (Sect. 2.2): the node as one particle of
+// mass M at its centre of mass, softened with the mass-weighted mean eps of
+// its particles, through the symmetrised pair; the correction terms of its
+// particles gathered there: the sink's term once per particle (N times; with
+// the printed weighting, M times), theirs as X = sum m xi/Upsilon.  Staged
+// as a GravRec (x, y, z, M, eps, 1/eps, X, N).  The opening test keeps the
+// cell's centre of mass away from every sink of the batch (r > 0).
+template <int M>
+__device__ __forceinline__ void soft_cell(const GravArgs &A, Sink &s, const GravRec &b) {
+  const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ir = rsq64(r2);
+  const double r = r2 * ir;
+  const double qi = r * s.ieps, qj = r * b.ieps;
+  double F = 0.5 * b.m * (soft_fr_q(qi, s.ieps, ir) + soft_fr_q(qj, b.ieps, ir));
+  if (M & kCorr) {
+    const double ii2 = s.ieps * s.ieps, ij2 = b.ieps * b.ieps;
+    const double Wi = m4_dw(qi) * (ii2 * ii2) * kInvPiG;
+    const double Wj = m4_dw(qj) * (ij2 * ij2) * kInvPiG;
+    F += 0.5 * ((A.lit ? b.m : b.s4) * s.xiu * Wi + (A.lit ? 1.0 : s.im) * b.xiu * Wj);
+  }
+  const double fr = A.G * F * ir;
+  s.ax -= fr * dx;
+  s.ay -= fr * dy;
+  s.az -= fr * dz;
+  if (M & kPot) s.pot += A.G * b.m * 0.5 * (soft_ph_q(qi, s.ieps, ir) + soft_ph_q(qj, b.ieps, ir));
 }
 
 __device__ __forceinline__ void debug_pair(const GravArgs &A, Sink &s, const GravRec &b, int q) {
@@ -282,7 +316,7 @@ __device__ __forceinline__ void newton_pair32(Sink32 &s, const RecF32 &b) {
 }
 
 template <int M>
-__device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b) {
+__device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b, bool lit) {
   const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
   const float r2 = dx * dx + dy * dy + dz * dz;
   if (r2 >= max_nonneg(s.s4, b.s4)) {
@@ -298,7 +332,10 @@ __device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b) {
       const float ii2 = s.ieps * s.ieps, ij2 = b.ieps * b.ieps;
       const float Wi = m4_dw(qi) * (ii2 * ii2) * (float)kInvPiG;
       const float Wj = m4_dw(qj) * (ij2 * ij2) * (float)kInvPiG;
-      F += 0.5f * (s.xiu * Wi + (b.m * s.im) * b.xiu * Wj);
+      if (lit)
+        F += 0.5f * b.m * (s.xiu * Wi + b.xiu * Wj);
+      else
+        F += 0.5f * (s.xiu * Wi + (b.m * s.im) * b.xiu * Wj);
     }
     const float fr = F * ir;
     s.tax -= fr * dx;
@@ -310,10 +347,32 @@ __device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b) {
   }
 }
 
+// soft_cell in the FP32 form (RecF32: x, y, z, M, eps, 1/eps, X, N)
+template <int M>
+__device__ __forceinline__ void soft_cell32(Sink32 &s, const RecF32 &b, bool lit) {
+  const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  const float ir = rsq32(r2);
+  const float r = r2 * ir;
+  const float qi = r * s.ieps, qj = r * b.ieps;
+  float F = 0.5f * b.m * (soft_fr_q(qi, s.ieps, ir) + soft_fr_q(qj, b.ieps, ir));
+  if (M & kCorr) {
+    const float ii2 = s.ieps * s.ieps, ij2 = b.ieps * b.ieps;
+    const float Wi = m4_dw(qi) * (ii2 * ii2) * (float)kInvPiG;
+    const float Wj = m4_dw(qj) * (ij2 * ij2) * (float)kInvPiG;
+    F += 0.5f * ((lit ? b.m : b.s4) * s.xiu * Wi + (lit ? 1.0f : s.im) * b.xiu * Wj);
+  }
+  const float fr = F * ir;
+  s.tax -= fr * dx;
+  s.tay -= fr * dy;
+  s.taz -= fr * dz;
+  if (M & kPot) s.tpot += b.m * 0.5f * (soft_ph_q(qi, s.ieps, ir) + soft_ph_q(qj, b.ieps, ir));
+}
+
 // As near_tile: Newtonian pass over the tile, then each lane's own
 // softened pairs.
 template <int M>
-__device__ __forceinline__ void near_tile32(Sink32 &s, const RecF32 *rec, const int *tq, int nt) {
+__device__ __forceinline__ void near_tile32(Sink32 &s, const RecF32 *rec, const int *tq, int nt, bool lit) {
   uint64_t soft = tile_mask(nt, [&](int j) {
     const RecF32 b = rec[j];
     const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
@@ -331,7 +390,7 @@ __device__ __forceinline__ void near_tile32(Sink32 &s, const RecF32 *rec, const 
   while (soft) {
     const int j = __builtin_ctzll(soft);
     soft &= soft - 1;
-    if (tq[j] != s.p) near_pair32<M>(s, rec[j]);
+    if (tq[j] != s.p) near_pair32<M>(s, rec[j], lit);
   }
 }
 
@@ -381,7 +440,7 @@ __device__ __forceinline__ int near_entries(const GravArgs &A, SinkT<F32> &s, co
     }
     __syncthreads();
     if constexpr (F32) {
-      near_tile32<M>(s, T.rec32, tq, nt);
+      near_tile32<M>(s, T.rec32, tq, nt, A.lit != 0);
       carry_tile(s);
     } else {
       near_tile<M>(A, s, T.rec, tq, nt);
@@ -454,12 +513,12 @@ __device__ __forceinline__ void load_sink(const GravArgs &A, SinkT<F32> &s, cons
 // node apart), taken whole as near particles (a leaf, or a node lying within
 // the softening reach of the batch), or opened.
 struct GClass {
-  bool acc, leaf, open;
+  bool acc, leaf, open, scell;
   int child, nchild;
 };
 
 __device__ __forceinline__ GClass classify(const GravArgs &A, const NodeBox &gb, double gemax, int k) {
-  GClass c{false, false, false, -1, 0};
+  GClass c{false, false, false, false, -1, 0};
   if (k < 0) return c;
   const NodeFar f = A.nfar[k];
   const NodeBox b = A.nbox[k];
@@ -472,12 +531,16 @@ __device__ __forceinline__ GClass classify(const GravArgs &A, const NodeBox &gb,
     c2 = c2 + axis_gap_box(gb.loz, gb.hiz, b.loz, b.hiz);
     const double sr = 2.0 * fmax(gemax, b.epsmax);
     c.acc = c2 >= sr * sr;
+    // with softened cells, a node that passes the opening test inside the
+    // softening reach acts as one softened particle
+    c.scell = A.soften && !c.acc;
   }
-  if (!c.acc) {
+  if (!c.acc && !c.scell) {
     const NodeTopo nd = A.topo[k];
     // a node wholly inside the softening reach of the batch is taken whole:
-    // all its particles are near pairs
-    c.leaf = nd.nchild == 0 || box_within(gb, b, 2.0 * gemax);
+    // all its particles are near pairs (unless a descendant may become a
+    // softened cell)
+    c.leaf = nd.nchild == 0 || (!A.soften && box_within(gb, b, 2.0 * gemax));
     c.open = !c.leaf;
     c.child = nd.child;
     c.nchild = nd.nchild;
@@ -490,6 +553,7 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
   __shared__ int s_stack[kGStackCap];
   __shared__ int s_cell[kGListCap];
   __shared__ int s_leaf[kGListCap];
+  __shared__ int s_scell[kGListCap];  // softened cells
   // staging tile: 64 node records (far flush) or 64 particle records (near
   // flush), filled with one vector load per lane and read back as broadcasts
   __shared__ TileT<F32> s_t;
@@ -515,7 +579,7 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
       load_sink<F32>(A, s, gnd, c0, cx, cy, cz, true);
       int near_done = 0;  // near-field particles evaluated by this wave
       int nfar = 0, npair = 0;
-      int sp = 1, ncell = 0, nleaf = 0;
+      int sp = 1, ncell = 0, nleaf = 0, nscell = 0;
       bool overflow = false;
       int rounds = 0;
       const int guard = *A.nnodes + 2;
@@ -542,6 +606,12 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
           m = ballot(c1.acc);
           if (c1.acc) s_cell[ncell + mbcnt(m)] = k1;
           ncell += __popcll(m);
+          m = ballot(c0.scell);
+          if (c0.scell) s_scell[nscell + mbcnt(m)] = k0;
+          nscell += __popcll(m);
+          m = ballot(c1.scell);
+          if (c1.scell) s_scell[nscell + mbcnt(m)] = k1;
+          nscell += __popcll(m);
           m = ballot(c0.leaf);
           if (c0.leaf) s_leaf[nleaf + mbcnt(m)] = k0;
           nleaf += __popcll(m);
@@ -592,6 +662,38 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
           }
           nfar += ncell;
           ncell = 0;
+        }
+        if (nscell >= kGCellFlush || (last && nscell > 0)) {
+          // softened cells, 64 per tile, staged as particle records
+          for (int t0 = 0; t0 < nscell; t0 += kWave) {
+            const int nt = uniform(min(kWave, nscell - t0));
+            if (ln < nt) {
+              const int k = s_scell[t0 + ln];
+              const NodeFar f = A.nfar[k];
+              const double2 ns = A.nsoft[k];
+              const double e = ns.x / f.m;
+              const double cntk = (double)A.topo[k].count;
+              if constexpr (F32) {
+                RecF32 h;
+                h.x = (float)(f.cx - cx); h.y = (float)(f.cy - cy); h.z = (float)(f.cz - cz);
+                h.m = (float)f.m; h.eps = (float)e; h.ieps = (float)(1.0 / e); h.xiu = (float)ns.y;
+                h.s4 = (float)cntk;
+                s_t.rec32[ln] = h;
+              } else {
+                s_t.rec[ln] = GravRec{f.cx, f.cy, f.cz, f.m, e, 1.0 / e, ns.y, cntk};
+              }
+            }
+            __syncthreads();
+            if constexpr (F32) {
+              for (int j = 0; j < nt; j++) soft_cell32<M>(s, s_t.rec32[j], A.lit != 0);
+              carry_tile(s);
+            } else {
+              for (int j = 0; j < nt; j++) soft_cell<M>(A, s, s_t.rec[j]);
+            }
+            __syncthreads();
+          }
+          nfar += nscell;
+          nscell = 0;
         }
         const bool splitting = A.split_particles > 0 && near_done >= A.split_particles;
         if (nleaf >= (splitting ? kGSplitFlush : kGLeafFlush) || (last && nleaf > 0)) {
@@ -813,6 +915,9 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
   A.G = c->p.G;
   A.quadrupole = c->p.quadrupole;
   A.corr = c->p.soft_mode == TSPH_SOFT_ADAPTIVE ? 1 : 0;
+  A.lit = c->p.grav_corr_literal;
+  A.soften = c->p.soften_cells;
+  A.nsoft = c->nsoft;
   A.want_pot = want_pot ? 1 : 0;
   // debug lists are written by the batch's own wave
   A.split_particles = c->dbg_nbr ? 0 : c->p.split_leaves * c->p.leaf_size;

@@ -27,9 +27,9 @@ struct FinishArgs {
   const double *hs, *es, *solve;
   double *dt_i;
   double *ax, *ay, *az, *pot, *dudt, *rho, *h, *eps;
-  double *pdiv;  // 2 x cap_n, caller order
-  double eta_dt, alpha, beta;
-  int32_t hydro;
+  double *pdiv;  // kCarryRows x cap_n, caller order
+  double eta_dt, alpha, beta, gamma, xsph_eta;
+  int32_t hydro, entropy;
 };
 
 __global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
@@ -38,8 +38,12 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
   const int i = A.perm[p];
   const bool g = A.gas[p];
   const double ax = A.acc[p], ay = A.acc[A.cap_n + p], az = A.acc[2 * A.cap_n + p];
-  const double du = g ? A.acc[4 * A.cap_n + p] : 0.0;
   const double4 s = A.sph[p];
+  // with the entropic function as energy variable its rate is the viscous
+  // heating times (gamma - 1) rho^(1 - gamma) (Sect. 3.4, Eq. SPHentr)
+  const double du = !g ? 0.0
+                       : (A.entropy ? (A.gamma - 1.0) * pow(s.y, 1.0 - A.gamma) * A.solve[kDuv * A.cap_n + p]
+                                    : A.acc[4 * A.cap_n + p]);
   A.ax[i] = ax;
   A.ay[i] = ay;
   A.az[i] = az;
@@ -50,6 +54,10 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
   if (A.eps) A.eps[i] = A.es[p];
   A.pdiv[i] = g ? A.solve[kDivv * A.cap_n + p] : 0.0;
   A.pdiv[A.cap_n + i] = A.solve[kDivvE * A.cap_n + p];
+  // X-SPH velocity correction of the next drift (Sect. 3.5, Eq. xsph)
+  A.pdiv[2 * A.cap_n + i] = g ? A.xsph_eta * A.solve[kXsx * A.cap_n + p] : 0.0;
+  A.pdiv[3 * A.cap_n + i] = g ? A.xsph_eta * A.solve[kXsy * A.cap_n + p] : 0.0;
+  A.pdiv[4 * A.cap_n + i] = g ? A.xsph_eta * A.solve[kXsz * A.cap_n + p] : 0.0;
   // time-step criteria (Sect. 4.2): acceleration, Courant, internal energy
   double dt = INFINITY;
   const double amag = sqrt(ax * ax + ay * ay + az * az);
@@ -83,7 +91,7 @@ __global__ __launch_bounds__(256) void k_kick_drift(Members M, double dt, int ph
                                                     const double *__restrict__ dudt, double *vpx, double *vpy,
                                                     double *vpz, double *up, double *h, double *eps,
                                                     const double *__restrict__ pdiv, int64_t cap_n,
-                                                    const double *__restrict__ dt_dev) {
+                                                    const double *__restrict__ dt_dev, int xsph) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= M.n) return;
   const int mem = member_of(M, i);
@@ -104,9 +112,16 @@ __global__ __launch_bounds__(256) void k_kick_drift(Members M, double dt, int ph
     v0 += hdt * a0;
     v1 += hdt * a1;
     v2 += hdt * a2;
-    x[i] += dt * v0;
-    y[i] += dt * v1;
-    z[i] += dt * v2;
+    if (xsph && pdiv && gas) {
+      // X-SPH: the gas drifts with v + dv of the last force pass (Eq. xsph)
+      x[i] += dt * (v0 + pdiv[2 * cap_n + i]);
+      y[i] += dt * (v1 + pdiv[3 * cap_n + i]);
+      z[i] += dt * (v2 + pdiv[4 * cap_n + i]);
+    } else {
+      x[i] += dt * v0;
+      y[i] += dt * v1;
+      z[i] += dt * v2;
+    }
     // lengths along the drift: h n^(1/3) = eta with dn/dt = -n div v gives
     // dh/dt = (h/3) div v (Sect. 2.1); the next solve starts from them
     if (pdiv) {
@@ -176,7 +191,8 @@ __global__ __launch_bounds__(256) void k_diag_partial(Members M, const double *_
                                                       const double *__restrict__ vx, const double *__restrict__ vy,
                                                       const double *__restrict__ vz, const double *__restrict__ m,
                                                       const double *__restrict__ u, const double *__restrict__ pot,
-                                                      double *__restrict__ part) {
+                                                      double *__restrict__ part, const double *__restrict__ rho,
+                                                      double gamma, int entropy) {
   double acc[kNDiag] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int mem = blockIdx.y;
   // member ranges clamped to [0, n): tables the host never read stay in bounds
@@ -187,7 +203,8 @@ __global__ __launch_bounds__(256) void k_diag_partial(Members M, const double *_
        i += (int64_t)gridDim.x * blockDim.x) {
     const double mi = m[i], a = vx[i], b = vy[i], c = vz[i];
     acc[0] += 0.5 * mi * (a * a + b * b + c * c);
-    if (i < gas_end && u) acc[1] += mi * u[i];
+    // u = A rho^(gamma - 1) / (gamma - 1) with the entropy variable (Sect. 3.4)
+    if (i < gas_end && u) acc[1] += mi * (entropy ? u[i] * pow(rho[i], gamma - 1.0) / (gamma - 1.0) : u[i]);
     if (pot) acc[2] += 0.5 * mi * pot[i];
     acc[3] += mi * a;
     acc[4] += mi * b;
@@ -256,6 +273,9 @@ tsph_status tsph_impl_finish(Ctx *c, tsph_state *s, hipStream_t st) {
   A.alpha = c->p.alpha;
   A.beta = c->p.beta;
   A.hydro = c->p.hydro;
+  A.gamma = c->p.gamma;
+  A.xsph_eta = c->p.xsph_eta;
+  A.entropy = c->p.entropy;
   hipLaunchKernelGGL(k_finish, dim3(blocks_for(c->n, 256, 1 << 20)), dim3(256), 0, st, A);
   // time-step of each member kept on the device for tsph_timestep
   const Members M = members_of(c, c->n, c->n_gas);
@@ -271,7 +291,7 @@ tsph_status tsph_impl_kick_drift(Ctx *c, tsph_state *s, double dt, const double 
   hipLaunchKernelGGL(k_kick_drift, dim3(blocks_for(s->n, 256, 1 << 20)), dim3(256), 0, st,
                      members_of(c, s->n, s->n_gas), dt, phase, s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->ax, s->ay, s->az, s->dudt, s->vpx,
                      s->vpy, s->vpz, s->up, s->h, s->eps, c->pdiv_n == s->n ? c->pdiv : nullptr, c->cap_n,
-                     dt_dev);
+                     dt_dev, c->p.xsph_eta > 0.0 ? 1 : 0);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }
@@ -283,16 +303,17 @@ tsph_status tsph_impl_timestep(Ctx *c, double *dt_device, hipStream_t st) {
 
 // diagnostics of the systems of M: partial sums per block to part, totals to out
 static hipError_t launch_diagnostics(const Members &M, const tsph_state *s, double *part, double *out,
-                                     hipStream_t st) {
+                                     hipStream_t st, double gamma = 0.0, int entropy = 0) {
   const int rb = M.count > 1 ? kMemberBlocks : kRedBlocks;
   hipLaunchKernelGGL(k_diag_partial, dim3(rb, M.count), dim3(256), 0, st, M, s->x, s->y, s->z, s->vx, s->vy,
-                     s->vz, s->m, s->u, s->pot, part);
+                     s->vz, s->m, s->u, s->pot, part, s->rho, gamma, entropy);
   hipLaunchKernelGGL(k_diag_final, dim3(M.count), dim3(256), 0, st, rb, part, out);
   return hipGetLastError();
 }
 
 tsph_status tsph_impl_diagnostics(Ctx *c, const tsph_state *s, double *out, hipStream_t st) {
-  TSPH_HIP_CHECK(c, launch_diagnostics(members_of(c, s->n, s->n_gas), s, c->red, out, st));
+  if (c->p.entropy && s->n_gas > 0 && !s->rho) return TSPH_EINVAL;
+  TSPH_HIP_CHECK(c, launch_diagnostics(members_of(c, s->n, s->n_gas), s, c->red, out, st, c->p.gamma, c->p.entropy));
   return TSPH_OK;
 }
 

@@ -7,11 +7,20 @@
 // gradient), App. B.  With grad_i W_ij(h) = W'(r, h) (x_i - x_j)/r:
 //   a_i  = -sum_j m_j [A_ij gW(h_i) + A_ji gW(h_j) + Pi_ij Gbar_ij]
 //   du_i =  sum_j m_j [A_ij v_ij . gW(h_i) + 1/2 Pi_ij v_ij . Gbar_ij]
-//   A_ij = (P_i / rho_i^2) f_ij,  f_ij = 1 + zeta_i / (m_j Omega*_i),
+//   A_ij = (P_i / rho_i^2) f_ij,  f_ij = fa_i + zeta_i / (m_j Omega*_i)
+//   (fa = 1 with the number-density relation, 1/Omega with the mass-density
+//   one, and f = 1 in the standard scheme),
 //   Gbar_ij = 1/2 [f_ij gW(h_i) + f_ji gW(h_j)],
 //   Pi_ij = (-alpha cbar mu + beta mu^2) / rhobar  when v_ij . x_ij < 0,
 //   mu = hbar v_ij . x_ij / (r^2 + av_eps2 hbar^2), bars = pair means,
-// evaluated with the predicted velocities and energies.
+// evaluated with the predicted velocities and energies.  Variants: the
+// signal-velocity viscosity Pi_ij = -alpha (2 cbar - w) w / rhobar,
+// w = v_ij . x_ij / r (Sect. 3.3.1, Eqs. pvsig, vsig); the entropic function
+// as energy variable, whose rate is the viscous heating times
+// (gamma - 1) rho^(1 - gamma) (Sect. 3.4, Eq. SPHentr); the X-SPH velocity
+// correction eta sum_j m_j (v_j - v_i) Wbar_ij / rhobar (Sect. 3.5, Eq.
+// xsph).  Every pair also gives the signal velocity 2 cbar - min(w, 0),
+// whose largest value per particle is kept.
 //
 // One wavefront per walk group that holds gas; the wave walks the tree once
 // (opening nodes with gas within 2 max(h_group, h_node) of the group box),
@@ -34,6 +43,7 @@ constexpr int kSStackCap = 1024;
 constexpr int kSListCap = 128;
 constexpr int kSLeafFlush = 32;
 constexpr double kInvPiS = 0.31830988618379067154;
+constexpr int kSphPart = 3;  // partial-sum records per lane of a handed-off item
 
 // candidates of a flush staged for the pair tests
 struct SphTile {
@@ -66,8 +76,8 @@ struct SphArgs {
   uint32_t *flags;
   int32_t *dbg;
   int32_t dbg_max;
-  double alpha, beta, av_eps2;
-  int32_t tc92;
+  double alpha, beta, av_eps2, gamma, xsph_eta;
+  int32_t tc92, visc_signal, entropy;
   // hand-off of flushes (0 split_particles: none); the buffers are those of
   // the gravity walk's near-field hand-off, free again by now
   int32_t split_particles;
@@ -85,7 +95,10 @@ struct SphLane {
   double4 v;   // predicted velocity, u
   double4 hd;  // h, rho, c, P/rho^2
   double zi;   // zeta / Omega*
+  double fa;   // f_ij = fa + zi / m_j
   double ax, ay, az, du, mumax;
+  double duv, vsig;     // viscous heating, largest pair signal velocity
+  double xsx, xsy, xsz; // X-SPH sum (without eta)
   int p, npair, ndbg;
   bool sink;
   int32_t *dbg;
@@ -98,7 +111,9 @@ __device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bo
   L.v = A.vu[p];
   L.hd = A.sph[p];
   L.zi = A.zo[p];
+  L.fa = A.srec[p].fa;
   L.ax = L.ay = L.az = L.du = L.mumax = 0.0;
+  L.duv = L.vsig = L.xsx = L.xsy = L.xsz = 0.0;
   L.npair = 0;
   L.ndbg = 0;
   L.dbg = (A.dbg && sink) ? A.dbg + ((int64_t)1 * A.cap_n + A.perm[p]) * A.dbg_max : nullptr;
@@ -136,24 +151,38 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
     const double gi = m4_grad(r * ihi, tc) * ihi4 * ir;
     const double gj = m4_grad(r * b.ih, tc) * (ihj2 * ihj2 * kInvPiS) * ir;
     const double mj = b.m;
-    const double fij = 1.0 + L.zi * b.im;
-    const double fji = 1.0 + b.zo * imi;
+    const double fij = L.fa + L.zi * b.im;
+    const double fji = b.fa + b.zo * imi;
     const double Ai = L.hd.w * fij;
     const double Aj = b.pr2 * fji;
     const double vx = L.v.x - b.vx, vy = L.v.y - b.vy, vz = L.v.z - b.vz;
     const double vd = vx * dx + vy * dy + vz * dz;
     double sf = mj * (Ai * gi + Aj * gj);
     double e = mj * Ai * gi * vd;
+    const double cb = 0.5 * (L.hd.z + b.c);
+    const double rb = 0.5 * (L.hd.y + b.rho);
+    const double w = vd * ir;  // v_ij . x_ij / r
     if (vd < 0.0) {
       const double hb = 0.5 * (hi + b.h);
       const double mu = hb * vd / (r2 + A.av_eps2 * hb * hb);
-      const double cb = 0.5 * (L.hd.z + b.c);
-      const double rb = 0.5 * (L.hd.y + b.rho);
-      const double Pi = (-A.alpha * cb * mu + A.beta * mu * mu) / rb;
+      const double Pi = A.visc_signal ? -A.alpha * (2.0 * cb - w) * w / rb
+                                      : (-A.alpha * cb * mu + A.beta * mu * mu) / rb;
       const double Gb = 0.5 * (fij * gi + fji * gj);
       sf += mj * Pi * Gb;
-      e += 0.5 * mj * Pi * Gb * vd;
+      const double ev = 0.5 * mj * Pi * Gb * vd;
+      e += ev;
+      L.duv += ev;
       L.mumax = fmax(L.mumax, fabs(mu));
+    }
+    L.vsig = fmax(L.vsig, 2.0 * cb - fmin(w, 0.0));
+    if (A.xsph_eta > 0.0) {
+      double wi, dwi, wj, dwj;
+      m4(r * ihi, wi, dwi);
+      m4(r * b.ih, wj, dwj);
+      const double wb = 0.5 * (wi * (ihi * ihi * ihi) + wj * (b.ih * b.ih * b.ih)) * kInvPiS / rb;
+      L.xsx -= mj * vx * wb;
+      L.xsy -= mj * vy * wb;
+      L.xsz -= mj * vz * wb;
     }
     L.ax -= sf * dx;
     L.ay -= sf * dy;
@@ -340,6 +369,11 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
         A.acc[2 * A.cap_n + p] += L.az;
         A.acc[4 * A.cap_n + p] = L.du;
         A.solve[kMaxmu * A.cap_n + p] = L.mumax;
+        A.solve[kVsig * A.cap_n + p] = L.vsig;
+        A.solve[kDuv * A.cap_n + p] = L.duv;
+        A.solve[kXsx * A.cap_n + p] = L.xsx;
+        A.solve[kXsy * A.cap_n + p] = L.xsy;
+        A.solve[kXsz * A.cap_n + p] = L.xsz;
         A.cnt[2 * A.cap_n + A.perm[p]] = L.npair;
       }
     }
@@ -347,7 +381,7 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
 }
 
 // The handed-off flushes: each item's ranges on the sinks of its batch
-// chunk; per-lane partial sums to split_part (two records per lane).
+// chunk; per-lane partial sums to split_part (kSphPart records per lane).
 __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
   __shared__ int2 s_rng[kSplitItemRanges];
   __shared__ SphTile s_t;
@@ -371,8 +405,10 @@ __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
     for (int a = ln; a < I.count; a += kWave) s_rng[a] = A.split_rng[I.start + a];
     __syncthreads();
     sph_ranges(A, L, s_t, SphRangeSrc{s_rng}, I.count, tc);
-    A.split_part[(int64_t)(2 * it) * kWave + ln] = make_double4(L.ax, L.ay, L.az, L.du);
-    A.split_part[(int64_t)(2 * it + 1) * kWave + ln] = make_double4(L.mumax, (double)L.npair, 0.0, 0.0);
+    double4 *part = A.split_part + (int64_t)kSphPart * it * kWave;
+    part[ln] = make_double4(L.ax, L.ay, L.az, L.du);
+    part[kWave + ln] = make_double4(L.mumax, (double)L.npair, L.duv, L.vsig);
+    part[2 * kWave + ln] = make_double4(L.xsx, L.xsy, L.xsz, 0.0);
   }
 }
 
@@ -390,14 +426,19 @@ __global__ __launch_bounds__(64) void k_sph_reduce(SphArgs A) {
       const SplitItem I = A.split_item[it];
       const int p = bt.first + I.c0 + ln;
       if (I.c0 + ln < bt.count && A.gas[p]) {
-        const double4 v = A.split_part[(int64_t)(2 * it) * kWave + ln];
-        const double4 w = A.split_part[(int64_t)(2 * it + 1) * kWave + ln];
+        const double4 *part = A.split_part + (int64_t)kSphPart * it * kWave;
+        const double4 v = part[ln], w = part[kWave + ln], x = part[2 * kWave + ln];
         A.acc[0 * A.cap_n + p] += v.x;
         A.acc[1 * A.cap_n + p] += v.y;
         A.acc[2 * A.cap_n + p] += v.z;
         A.acc[4 * A.cap_n + p] += v.w;
         A.solve[kMaxmu * A.cap_n + p] = fmax(A.solve[kMaxmu * A.cap_n + p], w.x);
         A.cnt[2 * A.cap_n + A.perm[p]] += (int)w.y;
+        A.solve[kDuv * A.cap_n + p] += w.z;
+        A.solve[kVsig * A.cap_n + p] = fmax(A.solve[kVsig * A.cap_n + p], w.w);
+        A.solve[kXsx * A.cap_n + p] += x.x;
+        A.solve[kXsy * A.cap_n + p] += x.y;
+        A.solve[kXsz * A.cap_n + p] += x.z;
       }
       it = I.next;
     }
@@ -410,6 +451,11 @@ __global__ __launch_bounds__(256) void k_zero_sph(int64_t n, int64_t cap_n, doub
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
     acc[4 * cap_n + p] = 0.0;
     solve[kMaxmu * cap_n + p] = 0.0;
+    solve[kVsig * cap_n + p] = 0.0;
+    solve[kDuv * cap_n + p] = 0.0;
+    solve[kXsx * cap_n + p] = 0.0;
+    solve[kXsy * cap_n + p] = 0.0;
+    solve[kXsz * cap_n + p] = 0.0;
     cnt[2 * cap_n + perm[p]] = 0;
   }
 }
@@ -454,11 +500,15 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   A.beta = c->p.beta;
   A.av_eps2 = c->p.av_eps2;
   A.tc92 = c->p.tc92;
+  A.gamma = c->p.gamma;
+  A.xsph_eta = c->p.xsph_eta;
+  A.visc_signal = c->p.visc_form == TSPH_VISC_SIGNAL;
+  A.entropy = c->p.entropy;
   // debug lists are written in the batch's own order: no hand-off then.  The
   // SPH pairs cost more per candidate than the near-field gravity pairs, so
   // the batch keeps a quarter of the gravity walk's share.
   A.split_particles = c->dbg_nbr ? 0 : c->p.split_leaves * c->p.leaf_size / 4;
-  A.split_cap = split_cap_used(c) / 2;
+  A.split_cap = split_cap_used(c) / kSphPart;
   A.split_rng = c->split_rng;
   A.split_item = c->split_item;
   A.split_part = c->split_part;

@@ -604,28 +604,44 @@ __global__ __launch_bounds__(256) void k_moments(int level, double theta, const 
 }
 
 // refresh of the per-node largest eps (all) and h (gas) after the solves
+// Per-node maxima of eps (all) and h (gas), one level at a time from the
+// deepest; with nsoft (softened cells) also the node's sums of m eps and of
+// m xi/Upsilon, from its particles (leaves) or its children.
 __global__ __launch_bounds__(256) void k_refresh(int level, const int32_t *__restrict__ lvl,
                                                  const NodeTopo *__restrict__ topo,
                                                  const double *__restrict__ hs, const double *__restrict__ es,
-                                                 const uint8_t *__restrict__ gas, NodeBox *__restrict__ box) {
+                                                 const uint8_t *__restrict__ gas, NodeBox *__restrict__ box,
+                                                 const double4 *__restrict__ pm, const double2 *__restrict__ soft,
+                                                 double2 *__restrict__ nsoft) {
   int begin = lvl[level], count = lvl[23 + level];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
     int k = begin + t;
     NodeTopo nd = topo[k];
-    double em = 0.0, hm = 0.0;
+    double em = 0.0, hm = 0.0, me = 0.0, mx = 0.0;
     if (nd.nchild == 0) {
       for (int p = nd.first; p < nd.first + nd.count; p++) {
         em = fmax(em, es[p]);
         if (gas[p]) hm = fmax(hm, hs[p]);
+        if (nsoft) {
+          const double m = pm[p].w;
+          const double2 sf = soft[p];
+          me += m * sf.x;
+          mx += m * sf.y;
+        }
       }
     } else {
       for (int c = nd.child; c < nd.child + nd.nchild; c++) {
         em = fmax(em, box[c].epsmax);
         hm = fmax(hm, box[c].hmax);
+        if (nsoft) {
+          me += nsoft[c].x;
+          mx += nsoft[c].y;
+        }
       }
     }
     box[k].epsmax = em;
     box[k].hmax = hm;
+    if (nsoft) nsoft[k] = make_double2(me, mx);
   }
 }
 
@@ -786,7 +802,7 @@ tsph_status tsph_impl_refresh(Ctx *c, hipStream_t st) {
   int lb = blocks_for(maxlev, 256, 4096);
   for (int L = kMaxLevel; L >= 0; L--)
     hipLaunchKernelGGL(k_refresh, dim3(lb), dim3(256), 0, st, L, c->lvl, c->topo, c->hs, c->es, c->gas,
-                       c->nbox);
+                       c->nbox, c->pm, c->soft, c->p.soften_cells && c->p.gravity ? c->nsoft : nullptr);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

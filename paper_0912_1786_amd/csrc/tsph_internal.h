@@ -52,7 +52,7 @@ struct SphRec {
   double x, y, z, m;
   double vx, vy, vz, im;       // predicted velocity, 1/m
   double h, ih, rho, c;        // h, 1/h, density, sound speed
-  double pr2, zo, pad0, pad1;  // P / rho^2, zeta / Omega*
+  double pr2, zo, fa, pad1;    // P / rho^2, zeta / Omega*, grad-h factor f_ij = fa + zo / m_j
 };
 
 // The simulations a context holds (a forest of independent trees).  Member
@@ -117,7 +117,14 @@ inline int64_t split_item_cap(int64_t cap_nodes) {
 // capacity of the list of density batches solved one sink per wavefront
 inline int64_t heavy_batch_cap(int64_t cap_nodes) { return cap_nodes < 4096 ? 4096 : cap_nodes; }
 
-enum SolveField { kNh = 0, kOmega, kZeta, kDivv, kNeps, kUps, kXi, kMaxmu, kDivvE, kNumSolve };
+// per-particle outputs of the force pass kept in key order: the solves'
+// sums and factors, and the SPH pass's largest |mu|, largest signal
+// velocity, viscous heating and X-SPH sum
+// rows of the carry from one force pass to the next drift (caller order)
+constexpr int kCarryRows = 5;
+
+enum SolveField { kNh = 0, kOmega, kZeta, kDivv, kNeps, kUps, kXi, kMaxmu, kDivvE, kVsig, kDuv, kXsx, kXsy, kXsz,
+                  kNumSolve };
 
 struct Ctx {
   int device;
@@ -144,7 +151,8 @@ struct Ctx {
   GravRec *grec;          // gravity source records
   SphRec *srec;           // SPH source records (gas entries)
   double *solve;          // kNumSolve x cap_n
-  double *pdiv;           // 2 x cap_n, caller order: div v with the h kernel (gas) and the eps kernel
+  double *pdiv;           // kCarryRows x cap_n, caller order: div v with the h kernel (gas) and the eps
+                          // kernel, the X-SPH velocity correction (3 rows)
   int64_t pdiv_n;         // particle count the divergences belong to (0: none yet)
   double *acc;            // 6 x cap_n: ax, ay, az, pot, dudt, dt_i
   int32_t *cnt;           // 3 x cap_n: far nodes, near pairs, SPH pairs
@@ -154,6 +162,7 @@ struct Ctx {
   int32_t *nlevel, *nparent, *nngas;
   NodeFar *nfar;
   NodeBox *nbox;
+  double2 *nsoft;         // softened cells: sum of m eps and of m xi/Upsilon over the node
   int2 *ctmp;             // 8 x cap_nodes child (first, count) scratch
   int32_t *ctmpn;         // cap_nodes child counts of a level
   int32_t *cscan;         // cap_nodes exclusive scan of ctmpn

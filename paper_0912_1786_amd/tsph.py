@@ -18,12 +18,16 @@ TSPH_OK, TSPH_EINVAL, TSPH_ENOMEM, TSPH_EHIP, TSPH_ECAPACITY, TSPH_ENOCONV, TSPH
 SOFT_ADAPTIVE, SOFT_CONSTANT, SOFT_ADAPTIVE_NOCORR = 0, 1, 2
 FP64, FP32_BULK = 0, 1
 KD_FIRST, KD_SECOND = 0, 1
+VISC_MG, VISC_SIGNAL = 0, 1
+H_LAGRANGIAN, H_STANDARD = 0, 1
+HW_NUMBER, HW_MASS = 0, 1
 FLAG_NODE_CAPACITY, FLAG_STACK_OVERFLOW, FLAG_LIST_OVERFLOW, FLAG_NOCONV, FLAG_NONFINITE, FLAG_INTERNAL = (
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20)
 FLAG_HANDOFF_CAPACITY = 0x40
 DBG_KEYS, DBG_PERM, DBG_NODES, DBG_NNODES, DBG_MOMENTS, DBG_GROUPS, DBG_NGROUPS, DBG_COUNTS, DBG_NBR, DBG_ROOT, \
     DBG_SOLVE, DBG_BATCHES, DBG_NBATCHES = range(13)
-SOLVE_FIELDS = ("nh", "omega", "zeta", "divv", "neps", "ups", "xi", "maxmu", "divv_eps")
+SOLVE_FIELDS = ("nh", "omega", "zeta", "divv", "neps", "ups", "xi", "maxmu", "divv_eps", "vsig", "duv", "xsph_sx",
+                "xsph_sy", "xsph_sz")
 
 
 class TsphError(RuntimeError):
@@ -39,7 +43,9 @@ class Params(C.Structure):
                 ("h_tol", C.c_double), ("kappa", C.c_double), ("leaf_size", C.c_int32),
                 ("group_size", C.c_int32), ("precision", C.c_int32), ("gravity", C.c_int32),
                 ("hydro", C.c_int32), ("split_leaves", C.c_int32), ("eta_dt", C.c_double),
-                ("max_members", C.c_int32)]
+                ("max_members", C.c_int32), ("grav_corr_literal", C.c_int32), ("soften_cells", C.c_int32),
+                ("visc_form", C.c_int32), ("entropy", C.c_int32), ("xsph_eta", C.c_double),
+                ("h_scheme", C.c_int32), ("h_weight", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -79,6 +85,7 @@ def lib():
             "tsph_compute_forces": ([_P, S, _P], C.c_int),
             "tsph_kick_drift": ([_P, S, C.c_double, C.c_int32, _P], C.c_int),
             "tsph_kick_drift_dt": ([_P, S, _P, C.c_int32, _P], C.c_int),
+            "tsph_batch_step": ([_P, S, _P, _P], C.c_int),
             "tsph_carry_bytes": ([C.c_int64, C.POINTER(C.c_size_t)], C.c_int),
             "tsph_carry_save": ([_P, C.c_int64, _P, _P], C.c_int),
             "tsph_carry_load": ([_P, C.c_int64, _P, _P], C.c_int),
@@ -114,7 +121,7 @@ EXPORTED = ("tsph_create", "tsph_destroy", "tsph_set_params", "tsph_default_para
             "tsph_set_members", "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_kick_drift_dt", "tsph_carry_bytes",
             "tsph_carry_save", "tsph_carry_load", "tsph_timestep", "tsph_diagnostics", "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
             "tsph_timing", "tsph_phase_times", "tsph_probe", "tsph_debug_handoff_cap", "tsph_source_id",
-            "tsph_diagnostics_noalloc", "tsph_noalloc_last_error")
+            "tsph_diagnostics_noalloc", "tsph_noalloc_last_error", "tsph_batch_step")
 PHASES = ("tree", "density", "gravity", "sph", "finish")
 
 
@@ -199,6 +206,10 @@ def tsph_kick_drift(ctx, st: State, dt: float, phase: int, stream=None):
 def tsph_kick_drift_dt(ctx, st: State, dt_ptr: int, phase: int, stream=None):
     _check("tsph_kick_drift_dt",
            lib().tsph_kick_drift_dt(ctx, C.byref(st), C.c_void_p(dt_ptr), int(phase), _stream(stream)), ctx)
+
+
+def tsph_batch_step(ctx, st: State, dt_ptr: int, stream=None):
+    _check("tsph_batch_step", lib().tsph_batch_step(ctx, C.byref(st), C.c_void_p(dt_ptr), _stream(stream)), ctx)
 
 
 def tsph_carry_bytes(n: int) -> int:
@@ -424,13 +435,10 @@ class Simulation:
         torch.cuda.current_stream().synchronize()
 
     def device_step(self, stream=None):
-        """One KDK step with the global time-step taken and used on the device
-        (no host round trip; capturable in a HIP graph)."""
-        ptr = self.dt_buf.data_ptr()
-        tsph_timestep(self.ctx, self.state, ptr, stream)
-        tsph_kick_drift_dt(self.ctx, self.state, ptr, KD_FIRST, stream)
-        self.compute_forces(stream)
-        tsph_kick_drift_dt(self.ctx, self.state, ptr, KD_SECOND, stream)
+        """One KDK step of every system held, each with its own global
+        time-step taken and used on the device (tsph_batch_step: no host
+        round trip; capturable in a HIP graph)."""
+        tsph_batch_step(self.ctx, self.state, self.dt_buf.data_ptr(), stream)
 
     def flags(self):
         return tsph_read_flags(self.ctx)

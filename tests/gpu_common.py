@@ -17,7 +17,9 @@ def oracle_params(orc, gp, walk_mode=None):
                       leaf_size=gp.leaf_size, group_size=gp.group_size,
                       walk_mode=orc.WALK_GROUP if walk_mode is None else walk_mode,
                       nbr_mode=orc.NBR_TREE, gravity=gp.gravity, hydro=gp.hydro, batch_size=64,
-                      batch_mode=0)
+                      batch_mode=0, grav_corr_literal=gp.grav_corr_literal, soften_cells=gp.soften_cells,
+                      visc_form=gp.visc_form, entropy=gp.entropy, xsph_eta=gp.xsph_eta, h_scheme=gp.h_scheme,
+                      h_weight=gp.h_weight)
 
 
 def run_gpu(ic, gp, lists=0, eps_const=None):

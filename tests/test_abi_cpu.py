@@ -52,9 +52,11 @@ def test_host_only_entry_points(T):
 def test_param_struct_layout_matches_header(T):
     import ctypes as C
     # field order and padding of tsph_params / tsph_state as declared
-    # ... max_members (int32) last, padded to the struct's 8-byte alignment
-    assert C.sizeof(T.Params) == 8 * 2 + 4 * 2 + 8 * 6 + 4 * 2 + 8 * 2 + 4 * 6 + 8 + 4 + 4
-    assert T.Params.max_members.offset == C.sizeof(T.Params) - 8
+    # ... max_members, grav_corr_literal, soften_cells, visc_form, entropy
+    # (int32), xsph_eta (double), h_scheme, h_weight (int32)
+    assert C.sizeof(T.Params) == 8 * 2 + 4 * 2 + 8 * 6 + 4 * 2 + 8 * 2 + 4 * 6 + 8 + 4 * 5 + 4 + 8 + 4 * 2
+    assert T.Params.h_weight.offset == C.sizeof(T.Params) - 4
+    assert T.Params.xsph_eta.offset % 8 == 0
     assert C.sizeof(T.State) == 8 * 2 + 8 * 20
 
 

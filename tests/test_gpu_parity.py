@@ -259,6 +259,25 @@ def test_forces_other_tree_shapes(orc_mod, leaf, group):
     _compare_full(orc_mod, ic, gpu_params(leaf_size=leaf, group_size=group))
 
 
+@pytest.mark.parametrize("literal,soften,precision", [(1, 0, "fp64"), (0, 1, "fp64"), (1, 1, "fp64"),
+                                                       (0, 1, "fp32_bulk"), (1, 0, "fp32_bulk")])
+def test_correction_weighting_and_softened_cells(orc_mod, literal, soften, precision):
+    """The printed mass weighting of the correction terms (grav_corr_literal)
+    and softened cells (soften_cells) on the two-species field (masses 1:5):
+    lengths, xi, accelerations and counts as the oracle's same walk."""
+    _say(f"[flags] literal={literal} soften={soften} precision={precision}")
+    ic = CASES["field2x3000"]()
+    prec = tsph.FP32_BULK if precision == "fp32_bulk" else tsph.FP64
+    gp = gpu_params(nnei=60, grav_corr_literal=literal, soften_cells=soften, precision=prec)
+    g, o = _compare_full(orc_mod, ic, gp, tol_pot=1e-5 if precision == "fp32_bulk" else 1e-8)
+    if soften:
+        plain = orc_mod.compute_forces(ic, oracle_params(orc_mod, gpu_params(nnei=60, grav_corr_literal=literal)))
+        assert g["cnt_pair"].sum() < plain["cnt_pair"].sum()  # softened cells replaced near pairs
+    if literal:
+        plain = orc_mod.compute_forces(ic, oracle_params(orc_mod, gpu_params(nnei=60, soften_cells=soften)))
+        assert relrms(acc(o), acc(plain)) > 1e-8  # the weighting matters at unequal masses
+
+
 def test_theta_zero_equals_direct_sum(orc_mod):
     _say("[theta0]")
     ic = inputs.two_species_field(n_dm=1000, n_gas=1000, n_halo=4, seed=6)

@@ -1,0 +1,168 @@
+"""GPU parity of the scheme variants (Sect. 3 standard scheme and the
+mass-density relation, Sect. 3.3.1 signal-velocity viscosity, Sect. 3.4
+entropy equation, Sect. 3.5 X-SPH) against the oracle on the same seeded
+inputs: lengths, densities, forces, rates, the largest signal velocity, the
+X-SPH correction and a whole KDK step, at the bars of the plain scheme."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0912_1786_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # collected on CPU-only machines but never run there
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_0912_1786_amd import tsph  # noqa: E402
+
+from gpu_common import acc, gpu_params, maxrel, oracle_params, relrms, run_gpu  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    return oracle
+
+
+def _check(O, ic, gp, tol_acc=1e-5):
+    sim, g = run_gpu(ic, gp)
+    sim.close()
+    o = O.compute_forces(ic, oracle_params(O, gp))
+    assert g["flags"] == 0, hex(g["flags"])
+    assert g["noconv"] == 0 and o["n_noconv"] == 0
+    gas = np.arange(ic["n"]) < ic["n_gas"]
+    assert maxrel(g["h"], o["h"], gas) < 1e-9
+    assert maxrel(g["rho"], o["rho"], gas) < 1e-6
+    assert np.allclose(g["omega"][gas], o["omega"][gas], rtol=1e-8)
+    assert np.allclose(g["divv"][gas], o["divv"][gas], rtol=1e-7, atol=1e-9 * np.abs(o["divv"]).max())
+    e = relrms(acc(g), acc(o))
+    ed = relrms(g["dudt"], o["dudt"]) if np.any(o["dudt"]) else float(np.abs(g["dudt"]).max())
+    _say(f"    acc relRMS {e:.2e}, du/dt relRMS {ed:.2e}")
+    assert e < tol_acc and ed < 1e-6
+    assert np.allclose(g["maxmu"][gas], o["maxmu"][gas], rtol=1e-8, atol=1e-14)
+    assert np.allclose(g["vsig"][gas], o["vsig"][gas], rtol=1e-12)
+    assert np.array_equal(g["cnt_sph"], o["cnt_sph"])
+    return g, o
+
+
+@pytest.mark.parametrize("case", ["evrard", "field"])
+def test_signal_velocity_viscosity(O, case):
+    _say(f"[variant] signal viscosity {case}")
+    if case == "evrard":
+        ic, nnei = inputs.evrard(4096, seed=2, v_sigma=0.1), 50
+    else:
+        ic, nnei = inputs.two_species_field(n_dm=3000, n_gas=3000, n_halo=8, seed=3), 60
+    _check(O, ic, gpu_params(nnei=nnei, visc_form=tsph.VISC_SIGNAL))
+
+
+def _entropy_ic(ic):
+    """The same state with u read as the entropic function A."""
+    out = dict(ic)
+    out["u"] = ic["u"].copy()
+    return out
+
+
+@pytest.mark.parametrize("visc", [tsph.VISC_MG, tsph.VISC_SIGNAL])
+def test_entropy_variable_step(O, visc):
+    _say(f"[variant] entropy visc={visc}")
+    ic = _entropy_ic(inputs.evrard(3000, seed=4, v_sigma=0.1))
+    gp = gpu_params(entropy=1, visc_form=visc)
+    g, o = _check(O, ic, gp)
+    assert np.all(g["dudt"][: ic["n_gas"]] >= 0.0)
+    # one KDK step with the global time-step (c from A and rho)
+    op = oracle_params(O, gp)
+    sim = tsph.Simulation(ic, gp)
+    sim.compute_forces()
+    dt = sim.timestep()
+    dt_o = O.timestep(op, ic, o)
+    assert dt == pytest.approx(dt_o, rel=1e-8)
+    st = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ic.items()}
+    pred = {"vx": st["vx"].copy(), "vy": st["vy"].copy(), "vz": st["vz"].copy(), "u": st["u"].copy()}
+    lengths = {"h": o["h"].copy(), "eps": o["eps"].copy(), "divv": o["divv"], "divv_eps": o["divv_eps"]}
+    O.kick_drift(st, dt_o, 0, (o["ax"], o["ay"], o["az"]), o["dudt"], pred, lengths)
+    sim.kick_drift(dt_o, tsph.KD_FIRST)
+    o1 = O.compute_forces(st, op, h_in=lengths["h"], eps_in=lengths["eps"],
+                          vel=(pred["vx"], pred["vy"], pred["vz"]), u=pred["u"])
+    O.kick_drift(st, dt_o, 1, (o1["ax"], o1["ay"], o1["az"]), o1["dudt"])
+    sim.compute_forces()
+    sim.kick_drift(dt_o, tsph.KD_SECOND)
+    assert sim.flags() == (0, 0)
+    for k in ("x", "vx", "u"):
+        a, b = sim.host(k), st[k]
+        assert np.max(np.abs(a - b)) < 1e-9 * max(np.abs(b).max(), 1e-3), k
+    d_gpu = sim.diagnostics()
+    d_orc = O.diagnostics(st, o1["pot"], rho=o1["rho"], gamma=gp.gamma, entropy=True)
+    assert np.allclose(d_gpu[:3], d_orc[:3], rtol=1e-8)
+    sim.close()
+
+
+def test_xsph_correction_and_drift(O):
+    _say("[variant] X-SPH")
+    ic = inputs.evrard(3000, seed=5, v_sigma=0.1)
+    gp = gpu_params(xsph_eta=0.5)
+    g, o = _check(O, ic, gp)
+    n_gas = ic["n_gas"]
+    for ax in "xyz":
+        a, b = 0.5 * g[f"xsph_s{ax}"][:n_gas], o[f"xsph_{ax}"][:n_gas]
+        assert relrms(a, b) < 1e-10, ax
+    # the drift takes v + dv
+    sim = tsph.Simulation(ic, gp)
+    sim.compute_forces()
+    dt = 1e-3
+    st = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ic.items()}
+    O.kick_drift(st, dt, 0, (o["ax"], o["ay"], o["az"]), o["dudt"], xsph=(o["xsph_x"], o["xsph_y"], o["xsph_z"]))
+    sim.kick_drift(dt, tsph.KD_FIRST)
+    for k in ("x", "y", "z"):
+        assert np.max(np.abs(sim.host(k) - st[k])) < 1e-12, k
+    sim.close()
+
+
+@pytest.mark.parametrize("case", ["evrard", "field"])
+def test_standard_scheme(O, case):
+    _say(f"[variant] standard scheme {case}")
+    if case == "evrard":
+        ic, nnei = inputs.evrard(4096, seed=6, v_sigma=0.05), 50
+    else:
+        ic, nnei = inputs.two_species_field(n_dm=3000, n_gas=3000, n_halo=8, seed=7), 60
+    gp = gpu_params(nnei=nnei, h_scheme=tsph.H_STANDARD)
+    g, o = _check(O, ic, gp)
+    gas = np.arange(ic["n"]) < ic["n_gas"]
+    assert np.all(g["omega"][gas] == 1.0) and np.all(g["zeta"][gas] == 0.0)
+    assert maxrel(g["h"], o["h"], gas) < 1e-15
+
+
+def test_mass_density_relation(O):
+    _say("[variant] mass-density relation")
+    ic = inputs.two_species_field(n_dm=3000, n_gas=3000, n_halo=8, seed=8)
+    # gas of two masses so that the relation matters
+    ic["m"] = ic["m"].copy()
+    ic["m"][: ic["n_gas"]:2] *= 3.0
+    g, o = _check(O, ic, gpu_params(nnei=60, h_weight=tsph.HW_MASS))
+    _check(O, ic, gpu_params(nnei=60, h_weight=tsph.HW_MASS, precision=tsph.FP32_BULK))
+    with pytest.raises(tsph.TsphError):
+        tsph.tsph_create(100, gpu_params(h_weight=tsph.HW_MASS, h_scheme=tsph.H_STANDARD))
+
+
+@pytest.mark.parametrize("scheme", ["lagrangian_number", "lagrangian_mass", "standard_number"])
+def test_mixed_mass_lattice(O, scheme):
+    """The four-scheme density test of Sect. 3 (the three schemes the GPU
+    takes): densities and lengths equal to the oracle's."""
+    _say(f"[variant] mixed-mass lattice {scheme}")
+    ic = inputs.mixed_mass_lattice()
+    hs = tsph.H_STANDARD if scheme.startswith("standard") else tsph.H_LAGRANGIAN
+    hw = tsph.HW_MASS if scheme.endswith("mass") else tsph.HW_NUMBER
+    gp = gpu_params(nnei=50, gravity=0, h_scheme=hs, h_weight=hw, leaf_size=8, group_size=32)
+    sim, g = run_gpu(ic, gp)
+    sim.close()
+    o = O.compute_forces(ic, oracle_params(O, gp))
+    assert g["flags"] == 0 and g["noconv"] == 0 and o["n_noconv"] == 0
+    assert maxrel(g["h"], o["h"]) < 1e-9
+    assert maxrel(g["rho"], o["rho"]) < 1e-6
