@@ -162,6 +162,25 @@ typedef struct {
                           sum m dW/dh).  The mass form is taken with
                           TSPH_H_LAGRANGIAN only (TSPH_EINVAL otherwise).
                           rho is Eq. densitySPH in every scheme              */
+  /* dissipation switches (Sect. 3.3.1, 3.3.2); each needs the state's
+   * alpha / alpha_u arrays where noted */
+  int32_t balsara;     /* 1: Pi_ij times (f_i + f_j)/2, f = |div v| / (|div v|
+                          + |curl v| + 1e-4 c/h), the curl from the h kernel
+                          normalised as the divergence                      */
+  int32_t alpha_switch;/* 1: per-particle alpha (state alpha, gas): the pair
+                          mean replaces alpha in Pi_ij (both forms) and in the
+                          Courant criterion; d alpha/dt = -(alpha -
+                          alpha_min)/tau + 0.75 f max(0, -div v) with
+                          tau = h / (0.1 v_sig) (Eq. alphaswitch)             */
+  int32_t conduction;  /* 1: artificial conductivity: du_i += sum_j m_j Pi^u_ij
+                          |Gbar_ij|, Pi^u_ij = -alphabar^u v^u_sig (u_i - u_j)
+                          / rhobar, v^u_sig = sqrt(|P_i - P_j| / rhobar), with
+                          per-particle alpha_u (state alpha_u, gas),
+                          d alpha_u/dt = -(alpha_u - alpha_u_min)/tau + h
+                          |lap u| / sqrt(u) (Brookshaw's Laplacian).  Not
+                          with entropy (TSPH_EINVAL)                         */
+  double alpha_min;    /* floor of alpha (0.01)                               */
+  double alpha_u_min;  /* floor of alpha_u (0)                                */
 } tsph_params;
 enum { TSPH_VISC_MG = 0, TSPH_VISC_SIGNAL = 1 };
 enum { TSPH_H_LAGRANGIAN = 0, TSPH_H_STANDARD = 1 };
@@ -186,6 +205,11 @@ typedef struct {
   double *dudt;              /* du/dt (gas)                                     */
   double *rho;               /* SPH mass density (gas)                          */
   double *pot;               /* potential per unit mass; may be NULL            */
+  /* dissipation coefficients (gas entries; integrator state advanced by
+   * tsph_kick_drift with the rates of the last force pass, kept at or above
+   * alpha_min / alpha_u_min); required with alpha_switch / conduction, read
+   * by balsara-only passes if given, else NULL */
+  double *alpha, *alpha_u;
 } tsph_state;
 
 /* Create a context on the current HIP device for up to capacity_n particles.
@@ -256,8 +280,9 @@ tsph_status tsph_batch_step(void *ctx, tsph_state *s, double *dt_device, void *s
 
 /* The carry of a context from one step to the next: the global time-step
  * of the last force pass, the velocity divergences with which the next
- * drift carries h and eps, and the X-SPH velocity correction of that drift
- * (5 n + 1 doubles for n particles).  Saving it and
+ * drift carries h and eps, the X-SPH velocity correction of that drift and
+ * the rates of alpha and alpha_u for the next kicks (7 n + 1 doubles for n
+ * particles).  Saving it and
  * loading it into a context (the same or a new one) lets a simulation leave
  * the device between steps and continue bit for bit: after tsph_carry_load
  * the next tsph_timestep / tsph_kick_drift behave as if the force pass had
@@ -342,8 +367,10 @@ enum { TSPH_DBG_KEYS = 0,      /* uint64[n] sorted Morton keys                  
                                 * SPH pairs per particle in the last force pass        */
        TSPH_DBG_NBR = 8,       /* int32[3][n][max] neighbour lists, see below          */
        TSPH_DBG_ROOT = 9,      /* double[4] x0, y0, z0, side (of the first system)     */
-       TSPH_DBG_SOLVE = 10,    /* double[9][n] (caller order) nh, omega, zeta, divv,   *
-                                * neps, ups, xi, maxmu, divv with the eps kernel        */
+       TSPH_DBG_SOLVE = 10,    /* double[19][n] (caller order) nh, omega, zeta, divv,  *
+                                * neps, ups, xi, maxmu, divv with the eps kernel,       *
+                                * largest signal velocity, viscous heating, X-SPH sum  *
+                                * (3, without eta), curl (3), Balsara factor, lap u     */
        TSPH_DBG_BATCHES = 11,  /* int32[nbatches][2] walk batches: group-list ranges   *
                                 * [g0, g1) of consecutive sibling groups packed to <= 64 */
        TSPH_DBG_NBATCHES = 12  /* int64[1]                                             */ };

@@ -104,6 +104,8 @@ def lib():
             [D, D, C.c_double, D, D, C.c_double]
         L.orc_timestep.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64] + [D] * 12 + [C.c_double, D, D]
         L.orc_timestep.restype = C.c_double
+        L.orc_timestep_each.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64] + [D] * 12 + [C.c_double, D, D, D]
+        L.orc_timestep_each.restype = C.c_double
         L.orc_diagnostics.argtypes = [C.c_int64, C.c_int64] + [D] * 10 + [D, C.c_double, C.c_int32]
         L.orc_eval_kernel.argtypes = [C.c_int, C.c_int64, D, D, D]
         L.orc_num_threads.restype = C.c_int
@@ -293,8 +295,21 @@ def timestep(prm: Params, st: dict, out: dict, eta_dt: float = 0.1) -> float:
             out["az"], out["dudt"], out["divv"], out["maxmu"]]
     arrs = [_f64(a) for a in arrs]
     rho = _f64(out["rho"]) if "rho" in out else None
-    al = _f64(st["alpha"]) if st.get("alpha") is not None else None
+    al = _f64(st["alpha"]) if (prm.alpha_switch and st.get("alpha") is not None) else None
     return lib().orc_timestep(C.byref(prm), n, n_gas, *(_p(a) for a in arrs), eta_dt, _p(rho), _p(al))
+
+
+def timestep_each(prm: Params, st: dict, out: dict, eta_dt: float = 0.1) -> np.ndarray:
+    """Per-particle time-step criteria (Sect. 4.2), INFINITY where none applies."""
+    n, n_gas = int(st["n"]), int(st["n_gas"])
+    arrs = [st["vx"], st["vy"], st["vz"], st["u"], out["h"], out["eps"], out["ax"], out["ay"],
+            out["az"], out["dudt"], out["divv"], out["maxmu"]]
+    arrs = [_f64(a) for a in arrs]
+    rho = _f64(out["rho"]) if "rho" in out else None
+    al = _f64(st["alpha"]) if (prm.alpha_switch and st.get("alpha") is not None) else None
+    dt = np.zeros(n)
+    lib().orc_timestep_each(C.byref(prm), n, n_gas, *(_p(a) for a in arrs), eta_dt, _p(rho), _p(al), _p(dt))
+    return dt
 
 
 def diagnostics(st: dict, pot, rho=None, gamma: float = 5.0 / 3.0, entropy: bool = False) -> np.ndarray:

@@ -1678,9 +1678,22 @@ double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double 
                     const double *dudt, const double *divv, const double *maxmu, double eta_dt,
                     const double *rho, const double *alpha)
 {
+  return orc_timestep_each(p, n, n_gas, vx, vy, vz, u, h, eps, ax, ay, az, dudt, divv, maxmu, eta_dt, rho, alpha,
+                           NULL);
+}
+
+/* The same criteria per particle (dt_out[i], INFINITY when none applies);
+ * returns their minimum. */
+double orc_timestep_each(const orc_params *p, int64_t n, int64_t n_gas, const double *vx,
+                         const double *vy, const double *vz, const double *u, const double *h,
+                         const double *eps, const double *ax, const double *ay, const double *az,
+                         const double *dudt, const double *divv, const double *maxmu, double eta_dt,
+                         const double *rho, const double *alpha, double *dt_out)
+{
   (void)vx; (void)vy; (void)vz;
-  double dt = INFINITY;
+  double dt_min = INFINITY;
   for (int64_t i = 0; i < n; i++) {
+    double dt = INFINITY;
     double amag = sqrt(ax[i] * ax[i] + ay[i] * ay[i] + az[i] * az[i]);
     double len = eps ? eps[i] : INFINITY;
     if (i < n_gas && h && h[i] < len) len = h[i];
@@ -1704,8 +1717,10 @@ double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double 
         if (t < dt) dt = t;
       }
     }
+    if (dt_out) dt_out[i] = dt;
+    if (dt < dt_min) dt_min = dt;
   }
-  return dt;
+  return dt_min;
 }
 
 void orc_diagnostics(int64_t n, int64_t n_gas, const double *x, const double *y, const double *z,

@@ -180,6 +180,12 @@ double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double 
                     const double *dudt, const double *divv, const double *maxmu, double eta_dt,
                     const double *rho /* entropy form: c from A and rho */,
                     const double *alpha /* per-particle alpha, or NULL */);
+/* the same criteria per particle into dt_out (INFINITY where none applies) */
+double orc_timestep_each(const orc_params *p, int64_t n, int64_t n_gas, const double *vx,
+                         const double *vy, const double *vz, const double *u, const double *h,
+                         const double *eps, const double *ax, const double *ay, const double *az,
+                         const double *dudt, const double *divv, const double *maxmu, double eta_dt,
+                         const double *rho, const double *alpha, double *dt_out);
 /* out[9] = E_kin, E_th, V, Px, Py, Pz, Lx, Ly, Lz (V from pot: 0.5 sum m pot) */
 void orc_diagnostics(int64_t n, int64_t n_gas, const double *x, const double *y, const double *z,
                      const double *vx, const double *vy, const double *vz, const double *m,

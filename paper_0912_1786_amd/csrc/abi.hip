@@ -62,6 +62,9 @@ const char *param_error(const tsph_params *p) {
   if (p->h_weight != TSPH_HW_NUMBER && p->h_weight != TSPH_HW_MASS) return "unknown h_weight";
   if (p->h_weight == TSPH_HW_MASS && p->h_scheme != TSPH_H_LAGRANGIAN)
     return "the mass-density relation is taken with the Lagrangian scheme only";
+  if ((p->balsara | p->alpha_switch | p->conduction) & ~1) return "balsara, alpha_switch, conduction must be 0 or 1";
+  if (!(p->alpha_min >= 0.0) || !(p->alpha_u_min >= 0.0)) return "alpha_min and alpha_u_min must be >= 0";
+  if (p->conduction && p->entropy) return "conduction acts on u: not with the entropy variable";
   return nullptr;
 }
 
@@ -91,6 +94,8 @@ size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->add(4 * N);        // 16 gflag
   L->add(sizeof(GravRec) * N);  // grec
   L->add(sizeof(SphRec) * N);   // srec
+  L->add(32 * N);               // srec2: alpha, alpha_u, Balsara factor, u of the gas
+  L->add(16 * N);               // av: alpha, alpha_u in key order
   L->add(8 * kCarryRows * N);   // pdiv: the carry to the next drift
   // nodes
   L->add(sizeof(NodeTopo) * M);  // 17 topo
@@ -183,6 +188,8 @@ tsph_status check_state(Ctx *c, const tsph_state *s, bool forces) {
     if (s->n_gas > 0 && c->p.hydro && (!s->up || !s->h || !s->dudt || !s->rho))
       return set_err(c, TSPH_EINVAL, "gas needs up, h, dudt and rho");
     if (c->p.gravity && !s->eps) return set_err(c, TSPH_EINVAL, "eps is required with gravity");
+    if (s->n_gas > 0 && c->p.hydro && ((c->p.alpha_switch && !s->alpha) || (c->p.conduction && !s->alpha_u)))
+      return set_err(c, TSPH_EINVAL, "alpha_switch needs alpha and conduction needs alpha_u");
   }
   return TSPH_OK;
 }
@@ -225,6 +232,7 @@ void tsph_default_params(tsph_params *p) {
   p->eta_dt = 0.1;
   p->split_leaves = 256;
   p->max_members = 1;
+  p->alpha_min = 0.01;
 }
 
 tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t *bytes) {
@@ -292,6 +300,8 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->gflag = AT(int32_t *);
   c->grec = AT(GravRec *);
   c->srec = AT(SphRec *);
+  c->srec2 = AT(double4 *);
+  c->av = AT(double2 *);
   c->pdiv = AT(double *);
   c->topo = AT(NodeTopo *);
   c->nlevel = AT(int32_t *);
@@ -448,6 +458,8 @@ tsph_status tsph_compute_forces(void *ctx, tsph_state *s, void *stream) {
 #define MARK(i) \
   if (ev) TSPH_HIP_CHECK(c, hipEventRecord(ev[i], st));
   MARK(0);
+  c->alpha_state = s->alpha;
+  c->alpha_u_state = s->alpha_u;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(kWorkCounters), 0, st, c->work, kWorkCounters);
   if (c->dbg_nbr)
     hipLaunchKernelGGL(k_fill_dbg, dim3(1024), dim3(256), 0, st, (int64_t)3 * c->cap_n * c->dbg_max, c->dbg_nbr);

@@ -30,6 +30,10 @@ struct FinishArgs {
   double *pdiv;  // kCarryRows x cap_n, caller order
   double eta_dt, alpha, beta, gamma, xsph_eta;
   int32_t hydro, entropy;
+  // dissipation switches: key-order alpha, alpha_u; floors
+  const double2 *av;
+  int32_t alpha_switch, conduction;
+  double alpha_min, alpha_u_min;
 };
 
 __global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
@@ -58,6 +62,26 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
   A.pdiv[2 * A.cap_n + i] = g ? A.xsph_eta * A.solve[kXsx * A.cap_n + p] : 0.0;
   A.pdiv[3 * A.cap_n + i] = g ? A.xsph_eta * A.solve[kXsy * A.cap_n + p] : 0.0;
   A.pdiv[4 * A.cap_n + i] = g ? A.xsph_eta * A.solve[kXsz * A.cap_n + p] : 0.0;
+  // rates of the dissipation coefficients (Sect. 3.3.1, 3.3.2): relaxation to
+  // the floor over tau = h / (0.1 v_sig), sources 0.75 f max(0, -div v) and
+  // h |lap u| / sqrt(u)
+  double da = 0.0, dau = 0.0;
+  if (g && (A.alpha_switch || A.conduction)) {
+    const double vs = A.solve[kVsig * A.cap_n + p];
+    const double tau = vs > 0.0 ? s.x / (0.1 * vs) : INFINITY;
+    const double2 al = A.av[p];
+    if (A.alpha_switch) {
+      const double dv = A.solve[kDivv * A.cap_n + p];
+      da = -(al.x - A.alpha_min) / tau + 0.75 * A.solve[kFbal * A.cap_n + p] * (dv < 0.0 ? -dv : 0.0);
+    }
+    if (A.conduction) {
+      const double uu = A.vu[p].w;
+      dau = -(al.y - A.alpha_u_min) / tau +
+            (uu > 0.0 ? s.x * fabs(A.solve[kLapu * A.cap_n + p]) / sqrt(uu) : 0.0);
+    }
+  }
+  A.pdiv[5 * A.cap_n + i] = da;
+  A.pdiv[6 * A.cap_n + i] = dau;
   // time-step criteria (Sect. 4.2): acceleration, Courant, internal energy
   double dt = INFINITY;
   const double amag = sqrt(ax * ax + ay * ay + az * az);
@@ -67,7 +91,8 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
   if (g && A.hydro) {
     const double c = s.z, hh = s.x;
     const double divv = A.solve[kDivv * A.cap_n + p], mumax = A.solve[kMaxmu * A.cap_n + p];
-    const double den = hh * fabs(divv) + c + 1.2 * (A.alpha * c + A.beta * mumax);
+    const double al = A.alpha_switch ? A.av[p].x : A.alpha;
+    const double den = hh * fabs(divv) + c + 1.2 * (al * c + A.beta * mumax);
     if (den > 0.0) dt = fmin(dt, A.eta_dt * hh / den);
     const double u = A.vu[p].w;
     if (du != 0.0) dt = fmin(dt, A.eta_dt * fabs(u / du));
@@ -91,7 +116,8 @@ __global__ __launch_bounds__(256) void k_kick_drift(Members M, double dt, int ph
                                                     const double *__restrict__ dudt, double *vpx, double *vpy,
                                                     double *vpz, double *up, double *h, double *eps,
                                                     const double *__restrict__ pdiv, int64_t cap_n,
-                                                    const double *__restrict__ dt_dev, int xsph) {
+                                                    const double *__restrict__ dt_dev, int xsph, double *alpha,
+                                                    double *alpha_u, double alpha_min, double alpha_u_min) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= M.n) return;
   const int mem = member_of(M, i);
@@ -142,6 +168,12 @@ __global__ __launch_bounds__(256) void k_kick_drift(Members M, double dt, int ph
   vx[i] = v0;
   vy[i] = v1;
   vz[i] = v2;
+  // the dissipation coefficients follow the half kicks with the rates of the
+  // last force pass, kept at or above their floors
+  if (pdiv && gas) {
+    if (alpha) alpha[i] = fmax(alpha[i] + hdt * pdiv[5 * cap_n + i], alpha_min);
+    if (alpha_u) alpha_u[i] = fmax(alpha_u[i] + hdt * pdiv[6 * cap_n + i], alpha_u_min);
+  }
 }
 
 // grid (blocks per member, members); a in key order, where member m holds
@@ -276,6 +308,11 @@ tsph_status tsph_impl_finish(Ctx *c, tsph_state *s, hipStream_t st) {
   A.gamma = c->p.gamma;
   A.xsph_eta = c->p.xsph_eta;
   A.entropy = c->p.entropy;
+  A.av = c->av;
+  A.alpha_switch = c->p.alpha_switch;
+  A.conduction = c->p.conduction;
+  A.alpha_min = c->p.alpha_min;
+  A.alpha_u_min = c->p.alpha_u_min;
   hipLaunchKernelGGL(k_finish, dim3(blocks_for(c->n, 256, 1 << 20)), dim3(256), 0, st, A);
   // time-step of each member kept on the device for tsph_timestep
   const Members M = members_of(c, c->n, c->n_gas);
@@ -291,7 +328,8 @@ tsph_status tsph_impl_kick_drift(Ctx *c, tsph_state *s, double dt, const double 
   hipLaunchKernelGGL(k_kick_drift, dim3(blocks_for(s->n, 256, 1 << 20)), dim3(256), 0, st,
                      members_of(c, s->n, s->n_gas), dt, phase, s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->ax, s->ay, s->az, s->dudt, s->vpx,
                      s->vpy, s->vpz, s->up, s->h, s->eps, c->pdiv_n == s->n ? c->pdiv : nullptr, c->cap_n,
-                     dt_dev, c->p.xsph_eta > 0.0 ? 1 : 0);
+                     dt_dev, c->p.xsph_eta > 0.0 ? 1 : 0, c->p.alpha_switch ? s->alpha : nullptr,
+                     c->p.conduction ? s->alpha_u : nullptr, c->p.alpha_min, c->p.alpha_u_min);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

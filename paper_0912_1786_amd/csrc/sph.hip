@@ -20,7 +20,13 @@
 // (gamma - 1) rho^(1 - gamma) (Sect. 3.4, Eq. SPHentr); the X-SPH velocity
 // correction eta sum_j m_j (v_j - v_i) Wbar_ij / rhobar (Sect. 3.5, Eq.
 // xsph).  Every pair also gives the signal velocity 2 cbar - min(w, 0),
-// whose largest value per particle is kept.
+// whose largest value per particle is kept.  Dissipation switches (Sect.
+// 3.3.1, 3.3.2): a first pass over the same pairs (mode 1) forms the
+// velocity curl, the Balsara factor f = |div v| / (|div v| + |curl v| +
+// 1e-4 c/h) and the record (alpha, alpha_u, f, u) of every gas particle;
+// the force pass then takes the pair mean of alpha, multiplies Pi_ij by the
+// pair mean of f, and adds the conductivity term m_j Pi^u_ij |Gbar_ij| to
+// du/dt and the Laplacian of u to its own sum.
 //
 // One wavefront per walk group that holds gas; the wave walks the tree once
 // (opening nodes with gas within 2 max(h_group, h_node) of the group box),
@@ -78,6 +84,10 @@ struct SphArgs {
   int32_t dbg_max;
   double alpha, beta, av_eps2, gamma, xsph_eta;
   int32_t tc92, visc_signal, entropy;
+  // dissipation switches
+  int32_t f2, balsara, alpha_switch, conduction;
+  double4 *srec2;      // alpha, alpha_u, Balsara factor, u (gas, key order)
+  const double2 *av;   // alpha, alpha_u (key order)
   // hand-off of flushes (0 split_particles: none); the buffers are those of
   // the gravity walk's near-field hand-off, free again by now
   int32_t split_particles;
@@ -98,7 +108,9 @@ struct SphLane {
   double fa;   // f_ij = fa + zi / m_j
   double ax, ay, az, du, mumax;
   double duv, vsig;     // viscous heating, largest pair signal velocity
-  double xsx, xsy, xsz; // X-SPH sum (without eta)
+  double xsx, xsy, xsz; // X-SPH sum (without eta); the curl sum in mode 1
+  double lapu;          // Laplacian of u (conduction)
+  double4 e2;           // alpha, alpha_u, Balsara factor, u
   int p, npair, ndbg;
   bool sink;
   int32_t *dbg;
@@ -113,7 +125,8 @@ __device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bo
   L.zi = A.zo[p];
   L.fa = A.srec[p].fa;
   L.ax = L.ay = L.az = L.du = L.mumax = 0.0;
-  L.duv = L.vsig = L.xsx = L.xsy = L.xsz = 0.0;
+  L.duv = L.vsig = L.xsx = L.xsy = L.xsz = L.lapu = 0.0;
+  L.e2 = A.f2 ? A.srec2[p] : make_double4(A.alpha, 0.0, 1.0, 0.0);
   L.npair = 0;
   L.ndbg = 0;
   L.dbg = (A.dbg && sink) ? A.dbg + ((int64_t)1 * A.cap_n + A.perm[p]) * A.dbg_max : nullptr;
@@ -121,6 +134,9 @@ __device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bo
 
 // Pairs of the lane's sink among the nt staged candidates: the distance
 // tests of the whole tile first, then the lane's own pairs in tile order.
+// kMode 0: forces and heating; kMode 1: the velocity curl sum
+// sum_j v_ij x grad_i W_ij(h_i) (plain kernel gradient) in xsx, xsy, xsz.
+template <int kMode>
 __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const SphTile &T, int nt, bool tc) {
   const double hi = L.hd.x;
   uint64_t mask = tile_mask(nt, [&](int j) {
@@ -147,6 +163,14 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
     if (!(r2 > 0.0)) continue;
     const double ir = rsq64(r2);
     const double r = r2 * ir;
+    if constexpr (kMode == 1) {
+      const double g = m4_dw(r * ihi) * ihi4 * ir;  // dW/dr(r, h_i) / r, zero beyond 2 h_i
+      const double vx = L.v.x - b.vx, vy = L.v.y - b.vy, vz = L.v.z - b.vz;
+      L.xsx += g * (vy * dz - vz * dy);
+      L.xsy += g * (vz * dx - vx * dz);
+      L.xsz += g * (vx * dy - vy * dx);
+      continue;
+    }
     const double ihj2 = b.ih * b.ih;
     const double gi = m4_grad(r * ihi, tc) * ihi4 * ir;
     const double gj = m4_grad(r * b.ih, tc) * (ihj2 * ihj2 * kInvPiS) * ir;
@@ -165,8 +189,12 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
     if (vd < 0.0) {
       const double hb = 0.5 * (hi + b.h);
       const double mu = hb * vd / (r2 + A.av_eps2 * hb * hb);
-      const double Pi = A.visc_signal ? -A.alpha * (2.0 * cb - w) * w / rb
-                                      : (-A.alpha * cb * mu + A.beta * mu * mu) / rb;
+      // per-particle alpha: the pair mean replaces alpha; Balsara: times the
+      // pair mean of f (Sect. 3.3.1)
+      const double4 e2j = A.f2 ? A.srec2[q] : make_double4(A.alpha, 0.0, 1.0, 0.0);
+      const double al = A.alpha_switch ? 0.5 * (L.e2.x + e2j.x) : A.alpha;
+      double Pi = A.visc_signal ? -al * (2.0 * cb - w) * w / rb : (-al * cb * mu + A.beta * mu * mu) / rb;
+      if (A.balsara) Pi *= 0.5 * (L.e2.z + e2j.z);
       const double Gb = 0.5 * (fij * gi + fji * gj);
       sf += mj * Pi * Gb;
       const double ev = 0.5 * mj * Pi * Gb * vd;
@@ -175,6 +203,17 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
       L.mumax = fmax(L.mumax, fabs(mu));
     }
     L.vsig = fmax(L.vsig, 2.0 * cb - fmin(w, 0.0));
+    if (A.conduction) {
+      // artificial conductivity (Sect. 3.3.2) through |Gbar| = |Gb| r, and
+      // Brookshaw's Laplacian of u
+      const double4 e2j = A.srec2[q];
+      const double Gbm = fabs(0.5 * (fij * gi + fji * gj)) * r;
+      const double du_ij = L.e2.w - e2j.w;
+      const double Pd = L.hd.w * L.hd.y * L.hd.y - b.pr2 * b.rho * b.rho;  // P_i - P_j
+      const double Piu = -0.5 * (L.e2.y + e2j.y) * sqrt(fabs(Pd) / rb) * du_ij / rb;
+      e += mj * Piu * Gbm;
+      L.lapu -= 2.0 * mj * du_ij / b.rho * Gbm * ir;
+    }
     if (A.xsph_eta > 0.0) {
       double wi, dwi, wj, dwj;
       m4(r * ihi, wi, dwi);
@@ -221,7 +260,7 @@ struct SphRangeSrc {
 
 // Pairs of the lane's sink with the particles of ranges [0, n), packed 64
 // to a tile in range order.  Returns the number of particles scanned.
-template <class Src>
+template <int kMode = 0, class Src>
 __device__ __forceinline__ int sph_ranges(const SphArgs &A, SphLane &L, SphTile &T, const Src &src, int n, bool tc) {
   const int ln = lane();
   int fill = 0, rq = 0, scanned = 0;
@@ -239,7 +278,7 @@ __device__ __forceinline__ int sph_ranges(const SphArgs &A, SphLane &L, SphTile 
         off += tk;
         if (fill == kWave) {
           stage_sph(A, T, kWave, rq);
-          tile_pairs(A, L, T, kWave, tc);
+          tile_pairs<kMode>(A, L, T, kWave, tc);
           fill = 0;
         }
       }
@@ -247,11 +286,12 @@ __device__ __forceinline__ int sph_ranges(const SphArgs &A, SphLane &L, SphTile 
   }
   if (fill > 0) {
     stage_sph(A, T, fill, rq);
-    tile_pairs(A, L, T, fill, tc);
+    tile_pairs<kMode>(A, L, T, fill, tc);
   }
   return scanned;
 }
 
+template <int kMode>
 __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
   __shared__ int s_stack[kSStackCap];
   __shared__ int s_leaf[kSListCap];
@@ -355,7 +395,7 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
               atomicOr(A.flags, TSPH_FLAG_HANDOFF_CAPACITY);
             }
           }
-          if (!handed) done += sph_ranges(A, L, s_t, SphLeafSrc{A.topo, s_leaf}, nleaf, tc);
+          if (!handed) done += sph_ranges<kMode>(A, L, s_t, SphLeafSrc{A.topo, s_leaf}, nleaf, tc);
           nleaf = 0;
         }
         __syncthreads();
@@ -363,7 +403,20 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
       }
       if (overflow) atomicOr(A.flags, TSPH_FLAG_STACK_OVERFLOW);
       if (L.dbg && L.ndbg > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
-      if (L.sink) {
+      if (kMode == 1 && L.sink) {
+        // curl with the divergence's normalisation, Balsara factor, record
+        const double nom = A.solve[kNh * A.cap_n + p] * A.solve[kOmega * A.cap_n + p];
+        const double cx = L.xsx / nom, cy = L.xsy / nom, cz = L.xsz / nom;
+        A.solve[kCurlx * A.cap_n + p] = cx;
+        A.solve[kCurly * A.cap_n + p] = cy;
+        A.solve[kCurlz * A.cap_n + p] = cz;
+        const double dv = fabs(A.solve[kDivv * A.cap_n + p]);
+        const double fb = dv / (dv + sqrt(cx * cx + cy * cy + cz * cz) + 1e-4 * L.hd.z / L.hd.x);
+        A.solve[kFbal * A.cap_n + p] = fb;
+        const double2 al = A.av[p];
+        A.srec2[p] = make_double4(A.alpha_switch ? al.x : A.alpha, al.y, fb, L.v.w);
+      }
+      if (kMode == 0 && L.sink) {
         A.acc[0 * A.cap_n + p] += L.ax;
         A.acc[1 * A.cap_n + p] += L.ay;
         A.acc[2 * A.cap_n + p] += L.az;
@@ -374,6 +427,7 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
         A.solve[kXsx * A.cap_n + p] = L.xsx;
         A.solve[kXsy * A.cap_n + p] = L.xsy;
         A.solve[kXsz * A.cap_n + p] = L.xsz;
+        A.solve[kLapu * A.cap_n + p] = L.lapu;
         A.cnt[2 * A.cap_n + A.perm[p]] = L.npair;
       }
     }
@@ -408,7 +462,7 @@ __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
     double4 *part = A.split_part + (int64_t)kSphPart * it * kWave;
     part[ln] = make_double4(L.ax, L.ay, L.az, L.du);
     part[kWave + ln] = make_double4(L.mumax, (double)L.npair, L.duv, L.vsig);
-    part[2 * kWave + ln] = make_double4(L.xsx, L.xsy, L.xsz, 0.0);
+    part[2 * kWave + ln] = make_double4(L.xsx, L.xsy, L.xsz, L.lapu);
   }
 }
 
@@ -439,6 +493,7 @@ __global__ __launch_bounds__(64) void k_sph_reduce(SphArgs A) {
         A.solve[kXsx * A.cap_n + p] += x.x;
         A.solve[kXsy * A.cap_n + p] += x.y;
         A.solve[kXsz * A.cap_n + p] += x.z;
+        A.solve[kLapu * A.cap_n + p] += x.w;
       }
       it = I.next;
     }
@@ -456,8 +511,29 @@ __global__ __launch_bounds__(256) void k_zero_sph(int64_t n, int64_t cap_n, doub
     solve[kXsx * cap_n + p] = 0.0;
     solve[kXsy * cap_n + p] = 0.0;
     solve[kXsz * cap_n + p] = 0.0;
+    solve[kLapu * cap_n + p] = 0.0;
+    solve[kCurlx * cap_n + p] = 0.0;
+    solve[kCurly * cap_n + p] = 0.0;
+    solve[kCurlz * cap_n + p] = 0.0;
+    solve[kFbal * cap_n + p] = 1.0;
     cnt[2 * cap_n + perm[p]] = 0;
   }
+}
+
+// alpha and alpha_u of the state (caller order; NULL: the fixed alpha, 0)
+// gathered into key order
+__global__ __launch_bounds__(256) void k_gather_alpha(int64_t n, const int32_t *__restrict__ perm,
+                                                      const double *__restrict__ alpha,
+                                                      const double *__restrict__ alpha_u, double2 *__restrict__ av) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const int i = perm[p];
+    av[p] = make_double2(alpha ? alpha[i] : 0.0, alpha_u ? alpha_u[i] : 0.0);
+  }
+}
+
+// zero k work-queue counters (the curl pass used the SPH walk's queues)
+__global__ void k_reset_counter(int32_t *ctr, int k) {
+  if ((int)threadIdx.x < k) ctr[threadIdx.x] = 0;
 }
 
 }  // namespace tsph
@@ -504,6 +580,12 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   A.xsph_eta = c->p.xsph_eta;
   A.visc_signal = c->p.visc_form == TSPH_VISC_SIGNAL;
   A.entropy = c->p.entropy;
+  A.balsara = c->p.balsara;
+  A.alpha_switch = c->p.alpha_switch;
+  A.conduction = c->p.conduction;
+  A.f2 = (A.balsara || A.alpha_switch || A.conduction) ? 1 : 0;
+  A.srec2 = c->srec2;
+  A.av = c->av;
   // debug lists are written in the batch's own order: no hand-off then.  The
   // SPH pairs cost more per candidate than the near-field gravity pairs, so
   // the batch keeps a quarter of the gravity walk's share.
@@ -516,7 +598,17 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   if (A.split_particles > 0)
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(c->cap_nodes, 256, 4096)), dim3(256), 0, st, c->cap_nodes,
                        c->split_head, -1);
-  hipLaunchKernelGGL(k_sph, dim3(persistent_blocks(c, (const void *)k_sph)), dim3(64), 0, st, A);
+  if (A.f2) {
+    // the switches' inputs in key order, then the curl pass (its own walk,
+    // no hand-off), then the forces
+    hipLaunchKernelGGL(k_gather_alpha, dim3(blocks_for(c->n, 256, 8192)), dim3(256), 0, st, c->n, c->perm,
+                       c->alpha_state, c->alpha_u_state, c->av);
+    SphArgs Ac = A;
+    Ac.split_particles = 0;
+    hipLaunchKernelGGL(k_sph<1>, dim3(persistent_blocks(c, (const void *)k_sph<1>)), dim3(64), 0, st, Ac);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, A.work + 24, 8);
+  }
+  hipLaunchKernelGGL(k_sph<0>, dim3(persistent_blocks(c, (const void *)k_sph<0>)), dim3(64), 0, st, A);
   if (A.split_particles > 0) {
     hipLaunchKernelGGL(k_sph_split, dim3(persistent_blocks(c, (const void *)k_sph_split)), dim3(64), 0, st, A);
     hipLaunchKernelGGL(k_sph_reduce, dim3(4096), dim3(64), 0, st, A);

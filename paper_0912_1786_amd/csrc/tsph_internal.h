@@ -121,10 +121,10 @@ inline int64_t heavy_batch_cap(int64_t cap_nodes) { return cap_nodes < 4096 ? 40
 // sums and factors, and the SPH pass's largest |mu|, largest signal
 // velocity, viscous heating and X-SPH sum
 // rows of the carry from one force pass to the next drift (caller order)
-constexpr int kCarryRows = 5;
+constexpr int kCarryRows = 7;  // + the rates of alpha and alpha_u
 
 enum SolveField { kNh = 0, kOmega, kZeta, kDivv, kNeps, kUps, kXi, kMaxmu, kDivvE, kVsig, kDuv, kXsx, kXsy, kXsz,
-                  kNumSolve };
+                  kCurlx, kCurly, kCurlz, kFbal, kLapu, kNumSolve };
 
 struct Ctx {
   int device;
@@ -150,6 +150,9 @@ struct Ctx {
   double2 *soft;          // eps, xi / Upsilon
   GravRec *grec;          // gravity source records
   SphRec *srec;           // SPH source records (gas entries)
+  double4 *srec2;         // dissipation switches: alpha, alpha_u, Balsara factor, u (gas entries)
+  double2 *av;            // alpha, alpha_u gathered into key order
+  const double *alpha_state, *alpha_u_state;  // the state's arrays of the current force pass (caller order)
   double *solve;          // kNumSolve x cap_n
   double *pdiv;           // kCarryRows x cap_n, caller order: div v with the h kernel (gas) and the eps
                           // kernel, the X-SPH velocity correction (3 rows)

@@ -28,7 +28,7 @@ import numpy as np
 from . import inputs, tsph
 
 HOST_KEYS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "vpx", "vpy", "vpz", "up", "h", "eps", "ax", "ay", "az",
-             "dudt", "rho")
+             "dudt", "rho", "alpha", "alpha_u")
 
 
 def population(n_sim: int = 64, seed: int = 2000, lo_log2: float = 12.0, hi_log2: float = 20.0):

@@ -27,7 +27,7 @@ FLAG_HANDOFF_CAPACITY = 0x40
 DBG_KEYS, DBG_PERM, DBG_NODES, DBG_NNODES, DBG_MOMENTS, DBG_GROUPS, DBG_NGROUPS, DBG_COUNTS, DBG_NBR, DBG_ROOT, \
     DBG_SOLVE, DBG_BATCHES, DBG_NBATCHES = range(13)
 SOLVE_FIELDS = ("nh", "omega", "zeta", "divv", "neps", "ups", "xi", "maxmu", "divv_eps", "vsig", "duv", "xsph_sx",
-                "xsph_sy", "xsph_sz")
+                "xsph_sy", "xsph_sz", "curlx", "curly", "curlz", "fbal", "lapu")
 
 
 class TsphError(RuntimeError):
@@ -45,7 +45,9 @@ class Params(C.Structure):
                 ("hydro", C.c_int32), ("split_leaves", C.c_int32), ("eta_dt", C.c_double),
                 ("max_members", C.c_int32), ("grav_corr_literal", C.c_int32), ("soften_cells", C.c_int32),
                 ("visc_form", C.c_int32), ("entropy", C.c_int32), ("xsph_eta", C.c_double),
-                ("h_scheme", C.c_int32), ("h_weight", C.c_int32)]
+                ("h_scheme", C.c_int32), ("h_weight", C.c_int32), ("balsara", C.c_int32),
+                ("alpha_switch", C.c_int32), ("conduction", C.c_int32), ("alpha_min", C.c_double),
+                ("alpha_u_min", C.c_double)]
 
 
 _P = C.c_void_p
@@ -55,7 +57,8 @@ class State(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_gas", C.c_int64),
                 ("x", _P), ("y", _P), ("z", _P), ("vx", _P), ("vy", _P), ("vz", _P), ("m", _P), ("u", _P),
                 ("vpx", _P), ("vpy", _P), ("vpz", _P), ("up", _P), ("h", _P), ("eps", _P),
-                ("ax", _P), ("ay", _P), ("az", _P), ("dudt", _P), ("rho", _P), ("pot", _P)]
+                ("ax", _P), ("ay", _P), ("az", _P), ("dudt", _P), ("rho", _P), ("pot", _P),
+                ("alpha", _P), ("alpha_u", _P)]
 
 
 _LIB = None
@@ -331,7 +334,7 @@ class Simulation:
     """
 
     FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "vpx", "vpy", "vpz", "up", "h", "eps", "ax", "ay", "az",
-              "dudt", "rho", "pot")
+              "dudt", "rho", "pot", "alpha", "alpha_u")
 
     def __init__(self, ic: dict, params: Params | None = None, capacity: int | None = None, device: str = "cuda",
                  want_pot: bool = True, eps_const=None, members=None, ctx=None, bufs=None):
@@ -367,6 +370,10 @@ class Simulation:
         self.a["eps"] = z("eps") if eps_const is None else t(eps_const, "eps")
         for k in ("ax", "ay", "az", "dudt", "rho"):
             self.a[k] = z(k)
+        # dissipation coefficients: alpha from the parameters, alpha_u zero,
+        # unless the initial conditions give them
+        self.a["alpha"] = t(ic["alpha"], "alpha") if "alpha" in ic else z("alpha").fill_(self.params.alpha)
+        self.a["alpha_u"] = t(ic["alpha_u"], "alpha_u") if "alpha_u" in ic else z("alpha_u")
         self.a["pot"] = z("pot") if want_pot else None
         self.owns_ctx = ctx is None
         self.ctx = ctx if ctx is not None else tsph_create(capacity or self.n, self.params)

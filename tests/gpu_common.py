@@ -19,7 +19,8 @@ def oracle_params(orc, gp, walk_mode=None):
                       nbr_mode=orc.NBR_TREE, gravity=gp.gravity, hydro=gp.hydro, batch_size=64,
                       batch_mode=0, grav_corr_literal=gp.grav_corr_literal, soften_cells=gp.soften_cells,
                       visc_form=gp.visc_form, entropy=gp.entropy, xsph_eta=gp.xsph_eta, h_scheme=gp.h_scheme,
-                      h_weight=gp.h_weight)
+                      h_weight=gp.h_weight, balsara=gp.balsara, alpha_switch=gp.alpha_switch,
+                      alpha_min=gp.alpha_min, conduction=gp.conduction, alpha_u_min=gp.alpha_u_min)
 
 
 def run_gpu(ic, gp, lists=0, eps_const=None):
@@ -28,7 +29,7 @@ def run_gpu(ic, gp, lists=0, eps_const=None):
         tsph.tsph_debug_lists(sim.ctx, lists)
     sim.compute_forces()
     flags, noconv = sim.flags()
-    out = {k: sim.host(k) for k in ("ax", "ay", "az", "dudt", "rho", "pot", "h", "eps")}
+    out = {k: sim.host(k) for k in ("ax", "ay", "az", "dudt", "rho", "pot", "h", "eps", "alpha", "alpha_u")}
     n = ic["n"]
     nf = len(tsph.SOLVE_FIELDS)
     solve = sim.export(tsph.DBG_SOLVE, np.float64, nf * n).reshape(nf, n)

@@ -53,11 +53,12 @@ def test_param_struct_layout_matches_header(T):
     import ctypes as C
     # field order and padding of tsph_params / tsph_state as declared
     # ... max_members, grav_corr_literal, soften_cells, visc_form, entropy
-    # (int32), xsph_eta (double), h_scheme, h_weight (int32)
-    assert C.sizeof(T.Params) == 8 * 2 + 4 * 2 + 8 * 6 + 4 * 2 + 8 * 2 + 4 * 6 + 8 + 4 * 5 + 4 + 8 + 4 * 2
-    assert T.Params.h_weight.offset == C.sizeof(T.Params) - 4
-    assert T.Params.xsph_eta.offset % 8 == 0
-    assert C.sizeof(T.State) == 8 * 2 + 8 * 20
+    # (int32), xsph_eta (double), h_scheme, h_weight, balsara, alpha_switch,
+    # conduction (int32), alpha_min, alpha_u_min (double)
+    assert C.sizeof(T.Params) == 8 * 2 + 4 * 2 + 8 * 6 + 4 * 2 + 8 * 2 + 4 * 6 + 8 + 4 * 5 + 4 + 8 + 4 * 5 + 4 + 8 * 2
+    assert T.Params.alpha_u_min.offset == C.sizeof(T.Params) - 8
+    assert T.Params.xsph_eta.offset % 8 == 0 and T.Params.alpha_min.offset % 8 == 0
+    assert C.sizeof(T.State) == 8 * 2 + 8 * 22
 
 
 def test_probe_argument_checks(T):
