@@ -1695,7 +1695,9 @@ double orc_timestep_each(const orc_params *p, int64_t n, int64_t n_gas, const do
   for (int64_t i = 0; i < n; i++) {
     double dt = INFINITY;
     double amag = sqrt(ax[i] * ax[i] + ay[i] * ay[i] + az[i] * az[i]);
-    double len = eps ? eps[i] : INFINITY;
+    /* min(eps, h) over the lengths the particle has: a softening that is
+     * not positive (no gravity) drops out */
+    double len = (eps && eps[i] > 0.0) ? eps[i] : INFINITY;
     if (i < n_gas && h && h[i] < len) len = h[i];
     if (amag > 0.0 && len < INFINITY) {
       double t = eta_dt * sqrt(len / amag);
