@@ -278,11 +278,11 @@ tsph_status tsph_kick_drift_dt(void *ctx, tsph_state *s, const double *dt_device
  * independent simulations advanced by one graph launch per step). */
 tsph_status tsph_batch_step(void *ctx, tsph_state *s, double *dt_device, void *stream);
 
-/* The carry of a context from one step to the next: the global time-step
- * of the last force pass, the velocity divergences with which the next
- * drift carries h and eps, the X-SPH velocity correction of that drift and
- * the rates of alpha and alpha_u for the next kicks (7 n + 1 doubles for n
- * particles).  Saving it and
+/* The carry of a context from one step to the next: the velocity
+ * divergences with which the next drift carries h and eps, the X-SPH
+ * velocity correction of that drift, the rates of alpha and alpha_u for the
+ * next kicks and the largest |mu_ij| per particle for the Courant criterion
+ * (8 n doubles for n particles).  Saving it and
  * loading it into a context (the same or a new one) lets a simulation leave
  * the device between steps and continue bit for bit: after tsph_carry_load
  * the next tsph_timestep / tsph_kick_drift behave as if the force pass had
@@ -315,10 +315,60 @@ tsph_status tsph_diagnostics_noalloc(const tsph_state *s, int32_t count, const i
                                      const int64_t *ngas_device, double *out_device, void *stream);
 const char *tsph_noalloc_last_error(void);
 
-/* Global time-step (Sect. 4.2) from the last tsph_compute_forces: min over
- * particles of eta_dt sqrt(min(eps,h)/|a|), the Courant criterion and
- * eta_dt |u / du/dt|.  Writes one double per system held to dt_device. */
+/* Global time-step (Sect. 4.2): the minimum over particles of
+ * eta_dt sqrt(min(eps, h)/|a|) (a non-positive eps, as without gravity, drops
+ * out of the min), the Courant criterion
+ * eta_dt h / (h |div v| + c + 1.2 (alpha c + beta max_j |mu_ij|)) and
+ * eta_dt |u / du/dt|, taken from the state as it stands (call it at the end
+ * of a step, after the closing kick and before the next drift: u, c, a,
+ * du/dt, h, eps, rho and alpha of the state, div v and max |mu| of the last
+ * force pass).  Writes one double per system held to dt_device. */
 tsph_status tsph_timestep(void *ctx, const tsph_state *s, double *dt_device, void *stream);
+
+/* Individual power-of-two time-steps (Sect. 4.2.1) of a context holding one
+ * system.  Time runs in integer ticks: the largest step dt_max is 2^max_level
+ * ticks.  Particle i steps with dt_max / 2^n_i, the largest such step not
+ * above its criteria (those of tsph_timestep, n_i <= max_level), shortened to
+ * divide the current tick (a longer step only where synchronised).  Each
+ * step is a kick-drift-kick leapfrog of the particle's own length; all
+ * particles drift to every system time with their half-kicked velocities;
+ * the system time advances to the earliest step end, where the particles
+ * whose steps end are active.  A force pass evaluates gravity and the SPH
+ * sums for the active particles only (walk chunks without an active sink are
+ * skipped) and solves the lengths and densities of all gas particles (their
+ * neighbours at the current time); inactive particles lend the predicted
+ * velocity v_n + a_n (t - t_n) and energy u_n + du_n (t - t_n) of their last
+ * synchronised state.  Wake-up (wake = f > 0, a power of two): an active gas
+ * particle's step is at most f times the shortest current step among its SPH
+ * neighbours (r_ij < 2 max(h_i, h_j)); an inactive gas particle whose step is
+ * longer than f times the shortest criterion step w of its active neighbours
+ * ends at the current time plus w, its opening half kick redone for the
+ * shorter step from its synchronised state (its drift so far is kept).
+ * The caller owns the device arrays (n entries, caller order); the library
+ * updates them and the host fields t, n_active, n_woken. */
+typedef struct {
+  double dt_max;          /* largest step (> 0)                                  */
+  int32_t max_level;      /* dt_max = 2^max_level ticks, 0..30                   */
+  int32_t wake;           /* wake-up factor f: 0 (off) or a power of two <= 64   */
+  int64_t t;              /* host: system time in ticks, in [0, 2^max_level);     *
+                           * 0 at every synchronisation point                    */
+  int64_t n_active;       /* host: particles evaluated by the last call           */
+  int64_t n_woken;        /* host: particles woken by the last call               */
+  int32_t *t0, *t1;       /* device: step start and end of each particle (ticks)  */
+  double *vsx, *vsy, *vsz, *us;  /* device: v and u at the step start            */
+} tsph_blocks;
+/* First system time (t = 0): every particle active.  Takes x, v, u of the
+ * state as the initial condition (v^p = v, u^p = u; h and eps as in
+ * tsph_compute_forces), runs a force pass, chooses the steps (with the
+ * wake-up) and gives the opening half kicks.  Synchronous (waits for the
+ * stream).  TSPH_EINVAL for missing arrays, a bad dt_max, max_level or wake,
+ * or a context holding several systems. */
+tsph_status tsph_block_start(void *ctx, tsph_state *s, tsph_blocks *b, void *stream);
+/* Advance to the next system time: drift every particle there, evaluate the
+ * active ones, close their steps, choose their next steps (wake-up included)
+ * and open them.  Synchronous: the earliest step end is read back to the
+ * host (b->t, b->n_active and b->n_woken are set on return). */
+tsph_status tsph_block_advance(void *ctx, tsph_state *s, tsph_blocks *b, void *stream);
 /* FP64 totals: out_device[0..8] = E_kin, E_th, V (= 1/2 sum m pot), Px, Py,
  * Pz, Lx, Ly, Lz; nine per system held (system k at out_device[9k]).
  * Needs s->pot from the last force pass. */

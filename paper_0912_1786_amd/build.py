@@ -21,7 +21,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 OUT = os.path.join(HERE, "libtsph.so")
-SOURCES = ["tree.hip", "density.hip", "gravity.hip", "sph.hip", "integrate.hip", "probe.hip", "abi.hip"]
+SOURCES = ["tree.hip", "density.hip", "gravity.hip", "sph.hip", "integrate.hip", "blocks.hip", "probe.hip", "abi.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall",
          "-Wno-unused-result", "-Wno-unknown-pragmas"]

@@ -132,6 +132,14 @@ size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->add(4 * 16);                    // 35 noconv
   L->add(8 * 9 * std::max<int64_t>(1024, kMemberBlocks * S));  // 36 red
   L->add(8 * std::max<int64_t>(16, S));                         // 37 dt
+  // individual time-steps
+  L->add(N);            // bact
+  L->add(N);            // bact_s
+  L->add(4 * N);        // bcur
+  L->add(4 * N);        // bcur_s
+  L->add(4 * N);        // bm
+  L->add(4 * N);        // bw
+  L->add(4 * 16);       // bnext
   return L->total;
 }
 
@@ -191,6 +199,20 @@ tsph_status check_state(Ctx *c, const tsph_state *s, bool forces) {
     if (s->n_gas > 0 && c->p.hydro && ((c->p.alpha_switch && !s->alpha) || (c->p.conduction && !s->alpha_u)))
       return set_err(c, TSPH_EINVAL, "alpha_switch needs alpha and conduction needs alpha_u");
   }
+  return TSPH_OK;
+}
+
+// fields the time-step criteria read, after a force pass with this n
+tsph_status check_timestep_state(Ctx *c, const tsph_state *s) {
+  if (!s || s->n < 1 || s->n_gas < 0 || s->n_gas > s->n) return set_err(c, TSPH_EINVAL, "bad state sizes");
+  if (s->n > c->cap_n) return set_err(c, TSPH_ECAPACITY, "n exceeds the context capacity");
+  if (tsph_status r = check_members(c, s)) return r;
+  if (!s->ax || !s->ay || !s->az) return set_err(c, TSPH_EINVAL, "ax, ay, az are required");
+  if (s->n_gas > 0 && (!s->h || !s->u || !s->dudt || !s->rho))
+    return set_err(c, TSPH_EINVAL, "gas needs h, u, dudt and rho");
+  if (c->p.alpha_switch && s->n_gas > 0 && !s->alpha) return set_err(c, TSPH_EINVAL, "alpha_switch needs alpha");
+  if (c->p.gravity && !s->eps) return set_err(c, TSPH_EINVAL, "eps is required with gravity");
+  if (c->pdiv_n != s->n) return set_err(c, TSPH_EINVAL, "no force pass with this n");
   return TSPH_OK;
 }
 
@@ -337,6 +359,13 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->noconv = AT(int32_t *);
   c->red = AT(double *);
   c->dt = AT(double *);
+  c->bact = AT(uint8_t *);
+  c->bact_s = AT(uint8_t *);
+  c->bcur = AT(int32_t *);
+  c->bcur_s = AT(int32_t *);
+  c->bm = AT(int32_t *);
+  c->bw = AT(int32_t *);
+  c->bnext = AT(int32_t *);
 #undef AT
   c->perm = c->idx[0];
   e = hipHostMalloc((void **)&c->h_flags, 64, hipHostMallocDefault);
@@ -464,6 +493,7 @@ tsph_status tsph_compute_forces(void *ctx, tsph_state *s, void *stream) {
   if (c->dbg_nbr)
     hipLaunchKernelGGL(k_fill_dbg, dim3(1024), dim3(256), 0, st, (int64_t)3 * c->cap_n * c->dbg_max, c->dbg_nbr);
   if ((r = tsph_impl_build_tree(c, s, st)) != TSPH_OK) return r;
+  if (c->blk_on && (r = tsph_impl_gather_active(c, st)) != TSPH_OK) return r;
   MARK(1);
   if ((r = tsph_impl_density(c, st)) != TSPH_OK) return r;
   MARK(2);
@@ -523,7 +553,7 @@ static tsph_status kick_drift_checks(Ctx *c, tsph_state *s, int32_t phase) {
 
 tsph_status tsph_carry_bytes(int64_t n, size_t *bytes) {
   if (!bytes || n < 1) return TSPH_EINVAL;
-  *bytes = sizeof(double) * (kCarryRows * (size_t)n + 1);
+  *bytes = sizeof(double) * (kCarryRows * (size_t)n);
   return TSPH_OK;
 }
 
@@ -535,9 +565,8 @@ tsph_status tsph_carry_save(void *ctx, int64_t n, void *dst_device, void *stream
   if (n < 1 || n != c->pdiv_n) return set_err(c, TSPH_EINVAL, "no force pass with this n to save");
   hipStream_t st = (hipStream_t)stream;
   double *d = (double *)dst_device;
-  TSPH_HIP_CHECK(c, hipMemcpyAsync(d, c->dt, sizeof(double), hipMemcpyDeviceToDevice, st));
   for (int k = 0; k < kCarryRows; k++)
-    TSPH_HIP_CHECK(c, hipMemcpyAsync(d + 1 + k * n, c->pdiv + k * c->cap_n, sizeof(double) * n,
+    TSPH_HIP_CHECK(c, hipMemcpyAsync(d + k * n, c->pdiv + k * c->cap_n, sizeof(double) * n,
                                      hipMemcpyDeviceToDevice, st));
   return TSPH_OK;
 }
@@ -550,9 +579,8 @@ tsph_status tsph_carry_load(void *ctx, int64_t n, const void *src_device, void *
   if (n < 1 || n > c->cap_n) return set_err(c, TSPH_ECAPACITY, "n exceeds the context capacity");
   hipStream_t st = (hipStream_t)stream;
   const double *d = (const double *)src_device;
-  TSPH_HIP_CHECK(c, hipMemcpyAsync(c->dt, d, sizeof(double), hipMemcpyDeviceToDevice, st));
   for (int k = 0; k < kCarryRows; k++)
-    TSPH_HIP_CHECK(c, hipMemcpyAsync(c->pdiv + k * c->cap_n, d + 1 + k * n, sizeof(double) * n,
+    TSPH_HIP_CHECK(c, hipMemcpyAsync(c->pdiv + k * c->cap_n, d + k * n, sizeof(double) * n,
                                      hipMemcpyDeviceToDevice, st));
   c->pdiv_n = n;
   return TSPH_OK;
@@ -589,7 +617,8 @@ tsph_status tsph_batch_step(void *ctx, tsph_state *s, double *dt_device, void *s
   if ((r = kick_drift_checks(c, s, TSPH_KD_FIRST)) != TSPH_OK) return r;
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
-  if ((r = tsph_impl_timestep(c, dt_device, st)) != TSPH_OK) return r;
+  if ((r = check_timestep_state(c, s)) != TSPH_OK) return r;
+  if ((r = tsph_impl_timestep(c, s, dt_device, st)) != TSPH_OK) return r;
   if ((r = tsph_impl_kick_drift(c, s, 0.0, dt_device, TSPH_KD_FIRST, st)) != TSPH_OK) return r;
   if ((r = tsph_compute_forces(ctx, s, stream)) != TSPH_OK) return r;
   return tsph_impl_kick_drift(c, s, 0.0, dt_device, TSPH_KD_SECOND, st);
@@ -598,10 +627,11 @@ tsph_status tsph_batch_step(void *ctx, tsph_state *s, double *dt_device, void *s
 tsph_status tsph_timestep(void *ctx, const tsph_state *s, double *dt_device, void *stream) {
   Ctx *c = (Ctx *)ctx;
   if (!c || !dt_device) return TSPH_EINVAL;
-  (void)s;
+  tsph_status r = check_timestep_state(c, s);
+  if (r != TSPH_OK) return r;
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
-  return tsph_impl_timestep(c, dt_device, st);
+  return tsph_impl_timestep(c, s, dt_device, st);
 }
 
 tsph_status tsph_diagnostics(void *ctx, const tsph_state *s, double *out_device, void *stream) {

@@ -35,6 +35,7 @@ constexpr double kInvPiG = 0.31830988618379067154;
 
 struct GravArgs {
   int64_t cap_n;
+  const uint8_t *act;  // key order: evaluate chunks holding one of these only (NULL: all)
   const int32_t *groups;
   const int32_t *ngroups;
   const int2 *batches;
@@ -575,6 +576,8 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
     const double cx = 0.5 * (gb.lox + gb.hix), cy = 0.5 * (gb.loy + gb.hiy), cz = 0.5 * (gb.loz + gb.hiz);
     int prev_item = -1;  // last handed-off item of this batch
     for (int c0 = 0; c0 < gnd.count; c0 += kWave) {
+      // individual time-steps: a chunk without an active sink is skipped
+      if (A.act && ballot(c0 + ln < gnd.count && A.act[gnd.first + c0 + ln]) == 0) continue;
       SinkT<F32> s;
       load_sink<F32>(A, s, gnd, c0, cx, cy, cz, true);
       int near_done = 0;  // near-field particles evaluated by this wave
@@ -917,6 +920,7 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
   A.corr = c->p.soft_mode == TSPH_SOFT_ADAPTIVE ? 1 : 0;
   A.lit = c->p.grav_corr_literal;
   A.soften = c->p.soften_cells;
+  A.act = c->blk_on ? c->bact_s : nullptr;
   A.nsoft = c->nsoft;
   A.want_pot = want_pot ? 1 : 0;
   // debug lists are written by the batch's own wave

@@ -21,43 +21,45 @@ struct FinishArgs {
   int64_t n, cap_n;
   const int32_t *perm;
   const uint8_t *gas;
+  const uint8_t *act;  // key order: force outputs of these only (NULL: all)
   const double *acc;
   const double4 *sph;
   const double4 *vu;
   const double *hs, *es, *solve;
-  double *dt_i;
   double *ax, *ay, *az, *pot, *dudt, *rho, *h, *eps;
   double *pdiv;  // kCarryRows x cap_n, caller order
-  double eta_dt, alpha, beta, gamma, xsph_eta;
-  int32_t hydro, entropy;
+  double alpha, gamma, xsph_eta;
+  int32_t entropy;
   // dissipation switches: key-order alpha, alpha_u; floors
   const double2 *av;
   int32_t alpha_switch, conduction;
   double alpha_min, alpha_u_min;
 };
 
+// Key order -> caller order: the lengths, densities and divergences of every
+// particle, the forces and rates of the evaluated ones.
 __global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= A.n) return;
   const int i = A.perm[p];
   const bool g = A.gas[p];
-  const double ax = A.acc[p], ay = A.acc[A.cap_n + p], az = A.acc[2 * A.cap_n + p];
   const double4 s = A.sph[p];
-  // with the entropic function as energy variable its rate is the viscous
-  // heating times (gamma - 1) rho^(1 - gamma) (Sect. 3.4, Eq. SPHentr)
-  const double du = !g ? 0.0
-                       : (A.entropy ? (A.gamma - 1.0) * pow(s.y, 1.0 - A.gamma) * A.solve[kDuv * A.cap_n + p]
-                                    : A.acc[4 * A.cap_n + p]);
-  A.ax[i] = ax;
-  A.ay[i] = ay;
-  A.az[i] = az;
-  if (A.pot) A.pot[i] = A.acc[3 * A.cap_n + p];
-  if (A.dudt) A.dudt[i] = du;
   if (A.rho) A.rho[i] = g ? s.y : 0.0;
   if (A.h) A.h[i] = g ? A.hs[p] : 0.0;
   if (A.eps) A.eps[i] = A.es[p];
   A.pdiv[i] = g ? A.solve[kDivv * A.cap_n + p] : 0.0;
   A.pdiv[A.cap_n + i] = A.solve[kDivvE * A.cap_n + p];
+  if (A.act && !A.act[p]) return;
+  // with the entropic function as energy variable its rate is the viscous
+  // heating times (gamma - 1) rho^(1 - gamma) (Sect. 3.4, Eq. SPHentr)
+  const double du = !g ? 0.0
+                       : (A.entropy ? (A.gamma - 1.0) * pow(s.y, 1.0 - A.gamma) * A.solve[kDuv * A.cap_n + p]
+                                    : A.acc[4 * A.cap_n + p]);
+  A.ax[i] = A.acc[p];
+  A.ay[i] = A.acc[A.cap_n + p];
+  A.az[i] = A.acc[2 * A.cap_n + p];
+  if (A.pot) A.pot[i] = A.acc[3 * A.cap_n + p];
+  if (A.dudt) A.dudt[i] = du;
   // X-SPH velocity correction of the next drift (Sect. 3.5, Eq. xsph)
   A.pdiv[2 * A.cap_n + i] = g ? A.xsph_eta * A.solve[kXsx * A.cap_n + p] : 0.0;
   A.pdiv[3 * A.cap_n + i] = g ? A.xsph_eta * A.solve[kXsy * A.cap_n + p] : 0.0;
@@ -82,22 +84,44 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
   }
   A.pdiv[5 * A.cap_n + i] = da;
   A.pdiv[6 * A.cap_n + i] = dau;
-  // time-step criteria (Sect. 4.2): acceleration, Courant, internal energy
+  A.pdiv[7 * A.cap_n + i] = g ? A.solve[kMaxmu * A.cap_n + p] : 0.0;
+}
+
+struct CritArgs {
+  Members M;
+  const double *ax, *ay, *az, *eps, *h, *u, *dudt, *rho, *alpha;
+  const double *pdiv;
+  int64_t cap_n;
+  double *dt_i;  // caller order
+  double eta_dt, alpha0, beta, gamma;
+  int32_t hydro, entropy;
+};
+
+// Time-step criteria of Sect. 4.2 per particle (caller order) from the
+// state: acceleration, Courant and internal-energy criteria, one eta.
+__global__ __launch_bounds__(256) void k_criteria(CritArgs A) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= A.M.n) return;
+  const bool g = member_gas(A.M, member_of(A.M, i), i);
   double dt = INFINITY;
+  const double ax = A.ax[i], ay = A.ay[i], az = A.az[i];
   const double amag = sqrt(ax * ax + ay * ay + az * az);
-  double len = A.es[p] > 0.0 ? A.es[p] : INFINITY;
-  if (g && A.hs[p] < len) len = A.hs[p];
+  // min(eps, h) over the lengths the particle has (no softening: h alone)
+  double len = (A.eps && A.eps[i] > 0.0) ? A.eps[i] : INFINITY;
+  if (g && A.h[i] < len) len = A.h[i];
   if (amag > 0.0 && len < INFINITY) dt = fmin(dt, A.eta_dt * sqrt(len / amag));
   if (g && A.hydro) {
-    const double c = s.z, hh = s.x;
-    const double divv = A.solve[kDivv * A.cap_n + p], mumax = A.solve[kMaxmu * A.cap_n + p];
-    const double al = A.alpha_switch ? A.av[p].x : A.alpha;
-    const double den = hh * fabs(divv) + c + 1.2 * (al * c + A.beta * mumax);
+    const double u = A.u[i], hh = A.h[i];
+    // with the entropic function A: c^2 = gamma A rho^(gamma - 1) (Sect. 3.4)
+    const double c = A.entropy ? sqrt(A.gamma * u * pow(A.rho[i], A.gamma - 1.0))
+                               : sqrt(A.gamma * (A.gamma - 1.0) * u);
+    const double al = A.alpha ? A.alpha[i] : A.alpha0;
+    const double den = hh * fabs(A.pdiv[i]) + c + 1.2 * (al * c + A.beta * A.pdiv[7 * A.cap_n + i]);
     if (den > 0.0) dt = fmin(dt, A.eta_dt * hh / den);
-    const double u = A.vu[p].w;
+    const double du = A.dudt[i];
     if (du != 0.0) dt = fmin(dt, A.eta_dt * fabs(u / du));
   }
-  A.dt_i[p] = dt;
+  A.dt_i[i] = dt;
 }
 
 // growth factor of a length over a drift of dt, clamped to [1/2, 2]
@@ -176,8 +200,8 @@ __global__ __launch_bounds__(256) void k_kick_drift(Members M, double dt, int ph
   }
 }
 
-// grid (blocks per member, members); a in key order, where member m holds
-// the same range as in caller order
+// grid (blocks per member, members); a in key or caller order (member m
+// holds the same range in both)
 __global__ __launch_bounds__(256) void k_min_partial(Members M, const double *__restrict__ a,
                                                      double *__restrict__ part) {
   __shared__ double s[256];
@@ -285,13 +309,13 @@ tsph_status tsph_impl_finish(Ctx *c, tsph_state *s, hipStream_t st) {
   A.cap_n = c->cap_n;
   A.perm = c->perm;
   A.gas = c->gas;
+  A.act = c->blk_on ? c->bact_s : nullptr;
   A.acc = c->acc;
   A.sph = c->sph;
   A.vu = c->vu;
   A.hs = c->hs;
   A.es = c->es;
   A.solve = c->solve;
-  A.dt_i = c->acc + 5 * c->cap_n;
   A.ax = s->ax;
   A.ay = s->ay;
   A.az = s->az;
@@ -301,10 +325,7 @@ tsph_status tsph_impl_finish(Ctx *c, tsph_state *s, hipStream_t st) {
   A.h = s->h;
   A.eps = s->eps;
   A.pdiv = c->pdiv;
-  A.eta_dt = c->p.eta_dt;
   A.alpha = c->p.alpha;
-  A.beta = c->p.beta;
-  A.hydro = c->p.hydro;
   A.gamma = c->p.gamma;
   A.xsph_eta = c->p.xsph_eta;
   A.entropy = c->p.entropy;
@@ -314,11 +335,32 @@ tsph_status tsph_impl_finish(Ctx *c, tsph_state *s, hipStream_t st) {
   A.alpha_min = c->p.alpha_min;
   A.alpha_u_min = c->p.alpha_u_min;
   hipLaunchKernelGGL(k_finish, dim3(blocks_for(c->n, 256, 1 << 20)), dim3(256), 0, st, A);
-  // time-step of each member kept on the device for tsph_timestep
-  const Members M = members_of(c, c->n, c->n_gas);
-  const int rb = M.count > 1 ? kMemberBlocks : kRedBlocks;
-  hipLaunchKernelGGL(k_min_partial, dim3(rb, M.count), dim3(256), 0, st, M, A.dt_i, c->red);
-  hipLaunchKernelGGL(k_min_final, dim3(M.count), dim3(256), 0, st, rb, c->red, (double *)nullptr, c->dt);
+  TSPH_HIP_CHECK(c, hipGetLastError());
+  return TSPH_OK;
+}
+
+tsph_status tsph_impl_criteria(Ctx *c, const tsph_state *s, hipStream_t st) {
+  CritArgs A;
+  A.M = members_of(c, s->n, s->n_gas);
+  A.ax = s->ax;
+  A.ay = s->ay;
+  A.az = s->az;
+  A.eps = c->p.gravity ? s->eps : nullptr;
+  A.h = s->h;
+  A.u = s->u;
+  A.dudt = s->dudt;
+  A.rho = s->rho;
+  A.alpha = c->p.alpha_switch ? s->alpha : nullptr;
+  A.pdiv = c->pdiv;
+  A.cap_n = c->cap_n;
+  A.dt_i = c->acc + 5 * c->cap_n;
+  A.eta_dt = c->p.eta_dt;
+  A.alpha0 = c->p.alpha;
+  A.beta = c->p.beta;
+  A.gamma = c->p.gamma;
+  A.hydro = c->p.hydro && s->n_gas > 0;
+  A.entropy = c->p.entropy;
+  hipLaunchKernelGGL(k_criteria, dim3(blocks_for(s->n, 256, 1 << 20)), dim3(256), 0, st, A);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }
@@ -334,8 +376,15 @@ tsph_status tsph_impl_kick_drift(Ctx *c, tsph_state *s, double dt, const double 
   return TSPH_OK;
 }
 
-tsph_status tsph_impl_timestep(Ctx *c, double *dt_device, hipStream_t st) {
-  TSPH_HIP_CHECK(c, hipMemcpyAsync(dt_device, c->dt, sizeof(double) * c->nmem, hipMemcpyDeviceToDevice, st));
+tsph_status tsph_impl_timestep(Ctx *c, const tsph_state *s, double *dt_device, hipStream_t st) {
+  tsph_status r = tsph_impl_criteria(c, s, st);
+  if (r != TSPH_OK) return r;
+  // the minimum of each member, in a fixed tree order
+  const Members M = members_of(c, s->n, s->n_gas);
+  const int rb = M.count > 1 ? kMemberBlocks : kRedBlocks;
+  hipLaunchKernelGGL(k_min_partial, dim3(rb, M.count), dim3(256), 0, st, M, c->acc + 5 * c->cap_n, c->red);
+  hipLaunchKernelGGL(k_min_final, dim3(M.count), dim3(256), 0, st, rb, c->red, dt_device, c->dt);
+  TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }
 

@@ -96,6 +96,11 @@ struct SphArgs {
   SplitItem *split_item;
   double4 *split_part;
   int32_t *split_head;
+  // individual time-steps: force pass over the active sinks (act, key
+  // order; NULL: all), and the wake-up pass (mode 2) over the step lengths
+  const uint8_t *act;
+  const int32_t *bcur_s;
+  int32_t *bm, *bw;
 };
 
 // The sink side of the pairs of one lane: particle p (a gas sink when
@@ -111,6 +116,7 @@ struct SphLane {
   double xsx, xsy, xsz; // X-SPH sum (without eta); the curl sum in mode 1
   double lapu;          // Laplacian of u (conduction)
   double4 e2;           // alpha, alpha_u, Balsara factor, u
+  int bm, bw;           // mode 2: shortest step around, shortest active step around
   int p, npair, ndbg;
   bool sink;
   int32_t *dbg;
@@ -129,13 +135,16 @@ __device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bo
   L.e2 = A.f2 ? A.srec2[p] : make_double4(A.alpha, 0.0, 1.0, 0.0);
   L.npair = 0;
   L.ndbg = 0;
+  L.bm = L.bw = INT32_MAX;
   L.dbg = (A.dbg && sink) ? A.dbg + ((int64_t)1 * A.cap_n + A.perm[p]) * A.dbg_max : nullptr;
 }
 
 // Pairs of the lane's sink among the nt staged candidates: the distance
 // tests of the whole tile first, then the lane's own pairs in tile order.
 // kMode 0: forces and heating; kMode 1: the velocity curl sum
-// sum_j v_ij x grad_i W_ij(h_i) (plain kernel gradient) in xsx, xsy, xsz.
+// sum_j v_ij x grad_i W_ij(h_i) (plain kernel gradient) in xsx, xsy, xsz;
+// kMode 2: the least step length among the neighbours, and among the
+// active neighbours (coincident ones included).
 template <int kMode>
 __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const SphTile &T, int nt, bool tc) {
   const double hi = L.hd.x;
@@ -152,6 +161,12 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
     mask &= mask - 1;
     const int q = T.q[j];
     if (q == L.p) continue;  // the sink itself
+    if constexpr (kMode == 2) {
+      const int cq = A.bcur_s[q];
+      L.bm = min(L.bm, cq);
+      if (A.act[q]) L.bw = min(L.bw, cq);
+      continue;
+    }
     const SphRec b = A.srec[q];
     if (L.dbg) {
       if (L.ndbg < A.dbg_max) L.dbg[L.ndbg] = A.perm[q];
@@ -317,7 +332,10 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
       const bool act = c0 + ln < gnd.count;
       const int p = gnd.first + c0 + (act ? ln : 0);
       SphLane L;
-      sph_lane(A, L, p, act && A.gas[p]);
+      // the force pass of individual time-steps evaluates active sinks only
+      sph_lane(A, L, p, act && A.gas[p] && (kMode != 0 || !A.act || A.act[p]));
+      if (ballot(L.sink) == 0) continue;
+      if (kMode == 2) L.dbg = nullptr;
       const double hi = L.hd.x;
       int done = 0;  // candidates evaluated by this wave
       int sp = 1, nleaf = 0;
@@ -416,6 +434,10 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
         const double2 al = A.av[p];
         A.srec2[p] = make_double4(A.alpha_switch ? al.x : A.alpha, al.y, fb, L.v.w);
       }
+      if (kMode == 2 && L.sink) {
+        A.bm[A.perm[p]] = L.bm;
+        A.bw[A.perm[p]] = L.bw;
+      }
       if (kMode == 0 && L.sink) {
         A.acc[0 * A.cap_n + p] += L.ax;
         A.acc[1 * A.cap_n + p] += L.ay;
@@ -454,7 +476,7 @@ __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
     const bool act = I.c0 + ln < bt.count;
     const int p = bt.first + I.c0 + (act ? ln : 0);
     SphLane L;
-    sph_lane(A, L, p, act && A.gas[p]);
+    sph_lane(A, L, p, act && A.gas[p] && (!A.act || A.act[p]));
     L.dbg = nullptr;
     for (int a = ln; a < I.count; a += kWave) s_rng[a] = A.split_rng[I.start + a];
     __syncthreads();
@@ -540,13 +562,7 @@ __global__ void k_reset_counter(int32_t *ctr, int k) {
 
 using namespace tsph;
 
-tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_sph, dim3(blocks_for(c->n, 256, 8192)), dim3(256), 0, st, c->n, c->cap_n, c->acc,
-                     c->solve, c->cnt, c->perm);
-  if (!c->p.hydro || c->n_gas == 0) {
-    TSPH_HIP_CHECK(c, hipGetLastError());
-    return TSPH_OK;
-  }
+static SphArgs sph_args(Ctx *c) {
   SphArgs A;
   A.cap_n = c->cap_n;
   A.groups = c->groups;
@@ -586,15 +602,32 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   A.f2 = (A.balsara || A.alpha_switch || A.conduction) ? 1 : 0;
   A.srec2 = c->srec2;
   A.av = c->av;
-  // debug lists are written in the batch's own order: no hand-off then.  The
-  // SPH pairs cost more per candidate than the near-field gravity pairs, so
-  // the batch keeps a quarter of the gravity walk's share.
-  A.split_particles = c->dbg_nbr ? 0 : c->p.split_leaves * c->p.leaf_size / 4;
+  A.split_particles = 0;
   A.split_cap = split_cap_used(c) / kSphPart;
   A.split_rng = c->split_rng;
   A.split_item = c->split_item;
   A.split_part = c->split_part;
   A.split_head = c->split_head;
+  A.act = nullptr;
+  A.bcur_s = c->bcur_s;
+  A.bm = c->bm;
+  A.bw = c->bw;
+  return A;
+}
+
+tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_sph, dim3(blocks_for(c->n, 256, 8192)), dim3(256), 0, st, c->n, c->cap_n, c->acc,
+                     c->solve, c->cnt, c->perm);
+  if (!c->p.hydro || c->n_gas == 0) {
+    TSPH_HIP_CHECK(c, hipGetLastError());
+    return TSPH_OK;
+  }
+  SphArgs A = sph_args(c);
+  A.act = c->blk_on ? c->bact_s : nullptr;
+  // debug lists are written in the batch's own order: no hand-off then.  The
+  // SPH pairs cost more per candidate than the near-field gravity pairs, so
+  // the batch keeps a quarter of the gravity walk's share.
+  A.split_particles = c->dbg_nbr ? 0 : c->p.split_leaves * c->p.leaf_size / 4;
   if (A.split_particles > 0)
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(c->cap_nodes, 256, 4096)), dim3(256), 0, st, c->cap_nodes,
                        c->split_head, -1);
@@ -613,6 +646,20 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
     hipLaunchKernelGGL(k_sph_split, dim3(persistent_blocks(c, (const void *)k_sph_split)), dim3(64), 0, st, A);
     hipLaunchKernelGGL(k_sph_reduce, dim3(4096), dim3(64), 0, st, A);
   }
+  TSPH_HIP_CHECK(c, hipGetLastError());
+  return TSPH_OK;
+}
+
+// Wake-up sums of the individual time-steps: for every gas particle the least
+// current step length among its SPH neighbours and among the active ones.
+tsph_status tsph_impl_wake(Ctx *c, hipStream_t st) {
+  if (!c->p.hydro || c->n_gas == 0) return TSPH_OK;
+  SphArgs A = sph_args(c);
+  A.act = c->bact_s;
+  A.dbg = nullptr;
+  A.split_particles = 0;
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, A.work + 24, 8);
+  hipLaunchKernelGGL(k_sph<2>, dim3(persistent_blocks(c, (const void *)k_sph<2>)), dim3(64), 0, st, A);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

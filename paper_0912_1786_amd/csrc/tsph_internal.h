@@ -120,8 +120,10 @@ inline int64_t heavy_batch_cap(int64_t cap_nodes) { return cap_nodes < 4096 ? 40
 // per-particle outputs of the force pass kept in key order: the solves'
 // sums and factors, and the SPH pass's largest |mu|, largest signal
 // velocity, viscous heating and X-SPH sum
-// rows of the carry from one force pass to the next drift (caller order)
-constexpr int kCarryRows = 7;  // + the rates of alpha and alpha_u
+// rows of the carry from one force pass to the next step (caller order):
+// div v (h kernel), div v (eps kernel), X-SPH correction (3), the rates of
+// alpha and alpha_u, the largest |mu_ij| (for the Courant criterion)
+constexpr int kCarryRows = 8;
 
 enum SolveField { kNh = 0, kOmega, kZeta, kDivv, kNeps, kUps, kXi, kMaxmu, kDivvE, kVsig, kDuv, kXsx, kXsy, kXsz,
                   kCurlx, kCurly, kCurlz, kFbal, kLapu, kNumSolve };
@@ -157,7 +159,8 @@ struct Ctx {
   double *pdiv;           // kCarryRows x cap_n, caller order: div v with the h kernel (gas) and the eps
                           // kernel, the X-SPH velocity correction (3 rows)
   int64_t pdiv_n;         // particle count the divergences belong to (0: none yet)
-  double *acc;            // 6 x cap_n: ax, ay, az, pot, dudt, dt_i
+  double *acc;            // 6 x cap_n: ax, ay, az, pot, dudt (key order); per-particle time-steps
+                          // (caller order)
   int32_t *cnt;           // 3 x cap_n: far nodes, near pairs, SPH pairs
 
   // ---- nodes, level order (capacity cap_nodes) ----
@@ -203,7 +206,17 @@ struct Ctx {
   uint32_t *flags;        // device flag word
   int32_t *noconv;        // unconverged solves
   double *red;            // reduction scratch
-  double *dt;             // cap_mem time-steps of the last force pass (one per member)
+  double *dt;             // cap_mem time-steps of the last tsph_timestep (one per member)
+
+  // ---- individual time-steps (tsph_block_*) ----
+  uint8_t *bact;          // cap_n active flags, caller order
+  uint8_t *bact_s;        // cap_n active flags, key order (force passes with blk_on)
+  int32_t *bcur;          // cap_n current step lengths in ticks (criterion step of the active), caller order
+  int32_t *bcur_s;        // cap_n the same in key order
+  int32_t *bm, *bw;       // cap_n: shortest current step around each gas particle, shortest criterion
+                          // step of its active neighbours (caller order; INT32_MAX: none)
+  int32_t *bnext;         // [0] next system time, [1] active count, [2] woken count
+  int32_t blk_on;         // the force pass evaluates the active sinks only
 
   // ---- phase timing (ring of event sets) ----
   int32_t timing;
@@ -554,7 +567,13 @@ tsph_status tsph_impl_sph(tsph::Ctx *c, hipStream_t st);
 tsph_status tsph_impl_finish(tsph::Ctx *c, tsph_state *s, hipStream_t st);
 tsph_status tsph_impl_kick_drift(tsph::Ctx *c, tsph_state *s, double dt, const double *dt_dev, int phase,
                                  hipStream_t st);
-tsph_status tsph_impl_timestep(tsph::Ctx *c, double *dt_device, hipStream_t st);
+tsph_status tsph_impl_timestep(tsph::Ctx *c, const tsph_state *s, double *dt_device, hipStream_t st);
+// per-particle time-step criteria of the state into c->acc + 5 cap_n (caller order)
+tsph_status tsph_impl_criteria(tsph::Ctx *c, const tsph_state *s, hipStream_t st);
+// neighbour minima of the step lengths for the wake-up (sph.hip)
+tsph_status tsph_impl_wake(tsph::Ctx *c, hipStream_t st);
+// active flags into key order for a force pass over the active sinks (blocks.hip)
+tsph_status tsph_impl_gather_active(tsph::Ctx *c, hipStream_t st);
 tsph_status tsph_impl_diagnostics(tsph::Ctx *c, const tsph_state *s, double *out, hipStream_t st);
 tsph_status tsph_impl_reset_work(tsph::Ctx *c, hipStream_t st);
 

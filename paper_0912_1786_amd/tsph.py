@@ -61,6 +61,13 @@ class State(C.Structure):
                 ("alpha", _P), ("alpha_u", _P)]
 
 
+class Blocks(C.Structure):
+    """tsph_blocks: individual power-of-two time-steps (see tsph.h)."""
+    _fields_ = [("dt_max", C.c_double), ("max_level", C.c_int32), ("wake", C.c_int32), ("t", C.c_int64),
+                ("n_active", C.c_int64), ("n_woken", C.c_int64), ("t0", _P), ("t1", _P), ("vsx", _P),
+                ("vsy", _P), ("vsz", _P), ("us", _P)]
+
+
 _LIB = None
 
 
@@ -106,6 +113,8 @@ def lib():
             "tsph_diagnostics_noalloc": ([S, C.c_int32, _P, _P, _P, _P], C.c_int),
             "tsph_noalloc_last_error": ([], C.c_char_p),
             "tsph_probe": ([C.c_int32, C.c_int64, _P, _P, _P, _P, C.POINTER(C.c_double)], C.c_int),
+            "tsph_block_start": ([_P, S, C.POINTER(Blocks), _P], C.c_int),
+            "tsph_block_advance": ([_P, S, C.POINTER(Blocks), _P], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -124,7 +133,8 @@ EXPORTED = ("tsph_create", "tsph_destroy", "tsph_set_params", "tsph_default_para
             "tsph_set_members", "tsph_build_tree", "tsph_compute_forces", "tsph_kick_drift", "tsph_kick_drift_dt", "tsph_carry_bytes",
             "tsph_carry_save", "tsph_carry_load", "tsph_timestep", "tsph_diagnostics", "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
             "tsph_timing", "tsph_phase_times", "tsph_probe", "tsph_debug_handoff_cap", "tsph_source_id",
-            "tsph_diagnostics_noalloc", "tsph_noalloc_last_error", "tsph_batch_step")
+            "tsph_diagnostics_noalloc", "tsph_noalloc_last_error", "tsph_batch_step", "tsph_block_start",
+            "tsph_block_advance")
 PHASES = ("tree", "density", "gravity", "sph", "finish")
 
 
@@ -238,6 +248,14 @@ def tsph_diagnostics(ctx, st: State, out_ptr: int, stream=None):
 
 
 NOALLOC_MAX_SYSTEMS = 910
+
+
+def tsph_block_start(ctx, st: State, blk: Blocks, stream=None):
+    _check("tsph_block_start", lib().tsph_block_start(ctx, C.byref(st), C.byref(blk), _stream(stream)), ctx)
+
+
+def tsph_block_advance(ctx, st: State, blk: Blocks, stream=None):
+    _check("tsph_block_advance", lib().tsph_block_advance(ctx, C.byref(st), C.byref(blk), _stream(stream)), ctx)
 
 
 def tsph_diagnostics_noalloc(st: State, count: int, off_ptr: int, ngas_ptr: int, out_ptr: int, stream=None):
@@ -401,6 +419,33 @@ class Simulation:
 
     def compute_forces(self, stream=None):
         tsph_compute_forces(self.ctx, self.state, stream)
+
+    # ---- individual power-of-two time-steps ---------------------------------
+    def block_start(self, dt_max: float, max_level: int, wake: int = 4, stream=None):
+        """First system time of a run with individual time-steps: force pass
+        over all particles, steps chosen, opening kicks."""
+        torch = self.torch
+        dev = self.a["x"].device
+        n = self.n
+        self.blk_a = {k: torch.zeros(n, dtype=torch.int32, device=dev) for k in ("t0", "t1")}
+        for k in ("vsx", "vsy", "vsz", "us"):
+            self.blk_a[k] = torch.zeros(n, dtype=torch.float64, device=dev)
+        b = Blocks()
+        b.dt_max, b.max_level, b.wake = float(dt_max), int(max_level), int(wake)
+        for k, v in self.blk_a.items():
+            setattr(b, k, v.data_ptr())
+        self.blk = b
+        tsph_block_start(self.ctx, self.state, b, stream)
+
+    def block_advance(self, stream=None):
+        """Advance to the next system time; returns (t, n_active, n_woken)."""
+        tsph_block_advance(self.ctx, self.state, self.blk, stream)
+        return int(self.blk.t), int(self.blk.n_active), int(self.blk.n_woken)
+
+    def block_host(self, key: str):
+        """Host copy of a block-step array: t0, t1 (ticks), vsx, vsy, vsz, us."""
+        self.torch.cuda.synchronize()
+        return self.blk_a[key].cpu().numpy()
 
     def kick_drift(self, dt: float, phase: int, stream=None):
         tsph_kick_drift(self.ctx, self.state, dt, phase, stream)

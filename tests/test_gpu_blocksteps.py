@@ -1,0 +1,149 @@
+"""GPU parity of the individual power-of-two time-steps (Sect. 4.2.1)
+against the oracle's block-step driver, event by event:
+
+* the system times, the active sets and every particle's step start and end
+  (integers: exact), the woken counts, and the state (positions,
+  half-kicked velocities, energies, lengths) to the force parity;
+* a point blast on a cold lattice, where the wake-up shortens the steps of
+  the blast's neighbours;
+* with every particle in the largest step the run is the global
+  kick-drift-kick run of the same step, bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0912_1786_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # collected on CPU-only machines but never run there
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_0912_1786_amd import tsph  # noqa: E402
+
+from gpu_common import gpu_params, oracle_params  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def BS():
+    from oracle import blocksteps
+    return blocksteps
+
+
+def _close(a, b, tol):
+    scale = max(float(np.abs(b).max()), 1e-30)
+    return float(np.abs(a - b).max()) <= tol * scale
+
+
+def _lockstep(O, BS, ic, gp, dt_max, L, wake, events, tol=1e-9):
+    op = oracle_params(O, gp)
+    ob = BS.BlockSteps(ic, op, dt_max, L, eta_dt=gp.eta_dt, wake=wake)
+    sim = tsph.Simulation(ic, gp)
+    try:
+        sim.block_start(dt_max, L, wake)
+        assert np.array_equal(sim.block_host("t1"), ob.t1), "steps at the first system time"
+        woken = 0
+        for ev in range(events):
+            t, nact, nw = sim.block_advance()
+            act = ob.advance()
+            flags, noconv = sim.flags()
+            assert flags == 0 and noconv == 0, hex(flags)
+            assert t == ob.t and nact == int(act.sum()), (ev, t, ob.t, nact, int(act.sum()))
+            assert np.array_equal(sim.block_host("t0"), ob.t0), ev
+            assert np.array_equal(sim.block_host("t1"), ob.t1), ev
+            woken += nw
+        assert woken == ob.woken
+        for k in ("x", "y", "z", "vx", "vy", "vz"):
+            assert _close(sim.host(k), ob.st[k], tol), k
+        g = slice(0, ic["n_gas"])
+        assert _close(sim.host("u")[g], ob.st["u"][g], tol)
+        assert _close(sim.host("h")[g], ob.out["h"][g], tol)
+        for k in ("ax", "ay", "az"):
+            assert _close(sim.host(k), ob.out[k], tol), k
+        return ob
+    finally:
+        sim.close()
+
+
+def test_block_steps_match_oracle(O, BS):
+    _say("[blocks] evrard 2000, 6 levels")
+    ic = inputs.evrard(2000, seed=31, v_sigma=0.1)
+    gp = gpu_params(nnei=40, h_tol=1e-12, leaf_size=8)
+    o0 = O.compute_forces(ic, oracle_params(O, gp))
+    dt_max = 16.0 * O.timestep(oracle_params(O, gp), ic, o0, gp.eta_dt)
+    ob = _lockstep(O, BS, ic, gp, dt_max, 6, 4, 14)
+    lev = ob.L - np.log2(ob.t1 - ob.t0).astype(int)
+    assert len(set(lev)) >= 3
+    assert ob.sink_evals < 0.8 * ic["n"] * (ob.events + 1)
+
+
+def test_block_steps_wakeup_blast(O, BS):
+    _say("[blocks] point blast on a 10^3 lattice")
+    n_side = 10
+    ic = inputs.cubic_lattice(n_side, spacing=1.0 / n_side, mass=1.0 / n_side ** 3)
+    ic["u"][:] = 1e-4
+    pos = np.stack([ic["x"], ic["y"], ic["z"]], 1)
+    ic["u"][int(np.argmin(((pos - 0.5) ** 2).sum(1)))] = 100.0
+    gp = gpu_params(gravity=0, nnei=40, h_tol=1e-12, leaf_size=8)
+    ob = _lockstep(O, BS, ic, gp, 0.05, 14, 4, 30)
+    assert ob.woken > 0
+
+
+def test_single_bin_equals_global_steps(O):
+    """Largest step below every criterion: all particles in one bin; the
+    block run equals the global kick-drift-kick run of that step bit for
+    bit."""
+    _say("[blocks] one bin vs global steps")
+    ic = inputs.evrard(1500, seed=32, v_sigma=0.1)
+    gp = gpu_params(nnei=40, leaf_size=8)
+    a = tsph.Simulation(ic, gp)
+    b = tsph.Simulation(ic, gp)
+    try:
+        a.compute_forces()
+        dt = 0.25 * a.timestep()
+        a.close()
+        a = tsph.Simulation(ic, gp)
+        a.block_start(dt, 3, 4)
+        assert np.all(a.block_host("t1") == 8)
+        b.compute_forces()
+        for _ in range(3):
+            a.block_advance()
+            b.kick_drift(dt, tsph.KD_FIRST)
+            b.compute_forces()
+            b.kick_drift(dt, tsph.KD_SECOND)
+        for k in ("x", "y", "z"):
+            assert np.array_equal(a.host(k), b.host(k)), k
+        assert np.array_equal(a.block_host("vsx"), b.host("vx"))
+        assert np.array_equal(a.block_host("vsz"), b.host("vz"))
+        g = slice(0, ic["n_gas"])
+        assert np.array_equal(a.block_host("us")[g], b.host("u")[g])
+    finally:
+        a.close()
+        b.close()
+
+
+def test_block_argument_errors():
+    ic = inputs.evrard(300, seed=33)
+    sim = tsph.Simulation(ic, gpu_params())
+    try:
+        for kw in (dict(dt_max=-1.0, max_level=4, wake=4), dict(dt_max=0.1, max_level=31, wake=4),
+                   dict(dt_max=0.1, max_level=4, wake=3)):
+            with pytest.raises(tsph.TsphError) as e:
+                sim.block_start(**kw)
+            assert e.value.status == tsph.TSPH_EINVAL
+    finally:
+        sim.close()

@@ -46,7 +46,7 @@ def _carry_rates(sim):
     """alpha and alpha_u rates of the last force pass (rows of the carry)."""
     c = sim.carry()
     n = sim.n
-    return c[1 + 5 * n:1 + 6 * n], c[1 + 6 * n:1 + 7 * n]
+    return c[5 * n:6 * n], c[6 * n:7 * n]
 
 
 @pytest.mark.parametrize("flags", ["balsara", "alpha_switch", "conduction", "all", "all_signal"])
