@@ -111,6 +111,8 @@ size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->add(4 * M);        // 26 groups
   L->add(8 * M);        // batches
   L->add(4 * 16);       // nbatches
+  L->add(8 * M);        // sbatches
+  L->add(4 * 16);       // nsbatches
   const int64_t icap = split_item_cap(M);
   L->add(8 * (size_t)icap * kSplitItemRanges);  // split_rng
   L->add(sizeof(SplitItem) * (size_t)icap);     // split_item
@@ -338,6 +340,8 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->groups = AT(int32_t *);
   c->batches = AT(int2 *);
   c->nbatches = AT(int32_t *);
+  c->sbatches = AT(int2 *);
+  c->nsbatches = AT(int32_t *);
   c->split_rng = AT(int2 *);
   c->split_item = AT(SplitItem *);
   c->split_part = AT(double4 *);
@@ -376,6 +380,7 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->h_noconv = (int32_t *)(c->h_flags + 4);
   if ((e = hipMemset(c->flags, 0, 64)) != hipSuccess || (e = hipMemset(c->noconv, 0, 64)) != hipSuccess ||
       (e = hipMemset(c->lvl, 0, 256)) != hipSuccess || (e = hipMemset(c->ngroups, 0, 64)) != hipSuccess ||
+      (e = hipMemset(c->nsbatches, 0, 64)) != hipSuccess ||
       (e = hipMemset(c->split_item, 0xff, sizeof(SplitItem) * (size_t)c->split_cap)) != hipSuccess ||
       (e = hipMemset(c->split_head, 0xff, 4 * (size_t)c->cap_nodes)) != hipSuccess ||
       (e = hipDeviceSynchronize()) != hipSuccess)

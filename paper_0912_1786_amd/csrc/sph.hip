@@ -122,6 +122,9 @@ struct SphLane {
   int32_t *dbg;
 };
 
+// kFull: the kernel form with the dissipation switches, the conductivity and
+// X-SPH (the plain form keeps none of their state in registers)
+template <bool kFull>
 __device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bool sink) {
   L.p = p;
   L.sink = sink;
@@ -132,7 +135,7 @@ __device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bo
   L.fa = A.srec[p].fa;
   L.ax = L.ay = L.az = L.du = L.mumax = 0.0;
   L.duv = L.vsig = L.xsx = L.xsy = L.xsz = L.lapu = 0.0;
-  L.e2 = A.f2 ? A.srec2[p] : make_double4(A.alpha, 0.0, 1.0, 0.0);
+  L.e2 = (kFull && A.f2) ? A.srec2[p] : make_double4(A.alpha, 0.0, 1.0, 0.0);
   L.npair = 0;
   L.ndbg = 0;
   L.bm = L.bw = INT32_MAX;
@@ -145,7 +148,7 @@ __device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bo
 // sum_j v_ij x grad_i W_ij(h_i) (plain kernel gradient) in xsx, xsy, xsz;
 // kMode 2: the least step length among the neighbours, and among the
 // active neighbours (coincident ones included).
-template <int kMode>
+template <int kMode, bool kFull>
 __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const SphTile &T, int nt, bool tc) {
   const double hi = L.hd.x;
   uint64_t mask = tile_mask(nt, [&](int j) {
@@ -206,10 +209,10 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
       const double mu = hb * vd / (r2 + A.av_eps2 * hb * hb);
       // per-particle alpha: the pair mean replaces alpha; Balsara: times the
       // pair mean of f (Sect. 3.3.1)
-      const double4 e2j = A.f2 ? A.srec2[q] : make_double4(A.alpha, 0.0, 1.0, 0.0);
-      const double al = A.alpha_switch ? 0.5 * (L.e2.x + e2j.x) : A.alpha;
+      const double4 e2j = (kFull && A.f2) ? A.srec2[q] : make_double4(A.alpha, 0.0, 1.0, 0.0);
+      const double al = (kFull && A.alpha_switch) ? 0.5 * (L.e2.x + e2j.x) : A.alpha;
       double Pi = A.visc_signal ? -al * (2.0 * cb - w) * w / rb : (-al * cb * mu + A.beta * mu * mu) / rb;
-      if (A.balsara) Pi *= 0.5 * (L.e2.z + e2j.z);
+      if (kFull && A.balsara) Pi *= 0.5 * (L.e2.z + e2j.z);
       const double Gb = 0.5 * (fij * gi + fji * gj);
       sf += mj * Pi * Gb;
       const double ev = 0.5 * mj * Pi * Gb * vd;
@@ -218,7 +221,7 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
       L.mumax = fmax(L.mumax, fabs(mu));
     }
     L.vsig = fmax(L.vsig, 2.0 * cb - fmin(w, 0.0));
-    if (A.conduction) {
+    if (kFull && A.conduction) {
       // artificial conductivity (Sect. 3.3.2) through |Gbar| = |Gb| r, and
       // Brookshaw's Laplacian of u
       const double4 e2j = A.srec2[q];
@@ -229,7 +232,7 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
       e += mj * Piu * Gbm;
       L.lapu -= 2.0 * mj * du_ij / b.rho * Gbm * ir;
     }
-    if (A.xsph_eta > 0.0) {
+    if (kFull && A.xsph_eta > 0.0) {
       double wi, dwi, wj, dwj;
       m4(r * ihi, wi, dwi);
       m4(r * b.ih, wj, dwj);
@@ -246,17 +249,35 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
   __syncthreads();
 }
 
-// Candidate q of this lane's slot staged for the pair tests (non-gas at
-// infinity).
-__device__ __forceinline__ void stage_sph(const SphArgs &A, SphTile &T, int nt, int q) {
+// The gas among the candidates of the lanes' raw slots (slot ln holds
+// candidate q, nt valid) appended to the tile of gas candidates, which holds
+// fill of them: a full tile is evaluated and the remainder carried over to
+// the next.  Non-gas candidates never reach the pair tests, and each lane
+// still meets its pairs in candidate order.  Returns the new fill.
+template <int kMode, bool kFull>
+__device__ __forceinline__ int stage_gas(const SphArgs &A, SphLane &L, SphTile &T, int nt, int q, int fill, bool tc) {
   const int ln = lane();
-  if (ln < nt) {
-    const bool g = A.gas[q] != 0;
+  const bool g = ln < nt && A.gas[q] != 0;
+  const uint64_t gm = ballot(g);
+  const int slot = fill + mbcnt(gm);
+  const int ng = __popcll(gm);
+  if (g && slot < kWave) {
     const SphRec *r = A.srec + q;
-    T.pos[ln] = g ? make_double4(r->x, r->y, r->z, r->h) : make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-    T.q[ln] = g ? q : -1;
+    T.pos[slot] = make_double4(r->x, r->y, r->z, r->h);
+    T.q[slot] = q;
   }
   __syncthreads();
+  if (fill + ng < kWave) return fill + ng;
+  tile_pairs<kMode, kFull>(A, L, T, kWave, tc);
+  // the remainder (its record read again: fewer registers live across the
+  // pair evaluation)
+  if (g && slot >= kWave) {
+    const SphRec *r = A.srec + q;
+    T.pos[slot - kWave] = make_double4(r->x, r->y, r->z, r->h);
+    T.q[slot - kWave] = q;
+  }
+  __syncthreads();
+  return fill + ng - kWave;
 }
 
 // particle ranges (first, count) of listed leaves, or given explicitly
@@ -275,10 +296,10 @@ struct SphRangeSrc {
 
 // Pairs of the lane's sink with the particles of ranges [0, n), packed 64
 // to a tile in range order.  Returns the number of particles scanned.
-template <int kMode = 0, class Src>
+template <int kMode, bool kFull, class Src>
 __device__ __forceinline__ int sph_ranges(const SphArgs &A, SphLane &L, SphTile &T, const Src &src, int n, bool tc) {
   const int ln = lane();
-  int fill = 0, rq = 0, scanned = 0;
+  int fill = 0, rq = 0, scanned = 0, gfill = 0;
   for (int c1 = 0; c1 < n; c1 += kWave) {
     const int nc = min(kWave, n - c1);
     const int2 my = ln < nc ? src(c1 + ln) : make_int2(0, 0);
@@ -292,27 +313,44 @@ __device__ __forceinline__ int sph_ranges(const SphArgs &A, SphLane &L, SphTile 
         fill += tk;
         off += tk;
         if (fill == kWave) {
-          stage_sph(A, T, kWave, rq);
-          tile_pairs<kMode>(A, L, T, kWave, tc);
+          gfill = stage_gas<kMode, kFull>(A, L, T, kWave, rq, gfill, tc);
           fill = 0;
         }
       }
     }
   }
-  if (fill > 0) {
-    stage_sph(A, T, fill, rq);
-    tile_pairs<kMode>(A, L, T, fill, tc);
-  }
+  if (fill > 0) gfill = stage_gas<kMode, kFull>(A, L, T, fill, rq, gfill, tc);
+  if (gfill > 0) tile_pairs<kMode, kFull>(A, L, T, gfill, tc);
   return scanned;
 }
 
-template <int kMode>
+// The gas particles c0 .. c0 + 63 of batch bt (in key order) listed in
+// s_gs: the lanes of one chunk of the batch's gas sinks.  The SPH batches are
+// packed by gas count, so one chunk holds them all unless a single group has
+// more than 64 (an unsplittable clump).
+__device__ __forceinline__ void gas_sinks(const SphArgs &A, const Batch &bt, int c0, int *s_gs) {
+  const int ln = lane();
+  int n = 0;
+  __syncthreads();
+  for (int o = 0; o < bt.count && n < c0 + kWave; o += kWave) {
+    const int q = bt.first + o + ln;
+    const bool g = o + ln < bt.count && A.gas[q] != 0;
+    const uint64_t m = ballot(g);
+    const int slot = n + mbcnt(m) - c0;
+    if (g && slot >= 0 && slot < kWave) s_gs[slot] = q;
+    n += __popcll(m);
+  }
+  __syncthreads();
+}
+
+template <int kMode, bool kFull>
 __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
   __shared__ int s_stack[kSStackCap];
   __shared__ int s_leaf[kSListCap];
   __shared__ double4 s_snk[kWave];
   __shared__ SphTile s_t;
   __shared__ int s_g;
+  __shared__ int s_gs[kWave];
   const int ln = lane();
   const int ng = *A.nbatches;
   const bool tc = A.tc92 != 0;
@@ -324,16 +362,17 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
     if (g < 0) break;
     const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, g);
     if (bt.ngas == 0) continue;
-    const NodeTopo gnd{bt.first, bt.count, -1, 0};
     const NodeBox gb = bt.box;
     const double ghmax = gb.hmax;
+    const int ngs = bt.ngas;
     int prev_item = -1;  // last handed-off item of this batch
-    for (int c0 = 0; c0 < gnd.count; c0 += kWave) {
-      const bool act = c0 + ln < gnd.count;
-      const int p = gnd.first + c0 + (act ? ln : 0);
+    for (int c0 = 0; c0 < ngs; c0 += kWave) {
+      gas_sinks(A, bt, c0, s_gs);
+      const bool act = c0 + ln < ngs;
+      const int p = act ? s_gs[ln] : bt.first;
       SphLane L;
       // the force pass of individual time-steps evaluates active sinks only
-      sph_lane(A, L, p, act && A.gas[p] && (kMode != 0 || !A.act || A.act[p]));
+      sph_lane<kFull>(A, L, p, act && (kMode != 0 || !A.act || A.act[p]));
       if (ballot(L.sink) == 0) continue;
       if (kMode == 2) L.dbg = nullptr;
       const double hi = L.hd.x;
@@ -413,7 +452,7 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
               atomicOr(A.flags, TSPH_FLAG_HANDOFF_CAPACITY);
             }
           }
-          if (!handed) done += sph_ranges<kMode>(A, L, s_t, SphLeafSrc{A.topo, s_leaf}, nleaf, tc);
+          if (!handed) done += sph_ranges<kMode, kFull>(A, L, s_t, SphLeafSrc{A.topo, s_leaf}, nleaf, tc);
           nleaf = 0;
         }
         __syncthreads();
@@ -458,10 +497,12 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
 
 // The handed-off flushes: each item's ranges on the sinks of its batch
 // chunk; per-lane partial sums to split_part (kSphPart records per lane).
+template <bool kFull>
 __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
   __shared__ int2 s_rng[kSplitItemRanges];
   __shared__ SphTile s_t;
   __shared__ int s_i;
+  __shared__ int s_gs[kWave];
   const int ln = lane();
   const bool tc = A.tc92 != 0;
   const int nitems = (int)min((int64_t)A.work[35], A.split_cap);
@@ -473,14 +514,15 @@ __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
     if (it >= nitems) break;
     const SplitItem I = A.split_item[it];
     const Batch bt = load_batch(A.batches, A.groups, A.topo, A.nbox, A.nngas, A.mem, I.g);
-    const bool act = I.c0 + ln < bt.count;
-    const int p = bt.first + I.c0 + (act ? ln : 0);
+    gas_sinks(A, bt, I.c0, s_gs);
+    const bool act = I.c0 + ln < bt.ngas;
+    const int p = act ? s_gs[ln] : bt.first;
     SphLane L;
-    sph_lane(A, L, p, act && A.gas[p] && (!A.act || A.act[p]));
+    sph_lane<kFull>(A, L, p, act && (!A.act || A.act[p]));
     L.dbg = nullptr;
     for (int a = ln; a < I.count; a += kWave) s_rng[a] = A.split_rng[I.start + a];
     __syncthreads();
-    sph_ranges(A, L, s_t, SphRangeSrc{s_rng}, I.count, tc);
+    sph_ranges<0, kFull>(A, L, s_t, SphRangeSrc{s_rng}, I.count, tc);
     double4 *part = A.split_part + (int64_t)kSphPart * it * kWave;
     part[ln] = make_double4(L.ax, L.ay, L.az, L.du);
     part[kWave + ln] = make_double4(L.mumax, (double)L.npair, L.duv, L.vsig);
@@ -491,6 +533,7 @@ __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
 // Adds the items' partial sums to each batch's sinks along the batch's item
 // chain (creation order).
 __global__ __launch_bounds__(64) void k_sph_reduce(SphArgs A) {
+  __shared__ int s_gs[kWave];
   const int ln = lane();
   const int ng = *A.nbatches;
   for (int g = blockIdx.x; g < ng; g += gridDim.x) {
@@ -500,8 +543,9 @@ __global__ __launch_bounds__(64) void k_sph_reduce(SphArgs A) {
     int guard = 0;
     while (it >= 0 && it < A.split_cap && ++guard <= A.split_cap) {
       const SplitItem I = A.split_item[it];
-      const int p = bt.first + I.c0 + ln;
-      if (I.c0 + ln < bt.count && A.gas[p]) {
+      gas_sinks(A, bt, I.c0, s_gs);
+      const int p = I.c0 + ln < bt.ngas ? s_gs[ln] : bt.first;
+      if (I.c0 + ln < bt.ngas) {
         const double4 *part = A.split_part + (int64_t)kSphPart * it * kWave;
         const double4 v = part[ln], w = part[kWave + ln], x = part[2 * kWave + ln];
         A.acc[0 * A.cap_n + p] += v.x;
@@ -567,8 +611,8 @@ static SphArgs sph_args(Ctx *c) {
   A.cap_n = c->cap_n;
   A.groups = c->groups;
   A.ngroups = c->ngroups;
-  A.batches = c->batches;
-  A.nbatches = c->nbatches;
+  A.batches = c->sbatches;
+  A.nbatches = c->nsbatches;
   A.topo = c->topo;
   A.nbox = c->nbox;
   A.nngas = c->nngas;
@@ -638,12 +682,23 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
                        c->alpha_state, c->alpha_u_state, c->av);
     SphArgs Ac = A;
     Ac.split_particles = 0;
-    hipLaunchKernelGGL(k_sph<1>, dim3(persistent_blocks(c, (const void *)k_sph<1>)), dim3(64), 0, st, Ac);
+    hipLaunchKernelGGL((k_sph<1, true>), dim3(persistent_blocks(c, (const void *)k_sph<1, true>)), dim3(64), 0, st,
+                       Ac);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, A.work + 24, 8);
   }
-  hipLaunchKernelGGL(k_sph<0>, dim3(persistent_blocks(c, (const void *)k_sph<0>)), dim3(64), 0, st, A);
+  // the plain form without the switches, the conductivity and X-SPH
+  const bool full = A.f2 || A.xsph_eta > 0.0;
+  const void *ks = full ? (const void *)k_sph<0, true> : (const void *)k_sph<0, false>;
+  const void *kx = full ? (const void *)k_sph_split<true> : (const void *)k_sph_split<false>;
+  if (full)
+    hipLaunchKernelGGL((k_sph<0, true>), dim3(persistent_blocks(c, ks)), dim3(64), 0, st, A);
+  else
+    hipLaunchKernelGGL((k_sph<0, false>), dim3(persistent_blocks(c, ks)), dim3(64), 0, st, A);
   if (A.split_particles > 0) {
-    hipLaunchKernelGGL(k_sph_split, dim3(persistent_blocks(c, (const void *)k_sph_split)), dim3(64), 0, st, A);
+    if (full)
+      hipLaunchKernelGGL(k_sph_split<true>, dim3(persistent_blocks(c, kx)), dim3(64), 0, st, A);
+    else
+      hipLaunchKernelGGL(k_sph_split<false>, dim3(persistent_blocks(c, kx)), dim3(64), 0, st, A);
     hipLaunchKernelGGL(k_sph_reduce, dim3(4096), dim3(64), 0, st, A);
   }
   TSPH_HIP_CHECK(c, hipGetLastError());
@@ -659,7 +714,8 @@ tsph_status tsph_impl_wake(Ctx *c, hipStream_t st) {
   A.dbg = nullptr;
   A.split_particles = 0;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, A.work + 24, 8);
-  hipLaunchKernelGGL(k_sph<2>, dim3(persistent_blocks(c, (const void *)k_sph<2>)), dim3(64), 0, st, A);
+  hipLaunchKernelGGL((k_sph<2, false>), dim3(persistent_blocks(c, (const void *)k_sph<2, false>)), dim3(64), 0,
+                     st, A);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

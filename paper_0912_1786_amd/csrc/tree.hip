@@ -696,17 +696,21 @@ __device__ __forceinline__ bool next_sibling(const int32_t *groups, const int32_
   return u == v + 1 && nparent[u] >= 0 && nparent[u] == nparent[v];
 }
 
+// weight: per-node particle counts to pack by (NULL: all particles; the SPH
+// walks pack by gas count, so that their batches hold up to batch_size gas
+// sinks)
 __global__ __launch_bounds__(256) void k_batch_mark(const int32_t *__restrict__ ngroups,
                                                     const int32_t *__restrict__ groups,
                                                     const int32_t *__restrict__ nparent,
                                                     const NodeTopo *__restrict__ topo, int batch_size,
-                                                    int32_t *__restrict__ bstart) {
+                                                    int32_t *__restrict__ bstart,
+                                                    const int32_t *__restrict__ weight) {
   const int ng = *ngroups;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
     if (g > 0 && next_sibling(groups, nparent, g)) continue;  // not a run start
     int fill = 0;
     for (int h = g; h < ng && (h == g || next_sibling(groups, nparent, h)); h++) {
-      const int c = topo[groups[h]].count;
+      const int c = weight ? weight[groups[h]] : topo[groups[h]].count;
       const bool start = (h == g) || (fill + c > batch_size);
       bstart[h] = start ? 1 : 0;
       fill = start ? c : fill + c;
@@ -787,10 +791,18 @@ tsph_status tsph_impl_build_tree(Ctx *c, const tsph_state *s, hipStream_t st) {
   // walk batches of sibling groups
   const int gbl = blocks_for(c->cap_nodes, T, 8192);
   hipLaunchKernelGGL(k_batch_mark, dim3(gbl), dim3(T), 0, st, c->ngroups, c->groups, c->nparent, c->topo,
-                     kWave, c->ctmpn);
+                     kWave, c->ctmpn, (const int32_t *)nullptr);
   launch_scan(c, c->ctmpn, 0, c->ngroups, c->cap_nodes, c->cscan, c->nbatches, nullptr, 0, st);
   hipLaunchKernelGGL(k_batch_emit, dim3(gbl), dim3(T), 0, st, c->ngroups, c->ctmpn, c->cscan, c->batches,
                      c->cap_nodes, c->flags);
+  // the SPH walks' batches: up to 64 gas sinks each
+  if (s->n_gas > 0) {
+    hipLaunchKernelGGL(k_batch_mark, dim3(gbl), dim3(T), 0, st, c->ngroups, c->groups, c->nparent, c->topo,
+                       kWave, c->ctmpn, (const int32_t *)c->nngas);
+    launch_scan(c, c->ctmpn, 0, c->ngroups, c->cap_nodes, c->cscan, c->nsbatches, nullptr, 0, st);
+    hipLaunchKernelGGL(k_batch_emit, dim3(gbl), dim3(T), 0, st, c->ngroups, c->ctmpn, c->cscan, c->sbatches,
+                       c->cap_nodes, c->flags);
+  }
   TSPH_HIP_CHECK(c, hipGetLastError());
   c->n = n;
   c->n_gas = s->n_gas;

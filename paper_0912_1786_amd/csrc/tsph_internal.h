@@ -175,6 +175,8 @@ struct Ctx {
   int32_t *groups;        // cap_nodes group nodes
   int2 *batches;          // cap_nodes walk batches: group ranges [g0, g1)
   int32_t *nbatches;
+  int2 *sbatches;         // cap_nodes SPH walk batches (packed by gas count)
+  int32_t *nsbatches;
   int32_t *gflag;         // cap_n group start flags / scan
 
   // ---- members (tsph_set_members) ----
