@@ -102,7 +102,9 @@ typedef struct {
   int32_t tc92;        /* 1: Thomas & Couchman gradient in the SPH pairs       */
   int32_t h_maxit;     /* Newton iterations per solve                          */
   double h_tol;        /* stop when |dh| < h_tol * h_start                      */
-  double kappa;        /* candidate search radius 2 h_guess (1 + kappa)        */
+  double kappa;        /* candidate search radius 2 h_guess (1 + kappa); a    *
+                        * margin that saves walks when h grows (the results  *
+                        * do not depend on it)                               */
   int32_t leaf_size;   /* particles per tree leaf (1..64)                      */
   int32_t group_size;  /* sinks per walk group (leaf_size..64)                 */
   int32_t precision;   /* TSPH_FP64 or TSPH_FP32_BULK                           */
@@ -220,7 +222,7 @@ tsph_status tsph_destroy(void *ctx);
 tsph_status tsph_set_params(void *ctx, const tsph_params *p);
 /* Fill p with the defaults: G=1, theta=0.5, quadrupoles, adaptive softening,
  * 50 neighbours, gamma=5/3, alpha=1, beta=2, av_eps2=0.01, TC92 on,
- * h_tol=1e-10, kappa=0.1, leaf 16, group 64, eta_dt=0.1, split_leaves 256,
+ * h_tol=1e-10, kappa=0.02, leaf 16, group 64, eta_dt=0.1, split_leaves 256,
  * max_members 1. */
 void tsph_default_params(tsph_params *p);
 /* Device bytes a context of this capacity reserves (host-only, no GPU).  The

@@ -247,7 +247,7 @@ void tsph_default_params(tsph_params *p) {
   p->tc92 = 1;
   p->h_maxit = 60;
   p->h_tol = 1e-10;
-  p->kappa = 0.1;
+  p->kappa = 0.02;
   p->leaf_size = 16;
   p->group_size = 64;
   p->precision = TSPH_FP64;

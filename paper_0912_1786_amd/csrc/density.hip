@@ -171,11 +171,10 @@ __device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, 
   const double ih4 = ih3 * ih;
   const double two_h = 2.0 * h;
   const double R2 = two_h * two_h;
-  uint64_t mask = 0;
-  for (int j = 0; j < nt; j++) {
+  uint64_t mask = tile_mask(nt, [&](int j) {
     const double4 a = T.pm[j];
-    if (dist2_pair(px, py, pz, a.x, a.y, a.z) < R2) mask |= 1ull << j;
-  }
+    return dist2_pair(px, py, pz, a.x, a.y, a.z) < R2;
+  });
   while (mask) {
     const int j = __builtin_ctzll(mask);
     mask &= mask - 1;
@@ -221,18 +220,50 @@ __device__ __forceinline__ void stage_tile(const DensArgs &A, DensTile &T, int n
   __syncthreads();
 }
 
+// The gas among the candidates of the lanes' raw slots (slot ln holds q, nt
+// valid) appended to the tile, which holds fill gas candidates: a full tile
+// is evaluated and the remainder carried over.  Each lane meets its
+// neighbours in candidate order, as without the compaction.  Returns the new
+// fill.
+template <bool kFull>
+__device__ __forceinline__ int stage_gas_sums(const DensArgs &A, DensTile &T, int nt, int q, int fill, double px,
+                                              double py, double pz, const double4 &vp, double h, bool want_div,
+                                              bool want_phi, int32_t *dbg_row, int &ndbg, Sums &s) {
+  const int ln = lane();
+  const bool g = ln < nt && A.gas[q] != 0;
+  const uint64_t gm = ballot(g);
+  const int slot = fill + mbcnt(gm);
+  const int ng = __popcll(gm);
+  if (g && slot < kWave) {
+    T.pm[slot] = A.pm[q];
+    if (kFull && want_div) T.vu[slot] = A.vu[q];
+    T.q[slot] = q;
+  }
+  __syncthreads();
+  if (fill + ng < kWave) return fill + ng;
+  tile_sums<kFull>(A, T, kWave, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
+  __syncthreads();
+  if (g && slot >= kWave) {
+    T.pm[slot - kWave] = A.pm[q];
+    if (kFull && want_div) T.vu[slot - kWave] = A.vu[q];
+    T.q[slot - kWave] = q;
+  }
+  __syncthreads();
+  return fill + ng - kWave;
+}
+
 // Kernel sums over the particles of a batch of candidate leaves at length h
 // (per lane).  The leaves are scanned in order and their particles packed 64
-// to a tile, each lane loading the particle of its slot; every lane then
-// evaluates the whole tile.  kFull adds the mass density, the mass-weighted
-// h-derivative, the velocity divergence (gas solve) and the mass-weighted
-// d phi / d eps (softening).
+// to a tile, each lane loading the particle of its slot (gas solves: only
+// the gas particles, compacted); every lane then evaluates the whole tile.
+// kFull adds the mass density, the mass-weighted h-derivative, the velocity
+// divergence (gas solve) and the mass-weighted d phi / d eps (softening).
 template <bool kFull>
 __device__ void leaf_sums(const DensArgs &A, int nleaf, const int *s_leaf, DensTile &T, bool gas_only, double px,
                           double py, double pz, const double4 &vp, double h, bool want_div, bool want_phi,
                           int32_t *dbg_row, int &ndbg, Sums &s) {
   const int ln = lane();
-  int fill = 0, rq = 0;
+  int fill = 0, rq = 0, gfill = 0;
   for (int c1 = 0; c1 < nleaf; c1 += kWave) {
     const int nc = min(kWave, nleaf - c1);
     const NodeTopo my = ln < nc ? A.topo[s_leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
@@ -245,15 +276,28 @@ __device__ void leaf_sums(const DensArgs &A, int nleaf, const int *s_leaf, DensT
         fill += tk;
         off += tk;
         if (fill == kWave) {
-          stage_tile(A, T, kWave, rq, gas_only, kFull && want_div);
-          tile_sums<kFull>(A, T, kWave, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
-          __syncthreads();
+          if (gas_only) {
+            gfill = stage_gas_sums<kFull>(A, T, kWave, rq, gfill, px, py, pz, vp, h, want_div, want_phi, dbg_row,
+                                          ndbg, s);
+          } else {
+            stage_tile(A, T, kWave, rq, gas_only, kFull && want_div);
+            tile_sums<kFull>(A, T, kWave, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
+            __syncthreads();
+          }
           fill = 0;
         }
       }
     }
   }
-  if (fill > 0) {
+  if (gas_only) {
+    if (fill > 0)
+      gfill = stage_gas_sums<kFull>(A, T, fill, rq, gfill, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg,
+                                    s);
+    if (gfill > 0) {
+      tile_sums<kFull>(A, T, gfill, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
+      __syncthreads();
+    }
+  } else if (fill > 0) {
     stage_tile(A, T, fill, rq, gas_only, kFull && want_div);
     tile_sums<kFull>(A, T, fill, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg, s);
     __syncthreads();
