@@ -20,7 +20,7 @@ def build(verbose: bool = False, out: str = OUT, native: bool = False) -> str:
     builds it (the default build also runs on other hosts)."""
     opt = ["-O3", "-march=native"] if native else ["-O2"]
     cmd = ["gcc", *opt, "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11",
-           "-D_GNU_SOURCE", "-Wall", "-o", out + ".tmp", SRC, "-lm"]
+           "-D_GNU_SOURCE", "-Wall", "-o", out + ".tmp", SRC, "-lm", "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

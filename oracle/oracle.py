@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("visc_form", C.c_int32), ("entropy", C.c_int32), ("xsph_eta", C.c_double),
                 ("h_scheme", C.c_int32), ("h_weight", C.c_int32), ("balsara", C.c_int32),
                 ("alpha_switch", C.c_int32), ("alpha_min", C.c_double), ("conduction", C.c_int32),
-                ("alpha_u_min", C.c_double)]
+                ("alpha_u_min", C.c_double), ("period", C.c_double)]
 
 
 class Run(C.Structure):
@@ -96,12 +96,14 @@ def lib():
         L.orc_tree_batches.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, I64, I64]
         L.orc_tree_batches.restype = C.c_int64
         L.orc_neighbours.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_int64, D, D, D, D, C.c_int32,
-                                     I64, I64, C.c_int64]
+                                     I64, I64, C.c_int64, C.c_double]
         L.orc_neighbours.restype = C.c_int64
         L.orc_potential_energy.argtypes = [C.c_int64, D, D, D, D, D, C.c_double]
         L.orc_potential_energy.restype = C.c_double
         L.orc_kick_drift.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_int32] + [D] * 22 + \
-            [D, D, C.c_double, D, D, C.c_double]
+            [D, D, C.c_double, D, D, C.c_double, C.c_double]
+        L.orc_ewald_exact.argtypes = [C.c_double] * 5 + [D]
+        L.orc_ewald_interp.argtypes = [C.c_double] * 4 + [D]
         L.orc_timestep.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64] + [D] * 12 + [C.c_double, D, D]
         L.orc_timestep.restype = C.c_double
         L.orc_timestep_each.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64] + [D] * 12 + [C.c_double, D, D, D]
@@ -135,7 +137,7 @@ def params(**kw) -> Params:
              group_size=32, walk_mode=WALK_GROUP, nbr_mode=NBR_TREE, gravity=1, hydro=1, batch_size=64,
              batch_mode=0, grav_corr_literal=0, soften_cells=0, visc_form=VISC_MG, entropy=0, xsph_eta=0.0,
              h_scheme=H_LAGRANGIAN, h_weight=HW_NUMBER, balsara=0, alpha_switch=0, alpha_min=0.01,
-             conduction=0, alpha_u_min=0.0)
+             conduction=0, alpha_u_min=0.0, period=0.0)
     if "nnei" in kw:
         e = eta_from_nnei(kw.pop("nnei"))
         d["eta_h"] = d["eta_eps"] = e
@@ -242,7 +244,7 @@ def tree(ic_or_xyz, leaf_size: int, m=None, group_size: int | None = None, batch
 
 
 def neighbours(kind: int, x, y, z, length, n_gas: int, mode: int = NBR_TREE, leaf_size: int = 8,
-               cap: int | None = None):
+               cap: int | None = None, period: float = 0.0):
     """CSR neighbour sets (offsets[n+1], idx) -- see orc_neighbours."""
     x, y, z, length = (_f64(a) for a in (x, y, z, length))
     n = x.size
@@ -251,9 +253,9 @@ def neighbours(kind: int, x, y, z, length, n_gas: int, mode: int = NBR_TREE, lea
         cap = 256 * n + 1024
     idx = np.zeros(cap, np.int64)
     tot = lib().orc_neighbours(kind, mode, n, n_gas, _p(x), _p(y), _p(z), _p(length), leaf_size,
-                               _p(off, I64), _p(idx, I64), cap)
+                               _p(off, I64), _p(idx, I64), cap, float(period))
     if tot < 0:
-        return neighbours(kind, x, y, z, length, n_gas, mode, leaf_size, cap=int(off[-1]) + 1)
+        return neighbours(kind, x, y, z, length, n_gas, mode, leaf_size, cap=int(off[-1]) + 1, period=period)
     return off, idx[:tot].copy()
 
 
@@ -263,7 +265,7 @@ def potential_energy(x, y, z, m, eps, G: float = 1.0) -> float:
 
 
 def kick_drift(st: dict, dt: float, phase: int, acc, dudt, pred: dict | None = None,
-               lengths: dict | None = None, xsph=None, alphas: dict | None = None):
+               lengths: dict | None = None, xsph=None, alphas: dict | None = None, period: float = 0.0):
     """In-place KDK half step on a state dict (x, y, z, vx, vy, vz, u).
 
     ``lengths`` (phase 0): arrays "h" and "eps", updated in place along the
@@ -286,7 +288,18 @@ def kick_drift(st: dict, dt: float, phase: int, acc, dudt, pred: dict | None = N
                          *((_p(_f64(v)) for v in xsph) if xsph is not None else (D(), D(), D())),
                          *((_p(alphas["alpha"]), _p(_f64(alphas["dalpha"])), float(alphas["alpha_min"]),
                             _p(alphas["alpha_u"]), _p(_f64(alphas["dalpha_u"])), float(alphas["alpha_u_min"]))
-                           if alphas is not None else (D(), D(), 0.0, D(), D(), 0.0)))
+                           if alphas is not None else (D(), D(), 0.0, D(), D(), 0.0)), float(period))
+
+
+def ewald(x, y, z, L: float, omega: float | None = None) -> np.ndarray:
+    """Ewald correction per unit mass at displacement (x, y, z): the sums
+    (omega given) or the tabulated, interpolated form (omega None)."""
+    out = np.zeros(3)
+    if omega is None:
+        lib().orc_ewald_interp(float(x), float(y), float(z), float(L), _p(out))
+    else:
+        lib().orc_ewald_exact(float(x), float(y), float(z), float(L), float(omega), _p(out))
+    return out
 
 
 def timestep(prm: Params, st: dict, out: dict, eta_dt: float = 0.1) -> float:

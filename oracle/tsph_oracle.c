@@ -33,6 +33,7 @@
 #include "tsph_oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -497,11 +498,29 @@ static double sq_axis(double lo, double hi, double p)
   return d * d;
 }
 
-static double box_point_d2(const double *lo, const double *hi, double px, double py, double pz)
+/* nearest-image component of a displacement in a periodic box of side L
+ * (Sect. 4.3; L = 0: open boundaries) */
+static double wrapd(double d, double L)
 {
-  double s = sq_axis(lo[0], hi[0], px);
-  s = s + sq_axis(lo[1], hi[1], py);
-  s = s + sq_axis(lo[2], hi[2], pz);
+  return L > 0.0 ? d - L * nearbyint(d / L) : d;
+}
+
+/* the same gaps on a circle of circumference L: the nearest-image distance
+ * of the centres less the half-widths */
+static double sq_axis_p(double lo, double hi, double p, double L)
+{
+  if (!(L > 0.0)) return sq_axis(lo, hi, p);
+  double c = 0.5 * (lo + hi), w = 0.5 * (hi - lo);
+  double t = fabs(wrapd(p - c, L));
+  double d = t > w ? t - w : 0.0;
+  return d * d;
+}
+
+static double box_point_d2(const double *lo, const double *hi, double px, double py, double pz, double L)
+{
+  double s = sq_axis_p(lo[0], hi[0], px, L);
+  s = s + sq_axis_p(lo[1], hi[1], py, L);
+  s = s + sq_axis_p(lo[2], hi[2], pz, L);
   return s;
 }
 
@@ -513,18 +532,142 @@ static double gap_axis(double lo1, double hi1, double lo2, double hi2)
   return d * d;
 }
 
-static double box_box_d2(const double *lo1, const double *hi1, const double *lo2, const double *hi2)
+static double gap_axis_p(double lo1, double hi1, double lo2, double hi2, double L)
 {
-  double s = gap_axis(lo1[0], hi1[0], lo2[0], hi2[0]);
-  s = s + gap_axis(lo1[1], hi1[1], lo2[1], hi2[1]);
-  s = s + gap_axis(lo1[2], hi1[2], lo2[2], hi2[2]);
+  if (!(L > 0.0)) return gap_axis(lo1, hi1, lo2, hi2);
+  double c1 = 0.5 * (lo1 + hi1), w1 = 0.5 * (hi1 - lo1);
+  double c2 = 0.5 * (lo2 + hi2), w2 = 0.5 * (hi2 - lo2);
+  double d = fabs(wrapd(c2 - c1, L)) - w1 - w2;
+  if (!(d > 0.0)) d = 0.0;
+  return d * d;
+}
+
+static double box_box_d2(const double *lo1, const double *hi1, const double *lo2, const double *hi2, double L)
+{
+  double s = gap_axis_p(lo1[0], hi1[0], lo2[0], hi2[0], L);
+  s = s + gap_axis_p(lo1[1], hi1[1], lo2[1], hi2[1], L);
+  s = s + gap_axis_p(lo1[2], hi1[2], lo2[2], hi2[2], L);
   return s;
 }
 
-static double pair_r2(double xi, double yi, double zi, double xj, double yj, double zj)
+static double pair_r2(double xi, double yi, double zi, double xj, double yj, double zj, double L)
 {
-  double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+  double dx = wrapd(xj - xi, L), dy = wrapd(yj - yi, L), dz = wrapd(zj - zi, L);
   return dx * dx + dy * dy + dz * dz;
+}
+
+/* ---- Ewald correction (Sect. 4.3) ---------------------------------------- */
+
+/* The acceleration per unit mass of all replicas of a unit mass at
+ * displacement x (evaluation point minus mass), with the direct term
+ * -x/|x|^3 taken out: the real-space sum over |n| < 5 with erfc and the
+ * Gaussian, and the Fourier sum over 0 < |h| < 5, splitting parameter
+ * omega.  Zero at x = 0 (by symmetry). */
+void orc_ewald_exact(double x, double y, double z, double L, double omega, double *acc)
+{
+  acc[0] = acc[1] = acc[2] = 0.0;
+  if (x == 0.0 && y == 0.0 && z == 0.0) return;
+  double r2 = x * x + y * y + z * z, r = sqrt(r2);
+  double ax = x / (r2 * r), ay = y / (r2 * r), az = z / (r2 * r);
+  for (int nx = -4; nx <= 4; nx++)
+    for (int ny = -4; ny <= 4; ny++)
+      for (int nz = -4; nz <= 4; nz++) {
+        if (nx * nx + ny * ny + nz * nz >= 25) continue;
+        double dx = x - nx * L, dy = y - ny * L, dz = z - nz * L;
+        double d2 = dx * dx + dy * dy + dz * dz, d = sqrt(d2);
+        double f = (erfc(omega * d) + 2.0 * omega * d / sqrt(M_PI) * exp(-omega * omega * d2)) / (d2 * d);
+        ax -= dx * f;
+        ay -= dy * f;
+        az -= dz * f;
+      }
+  for (int hx = -4; hx <= 4; hx++)
+    for (int hy = -4; hy <= 4; hy++)
+      for (int hz = -4; hz <= 4; hz++) {
+        int h2 = hx * hx + hy * hy + hz * hz;
+        if (h2 == 0 || h2 >= 25) continue;
+        double c = 2.0 / (L * L) / h2 * exp(-M_PI * M_PI * h2 / (omega * omega * L * L)) *
+                   sin(2.0 * M_PI / L * (hx * x + hy * y + hz * z));
+        ax -= c * hx;
+        ay -= c * hy;
+        az -= c * hz;
+      }
+  acc[0] = ax;
+  acc[1] = ay;
+  acc[2] = az;
+}
+
+/* Tables of the correction on [0, L/2]^3 for omega = 2/L, ORC_EWALD_GRID
+ * intervals per axis, built once per L (a few tables kept) */
+#define EW_N ORC_EWALD_GRID
+#define EW_KEEP 4
+static double ew_L[EW_KEEP];
+static double *ew_T[EW_KEEP];
+static pthread_mutex_t ew_lock = PTHREAD_MUTEX_INITIALIZER;
+
+static const double *ewald_table(double L)
+{
+  pthread_mutex_lock(&ew_lock);
+  const double *T = NULL;
+  for (int k = 0; k < EW_KEEP; k++)
+    if (ew_T[k] && ew_L[k] == L) T = ew_T[k];
+  if (!T) {
+    int slot = 0;
+    while (slot < EW_KEEP - 1 && ew_T[slot]) slot++;
+    free(ew_T[slot]);
+    const int n1 = EW_N + 1;
+    double *W = malloc((size_t)3 * n1 * n1 * n1 * sizeof(double));
+    double step = 0.5 * L / EW_N;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t a = 0; a < (int64_t)n1 * n1 * n1; a++) {
+      int i = (int)(a / (n1 * n1)), j = (int)((a / n1) % n1), k = (int)(a % n1);
+      double e[3];
+      orc_ewald_exact(i * step, j * step, k * step, L, 2.0 / L, e);
+      /* odd in its own coordinate: zero on that coordinate plane */
+      W[3 * a + 0] = i == 0 ? 0.0 : e[0];
+      W[3 * a + 1] = j == 0 ? 0.0 : e[1];
+      W[3 * a + 2] = k == 0 ? 0.0 : e[2];
+    }
+    ew_T[slot] = W;
+    ew_L[slot] = L;
+    T = W;
+  }
+  pthread_mutex_unlock(&ew_lock);
+  return T;
+}
+
+/* trilinear interpolation on |x_k|, the component taking the sign of x_k
+ * (the correction is odd in its own coordinate, even in the others) */
+static void ewald_interp(const double *T, double L, double x, double y, double z, double *acc)
+{
+  const int n1 = EW_N + 1;
+  double a[3] = {fabs(x), fabs(y), fabs(z)}, f[3];
+  int i[3];
+  double step = 0.5 * L / EW_N;
+  for (int d = 0; d < 3; d++) {
+    double u = a[d] / step;
+    int k = (int)floor(u);
+    if (k > EW_N - 1) k = EW_N - 1;
+    if (k < 0) k = 0;
+    i[d] = k;
+    f[d] = u - k;
+  }
+  for (int c = 0; c < 3; c++) {
+    double v = 0.0;
+    for (int b = 0; b < 8; b++) {
+      int ox = b >> 2, oy = (b >> 1) & 1, oz = b & 1;
+      double w = (ox ? f[0] : 1.0 - f[0]) * (oy ? f[1] : 1.0 - f[1]) * (oz ? f[2] : 1.0 - f[2]);
+      v += w * T[3 * (((int64_t)(i[0] + ox) * n1 + (i[1] + oy)) * n1 + (i[2] + oz)) + c];
+    }
+    acc[c] = v;
+  }
+  if (x < 0.0) acc[0] = -acc[0];
+  if (y < 0.0) acc[1] = -acc[1];
+  if (z < 0.0) acc[2] = -acc[2];
+}
+
+void orc_ewald_interp(double x, double y, double z, double L, double *acc)
+{
+  ewald_interp(ewald_table(L), L, x, y, z, acc);
 }
 
 /* ===================================================================== */
@@ -554,6 +697,9 @@ typedef struct {
   int64_t *ngas;
   /* per-node softened-cell data: mass-weighted mean eps, sum of m xi/Ups */
   double *epsbar, *xsum;
+  /* periodic box side (0: open) and its Ewald table */
+  double L;
+  const double *ewt;
 } ctx_t;
 
 typedef struct {
@@ -583,11 +729,11 @@ static void collect(const ctx_t *C, int64_t p, double R, int gas_only, cand_t *c
   while (sp > 0) {
     int64_t k = c->stack[--sp];
     if (gas_only && C->ngas[k] == 0) continue;
-    if (!(box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz) < R2)) continue;
+    if (!(box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz, C->L) < R2)) continue;
     if (t->nchild[k] == 0) {
       for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++) {
         if (gas_only && !C->gas[q]) continue;
-        if (pair_r2(px, py, pz, t->xs[q], t->ys[q], t->zs[q]) < R2) cand_add(c, q);
+        if (pair_r2(px, py, pz, t->xs[q], t->ys[q], t->zs[q], C->L) < R2) cand_add(c, q);
       }
     } else {
       for (int32_t a = t->nchild[k] - 1; a >= 0; a--) c->stack[sp++] = t->child[k] + a;
@@ -606,9 +752,11 @@ static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, 
   double px = t->xs[p], py = t->ys[p], pz = t->zs[p];
   for (int64_t a = 0; a < c->n; a++) {
     int64_t q = c->idx[a];
-    double r2 = pair_r2(px, py, pz, t->xs[q], t->ys[q], t->zs[q]);
+    double r2 = pair_r2(px, py, pz, t->xs[q], t->ys[q], t->zs[q], C->L);
     double r = sqrt(r2);
     if (!(r < 2.0 * h)) continue;
+    /* x_i - x_j, the nearest image */
+    double ex = wrapd(px - t->xs[q], C->L), ey = wrapd(py - t->ys[q], C->L), ez = wrapd(pz - t->zs[q], C->L);
     double W = orc_W(r, h), dWdh = orc_dWdh(r, h);
     s.n += W;
     s.sdh += dWdh;
@@ -621,9 +769,8 @@ static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, 
         if (r > 0.0) {
           double g = orc_dWdr(r, h) / r; /* grad_i W = g (x_i - x_j) */
           double dvx = C->vx[p] - C->vx[q], dvy = C->vy[p] - C->vy[q], dvz = C->vz[p] - C->vz[q];
-          s.divv += g * (dvx * (px - t->xs[q]) + dvy * (py - t->ys[q]) + dvz * (pz - t->zs[q]));
+          s.divv += g * (dvx * ex + dvy * ey + dvz * ez);
           /* curl: v_ij x grad_i W_ij */
-          double ex = px - t->xs[q], ey = py - t->ys[q], ez = pz - t->zs[q];
           s.curl[0] += g * (dvy * ez - dvz * ey);
           s.curl[1] += g * (dvz * ex - dvx * ez);
           s.curl[2] += g * (dvx * ey - dvy * ex);
@@ -636,7 +783,7 @@ static sums_t kernel_sums(const ctx_t *C, int64_t p, double h, const cand_t *c, 
         if (r > 0.0) {
           double g = orc_dWdr(r, h) / r;
           double dvx = C->vx[p] - C->vx[q], dvy = C->vy[p] - C->vy[q], dvz = C->vz[p] - C->vz[q];
-          s.divv += g * (dvx * (px - t->xs[q]) + dvy * (py - t->ys[q]) + dvz * (pz - t->zs[q]));
+          s.divv += g * (dvx * ex + dvy * ey + dvz * ez);
         }
       }
     }
@@ -743,7 +890,7 @@ static int solve_count(const ctx_t *C, int64_t p, int64_t nstd, double guess, ca
     double *d = malloc(2 * (c->n + 1) * sizeof(double));
     for (int64_t a = 0; a < c->n; a++) {
       int64_t q = c->idx[a];
-      d[2 * a] = pair_r2(t->xs[p], t->ys[p], t->zs[p], t->xs[q], t->ys[q], t->zs[q]);
+      d[2 * a] = pair_r2(t->xs[p], t->ys[p], t->zs[p], t->xs[q], t->ys[q], t->zs[q], C->L);
       d[2 * a + 1] = mass_w ? t->ms[q] / t->ms[p] : 1.0;
     }
     qsort(d, c->n, 2 * sizeof(double), cmp_double);
@@ -902,6 +1049,18 @@ static void node_maxima(ctx_t *C)
 
 /* ---- gravity ----------------------------------------------------------- */
 
+/* periodic box: the replicas of mass m at displacement x (Sect. 4.3) */
+static void ewald_add(const ctx_t *C, double m, double dx, double dy, double dz, double *a)
+{
+  if (!(C->L > 0.0)) return;
+  double e[3];
+  ewald_interp(C->ewt, C->L, dx, dy, dz, e);
+  double G = C->p->G;
+  a[0] += G * m * e[0];
+  a[1] += G * m * e[1];
+  a[2] += G * m * e[2];
+}
+
 /* Far-field node: monopole plus traceless quadrupole about the centre of
  * mass (Sect. 2.2), unsoftened. r = x_i - com.
  *   a = -G M r/r^3 + G [Q r / r^5 - 5/2 (r.Q.r) r / r^7]
@@ -911,7 +1070,8 @@ static void far_node(const ctx_t *C, int64_t k, double px, double py, double pz,
 {
   const orc_tree *t = C->t;
   double G = C->p->G;
-  double dx = px - t->com[3 * k], dy = py - t->com[3 * k + 1], dz = pz - t->com[3 * k + 2];
+  double dx = wrapd(px - t->com[3 * k], C->L), dy = wrapd(py - t->com[3 * k + 1], C->L),
+         dz = wrapd(pz - t->com[3 * k + 2], C->L);
   double r2 = dx * dx + dy * dy + dz * dz;
   double r = sqrt(r2), M = t->mass[k];
   double ir3 = 1.0 / (r2 * r);
@@ -931,6 +1091,7 @@ static void far_node(const ctx_t *C, int64_t k, double px, double py, double pz,
     a[2] += G * (qz * ir5 - 2.5 * rqr * dz * ir7);
     *pot -= 0.5 * G * rqr * ir5;
   }
+  ewald_add(C, M, dx, dy, dz, a);
 }
 
 /* Softened pair j -> i (Sect. 2.1 Eq. dLgravdr, App. B):
@@ -944,11 +1105,13 @@ static void near_pair(const ctx_t *C, int64_t p, int64_t q, double *a, double *p
 {
   const orc_tree *t = C->t;
   double G = C->p->G;
-  double dx = t->xs[p] - t->xs[q], dy = t->ys[p] - t->ys[q], dz = t->zs[p] - t->zs[q];
+  double dx = wrapd(t->xs[p] - t->xs[q], C->L), dy = wrapd(t->ys[p] - t->ys[q], C->L),
+         dz = wrapd(t->zs[p] - t->zs[q], C->L);
   double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
   double ei = C->eps[p], ej = C->eps[q], mj = t->ms[q];
   *pot += G * mj * 0.5 * (orc_phi(r, ei) + orc_phi(r, ej));
   if (!(r > 0.0)) return;
+  ewald_add(C, mj, dx, dy, dz, a);
   double f = G * mj * 0.5 * (orc_dphidr(r, ei) + orc_dphidr(r, ej));
   if (C->p->soft_mode == ORC_SOFT_ADAPTIVE) {
     if (C->p->grav_corr_literal)
@@ -974,9 +1137,11 @@ static void soft_cell(const ctx_t *C, int64_t k, int64_t p, double *a, double *p
 {
   const orc_tree *t = C->t;
   double G = C->p->G;
-  double dx = t->xs[p] - t->com[3 * k], dy = t->ys[p] - t->com[3 * k + 1], dz = t->zs[p] - t->com[3 * k + 2];
+  double dx = wrapd(t->xs[p] - t->com[3 * k], C->L), dy = wrapd(t->ys[p] - t->com[3 * k + 1], C->L),
+         dz = wrapd(t->zs[p] - t->com[3 * k + 2], C->L);
   double r = sqrt(dx * dx + dy * dy + dz * dz);
   double ei = C->eps[p], ek = C->epsbar[k], M = t->mass[k];
+  ewald_add(C, M, dx, dy, dz, a);
   *pot += G * M * 0.5 * (orc_phi(r, ei) + orc_phi(r, ek));
   double f = G * M * 0.5 * (orc_dphidr(r, ei) + orc_dphidr(r, ek));
   if (C->p->soft_mode == ORC_SOFT_ADAPTIVE) {
@@ -1004,10 +1169,10 @@ static int accept_point(const ctx_t *C, int64_t k, double px, double py, double 
   const orc_tree *t = C->t;
   if (!(P->theta > 0.0)) return 0;
   double rm = t->side[k] / P->theta + t->delta[k];
-  double d2 = pair_r2(px, py, pz, t->com[3 * k], t->com[3 * k + 1], t->com[3 * k + 2]);
+  double d2 = pair_r2(px, py, pz, t->com[3 * k], t->com[3 * k + 1], t->com[3 * k + 2], C->L);
   if (!(d2 > rm * rm)) return 0;
   double s = 2.0 * (ei > C->epsmax[k] ? ei : C->epsmax[k]);
-  if (box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz) >= s * s) return 1;
+  if (box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz, C->L) >= s * s) return 1;
   return P->soften_cells ? 2 : 0;
 }
 
@@ -1017,10 +1182,10 @@ static int accept_box(const ctx_t *C, int64_t k, const double *lo, const double 
   const orc_tree *t = C->t;
   if (!(P->theta > 0.0)) return 0;
   double rm = t->side[k] / P->theta + t->delta[k];
-  double d2 = box_point_d2(lo, hi, t->com[3 * k], t->com[3 * k + 1], t->com[3 * k + 2]);
+  double d2 = box_point_d2(lo, hi, t->com[3 * k], t->com[3 * k + 1], t->com[3 * k + 2], C->L);
   if (!(d2 > rm * rm)) return 0;
   double s = 2.0 * (emax > C->epsmax[k] ? emax : C->epsmax[k]);
-  if (box_box_d2(lo, hi, &t->bmin[3 * k], &t->bmax[3 * k]) >= s * s) return 1;
+  if (box_box_d2(lo, hi, &t->bmin[3 * k], &t->bmax[3 * k], C->L) >= s * s) return 1;
   return P->soften_cells ? 2 : 0;
 }
 
@@ -1057,7 +1222,7 @@ static void gravity_particle_walk(ctx_t *C)
               near_pair(C, p, q, a, &pot);
               npair++;
               double R = 2.0 * (C->eps[p] > C->eps[q] ? C->eps[p] : C->eps[q]);
-              if (pair_r2(px, py, pz, t->xs[q], t->ys[q], t->zs[q]) < R * R) nsoft++;
+              if (pair_r2(px, py, pz, t->xs[q], t->ys[q], t->zs[q], C->L) < R * R) nsoft++;
             }
         } else {
           for (int32_t b = t->nchild[k] - 1; b >= 0; b--) stack[sp++] = t->child[k] + b;
@@ -1204,7 +1369,8 @@ static void sph_pair(const ctx_t *C, int64_t p, int64_t q, sph_acc_t *acc)
 {
   const orc_params *P = C->p;
   const orc_tree *t = C->t;
-  double dx = t->xs[p] - t->xs[q], dy = t->ys[p] - t->ys[q], dz = t->zs[p] - t->zs[q];
+  double dx = wrapd(t->xs[p] - t->xs[q], C->L), dy = wrapd(t->ys[p] - t->ys[q], C->L),
+         dz = wrapd(t->zs[p] - t->zs[q], C->L);
   double r2 = dx * dx + dy * dy + dz * dz;
   if (!(r2 > 0.0)) return;
   double r = sqrt(r2);
@@ -1269,7 +1435,7 @@ static void sph_pair(const ctx_t *C, int64_t p, int64_t q, sph_acc_t *acc)
 static int sph_nbr(const ctx_t *C, int64_t p, int64_t q)
 {
   const orc_tree *t = C->t;
-  double r2 = pair_r2(t->xs[p], t->ys[p], t->zs[p], t->xs[q], t->ys[q], t->zs[q]);
+  double r2 = pair_r2(t->xs[p], t->ys[p], t->zs[p], t->xs[q], t->ys[q], t->zs[q], C->L);
   double R = 2.0 * (C->h[p] > C->h[q] ? C->h[p] : C->h[q]);
   return r2 < R * R;
 }
@@ -1317,7 +1483,7 @@ static void sph_phase(ctx_t *C)
           int64_t k = stack[--sp];
           if (C->ngas[k] == 0) continue;
           double R = 2.0 * (C->h[p] > C->hmax[k] ? C->h[p] : C->hmax[k]);
-          if (!(box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz) < R * R)) continue;
+          if (!(box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], px, py, pz, C->L) < R * R)) continue;
           if (t->nchild[k] == 0) {
             for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++)
               if (q != p && C->gas[q] && sph_nbr(C, p, q)) { sph_pair(C, p, q, &acc); npair++; }
@@ -1378,13 +1544,36 @@ int orc_compute_forces(const orc_params *p, orc_run *r)
   if (!r->x || !r->y || !r->z || !r->m) return -1;
   if (p->gravity && p->soft_mode == ORC_SOFT_CONSTANT && !r->eps_in) return -1;
   if (p->conduction && p->entropy) return -1;  /* conduction acts on u */
+  if (!(p->period >= 0.0)) return -1;
   int64_t n = r->n;
   double t0 = wall_seconds();
-  orc_tree *t = orc_tree_build(n, r->x, r->y, r->z, r->m, p->leaf_size);
+  /* a periodic box takes the positions modulo its side (Sect. 4.3) */
+  const double L = p->period;
+  double *wx = NULL, *wy = NULL, *wz = NULL;
+  const double *px = r->x, *py = r->y, *pz = r->z;
+  if (L > 0.0) {
+    wx = malloc(n * sizeof(double));
+    wy = malloc(n * sizeof(double));
+    wz = malloc(n * sizeof(double));
+    for (int64_t i = 0; i < n; i++) {
+      wx[i] = r->x[i] - L * floor(r->x[i] / L);
+      wy[i] = r->y[i] - L * floor(r->y[i] / L);
+      wz[i] = r->z[i] - L * floor(r->z[i] / L);
+    }
+    px = wx;
+    py = wy;
+    pz = wz;
+  }
+  orc_tree *t = orc_tree_build(n, px, py, pz, r->m, p->leaf_size);
+  free(wx);
+  free(wy);
+  free(wz);
   if (!t) return -2;
   ctx_t C;
   memset(&C, 0, sizeof(C));
   C.p = p;
+  C.L = L;
+  C.ewt = (L > 0.0 && p->gravity) ? ewald_table(L) : NULL;
   C.t = t;
   C.n = n;
   C.n_gas = r->n_gas;
@@ -1502,11 +1691,28 @@ static int cmp_i64_int(const void *a, const void *b)
 
 int64_t orc_neighbours(int kind, int mode, int64_t n, int64_t n_gas, const double *x,
                        const double *y, const double *z, const double *len, int32_t leaf_size,
-                       int64_t *offsets, int64_t *idx, int64_t cap)
+                       int64_t *offsets, int64_t *idx, int64_t cap, double period)
 {
   /* The predicates are the symmetric ones of Sect. 3.1 and the correction
    * criterion of Sect. 2.1, evaluated on caller-order coordinates with
-   * dx = x_j - x_i, r^2 = dx dx + dy dy + dz dz (left to right). */
+   * dx = x_j - x_i, r^2 = dx dx + dy dy + dz dz (left to right); in a
+   * periodic box the positions are taken modulo the side and dx is the
+   * nearest image. */
+  const double L = period > 0.0 ? period : 0.0;
+  double *wx = NULL, *wy = NULL, *wz = NULL;
+  if (L > 0.0) {
+    wx = malloc(n * sizeof(double));
+    wy = malloc(n * sizeof(double));
+    wz = malloc(n * sizeof(double));
+    for (int64_t i = 0; i < n; i++) {
+      wx[i] = x[i] - L * floor(x[i] / L);
+      wy[i] = y[i] - L * floor(y[i] / L);
+      wz[i] = z[i] - L * floor(z[i] / L);
+    }
+    x = wx;
+    y = wy;
+    z = wz;
+  }
   int64_t *cnt = calloc(n, sizeof(int64_t));
   orc_tree *t = (mode == ORC_NBR_TREE) ? orc_tree_build(n, x, y, z, NULL, leaf_size) : NULL;
   double *lmax = NULL;
@@ -1528,7 +1734,7 @@ int64_t orc_neighbours(int kind, int mode, int64_t n, int64_t n_gas, const doubl
       offsets[0] = 0;
       for (int64_t i = 0; i < n; i++) offsets[i + 1] = offsets[i] + cnt[i];
       total = offsets[n];
-      if (total > cap) { free(cnt); free(lmax); orc_tree_free(t); return -1; }
+      if (total > cap) { free(cnt); free(lmax); orc_tree_free(t); free(wx); free(wy); free(wz); return -1; }
     }
 #pragma omp parallel
     {
@@ -1542,9 +1748,9 @@ int64_t orc_neighbours(int kind, int mode, int64_t n, int64_t n_gas, const doubl
           for (int64_t j = 0; j < n; j++) {
             if (kind != 2 && j >= n_gas) continue;
             if (kind != 0 && j == i) continue;
-            double r2 = pair_r2(x[i], y[i], z[i], x[j], y[j], z[j]);
-            double L = (kind == 0) ? len[i] : (len[i] > len[j] ? len[i] : len[j]);
-            double R = 2.0 * L;
+            double r2 = pair_r2(x[i], y[i], z[i], x[j], y[j], z[j], L);
+            double Lj = (kind == 0) ? len[i] : (len[i] > len[j] ? len[i] : len[j]);
+            double R = 2.0 * Lj;
             if (r2 < R * R) { if (pass) idx[base + c] = j; c++; }
           }
         } else {
@@ -1552,15 +1758,15 @@ int64_t orc_neighbours(int kind, int mode, int64_t n, int64_t n_gas, const doubl
           stack[sp++] = 0;
           while (sp > 0) {
             int64_t k = stack[--sp];
-            double L = (kind == 0) ? len[i] : (len[i] > lmax[k] ? len[i] : lmax[k]);
-            double R = 2.0 * L;
-            if (!(box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], x[i], y[i], z[i]) < R * R)) continue;
+            double Lk = (kind == 0) ? len[i] : (len[i] > lmax[k] ? len[i] : lmax[k]);
+            double R = 2.0 * Lk;
+            if (!(box_point_d2(&t->bmin[3 * k], &t->bmax[3 * k], x[i], y[i], z[i], L) < R * R)) continue;
             if (t->nchild[k] == 0) {
               for (int64_t q = t->first[k]; q < t->first[k] + t->count[k]; q++) {
                 int64_t j = t->perm[q];
                 if (kind != 2 && j >= n_gas) continue;
                 if (kind != 0 && j == i) continue;
-                double r2 = pair_r2(x[i], y[i], z[i], x[j], y[j], z[j]);
+                double r2 = pair_r2(x[i], y[i], z[i], x[j], y[j], z[j], L);
                 double Lp = (kind == 0) ? len[i] : (len[i] > len[j] ? len[i] : len[j]);
                 double Rp = 2.0 * Lp;
                 if (r2 < Rp * Rp) { if (pass) idx[base + c] = j; c++; }
@@ -1576,7 +1782,7 @@ int64_t orc_neighbours(int kind, int mode, int64_t n, int64_t n_gas, const doubl
       free(stack);
     }
     if (pass == 1) {
-      free(cnt); free(lmax); orc_tree_free(t);
+      free(cnt); free(lmax); orc_tree_free(t); free(wx); free(wy); free(wz);
       return total;
     }
   }
@@ -1624,7 +1830,7 @@ void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
                     double *h, double *eps, const double *divv_h, const double *divv_e,
                     const double *xsx, const double *xsy, const double *xsz,
                     double *alpha, const double *dalpha, double alpha_min,
-                    double *alpha_u, const double *dalpha_u, double alpha_u_min)
+                    double *alpha_u, const double *dalpha_u, double alpha_u_min, double period)
 {
   for (int64_t i = 0; i < n; i++) {
     if (phase == 0) {
@@ -1646,6 +1852,12 @@ void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
         x[i] += dt * vx[i];
         y[i] += dt * vy[i];
         z[i] += dt * vz[i];
+      }
+      if (period > 0.0) {
+        /* back into the periodic box */
+        x[i] -= period * floor(x[i] / period);
+        y[i] -= period * floor(y[i] / period);
+        z[i] -= period * floor(z[i] / period);
       }
       if (i < n_gas) {
         if (up) up[i] = u[i] + dt * dudt[i];

@@ -82,7 +82,14 @@ typedef struct {
   double alpha_min;             /* its floor (0.01)                             */
   int32_t conduction;           /* artificial thermal conductivity              */
   double alpha_u_min;           /* floor of the conductivity coefficient (0)    */
+  /* periodic box [0, L)^3 of side period (0: open), Sect. 4.3: positions are
+   * taken modulo L, every pair and node interaction uses the nearest image,
+   * and gravity adds the Ewald correction of the replicas, tabulated for
+   * omega = 2/L, |n|, |h| < 5, on a grid of ORC_EWALD_GRID intervals per
+   * half box and interpolated trilinearly (the potential gets no correction) */
+  double period;
 } orc_params;
+#define ORC_EWALD_GRID 32
 enum { ORC_VISC_MG = 0, ORC_VISC_SIGNAL = 1 };
 enum { ORC_H_LAGRANGIAN = 0, ORC_H_STANDARD = 1 };
 enum { ORC_HW_NUMBER = 0, ORC_HW_MASS = 1 };
@@ -156,7 +163,17 @@ int64_t orc_tree_batches(const orc_tree *t, int32_t group_size, int32_t batch_si
  * exceeds cap (offsets are still filled).                                   */
 int64_t orc_neighbours(int kind, int mode, int64_t n, int64_t n_gas, const double *x,
                        const double *y, const double *z, const double *len, int32_t leaf_size,
-                       int64_t *offsets, int64_t *idx, int64_t cap);
+                       int64_t *offsets, int64_t *idx, int64_t cap, double period);
+
+/* ---- Ewald correction (Sect. 4.3) ---------------------------------------------
+ * acc[3] = the acceleration per unit mass of the replicas of a unit mass at
+ * displacement x (x = the evaluation point minus the mass, |x_k| <= L/2):
+ * the Ewald sums over |n| < 5 and 0 < |h| < 5 (integer triplets, Euclidean
+ * norms) with splitting parameter omega, minus the direct term -x/|x|^3;
+ * zero at x = 0.  orc_ewald_interp: the same from the tabulated grid
+ * (omega = 2/L) by trilinear interpolation on |x_k| with the sign of x_k. */
+void orc_ewald_exact(double x, double y, double z, double L, double omega, double *acc);
+void orc_ewald_interp(double x, double y, double z, double L, double *acc);
 
 /* ---- direct sums, integrator and diagnostics ------------------------------ */
 /* V = (G/2) sum_i sum_j m_i m_j phi(r_ij, eps_i), self terms included        */
@@ -173,7 +190,8 @@ void orc_kick_drift(int64_t n, int64_t n_gas, double dt, int32_t phase,
                     double *h, double *eps, const double *divv_h, const double *divv_e,
                     const double *xsx, const double *xsy, const double *xsz,
                     double *alpha, const double *dalpha, double alpha_min,
-                    double *alpha_u, const double *dalpha_u, double alpha_u_min);
+                    double *alpha_u, const double *dalpha_u, double alpha_u_min,
+                    double period /* > 0: positions wrapped into [0, period) */);
 double orc_timestep(const orc_params *p, int64_t n, int64_t n_gas, const double *vx,
                     const double *vy, const double *vz, const double *u, const double *h,
                     const double *eps, const double *ax, const double *ay, const double *az,
