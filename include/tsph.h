@@ -88,6 +88,10 @@ enum { TSPH_KD_FIRST = 0, TSPH_KD_SECOND = 1 };
  * themselves.  The results stay valid, but their last bits then depend on
  * which batches got items first (not bitwise reproducible from run to run). */
 #define TSPH_FLAG_HANDOFF_CAPACITY 0x40u
+/* A periodic box too small for the kernels: some smoothing or softening
+ * reach 2h or 2eps is at least half the box side, where the nearest images
+ * no longer hold a particle's whole kernel (results invalid). */
+#define TSPH_FLAG_PERIOD 0x80u
 
 typedef struct {
   double G;            /* gravitational constant                               */
@@ -183,6 +187,15 @@ typedef struct {
                           with entropy (TSPH_EINVAL)                         */
   double alpha_min;    /* floor of alpha (0.01)                               */
   double alpha_u_min;  /* floor of alpha_u (0)                                */
+  double period;       /* > 0: periodic box [0, period)^3 (Sect. 4.3).  The
+                          positions are taken modulo the side (and wrapped by
+                          the drifts); every pair, node and opening test uses
+                          the nearest image (SPH included: no ghosts); gravity
+                          adds per particle and per accepted node the Ewald
+                          correction of the replicas (omega = 2/L, |n|, |h| <
+                          5), tabulated on the device for 32 intervals per half
+                          box and interpolated trilinearly.  The potential
+                          gets no correction.  0: open boundaries          */
 } tsph_params;
 enum { TSPH_VISC_MG = 0, TSPH_VISC_SIGNAL = 1 };
 enum { TSPH_H_LAGRANGIAN = 0, TSPH_H_STANDARD = 1 };

@@ -65,6 +65,7 @@ const char *param_error(const tsph_params *p) {
   if ((p->balsara | p->alpha_switch | p->conduction) & ~1) return "balsara, alpha_switch, conduction must be 0 or 1";
   if (!(p->alpha_min >= 0.0) || !(p->alpha_u_min >= 0.0)) return "alpha_min and alpha_u_min must be >= 0";
   if (p->conduction && p->entropy) return "conduction acts on u: not with the entropy variable";
+  if (!(p->period >= 0.0) || !(p->period < INFINITY)) return "period must be finite and >= 0";
   return nullptr;
 }
 
@@ -142,6 +143,7 @@ size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->add(4 * N);        // bm
   L->add(4 * N);        // bw
   L->add(4 * 16);       // bnext
+  L->add(8 * kEwaldValues);  // ewt: Ewald table of a periodic box
   return L->total;
 }
 
@@ -370,6 +372,7 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->bm = AT(int32_t *);
   c->bw = AT(int32_t *);
   c->bnext = AT(int32_t *);
+  c->ewt = AT(double *);
 #undef AT
   c->perm = c->idx[0];
   e = hipHostMalloc((void **)&c->h_flags, 64, hipHostMallocDefault);
@@ -385,6 +388,7 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
       (e = hipMemset(c->split_head, 0xff, 4 * (size_t)c->cap_nodes)) != hipSuccess ||
       (e = hipDeviceSynchronize()) != hipSuccess)
     return create_fail(c, TSPH_EHIP, "clearing the control block", e);
+  if (tsph_impl_ewald(c) != TSPH_OK) return create_fail(c, TSPH_EHIP, "the Ewald table", hipErrorUnknown);
   *out = c;
   return TSPH_OK;
 }
@@ -445,7 +449,7 @@ tsph_status tsph_set_params(void *ctx, const tsph_params *p) {
   if (node_capacity(c->cap_n, p->leaf_size) > c->cap_nodes)
     return set_err(c, TSPH_ECAPACITY, "a smaller leaf_size needs a new context");
   c->p = *p;
-  return TSPH_OK;
+  return tsph_impl_ewald(c);  // a new periodic box side: its table
 }
 
 tsph_status tsph_build_tree(void *ctx, const tsph_state *s, void *stream) {

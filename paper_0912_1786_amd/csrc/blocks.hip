@@ -44,7 +44,7 @@ struct BlkArgs {
   const int32_t *bm, *bw, *perm;
   const double *dt_i;
   int32_t *next;  // [0] next system time, [1] active count, [2] woken count
-  double dt_max, alpha_min, alpha_u_min;
+  double dt_max, alpha_min, alpha_u_min, period;
   int32_t L, wake, xsph, t, shift;
 };
 
@@ -98,6 +98,11 @@ __global__ __launch_bounds__(256) void k_blk_drift(BlkArgs A) {
   A.x[i] += d * v0;
   A.y[i] += d * v1;
   A.z[i] += d * v2;
+  if (A.period > 0.0) {  // back into the periodic box
+    A.x[i] = in_box(A.x[i], A.period);
+    A.y[i] = in_box(A.y[i], A.period);
+    A.z[i] = in_box(A.z[i], A.period);
+  }
   if (A.h && gas && A.h[i] > 0.0) A.h[i] *= grow(d, A.pdiv[i]);
   if (A.eps && A.eps[i] > 0.0) A.eps[i] *= grow(d, A.pdiv[cap + i]);
   const double dp = tick_dt(tn - A.t0[i], A.dt_max, A.L);
@@ -271,6 +276,7 @@ BlkArgs blk_args(Ctx *c, tsph_state *s, tsph_blocks *b) {
   A.dt_max = b->dt_max;
   A.alpha_min = c->p.alpha_min;
   A.alpha_u_min = c->p.alpha_u_min;
+  A.period = c->p.period;
   A.L = b->max_level;
   A.wake = (c->p.hydro && s->n_gas > 0) ? b->wake : 0;
   A.xsph = c->p.xsph_eta > 0.0 ? 1 : 0;

@@ -70,6 +70,7 @@ struct DensArgs {
   int32_t hstd;      // standard scheme: h from a fixed neighbour count nstd
   int32_t nstd;
   int32_t entropy;   // vu.w holds the entropic function A = P / rho^gamma
+  double L;          // periodic box side (0: open)
 };
 
 struct Sums {
@@ -107,16 +108,16 @@ __device__ bool walk_leaves(const DensArgs &A, int root, const NodeBox &gb, doub
     NodeTopo nd{0, 0, -1, 0};
     const NodeBox b = A.nbox[k >= 0 ? k : 0];
     if (k >= 0 && (!gas_only || A.nngas[k] > 0)) {
-      double d2 = axis_gap_box(gb.lox, gb.hix, b.lox, b.hix);
-      d2 = d2 + axis_gap_box(gb.loy, gb.hiy, b.loy, b.hiy);
-      d2 = d2 + axis_gap_box(gb.loz, gb.hiz, b.loz, b.hiz);
+      double d2 = axis_gap_box_p(gb.lox, gb.hix, b.lox, b.hix, A.L);
+      d2 = d2 + axis_gap_box_p(gb.loy, gb.hiy, b.loy, b.hiy, A.L);
+      d2 = d2 + axis_gap_box_p(gb.loz, gb.hiz, b.loz, b.hiz, A.L);
       hit = d2 < R2;
     }
-    hit = balls_reach_box(s_snk, b.lox, b.loy, b.loz, b.hix, b.hiy, b.hiz, 0.0, hit) && hit;
+    hit = balls_reach_box(s_snk, b.lox, b.loy, b.loz, b.hix, b.hiy, b.hiz, 0.0, hit, A.L) && hit;
     if (hit) {
       nd = A.topo[k];
       leaf = nd.nchild == 0;
-      if (whole && !leaf) {
+      if (whole && !leaf && !(A.L > 0.0)) {
         const double fx = fmax(fabs(gb.lox - b.lox), fabs(b.hix - gb.lox));
         const double fy = fmax(fabs(gb.loy - b.loy), fabs(b.hiy - gb.loy));
         const double fz = fmax(fabs(gb.loz - b.loz), fabs(b.hiz - gb.loz));
@@ -155,6 +156,15 @@ struct DensTile {
   int q[kWave];
 };
 
+// Pair geometry with the nearest image in a periodic box of side L (the open
+// forms, exactly, for L = 0): a component of x_i - x_j, and the squared
+// distance in the order of dist2_pair.
+__device__ __forceinline__ double pdx(double L, double pi, double pj) { return wrap_d(pi - pj, L); }
+__device__ __forceinline__ double pd2(double L, double px, double py, double pz, const double4 &a) {
+  return L > 0.0 ? dist2_disp(pdx(L, px, a.x), pdx(L, py, a.y), pdx(L, pz, a.z))
+                 : dist2_pair(px, py, pz, a.x, a.y, a.z);
+}
+
 // Per-lane kernel sums over the nt staged candidates at length h.  The
 // distance tests of all candidates come first (broadcast reads) and leave
 // each lane a mask of its neighbours in the tile; each lane then evaluates
@@ -166,6 +176,7 @@ template <bool kFull>
 __device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, int nt, double px, double py,
                                           double pz, const double4 &vp, double h, bool want_div, bool want_phi,
                                           int32_t *dbg_row, int &ndbg, Sums &s) {
+  const double L = A.L;
   const double ih = 1.0 / h;
   const double ih3 = ih * ih * ih / kPi;
   const double ih4 = ih3 * ih;
@@ -173,13 +184,13 @@ __device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, 
   const double R2 = two_h * two_h;
   uint64_t mask = tile_mask(nt, [&](int j) {
     const double4 a = T.pm[j];
-    return dist2_pair(px, py, pz, a.x, a.y, a.z) < R2;
+    return pd2(L, px, py, pz, a) < R2;
   });
   while (mask) {
     const int j = __builtin_ctzll(mask);
     mask &= mask - 1;
     const double4 a = T.pm[j];
-    const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+    const double r2 = pd2(L, px, py, pz, a);
     if (kFull && dbg_row) {
       if (ndbg < A.dbg_max) dbg_row[ndbg] = A.perm[T.q[j]];
       ndbg++;
@@ -200,7 +211,7 @@ __device__ __forceinline__ void tile_sums(const DensArgs &A, const DensTile &T, 
       if (want_div && r > 0.0) {
         const double4 v = T.vu[j];
         const double g = dw * ih4 * ir;  // dW/dr / r
-        s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
+        s.divv += g * ((vp.x - v.x) * pdx(L, px, a.x) + (vp.y - v.y) * pdx(L, py, a.y) + (vp.z - v.z) * pdx(L, pz, a.z));
       }
     }
   }
@@ -483,10 +494,10 @@ struct CountOut {
 };
 
 __device__ __forceinline__ void tile_count(const DensTile &T, int nt, double px, double py, double pz, double R2,
-                                           CountOut &k) {
+                                           CountOut &k, double L) {
   for (int j = 0; j < nt; j++) {
     const double4 a = T.pm[j];
-    const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);  // non-gas: at infinity
+    const double r2 = pd2(L, px, py, pz, a);  // non-gas: at infinity
     if (r2 < R2) {
       k.c += 1.0;
       if (r2 > k.r2in) {
@@ -518,7 +529,7 @@ __device__ void leaf_count(const DensArgs &A, int nleaf, const int *s_leaf, Dens
         off += tk;
         if (fill == kWave) {
           stage_tile(A, T, kWave, rq, true, false);
-          tile_count(T, kWave, px, py, pz, R2, k);
+          tile_count(T, kWave, px, py, pz, R2, k, A.L);
           __syncthreads();
           fill = 0;
         }
@@ -527,7 +538,7 @@ __device__ void leaf_count(const DensArgs &A, int nleaf, const int *s_leaf, Dens
   }
   if (fill > 0) {
     stage_tile(A, T, fill, rq, true, false);
-    tile_count(T, fill, px, py, pz, R2, k);
+    tile_count(T, fill, px, py, pz, R2, k, A.L);
     __syncthreads();
   }
 }
@@ -680,6 +691,7 @@ __device__ __forceinline__ void solver_update(Solver &v, const DensArgs &A, cons
 __device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T, int nt, uint64_t gas, double px,
                                            double py, double pz, const double4 &vp, bool do_h, double hh, bool do_e,
                                            double he, int32_t *dbg_row, int &ndbg, Sums5 &sh, Sums5 &se) {
+  const double L = A.L;
   const double ihh = 1.0 / hh, ihe = 1.0 / he;
   const double ihh3 = ihh * ihh * ihh / kPi, ihe3 = ihe * ihe * ihe / kPi;
   const double ihh4 = ihh3 * ihh, ihe4 = ihe3 * ihe;
@@ -692,20 +704,20 @@ __device__ __forceinline__ void tile_sums2(const DensArgs &A, const DensTile &T,
   const double R2g = fmax(R2h, R2e);
   uint64_t mask = tile_mask(nt, [&](int j) {
     const double4 a = T.pm[j];
-    const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+    const double r2 = pd2(L, px, py, pz, a);
     return r2 < (((gas >> j) & 1) ? R2g : R2e);
   });
   while (mask) {
     const int j = __builtin_ctzll(mask);
     mask &= mask - 1;
     const double4 a = T.pm[j];
-    const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+    const double r2 = pd2(L, px, py, pz, a);
     const double4 v = T.vu[j];
     const bool in_h = r2 < R2h && v.w != 0.0;
     const bool in_e = r2 < R2e;
     const double ir = r2 > 0.0 ? rsq64(r2) : 0.0;
     const double r = r2 * ir;
-    const double dot = (vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z);
+    const double dot = (vp.x - v.x) * pdx(L, px, a.x) + (vp.y - v.y) * pdx(L, py, a.y) + (vp.z - v.z) * pdx(L, pz, a.z);
     if (in_h) {
       if (dbg_row) {
         if (ndbg < A.dbg_max) dbg_row[ndbg] = A.perm[T.q[j]];
@@ -906,6 +918,8 @@ __device__ __forceinline__ void store_outputs(const DensArgs &A, int p, bool is_
   }
   A.hs[p] = h;
   A.es[p] = eps;
+  // nearest images cover a kernel only while its reach stays below half the box
+  if (A.L > 0.0 && (4.0 * h >= A.L || 4.0 * eps >= A.L)) atomicOr(A.flags, TSPH_FLAG_PERIOD);
   A.sph[p] = make_double4(h, rho, c, pr2);
   const double zo = is_gas ? zeta / omega : 0.0;
   A.zo[p] = zo;
@@ -937,8 +951,10 @@ __device__ __forceinline__ void store_outputs(const DensArgs &A, int p, bool is_
 
 // kFused: gas and softening lengths solved together (independent solves,
 // both species); otherwise one or the other (or one shared) separately.
-template <bool kFused>
+// kPer: the periodic-box form; the open one takes L = 0 as a constant
+template <bool kFused, bool kPer>
 __global__ __launch_bounds__(64, 3) void k_density(DensArgs A) {
+  if constexpr (!kPer) A.L = 0.0;
   __shared__ int s_stack[kDensStackCap];
   __shared__ int s_leaf[kDensLeafCap];
   __shared__ double4 s_snk[kWave];
@@ -1059,9 +1075,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // skip: filtered out) to the sums of the sink at (px, py, pz).
 __device__ __forceinline__ void add_candidate(const double4 &a, const double4 &v, bool skip, double px, double py,
                                               double pz, const double4 &vp, double ih, double ih3, double ih4,
-                                              double R2, bool want_div, bool want_phi, bool lit, Sums &s) {
+                                              double R2, bool want_div, bool want_phi, bool lit, Sums &s,
+                                              double L) {
   if (skip) return;
-  const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+  const double r2 = pd2(L, px, py, pz, a);
   if (!(r2 < R2)) return;
   const double ir = r2 > 0.0 ? rsq64(r2) : 0.0;
   const double r = r2 * ir;
@@ -1077,7 +1094,7 @@ __device__ __forceinline__ void add_candidate(const double4 &a, const double4 &v
   if (want_phi) s.mdphi += (lit ? 1.0 : a.w) * soft_pe_q(qq, ih);
   if (want_div && r > 0.0) {
     const double g = dw * ih4 * ir;
-    s.divv += g * ((vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z));
+    s.divv += g * ((vp.x - v.x) * pdx(L, px, a.x) + (vp.y - v.y) * pdx(L, py, a.y) + (vp.z - v.z) * pdx(L, pz, a.z));
   }
 }
 
@@ -1131,10 +1148,10 @@ __device__ __forceinline__ void sink_leaf_sums(const DensArgs &A, int nleaf, con
             const CandLoad c1 = load_candidate(A, q1, gas_only, want_div);
             const CandLoad c2 = load_candidate(A, q2, gas_only, want_div);
             const CandLoad c3 = load_candidate(A, rq, gas_only, want_div);
-            add_candidate(c0.a, c0.v, c0.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
-            add_candidate(c1.a, c1.v, c1.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
-            add_candidate(c2.a, c2.v, c2.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
-            add_candidate(c3.a, c3.v, c3.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
+            add_candidate(c0.a, c0.v, c0.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s, A.L);
+            add_candidate(c1.a, c1.v, c1.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s, A.L);
+            add_candidate(c2.a, c2.v, c2.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s, A.L);
+            add_candidate(c3.a, c3.v, c3.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s, A.L);
             nr = 0;
           }
         }
@@ -1144,19 +1161,19 @@ __device__ __forceinline__ void sink_leaf_sums(const DensArgs &A, int nleaf, con
   // pending full rounds, in order, then the partial round
   if (nr > 0) {
     const CandLoad c = load_candidate(A, q0, gas_only, want_div);
-    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s, A.L);
   }
   if (nr > 1) {
     const CandLoad c = load_candidate(A, q1, gas_only, want_div);
-    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s, A.L);
   }
   if (nr > 2) {
     const CandLoad c = load_candidate(A, q2, gas_only, want_div);
-    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s, A.L);
   }
   if (ln < fill) {
     const CandLoad c = load_candidate(A, rq, gas_only, want_div);
-    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s);
+    add_candidate(c.a, c.v, c.skip, px, py, pz, vp, ih, ih3, ih4, R2, want_div, want_phi, A.corr_lit != 0, s, A.L);
   }
 }
 
@@ -1230,15 +1247,15 @@ __device__ __forceinline__ SolveOut solve_one(const DensArgs &A, int root, bool 
 // softening length's mass-weighted d phi / d eps kept in the rho slot.
 __device__ __forceinline__ void add_candidate2(const CandLoad &c, double px, double py, double pz, const double4 &vp,
                                                double R2h, double ih, double ih3, double ih4, double R2e, double ie,
-                                               double ie3, double ie4, bool lit, Sums5 &sh, Sums5 &se) {
+                                               double ie3, double ie4, bool lit, Sums5 &sh, Sums5 &se, double L) {
   const double4 &a = c.a, &v = c.v;
-  const double r2 = dist2_pair(px, py, pz, a.x, a.y, a.z);
+  const double r2 = pd2(L, px, py, pz, a);
   const bool in_h = !c.skip && r2 < R2h;
   const bool in_e = r2 < R2e;
   if (!in_h && !in_e) return;
   const double ir = r2 > 0.0 ? rsq64(r2) : 0.0;
   const double r = r2 * ir;
-  const double dot = (vp.x - v.x) * (px - a.x) + (vp.y - v.y) * (py - a.y) + (vp.z - v.z) * (pz - a.z);
+  const double dot = (vp.x - v.x) * pdx(L, px, a.x) + (vp.y - v.y) * pdx(L, py, a.y) + (vp.z - v.z) * pdx(L, pz, a.z);
   if (in_h) {
     const double qq = r * ih;
     double w, dw;
@@ -1296,8 +1313,8 @@ __device__ __forceinline__ void sink_leaf_sums2(const DensArgs &A, int nleaf, co
           } else {
             const CandLoad c0 = load_candidate(A, q0, true, true);
             const CandLoad c1 = load_candidate(A, rq, true, true);
-            add_candidate2(c0, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se);
-            add_candidate2(c1, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se);
+            add_candidate2(c0, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se, A.L);
+            add_candidate2(c1, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se, A.L);
             pending = false;
           }
         }
@@ -1306,11 +1323,11 @@ __device__ __forceinline__ void sink_leaf_sums2(const DensArgs &A, int nleaf, co
   }
   if (pending) {
     const CandLoad c = load_candidate(A, q0, true, true);
-    add_candidate2(c, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se);
+    add_candidate2(c, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se, A.L);
   }
   if (ln < fill) {
     const CandLoad c = load_candidate(A, rq, true, true);
-    add_candidate2(c, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se);
+    add_candidate2(c, px, py, pz, vp, R2h, ih, ih3, ih4, R2e, ie, ie3, ie4, A.corr_lit != 0, sh, se, A.L);
   }
 }
 
@@ -1542,6 +1559,7 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
   A.hstd = c->p.h_scheme == TSPH_H_STANDARD;
   A.nstd = (int32_t)llround(4.0 / 3.0 * 3.14159265358979323846 * pow(2.0 * c->p.eta_h, 3.0));
   A.entropy = c->p.entropy;
+  A.L = c->p.period;
   A.hydro = c->p.hydro && c->n_gas > 0;
   A.gravity = c->p.gravity;
   // one shared length when the two solves are the same equation (pure gas,
@@ -1557,7 +1575,9 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
   A.heavy_cap = (c->dbg_nbr || c->p.split_leaves == 0 || A.hstd) ? 0 : (int32_t)c->heavy_cap;
   A.split_leaves = c->p.split_leaves;
   const bool fused = A.hydro && A.gravity && !A.shared && A.soft_mode != TSPH_SOFT_CONSTANT && !A.hstd;
-  void (*kd)(DensArgs) = fused ? k_density<true> : k_density<false>;
+  const bool per = A.L > 0.0;
+  void (*kd)(DensArgs) = fused ? (per ? k_density<true, true> : k_density<true, false>)
+                               : (per ? k_density<false, true> : k_density<false, false>);
   hipLaunchKernelGGL(kd, dim3(persistent_blocks(c, (const void *)kd)), dim3(64), 0, st, A);
   if (A.heavy_cap > 0) {
     hipLaunchKernelGGL(k_heavy_order, dim3(1), dim3(1024), 0, st, A);

@@ -66,6 +66,8 @@ struct GravArgs {
   SplitItem *split_item;
   double4 *split_part;
   int32_t *split_head;
+  double L;           // periodic box side (0: open)
+  const double *ewt;  // its Ewald correction table
 };
 
 struct Sink {
@@ -78,12 +80,113 @@ struct Sink {
   int ndbg;
 };
 
-// kernel variants: bit 0 quadrupoles, bit 1 correction terms, bit 2 potential
-constexpr int kQuad = 1, kCorr = 2, kPot = 4;
+// kernel variants: bit 0 quadrupoles, bit 1 correction terms, bit 2
+// potential, bit 3 periodic box
+constexpr int kQuad = 1, kCorr = 2, kPot = 4, kPer = 8;
+
+// ---- periodic box (Sect. 4.3): the correction for the replicas of a mass,
+// tabulated for omega = 2/L, |n|, |h| < 5 on [0, L/2]^3 with kEwaldGrid
+// intervals per axis, interpolated trilinearly on |x_k|; the component takes
+// the sign of x_k (odd in its own coordinate, even in the others).
+__device__ __forceinline__ void ewald_corr(const double *__restrict__ T, double L, double x, double y, double z,
+                                           double &ex, double &ey, double &ez) {
+#pragma clang fp contract(off)
+  constexpr int n1 = kEwaldGrid + 1;
+  const double step = 0.5 * L / kEwaldGrid;
+  const double a[3] = {fabs(x), fabs(y), fabs(z)};
+  int i[3];
+  double f[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const double u = a[d] / step;
+    int k = (int)floor(u);
+    k = k > kEwaldGrid - 1 ? kEwaldGrid - 1 : (k < 0 ? 0 : k);
+    i[d] = k;
+    f[d] = u - k;
+  }
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < 8; b++) {
+    const int ox = b >> 2, oy = (b >> 1) & 1, oz = b & 1;
+    const double w = (ox ? f[0] : 1.0 - f[0]) * (oy ? f[1] : 1.0 - f[1]) * (oz ? f[2] : 1.0 - f[2]);
+    const double *t = T + 3 * (((int64_t)(i[0] + ox) * n1 + (i[1] + oy)) * n1 + (i[2] + oz));
+    v0 = v0 + w * t[0];
+    v1 = v1 + w * t[1];
+    v2 = v2 + w * t[2];
+  }
+  ex = x < 0.0 ? -v0 : v0;
+  ey = y < 0.0 ? -v1 : v1;
+  ez = z < 0.0 ? -v2 : v2;
+}
+
+// the replicas of mass m at displacement (x_i - x_j) added to a sink's
+// acceleration (times g: G in the FP64 form, 1 in the FP32 form's units)
+template <class S>
+__device__ __forceinline__ void ewald_add(const GravArgs &A, S &s, double g, double m, double dx, double dy,
+                                          double dz) {
+#pragma clang fp contract(off)
+  double ex, ey, ez;
+  ewald_corr(A.ewt, A.L, dx, dy, dz, ex, ey, ez);
+  const double gm = g * m;
+  s.ax = s.ax + gm * ex;
+  s.ay = s.ay + gm * ey;
+  s.az = s.az + gm * ez;
+}
+
+// one thread per grid point: the Ewald sums (real space over |n| < 5 with
+// erfc and the Gaussian, Fourier space over 0 < |h| < 5) less the direct
+// term, the coordinate planes of each component set to zero by symmetry
+__global__ __launch_bounds__(256) void k_ewald_table(double L, double *__restrict__ T) {
+  constexpr int n1 = kEwaldGrid + 1;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n1 * n1 * n1) return;
+  const int i = a / (n1 * n1), j = (a / n1) % n1, k = a % n1;
+  const double step = 0.5 * L / kEwaldGrid;
+  const double x = i * step, y = j * step, z = k * step;
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  if (a > 0) {
+    const double w = 2.0 / L;
+    const double r2 = x * x + y * y + z * z, r = sqrt(r2);
+    ax = x / (r2 * r);
+    ay = y / (r2 * r);
+    az = z / (r2 * r);
+    for (int nx = -4; nx <= 4; nx++)
+      for (int ny = -4; ny <= 4; ny++)
+        for (int nz = -4; nz <= 4; nz++) {
+          if (nx * nx + ny * ny + nz * nz >= 25) continue;
+          const double dx = x - nx * L, dy = y - ny * L, dz = z - nz * L;
+          const double d2 = dx * dx + dy * dy + dz * dz, d = sqrt(d2);
+          const double g = (erfc(w * d) + 2.0 * w * d * (1.0 / sqrt(M_PI)) * exp(-w * w * d2)) / (d2 * d);
+          ax -= dx * g;
+          ay -= dy * g;
+          az -= dz * g;
+        }
+    for (int hx = -4; hx <= 4; hx++)
+      for (int hy = -4; hy <= 4; hy++)
+        for (int hz = -4; hz <= 4; hz++) {
+          const int h2 = hx * hx + hy * hy + hz * hz;
+          if (h2 == 0 || h2 >= 25) continue;
+          const double c = 2.0 / (L * L) / h2 * exp(-M_PI * M_PI * h2 / (w * w * L * L)) *
+                           sin(2.0 * M_PI / L * (hx * x + hy * y + hz * z));
+          ax -= c * hx;
+          ay -= c * hy;
+          az -= c * hz;
+        }
+  }
+  T[3 * a + 0] = i == 0 ? 0.0 : ax;
+  T[3 * a + 1] = j == 0 ? 0.0 : ay;
+  T[3 * a + 2] = k == 0 ? 0.0 : az;
+}
 
 template <int M>
 __device__ __forceinline__ void far_field(const GravArgs &A, Sink &s, const NodeFar &f) {
-  const double dx = s.x - f.cx, dy = s.y - f.cy, dz = s.z - f.cz;
+  double dx = s.x - f.cx, dy = s.y - f.cy, dz = s.z - f.cz;
+  if (M & kPer) {
+    dx = wrap_d(dx, A.L);
+    dy = wrap_d(dy, A.L);
+    dz = wrap_d(dz, A.L);
+    ewald_add(A, s, A.G, f.m, dx, dy, dz);
+  }
   const double r2 = dx * dx + dy * dy + dz * dz;
   const double ir = rsq64(r2);
   const double ir2 = ir * ir;
@@ -112,7 +215,12 @@ __device__ __forceinline__ void far_field(const GravArgs &A, Sink &s, const Node
 
 template <int M>
 __device__ __forceinline__ void near_pair(const GravArgs &A, Sink &s, const GravRec &b) {
-  const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  if (M & kPer) {
+    dx = wrap_d(dx, A.L);
+    dy = wrap_d(dy, A.L);
+    dz = wrap_d(dz, A.L);
+  }
   const double r2 = dx * dx + dy * dy + dz * dz;
   if (r2 >= fmax(s.s4, b.s4)) {
     const double ir = rsq64(r2);
@@ -157,7 +265,13 @@ __device__ __forceinline__ void near_pair(const GravArgs &A, Sink &s, const Grav
 // cell's centre of mass away from every sink of the batch (r > 0).
 template <int M>
 __device__ __forceinline__ void soft_cell(const GravArgs &A, Sink &s, const GravRec &b) {
-  const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  if (M & kPer) {
+    dx = wrap_d(dx, A.L);
+    dy = wrap_d(dy, A.L);
+    dz = wrap_d(dz, A.L);
+    ewald_add(A, s, A.G, b.m, dx, dy, dz);
+  }
   const double r2 = dx * dx + dy * dy + dz * dz;
   const double ir = rsq64(r2);
   const double r = r2 * ir;
@@ -176,8 +290,11 @@ __device__ __forceinline__ void soft_cell(const GravArgs &A, Sink &s, const Grav
   if (M & kPot) s.pot += A.G * b.m * 0.5 * (soft_ph_q(qi, s.ieps, ir) + soft_ph_q(qj, b.ieps, ir));
 }
 
+template <int M>
 __device__ __forceinline__ void debug_pair(const GravArgs &A, Sink &s, const GravRec &b, int q) {
-  const double r2 = dist2_pair(s.x, s.y, s.z, b.x, b.y, b.z);
+  const double r2 = (M & kPer)
+                        ? dist2_disp(wrap_d(s.x - b.x, A.L), wrap_d(s.y - b.y, A.L), wrap_d(s.z - b.z, A.L))
+                        : dist2_pair(s.x, s.y, s.z, b.x, b.y, b.z);
   const double R = 2.0 * fmax(s.eps, b.eps);
   if (r2 < R * R) {
     if (s.ndbg < A.dbg_max) s.dbg[s.ndbg] = A.perm[q];
@@ -195,7 +312,14 @@ template <int M>
 __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const GravRec *rec, const int *tq, int nt) {
   uint64_t soft = tile_mask(nt, [&](int j) {
     const GravRec b = rec[j];
-    const double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+    double dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+    if (M & kPer) {
+      // every pair: the replicas (none for the sink itself, at x = 0)
+      dx = wrap_d(dx, A.L);
+      dy = wrap_d(dy, A.L);
+      dz = wrap_d(dz, A.L);
+      ewald_add(A, s, A.G, b.m, dx, dy, dz);
+    }
     const double r2 = dx * dx + dy * dy + dz * dz;
     const bool near = r2 < fmax(s.s4, b.s4);
     const double ir = near ? 0.0 : rsq64(r2);
@@ -205,7 +329,7 @@ __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const Grav
     s.ay -= f * dy;
     s.az -= f * dz;
     if (M & kPot) s.pot -= A.G * mr;
-    if (s.dbg && tq[j] != s.p) debug_pair(A, s, b, tq[j]);
+    if (s.dbg && tq[j] != s.p) debug_pair<M>(A, s, b, tq[j]);
     return near;
   });
   while (soft) {
@@ -274,9 +398,19 @@ __device__ __forceinline__ void carry_tile(Sink32 &s) {
   s.tax = s.tay = s.taz = s.tpot = 0.0f;
 }
 
+// nearest image of an FP32 displacement (periodic box of side Lf)
+__device__ __forceinline__ float wrap_f(float d, float Lf) { return d - Lf * rintf(d / Lf); }
+
 template <int M>
-__device__ __forceinline__ void far_field32(Sink32 &s, const NodeF32 &f) {
-  const float dx = s.x - f.cx, dy = s.y - f.cy, dz = s.z - f.cz;
+__device__ __forceinline__ void far_field32(const GravArgs &A, Sink32 &s, const NodeF32 &f) {
+  float dx = s.x - f.cx, dy = s.y - f.cy, dz = s.z - f.cz;
+  if (M & kPer) {
+    const float Lf = (float)A.L;
+    dx = wrap_f(dx, Lf);
+    dy = wrap_f(dy, Lf);
+    dz = wrap_f(dz, Lf);
+    ewald_add(A, s, 1.0, (double)f.m, (double)dx, (double)dy, (double)dz);
+  }
   const float r2 = dx * dx + dy * dy + dz * dz;
   const float ir = rsq32(r2);
   const float ir2 = ir * ir;
@@ -304,8 +438,7 @@ __device__ __forceinline__ void far_field32(Sink32 &s, const NodeF32 &f) {
 }
 
 template <int M>
-__device__ __forceinline__ void newton_pair32(Sink32 &s, const RecF32 &b) {
-  const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+__device__ __forceinline__ void newton_pair32(Sink32 &s, const RecF32 &b, float dx, float dy, float dz) {
   const float r2 = dx * dx + dy * dy + dz * dz;
   const float ir = rsq32(r2);
   const float mr = b.m * ir;
@@ -317,11 +450,17 @@ __device__ __forceinline__ void newton_pair32(Sink32 &s, const RecF32 &b) {
 }
 
 template <int M>
-__device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b, bool lit) {
-  const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+__device__ __forceinline__ void near_pair32(const GravArgs &A, Sink32 &s, const RecF32 &b, bool lit) {
+  float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  if (M & kPer) {
+    const float Lf = (float)A.L;
+    dx = wrap_f(dx, Lf);
+    dy = wrap_f(dy, Lf);
+    dz = wrap_f(dz, Lf);
+  }
   const float r2 = dx * dx + dy * dy + dz * dz;
   if (r2 >= max_nonneg(s.s4, b.s4)) {
-    newton_pair32<M>(s, b);
+    newton_pair32<M>(s, b, dx, dy, dz);
     return;
   }
   if (r2 > 0.0f) {
@@ -350,8 +489,15 @@ __device__ __forceinline__ void near_pair32(Sink32 &s, const RecF32 &b, bool lit
 
 // soft_cell in the FP32 form (RecF32: x, y, z, M, eps, 1/eps, X, N)
 template <int M>
-__device__ __forceinline__ void soft_cell32(Sink32 &s, const RecF32 &b, bool lit) {
-  const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+__device__ __forceinline__ void soft_cell32(const GravArgs &A, Sink32 &s, const RecF32 &b, bool lit) {
+  float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+  if (M & kPer) {
+    const float Lf = (float)A.L;
+    dx = wrap_f(dx, Lf);
+    dy = wrap_f(dy, Lf);
+    dz = wrap_f(dz, Lf);
+    ewald_add(A, s, 1.0, (double)b.m, (double)dx, (double)dy, (double)dz);
+  }
   const float r2 = dx * dx + dy * dy + dz * dz;
   const float ir = rsq32(r2);
   const float r = r2 * ir;
@@ -373,10 +519,19 @@ __device__ __forceinline__ void soft_cell32(Sink32 &s, const RecF32 &b, bool lit
 // As near_tile: Newtonian pass over the tile, then each lane's own
 // softened pairs.
 template <int M>
-__device__ __forceinline__ void near_tile32(Sink32 &s, const RecF32 *rec, const int *tq, int nt, bool lit) {
+__device__ __forceinline__ void near_tile32(const GravArgs &A, Sink32 &s, const RecF32 *rec, const int *tq, int nt,
+                                            bool lit) {
   uint64_t soft = tile_mask(nt, [&](int j) {
     const RecF32 b = rec[j];
-    const float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+    float dx = s.x - b.x, dy = s.y - b.y, dz = s.z - b.z;
+    if (M & kPer) {
+      // every pair: the replicas (none for the sink itself, at x = 0)
+      const float Lf = (float)A.L;
+      dx = wrap_f(dx, Lf);
+      dy = wrap_f(dy, Lf);
+      dz = wrap_f(dz, Lf);
+      ewald_add(A, s, 1.0, (double)b.m, (double)dx, (double)dy, (double)dz);
+    }
     const float r2 = dx * dx + dy * dy + dz * dz;
     const bool near = r2 < max_nonneg(s.s4, b.s4);
     const float ir = near ? 0.0f : rsq32(r2);
@@ -391,7 +546,7 @@ __device__ __forceinline__ void near_tile32(Sink32 &s, const RecF32 *rec, const 
   while (soft) {
     const int j = __builtin_ctzll(soft);
     soft &= soft - 1;
-    if (tq[j] != s.p) near_pair32<M>(s, rec[j], lit);
+    if (tq[j] != s.p) near_pair32<M>(A, s, rec[j], lit);
   }
 }
 
@@ -430,7 +585,7 @@ __device__ __forceinline__ int near_entries(const GravArgs &A, SinkT<F32> &s, co
       const GravRec r = A.grec[rq];
       if constexpr (F32) {
         RecF32 h;
-        h.x = (float)(r.x - cx); h.y = (float)(r.y - cy); h.z = (float)(r.z - cz);
+        h.x = (float)((M & kPer) ? wrap_d(r.x - cx, A.L) : r.x - cx); h.y = (float)((M & kPer) ? wrap_d(r.y - cy, A.L) : r.y - cy); h.z = (float)((M & kPer) ? wrap_d(r.z - cz, A.L) : r.z - cz);
         h.m = (float)r.m; h.eps = (float)r.eps; h.ieps = (float)r.ieps; h.xiu = (float)r.xiu;
         h.s4 = (2.0f * h.eps) * (2.0f * h.eps);
         T.rec32[ln] = h;
@@ -441,7 +596,7 @@ __device__ __forceinline__ int near_entries(const GravArgs &A, SinkT<F32> &s, co
     }
     __syncthreads();
     if constexpr (F32) {
-      near_tile32<M>(s, T.rec32, tq, nt, A.lit != 0);
+      near_tile32<M>(A, s, T.rec32, tq, nt, A.lit != 0);
       carry_tile(s);
     } else {
       near_tile<M>(A, s, T.rec, tq, nt);
@@ -518,18 +673,20 @@ struct GClass {
   int child, nchild;
 };
 
+template <int M>
 __device__ __forceinline__ GClass classify(const GravArgs &A, const NodeBox &gb, double gemax, int k) {
+  const double L = (M & kPer) ? A.L : 0.0;  // periodic box (folded away in the open kernels)
   GClass c{false, false, false, false, -1, 0};
   if (k < 0) return c;
   const NodeFar f = A.nfar[k];
   const NodeBox b = A.nbox[k];
-  double d2 = axis_gap_point(gb.lox, gb.hix, f.cx);
-  d2 = d2 + axis_gap_point(gb.loy, gb.hiy, f.cy);
-  d2 = d2 + axis_gap_point(gb.loz, gb.hiz, f.cz);
+  double d2 = axis_gap_point_p(gb.lox, gb.hix, f.cx, L);
+  d2 = d2 + axis_gap_point_p(gb.loy, gb.hiy, f.cy, L);
+  d2 = d2 + axis_gap_point_p(gb.loz, gb.hiz, f.cz, L);
   if (d2 > f.rmac * f.rmac) {
-    double c2 = axis_gap_box(gb.lox, gb.hix, b.lox, b.hix);
-    c2 = c2 + axis_gap_box(gb.loy, gb.hiy, b.loy, b.hiy);
-    c2 = c2 + axis_gap_box(gb.loz, gb.hiz, b.loz, b.hiz);
+    double c2 = axis_gap_box_p(gb.lox, gb.hix, b.lox, b.hix, L);
+    c2 = c2 + axis_gap_box_p(gb.loy, gb.hiy, b.loy, b.hiy, L);
+    c2 = c2 + axis_gap_box_p(gb.loz, gb.hiz, b.loz, b.hiz, L);
     const double sr = 2.0 * fmax(gemax, b.epsmax);
     c.acc = c2 >= sr * sr;
     // with softened cells, a node that passes the opening test inside the
@@ -541,7 +698,7 @@ __device__ __forceinline__ GClass classify(const GravArgs &A, const NodeBox &gb,
     // a node wholly inside the softening reach of the batch is taken whole:
     // all its particles are near pairs (unless a descendant may become a
     // softened cell)
-    c.leaf = nd.nchild == 0 || (!A.soften && box_within(gb, b, 2.0 * gemax));
+    c.leaf = nd.nchild == 0 || (!A.soften && !(M & kPer) && box_within(gb, b, 2.0 * gemax));
     c.open = !c.leaf;
     c.child = nd.child;
     c.nchild = nd.nchild;
@@ -601,8 +758,8 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
           const int k1 = ln + kWave < take ? s_stack[sp - take + kWave + ln] : -1;
           sp -= take;
           __syncthreads();
-          const GClass c0 = classify(A, gb, gemax, k0);
-          const GClass c1 = classify(A, gb, gemax, k1);
+          const GClass c0 = classify<M>(A, gb, gemax, k0);
+          const GClass c1 = classify<M>(A, gb, gemax, k1);
           uint64_t m = ballot(c0.acc);
           if (c0.acc) s_cell[ncell + mbcnt(m)] = k0;
           ncell += __popcll(m);
@@ -643,7 +800,9 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
               const NodeFar f = A.nfar[s_cell[t0 + ln]];
               if constexpr (F32) {
                 NodeF32 h;
-                h.cx = (float)(f.cx - cx); h.cy = (float)(f.cy - cy); h.cz = (float)(f.cz - cz);
+                h.cx = (float)((M & kPer) ? wrap_d(f.cx - cx, A.L) : f.cx - cx);
+                h.cy = (float)((M & kPer) ? wrap_d(f.cy - cy, A.L) : f.cy - cy);
+                h.cz = (float)((M & kPer) ? wrap_d(f.cz - cz, A.L) : f.cz - cz);
                 h.m = (float)f.m;
                 h.qxx = (float)f.qxx; h.qyy = (float)f.qyy; h.qzz = (float)f.qzz;
                 h.qxy = (float)f.qxy; h.qxz = (float)f.qxz; h.qyz = (float)f.qyz;
@@ -656,7 +815,7 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
             __syncthreads();
             if constexpr (F32) {
 #pragma unroll 2
-              for (int j = 0; j < nt; j++) far_field32<M>(s, s_t.far32[j]);
+              for (int j = 0; j < nt; j++) far_field32<M>(A, s, s_t.far32[j]);
               carry_tile(s);
             } else {
               for (int j = 0; j < nt; j++) far_field<M>(A, s, s_t.far[j]);
@@ -678,7 +837,9 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
               const double cntk = (double)A.topo[k].count;
               if constexpr (F32) {
                 RecF32 h;
-                h.x = (float)(f.cx - cx); h.y = (float)(f.cy - cy); h.z = (float)(f.cz - cz);
+                h.x = (float)((M & kPer) ? wrap_d(f.cx - cx, A.L) : f.cx - cx);
+                h.y = (float)((M & kPer) ? wrap_d(f.cy - cy, A.L) : f.cy - cy);
+                h.z = (float)((M & kPer) ? wrap_d(f.cz - cz, A.L) : f.cz - cz);
                 h.m = (float)f.m; h.eps = (float)e; h.ieps = (float)(1.0 / e); h.xiu = (float)ns.y;
                 h.s4 = (float)cntk;
                 s_t.rec32[ln] = h;
@@ -688,7 +849,7 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
             }
             __syncthreads();
             if constexpr (F32) {
-              for (int j = 0; j < nt; j++) soft_cell32<M>(s, s_t.rec32[j], A.lit != 0);
+              for (int j = 0; j < nt; j++) soft_cell32<M>(A, s, s_t.rec32[j], A.lit != 0);
               carry_tile(s);
             } else {
               for (int j = 0; j < nt; j++) soft_cell<M>(A, s, s_t.rec[j]);
@@ -930,21 +1091,22 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
   A.split_item = c->split_item;
   A.split_part = c->split_part;
   A.split_head = c->split_head;
-  const int mode = (A.quadrupole ? kQuad : 0) | (A.corr ? kCorr : 0) | (A.want_pot ? kPot : 0);
-  void (*const k64[8])(GravArgs) = {k_gravity<0, false>, k_gravity<1, false>, k_gravity<2, false>,
-                                    k_gravity<3, false>, k_gravity<4, false>, k_gravity<5, false>,
-                                    k_gravity<6, false>, k_gravity<7, false>};
-  void (*const k32[8])(GravArgs) = {k_gravity<0, true>, k_gravity<1, true>, k_gravity<2, true>,
-                                    k_gravity<3, true>, k_gravity<4, true>, k_gravity<5, true>,
-                                    k_gravity<6, true>, k_gravity<7, true>};
-  void (*const s64[8])(GravArgs) = {k_gravity_split<0, false>, k_gravity_split<1, false>,
-                                    k_gravity_split<2, false>, k_gravity_split<3, false>,
-                                    k_gravity_split<4, false>, k_gravity_split<5, false>,
-                                    k_gravity_split<6, false>, k_gravity_split<7, false>};
-  void (*const s32[8])(GravArgs) = {k_gravity_split<0, true>, k_gravity_split<1, true>,
-                                    k_gravity_split<2, true>, k_gravity_split<3, true>,
-                                    k_gravity_split<4, true>, k_gravity_split<5, true>,
-                                    k_gravity_split<6, true>, k_gravity_split<7, true>};
+  A.L = c->p.period;
+  A.ewt = c->ewt;
+  if (A.L > 0.0 && c->ew_L != A.L) {
+    snprintf(c->err, sizeof(c->err), "the Ewald table of the periodic box was not built");
+    return TSPH_EINVAL;
+  }
+  const int mode =
+      (A.quadrupole ? kQuad : 0) | (A.corr ? kCorr : 0) | (A.want_pot ? kPot : 0) | (A.L > 0.0 ? kPer : 0);
+#define TSPH_G16(K, F)                                                                                   \
+  {K<0, F>, K<1, F>, K<2, F>, K<3, F>, K<4, F>, K<5, F>, K<6, F>, K<7, F>, K<8, F>, K<9, F>, K<10, F>, \
+   K<11, F>, K<12, F>, K<13, F>, K<14, F>, K<15, F>}
+  void (*const k64[16])(GravArgs) = TSPH_G16(k_gravity, false);
+  void (*const k32[16])(GravArgs) = TSPH_G16(k_gravity, true);
+  void (*const s64[16])(GravArgs) = TSPH_G16(k_gravity_split, false);
+  void (*const s32[16])(GravArgs) = TSPH_G16(k_gravity_split, true);
+#undef TSPH_G16
   const bool f32 = c->p.precision == TSPH_FP32_BULK;
   void (*kern)(GravArgs) = f32 ? k32[mode] : k64[mode];
   void (*skern)(GravArgs) = f32 ? s32[mode] : s64[mode];
@@ -956,5 +1118,18 @@ tsph_status tsph_impl_gravity(Ctx *c, bool want_pot, hipStream_t st) {
     hipLaunchKernelGGL(k_split_reduce, dim3(4096), dim3(64), 0, st, A);
   }
   TSPH_HIP_CHECK(c, hipGetLastError());
+  return TSPH_OK;
+}
+
+// The Ewald correction table of the context's periodic box (built when the
+// box side changes; synchronous).
+tsph_status tsph_impl_ewald(Ctx *c) {
+  const double L = c->p.period;
+  if (!(L > 0.0) || c->ew_L == L) return TSPH_OK;
+  constexpr int n1 = kEwaldGrid + 1;
+  hipLaunchKernelGGL(k_ewald_table, dim3((n1 * n1 * n1 + 255) / 256), dim3(256), 0, 0, L, c->ewt);
+  TSPH_HIP_CHECK(c, hipGetLastError());
+  TSPH_HIP_CHECK(c, hipDeviceSynchronize());
+  c->ew_L = L;
   return TSPH_OK;
 }

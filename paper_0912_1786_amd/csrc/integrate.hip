@@ -141,7 +141,8 @@ __global__ __launch_bounds__(256) void k_kick_drift(Members M, double dt, int ph
                                                     double *vpz, double *up, double *h, double *eps,
                                                     const double *__restrict__ pdiv, int64_t cap_n,
                                                     const double *__restrict__ dt_dev, int xsph, double *alpha,
-                                                    double *alpha_u, double alpha_min, double alpha_u_min) {
+                                                    double *alpha_u, double alpha_min, double alpha_u_min,
+                                                    double period) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= M.n) return;
   const int mem = member_of(M, i);
@@ -171,6 +172,11 @@ __global__ __launch_bounds__(256) void k_kick_drift(Members M, double dt, int ph
       x[i] += dt * v0;
       y[i] += dt * v1;
       z[i] += dt * v2;
+    }
+    if (period > 0.0) {  // back into the periodic box
+      x[i] = in_box(x[i], period);
+      y[i] = in_box(y[i], period);
+      z[i] = in_box(z[i], period);
     }
     // lengths along the drift: h n^(1/3) = eta with dn/dt = -n div v gives
     // dh/dt = (h/3) div v (Sect. 2.1); the next solve starts from them
@@ -371,7 +377,7 @@ tsph_status tsph_impl_kick_drift(Ctx *c, tsph_state *s, double dt, const double 
                      members_of(c, s->n, s->n_gas), dt, phase, s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->ax, s->ay, s->az, s->dudt, s->vpx,
                      s->vpy, s->vpz, s->up, s->h, s->eps, c->pdiv_n == s->n ? c->pdiv : nullptr, c->cap_n,
                      dt_dev, c->p.xsph_eta > 0.0 ? 1 : 0, c->p.alpha_switch ? s->alpha : nullptr,
-                     c->p.conduction ? s->alpha_u : nullptr, c->p.alpha_min, c->p.alpha_u_min);
+                     c->p.conduction ? s->alpha_u : nullptr, c->p.alpha_min, c->p.alpha_u_min, c->p.period);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

@@ -101,6 +101,7 @@ struct SphArgs {
   const uint8_t *act;
   const int32_t *bcur_s;
   int32_t *bm, *bw;
+  double L;  // periodic box side (0: open)
 };
 
 // The sink side of the pairs of one lane: particle p (a gas sink when
@@ -153,7 +154,9 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
   const double hi = L.hd.x;
   uint64_t mask = tile_mask(nt, [&](int j) {
     const double4 b = T.pos[j];
-    const double r2x = dist2_pair(L.a.x, L.a.y, L.a.z, b.x, b.y, b.z);
+    const double r2x = A.L > 0.0 ? dist2_disp(wrap_d(L.a.x - b.x, A.L), wrap_d(L.a.y - b.y, A.L),
+                                              wrap_d(L.a.z - b.z, A.L))
+                                 : dist2_pair(L.a.x, L.a.y, L.a.z, b.x, b.y, b.z);
     const double R = 2.0 * fmax(hi, b.w);
     return L.sink && r2x < R * R;
   });
@@ -176,8 +179,13 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
       L.ndbg++;
     }
     L.npair++;
-    const double dx = L.a.x - b.x, dy = L.a.y - b.y, dz = L.a.z - b.z;
-    const double r2 = dist2_pair(L.a.x, L.a.y, L.a.z, b.x, b.y, b.z);
+    double dx = L.a.x - b.x, dy = L.a.y - b.y, dz = L.a.z - b.z;
+    if (A.L > 0.0) {  // the nearest image
+      dx = wrap_d(dx, A.L);
+      dy = wrap_d(dy, A.L);
+      dz = wrap_d(dz, A.L);
+    }
+    const double r2 = dist2_disp(dx, dy, dz);
     if (!(r2 > 0.0)) continue;
     const double ir = rsq64(r2);
     const double r = r2 * ir;
@@ -343,8 +351,11 @@ __device__ __forceinline__ void gas_sinks(const SphArgs &A, const Batch &bt, int
   __syncthreads();
 }
 
-template <int kMode, bool kFull>
+// kPer: the periodic-box form; the open one takes L = 0 as a constant, so
+// that no nearest-image code is left in it
+template <int kMode, bool kFull, bool kPer>
 __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
+  if constexpr (!kPer) A.L = 0.0;
   __shared__ int s_stack[kSStackCap];
   __shared__ int s_leaf[kSListCap];
   __shared__ double4 s_snk[kWave];
@@ -398,14 +409,14 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
           NodeTopo nd{0, 0, -1, 0};
           NodeBox b = A.nbox[k >= 0 ? k : 0];
           if (k >= 0 && A.nngas[k] > 0) {
-            double d2 = axis_gap_box(gb.lox, gb.hix, b.lox, b.hix);
-            d2 = d2 + axis_gap_box(gb.loy, gb.hiy, b.loy, b.hiy);
-            d2 = d2 + axis_gap_box(gb.loz, gb.hiz, b.loz, b.hiz);
+            double d2 = axis_gap_box_p(gb.lox, gb.hix, b.lox, b.hix, A.L);
+            d2 = d2 + axis_gap_box_p(gb.loy, gb.hiy, b.loy, b.hiy, A.L);
+            d2 = d2 + axis_gap_box_p(gb.loz, gb.hiz, b.loz, b.hiz, A.L);
             const double R = 2.0 * fmax(ghmax, b.hmax);
             hit = d2 < R * R;
           }
           // keep the node only if some gas sink reaches it: |x_i - box| < 2 max(h_i, h_node)
-          hit = balls_reach_box(s_snk, b.lox, b.loy, b.loz, b.hix, b.hiy, b.hiz, 2.0 * b.hmax, hit) && hit;
+          hit = balls_reach_box(s_snk, b.lox, b.loy, b.loz, b.hix, b.hiy, b.hiz, 2.0 * b.hmax, hit, A.L) && hit;
           if (hit) {
             nd = A.topo[k];
             leaf = nd.nchild == 0;
@@ -497,8 +508,9 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
 
 // The handed-off flushes: each item's ranges on the sinks of its batch
 // chunk; per-lane partial sums to split_part (kSphPart records per lane).
-template <bool kFull>
+template <bool kFull, bool kPer>
 __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
+  if constexpr (!kPer) A.L = 0.0;
   __shared__ int2 s_rng[kSplitItemRanges];
   __shared__ SphTile s_t;
   __shared__ int s_i;
@@ -606,6 +618,28 @@ __global__ void k_reset_counter(int32_t *ctr, int k) {
 
 using namespace tsph;
 
+// the periodic or the open form of a walk kernel
+template <int kMode, bool kFull>
+static void launch_sph(Ctx *c, const SphArgs &A, hipStream_t st) {
+  if (A.L > 0.0) {
+    const void *k = (const void *)k_sph<kMode, kFull, true>;
+    hipLaunchKernelGGL((k_sph<kMode, kFull, true>), dim3(persistent_blocks(c, k)), dim3(64), 0, st, A);
+  } else {
+    const void *k = (const void *)k_sph<kMode, kFull, false>;
+    hipLaunchKernelGGL((k_sph<kMode, kFull, false>), dim3(persistent_blocks(c, k)), dim3(64), 0, st, A);
+  }
+}
+template <bool kFull>
+static void launch_sph_split(Ctx *c, const SphArgs &A, hipStream_t st) {
+  if (A.L > 0.0) {
+    const void *k = (const void *)k_sph_split<kFull, true>;
+    hipLaunchKernelGGL((k_sph_split<kFull, true>), dim3(persistent_blocks(c, k)), dim3(64), 0, st, A);
+  } else {
+    const void *k = (const void *)k_sph_split<kFull, false>;
+    hipLaunchKernelGGL((k_sph_split<kFull, false>), dim3(persistent_blocks(c, k)), dim3(64), 0, st, A);
+  }
+}
+
 static SphArgs sph_args(Ctx *c) {
   SphArgs A;
   A.cap_n = c->cap_n;
@@ -656,6 +690,7 @@ static SphArgs sph_args(Ctx *c) {
   A.bcur_s = c->bcur_s;
   A.bm = c->bm;
   A.bw = c->bw;
+  A.L = c->p.period;
   return A;
 }
 
@@ -682,23 +717,20 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
                        c->alpha_state, c->alpha_u_state, c->av);
     SphArgs Ac = A;
     Ac.split_particles = 0;
-    hipLaunchKernelGGL((k_sph<1, true>), dim3(persistent_blocks(c, (const void *)k_sph<1, true>)), dim3(64), 0, st,
-                       Ac);
+    launch_sph<1, true>(c, Ac, st);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, A.work + 24, 8);
   }
   // the plain form without the switches, the conductivity and X-SPH
   const bool full = A.f2 || A.xsph_eta > 0.0;
-  const void *ks = full ? (const void *)k_sph<0, true> : (const void *)k_sph<0, false>;
-  const void *kx = full ? (const void *)k_sph_split<true> : (const void *)k_sph_split<false>;
   if (full)
-    hipLaunchKernelGGL((k_sph<0, true>), dim3(persistent_blocks(c, ks)), dim3(64), 0, st, A);
+    launch_sph<0, true>(c, A, st);
   else
-    hipLaunchKernelGGL((k_sph<0, false>), dim3(persistent_blocks(c, ks)), dim3(64), 0, st, A);
+    launch_sph<0, false>(c, A, st);
   if (A.split_particles > 0) {
     if (full)
-      hipLaunchKernelGGL(k_sph_split<true>, dim3(persistent_blocks(c, kx)), dim3(64), 0, st, A);
+      launch_sph_split<true>(c, A, st);
     else
-      hipLaunchKernelGGL(k_sph_split<false>, dim3(persistent_blocks(c, kx)), dim3(64), 0, st, A);
+      launch_sph_split<false>(c, A, st);
     hipLaunchKernelGGL(k_sph_reduce, dim3(4096), dim3(64), 0, st, A);
   }
   TSPH_HIP_CHECK(c, hipGetLastError());
@@ -714,8 +746,7 @@ tsph_status tsph_impl_wake(Ctx *c, hipStream_t st) {
   A.dbg = nullptr;
   A.split_particles = 0;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, A.work + 24, 8);
-  hipLaunchKernelGGL((k_sph<2, false>), dim3(persistent_blocks(c, (const void *)k_sph<2, false>)), dim3(64), 0,
-                     st, A);
+  launch_sph<2, false>(c, A, st);
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
 }

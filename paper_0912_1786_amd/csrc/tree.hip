@@ -57,14 +57,14 @@ __global__ __launch_bounds__(256) void k_bbox_partial(Members M, const double *_
                                                       const double *__restrict__ z,
                                                       const double *__restrict__ m,
                                                       double *__restrict__ part,
-                                                      uint32_t *__restrict__ flags) {
+                                                      uint32_t *__restrict__ flags, double L) {
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
   const int mem = blockIdx.y;
   const int64_t i0 = member_begin(M, mem), i1 = member_end(M, mem);
   for (int64_t i = i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < i1;
        i += (int64_t)gridDim.x * blockDim.x) {
-    double p[3] = {x[i], y[i], z[i]};
+    double p[3] = {in_box(x[i], L), in_box(y[i], L), in_box(z[i], L)};
     double mi = m[i];
     bad |= !(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(mi) && mi > 0.0);
 #pragma unroll
@@ -166,13 +166,13 @@ __global__ __launch_bounds__(256) void k_keys(Members M, const double *__restric
                                               const double *__restrict__ y,
                                               const double *__restrict__ z,
                                               const DevRoot *__restrict__ roots,
-                                              uint64_t *__restrict__ key, int32_t *__restrict__ idx) {
+                                              uint64_t *__restrict__ key, int32_t *__restrict__ idx, double L) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= M.n) return;
   const DevRoot *root = roots + member_of(M, i);
   double sc = root->scale;
-  uint64_t cx = cell_of(x[i], root->x0, sc), cy = cell_of(y[i], root->y0, sc),
-           cz = cell_of(z[i], root->z0, sc);
+  uint64_t cx = cell_of(in_box(x[i], L), root->x0, sc), cy = cell_of(in_box(y[i], L), root->y0, sc),
+           cz = cell_of(in_box(z[i], L), root->z0, sc);
   key[i] = (dilate3(cx) << 2) | (dilate3(cy) << 1) | dilate3(cz);
   idx[i] = (int32_t)i;
 }
@@ -394,12 +394,12 @@ __global__ __launch_bounds__(256) void k_gather(Members M, const int32_t *__rest
                                                 const double *__restrict__ h, const double *__restrict__ eps,
                                                 double4 *__restrict__ pm, double4 *__restrict__ vu,
                                                 double *__restrict__ hs, double *__restrict__ es,
-                                                uint8_t *__restrict__ gas) {
+                                                uint8_t *__restrict__ gas, double L) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= M.n) return;
   int i = perm[p];
   bool g = member_gas(M, member_of(M, i), i);
-  pm[p] = make_double4(x[i], y[i], z[i], m[i]);
+  pm[p] = make_double4(in_box(x[i], L), in_box(y[i], L), in_box(z[i], L), m[i]);
   if (vpx) vu[p] = make_double4(vpx[i], vpy[i], vpz[i], (g && up) ? up[i] : 0.0);
   hs[p] = (g && h) ? h[i] : 0.0;
   es[p] = eps ? eps[i] : 0.0;
@@ -744,11 +744,12 @@ tsph_status tsph_impl_build_tree(Ctx *c, const tsph_state *s, hipStream_t st) {
   const Members M = members_of(c, n, s->n_gas);
   // root cube of each member
   const int bbm = M.count > 1 ? kMemberBlocks : kBBoxBlocks;
+  const double Lp = c->p.period;  // periodic box: positions modulo the side
   hipLaunchKernelGGL(k_bbox_partial, dim3(bbm, M.count), dim3(T), 0, st, M, s->x, s->y, s->z, s->m, c->bbox_part,
-                     c->flags);
+                     c->flags, Lp);
   hipLaunchKernelGGL(k_bbox_final, dim3(M.count), dim3(256), 0, st, bbm, c->bbox_part, c->root);
   // keys
-  hipLaunchKernelGGL(k_keys, dim3(gb), dim3(T), 0, st, M, s->x, s->y, s->z, c->root, c->key[0], c->idx[0]);
+  hipLaunchKernelGGL(k_keys, dim3(gb), dim3(T), 0, st, M, s->x, s->y, s->z, c->root, c->key[0], c->idx[0], Lp);
   // sort: 8 passes of 8 bits, ping-pong, result back in buffer 0
   const int nb = M.count > 1 ? c->sort_tiles : (int)((n + kSortTile - 1) / kSortTile);
   for (int pass = 0; pass < 8; pass++) {
@@ -762,7 +763,7 @@ tsph_status tsph_impl_build_tree(Ctx *c, const tsph_state *s, hipStream_t st) {
   c->perm = c->idx[0];
   // gather
   hipLaunchKernelGGL(k_gather, dim3(gb), dim3(T), 0, st, M, c->perm, s->x, s->y, s->z, s->m, s->vpx, s->vpy,
-                     s->vpz, s->up, s->h, s->eps, c->pm, c->vu, c->hs, c->es, c->gas);
+                     s->vpz, s->up, s->h, s->eps, c->pm, c->vu, c->hs, c->es, c->gas, Lp);
   // topology
   hipLaunchKernelGGL(k_topo_init, dim3(1), dim3(256), 0, st, M, c->topo, c->nlevel, c->nparent, c->lvl);
   int64_t maxlev = (c->cap_nodes + 7) / 8;

@@ -125,6 +125,10 @@ inline int64_t heavy_batch_cap(int64_t cap_nodes) { return cap_nodes < 4096 ? 40
 // alpha and alpha_u, the largest |mu_ij| (for the Courant criterion)
 constexpr int kCarryRows = 8;
 
+// intervals per axis of the Ewald correction table over [0, L/2]
+constexpr int kEwaldGrid = 32;
+constexpr int64_t kEwaldValues = 3 * (int64_t)(kEwaldGrid + 1) * (kEwaldGrid + 1) * (kEwaldGrid + 1);
+
 enum SolveField { kNh = 0, kOmega, kZeta, kDivv, kNeps, kUps, kXi, kMaxmu, kDivvE, kVsig, kDuv, kXsx, kXsy, kXsz,
                   kCurlx, kCurly, kCurlz, kFbal, kLapu, kNumSolve };
 
@@ -219,6 +223,10 @@ struct Ctx {
                           // step of its active neighbours (caller order; INT32_MAX: none)
   int32_t *bnext;         // [0] next system time, [1] active count, [2] woken count
   int32_t blk_on;         // the force pass evaluates the active sinks only
+
+  // ---- periodic box ----
+  double *ewt;            // Ewald correction table, 3 x (kEwaldGrid + 1)^3
+  double ew_L;            // box side the table was built for (0: none)
 
   // ---- phase timing (ring of event sets) ----
   int32_t timing;
@@ -448,6 +456,46 @@ __device__ __forceinline__ double axis_gap_box(double lo1, double hi1, double lo
   return d * d;
 }
 
+// squared length of a displacement, in the order of dist2_pair
+__device__ __forceinline__ double dist2_disp(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  double s = dx * dx;
+  s = s + dy * dy;
+  s = s + dz * dz;
+  return s;
+}
+
+// ---- periodic box (Sect. 4.3): nearest images, side L (0: open) ----
+// nearest-image component of a displacement
+__device__ __forceinline__ double wrap_d(double d, double L) {
+#pragma clang fp contract(off)
+  return L > 0.0 ? d - L * rint(d / L) : d;
+}
+// squared gaps on a circle of circumference L: the nearest-image distance of
+// the centres less the half-widths (the open forms when L = 0)
+__device__ __forceinline__ double axis_gap_point_p(double lo, double hi, double p, double L) {
+#pragma clang fp contract(off)
+  if (!(L > 0.0)) return axis_gap_point(lo, hi, p);
+  const double c = 0.5 * (lo + hi), w = 0.5 * (hi - lo);
+  const double t = fabs(wrap_d(p - c, L));
+  const double d = t > w ? t - w : 0.0;
+  return d * d;
+}
+__device__ __forceinline__ double axis_gap_box_p(double lo1, double hi1, double lo2, double hi2, double L) {
+#pragma clang fp contract(off)
+  if (!(L > 0.0)) return axis_gap_box(lo1, hi1, lo2, hi2);
+  const double c1 = 0.5 * (lo1 + hi1), w1 = 0.5 * (hi1 - lo1);
+  const double c2 = 0.5 * (lo2 + hi2), w2 = 0.5 * (hi2 - lo2);
+  double d = fabs(wrap_d(c2 - c1, L)) - w1 - w2;
+  if (!(d > 0.0)) d = 0.0;
+  return d * d;
+}
+// a coordinate taken into the periodic box [0, L)
+__device__ __forceinline__ double in_box(double x, double L) {
+#pragma clang fp contract(off)
+  return L > 0.0 ? x - L * floor(x / L) : x;
+}
+
 __device__ __forceinline__ double dist2_pair(double xi, double yi, double zi, double xj, double yj,
                                              double zj) {
 #pragma clang fp contract(off)
@@ -464,15 +512,16 @@ __device__ __forceinline__ double dist2_pair(double xi, double yi, double zi, do
 // staged sinks (broadcast reads); the loop stops once every lane that still
 // needs an answer has one.
 __device__ __forceinline__ bool balls_reach_box(const double4 *snk, double lox, double loy, double loz,
-                                                double hix, double hiy, double hiz, double r_node, bool want) {
+                                                double hix, double hiy, double hiz, double r_node, bool want,
+                                                double L = 0.0) {
   bool hit = false;
   for (int s = 0; s < kWave; s++) {
     const double4 q = snk[s];
     if (q.w > 0.0) {
       const double R = fmax(q.w, r_node);
-      double d2 = axis_gap_point(lox, hix, q.x);
-      d2 = d2 + axis_gap_point(loy, hiy, q.y);
-      d2 = d2 + axis_gap_point(loz, hiz, q.z);
+      double d2 = axis_gap_point_p(lox, hix, q.x, L);
+      d2 = d2 + axis_gap_point_p(loy, hiy, q.y, L);
+      d2 = d2 + axis_gap_point_p(loz, hiz, q.z, L);
       hit = hit || (d2 < R * R);
     }
     if ((s & 7) == 7 && !__any(want && !hit)) break;
@@ -574,6 +623,8 @@ tsph_status tsph_impl_timestep(tsph::Ctx *c, const tsph_state *s, double *dt_dev
 tsph_status tsph_impl_criteria(tsph::Ctx *c, const tsph_state *s, hipStream_t st);
 // neighbour minima of the step lengths for the wake-up (sph.hip)
 tsph_status tsph_impl_wake(tsph::Ctx *c, hipStream_t st);
+// the Ewald table of the context's periodic box (gravity.hip)
+tsph_status tsph_impl_ewald(tsph::Ctx *c);
 // active flags into key order for a force pass over the active sinks (blocks.hip)
 tsph_status tsph_impl_gather_active(tsph::Ctx *c, hipStream_t st);
 tsph_status tsph_impl_diagnostics(tsph::Ctx *c, const tsph_state *s, double *out, hipStream_t st);

@@ -24,6 +24,7 @@ HW_NUMBER, HW_MASS = 0, 1
 FLAG_NODE_CAPACITY, FLAG_STACK_OVERFLOW, FLAG_LIST_OVERFLOW, FLAG_NOCONV, FLAG_NONFINITE, FLAG_INTERNAL = (
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20)
 FLAG_HANDOFF_CAPACITY = 0x40
+FLAG_PERIOD = 0x80
 DBG_KEYS, DBG_PERM, DBG_NODES, DBG_NNODES, DBG_MOMENTS, DBG_GROUPS, DBG_NGROUPS, DBG_COUNTS, DBG_NBR, DBG_ROOT, \
     DBG_SOLVE, DBG_BATCHES, DBG_NBATCHES = range(13)
 SOLVE_FIELDS = ("nh", "omega", "zeta", "divv", "neps", "ups", "xi", "maxmu", "divv_eps", "vsig", "duv", "xsph_sx",
@@ -47,7 +48,7 @@ class Params(C.Structure):
                 ("visc_form", C.c_int32), ("entropy", C.c_int32), ("xsph_eta", C.c_double),
                 ("h_scheme", C.c_int32), ("h_weight", C.c_int32), ("balsara", C.c_int32),
                 ("alpha_switch", C.c_int32), ("conduction", C.c_int32), ("alpha_min", C.c_double),
-                ("alpha_u_min", C.c_double)]
+                ("alpha_u_min", C.c_double), ("period", C.c_double)]
 
 
 _P = C.c_void_p

@@ -20,7 +20,8 @@ def oracle_params(orc, gp, walk_mode=None):
                       batch_mode=0, grav_corr_literal=gp.grav_corr_literal, soften_cells=gp.soften_cells,
                       visc_form=gp.visc_form, entropy=gp.entropy, xsph_eta=gp.xsph_eta, h_scheme=gp.h_scheme,
                       h_weight=gp.h_weight, balsara=gp.balsara, alpha_switch=gp.alpha_switch,
-                      alpha_min=gp.alpha_min, conduction=gp.conduction, alpha_u_min=gp.alpha_u_min)
+                      alpha_min=gp.alpha_min, conduction=gp.conduction, alpha_u_min=gp.alpha_u_min,
+                      period=gp.period)
 
 
 def run_gpu(ic, gp, lists=0, eps_const=None):

@@ -54,9 +54,9 @@ def test_param_struct_layout_matches_header(T):
     # field order and padding of tsph_params / tsph_state as declared
     # ... max_members, grav_corr_literal, soften_cells, visc_form, entropy
     # (int32), xsph_eta (double), h_scheme, h_weight, balsara, alpha_switch,
-    # conduction (int32), alpha_min, alpha_u_min (double)
-    assert C.sizeof(T.Params) == 8 * 2 + 4 * 2 + 8 * 6 + 4 * 2 + 8 * 2 + 4 * 6 + 8 + 4 * 5 + 4 + 8 + 4 * 5 + 4 + 8 * 2
-    assert T.Params.alpha_u_min.offset == C.sizeof(T.Params) - 8
+    # conduction (int32), alpha_min, alpha_u_min, period (double)
+    assert C.sizeof(T.Params) == 8 * 2 + 4 * 2 + 8 * 6 + 4 * 2 + 8 * 2 + 4 * 6 + 8 + 4 * 5 + 4 + 8 + 4 * 5 + 4 + 8 * 3
+    assert T.Params.period.offset == C.sizeof(T.Params) - 8
     assert T.Params.xsph_eta.offset % 8 == 0 and T.Params.alpha_min.offset % 8 == 0
     assert C.sizeof(T.State) == 8 * 2 + 8 * 22
 

@@ -1,0 +1,168 @@
+"""GPU parity of the periodic box (Sect. 4.3) against the oracle: nearest
+images in every pair, node and opening test, the Ewald correction of the
+replicas (tabulated on the device), nearest-image SPH, wrapping drifts.
+
+* forces, heating, lengths and densities of a mixed-species cloud that fills
+  the box, in both arithmetic forms, with the interaction counts equal to the
+  oracle's (the same sets);
+* a perfect lattice: no force, uniform density, also shifted across the
+  faces;
+* neighbour lists across the faces equal the oracle's;
+* a leapfrog step that carries particles across the faces;
+* a box too small for the kernels raises its flag.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0912_1786_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # collected on CPU-only machines but never run there
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_0912_1786_amd import tsph  # noqa: E402
+
+from gpu_common import acc, gpu_params, maxrel, oracle_params, relrms, run_gpu  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    return oracle
+
+
+def _box_cloud(n=3000, L=1.0, seed=41):
+    ic = inputs.random_cloud(n, seed=seed, masses=(1.0, 4.0), n_gas=n // 2, v_sigma=0.2)
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, L, (n, 3))
+    # a clump straddling a corner of the box
+    k = n // 5
+    pos[:k] = np.mod(0.06 * rng.standard_normal((k, 3)), L)
+    ic["x"], ic["y"], ic["z"] = pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy()
+    return ic
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32_bulk"])
+def test_periodic_forces_match_oracle(O, form):
+    _say(f"[periodic] cloud {form}")
+    L = 1.0
+    ic = _box_cloud(L=L)
+    prec = tsph.FP64 if form == "fp64" else tsph.FP32_BULK
+    gp = gpu_params(nnei=40, h_tol=1e-12, leaf_size=8, period=L, precision=prec)
+    sim, g = run_gpu(ic, gp)
+    sim.close()
+    o = O.compute_forces(ic, oracle_params(O, gp))
+    assert g["flags"] == 0 and g["noconv"] == 0, hex(g["flags"])
+    gas = np.arange(ic["n"]) < ic["n_gas"]
+    assert maxrel(g["h"], o["h"], gas) < 1e-9
+    assert maxrel(g["rho"], o["rho"], gas) < 1e-8
+    assert maxrel(g["eps"], o["eps"]) < 1e-9
+    e = relrms(acc(g), acc(o))
+    ed = relrms(g["dudt"], o["dudt"])
+    _say(f"    acc relRMS {e:.3e}, du/dt relRMS {ed:.3e}")
+    assert e < (1e-11 if form == "fp64" else 2e-6)
+    assert ed < 1e-9
+    assert np.array_equal(g["cnt_node"], o["cnt_node"])
+    assert np.array_equal(g["cnt_pair"], o["cnt_pair"])
+    assert np.array_equal(g["cnt_sph"], o["cnt_sph"])
+    # the replicas matter: the open box differs by far more
+    oo = O.compute_forces(ic, oracle_params(O, gpu_params(nnei=40, h_tol=1e-12, leaf_size=8)))
+    assert relrms(acc(oo), acc(o)) > 1e3 * max(e, 1e-12)
+
+
+def test_periodic_lattice(O):
+    _say("[periodic] lattice")
+    # an odd count: no pair lies exactly half a box apart, where the nearest
+    # image is ambiguous and the interpolated correction would not cancel
+    L, ns = 1.0, 11
+    ic = inputs.cubic_lattice(ns, spacing=L / ns, mass=1.0 / ns ** 3)
+    for k, d in zip(("x", "y", "z"), (0.37, 0.81, 0.13)):
+        ic[k] = np.mod(ic[k] + d, L)  # across the faces
+    gp = gpu_params(nnei=40, h_tol=1e-12, leaf_size=8, period=L, theta=0.0)
+    sim, g = run_gpu(ic, gp)
+    sim.close()
+    assert g["flags"] == 0, hex(g["flags"])
+    scale = ic["m"][0] / (L / ns) ** 2
+    assert np.abs(acc(g)).max() < 1e-9 * scale
+    assert np.allclose(g["rho"], g["rho"][0], rtol=1e-12)
+    assert np.allclose(g["h"], g["h"][0], rtol=1e-12)
+
+
+def test_periodic_neighbour_lists(O):
+    _say("[periodic] lists")
+    L = 1.0
+    ic = _box_cloud(n=2000, L=L, seed=42)
+    gp = gpu_params(nnei=40, h_tol=1e-12, leaf_size=8, period=L)
+    o = O.compute_forces(ic, oracle_params(O, gp))
+    x, y, z = ic["x"], ic["y"], ic["z"]
+    n, n_gas = ic["n"], ic["n_gas"]
+    ref = {kind: O.neighbours(kind, x, y, z, length, n_gas, period=L)
+           for kind, length in ((0, o["h"]), (1, o["h"]), (2, o["eps"]))}
+    longest = int(max(np.diff(off).max() for off, _ in ref.values())) + 8
+    sim, g = run_gpu(ic, gp, lists=longest)
+    sim.close()
+    assert g["flags"] == 0, hex(g["flags"])
+    for kind in (0, 1, 2):
+        off, idx = ref[kind]
+        gl = g["lists"][kind]
+        for i in range(n):
+            got = np.sort(gl[i][gl[i] >= 0])
+            assert np.array_equal(got, idx[off[i]:off[i + 1]]), (kind, i)
+
+
+def test_periodic_step_wraps(O):
+    _say("[periodic] kdk step across the faces")
+    L = 1.0
+    ic = _box_cloud(n=1500, L=L, seed=43)
+    ic["vx"] = ic["vx"] + 3.0  # a bulk flow carries particles across the faces
+    gp = gpu_params(nnei=40, h_tol=1e-12, leaf_size=8, period=L)
+    op = oracle_params(O, gp)
+    sim = tsph.Simulation(ic, gp)
+    try:
+        sim.compute_forces()
+        o0 = O.compute_forces(ic, op)
+        dt = 0.02
+        st = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ic.items()}
+        pred = {c: st[c].copy() for c in ("vx", "vy", "vz", "u")}
+        lengths = {"h": o0["h"].copy(), "eps": o0["eps"].copy(), "divv": o0["divv"], "divv_eps": o0["divv_eps"]}
+        O.kick_drift(st, dt, 0, (o0["ax"], o0["ay"], o0["az"]), o0["dudt"], pred, lengths, period=L)
+        sim.kick_drift(dt, tsph.KD_FIRST)
+        crossed = int(np.sum(st["x"] < ic["x"]))
+        assert crossed > 10
+        for k in ("x", "y", "z"):
+            a = sim.host(k)
+            assert np.all((a >= 0.0) & (a < L))
+            assert np.max(np.abs(a - st[k])) < 1e-12, k
+        o1 = O.compute_forces(st, op, h_in=lengths["h"], eps_in=lengths["eps"],
+                              vel=(pred["vx"], pred["vy"], pred["vz"]), u=pred["u"])
+        sim.compute_forces()
+        flags, noconv = sim.flags()
+        assert flags == 0 and noconv == 0
+        assert relrms(np.stack([sim.host("ax"), sim.host("ay"), sim.host("az")], 1), acc(o1)) < 1e-10
+    finally:
+        sim.close()
+
+
+def test_small_box_is_flagged():
+    _say("[periodic] box too small")
+    ic = inputs.random_cloud(100, seed=44, masses=(1.0, 1.0), n_gas=100, v_sigma=0.0)
+    L = 0.2  # 60 of 100 particles inside 2h: the kernel reaches beyond half the box
+    for k in ("x", "y", "z"):
+        ic[k] = np.mod(ic[k], L)
+    gp = gpu_params(nnei=60, period=L)
+    sim = tsph.Simulation(ic, gp)
+    try:
+        sim.compute_forces()
+        flags, _ = sim.flags()
+        assert flags & tsph.FLAG_PERIOD
+    finally:
+        sim.close()
