@@ -95,6 +95,7 @@ size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->add(4 * N);        // 16 gflag
   L->add(sizeof(GravRec) * N);  // grec
   L->add(sizeof(SphRec) * N);   // srec
+  L->add(sizeof(SphRec32) * N); // srec32
   L->add(32 * N);               // srec2: alpha, alpha_u, Balsara factor, u of the gas
   L->add(16 * N);               // av: alpha, alpha_u in key order
   L->add(8 * kCarryRows * N);   // pdiv: the carry to the next drift
@@ -326,6 +327,7 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->gflag = AT(int32_t *);
   c->grec = AT(GravRec *);
   c->srec = AT(SphRec *);
+  c->srec32 = AT(SphRec32 *);
   c->srec2 = AT(double4 *);
   c->av = AT(double2 *);
   c->pdiv = AT(double *);

@@ -52,6 +52,7 @@ struct DensArgs {
   double2 *soft;
   GravRec *grec;
   SphRec *srec;
+  SphRec32 *srec32;  // the FP32-bulk form's single-precision SPH partner fields (else NULL)
   double *solve;
   int32_t *work;
   uint32_t *flags;
@@ -937,6 +938,13 @@ __device__ __forceinline__ void store_outputs(const DensArgs &A, int p, bool is_
     sr.h = h; sr.ih = 1.0 / h; sr.rho = rho; sr.c = c;
     sr.pr2 = pr2; sr.zo = zo; sr.fa = fa; sr.pad1 = 0.0;
     A.srec[p] = sr;
+    if (A.srec32) {
+      SphRec32 s32;
+      s32.vx = (float)vp.x; s32.vy = (float)vp.y; s32.vz = (float)vp.z; s32.m = (float)a.w;
+      s32.ih = (float)sr.ih; s32.rho = (float)rho; s32.c = (float)c; s32.pr2 = (float)pr2;
+      s32.zo = (float)zo; s32.fa = (float)fa; s32.im = (float)sr.im; s32.h = (float)h;
+      A.srec32[p] = s32;
+    }
   }
   double *S = A.solve;
   S[kNh * A.cap_n + p] = is_gas ? sh.n : 0.0;
@@ -1541,6 +1549,7 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
   A.soft = c->soft;
   A.grec = c->grec;
   A.srec = c->srec;
+  A.srec32 = c->p.precision == TSPH_FP32_BULK ? c->srec32 : nullptr;
   A.solve = c->solve;
   A.work = c->work;
   A.flags = c->flags;

@@ -343,11 +343,6 @@ __device__ __forceinline__ void near_tile(const GravArgs &A, Sink &s, const Grav
 // relative to the batch centre, partial sums per staged tile in single
 // precision carried into double-precision totals after every tile.
 
-// 1/sqrt(x) of the FP32 form: the hardware reciprocal square root.  For
-// normal x it is what rsqrtf returns; rsqrtf's extra scaling of denormal
-// arguments is left out (a squared distance never lies in that range: the
-// positions are relative to the batch centre, and zero gives +inf either way).
-__device__ __forceinline__ float rsq32(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // fmaxf of two non-negative floats, as the larger bit pattern (no NaN
 // canonicalisation).  With s4 = (2 eps)^2 rounded, max(s4_i, s4_j) is the

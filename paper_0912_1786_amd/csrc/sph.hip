@@ -28,6 +28,13 @@
 // pair mean of f, and adds the conductivity term m_j Pi^u_ij |Gbar_ij| to
 // du/dt and the Laplacian of u to its own sum.
 //
+// The FP32-bulk form (mode 3) runs the force pass's pair arithmetic in
+// single precision: the pair set is still decided by the double-precision
+// distance tests, each pair takes its double-precision displacement rounded
+// once and its partner's fields from a single-precision record, and each
+// lane's sums over one tile are carried into double-precision totals after
+// the tile.
+//
 // One wavefront per walk group that holds gas; the wave walks the tree once
 // (opening nodes with gas within 2 max(h_group, h_node) of the group box),
 // lists the candidate leaves in LDS and flushes them in batches.  A flush
@@ -57,6 +64,9 @@ struct SphTile {
   int q[kWave];
 };
 
+// the force passes: double precision (0) and single-precision pairs (3)
+constexpr bool force_mode(int m) { return m == 0 || m == 3; }
+
 struct SphArgs {
   int64_t cap_n;
   const int32_t *groups;
@@ -72,6 +82,7 @@ struct SphArgs {
   const double4 *sph;   // h, rho, c, P/rho^2
   const double *zo;     // zeta / Omega*
   const SphRec *srec;
+  const SphRec32 *srec32;  // single-precision partner fields (mode 3)
   const uint8_t *gas;
   const int32_t *perm;
   const int32_t *nnodes;
@@ -257,6 +268,129 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
   __syncthreads();
 }
 
+// The force pass of tile_pairs with single-precision pair arithmetic (the
+// same pairs, in the same order).
+template <bool kFull>
+__device__ __forceinline__ void tile_pairs32(const SphArgs &A, SphLane &L, const SphTile &T, int nt, bool tc) {
+  const double hi = L.hd.x;
+  uint64_t mask = tile_mask(nt, [&](int j) {
+    const double4 b = T.pos[j];
+    const double r2x = A.L > 0.0 ? dist2_disp(wrap_d(L.a.x - b.x, A.L), wrap_d(L.a.y - b.y, A.L),
+                                              wrap_d(L.a.z - b.z, A.L))
+                                 : dist2_pair(L.a.x, L.a.y, L.a.z, b.x, b.y, b.z);
+    const double R = 2.0 * fmax(hi, b.w);
+    return L.sink && r2x < R * R;
+  });
+  const float ihi = (float)(1.0 / hi), imi = (float)(1.0 / L.a.w), hif = (float)hi;
+  const float ihi4 = ihi * ihi * ihi * ihi * (float)kInvPiS;
+  const float vix = (float)L.v.x, viy = (float)L.v.y, viz = (float)L.v.z;
+  const float fai = (float)L.fa, zii = (float)L.zi;
+  const float rhoi = (float)L.hd.y, ci = (float)L.hd.z, pri = (float)L.hd.w;
+  const float alpha = (float)A.alpha, beta = (float)A.beta, aveps2 = (float)A.av_eps2;
+  float ax = 0.0f, ay = 0.0f, az = 0.0f, du = 0.0f, duv = 0.0f, mumax = 0.0f, vsig = 0.0f;
+  float xsx = 0.0f, xsy = 0.0f, xsz = 0.0f, lapu = 0.0f;
+  while (mask) {
+    const int j = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const int q = T.q[j];
+    if (q == L.p) continue;  // the sink itself
+    const SphRec32 b = A.srec32[q];
+    if (L.dbg) {
+      if (L.ndbg < A.dbg_max) L.dbg[L.ndbg] = A.perm[q];
+      L.ndbg++;
+    }
+    L.npair++;
+    const double4 pj = T.pos[j];
+    double ddx = L.a.x - pj.x, ddy = L.a.y - pj.y, ddz = L.a.z - pj.z;
+    if (A.L > 0.0) {  // the nearest image
+      ddx = wrap_d(ddx, A.L);
+      ddy = wrap_d(ddy, A.L);
+      ddz = wrap_d(ddz, A.L);
+    }
+    const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 > 0.0f)) continue;
+    const float ir = rsq32(r2);
+    const float r = r2 * ir;
+    const float ihj2 = b.ih * b.ih;
+    const float gi = m4_grad(r * ihi, tc) * ihi4 * ir;
+    const float gj = m4_grad(r * b.ih, tc) * (ihj2 * ihj2 * (float)kInvPiS) * ir;
+    const float mj = b.m;
+    const float fij = fai + zii * b.im;
+    const float fji = b.fa + b.zo * imi;
+    const float Ai = pri * fij;
+    const float Aj = b.pr2 * fji;
+    const float vx = vix - b.vx, vy = viy - b.vy, vz = viz - b.vz;
+    const float vd = vx * dx + vy * dy + vz * dz;
+    float sf = mj * (Ai * gi + Aj * gj);
+    float e = mj * Ai * gi * vd;
+    const float cb = 0.5f * (ci + b.c);
+    const float rb = 0.5f * (rhoi + b.rho);
+    const float irb = rcp32(rb);
+    const float w = vd * ir;  // v_ij . x_ij / r
+    double4 e2j = make_double4(0.0, 0.0, 1.0, 0.0);
+    if (kFull && A.f2) e2j = A.srec2[q];
+    if (vd < 0.0f) {
+      const float hb = 0.5f * (hif + b.h);
+      const float mu = hb * vd * rcp32(r2 + aveps2 * hb * hb);
+      const float al = (kFull && A.alpha_switch) ? 0.5f * (float)(L.e2.x + e2j.x) : alpha;
+      float Pi = A.visc_signal ? -al * (2.0f * cb - w) * w * irb : (-al * cb * mu + beta * mu * mu) * irb;
+      if (kFull && A.balsara) Pi *= 0.5f * (float)(L.e2.z + e2j.z);
+      const float Gb = 0.5f * (fij * gi + fji * gj);
+      sf += mj * Pi * Gb;
+      const float ev = 0.5f * mj * Pi * Gb * vd;
+      e += ev;
+      duv += ev;
+      mumax = fmaxf(mumax, fabsf(mu));
+    }
+    vsig = fmaxf(vsig, 2.0f * cb - fminf(w, 0.0f));
+    if (kFull && A.conduction) {
+      const float Gbm = fabsf(0.5f * (fij * gi + fji * gj)) * r;
+      const float du_ij = (float)(L.e2.w - e2j.w);
+      const float Pd = pri * rhoi * rhoi - b.pr2 * b.rho * b.rho;  // P_i - P_j
+      const float Piu = -0.5f * (float)(L.e2.y + e2j.y) * sqrtf(fabsf(Pd) * irb) * du_ij * irb;
+      e += mj * Piu * Gbm;
+      lapu -= 2.0f * mj * du_ij * rcp32(b.rho) * Gbm * ir;
+    }
+    if (kFull && A.xsph_eta > 0.0) {
+      float wi, dwi, wj, dwj;
+      m4_t(r * ihi, wi, dwi);
+      m4_t(r * b.ih, wj, dwj);
+      const float wb = 0.5f * (wi * (ihi * ihi * ihi) + wj * (b.ih * b.ih * b.ih)) * (float)kInvPiS * irb;
+      xsx -= mj * vx * wb;
+      xsy -= mj * vy * wb;
+      xsz -= mj * vz * wb;
+    }
+    ax -= sf * dx;
+    ay -= sf * dy;
+    az -= sf * dz;
+    du += e;
+  }
+  L.ax += (double)ax;
+  L.ay += (double)ay;
+  L.az += (double)az;
+  L.du += (double)du;
+  L.duv += (double)duv;
+  L.mumax = fmax(L.mumax, (double)mumax);
+  L.vsig = fmax(L.vsig, (double)vsig);
+  if (kFull) {
+    L.xsx += (double)xsx;
+    L.xsy += (double)xsy;
+    L.xsz += (double)xsz;
+    L.lapu += (double)lapu;
+  }
+  __syncthreads();
+}
+
+// one tile of the pass of mode kMode
+template <int kMode, bool kFull>
+__device__ __forceinline__ void tile_eval(const SphArgs &A, SphLane &L, const SphTile &T, int nt, bool tc) {
+  if constexpr (kMode == 3)
+    tile_pairs32<kFull>(A, L, T, nt, tc);
+  else
+    tile_pairs<kMode, kFull>(A, L, T, nt, tc);
+}
+
 // The gas among the candidates of the lanes' raw slots (slot ln holds
 // candidate q, nt valid) appended to the tile of gas candidates, which holds
 // fill of them: a full tile is evaluated and the remainder carried over to
@@ -276,7 +410,7 @@ __device__ __forceinline__ int stage_gas(const SphArgs &A, SphLane &L, SphTile &
   }
   __syncthreads();
   if (fill + ng < kWave) return fill + ng;
-  tile_pairs<kMode, kFull>(A, L, T, kWave, tc);
+  tile_eval<kMode, kFull>(A, L, T, kWave, tc);
   // the remainder (its record read again: fewer registers live across the
   // pair evaluation)
   if (g && slot >= kWave) {
@@ -328,7 +462,7 @@ __device__ __forceinline__ int sph_ranges(const SphArgs &A, SphLane &L, SphTile 
     }
   }
   if (fill > 0) gfill = stage_gas<kMode, kFull>(A, L, T, fill, rq, gfill, tc);
-  if (gfill > 0) tile_pairs<kMode, kFull>(A, L, T, gfill, tc);
+  if (gfill > 0) tile_eval<kMode, kFull>(A, L, T, gfill, tc);
   return scanned;
 }
 
@@ -383,7 +517,7 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
       const int p = act ? s_gs[ln] : bt.first;
       SphLane L;
       // the force pass of individual time-steps evaluates active sinks only
-      sph_lane<kFull>(A, L, p, act && (kMode != 0 || !A.act || A.act[p]));
+      sph_lane<kFull>(A, L, p, act && (!force_mode(kMode) || !A.act || A.act[p]));
       if (ballot(L.sink) == 0) continue;
       if (kMode == 2) L.dbg = nullptr;
       const double hi = L.hd.x;
@@ -488,7 +622,7 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
         A.bm[A.perm[p]] = L.bm;
         A.bw[A.perm[p]] = L.bw;
       }
-      if (kMode == 0 && L.sink) {
+      if (force_mode(kMode) && L.sink) {
         A.acc[0 * A.cap_n + p] += L.ax;
         A.acc[1 * A.cap_n + p] += L.ay;
         A.acc[2 * A.cap_n + p] += L.az;
@@ -508,7 +642,7 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
 
 // The handed-off flushes: each item's ranges on the sinks of its batch
 // chunk; per-lane partial sums to split_part (kSphPart records per lane).
-template <bool kFull, bool kPer>
+template <int kMode, bool kFull, bool kPer>
 __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
   if constexpr (!kPer) A.L = 0.0;
   __shared__ int2 s_rng[kSplitItemRanges];
@@ -534,7 +668,7 @@ __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
     L.dbg = nullptr;
     for (int a = ln; a < I.count; a += kWave) s_rng[a] = A.split_rng[I.start + a];
     __syncthreads();
-    sph_ranges<0, kFull>(A, L, s_t, SphRangeSrc{s_rng}, I.count, tc);
+    sph_ranges<kMode, kFull>(A, L, s_t, SphRangeSrc{s_rng}, I.count, tc);
     double4 *part = A.split_part + (int64_t)kSphPart * it * kWave;
     part[ln] = make_double4(L.ax, L.ay, L.az, L.du);
     part[kWave + ln] = make_double4(L.mumax, (double)L.npair, L.duv, L.vsig);
@@ -629,14 +763,14 @@ static void launch_sph(Ctx *c, const SphArgs &A, hipStream_t st) {
     hipLaunchKernelGGL((k_sph<kMode, kFull, false>), dim3(persistent_blocks(c, k)), dim3(64), 0, st, A);
   }
 }
-template <bool kFull>
+template <int kMode, bool kFull>
 static void launch_sph_split(Ctx *c, const SphArgs &A, hipStream_t st) {
   if (A.L > 0.0) {
-    const void *k = (const void *)k_sph_split<kFull, true>;
-    hipLaunchKernelGGL((k_sph_split<kFull, true>), dim3(persistent_blocks(c, k)), dim3(64), 0, st, A);
+    const void *k = (const void *)k_sph_split<kMode, kFull, true>;
+    hipLaunchKernelGGL((k_sph_split<kMode, kFull, true>), dim3(persistent_blocks(c, k)), dim3(64), 0, st, A);
   } else {
-    const void *k = (const void *)k_sph_split<kFull, false>;
-    hipLaunchKernelGGL((k_sph_split<kFull, false>), dim3(persistent_blocks(c, k)), dim3(64), 0, st, A);
+    const void *k = (const void *)k_sph_split<kMode, kFull, false>;
+    hipLaunchKernelGGL((k_sph_split<kMode, kFull, false>), dim3(persistent_blocks(c, k)), dim3(64), 0, st, A);
   }
 }
 
@@ -656,6 +790,7 @@ static SphArgs sph_args(Ctx *c) {
   A.sph = c->sph;
   A.zo = c->zo;
   A.srec = c->srec;
+  A.srec32 = c->srec32;
   A.gas = c->gas;
   A.perm = c->perm;
   A.nnodes = c->lvl + 46;
@@ -720,17 +855,33 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
     launch_sph<1, true>(c, Ac, st);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, A.work + 24, 8);
   }
-  // the plain form without the switches, the conductivity and X-SPH
+  // the plain form without the switches, the conductivity and X-SPH; the
+  // FP32-bulk form's pairs in single precision
   const bool full = A.f2 || A.xsph_eta > 0.0;
-  if (full)
-    launch_sph<0, true>(c, A, st);
-  else
-    launch_sph<0, false>(c, A, st);
-  if (A.split_particles > 0) {
+  const bool f32 = c->p.precision == TSPH_FP32_BULK;
+  if (f32) {
     if (full)
-      launch_sph_split<true>(c, A, st);
+      launch_sph<3, true>(c, A, st);
     else
-      launch_sph_split<false>(c, A, st);
+      launch_sph<3, false>(c, A, st);
+  } else {
+    if (full)
+      launch_sph<0, true>(c, A, st);
+    else
+      launch_sph<0, false>(c, A, st);
+  }
+  if (A.split_particles > 0) {
+    if (f32) {
+      if (full)
+        launch_sph_split<3, true>(c, A, st);
+      else
+        launch_sph_split<3, false>(c, A, st);
+    } else {
+      if (full)
+        launch_sph_split<0, true>(c, A, st);
+      else
+        launch_sph_split<0, false>(c, A, st);
+    }
     hipLaunchKernelGGL(k_sph_reduce, dim3(4096), dim3(64), 0, st, A);
   }
   TSPH_HIP_CHECK(c, hipGetLastError());

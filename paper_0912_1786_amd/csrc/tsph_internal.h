@@ -55,6 +55,14 @@ struct SphRec {
   double pr2, zo, fa, pad1;    // P / rho^2, zeta / Omega*, grad-h factor f_ij = fa + zo / m_j
 };
 
+// The partner fields of an SPH pair in single precision (the FP32-bulk
+// form's force pass; positions stay in the double-precision record)
+struct alignas(16) SphRec32 {
+  float vx, vy, vz, m;   // predicted velocity, mass
+  float ih, rho, c, pr2;
+  float zo, fa, im, h;
+};
+
 // The simulations a context holds (a forest of independent trees).  Member
 // m owns particles [off[m], off[m+1]) in caller order and, because the sort
 // is segmented by member, the same range in key order; its first ngas[m]
@@ -156,6 +164,7 @@ struct Ctx {
   double2 *soft;          // eps, xi / Upsilon
   GravRec *grec;          // gravity source records
   SphRec *srec;           // SPH source records (gas entries)
+  SphRec32 *srec32;       // their single-precision partner fields (FP32-bulk form)
   double4 *srec2;         // dissipation switches: alpha, alpha_u, Balsara factor, u (gas entries)
   double2 *av;            // alpha, alpha_u gathered into key order
   const double *alpha_state, *alpha_u_state;  // the state's arrays of the current force pass (caller order)
@@ -274,6 +283,13 @@ __device__ __forceinline__ double rsq64(double x) {
   return fma(u, fma(e, 0.375, 0.5), y);
 }
 
+// Single-precision hardware 1/sqrt(x) and 1/x (about one ulp).  For normal x
+// rsq32 is what rsqrtf returns; rsqrtf's extra scaling of denormal arguments
+// is left out (the callers' squared distances never lie in that range, and
+// zero gives +inf either way).
+__device__ __forceinline__ float rsq32(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Per-lane mask of the tile entries j < nt (nt <= 64) for which f(j) holds,
 // f called for j = 0, 1, ... in order.  Built as two 32-bit halves, so that
 // the bit of entry j is a wave-uniform constant.
@@ -358,16 +374,33 @@ __device__ __forceinline__ void m4(double q, double &w, double &dw) {
 
 // derivative of the M4 kernel used in the SPH pairs: the plain dw/dq or the
 // Thomas & Couchman (1992) form, constant inside q < 2/3 (Sect. 3).
-__device__ __forceinline__ double m4_grad(double q, bool tc92) {
-  if (q < 1.0) {
-    if (tc92 && q < (2.0 / 3.0)) return -1.0;
-    return q * (-3.0 + 2.25 * q);
+template <class T>
+__device__ __forceinline__ T m4_grad(T q, bool tc92) {
+  if (q < T(1)) {
+    if (tc92 && q < T(2.0 / 3.0)) return T(-1);
+    return q * (T(-3) + T(2.25) * q);
   }
-  if (q < 2.0) {
-    double t = 2.0 - q;
-    return -0.75 * t * t;
+  if (q < T(2)) {
+    const T t = T(2) - q;
+    return T(-0.75) * t * t;
   }
-  return 0.0;
+  return T(0);
+}
+
+// m4 in either precision
+template <class T>
+__device__ __forceinline__ void m4_t(T q, T &w, T &dw) {
+  if (q < T(1)) {
+    w = T(1) + q * q * (T(-1.5) + T(0.75) * q);
+    dw = q * (T(-3) + T(2.25) * q);
+  } else if (q < T(2)) {
+    const T t = T(2) - q;
+    w = T(0.25) * t * t * t;
+    dw = T(-0.75) * t * t;
+  } else {
+    w = T(0);
+    dw = T(0);
+  }
 }
 
 // Softened gravity of a unit mass smoothed by the spline (Sect. 2.1):

@@ -1,11 +1,20 @@
-"""GPU parity of the FP32-bulk form (gravity interactions in single
-precision relative to each walk batch's centre, tile sums carried in double)
-against the FP64 oracle on the same seeded inputs.
+"""GPU parity of the FP32-bulk form against the FP64 oracle on the same
+seeded inputs.  The form evaluates the gravity interactions in single
+precision relative to each walk batch's centre, and the SPH force pairs in
+single precision on the double-precision displacement.  In both, the tile
+sums are carried in double.
 
-Stated errors (bars): acceleration relative RMS against the oracle's
-same-theta group walk <= 1e-5 (the FP64 form's bar), potential relative RMS
-<= 1e-5, against the direct sum at theta = 0.5 <= 2e-3; the length solves,
-densities and SPH terms are the FP64 form's, bit for bit.
+Stated errors (bars):
+* acceleration relative RMS against the oracle's same-theta group walk
+  <= 1e-5 (the FP64 form's bar), against the direct sum at theta = 0.5
+  <= 2e-3; potential relative RMS <= 1e-5;
+* with gravity off (the SPH acceleration alone) and for du/dt: relative RMS
+  <= 2e-6 (about 2e-7 measured); max|mu| and the signal velocity within 5e-6
+  and 2e-6 relative;
+* the length solves and densities are the FP64 form's, bit for bit: the
+  lengths decide the neighbour sets, which must equal the oracle's, so the
+  solves stay in double precision;
+* the interaction sets (gravity and SPH) are the FP64 form's.
 """
 import sys
 
@@ -60,10 +69,13 @@ def test_fp32_bulk_forces(orc_mod, case):
     sim, g = run_gpu(ic, gp)
     sim.close()
     assert g["flags"] == 0 and g["noconv"] == 0
-    # the length solves, densities and SPH terms are the FP64 form's
-    for k in ("h", "eps", "rho", "dudt", "omega", "zeta", "xi", "ups"):
+    # the length solves and densities are the FP64 form's
+    for k in ("h", "eps", "rho", "omega", "zeta", "xi", "ups"):
         assert np.array_equal(g[k], g64[k]), k
     o = orc_mod.compute_forces(ic, oracle_params(orc_mod, gp))
+    eu = relrms(g["dudt"], o["dudt"])
+    _say(f"    du/dt relRMS vs oracle {eu:.3e} (FP64 form {relrms(g64['dudt'], o['dudt']):.3e})")
+    assert eu < 2e-6
     e = relrms(acc(g), acc(o))
     rel = np.linalg.norm(acc(g) - acc(o), axis=1) / np.linalg.norm(acc(o), axis=1)
     ep = relrms(g["pot"], o["pot"])
@@ -78,3 +90,48 @@ def test_fp32_bulk_forces(orc_mod, case):
     # the interaction sets are the FP64 form's
     assert np.array_equal(g["cnt_node"], g64["cnt_node"])
     assert np.array_equal(g["cnt_pair"], g64["cnt_pair"])
+    assert np.array_equal(g["cnt_sph"], g64["cnt_sph"])
+
+
+SPH_CASES = {
+    "evrard4096_v": (lambda: inputs.evrard(4096, seed=2, v_sigma=0.1), 50, {}),
+    "field2x3000": (lambda: inputs.two_species_field(n_dm=3000, n_gas=3000, n_halo=8, seed=3), 60, {}),
+    "switches_xsph": (lambda: inputs.evrard(4096, seed=4, v_sigma=0.1), 50,
+                      dict(balsara=1, alpha_switch=1, conduction=1, xsph_eta=0.25)),
+    "signal_viscosity": (lambda: inputs.evrard(4096, seed=5, v_sigma=0.1), 50, dict(visc_form=tsph.VISC_SIGNAL)),
+}
+
+
+@pytest.mark.parametrize("case", list(SPH_CASES))
+def test_fp32_bulk_sph_pairs(orc_mod, case):
+    """Gravity off: the acceleration is the SPH one alone, so its error is
+    the single-precision pair arithmetic's."""
+    _say(f"[fp32-sph] case={case}")
+    make, nnei, extra = SPH_CASES[case]
+    ic = make()
+    if extra.get("alpha_switch"):
+        ic["alpha"] = np.full(ic["n"], 0.5)
+        ic["alpha_u"] = np.full(ic["n"], 0.2)
+    kw = dict(nnei=nnei, gravity=0, **extra)
+    sim64, g64 = run_gpu(ic, gpu_params(**kw))
+    sim64.close()
+    sim, g = run_gpu(ic, gpu_params(precision=tsph.FP32_BULK, **kw))
+    sim.close()
+    assert g["flags"] == 0 and g["noconv"] == 0
+    gas = np.arange(ic["n"]) < ic["n_gas"]
+    o = orc_mod.compute_forces(ic, oracle_params(orc_mod, gpu_params(**kw)),
+                               alpha=ic.get("alpha"), alpha_u=ic.get("alpha_u"))
+    ea, eu = relrms(acc(g), acc(o)), relrms(g["dudt"], o["dudt"])
+    _say(f"    a_sph relRMS {ea:.3e}, du/dt relRMS {eu:.3e} (FP64 form {relrms(acc(g64), acc(o)):.1e}, "
+         f"{relrms(g64['dudt'], o['dudt']):.1e})")
+    assert ea < 2e-6 and eu < 2e-6
+    assert np.allclose(g["maxmu"][gas], o["maxmu"][gas], rtol=5e-6, atol=1e-14)
+    assert np.allclose(g["vsig"][gas], o["vsig"][gas], rtol=2e-6)
+    assert np.array_equal(g["cnt_sph"], g64["cnt_sph"])
+    for k in ("h", "rho"):
+        assert np.array_equal(g[k], g64[k]), k
+    if extra.get("xsph_eta"):
+        xs = np.stack([g["xsph_sx"], g["xsph_sy"], g["xsph_sz"]], 1)
+        xs64 = np.stack([g64["xsph_sx"], g64["xsph_sy"], g64["xsph_sz"]], 1)
+        assert relrms(xs, xs64) < 2e-6
+        assert relrms(g["lapu"], g64["lapu"]) < 2e-6

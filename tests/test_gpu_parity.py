@@ -117,7 +117,10 @@ def _compare_full(orc_mod, ic, gp, lists=0, direct=False, tol_acc=1e-5, tol_pot=
         ed = relrms(g["dudt"], o["dudt"])
         _say(f"    du/dt relRMS = {ed:.3e}")
         assert ed < 1e-6
-        assert np.allclose(g["maxmu"][gas], o["maxmu"][gas], rtol=1e-8, atol=1e-14)
+        # single-precision SPH pairs in the FP32-bulk form (measured max
+        # relative error 7e-7)
+        mu_rtol = 5e-6 if gp.precision == tsph.FP32_BULK else 1e-8
+        assert np.allclose(g["maxmu"][gas], o["maxmu"][gas], rtol=mu_rtol, atol=1e-14)
     if gp.gravity:
         pe = relrms(g["pot"], o["pot"])
         _say(f"    potential relRMS = {pe:.3e}")

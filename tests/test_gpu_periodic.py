@@ -70,7 +70,7 @@ def test_periodic_forces_match_oracle(O, form):
     ed = relrms(g["dudt"], o["dudt"])
     _say(f"    acc relRMS {e:.3e}, du/dt relRMS {ed:.3e}")
     assert e < (1e-11 if form == "fp64" else 2e-6)
-    assert ed < 1e-9
+    assert ed < (1e-9 if form == "fp64" else 2e-6)  # single-precision SPH pairs: 1.8e-7 measured
     assert np.array_equal(g["cnt_node"], o["cnt_node"])
     assert np.array_equal(g["cnt_pair"], o["cnt_pair"])
     assert np.array_equal(g["cnt_sph"], o["cnt_sph"])

@@ -47,8 +47,11 @@ def _check(O, ic, gp, tol_acc=1e-5):
     ed = relrms(g["dudt"], o["dudt"]) if np.any(o["dudt"]) else float(np.abs(g["dudt"]).max())
     _say(f"    acc relRMS {e:.2e}, du/dt relRMS {ed:.2e}")
     assert e < tol_acc and ed < 1e-6
-    assert np.allclose(g["maxmu"][gas], o["maxmu"][gas], rtol=1e-8, atol=1e-14)
-    assert np.allclose(g["vsig"][gas], o["vsig"][gas], rtol=1e-12)
+    # the FP32-bulk form's SPH pairs are single precision (measured: max
+    # relative error 7e-7 in max|mu|, 2e-7 in the signal velocity)
+    f32 = gp.precision == tsph.FP32_BULK
+    assert np.allclose(g["maxmu"][gas], o["maxmu"][gas], rtol=5e-6 if f32 else 1e-8, atol=1e-14)
+    assert np.allclose(g["vsig"][gas], o["vsig"][gas], rtol=2e-6 if f32 else 1e-12)
     assert np.array_equal(g["cnt_sph"], o["cnt_sph"])
     return g, o
 
