@@ -107,7 +107,9 @@ __device__ bool walk_leaves(const DensArgs &A, int root, const NodeBox &gb, doub
     __syncthreads();
     bool hit = false, leaf = false;
     NodeTopo nd{0, 0, -1, 0};
+    // box, gas count and topology in one round trip
     const NodeBox b = A.nbox[k >= 0 ? k : 0];
+    const NodeTopo ndk = A.topo[k >= 0 ? k : 0];
     if (k >= 0 && (!gas_only || A.nngas[k] > 0)) {
       double d2 = axis_gap_box_p(gb.lox, gb.hix, b.lox, b.hix, A.L);
       d2 = d2 + axis_gap_box_p(gb.loy, gb.hiy, b.loy, b.hiy, A.L);
@@ -116,7 +118,7 @@ __device__ bool walk_leaves(const DensArgs &A, int root, const NodeBox &gb, doub
     }
     hit = balls_reach_box(s_snk, b.lox, b.loy, b.loz, b.hix, b.hiy, b.hiz, 0.0, hit, A.L) && hit;
     if (hit) {
-      nd = A.topo[k];
+      nd = ndk;
       leaf = nd.nchild == 0;
       if (whole && !leaf && !(A.L > 0.0)) {
         const double fx = fmax(fabs(gb.lox - b.lox), fabs(b.hix - gb.lox));

@@ -673,8 +673,11 @@ __device__ __forceinline__ GClass classify(const GravArgs &A, const NodeBox &gb,
   const double L = (M & kPer) ? A.L : 0.0;  // periodic box (folded away in the open kernels)
   GClass c{false, false, false, false, -1, 0};
   if (k < 0) return c;
+  // all three records in one round trip (the topology is used only when the
+  // node is not accepted)
   const NodeFar f = A.nfar[k];
   const NodeBox b = A.nbox[k];
+  const NodeTopo nd = A.topo[k];
   double d2 = axis_gap_point_p(gb.lox, gb.hix, f.cx, L);
   d2 = d2 + axis_gap_point_p(gb.loy, gb.hiy, f.cy, L);
   d2 = d2 + axis_gap_point_p(gb.loz, gb.hiz, f.cz, L);
@@ -689,7 +692,6 @@ __device__ __forceinline__ GClass classify(const GravArgs &A, const NodeBox &gb,
     c.scell = A.soften && !c.acc;
   }
   if (!c.acc && !c.scell) {
-    const NodeTopo nd = A.topo[k];
     // a node wholly inside the softening reach of the batch is taken whole:
     // all its particles are near pairs (unless a descendant may become a
     // softened cell)

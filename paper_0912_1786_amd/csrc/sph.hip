@@ -399,13 +399,17 @@ __device__ __forceinline__ void tile_eval(const SphArgs &A, SphLane &L, const Sp
 template <int kMode, bool kFull>
 __device__ __forceinline__ int stage_gas(const SphArgs &A, SphLane &L, SphTile &T, int nt, int q, int fill, bool tc) {
   const int ln = lane();
-  const bool g = ln < nt && A.gas[q] != 0;
+  // the species flag and the leading part of the record in one round trip
+  // (a non-gas record is read but not used)
+  const bool in = ln < nt;
+  const bool g = in && A.gas[q] != 0;
+  const SphRec *r = A.srec + (in ? q : 0);
+  const double4 pos = make_double4(r->x, r->y, r->z, r->h);
   const uint64_t gm = ballot(g);
   const int slot = fill + mbcnt(gm);
   const int ng = __popcll(gm);
   if (g && slot < kWave) {
-    const SphRec *r = A.srec + q;
-    T.pos[slot] = make_double4(r->x, r->y, r->z, r->h);
+    T.pos[slot] = pos;
     T.q[slot] = q;
   }
   __syncthreads();
@@ -541,7 +545,9 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
           __syncthreads();
           bool hit = false, leaf = false;
           NodeTopo nd{0, 0, -1, 0};
+          // box, gas count and topology in one round trip
           NodeBox b = A.nbox[k >= 0 ? k : 0];
+          const NodeTopo ndk = A.topo[k >= 0 ? k : 0];
           if (k >= 0 && A.nngas[k] > 0) {
             double d2 = axis_gap_box_p(gb.lox, gb.hix, b.lox, b.hix, A.L);
             d2 = d2 + axis_gap_box_p(gb.loy, gb.hiy, b.loy, b.hiy, A.L);
@@ -552,7 +558,7 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
           // keep the node only if some gas sink reaches it: |x_i - box| < 2 max(h_i, h_node)
           hit = balls_reach_box(s_snk, b.lox, b.loy, b.loz, b.hix, b.hiy, b.hiz, 2.0 * b.hmax, hit, A.L) && hit;
           if (hit) {
-            nd = A.topo[k];
+            nd = ndk;
             leaf = nd.nchild == 0;
           }
           const uint64_t lm = ballot(leaf);

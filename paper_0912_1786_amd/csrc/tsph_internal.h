@@ -47,11 +47,12 @@ struct GravRec {
   double eps, ieps, xiu, s4;  // eps, 1/eps, xi~ / Upsilon, (2 eps)^2
 };
 
-// Source record of a gas particle for the SPH pairs (128 B).
+// Source record of a gas particle for the SPH pairs (128 B); position and
+// h lead, the part the candidate tiles stage.
 struct SphRec {
-  double x, y, z, m;
-  double vx, vy, vz, im;       // predicted velocity, 1/m
-  double h, ih, rho, c;        // h, 1/h, density, sound speed
+  double x, y, z, h;
+  double vx, vy, vz, m;        // predicted velocity, mass
+  double im, ih, rho, c;       // 1/m, 1/h, density, sound speed
   double pr2, zo, fa, pad1;    // P / rho^2, zeta / Omega*, grad-h factor f_ij = fa + zo / m_j
 };
 
