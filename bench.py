@@ -61,7 +61,7 @@ F_SPH = 100.0
 # phase timed by the library -> kernel that dominates it and its source files
 PHASE_KERNEL = {"density": ("k_density+k_density_sink", "density.hip"),
                 "gravity": ("k_gravity+k_gravity_split+k_split_reduce", "gravity.hip"),
-                "sph": ("k_sph", "sph.hip")}
+                "sph": ("k_sph+k_sph_split+k_sph_reduce", "sph.hip")}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_two_species_field_2M.txt")
 
 
