@@ -278,6 +278,8 @@ __device__ void leaf_sums(const DensArgs &A, int nleaf, const int *s_leaf, DensT
                           int32_t *dbg_row, int &ndbg, Sums &s) {
   const int ln = lane();
   int fill = 0, rq = 0, gfill = 0;
+  // among particles that are all gas there is nothing to compact
+  const bool compact = gas_only && A.n_gas < A.n;
   for (int c1 = 0; c1 < nleaf; c1 += kWave) {
     const int nc = min(kWave, nleaf - c1);
     const NodeTopo my = ln < nc ? A.topo[s_leaf[c1 + ln]] : NodeTopo{0, 0, -1, 0};
@@ -290,7 +292,7 @@ __device__ void leaf_sums(const DensArgs &A, int nleaf, const int *s_leaf, DensT
         fill += tk;
         off += tk;
         if (fill == kWave) {
-          if (gas_only) {
+          if (compact) {
             gfill = stage_gas_sums<kFull>(A, T, kWave, rq, gfill, px, py, pz, vp, h, want_div, want_phi, dbg_row,
                                           ndbg, s);
           } else {
@@ -303,7 +305,7 @@ __device__ void leaf_sums(const DensArgs &A, int nleaf, const int *s_leaf, DensT
       }
     }
   }
-  if (gas_only) {
+  if (compact) {
     if (fill > 0)
       gfill = stage_gas_sums<kFull>(A, T, fill, rq, gfill, px, py, pz, vp, h, want_div, want_phi, dbg_row, ndbg,
                                     s);
@@ -959,10 +961,12 @@ __device__ __forceinline__ void store_outputs(const DensArgs &A, int p, bool is_
   S[kDivvE * A.cap_n + p] = divve;
 }
 
-// kFused: gas and softening lengths solved together (independent solves,
-// both species); otherwise one or the other (or one shared) separately.
+// kForm 1 (fused): gas and softening lengths solved together (independent
+// solves, both species); 2 (shared): one length for both, a pure-gas
+// Lagrangian system with equal eta, so the kernel holds only that solve;
+// 0: one or the other separately, any scheme.
 // kPer: the periodic-box form; the open one takes L = 0 as a constant
-template <bool kFused, bool kPer>
+template <int kForm, bool kPer>
 __global__ __launch_bounds__(64, 3) void k_density(DensArgs A) {
   if constexpr (!kPer) A.L = 0.0;
   __shared__ int s_stack[kDensStackCap];
@@ -998,9 +1002,9 @@ __global__ __launch_bounds__(64, 3) void k_density(DensArgs A) {
       oh.handed = false;
       oh.s = Sums{0, 0, 0, 0, 0, 0};
       // both lengths solved in one pass when they are independent
-      constexpr bool fused = kFused;
+      constexpr bool fused = kForm == 1;
       SolveOut oe_f;
-      if constexpr (kFused) {
+      if constexpr (fused) {
         const double gh = A.hs[p], ge = A.es[p];
         const double guess_h = gh > 0.0 ? gh : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
         const double guess_e = ge > 0.0 ? ge : (act ? cold_guess(A, p, false, A.eta_eps) : 0.0);
@@ -1014,16 +1018,17 @@ __global__ __launch_bounds__(64, 3) void k_density(DensArgs A) {
           if (is_gas && !oh.ok) nnoconv++;
           if (act && !oe_f.ok) nnoconv++;
         }
-      } else if (A.hydro) {  // (not kFused)
+      } else if (A.hydro) {  // (not fused)
         double g0 = A.hs[p];
         double guess = g0 > 0.0 ? g0 : (is_gas ? cold_guess(A, p, true, A.eta_h) : 0.0);
-        if (A.hstd)
+        if (kForm != 2 && A.hstd)
           oh = solve_count(A, bt.root, gb, is_gas, guess, a.x, a.y, a.z, vp, s_stack, s_leaf, s_dt, s_snk,
                            is_gas ? dbg0 : nullptr);
         else
-          oh = solve_length(A, g, bt.root, gb, is_gas, true, A.eta_h, guess, a.x, a.y, a.z, vp, true, A.shared != 0,
-                            s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0), is_gas ? dbg0 : nullptr,
-                            A.hmass ? 1.0 / a.w : 0.0);
+          // (every particle is gas in the shared form: no species filter)
+          oh = solve_length(A, g, bt.root, gb, is_gas, kForm != 2, A.eta_h, guess, a.x, a.y, a.z, vp, true,
+                            kForm == 2 || A.shared != 0, s_stack, s_leaf, s_dt, s_snk, !(g0 > 0.0),
+                            is_gas ? dbg0 : nullptr, (kForm != 2 && A.hmass) ? 1.0 / a.w : 0.0);
         handed = oh.handed;
         if (is_gas && !oh.ok && !handed) nnoconv++;
       }
@@ -1037,10 +1042,10 @@ __global__ __launch_bounds__(64, 3) void k_density(DensArgs A) {
         xi = (A.soft_mode == TSPH_SOFT_ADAPTIVE) ? -(oe_f.h / (3.0 * oe_f.s.n)) * oe_f.s.mdphi : 0.0;
         divve = -oe_f.s.divv / (oe_f.s.n * ups);
       } else if (A.gravity && !handed) {
-        if (A.soft_mode == TSPH_SOFT_CONSTANT) {
+        if (kForm != 2 && A.soft_mode == TSPH_SOFT_CONSTANT) {
           eps = A.es[p];
           if (act && !(eps > 0.0 && eps < INFINITY)) atomicOr(A.flags, TSPH_FLAG_NONFINITE);
-        } else if (A.shared) {
+        } else if (kForm == 2 || A.shared) {
           eps = oh.h;
           neps = oh.s.n;
           ups = 1.0 + (oh.h / (3.0 * oh.s.n)) * oh.s.sdh;
@@ -1587,8 +1592,9 @@ tsph_status tsph_impl_density(Ctx *c, hipStream_t st) {
   A.split_leaves = c->p.split_leaves;
   const bool fused = A.hydro && A.gravity && !A.shared && A.soft_mode != TSPH_SOFT_CONSTANT && !A.hstd;
   const bool per = A.L > 0.0;
-  void (*kd)(DensArgs) = fused ? (per ? k_density<true, true> : k_density<true, false>)
-                               : (per ? k_density<false, true> : k_density<false, false>);
+  void (*kd)(DensArgs) = fused      ? (per ? k_density<1, true> : k_density<1, false>)
+                         : A.shared ? (per ? k_density<2, true> : k_density<2, false>)
+                                    : (per ? k_density<0, true> : k_density<0, false>);
   hipLaunchKernelGGL(kd, dim3(persistent_blocks(c, (const void *)kd)), dim3(64), 0, st, A);
   if (A.heavy_cap > 0) {
     hipLaunchKernelGGL(k_heavy_order, dim3(1), dim3(1024), 0, st, A);
