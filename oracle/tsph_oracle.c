@@ -26,6 +26,17 @@
  *                    hand-worked values; minimum over particles       pinned
  *   diagnostics      rigid rotation + drift: P = M V, L = M R x V + I w,
  *                    E_kin from the inertia tensor                    pinned
+ *   scheme variants  signal-velocity viscosity conserves momentum and
+ *                    energy; entropy rate = rescaled viscous heating;
+ *                    X-SPH carries no momentum; standard scheme counts
+ *                    exactly N; four-scheme mixed-mass lattice        pinned
+ *   switches         curl of a rigid rotation, Balsara limits, alpha
+ *                    rate closed forms, conduction conserves energy   pinned
+ *   periodic box     Ewald sums independent of omega, small-x and
+ *                    symmetry limits, table = sums on its grid; lattice
+ *                    at rest, translation invariance, nearest-image
+ *                    neighbours by brute force                        pinned
+ *   (the individual time-steps, oracle/blocksteps.py, are pinned there)
  *
  * Plain loops, no blocking or fusion; OpenMP only distributes independent
  * sinks over threads.
