@@ -544,20 +544,36 @@ __device__ __forceinline__ double dist2_pair(double xi, double yi, double zi, do
 // staged in LDS (R_s = 0 for lanes without a ball); the ball radius used for
 // sink s is max(R_s, r_node).  Every lane tests its own box against all
 // staged sinks (broadcast reads); the loop stops once every lane that still
-// needs an answer has one.
+// needs an answer has one.  The test only prunes candidates (the pair tests
+// decide), so it may keep more than the exact one and never less: in the
+// open box the gaps are max(lo - p, p - hi, 0) with fused squares, against
+// a radius widened by 1e-14 relative, which covers their rounding.
 __device__ __forceinline__ bool balls_reach_box(const double4 *snk, double lox, double loy, double loz,
                                                 double hix, double hiy, double hiz, double r_node, bool want,
                                                 double L = 0.0) {
   bool hit = false;
+  if (L > 0.0) {
+    for (int s = 0; s < kWave; s++) {
+      const double4 q = snk[s];
+      if (q.w > 0.0) {
+        const double R = fmax(q.w, r_node);
+        double d2 = axis_gap_point_p(lox, hix, q.x, L);
+        d2 = d2 + axis_gap_point_p(loy, hiy, q.y, L);
+        d2 = d2 + axis_gap_point_p(loz, hiz, q.z, L);
+        hit = hit || (d2 < R * R);
+      }
+      if ((s & 7) == 7 && !__any(want && !hit)) break;
+    }
+    return hit;
+  }
   for (int s = 0; s < kWave; s++) {
     const double4 q = snk[s];
-    if (q.w > 0.0) {
-      const double R = fmax(q.w, r_node);
-      double d2 = axis_gap_point_p(lox, hix, q.x, L);
-      d2 = d2 + axis_gap_point_p(loy, hiy, q.y, L);
-      d2 = d2 + axis_gap_point_p(loz, hiz, q.z, L);
-      hit = hit || (d2 < R * R);
-    }
+    const double R = fmax(q.w, r_node);
+    const double R2 = q.w > 0.0 ? (R * R) * (1.0 + 1e-14) : -1.0;
+    const double dx = fmax(fmax(lox - q.x, q.x - hix), 0.0);
+    const double dy = fmax(fmax(loy - q.y, q.y - hiy), 0.0);
+    const double dz = fmax(fmax(loz - q.z, q.z - hiz), 0.0);
+    hit = hit || (fma(dz, dz, fma(dy, dy, dx * dx)) < R2);
     if ((s & 7) == 7 && !__any(want && !hit)) break;
   }
   return hit;
