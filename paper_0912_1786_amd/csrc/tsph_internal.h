@@ -474,19 +474,18 @@ __device__ __forceinline__ T m4_dw(T q) {
 // ---------------------------------------------------------------------------
 // exact geometric predicates (one rounding per operation, fixed order)
 // ---------------------------------------------------------------------------
+// For boxes with lo <= hi the gap is the larger of the two differences and
+// zero: lo - p when p < lo, p - hi when p > hi, else both are <= 0 -- the
+// same rounded values as the case-by-case form, in fewer instructions.
 __device__ __forceinline__ double axis_gap_point(double lo, double hi, double p) {
 #pragma clang fp contract(off)
-  double d = 0.0;
-  if (p < lo) d = lo - p;
-  else if (p > hi) d = p - hi;
+  const double d = fmax(fmax(lo - p, p - hi), 0.0);
   return d * d;
 }
 
 __device__ __forceinline__ double axis_gap_box(double lo1, double hi1, double lo2, double hi2) {
 #pragma clang fp contract(off)
-  double d = 0.0;
-  if (hi1 < lo2) d = lo2 - hi1;
-  else if (hi2 < lo1) d = lo1 - hi2;
+  const double d = fmax(fmax(lo2 - hi1, lo1 - hi2), 0.0);
   return d * d;
 }
 
