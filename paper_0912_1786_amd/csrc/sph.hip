@@ -60,7 +60,7 @@ constexpr int kSphPart = 3;  // partial-sum records per lane of a handed-off ite
 
 // candidates of a flush staged for the pair tests
 struct SphTile {
-  double4 pos[kWave];  // x, y, z, h (non-gas candidates at infinity)
+  double4 pos[kWave];  // x, y, z, (2h)^2
   int q[kWave];
 };
 
@@ -163,13 +163,15 @@ __device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bo
 template <int kMode, bool kFull>
 __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const SphTile &T, int nt, bool tc) {
   const double hi = L.hd.x;
+  // (2 max(h_i, h_j))^2 as the larger of the two staged squares: squaring
+  // is monotone, so it is the same rounded value
+  const double R2i = (2.0 * hi) * (2.0 * hi);
   uint64_t mask = tile_mask(nt, [&](int j) {
     const double4 b = T.pos[j];
     const double r2x = A.L > 0.0 ? dist2_disp(wrap_d(L.a.x - b.x, A.L), wrap_d(L.a.y - b.y, A.L),
                                               wrap_d(L.a.z - b.z, A.L))
                                  : dist2_pair(L.a.x, L.a.y, L.a.z, b.x, b.y, b.z);
-    const double R = 2.0 * fmax(hi, b.w);
-    return L.sink && r2x < R * R;
+    return L.sink && r2x < fmax(R2i, b.w);
   });
   const double ihi = 1.0 / hi, imi = 1.0 / L.a.w;
   const double ihi4 = ihi * ihi * ihi * ihi * kInvPiS;
@@ -273,13 +275,15 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
 template <bool kFull>
 __device__ __forceinline__ void tile_pairs32(const SphArgs &A, SphLane &L, const SphTile &T, int nt, bool tc) {
   const double hi = L.hd.x;
+  // (2 max(h_i, h_j))^2 as the larger of the two staged squares: squaring
+  // is monotone, so it is the same rounded value
+  const double R2i = (2.0 * hi) * (2.0 * hi);
   uint64_t mask = tile_mask(nt, [&](int j) {
     const double4 b = T.pos[j];
     const double r2x = A.L > 0.0 ? dist2_disp(wrap_d(L.a.x - b.x, A.L), wrap_d(L.a.y - b.y, A.L),
                                               wrap_d(L.a.z - b.z, A.L))
                                  : dist2_pair(L.a.x, L.a.y, L.a.z, b.x, b.y, b.z);
-    const double R = 2.0 * fmax(hi, b.w);
-    return L.sink && r2x < R * R;
+    return L.sink && r2x < fmax(R2i, b.w);
   });
   const float ihi = (float)(1.0 / hi), imi = (float)(1.0 / L.a.w), hif = (float)hi;
   const float ihi4 = ihi * ihi * ihi * ihi * (float)kInvPiS;
@@ -404,7 +408,7 @@ __device__ __forceinline__ int stage_gas(const SphArgs &A, SphLane &L, SphTile &
   const bool in = ln < nt;
   const bool g = in && A.gas[q] != 0;
   const SphRec *r = A.srec + (in ? q : 0);
-  const double4 pos = make_double4(r->x, r->y, r->z, r->h);
+  const double4 pos = make_double4(r->x, r->y, r->z, (2.0 * r->h) * (2.0 * r->h));
   const uint64_t gm = ballot(g);
   const int slot = fill + mbcnt(gm);
   const int ng = __popcll(gm);
@@ -419,7 +423,7 @@ __device__ __forceinline__ int stage_gas(const SphArgs &A, SphLane &L, SphTile &
   // pair evaluation)
   if (g && slot >= kWave) {
     const SphRec *r = A.srec + q;
-    T.pos[slot - kWave] = make_double4(r->x, r->y, r->z, r->h);
+    T.pos[slot - kWave] = make_double4(r->x, r->y, r->z, (2.0 * r->h) * (2.0 * r->h));
     T.q[slot - kWave] = q;
   }
   __syncthreads();
