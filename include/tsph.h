@@ -65,12 +65,15 @@ typedef enum {
 enum { TSPH_SOFT_ADAPTIVE = 0,        /* eps solved, correction terms on (Sect. 2.1) */
        TSPH_SOFT_CONSTANT = 1,        /* eps given by the caller, no corrections     */
        TSPH_SOFT_ADAPTIVE_NOCORR = 2  /* eps solved, correction terms off            */ };
-/* Arithmetic of the walks (Sect. 2.2 gravity).  TSPH_FP32_BULK evaluates the
- * gravity interactions (far nodes and particle pairs) in single precision on
- * coordinates taken relative to the walk batch's centre, with single-
- * precision sums per staged tile of 64 interactions carried into double-
- * precision totals; positions, velocities, node centres of mass, the walk's
- * acceptance tests, the integrator and the diagnostics stay FP64. */
+/* Arithmetic of the walks (Sect. 2.2 gravity, Sect. 3 SPH).  TSPH_FP32_BULK
+ * evaluates the gravity interactions (far nodes and particle pairs) in single
+ * precision on coordinates taken relative to the walk batch's centre, and the
+ * SPH force pairs in single precision on the double-precision displacement
+ * rounded once; single-precision sums per staged tile of at most 64
+ * interactions are carried into double-precision totals.  Positions,
+ * velocities, node centres of mass, the walks' acceptance and neighbour
+ * tests (so the interaction sets are the FP64 form's), the length solves and
+ * densities, the integrator and the diagnostics stay FP64. */
 enum { TSPH_FP64 = 0, TSPH_FP32_BULK = 1 };
 enum { TSPH_KD_FIRST = 0, TSPH_KD_SECOND = 1 };
 

@@ -34,7 +34,23 @@ CASES = {
     "evrard4096_v": lambda: inputs.evrard(4096, seed=2, v_sigma=0.1),
     "field2x3000": lambda: inputs.two_species_field(n_dm=3000, n_gas=3000, n_halo=8, seed=3),
     "ragged777": lambda: inputs.evrard(777, seed=4, v_sigma=0.05),
+    "key_ties": lambda: _with_ties(inputs.two_species_field(n_dm=1500, n_gas=1500, n_halo=4, seed=16)),
 }
+
+
+def _with_ties(ic):
+    """Exactly equal Morton keys: coincident particles (gas on gas, dark
+    matter on gas, dark matter on dark matter) and a group sharing one key
+    cell, so that the stable sort's tie order (by caller index) decides the
+    permutation."""
+    for k in ("x", "y", "z"):
+        ic[k] = ic[k].copy()
+        ic[k][100:140] = ic[k][0:40]
+        ic[k][1500:1530] = ic[k][200:230]
+        ic[k][1600:1610] = ic[k][1700:1710]
+        # 16 particles within 1e-9 of particle 300: the same 21-bit cell
+        ic[k][2000:2016] = ic[k][300] + 1e-9 * np.arange(16)
+    return ic
 
 
 @pytest.fixture(scope="module")
@@ -46,7 +62,7 @@ def orc_mod():
     return oracle
 
 
-@pytest.mark.parametrize("case", ["evrard4096", "field2x3000", "ragged777"])
+@pytest.mark.parametrize("case", ["evrard4096", "field2x3000", "ragged777", "key_ties"])
 @pytest.mark.parametrize("leaf,group", [(16, 64), (8, 32), (1, 8)])
 def test_keys_perm_topology_groups_bit_exact(orc_mod, case, leaf, group):
     _say(f"[tree] case={case} leaf={leaf} group={group}")
