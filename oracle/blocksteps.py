@@ -194,7 +194,7 @@ class BlockSteps:
         if self.wake and self.n_gas and self.prm.hydro and not self.common:
             gx = slice(0, self.n_gas)
             off, nb = O.neighbours(1, self.st["x"][gx], self.st["y"][gx], self.st["z"][gx], self.out["h"][gx],
-                                   self.n_gas)
+                                   self.n_gas, period=self.prm.period)
             newlen = cur.copy()
             w = np.full(self.n, np.iinfo(np.int64).max)
             for i in range(self.n_gas):
@@ -258,6 +258,10 @@ class BlockSteps:
         st["x"] += d * v[:, 0]
         st["y"] += d * v[:, 1]
         st["z"] += d * v[:, 2]
+        L = self.prm.period
+        if L > 0.0:  # back into the periodic box (Sect. 4.3)
+            for k in ("x", "y", "z"):
+                st[k] = st[k] - L * np.floor(st[k] / L)
 
         def factor(dv):
             f = 1.0 + (d / 3.0) * dv

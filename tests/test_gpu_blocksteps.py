@@ -7,7 +7,8 @@ against the oracle's block-step driver, event by event:
 * a point blast on a cold lattice, where the wake-up shortens the steps of
   the blast's neighbours;
 * with every particle in the largest step the run is the global
-  kick-drift-kick run of the same step, bit for bit.
+  kick-drift-kick run of the same step, bit for bit;
+* a periodic box (Sect. 4.3) with a flow across the faces.
 """
 import sys
 
@@ -101,6 +102,28 @@ def test_block_steps_wakeup_blast(O, BS):
     gp = gpu_params(gravity=0, nnei=40, h_tol=1e-12, leaf_size=8)
     ob = _lockstep(O, BS, ic, gp, 0.05, 14, 4, 30)
     assert ob.woken > 0
+
+
+def test_block_steps_periodic_box(O, BS):
+    _say("[blocks] periodic box, flow across the faces, 5 levels")
+    L, n = 1.0, 1500
+    ic = inputs.random_cloud(n, seed=45, masses=(1.0, 4.0), n_gas=n // 2, v_sigma=0.2)
+    rng = np.random.default_rng(45)
+    pos = rng.uniform(0.0, L, (n, 3))
+    pos[: n // 5] = np.mod(0.06 * rng.standard_normal((n // 5, 3)), L)  # a clump across a corner
+    ic["x"], ic["y"], ic["z"] = pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy()
+    ic["vx"] = ic["vx"] + 3.0
+    gp = gpu_params(nnei=40, h_tol=1e-12, leaf_size=8, period=L)
+    op = oracle_params(O, gp)
+    o0 = O.compute_forces(ic, op)
+    # not a power of two times the smallest criterion: that particle would
+    # sit exactly on a bin boundary, where one rounding decides its bin
+    dt_max = 16.3 * O.timestep(op, ic, o0, gp.eta_dt)
+    ob = _lockstep(O, BS, ic, gp, dt_max, 5, 4, 10)
+    lev = ob.L - np.log2(ob.t1 - ob.t0).astype(int)
+    assert len(set(lev)) >= 2
+    for k in ("x", "y", "z"):
+        assert np.all((ob.st[k] >= 0.0) & (ob.st[k] < L))
 
 
 def test_single_bin_equals_global_steps(O):

@@ -63,7 +63,8 @@ def _global_loop(orc, ic, prm, dt_max, L, events, eta_dt=0.1, alpha=None, alpha_
                       alpha_min=prm.alpha_min, alpha_u=st.get("alpha_u", z.copy()),
                       dalpha_u=o["dalpha_u"] if alpha_u is not None else z, alpha_u_min=prm.alpha_u_min)
         xs = (o["xsph_x"], o["xsph_y"], o["xsph_z"]) if prm.xsph_eta > 0 else None
-        orc.kick_drift(st, dt, 0, (o["ax"], o["ay"], o["az"]), o["dudt"], pred, lengths, xsph=xs, alphas=sw)
+        orc.kick_drift(st, dt, 0, (o["ax"], o["ay"], o["az"]), o["dudt"], pred, lengths, xsph=xs, alphas=sw,
+                       period=prm.period)
         o = orc.compute_forces(st, prm, h_in=lengths["h"], eps_in=lengths["eps"],
                                vel=(pred["vx"], pred["vy"], pred["vz"]), u=pred["u"],
                                alpha=st.get("alpha"), alpha_u=st.get("alpha_u"))
@@ -75,12 +76,19 @@ def _global_loop(orc, ic, prm, dt_max, L, events, eta_dt=0.1, alpha=None, alpha_
     return st, o
 
 
-@pytest.mark.parametrize("case", ["plain", "switches"])
+@pytest.mark.parametrize("case", ["plain", "switches", "periodic"])
 def test_common_bin_equals_global_loop(orc, blk, case):
     ic = inputs.evrard(300, seed=21, v_sigma=0.05)
     kw = dict(gravity=1, hydro=1, nnei=40, h_tol=1e-12, leaf_size=8)
     if case == "switches":
         kw.update(alpha_switch=1, conduction=1, balsara=1, xsph_eta=0.25, alpha_min=0.05)
+    if case == "periodic":
+        # the sphere in a box of side 2.5 with a bulk flow across the faces
+        L = 2.5
+        for k in ("x", "y", "z"):
+            ic[k] = np.mod(ic[k] + 1.2, L)
+        ic["vx"] = ic["vx"] + 40.0
+        kw.update(period=L)
     prm = orc.params(**kw)
     L, events = 6, 5
     o0 = orc.compute_forces(ic, prm)
@@ -103,6 +111,12 @@ def test_common_bin_equals_global_loop(orc, blk, case):
     assert np.array_equal(b.vs[:, 0], st["vx"]) and np.array_equal(b.vs[:, 2], st["vz"])
     assert np.array_equal(b.us, st["u"])
     assert np.array_equal(b.out["h"], o["h"]) and np.array_equal(b.out["ax"], o["ax"])
+    if case == "periodic":
+        # wrapped into the box, and the flow has carried particles across x = L
+        Lb = kw["period"]
+        for k in ("x", "y", "z"):
+            assert np.all((b.st[k] >= 0.0) & (b.st[k] < Lb)), k
+        assert np.sum(b.st["x"] < ic["x"]) > 10
     if case == "switches":
         # the dissipation coefficients carry the opening kick of the next step
         dt = b.step_dt(b.t1 - b.t0)
