@@ -126,12 +126,16 @@ class Resident:
             self.sim.compute_forces()  # cold start: lengths and forces of the initial state
         else:
             # the state and the context's carry to the next step: the
-            # simulation continues exactly where it left the device
+            # simulation continues exactly where it left the device.  The
+            # copies come from pinned memory without waiting: they are
+            # ordered on the current stream after the eviction's copies out,
+            # and the step's stream waits for the current stream.
             src = dict(self.saved, n=self.n, n_gas=int(self.ic["n_gas"]))
-            self.sim = tsph.Simulation(src, self.params, want_pot=False, ctx=shell.ctx, bufs=shell.bufs)
+            self.sim = tsph.Simulation(src, self.params, want_pot=False, ctx=shell.ctx, bufs=shell.bufs, fill=False)
             for k in HOST_KEYS:
-                self.sim.a[k].copy_(self.saved[k])
-            self.sim.load_carry(self.saved["carry"])
+                self.sim.a[k].copy_(self.saved[k], non_blocking=True)
+            carry = self.saved["carry"].to(self.sim.a["x"].device, non_blocking=True)
+            tsph.tsph_carry_load(shell.ctx, self.n, carry.data_ptr())
         self.shell = shell
         g = shell.graphs.get(self.sid) if capture_stream is not None else None
         if g is None and capture_stream is not None:
@@ -154,25 +158,38 @@ class Resident:
             self.sim.device_step(stream)
 
     def evict(self) -> Shell:
-        """Moves the state to pinned host memory and hands back the shell."""
+        """Moves the state and the carry to pinned host memory (copies
+        ordered on the current stream, not waited for) and hands back the
+        shell.  The simulation is idle: its device flags were read when its
+        last request completed."""
         import torch
         if self.saved is None:
             self.saved = {k: torch.empty(self.n, dtype=torch.float64, pin_memory=True) for k in HOST_KEYS}
+            self.saved["carry"] = torch.empty(tsph.tsph_carry_bytes(self.n) // 8, dtype=torch.float64,
+                                              pin_memory=True)
         for k in HOST_KEYS:
             self.saved[k].copy_(self.sim.a[k], non_blocking=True)
-        self.saved["carry"] = self.sim.carry()  # synchronises the stream: the copies are done too
-        # its device flags go with it, and the shell's next occupant starts clean
-        f, nc = self.sim.flags()
-        self.flag_bits |= f
-        self.noconv += nc
+        carry = torch.empty(self.saved["carry"].numel(), dtype=torch.float64, device=self.sim.a["x"].device)
+        tsph.tsph_carry_save(self.sim.ctx, self.n, carry.data_ptr())
+        self.saved["carry"].copy_(carry, non_blocking=True)
         shell = self.shell
         self.sim.close()  # borrowed context: left as it is
         self.sim, self.shell, self.graph = None, None, None
         return shell
 
+    def read_flags(self):
+        """Adds the device flags the simulation's shell raised to its own."""
+        f, nc = self.sim.flags()
+        self.flag_bits |= f
+        self.noconv += nc
+
     def host(self, k):
         """Host copy of array k of the state, resident or not."""
-        return self.sim.host(k) if self.sim is not None else self.saved[k].numpy().copy()
+        if self.sim is not None:
+            return self.sim.host(k)
+        import torch
+        torch.cuda.synchronize()  # the eviction's copies out are not waited for
+        return self.saved[k].numpy().copy()
 
 
 class Server:
@@ -213,7 +230,15 @@ class Server:
         if shell is None:
             need = Shell.bytes_for(cap, self.params)
             if self.budget is not None:
-                while self.shell_bytes + need > self.budget:
+                # an idle simulation of the same capacity class gives up its
+                # shell directly (no context destroyed and made again)
+                same = [x for x in self.res if x.sim is not None and not x.busy and x.shell.cap == cap]
+                if same and self.shell_bytes + need > self.budget:
+                    v = min(same, key=lambda x: x.last_use)
+                    shell = v.evict()
+                    shell.last_use = now
+                    self.evictions += 1
+                while shell is None and self.shell_bytes + need > self.budget:
                     if self._drop_pooled():
                         continue
                     idle = [x for x in self.res if x.sim is not None and not x.busy]
@@ -279,6 +304,7 @@ class Server:
             for ev, slot, r, a, st in inflight:
                 if ev.query():
                     t = time.perf_counter() - t0
+                    r.read_flags()  # the step is done: nothing waits
                     r.busy = False
                     r.steps += 1
                     r.last_use = t

@@ -356,7 +356,7 @@ class Simulation:
               "dudt", "rho", "pot", "alpha", "alpha_u")
 
     def __init__(self, ic: dict, params: Params | None = None, capacity: int | None = None, device: str = "cuda",
-                 want_pot: bool = True, eps_const=None, members=None, ctx=None, bufs=None):
+                 want_pot: bool = True, eps_const=None, members=None, ctx=None, bufs=None, fill: bool = True):
         import torch
         self.torch = torch
         self.n = int(ic["n"])
@@ -375,8 +375,13 @@ class Simulation:
         if bufs is not None:
             if ctx is None:
                 raise ValueError("bufs need the context they belong to")
-            t = lambda a, k: bufs[k][:n].copy_(torch.as_tensor(a, dtype=torch.float64), non_blocking=False)
-            z = lambda k: bufs[k][:n].zero_()
+            if fill:
+                t = lambda a, k: bufs[k][:n].copy_(torch.as_tensor(a, dtype=torch.float64), non_blocking=False)
+                z = lambda k: bufs[k][:n].zero_()
+            else:
+                # bind the buffers as they are: the caller restores the state
+                t = lambda a, k: bufs[k][:n]
+                z = lambda k: bufs[k][:n]
         else:
             t = lambda a, k: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
             z = lambda k: torch.zeros(n, dtype=torch.float64, device=dev)
@@ -384,14 +389,20 @@ class Simulation:
         for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u"):
             self.a[k] = t(ic[k], k)
         for k, src in (("vpx", "vx"), ("vpy", "vy"), ("vpz", "vz"), ("up", "u")):
-            self.a[k] = bufs[k][:n].copy_(self.a[src]) if bufs is not None else self.a[src].clone()
+            if bufs is not None:
+                self.a[k] = bufs[k][:n].copy_(self.a[src]) if fill else bufs[k][:n]
+            else:
+                self.a[k] = self.a[src].clone()
         self.a["h"] = z("h")
         self.a["eps"] = z("eps") if eps_const is None else t(eps_const, "eps")
         for k in ("ax", "ay", "az", "dudt", "rho"):
             self.a[k] = z(k)
         # dissipation coefficients: alpha from the parameters, alpha_u zero,
         # unless the initial conditions give them
-        self.a["alpha"] = t(ic["alpha"], "alpha") if "alpha" in ic else z("alpha").fill_(self.params.alpha)
+        if "alpha" in ic:
+            self.a["alpha"] = t(ic["alpha"], "alpha")
+        else:
+            self.a["alpha"] = z("alpha").fill_(self.params.alpha) if fill else z("alpha")
         self.a["alpha_u"] = t(ic["alpha_u"], "alpha_u") if "alpha_u" in ic else z("alpha_u")
         self.a["pot"] = z("pot") if want_pot else None
         self.owns_ctx = ctx is None

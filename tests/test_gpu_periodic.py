@@ -74,6 +74,12 @@ def test_periodic_forces_match_oracle(O, form):
     assert np.array_equal(g["cnt_node"], o["cnt_node"])
     assert np.array_equal(g["cnt_pair"], o["cnt_pair"])
     assert np.array_equal(g["cnt_sph"], o["cnt_sph"])
+    # the time-step inputs across the faces: divergences and max |mu|
+    for k in ("divv", "divv_eps"):
+        sel = gas if k == "divv" else np.ones(ic["n"], bool)
+        assert np.allclose(g[k][sel], o[k][sel], rtol=1e-9, atol=1e-12 * np.abs(o[k]).max()), k
+    mu_rtol = 1e-9 if form == "fp64" else 5e-6
+    assert np.allclose(g["maxmu"][gas], o["maxmu"][gas], rtol=mu_rtol, atol=1e-14)
     # the replicas matter: the open box differs by far more
     oo = O.compute_forces(ic, oracle_params(O, gpu_params(nnei=40, h_tol=1e-12, leaf_size=8)))
     assert relrms(acc(oo), acc(o)) > 1e3 * max(e, 1e-12)
