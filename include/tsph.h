@@ -396,6 +396,14 @@ tsph_status tsph_diagnostics(void *ctx, const tsph_state *s, double *out_device,
  * copies and the clearing are ordered on the context's last stream, and the
  * call waits for that stream only (not for the whole device). */
 tsph_status tsph_read_flags(void *ctx, uint32_t *flags, int64_t *n_noconv);
+/* The same flag bits and unconverged count without waiting: dst[0] receives
+ * the flag word and dst[1] the count (uint32 each), then both are cleared,
+ * all ordered on `stream`.  dst is device memory or pinned host memory that
+ * the caller reads once the stream has passed this point.  For callers that
+ * must not block, such as a serving loop moving a simulation off the device;
+ * the stream must follow the work whose flags are taken (or that work must
+ * be complete).  TSPH_EINVAL for a NULL dst. */
+tsph_status tsph_take_flags_async(void *ctx, uint32_t *dst, void *stream);
 
 /* Per-phase timing with HIP events recorded on the stream of each
  * tsph_compute_forces call: phase 0 tree build, 1 length solves and

@@ -671,6 +671,19 @@ tsph_status tsph_read_flags(void *ctx, uint32_t *flags, int64_t *n_noconv) {
   return TSPH_OK;
 }
 
+tsph_status tsph_take_flags_async(void *ctx, uint32_t *dst, void *stream) {
+  Ctx *c = (Ctx *)ctx;
+  if (!c) return TSPH_EINVAL;
+  if (!dst) return set_err(c, TSPH_EINVAL, "dst is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(dst, c->flags, 4, hipMemcpyDefault, st));
+  TSPH_HIP_CHECK(c, hipMemcpyAsync(dst + 1, c->noconv, 4, hipMemcpyDefault, st));
+  TSPH_HIP_CHECK(c, hipMemsetAsync(c->flags, 0, 4, st));
+  TSPH_HIP_CHECK(c, hipMemsetAsync(c->noconv, 0, 4, st));
+  return TSPH_OK;
+}
+
 tsph_status tsph_debug_lists(void *ctx, int32_t max_per_particle) {
   Ctx *c = (Ctx *)ctx;
   if (!c || max_per_particle < 0) return TSPH_EINVAL;

@@ -109,6 +109,7 @@ class Resident:
         self.last_use = 0.0
         self.flag_bits = 0       # device flags raised while it was resident in earlier shells
         self.noconv = 0
+        self.flag_words = []     # pinned (flags, unconverged) taken at evictions, not read yet
 
     @property
     def n(self) -> int:
@@ -158,10 +159,10 @@ class Resident:
             self.sim.device_step(stream)
 
     def evict(self) -> Shell:
-        """Moves the state and the carry to pinned host memory (copies
-        ordered on the current stream, not waited for) and hands back the
-        shell.  The simulation is idle: its device flags were read when its
-        last request completed."""
+        """Moves the state, the carry and the device flags to pinned host
+        memory (copies ordered on the current stream, not waited for: the
+        simulation is idle, its last step complete) and hands back the
+        shell, whose flags start clean for the next occupant."""
         import torch
         if self.saved is None:
             self.saved = {k: torch.empty(self.n, dtype=torch.float64, pin_memory=True) for k in HOST_KEYS}
@@ -172,16 +173,21 @@ class Resident:
         carry = torch.empty(self.saved["carry"].numel(), dtype=torch.float64, device=self.sim.a["x"].device)
         tsph.tsph_carry_save(self.sim.ctx, self.n, carry.data_ptr())
         self.saved["carry"].copy_(carry, non_blocking=True)
+        words = torch.zeros(2, dtype=torch.int32, pin_memory=True)
+        tsph.tsph_take_flags_async(self.sim.ctx, words.data_ptr())
+        self.flag_words.append(words)
         shell = self.shell
         self.sim.close()  # borrowed context: left as it is
         self.sim, self.shell, self.graph = None, None, None
         return shell
 
-    def read_flags(self):
-        """Adds the device flags the simulation's shell raised to its own."""
-        f, nc = self.sim.flags()
-        self.flag_bits |= f
-        self.noconv += nc
+    def harvest_flags(self):
+        """Adds the flags taken at evictions to its own (after the device
+        has passed those copies)."""
+        for w in self.flag_words:
+            self.flag_bits |= int(w[0]) & 0xffffffff
+            self.noconv += int(w[1])
+        self.flag_words = []
 
     def host(self, k):
         """Host copy of array k of the state, resident or not."""
@@ -304,7 +310,6 @@ class Server:
             for ev, slot, r, a, st in inflight:
                 if ev.query():
                     t = time.perf_counter() - t0
-                    r.read_flags()  # the step is done: nothing waits
                     r.busy = False
                     r.steps += 1
                     r.last_use = t
@@ -345,8 +350,10 @@ class Server:
         """(sid, (flag bits, unconverged solves)) of every simulation since
         the previous call: what its shells raised while it was resident,
         including earlier residencies."""
+        self.torch.cuda.synchronize()  # the evictions' flag copies are done
         out = []
         for r in self.res:
+            r.harvest_flags()
             f, nc = r.sim.flags() if r.sim is not None else (0, 0)
             out.append((r.sid, (r.flag_bits | f, r.noconv + nc)))
             r.flag_bits, r.noconv = 0, 0

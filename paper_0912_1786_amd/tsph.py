@@ -103,6 +103,7 @@ def lib():
             "tsph_timestep": ([_P, S, _P, _P], C.c_int),
             "tsph_diagnostics": ([_P, S, _P, _P], C.c_int),
             "tsph_read_flags": ([_P, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)], C.c_int),
+            "tsph_take_flags_async": ([_P, _P, _P], C.c_int),
             "tsph_debug_lists": ([_P, C.c_int32], C.c_int),
             "tsph_timing": ([_P, C.c_int32], C.c_int),
             "tsph_phase_times": ([_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
@@ -135,7 +136,7 @@ EXPORTED = ("tsph_create", "tsph_destroy", "tsph_set_params", "tsph_default_para
             "tsph_carry_save", "tsph_carry_load", "tsph_timestep", "tsph_diagnostics", "tsph_read_flags", "tsph_debug_lists", "tsph_debug_export", "tsph_last_error", "tsph_version",
             "tsph_timing", "tsph_phase_times", "tsph_probe", "tsph_debug_handoff_cap", "tsph_source_id",
             "tsph_diagnostics_noalloc", "tsph_noalloc_last_error", "tsph_batch_step", "tsph_block_start",
-            "tsph_block_advance")
+            "tsph_block_advance", "tsph_take_flags_async")
 PHASES = ("tree", "density", "gravity", "sph", "finish")
 
 
@@ -273,6 +274,12 @@ def tsph_read_flags(ctx):
     nc = C.c_int64(0)
     _check("tsph_read_flags", lib().tsph_read_flags(ctx, C.byref(f), C.byref(nc)), ctx)
     return int(f.value), int(nc.value)
+
+
+def tsph_take_flags_async(ctx, dst_ptr: int, stream=None):
+    """Flag word and unconverged count (two uint32) to dst_ptr, then cleared,
+    on the stream, without waiting."""
+    _check("tsph_take_flags_async", lib().tsph_take_flags_async(ctx, C.c_void_p(dst_ptr), _stream(stream)), ctx)
 
 
 def tsph_timing(ctx, enable: bool):

@@ -480,3 +480,30 @@ def test_unsolvable_lengths_are_flagged():
     flags, noconv = sim.flags()
     sim.close()
     assert flags & tsph.FLAG_NOCONV and noconv > 0
+
+
+def test_flags_taken_without_waiting():
+    """tsph_take_flags_async copies the flag word and the unconverged count to
+    pinned or device memory on the stream and clears them: once the stream
+    has passed, the words hold what tsph_read_flags would have returned, and
+    a following tsph_read_flags sees nothing."""
+    ic = inputs.evrard(3, seed=15)
+    sim = tsph.Simulation(ic, gpu_params())
+    try:
+        sim.compute_forces()
+        w = torch.zeros(2, dtype=torch.int32, pin_memory=True)
+        tsph.tsph_take_flags_async(sim.ctx, w.data_ptr())
+        torch.cuda.synchronize()
+        assert int(w[0]) & tsph.FLAG_NOCONV and int(w[1]) > 0
+        assert sim.flags() == (0, 0)
+        sim.compute_forces()
+        d = torch.zeros(2, dtype=torch.int32, device="cuda")
+        tsph.tsph_take_flags_async(sim.ctx, d.data_ptr())
+        h = d.cpu()
+        assert int(h[0]) & tsph.FLAG_NOCONV and int(h[1]) > 0
+        assert sim.flags() == (0, 0)
+        with pytest.raises(tsph.TsphError) as e:
+            tsph.tsph_take_flags_async(sim.ctx, 0)
+        assert e.value.status == tsph.TSPH_EINVAL
+    finally:
+        sim.close()
