@@ -324,6 +324,54 @@ def row_c5(requests: int = 400) -> dict:
     return out
 
 
+def row_f1(torch, tsph, nps: int = 1 << 20, events: int = 48, span: int = 64, seed: int = 1) -> dict:
+    """Individual power-of-two time-steps on the 2M field (FP32 bulk): the
+    largest step `span` times the global step of the first force pass, ten
+    levels below it, wake-up factor 4.  Reports the simulated time advanced
+    per wall second against the global-step loop at the global step."""
+    from paper_0912_1786_amd import inputs
+    ic = inputs.two_species_field(n_dm=nps, n_gas=nps, n_halo=64, seed=seed)
+    prm = tsph.tsph_default_params(nnei=60, precision=tsph.FP32_BULK)
+    sim = tsph.Simulation(ic, prm, want_pot=False)
+    try:
+        sim.compute_forces()
+        dt = sim.timestep()
+        for _ in range(2):
+            sim.step(dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            sim.step(dt)
+        torch.cuda.synchronize()
+        global_ms = (time.perf_counter() - t0) * 1e3 / 3
+    finally:
+        sim.close()
+    levels = 10
+    sim = tsph.Simulation(ic, prm, want_pot=False)
+    try:
+        sim.block_start(span * dt, levels, 4)
+        active = woken = 0
+        ticks = prev = 0  # system time in ticks, counted across synchronisation points (t = 0)
+        t0 = time.perf_counter()
+        for _ in range(events):
+            t, nact, nw = sim.block_advance()
+            active += nact
+            woken += nw
+            ticks += (t - prev) if t > prev else (1 << levels) - prev + t
+            prev = t
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        flags, noconv = sim.flags()
+    finally:
+        sim.close()
+    advanced = ticks * span / (1 << levels)  # in global steps
+    return {"workload": "two_species_field_2M_individual_steps", "precision": "fp32_bulk", "largest_step_over_global": span,
+            "levels": levels, "wake": 4, "events": events, "active_particle_steps": active, "woken": woken,
+            "wall_ms": round(wall_ms, 1), "ms_per_event": round(wall_ms / events, 2),
+            "advanced_in_global_steps": advanced, "ms_per_global_step_equivalent": round(wall_ms / advanced, 2),
+            "global_step_ms": round(global_ms, 2), "speedup_in_simulated_time": round(global_ms * advanced / wall_ms, 2),
+            "device_flags": flags, "noconv": noconv}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -399,7 +447,8 @@ def main():
             obuild = "gcc -O2 -fopenmp -ffp-contract=off (native build failed)"
     if not args.no_rows:
         rows = {}
-        for name, fn in (("c1", lambda: row_c1(torch, tsph, O)), ("c2", row_c2), ("c4", row_c4), ("c5", row_c5)):
+        for name, fn in (("c1", lambda: row_c1(torch, tsph, O)), ("c2", row_c2), ("c4", row_c4), ("c5", row_c5),
+                         ("f1", lambda: row_f1(torch, tsph, nps=args.nps))):
             t1 = time.time()
             log(f"[bench] row {name} ...")
             try:
