@@ -128,7 +128,7 @@ struct SphLane {
   double xsx, xsy, xsz; // X-SPH sum (without eta); the curl sum in mode 1
   double lapu;          // Laplacian of u (conduction)
   double4 e2;           // alpha, alpha_u, Balsara factor, u
-  int bm, bw;           // mode 2: shortest step around, shortest active step around
+  int bm, bw;           // mode 2: shortest step around; the sink's own step
   int p, npair, ndbg;
   bool sink;
   int32_t *dbg;
@@ -158,8 +158,11 @@ __device__ __forceinline__ void sph_lane(const SphArgs &A, SphLane &L, int p, bo
 // tests of the whole tile first, then the lane's own pairs in tile order.
 // kMode 0: forces and heating; kMode 1: the velocity curl sum
 // sum_j v_ij x grad_i W_ij(h_i) (plain kernel gradient) in xsx, xsy, xsz;
-// kMode 2: the least step length among the neighbours, and among the
-// active neighbours (coincident ones included).
+// kMode 2 (active sinks only): the least step length among the sink's
+// neighbours, and the sink's own step scattered as a minimum to each of
+// them (coincident ones included).  The pair test is symmetric in i and j,
+// so a particle's minimum over its active neighbours is complete once every
+// active sink has been walked; integer minima make it independent of order.
 template <int kMode, bool kFull>
 __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const SphTile &T, int nt, bool tc) {
   const double hi = L.hd.x;
@@ -181,9 +184,8 @@ __device__ __forceinline__ void tile_pairs(const SphArgs &A, SphLane &L, const S
     const int q = T.q[j];
     if (q == L.p) continue;  // the sink itself
     if constexpr (kMode == 2) {
-      const int cq = A.bcur_s[q];
-      L.bm = min(L.bm, cq);
-      if (A.act[q]) L.bw = min(L.bw, cq);
+      L.bm = min(L.bm, A.bcur_s[q]);
+      atomicMin(A.bw + A.perm[q], L.bw);
       continue;
     }
     const SphRec b = A.srec[q];
@@ -524,10 +526,14 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
       const bool act = c0 + ln < ngs;
       const int p = act ? s_gs[ln] : bt.first;
       SphLane L;
-      // the force pass of individual time-steps evaluates active sinks only
-      sph_lane<kFull>(A, L, p, act && (!force_mode(kMode) || !A.act || A.act[p]));
+      // the force and wake-up passes of individual time-steps take active
+      // sinks only
+      sph_lane<kFull>(A, L, p, act && ((!force_mode(kMode) && kMode != 2) || !A.act || A.act[p]));
       if (ballot(L.sink) == 0) continue;
-      if (kMode == 2) L.dbg = nullptr;
+      if (kMode == 2) {
+        L.dbg = nullptr;
+        if (L.sink) L.bw = A.bcur_s[p];
+      }
       const double hi = L.hd.x;
       int done = 0;  // candidates evaluated by this wave
       int sp = 1, nleaf = 0;
@@ -628,10 +634,7 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
         const double2 al = A.av[p];
         A.srec2[p] = make_double4(A.alpha_switch ? al.x : A.alpha, al.y, fb, L.v.w);
       }
-      if (kMode == 2 && L.sink) {
-        A.bm[A.perm[p]] = L.bm;
-        A.bw[A.perm[p]] = L.bw;
-      }
+      if (kMode == 2 && L.sink) A.bm[A.perm[p]] = L.bm;
       if (force_mode(kMode) && L.sink) {
         A.acc[0 * A.cap_n + p] += L.ax;
         A.acc[1 * A.cap_n + p] += L.ay;
@@ -754,6 +757,11 @@ __global__ __launch_bounds__(256) void k_gather_alpha(int64_t n, const int32_t *
 }
 
 // zero k work-queue counters (the curl pass used the SPH walk's queues)
+__global__ __launch_bounds__(256) void k_wake_clear(int64_t n, int32_t *__restrict__ bw) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bw[i] = INT32_MAX;
+}
+
 __global__ void k_reset_counter(int32_t *ctr, int k) {
   if ((int)threadIdx.x < k) ctr[threadIdx.x] = 0;
 }
@@ -898,14 +906,22 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
   return TSPH_OK;
 }
 
-// Wake-up sums of the individual time-steps: for every gas particle the least
-// current step length among its SPH neighbours and among the active ones.
+// Wake-up minima of the individual time-steps: for every active gas particle
+// the least current step length among its SPH neighbours (bm), and for every
+// gas particle the least step among its active neighbours (bw), both walked
+// from the active particles alone.
 tsph_status tsph_impl_wake(Ctx *c, hipStream_t st) {
   if (!c->p.hydro || c->n_gas == 0) return TSPH_OK;
+  // the active flags in key order (the opening force pass of the steps
+  // gathers none: all particles are active then)
+  tsph_status r = tsph_impl_gather_active(c, st);
+  if (r != TSPH_OK) return r;
   SphArgs A = sph_args(c);
   A.act = c->bact_s;
   A.dbg = nullptr;
   A.split_particles = 0;
+  hipLaunchKernelGGL(k_wake_clear, dim3(blocks_for(c->n_gas, 256, 1 << 16)), dim3(256), 0, st, (int64_t)c->n_gas,
+                     A.bw);
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, A.work + 24, 8);
   launch_sph<2, false>(c, A, st);
   TSPH_HIP_CHECK(c, hipGetLastError());
