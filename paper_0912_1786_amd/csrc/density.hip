@@ -89,10 +89,11 @@ struct Sums {
 // of being opened.
 template <class V>
 __device__ bool walk_leaves(const DensArgs &A, int root, const NodeBox &gb, double R, bool gas_only, int *s_stack,
-                            int *s_leaf, const double4 *s_snk, int batch, V &&visit, bool whole = false) {
+                            int *s_leaf, double4 *s_snk, int batch, V &&visit, bool whole = false) {
   const int ln = lane();
   int nleaf = 0, sp = 1, rounds = 0;
   const int guard = *A.nnodes + 2;
+  if (!(A.L > 0.0)) stage_ball_groups(s_snk, s_snk[ln]);
   if (ln == 0) s_stack[0] = root;
   __syncthreads();
   const double R2 = R * R;
@@ -330,7 +331,7 @@ struct Cands {
 };
 
 __device__ Cands gather(const DensArgs &A, int root, const NodeBox &gb, double R, bool gas_only, int *s_stack, int *s_leaf,
-                        const double4 *s_snk, bool &fail, bool whole = false, int leaf_cap = kDensLeafCap) {
+                        double4 *s_snk, bool &fail, bool whole = false, int leaf_cap = kDensLeafCap) {
   Cands c{0, true, R, gas_only};
   bool full = false;
   bool ok = walk_leaves(A, root, gb, R, gas_only, s_stack, s_leaf, s_snk, leaf_cap - kWave,
@@ -354,7 +355,7 @@ __device__ Cands gather(const DensArgs &A, int root, const NodeBox &gb, double R
 
 template <bool kFull>
 __device__ Sums pass(const DensArgs &A, int root, const NodeBox &gb, const Cands &c, int *s_stack, int *s_leaf,
-                     DensTile &T, const double4 *s_snk, double px, double py, double pz, const double4 &vp, double h,
+                     DensTile &T, double4 *s_snk, double px, double py, double pz, const double4 &vp, double h,
                      bool want_div, bool want_phi, int32_t *dbg_row, int &ndbg, bool &fail) {
   Sums s{0, 0, 0, 0, 0, 0};
   ndbg = 0;
@@ -971,7 +972,7 @@ __global__ __launch_bounds__(64, 3) void k_density(DensArgs A) {
   if constexpr (!kPer) A.L = 0.0;
   __shared__ int s_stack[kDensStackCap];
   __shared__ int s_leaf[kDensLeafCap];
-  __shared__ double4 s_snk[kWave];
+  __shared__ double4 s_snk[kSnkRecs];
   __shared__ DensTile s_dt;
   __shared__ int s_g;
   const int ln = lane();
@@ -1442,7 +1443,7 @@ __global__ __launch_bounds__(1024) void k_heavy_order(DensArgs A) {
 __global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
   __shared__ int s_stack[kDensStackCap];
   __shared__ int s_leaf[kDensSinkLeafCap];
-  __shared__ double4 s_snk[kWave];
+  __shared__ double4 s_snk[kSnkRecs];
   __shared__ int s_t;
   const int ln = lane();
   const int nslot = min(A.work[6], A.heavy_cap);

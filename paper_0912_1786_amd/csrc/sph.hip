@@ -502,7 +502,7 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
   if constexpr (!kPer) A.L = 0.0;
   __shared__ int s_stack[kSStackCap];
   __shared__ int s_leaf[kSListCap];
-  __shared__ double4 s_snk[kWave];
+  __shared__ double4 s_snk[kSnkRecs];
   __shared__ SphTile s_t;
   __shared__ int s_g;
   __shared__ int s_gs[kWave];
@@ -541,7 +541,9 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
       int rounds = 0;
       const int guard = *A.nnodes + 2;
       if (ln == 0) s_stack[0] = bt.root;
-      s_snk[ln] = make_double4(L.a.x, L.a.y, L.a.z, L.sink ? 2.0 * hi : 0.0);
+      const double4 ball = make_double4(L.a.x, L.a.y, L.a.z, L.sink ? 2.0 * hi : 0.0);
+      s_snk[ln] = ball;
+      if constexpr (!kPer) stage_ball_groups(s_snk, ball);
       __syncthreads();
       for (;;) {
         if (sp > 0 && ++rounds > guard) {

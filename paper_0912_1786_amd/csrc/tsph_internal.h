@@ -539,14 +539,49 @@ __device__ __forceinline__ double dist2_pair(double xi, double yi, double zi, do
   return s;
 }
 
-// Does some sink ball of the wave reach the box?  snk[s] = (x, y, z, R_s)
-// staged in LDS (R_s = 0 for lanes without a ball); the ball radius used for
-// sink s is max(R_s, r_node).  Every lane tests its own box against all
+// Sink balls staged in LDS for the walk pruning: snk[s] = (x, y, z, R_s) for
+// lane s (R_s <= 0: no ball), then one pair of records per group of eight
+// consecutive lanes, snk[kWave + 2g] = (lowest x, y, z, largest R_s) and
+// snk[kWave + 2g + 1] = (highest x, y, z, 0) over the group's balls (a group
+// without a ball has largest radius -1).
+constexpr int kBallGroups = kWave / 8;
+constexpr int kSnkRecs = kWave + 2 * kBallGroups;
+
+// Writes the group records from each lane's own ball b.  The whole wave
+// calls it; the records are read after the caller's next barrier.
+__device__ __forceinline__ void stage_ball_groups(double4 *snk, const double4 &b) {
+  const bool on = b.w > 0.0;
+  double lx = on ? b.x : INFINITY, ly = on ? b.y : INFINITY, lz = on ? b.z : INFINITY;
+  double hx = on ? b.x : -INFINITY, hy = on ? b.y : -INFINITY, hz = on ? b.z : -INFINITY;
+  double w = on ? b.w : -1.0;
+  for (int o = 1; o < 8; o <<= 1) {
+    lx = fmin(lx, __shfl_xor(lx, o, kWave));
+    ly = fmin(ly, __shfl_xor(ly, o, kWave));
+    lz = fmin(lz, __shfl_xor(lz, o, kWave));
+    hx = fmax(hx, __shfl_xor(hx, o, kWave));
+    hy = fmax(hy, __shfl_xor(hy, o, kWave));
+    hz = fmax(hz, __shfl_xor(hz, o, kWave));
+    w = fmax(w, __shfl_xor(w, o, kWave));
+  }
+  const int ln = __lane_id();
+  if ((ln & 7) == 0) {
+    snk[kWave + 2 * (ln >> 3)] = make_double4(lx, ly, lz, w);
+    snk[kWave + 2 * (ln >> 3) + 1] = make_double4(hx, hy, hz, 0.0);
+  }
+}
+
+// Does some sink ball of the wave reach the box?  The ball radius used for
+// sink s is max(R_s, r_node).  Every lane tests its own box against the
 // staged sinks (broadcast reads); the loop stops once every lane that still
 // needs an answer has one.  The test only prunes candidates (the pair tests
 // decide), so it may keep more than the exact one and never less: in the
 // open box the gaps are max(lo - p, p - hi, 0) with fused squares, against
-// a radius widened by 1e-14 relative, which covers their rounding.
+// a radius widened by 1e-14 relative, which covers their rounding.  In the
+// open box a group of eight balls is tested first, as the gap from the box
+// to the box of the group's centres against the group's largest radius: that
+// gap is at most each member's (rounding is monotone), the radius at least
+// each member's, so a group that fails holds no ball that reaches, and the
+// result equals the test of every ball.
 __device__ __forceinline__ bool balls_reach_box(const double4 *snk, double lox, double loy, double loz,
                                                 double hix, double hiy, double hiz, double r_node, bool want,
                                                 double L = 0.0) {
@@ -565,15 +600,25 @@ __device__ __forceinline__ bool balls_reach_box(const double4 *snk, double lox, 
     }
     return hit;
   }
-  for (int s = 0; s < kWave; s++) {
-    const double4 q = snk[s];
-    const double R = fmax(q.w, r_node);
-    const double R2 = q.w > 0.0 ? (R * R) * (1.0 + 1e-14) : -1.0;
-    const double dx = fmax(fmax(lox - q.x, q.x - hix), 0.0);
-    const double dy = fmax(fmax(loy - q.y, q.y - hiy), 0.0);
-    const double dz = fmax(fmax(loz - q.z, q.z - hiz), 0.0);
-    hit = hit || (fma(dz, dz, fma(dy, dy, dx * dx)) < R2);
-    if ((s & 7) == 7 && !__any(want && !hit)) break;
+  for (int g = 0; g < kBallGroups; g++) {
+    if (!__any(want && !hit)) break;
+    const double4 glo = snk[kWave + 2 * g], ghi = snk[kWave + 2 * g + 1];
+    const double Rg = fmax(glo.w, r_node);
+    const double R2g = glo.w > 0.0 ? (Rg * Rg) * (1.0 + 1e-14) : -1.0;
+    const double gx = fmax(fmax(lox - ghi.x, glo.x - hix), 0.0);
+    const double gy = fmax(fmax(loy - ghi.y, glo.y - hiy), 0.0);
+    const double gz = fmax(fmax(loz - ghi.z, glo.z - hiz), 0.0);
+    const bool need = want && !hit && fma(gz, gz, fma(gy, gy, gx * gx)) < R2g;
+    if (!__any(need)) continue;
+    for (int s = 8 * g; s < 8 * g + 8; s++) {
+      const double4 q = snk[s];
+      const double R = fmax(q.w, r_node);
+      const double R2 = q.w > 0.0 ? (R * R) * (1.0 + 1e-14) : -1.0;
+      const double dx = fmax(fmax(lox - q.x, q.x - hix), 0.0);
+      const double dy = fmax(fmax(loy - q.y, q.y - hiy), 0.0);
+      const double dz = fmax(fmax(loz - q.z, q.z - hiz), 0.0);
+      hit = hit || (need && fma(dz, dz, fma(dy, dy, dx * dx)) < R2);
+    }
   }
   return hit;
 }
