@@ -540,11 +540,12 @@ __device__ __forceinline__ double dist2_pair(double xi, double yi, double zi, do
 }
 
 // Sink balls staged in LDS for the walk pruning: snk[s] = (x, y, z, R_s) for
-// lane s (R_s <= 0: no ball), then one pair of records per group of eight
-// consecutive lanes, snk[kWave + 2g] = (lowest x, y, z, largest R_s) and
+// lane s (R_s <= 0: no ball), then one pair of records per group of
+// kBallGroupSize consecutive lanes, snk[kWave + 2g] = (lowest x, y, z, largest R_s) and
 // snk[kWave + 2g + 1] = (highest x, y, z, 0) over the group's balls (a group
 // without a ball has largest radius -1).
-constexpr int kBallGroups = kWave / 8;
+constexpr int kBallGroupSize = 8;
+constexpr int kBallGroups = kWave / kBallGroupSize;
 constexpr int kSnkRecs = kWave + 2 * kBallGroups;
 
 // Writes the group records from each lane's own ball b.  The whole wave
@@ -554,7 +555,7 @@ __device__ __forceinline__ void stage_ball_groups(double4 *snk, const double4 &b
   double lx = on ? b.x : INFINITY, ly = on ? b.y : INFINITY, lz = on ? b.z : INFINITY;
   double hx = on ? b.x : -INFINITY, hy = on ? b.y : -INFINITY, hz = on ? b.z : -INFINITY;
   double w = on ? b.w : -1.0;
-  for (int o = 1; o < 8; o <<= 1) {
+  for (int o = 1; o < kBallGroupSize; o <<= 1) {
     lx = fmin(lx, __shfl_xor(lx, o, kWave));
     ly = fmin(ly, __shfl_xor(ly, o, kWave));
     lz = fmin(lz, __shfl_xor(lz, o, kWave));
@@ -564,9 +565,9 @@ __device__ __forceinline__ void stage_ball_groups(double4 *snk, const double4 &b
     w = fmax(w, __shfl_xor(w, o, kWave));
   }
   const int ln = __lane_id();
-  if ((ln & 7) == 0) {
-    snk[kWave + 2 * (ln >> 3)] = make_double4(lx, ly, lz, w);
-    snk[kWave + 2 * (ln >> 3) + 1] = make_double4(hx, hy, hz, 0.0);
+  if (ln % kBallGroupSize == 0) {
+    snk[kWave + 2 * (ln / kBallGroupSize)] = make_double4(lx, ly, lz, w);
+    snk[kWave + 2 * (ln / kBallGroupSize) + 1] = make_double4(hx, hy, hz, 0.0);
   }
 }
 
@@ -577,7 +578,7 @@ __device__ __forceinline__ void stage_ball_groups(double4 *snk, const double4 &b
 // decide), so it may keep more than the exact one and never less: in the
 // open box the gaps are max(lo - p, p - hi, 0) with fused squares, against
 // a radius widened by 1e-14 relative, which covers their rounding.  In the
-// open box a group of eight balls is tested first, as the gap from the box
+// open box a group of balls is tested first, as the gap from the box
 // to the box of the group's centres against the group's largest radius: that
 // gap is at most each member's (rounding is monotone), the radius at least
 // each member's, so a group that fails holds no ball that reaches, and the
@@ -610,7 +611,7 @@ __device__ __forceinline__ bool balls_reach_box(const double4 *snk, double lox, 
     const double gz = fmax(fmax(loz - ghi.z, glo.z - hiz), 0.0);
     const bool need = want && !hit && fma(gz, gz, fma(gy, gy, gx * gx)) < R2g;
     if (!__any(need)) continue;
-    for (int s = 8 * g; s < 8 * g + 8; s++) {
+    for (int s = kBallGroupSize * g; s < kBallGroupSize * (g + 1); s++) {
       const double4 q = snk[s];
       const double R = fmax(q.w, r_node);
       const double R2 = q.w > 0.0 ? (R * R) * (1.0 + 1e-14) : -1.0;
