@@ -9,8 +9,8 @@
 // Time runs in integer ticks, dt_max = 2^L ticks.  The per-particle kernels
 // here are elementwise over caller order and HBM-bound; the force pass of
 // the active particles is the ordinary one with chunks of 64 sinks without
-// an active sink skipped by the gravity and SPH walks, and the wake-up sums
-// are one more SPH-neighbour walk (sph.hip, mode 2).
+// an active sink skipped by the gravity and SPH walks, and the wake-up minima
+// are one more SPH-neighbour walk over the active gas (sph.hip, mode 2).
 #include <stdio.h>
 
 #include "tsph_internal.h"
