@@ -385,11 +385,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true",
                     help="time only the 2M field (skip the Evrard, ensemble and serving configurations)")
+    ap.add_argument("--rows", default="c1,c2,c4,c5,f1",
+                    help="comma-separated rows to run besides the 2M field (c1, c2, c4, c5, f1)")
     ap.add_argument("--precision", choices=["both", "fp32_bulk", "fp64"], default="both",
                     help="arithmetic form(s) to time; with both, the FP32-bulk form is the headline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel used to calibrate the HBM byte counters")
     args = ap.parse_args()
+    want = set() if args.no_rows else {r.strip() for r in args.rows.split(",") if r.strip()}
+    unknown = want - {"c1", "c2", "c4", "c5", "f1"}
+    if unknown:
+        ap.error(f"unknown rows: {sorted(unknown)}")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this engine has no multi-GPU path (each GPU would run its own "
               "simulations); run it with --gpus 1", file=sys.stderr)
@@ -438,17 +444,19 @@ def main():
             r["measured_peak"] = mp
             r["frac_of_measured_peak"] = round(r["achieved"] / mp, 4)
     O = obuild = None
-    if not args.no_cpu_baseline or not args.no_rows:
+    if not args.no_cpu_baseline or want:
         try:
             O, obuild = load_native_oracle()
         except Exception as e:  # no compiler on the host: the portable build
             log(f"[bench] native oracle build failed ({e}); using the portable -O2 build")
             from oracle import oracle as O
             obuild = "gcc -O2 -fopenmp -ffp-contract=off (native build failed)"
-    if not args.no_rows:
+    if want:
         rows = {}
         for name, fn in (("c1", lambda: row_c1(torch, tsph, O)), ("c2", row_c2), ("c4", row_c4), ("c5", row_c5),
                          ("f1", lambda: row_f1(torch, tsph, nps=args.nps))):
+            if name not in want:
+                continue
             t1 = time.time()
             log(f"[bench] row {name} ...")
             try:
