@@ -758,12 +758,13 @@ __global__ __launch_bounds__(256) void k_gather_alpha(int64_t n, const int32_t *
   }
 }
 
-// zero k work-queue counters (the curl pass used the SPH walk's queues)
+// the wake-up pass's minima over active neighbours start at "none"
 __global__ __launch_bounds__(256) void k_wake_clear(int64_t n, int32_t *__restrict__ bw) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     bw[i] = INT32_MAX;
 }
 
+// zero k work-queue counters (the curl pass used the SPH walk's queues)
 __global__ void k_reset_counter(int32_t *ctr, int k) {
   if ((int)threadIdx.x < k) ctr[threadIdx.x] = 0;
 }
