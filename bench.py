@@ -372,6 +372,59 @@ def row_f1(torch, tsph, nps: int = 1 << 20, events: int = 48, span: int = 64, se
             "device_flags": flags, "noconv": noconv}
 
 
+def row_options(torch, tsph, ic, steps: int = 5, warmup: int = 2) -> dict:
+    """The 2M field (FP32 bulk) with each option of the scheme switched on
+    alone, timed like the headline (KDK steps on resident inputs, HIP events)
+    beside the plain form in the same row: the dissipation switches (f2), the
+    periodic box with the Ewald correction on the field folded into the unit
+    box (f3), and the scheme variants (f4)."""
+    import numpy as np
+    per = dict(ic)
+    for k in ("x", "y", "z"):
+        per[k] = np.mod(ic[k], 1.0)
+    cases = {
+        "plain": (ic, {}),
+        "f2_switches": (ic, dict(balsara=1, alpha_switch=1, conduction=1)),
+        "f3_periodic": (per, dict(period=1.0)),
+        "f3_plain_folded": (per, {}),
+        "f4_signal_viscosity": (ic, dict(visc_form=tsph.VISC_SIGNAL)),
+        "f4_entropy": (ic, dict(entropy=1)),
+        "f4_xsph": (ic, dict(xsph_eta=0.5)),
+        "f4_standard_scheme": (ic, dict(h_scheme=tsph.H_STANDARD)),
+        "f4_mass_density": (ic, dict(h_weight=tsph.HW_MASS)),
+    }
+    out = {"workload": "two_species_field_2M", "precision": "fp32_bulk", "steps": steps, "warmup": warmup}
+    for name, (c, kw) in cases.items():
+        prm = tsph.tsph_default_params(nnei=60, precision=tsph.FP32_BULK, **kw)
+        sim = tsph.Simulation(c, prm, want_pot=False)
+        try:
+            sim.compute_forces()
+            dt = sim.timestep()
+            for _ in range(warmup):
+                sim.step(dt)
+            tsph.tsph_timing(sim.ctx, True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(steps):
+                sim.step(dt)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            phases, calls = tsph.tsph_phase_times(sim.ctx)
+            flags, noconv = sim.flags()
+        finally:
+            sim.close()
+        out[name] = {"ms_per_step": round(ms, 3), "particle_steps_per_s": round(c["n"] / (ms / 1e3), 1),
+                     "phase_ms_per_step": {k: round(v / calls, 3) for k, v in phases.items()},
+                     "device_flags": flags, "noconv": noconv}
+        log(f"[bench] options: {name} {ms:.2f} ms/step")
+    base = out["plain"]["ms_per_step"]
+    for name in cases:
+        out[name]["over_plain"] = round(out[name]["ms_per_step"] / base, 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,15 +438,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true",
                     help="time only the 2M field (skip the Evrard, ensemble and serving configurations)")
-    ap.add_argument("--rows", default="c1,c2,c4,c5,f1",
-                    help="comma-separated rows to run besides the 2M field (c1, c2, c4, c5, f1)")
+    ap.add_argument("--rows", default="c1,c2,c4,c5,f1,options",
+                    help="comma-separated rows to run besides the 2M field (c1, c2, c4, c5, f1, options)")
     ap.add_argument("--precision", choices=["both", "fp32_bulk", "fp64"], default="both",
                     help="arithmetic form(s) to time; with both, the FP32-bulk form is the headline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel used to calibrate the HBM byte counters")
     args = ap.parse_args()
     want = set() if args.no_rows else {r.strip() for r in args.rows.split(",") if r.strip()}
-    unknown = want - {"c1", "c2", "c4", "c5", "f1"}
+    unknown = want - {"c1", "c2", "c4", "c5", "f1", "options"}
     if unknown:
         ap.error(f"unknown rows: {sorted(unknown)}")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -454,7 +507,8 @@ def main():
     if want:
         rows = {}
         for name, fn in (("c1", lambda: row_c1(torch, tsph, O)), ("c2", row_c2), ("c4", row_c4), ("c5", row_c5),
-                         ("f1", lambda: row_f1(torch, tsph, nps=args.nps))):
+                         ("f1", lambda: row_f1(torch, tsph, nps=args.nps)),
+                         ("options", lambda: row_options(torch, tsph, ic))):
             if name not in want:
                 continue
             t1 = time.time()

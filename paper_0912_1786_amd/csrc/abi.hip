@@ -25,13 +25,19 @@ int64_t node_capacity(int64_t cap_n, int leaf) {
   return 8 * cap_n / (leaf > 0 ? leaf : 1) + 1024;
 }
 
+// Offsets of the arena's buffers, in the order tsph_create maps them.  A
+// layout with more buffers than the table holds is marked full (an internal
+// error reported by both callers) instead of writing past the table.
 struct Layout {
-  size_t off[64];
+  static constexpr int kSlots = 96;
+  size_t off[kSlots];
   int k = 0;
+  bool full = false;
   size_t total = 0;
   size_t add(size_t bytes) {
     size_t o = total;
-    off[k++] = o;
+    if (k < kSlots) off[k++] = o;
+    else full = true;
     total = align_up(total + bytes);
     return o;
   }
@@ -71,6 +77,7 @@ const char *param_error(const tsph_params *p) {
 
 size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->k = 0;
+  L->full = false;
   L->total = 0;
   int64_t sort_blocks = (N + kSortTile - 1) / kSortTile + 1 + S;
   int64_t scan_blocks = (std::max<int64_t>(std::max<int64_t>(N, M), sort_blocks * kSortBins) + kScanTile - 1) /
@@ -145,6 +152,7 @@ size_t layout_bytes(int64_t N, int64_t M, int64_t S, Layout *L) {
   L->add(4 * N);        // bw
   L->add(4 * 16);       // bnext
   L->add(8 * kEwaldValues);  // ewt: Ewald table of a periodic box
+  L->add(16 * (kEwaldValues / 3));  // ewt32: the same in single precision
   return L->total;
 }
 
@@ -267,7 +275,7 @@ tsph_status tsph_bytes_required(int64_t capacity_n, const tsph_params *p, size_t
   if (param_error(p)) return TSPH_EINVAL;
   Layout L;
   *bytes = layout_bytes(capacity_n, node_capacity(capacity_n, p->leaf_size), p->max_members, &L);
-  return TSPH_OK;
+  return L.full ? TSPH_EINVAL : TSPH_OK;
 }
 
 tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
@@ -298,6 +306,7 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->h_mgas = (int64_t *)calloc((size_t)c->cap_mem, sizeof(int64_t));
   if (!c->h_moff || !c->h_mgas) return create_fail(c, TSPH_ENOMEM, "member tables", hipSuccess);
   size_t bytes = layout_bytes(c->cap_n, c->cap_nodes, c->cap_mem, &L);
+  if (L.full) return create_fail(c, TSPH_EINVAL, "internal: arena layout exceeds its offset table", hipSuccess);
   e = hipMalloc(&c->arena, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -375,7 +384,9 @@ tsph_status tsph_create(void **out, int64_t capacity_n, const tsph_params *p) {
   c->bw = AT(int32_t *);
   c->bnext = AT(int32_t *);
   c->ewt = AT(double *);
+  c->ewt32 = AT(float4 *);
 #undef AT
+  if (k != L.k) return create_fail(c, TSPH_EINVAL, "internal: arena layout and mapping disagree", hipSuccess);
   c->perm = c->idx[0];
   e = hipHostMalloc((void **)&c->h_flags, 64, hipHostMallocDefault);
   if (e != hipSuccess) {

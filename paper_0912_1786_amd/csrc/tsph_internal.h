@@ -236,6 +236,7 @@ struct Ctx {
 
   // ---- periodic box ----
   double *ewt;            // Ewald correction table, 3 x (kEwaldGrid + 1)^3
+  float4 *ewt32;          // the same table in single precision, (x, y, z, 0) per grid point
   double ew_L;            // box side the table was built for (0: none)
 
   // ---- phase timing (ring of event sets) ----
