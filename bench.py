@@ -22,9 +22,13 @@ for one step of the same workload.  "rows" adds the other configurations:
 c1 (Evrard 4096, FP64: step and per-phase times, GPU and oracle), c2 (Evrard
 262,144, 20 steps in both forms: step time, energy and momentum drift), c4
 (256-member ensemble, one graph launch per step, autotuned leaf, group and
-hand-off sizes) and c5 (serving: closed-loop saturation, then p50/p99
-latency under Poisson arrivals at 0.5x and 0.8x of it); "served_p50_ms" and
-"served_p99_ms" are those at 0.5x.
+hand-off sizes), c5 (serving: closed-loop saturation, then p50/p99
+latency under Poisson arrivals at 0.5x and 0.8x of it), f1 (individual
+power-of-two time-steps on the 2M field: simulated time per wall second
+against the global step) and options (the 2M field with each scheme option
+alone: dissipation switches, periodic box, viscosity, entropy, X-SPH,
+standard scheme, mass-density relation); "served_p50_ms" and
+"served_p99_ms" are those at 0.5x.  --rows picks the rows to run.
 """
 import argparse
 import json
