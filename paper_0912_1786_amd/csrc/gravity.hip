@@ -137,6 +137,14 @@ __device__ __forceinline__ void ewald_add(const GravArgs &A, S &s, double g, dou
 // The FP32-bulk form of ewald_add: the table in single precision, one
 // 16-byte record per grid point (a third of the loads of the FP64 table),
 // the interpolation in single precision, added to the sink's tile sums.
+// Records of the table's corner (kEwaldNear points per axis from the
+// origin) that the periodic FP32 walks keep in LDS: a wave whose lanes all
+// interpolate inside it (near pairs, close nodes) reads them there instead
+// of gathering from global memory; a wave whose lanes share one cell reads
+// its eight records as scalars.  Same records, same arithmetic.
+constexpr int kEwaldNear = 4;
+constexpr int kEwaldNearRecs = kEwaldNear * kEwaldNear * kEwaldNear;
+
 template <class S>
 __device__ __forceinline__ void ewald_add32(const GravArgs &A, S &s, float m, float x, float y, float z) {
   constexpr int n1 = kEwaldGrid + 1;
@@ -153,18 +161,56 @@ __device__ __forceinline__ void ewald_add32(const GravArgs &A, S &s, float m, fl
     f[d] = u - (float)k;
   }
   float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+  // one cell for the whole wave (a node far from a compact batch): the
+  // corner records are wave-uniform and come through the scalar cache
+  const int c0 = __builtin_amdgcn_readfirstlane(i[0]), c1 = __builtin_amdgcn_readfirstlane(i[1]),
+            c2 = __builtin_amdgcn_readfirstlane(i[2]);
+  const bool corner = i[0] < kEwaldNear - 1 && i[1] < kEwaldNear - 1 && i[2] < kEwaldNear - 1;
+  if (__all(i[0] == c0 && i[1] == c1 && i[2] == c2)) {
+    const float4 *cell = A.ewt32 + (c0 * n1 + c1) * n1 + c2;
 #pragma unroll
-  for (int b = 0; b < 8; b++) {
-    const int ox = b >> 2, oy = (b >> 1) & 1, oz = b & 1;
-    const float w = (ox ? f[0] : 1.0f - f[0]) * (oy ? f[1] : 1.0f - f[1]) * (oz ? f[2] : 1.0f - f[2]);
-    const float4 t = A.ewt32[((i[0] + ox) * n1 + (i[1] + oy)) * n1 + (i[2] + oz)];
-    v0 += w * t.x;
-    v1 += w * t.y;
-    v2 += w * t.z;
+    for (int b = 0; b < 8; b++) {
+      const int ox = b >> 2, oy = (b >> 1) & 1, oz = b & 1;
+      const float w = (ox ? f[0] : 1.0f - f[0]) * (oy ? f[1] : 1.0f - f[1]) * (oz ? f[2] : 1.0f - f[2]);
+      const float4 t = sload(cell + (ox * n1 + oy) * n1 + oz);
+      v0 += w * t.x;
+      v1 += w * t.y;
+      v2 += w * t.z;
+    }
+  } else if (__all(corner)) {
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      const int ox = b >> 2, oy = (b >> 1) & 1, oz = b & 1;
+      const float w = (ox ? f[0] : 1.0f - f[0]) * (oy ? f[1] : 1.0f - f[1]) * (oz ? f[2] : 1.0f - f[2]);
+      const float4 t = s.ew[((i[0] + ox) * kEwaldNear + (i[1] + oy)) * kEwaldNear + (i[2] + oz)];
+      v0 += w * t.x;
+      v1 += w * t.y;
+      v2 += w * t.z;
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      const int ox = b >> 2, oy = (b >> 1) & 1, oz = b & 1;
+      const float w = (ox ? f[0] : 1.0f - f[0]) * (oy ? f[1] : 1.0f - f[1]) * (oz ? f[2] : 1.0f - f[2]);
+      const float4 t = A.ewt32[((i[0] + ox) * n1 + (i[1] + oy)) * n1 + (i[2] + oz)];
+      v0 += w * t.x;
+      v1 += w * t.y;
+      v2 += w * t.z;
+    }
   }
   s.tax += m * (x < 0.0f ? -v0 : v0);
   s.tay += m * (y < 0.0f ? -v1 : v1);
   s.taz += m * (z < 0.0f ? -v2 : v2);
+}
+
+// The table's corner records into LDS (the whole wave; the caller's next
+// barrier publishes them).
+__device__ __forceinline__ void ewald_near_fill(const GravArgs &A, float4 *ew) {
+  constexpr int n1 = kEwaldGrid + 1;
+  for (int r = __lane_id(); r < kEwaldNearRecs; r += kWave) {
+    const int a = r / (kEwaldNear * kEwaldNear), b = (r / kEwaldNear) % kEwaldNear, c = r % kEwaldNear;
+    ew[r] = A.ewt32[(a * n1 + b) * n1 + c];
+  }
 }
 
 // the single-precision copy of the table, (x, y, z, 0) per grid point
@@ -422,6 +468,7 @@ struct Sink32 {
   float s4;                              // (2 eps)^2
   float tax, tay, taz, tpot;             // sums over the current tile
   double ax, ay, az, pot;                // totals (in units of G)
+  const float4 *ew;                      // periodic box: the table's first kEwaldNear^3 records in LDS
   int p;
   bool act;
 };
@@ -755,8 +802,10 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
   __shared__ TileT<F32> s_t;
   __shared__ int s_tq[kWave];
   __shared__ int s_g;
+  __shared__ float4 s_ew[(F32 && (M & kPer)) ? kEwaldNearRecs : 1];
   const int ln = lane();
   const int ng = *A.nbatches;
+  if constexpr (F32 && (M & kPer)) ewald_near_fill(A, s_ew);
   for (;;) {
     if (ln == 0) s_g = xcd_next(A.work + 16, ng);
     __syncthreads();
@@ -775,6 +824,7 @@ __global__ __launch_bounds__(64, 3) void k_gravity(GravArgs A) {
       if (A.act && ballot(c0 + ln < gnd.count && A.act[gnd.first + c0 + ln]) == 0) continue;
       SinkT<F32> s;
       load_sink<F32>(A, s, gnd, c0, cx, cy, cz, true);
+      if constexpr (F32) s.ew = s_ew;
       int near_done = 0;  // near-field particles evaluated by this wave
       int nfar = 0, npair = 0;
       int sp = 1, ncell = 0, nleaf = 0, nscell = 0;
@@ -1019,8 +1069,10 @@ __global__ __launch_bounds__(64) void k_gravity_split(GravArgs A) {
   __shared__ TileT<F32> s_t;
   __shared__ int s_tq[kWave];
   __shared__ int s_g;
+  __shared__ float4 s_ew[(F32 && (M & kPer)) ? kEwaldNearRecs : 1];
   const int ln = lane();
   const int nitems = min((int64_t)A.work[4], A.split_cap);
+  if constexpr (F32 && (M & kPer)) ewald_near_fill(A, s_ew);
   for (;;) {
     if (ln == 0) s_g = atomicAdd(&A.work[5], 1);
     __syncthreads();
@@ -1035,6 +1087,7 @@ __global__ __launch_bounds__(64) void k_gravity_split(GravArgs A) {
     const double cx = 0.5 * (gb.lox + gb.hix), cy = 0.5 * (gb.loy + gb.hiy), cz = 0.5 * (gb.loz + gb.hiz);
     SinkT<F32> s;
     load_sink<F32>(A, s, gnd, I.c0, cx, cy, cz, false);
+    if constexpr (F32) s.ew = s_ew;
     for (int a = ln; a < I.count; a += kWave) s_rng[a] = A.split_rng[I.start + a];
     __syncthreads();
     near_entries<M, F32>(A, s, RangeSrc{s_rng}, I.count, s_t, s_tq, cx, cy, cz);
