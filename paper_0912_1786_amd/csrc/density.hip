@@ -93,7 +93,8 @@ __device__ bool walk_leaves(const DensArgs &A, int root, const NodeBox &gb, doub
   const int ln = lane();
   int nleaf = 0, sp = 1, rounds = 0;
   const int guard = *A.nnodes + 2;
-  if (!(A.L > 0.0)) stage_ball_groups(s_snk, s_snk[ln]);
+  if (A.L > 0.0) stage_ball_groups_p(s_snk, s_snk[ln], A.L);
+  else stage_ball_groups(s_snk, s_snk[ln]);
   if (ln == 0) s_stack[0] = root;
   __syncthreads();
   const double R2 = R * R;
@@ -1440,7 +1441,7 @@ __global__ __launch_bounds__(1024) void k_heavy_order(DensArgs A) {
   for (int i = t; i < n; i += blockDim.x) A.heavy_ord[atomicAdd(&s_cnt[key_class(A.heavy_key[i])], 1)] = A.heavy[i];
 }
 
-__global__ __launch_bounds__(64) void k_density_sink(DensArgs A) {
+__global__ __launch_bounds__(64, 2) void k_density_sink(DensArgs A) {
   __shared__ int s_stack[kDensStackCap];
   __shared__ int s_leaf[kDensSinkLeafCap];
   __shared__ double4 s_snk[kSnkRecs];

@@ -543,7 +543,8 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
       if (ln == 0) s_stack[0] = bt.root;
       const double4 ball = make_double4(L.a.x, L.a.y, L.a.z, L.sink ? 2.0 * hi : 0.0);
       s_snk[ln] = ball;
-      if constexpr (!kPer) stage_ball_groups(s_snk, ball);
+      if constexpr (kPer) stage_ball_groups_p(s_snk, ball, A.L);
+      else stage_ball_groups(s_snk, ball);
       __syncthreads();
       for (;;) {
         if (sp > 0 && ++rounds > guard) {

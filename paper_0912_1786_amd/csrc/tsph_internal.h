@@ -572,33 +572,85 @@ __device__ __forceinline__ void stage_ball_groups(double4 *snk, const double4 &b
   }
 }
 
+// The periodic form: each group's centres are unwrapped around its first
+// lane's position (nearest images), so its box may reach past the cell; a
+// group spread over a quarter of the box or more keeps an infinite radius
+// (its members are always tested).
+__device__ __forceinline__ void stage_ball_groups_p(double4 *snk, const double4 &b, double L) {
+  const int ln = __lane_id();
+  const int first = ln & ~(kBallGroupSize - 1);
+  const double rx = __shfl(b.x, first, kWave), ry = __shfl(b.y, first, kWave), rz = __shfl(b.z, first, kWave);
+  const bool on = b.w > 0.0;
+  const double ux = rx + wrap_d(b.x - rx, L), uy = ry + wrap_d(b.y - ry, L), uz = rz + wrap_d(b.z - rz, L);
+  double lx = on ? ux : INFINITY, ly = on ? uy : INFINITY, lz = on ? uz : INFINITY;
+  double hx = on ? ux : -INFINITY, hy = on ? uy : -INFINITY, hz = on ? uz : -INFINITY;
+  double w = on ? b.w : -1.0;
+  for (int o = 1; o < kBallGroupSize; o <<= 1) {
+    lx = fmin(lx, __shfl_xor(lx, o, kWave));
+    ly = fmin(ly, __shfl_xor(ly, o, kWave));
+    lz = fmin(lz, __shfl_xor(lz, o, kWave));
+    hx = fmax(hx, __shfl_xor(hx, o, kWave));
+    hy = fmax(hy, __shfl_xor(hy, o, kWave));
+    hz = fmax(hz, __shfl_xor(hz, o, kWave));
+    w = fmax(w, __shfl_xor(w, o, kWave));
+  }
+  if (w > 0.0 && (hx - lx >= 0.25 * L || hy - ly >= 0.25 * L || hz - lz >= 0.25 * L)) w = INFINITY;
+  if (ln % kBallGroupSize == 0) {
+    snk[kWave + 2 * (ln / kBallGroupSize)] = make_double4(lx, ly, lz, w);
+    snk[kWave + 2 * (ln / kBallGroupSize) + 1] = make_double4(hx, hy, hz, 0.0);
+  }
+}
+
+// Periodic gap along one axis between a box and a group's box, lowered by
+// 1e-12 L, far more than the rounding of either gap: never more than the
+// nearest-image gap of any member inside the group's box.
+__device__ __forceinline__ double group_gap_p(double lo, double hi, double glo, double ghi, double L) {
+  const double c1 = 0.5 * (lo + hi), w1 = 0.5 * (hi - lo);
+  const double c2 = 0.5 * (glo + ghi), w2 = 0.5 * (ghi - glo);
+  const double d = fabs(wrap_d(c2 - c1, L)) - w1 - w2 - 1e-12 * L;
+  return d > 0.0 ? d : 0.0;
+}
+
 // Does some sink ball of the wave reach the box?  The ball radius used for
 // sink s is max(R_s, r_node).  Every lane tests its own box against the
 // staged sinks (broadcast reads); the loop stops once every lane that still
 // needs an answer has one.  The test only prunes candidates (the pair tests
 // decide), so it may keep more than the exact one and never less: in the
 // open box the gaps are max(lo - p, p - hi, 0) with fused squares, against
-// a radius widened by 1e-14 relative, which covers their rounding.  In the
-// open box a group of balls is tested first, as the gap from the box
-// to the box of the group's centres against the group's largest radius: that
-// gap is at most each member's (rounding is monotone), the radius at least
-// each member's, so a group that fails holds no ball that reaches, and the
-// result equals the test of every ball.
+// a radius widened by 1e-14 relative, which covers their rounding.  A group
+// of balls is tested first, as the gap from the box to the box of the
+// group's centres against the group's largest radius: that gap is at most
+// each member's (in the open box because rounding is monotone, in the
+// periodic box because the periodic distance is a metric and group_gap_p
+// keeps a margin), the radius at least each member's, so a group that fails
+// holds no ball that reaches, and the result equals the test of every ball.
 __device__ __forceinline__ bool balls_reach_box(const double4 *snk, double lox, double loy, double loz,
                                                 double hix, double hiy, double hiz, double r_node, bool want,
                                                 double L = 0.0) {
   bool hit = false;
   if (L > 0.0) {
-    for (int s = 0; s < kWave; s++) {
-      const double4 q = snk[s];
-      if (q.w > 0.0) {
-        const double R = fmax(q.w, r_node);
-        double d2 = axis_gap_point_p(lox, hix, q.x, L);
-        d2 = d2 + axis_gap_point_p(loy, hiy, q.y, L);
-        d2 = d2 + axis_gap_point_p(loz, hiz, q.z, L);
-        hit = hit || (d2 < R * R);
+    for (int g = 0; g < kBallGroups; g++) {
+      if (!__any(want && !hit)) break;
+      const double4 glo = snk[kWave + 2 * g], ghi = snk[kWave + 2 * g + 1];
+      bool need = false;
+      if (want && !hit && glo.w > 0.0) {
+        const double Rg = fmax(glo.w, r_node);
+        const double gx = group_gap_p(lox, hix, glo.x, ghi.x, L);
+        const double gy = group_gap_p(loy, hiy, glo.y, ghi.y, L);
+        const double gz = group_gap_p(loz, hiz, glo.z, ghi.z, L);
+        need = gx * gx + gy * gy + gz * gz < (Rg * Rg) * (1.0 + 1e-12);
       }
-      if ((s & 7) == 7 && !__any(want && !hit)) break;
+      if (!__any(need)) continue;
+      for (int s = kBallGroupSize * g; s < kBallGroupSize * (g + 1); s++) {
+        const double4 q = snk[s];
+        if (need && q.w > 0.0) {
+          const double R = fmax(q.w, r_node);
+          double d2 = axis_gap_point_p(lox, hix, q.x, L);
+          d2 = d2 + axis_gap_point_p(loy, hiy, q.y, L);
+          d2 = d2 + axis_gap_point_p(loz, hiz, q.z, L);
+          hit = hit || (d2 < R * R);
+        }
+      }
     }
     return hit;
   }
