@@ -625,17 +625,11 @@ __global__ __launch_bounds__(64, 4) void k_sph(SphArgs A) {
       if (overflow) atomicOr(A.flags, TSPH_FLAG_STACK_OVERFLOW);
       if (L.dbg && L.ndbg > A.dbg_max) atomicOr(A.flags, TSPH_FLAG_LIST_OVERFLOW);
       if (kMode == 1 && L.sink) {
-        // curl with the divergence's normalisation, Balsara factor, record
-        const double nom = A.solve[kNh * A.cap_n + p] * A.solve[kOmega * A.cap_n + p];
-        const double cx = L.xsx / nom, cy = L.xsy / nom, cz = L.xsz / nom;
-        A.solve[kCurlx * A.cap_n + p] = cx;
-        A.solve[kCurly * A.cap_n + p] = cy;
-        A.solve[kCurlz * A.cap_n + p] = cz;
-        const double dv = fabs(A.solve[kDivv * A.cap_n + p]);
-        const double fb = dv / (dv + sqrt(cx * cx + cy * cy + cz * cz) + 1e-4 * L.hd.z / L.hd.x);
-        A.solve[kFbal * A.cap_n + p] = fb;
-        const double2 al = A.av[p];
-        A.srec2[p] = make_double4(A.alpha_switch ? al.x : A.alpha, al.y, fb, L.v.w);
+        // the batch's own share of the curl sum; handed-off items add theirs
+        // (k_sph_reduce) before k_curl_finish normalises it
+        A.solve[kCurlx * A.cap_n + p] = L.xsx;
+        A.solve[kCurly * A.cap_n + p] = L.xsy;
+        A.solve[kCurlz * A.cap_n + p] = L.xsz;
       }
       if (kMode == 2 && L.sink) A.bm[A.perm[p]] = L.bm;
       if (force_mode(kMode) && L.sink) {
@@ -680,7 +674,7 @@ __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
     const bool act = I.c0 + ln < bt.ngas;
     const int p = act ? s_gs[ln] : bt.first;
     SphLane L;
-    sph_lane<kFull>(A, L, p, act && (!A.act || A.act[p]));
+    sph_lane<kFull>(A, L, p, act && (kMode == 1 || !A.act || A.act[p]));
     L.dbg = nullptr;
     for (int a = ln; a < I.count; a += kWave) s_rng[a] = A.split_rng[I.start + a];
     __syncthreads();
@@ -694,6 +688,7 @@ __global__ __launch_bounds__(64, 4) void k_sph_split(SphArgs A) {
 
 // Adds the items' partial sums to each batch's sinks along the batch's item
 // chain (creation order).
+template <int kMode>
 __global__ __launch_bounds__(64) void k_sph_reduce(SphArgs A) {
   __shared__ int s_gs[kWave];
   const int ln = lane();
@@ -707,7 +702,12 @@ __global__ __launch_bounds__(64) void k_sph_reduce(SphArgs A) {
       const SplitItem I = A.split_item[it];
       gas_sinks(A, bt, I.c0, s_gs);
       const int p = I.c0 + ln < bt.ngas ? s_gs[ln] : bt.first;
-      if (I.c0 + ln < bt.ngas) {
+      if (kMode == 1 && I.c0 + ln < bt.ngas) {
+        const double4 x = A.split_part[(int64_t)kSphPart * it * kWave + 2 * kWave + ln];
+        A.solve[kCurlx * A.cap_n + p] += x.x;
+        A.solve[kCurly * A.cap_n + p] += x.y;
+        A.solve[kCurlz * A.cap_n + p] += x.z;
+      } else if (I.c0 + ln < bt.ngas) {
         const double4 *part = A.split_part + (int64_t)kSphPart * it * kWave;
         const double4 v = part[ln], w = part[kWave + ln], x = part[2 * kWave + ln];
         A.acc[0 * A.cap_n + p] += v.x;
@@ -725,6 +725,26 @@ __global__ __launch_bounds__(64) void k_sph_reduce(SphArgs A) {
       }
       it = I.next;
     }
+  }
+}
+
+// The curl with the divergence's normalisation, the Balsara factor and the
+// switches' record of every gas particle (key order).
+__global__ __launch_bounds__(256) void k_curl_finish(SphArgs A, int64_t n) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    if (!A.gas[p]) continue;
+    const double nom = A.solve[kNh * A.cap_n + p] * A.solve[kOmega * A.cap_n + p];
+    const double cx = A.solve[kCurlx * A.cap_n + p] / nom, cy = A.solve[kCurly * A.cap_n + p] / nom,
+                 cz = A.solve[kCurlz * A.cap_n + p] / nom;
+    A.solve[kCurlx * A.cap_n + p] = cx;
+    A.solve[kCurly * A.cap_n + p] = cy;
+    A.solve[kCurlz * A.cap_n + p] = cz;
+    const double4 hd = A.sph[p];
+    const double dv = fabs(A.solve[kDivv * A.cap_n + p]);
+    const double fb = dv / (dv + sqrt(cx * cx + cy * cy + cz * cz) + 1e-4 * hd.z / hd.x);
+    A.solve[kFbal * A.cap_n + p] = fb;
+    const double2 al = A.av[p];
+    A.srec2[p] = make_double4(A.alpha_switch ? al.x : A.alpha, al.y, fb, A.vu[p].w);
   }
 }
 
@@ -869,12 +889,19 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
                        c->split_head, -1);
   if (A.f2) {
     // the switches' inputs in key order, then the curl pass (its own walk,
-    // no hand-off), then the forces
+    // with the same hand-off as the forces), the curl's normalisation and
+    // Balsara factors, then the forces with the queues and hand-off reset
     hipLaunchKernelGGL(k_gather_alpha, dim3(blocks_for(c->n, 256, 8192)), dim3(256), 0, st, c->n, c->perm,
                        c->alpha_state, c->alpha_u_state, c->av);
-    SphArgs Ac = A;
-    Ac.split_particles = 0;
-    launch_sph<1, true>(c, Ac, st);
+    launch_sph<1, true>(c, A, st);
+    if (A.split_particles > 0) {
+      launch_sph_split<1, true>(c, A, st);
+      hipLaunchKernelGGL(k_sph_reduce<1>, dim3(4096), dim3(64), 0, st, A);
+      hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, A.work + 34, 3);
+      hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(c->cap_nodes, 256, 4096)), dim3(256), 0, st, c->cap_nodes,
+                         c->split_head, -1);
+    }
+    hipLaunchKernelGGL(k_curl_finish, dim3(blocks_for(c->n, 256, 8192)), dim3(256), 0, st, A, (int64_t)c->n);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, A.work + 24, 8);
   }
   // the plain form without the switches, the conductivity and X-SPH; the
@@ -904,7 +931,7 @@ tsph_status tsph_impl_sph(Ctx *c, hipStream_t st) {
       else
         launch_sph_split<0, false>(c, A, st);
     }
-    hipLaunchKernelGGL(k_sph_reduce, dim3(4096), dim3(64), 0, st, A);
+    hipLaunchKernelGGL(k_sph_reduce<0>, dim3(4096), dim3(64), 0, st, A);
   }
   TSPH_HIP_CHECK(c, hipGetLastError());
   return TSPH_OK;
