@@ -49,7 +49,7 @@ def _carry_rates(sim):
     return c[5 * n:6 * n], c[6 * n:7 * n]
 
 
-@pytest.mark.parametrize("flags", ["balsara", "alpha_switch", "conduction", "all", "all_signal"])
+@pytest.mark.parametrize("flags", ["balsara", "alpha_switch", "conduction", "all", "all_signal", "all_handoff"])
 def test_switches_match_oracle(O, flags):
     _say(f"[switches] {flags}")
     ic = _ic()
@@ -64,6 +64,10 @@ def test_switches_match_oracle(O, flags):
         kw = dict(balsara=1, alpha_switch=1, conduction=1)
     if flags == "all_signal":
         kw["visc_form"] = tsph.VISC_SIGNAL
+    if flags == "all_handoff":
+        # a tiny own share: the curl and force passes hand nearly every
+        # near field on to other wavefronts (and density its batches)
+        kw["split_leaves"] = 4
     gp = gpu_params(**kw)
     sim = tsph.Simulation(ic, gp)
     sim.compute_forces()
